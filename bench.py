@@ -1,0 +1,283 @@
+#!/usr/bin/env python
+"""Benchmark of the sparse GEE hot path on one MI355X.
+
+A step is one whole pass of the path over the workload: gee_embed on the edge list
+(class counts, CSR build, degrees, Laplacian rescale, per-row class scatter, diagonal
+term, correlation), inputs resident in HBM. Default workload: Chung-Lu power-law graph,
+N=600,000, E=10,000,000 undirected weighted edges, K=50 (10% unknown labels), all
+options on.
+
+Prints one JSON line. `value` is edges embedded per second over the timed steps.
+`roofline` is for the kernel with the largest share of the step, timed live with HIP
+events recorded around each of its launches on the launch stream (library hook), and
+priced with its algorithmic bytes against the 8 TB/s HBM peak. `cpu_baseline` is the
+FP64 oracle timed on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges embedded/sec + % HBM peak; served p50/p99 latency vs plain per-graph loop"
+HBM_PEAK_GBS = 8000.0
+
+KERNELS = ["class_count_partial", "class_count_final", "p1_hist", "p1_scan", "p1_totals", "p1_scatter",
+           "p2_bucket", "fill_empty", "embed_rows", "embed_fixup"]
+
+
+def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
+    """Bytes a kernel must move at minimum for one launch (inputs read once, outputs
+    written once), from the sizes of its own inputs and outputs."""
+    wv = 4 if weighted else 0
+    if name == "class_count_partial":
+        return 4 * N
+    if name == "p1_hist":
+        return 8 * E
+    if name == "p1_scatter":
+        return (8 + wv) * E + (2 + 4 + wv) * M
+    if name == "p2_bucket":
+        return (2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1) + 4 * N + 8 * N + 4 * N
+    if name == "fill_empty":
+        return 4 * (N + 1) + 4 * K * n_empty
+    if name == "embed_rows":
+        return 4 * (N + 1) + (4 + wv) * M + 8 * N + 4 * N + 4 * N * K
+    return 0
+
+
+def make_workload(name):
+    from gee_workloads import powerlaw_10m, sbm_dense, sbm_small
+
+    if name == "powerlaw_10m":
+        return powerlaw_10m()
+    if name == "sbm_dense":
+        return sbm_dense()
+    if name == "sbm_small_all":
+        return sbm_small("all")
+    if name == "sbm_small_off":
+        return sbm_small("off")
+    raise ValueError(name)
+
+
+class HipEvents:
+    """hipEvent create/elapsed through the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        import ctypes
+
+        import torch
+
+        path = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+        self.ct = ctypes
+        self.hip = ctypes.CDLL(path)
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        h = self.ct.c_void_p()
+        rc = self.hip.hipEventCreate(self.ct.byref(h))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed ({rc})")
+        return h
+
+    def elapsed_ms(self, a, b):
+        out = self.ct.c_float()
+        rc = self.hip.hipEventElapsedTime(self.ct.byref(out), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(out.value)
+
+    def destroy(self, h):
+        self.hip.hipEventDestroy(h)
+
+
+def cpu_baseline(g, budget_s=12.0, max_reps=30):
+    """The FP64 oracle (single-threaded C edge-list loop) on this host's cores."""
+    from oracle import oracle as orc
+
+    orc.load()
+    reps, total = 0, 0.0
+    while reps < max_reps and (total < budget_s or reps < 1):
+        t0 = time.perf_counter()
+        orc.embed_graph(g)
+        total += time.perf_counter() - t0
+        reps += 1
+    return {"value": g.E * reps / total, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full workload edge list, {reps} repetition(s), {total:.1f} s of CPU time",
+            "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="powerlaw_10m",
+                    choices=["powerlaw_10m", "sbm_dense", "sbm_small_all", "sbm_small_off"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--report", default=None, help="also write a detailed JSON report here")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
+                                   "part of this build (see the sharding notes in DESIGN.md)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2406_03726_amd as gee
+    from paper_2406_03726_amd import _lib
+
+    if not os.path.exists(_lib.LIB):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    lib = _lib.load()
+
+    t_gen = time.perf_counter()
+    g = make_workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
+    src, dst, w, lab = t(g.src, torch.int32), t(g.dst, torch.int32), t(g.w, torch.float32), t(g.labels, torch.int32)
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    E, N, K = g.E, g.N, g.K
+    Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    ws_bytes = gee.gee_embed_workspace_bytes(E, N, K, flags, w is not None)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if gee.gee_get_data_errors() != 0:
+        raise RuntimeError("device reported a data error on the benchmark input")
+
+    # CSR entry count and empty rows (for the byte counts)
+    rp, col, val = gee.gee_build_csr(src, dst, w, N, flags)
+    torch.cuda.synchronize()
+    M = int(rp[-1].item())
+    n_empty = int((rp[1:] == rp[:-1]).sum().item())
+
+    ev = HipEvents()
+
+    # Untimed pass: each kernel's duration, to find the dominant one.
+    per_kernel = {}
+    for name in KERNELS:
+        a, b = ev.create(), ev.create()
+        lib.gee_profile_kernel(name.encode(), a, b)
+        step()
+        torch.cuda.synchronize()
+        lib.gee_profile_kernel(name.encode(), None, None)
+        per_kernel[name] = ev.elapsed_ms(a, b)
+        ev.destroy(a)
+        ev.destroy(b)
+    dominant = max(per_kernel, key=per_kernel.get)
+
+    # Timed region: K steps; HIP events around every launch of the dominant kernel.
+    pairs = [(ev.create(), ev.create()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lib.gee_profile_kernel(dominant.encode(), pairs[i][0], pairs[i][1])
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.gee_profile_kernel(dominant.encode(), None, None)
+    dom_ms = [ev.elapsed_ms(a, b) for a, b in pairs]
+    for a, b in pairs:
+        ev.destroy(a)
+        ev.destroy(b)
+
+    elapsed = t1 - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = E * args.steps / elapsed
+    dom_avg_ms = float(np.mean(dom_ms))
+    alg = algorithmic_bytes(dominant, E, N, K, M, w is not None, n_empty)
+    achieved = alg / (dom_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(dom_avg_ms, 5)}
+
+    # Steady state on a resident CSR (re-embedding, the serving/iterative form).
+    Zr = torch.empty_like(Z)
+    ws2 = torch.empty(max(1, gee.gee_embed_csr_workspace_bytes(M, N, K, flags)), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        gee.gee_embed_csr(rp, col, val, M, lab, K, flags, Z=Zr, workspace=ws2, stream=stream)
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    for _ in range(args.steps):
+        gee.gee_embed_csr(rp, col, val, M, lab, K, flags, Z=Zr, workspace=ws2, stream=stream)
+    torch.cuda.synchronize()
+    resident_ms = (time.perf_counter() - tr0) / args.steps * 1e3
+    same = bool(torch.equal(Z, Zr))
+
+    kernels = {}
+    for name, ms in per_kernel.items():
+        b = algorithmic_bytes(name, E, N, K, M, w is not None, n_empty)
+        kernels[name] = {"ms": round(ms, 5), "algorithmic_bytes": int(b),
+                         "GB_per_s": round(b / (ms * 1e-3) / 1e9, 1) if (b and ms > 0) else None}
+    e2e_min_bytes = (8 + (4 if w is not None else 0)) * E + 4 * N + 4 * N * K
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": g.name, "N": N, "E": E, "M_csr_entries": M, "K": K,
+                   "options": "+".join(o for o, on in (("diag", g.diag), ("laplacian", g.lap),
+                                                       ("correlation", g.cor)) if on) or "none",
+                   "weighted": w is not None, "symmetrize": g.sym, "schedule": gee.gee_default_schedule(E, N, K, flags)},
+        "roofline": roofline,
+        "e2e_hbm_frac_min_bytes": round(e2e_min_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": kernels,
+        "resident_csr_embed": {"ms_per_call": round(resident_ms, 5),
+                               "edges_per_s": round(E / (resident_ms * 1e-3), 1),
+                               "bitwise_equal_to_edge_list_path": same},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g)
+    else:
+        out["cpu_baseline"] = None
+    line = json.dumps(out)
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump({**out, "generation_s": t_gen, "dominant_ms_all": dom_ms}, f, indent=1)
+    print(line, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * gee.h - C ABI of the MI355X (gfx950) sparse Graph Encoder Embedding library.
+ *
+ * The library computes the embedding of Qin & Shen, "Efficient Graph Encoder
+ * Embedding for Large Sparse Graphs in Python":
+ *   Section 2: W is the N x K normalized one-hot label matrix (row j holds 1/n_k in
+ *   column k = y_j, with n_k the number of nodes labelled k) and Z = A W (Eq. 1),
+ *   Z_i^k = sum over neighbours j of i with label k of e_ij / n_k.
+ *   Section 2 options, Table 1: diagonal augmentation (A + I), Laplacian
+ *   normalization (D^-1/2 A D^-1/2) and correlation (each row of Z divided by its
+ *   2-norm).
+ *   Section 3: the adjacency is held in CSR (index_pointers of N + 1 entries, then
+ *   col_indices and data row by row).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer on the current HIP device, owned by
+ *     the caller. The library never frees, retains or reads caller memory after the
+ *     call's work on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). All
+ *     work is enqueued asynchronously on it; inputs must stay valid and outputs must
+ *     not be read until the stream reaches that point.
+ *   - Node ids, labels and CSR indices are int32; E and M (entry counts) are int64.
+ *     Weights and Z are float32; Z is row-major N x K and is fully overwritten.
+ *   - Label -1 means "unknown": the node contributes a zero W row and is counted in
+ *     no class, but it keeps its degree and gets its own Z row.
+ *   - Return value: GEE_OK or a negative gee_status. An argument error is detected
+ *     on the host before anything is enqueued. A data error found on the device
+ *     (a label outside [-1, K), a node index outside [0, N), a non-finite weight, a
+ *     malformed CSR) never makes a kernel read or write out of bounds: the offending
+ *     item is skipped, Z is then unspecified, and a sticky per-device bit is raised
+ *     that gee_get_data_errors() reads and clears.
+ *   - Results are deterministic: the same inputs give bitwise identical Z, CSR and
+ *     class counts on every call. No floating-point global atomics are used.
+ *   - Calls on different streams may run concurrently. The data-error word is per
+ *     device, so concurrent calls share it.
+ */
+#ifndef GEE_H
+#define GEE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GEE_ABI_VERSION 1
+
+/* Option bits (Section 2 options; Table 1 rows). */
+#define GEE_DIAG (1u << 0)        /* A -> A + I */
+#define GEE_LAPLACIAN (1u << 1)   /* A -> D^-1/2 A D^-1/2, D = row sums of A (+ I) */
+#define GEE_CORRELATION (1u << 2) /* each row of Z divided by its 2-norm (zero rows stay 0) */
+#define GEE_SYMMETRIZE (1u << 3)  /* each input row (s, d, w) is an undirected edge:
+                                     A[s,d] and A[d,s] (a self-loop once) */
+
+/* Status codes. */
+typedef enum {
+    GEE_OK = 0,
+    GEE_ERR_ARG = -1,         /* bad argument (NULL, negative size, unknown flag bit, ...) */
+    GEE_ERR_LABEL = -2,       /* (data error bit) label outside [-1, K) */
+    GEE_ERR_INDEX = -3,       /* (data error bit) node index outside [0, N) */
+    GEE_ERR_WEIGHT = -4,      /* (data error bit) non-finite weight */
+    GEE_ERR_TOO_LARGE = -5,   /* sizes beyond what this build supports (see below) */
+    GEE_ERR_OOM = -6,         /* device allocation failed */
+    GEE_ERR_HIP = -7,         /* a HIP runtime call failed */
+    GEE_ERR_UNSUPPORTED = -8, /* valid request this build does not implement */
+    GEE_ERR_WORKSPACE = -9    /* caller workspace too small */
+} gee_status;
+
+/* Device data-error bits returned by gee_get_data_errors. */
+#define GEE_DATA_LABEL (1u << 0)
+#define GEE_DATA_INDEX (1u << 1)
+#define GEE_DATA_WEIGHT (1u << 2)
+#define GEE_DATA_CSR (1u << 3)
+
+/* Limits of this build: N <= 2^24, K <= 128, CSR entries M < 2^31 - 2^16.
+   (M = 2E minus self-loops under GEE_SYMMETRIZE, else E.) */
+#define GEE_MAX_NODES (1 << 24)
+#define GEE_MAX_CLASSES 128
+
+/* Launch schedule of the embedding kernels. A zero field takes the library's
+   default for the graph's size. Schedules change speed, never results except for
+   floating-point rounding order (a schedule is chosen from the graph's own sizes, so
+   a graph embedded alone or inside a batch with the same schedule is bit-identical). */
+typedef struct {
+    int32_t wave_entries;   /* CSR entries per wavefront in the embed kernel (power of 2, 256..16384) */
+    int32_t waves_per_block;/* wavefronts per workgroup in the embed kernel (1, 2 or 4) */
+    int32_t tile_entries;   /* edge-list entries per workgroup tile of the CSR partition pass
+                               (power of 2, 2048..65536) */
+    int32_t bucket_rows_log2; /* rows per partition bucket = 2^this (0 = automatic, else 0..12) */
+} gee_schedule;
+
+int gee_abi_version(void);
+const char *gee_status_string(int status);
+
+/* Per-device set-up (the data-error word). Called lazily by every entry point; call it
+   once up front on each device when later calls run under stream capture. */
+int gee_init(void);
+
+/* Reads and clears the current device's sticky data-error bits (GEE_DATA_*). Waits for
+   `stream` to finish first. */
+int gee_get_data_errors(void *stream, uint32_t *bits);
+
+/* Profiling hook (for benchmarks and tests). From this call on, every launch of the named
+   kernel records hipEvent `start_event` on its stream right before the launch and
+   `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
+   Kernel names: "class_count_partial", "class_count_final", "p1_hist", "p1_scan",
+   "p1_totals", "p1_scatter", "p2_bucket", "prep_from_csr", "fill_empty", "embed_rows",
+   "embed_fixup", "set_meta", "batch_embed_rows", "batch_embed_fixup". The caller owns the
+   events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
+   name. Process-wide; not meant for concurrent use from several threads. */
+int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);
+
+/* Default schedule for a graph of these sizes. */
+int gee_default_schedule(int64_t E, int32_t N, int32_t K, uint32_t flags, gee_schedule *out);
+
+/* ---------------------------------------------------------------------------------
+ * gee_class_counts - n_k = #{j : labels[j] = k} for k in [0, K) (Section 2).
+ *   labels : int32[N] device, values in [-1, K)
+ *   counts : int32[K] device, output (exact integers)
+ * Out-of-range labels are counted nowhere and raise GEE_DATA_LABEL. */
+int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *counts, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_build_csr - edge list -> CSR (Section 3 layout), built on the device by a stable
+ * two-level radix partition on the row index.
+ *   src, dst : int32[E] device, node ids in [0, N)
+ *   w        : float32[E] device weights, or NULL (every weight is 1)
+ *   flags    : only GEE_SYMMETRIZE is meaningful here
+ *   row_ptr  : int32[N + 1] device output; row_ptr[N] = M, the number of entries
+ *   col      : int32[capacity] device output, capacity = gee_csr_capacity(E, flags)
+ *   val      : float32[capacity] device output, or NULL when w is NULL
+ * Canonical order: row i lists, in increasing input row index e, the other endpoint of
+ * every input row with src = i (and, under GEE_SYMMETRIZE, with dst = i); for one e the
+ * (src,dst) entry precedes its mirror; a self-loop appears once; val holds the input
+ * weight bits unchanged. Rows with an out-of-range endpoint are dropped (GEE_DATA_INDEX).
+ * gee_build_csr allocates its scratch with hipMallocAsync on `stream`; the _ws variant
+ * uses caller scratch of gee_build_csr_workspace_bytes() bytes instead. */
+int64_t gee_csr_capacity(int64_t E, uint32_t flags);
+size_t gee_build_csr_workspace_bytes(int64_t E, int32_t N, uint32_t flags, const gee_schedule *sched);
+int gee_build_csr(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                  uint32_t flags, int32_t *row_ptr, int32_t *col, float *val, void *stream);
+int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                     uint32_t flags, int32_t *row_ptr, int32_t *col, float *val,
+                     const gee_schedule *sched, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_embed - the whole path, edge list -> Z (Eq. 1 with the Table 1 options).
+ *   src, dst : int32[E] device edge list, node ids in [0, N)
+ *   w        : float32[E] device weights, or NULL (every weight is 1)
+ *   labels   : int32[N] device, values in [-1, K)
+ *   flags    : GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE
+ *   Z        : float32[N * K] device output, row-major
+ * Steps, all on the device: class counts, CSR build, degrees (Laplacian), the
+ * per-row class scatter with the rescale and diagonal term fused, correlation.
+ * Diagonal augmentation is applied before the Laplacian (degrees are those of A + I).
+ * gee_embed allocates its scratch with hipMallocAsync/hipFreeAsync on `stream`; the
+ * _ws variant takes caller scratch of gee_embed_workspace_bytes() bytes and a schedule
+ * (NULL = default) and allocates nothing. */
+size_t gee_embed_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
+                                 const gee_schedule *sched);
+int gee_embed(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+              const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream);
+int gee_embed_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                 const int32_t *labels, int32_t K, uint32_t flags, float *Z,
+                 const gee_schedule *sched, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_embed_csr - Z from a resident CSR (for example one built by gee_build_csr).
+ *   row_ptr : int32[N + 1] device, non-decreasing, row_ptr[0] = 0, row_ptr[N] = M
+ *   col     : int32[M] device, column indices in [0, N)
+ *   val     : float32[M] device, or NULL (every value is 1)
+ *   M       : number of entries (must equal row_ptr[N])
+ *   labels, K, flags, Z : as for gee_embed (GEE_SYMMETRIZE is ignored: the CSR
+ *             already holds both directions when wanted)
+ * Columns outside [0, N) are skipped and raise GEE_DATA_CSR. */
+size_t gee_embed_csr_workspace_bytes(int64_t M, int32_t N, int32_t K, uint32_t flags,
+                                     const gee_schedule *sched);
+int gee_embed_csr(const int32_t *row_ptr, const int32_t *col, const float *val, int64_t M, int32_t N,
+                  const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream);
+int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *val, int64_t M,
+                     int32_t N, const int32_t *labels, int32_t K, uint32_t flags, float *Z,
+                     const gee_schedule *sched, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEE_H */

@@ -1,0 +1,31 @@
+"""MI355X-native sparse Graph Encoder Embedding (Qin & Shen, Sections 2-3).
+
+The hot path (edge list -> CSR -> degrees -> Laplacian rescale -> per-row class
+scatter -> correlation) runs in hand-written HIP kernels for gfx950 behind the C ABI
+of include/gee.h (libgee.so); this package is the thin Python binding over it.
+"""
+
+from .gee import (  # noqa: F401
+    GEE_CORRELATION,
+    GEE_DATA_CSR,
+    GEE_DATA_INDEX,
+    GEE_DATA_LABEL,
+    GEE_DATA_WEIGHT,
+    GEE_DIAG,
+    GEE_LAPLACIAN,
+    GEE_SYMMETRIZE,
+    GeeError,
+    flags_of,
+    gee_abi_version,
+    gee_build_csr,
+    gee_class_counts,
+    gee_csr_capacity,
+    gee_default_schedule,
+    gee_embed,
+    gee_embed_csr,
+    gee_embed_csr_workspace_bytes,
+    gee_embed_workspace_bytes,
+    gee_get_data_errors,
+    gee_init,
+    schedule,
+)

@@ -1,0 +1,214 @@
+"""Python binding of libgee: the C ABI's entry points under the same names.
+
+Argument marshalling only: tensors are checked for device, dtype and layout and their
+device addresses and the current HIP stream are handed to the library. Every step of
+the embedding runs in the library's HIP kernels; there is no CPU path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+GEE_DIAG = 1 << 0
+GEE_LAPLACIAN = 1 << 1
+GEE_CORRELATION = 1 << 2
+GEE_SYMMETRIZE = 1 << 3
+
+GEE_DATA_LABEL = 1 << 0
+GEE_DATA_INDEX = 1 << 1
+GEE_DATA_WEIGHT = 1 << 2
+GEE_DATA_CSR = 1 << 3
+
+GEE_OK = 0
+GEE_ERR_ARG = -1
+GEE_ERR_TOO_LARGE = -5
+GEE_ERR_OOM = -6
+GEE_ERR_UNSUPPORTED = -8
+GEE_ERR_WORKSPACE = -9
+
+
+class GeeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.load().gee_status_string(code).decode()
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def flags_of(diag=False, lap=False, cor=False, sym=True) -> int:
+    return ((GEE_DIAG if diag else 0) | (GEE_LAPLACIAN if lap else 0)
+            | (GEE_CORRELATION if cor else 0) | (GEE_SYMMETRIZE if sym else 0))
+
+
+def _check(rc: int, where: str):
+    if rc != GEE_OK:
+        raise GeeError(rc, where)
+
+
+def _dev(t: Optional[torch.Tensor], dtype, name: str, device=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def schedule(wave_entries=0, waves_per_block=0, tile_entries=0, bucket_rows_log2=0) -> _lib.GeeSchedule:
+    return _lib.GeeSchedule(wave_entries, waves_per_block, tile_entries, bucket_rows_log2)
+
+
+def _sched_ptr(s):
+    if s is None:
+        return None
+    if isinstance(s, dict):
+        s = schedule(**s)
+    return ctypes.byref(s)
+
+
+def gee_abi_version() -> int:
+    return _lib.load().gee_abi_version()
+
+
+def gee_init() -> None:
+    _check(_lib.load().gee_init(), "gee_init")
+
+
+def gee_get_data_errors(stream=None) -> int:
+    bits = ctypes.c_uint32(0)
+    _check(_lib.load().gee_get_data_errors(_stream(stream), ctypes.byref(bits)), "gee_get_data_errors")
+    return int(bits.value)
+
+
+def gee_default_schedule(E: int, N: int, K: int, flags: int) -> dict:
+    s = _lib.GeeSchedule()
+    _check(_lib.load().gee_default_schedule(E, N, K, flags, ctypes.byref(s)), "gee_default_schedule")
+    return {f: getattr(s, f) for f, _ in _lib.GeeSchedule._fields_}
+
+
+def gee_class_counts(labels: torch.Tensor, K: int, counts: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    labels = _dev(labels, torch.int32, "labels")
+    if counts is None:
+        counts = torch.empty(K, dtype=torch.int32, device=labels.device)
+    _dev(counts, torch.int32, "counts", labels.device)
+    _check(_lib.load().gee_class_counts(_ptr(labels), labels.numel(), K, _ptr(counts), _stream(stream)),
+           "gee_class_counts")
+    return counts
+
+
+def gee_csr_capacity(E: int, flags: int) -> int:
+    return int(_lib.load().gee_csr_capacity(E, flags))
+
+
+def gee_build_csr(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], N: int, flags: int,
+                  row_ptr: Optional[torch.Tensor] = None, col: Optional[torch.Tensor] = None,
+                  val: Optional[torch.Tensor] = None, sched=None, stream=None):
+    """Returns (row_ptr, col, val) with col/val at full capacity; the entry count is
+    row_ptr[N] (read it with row_ptr[-1].item() when needed)."""
+    src = _dev(src, torch.int32, "src")
+    dst = _dev(dst, torch.int32, "dst", src.device)
+    w = _dev(w, torch.float32, "w", src.device)
+    E = src.numel()
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    cap = gee_csr_capacity(E, flags)
+    dev = src.device
+    if row_ptr is None:
+        row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    if col is None:
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    if val is None and w is not None:
+        val = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    lib = _lib.load()
+    sp = _sched_ptr(sched)
+    nbytes = lib.gee_build_csr_workspace_bytes(E, N, flags, sp)
+    if nbytes == 0:
+        raise GeeError(GEE_ERR_ARG, "gee_build_csr_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _check(lib.gee_build_csr_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, flags, _ptr(row_ptr), _ptr(col),
+                                _ptr(val), sp, _ptr(ws), nbytes, _stream(stream)), "gee_build_csr")
+    return row_ptr, col, val
+
+
+def gee_embed(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], labels: torch.Tensor,
+              K: int, flags: int, Z: Optional[torch.Tensor] = None, sched=None,
+              workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Z (float32, N x K) of the edge list; N is labels.numel()."""
+    labels = _dev(labels, torch.int32, "labels")
+    dev = labels.device
+    src = _dev(src, torch.int32, "src", dev)
+    dst = _dev(dst, torch.int32, "dst", dev)
+    w = _dev(w, torch.float32, "w", dev)
+    E = src.numel()
+    N = labels.numel()
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    if Z is None:
+        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    _dev(Z, torch.float32, "Z", dev)
+    if Z.numel() != N * K:
+        raise ValueError("Z must hold N * K floats")
+    lib = _lib.load()
+    sp = _sched_ptr(sched)
+    nbytes = lib.gee_embed_workspace_bytes(E, N, K, flags, int(w is not None), sp)
+    if nbytes == 0 and N > 0:
+        raise GeeError(GEE_ERR_ARG if E >= 0 else GEE_ERR_TOO_LARGE, "gee_embed_workspace_bytes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib.gee_embed_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z), sp,
+                            _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed")
+    return Z
+
+
+def gee_embed_workspace_bytes(E: int, N: int, K: int, flags: int, weighted: bool, sched=None) -> int:
+    return int(_lib.load().gee_embed_workspace_bytes(E, N, K, flags, int(weighted), _sched_ptr(sched)))
+
+
+def gee_embed_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: Optional[torch.Tensor], M: int,
+                  labels: torch.Tensor, K: int, flags: int, Z: Optional[torch.Tensor] = None,
+                  sched=None, workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Z from a resident CSR with M entries (row_ptr[N] must equal M)."""
+    labels = _dev(labels, torch.int32, "labels")
+    dev = labels.device
+    row_ptr = _dev(row_ptr, torch.int32, "row_ptr", dev)
+    col = _dev(col, torch.int32, "col", dev)
+    val = _dev(val, torch.float32, "val", dev)
+    N = labels.numel()
+    if row_ptr.numel() != N + 1 or col.numel() < M or (val is not None and val.numel() < M):
+        raise ValueError("row_ptr must have N + 1 entries and col/val at least M")
+    if Z is None:
+        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    _dev(Z, torch.float32, "Z", dev)
+    lib = _lib.load()
+    sp = _sched_ptr(sched)
+    nbytes = lib.gee_embed_csr_workspace_bytes(M, N, K, flags, sp)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib.gee_embed_csr_ws(_ptr(row_ptr), _ptr(col), _ptr(val), M, N, _ptr(labels), K, flags,
+                                _ptr(Z), sp, _ptr(workspace), workspace.numel(), _stream(stream)),
+           "gee_embed_csr")
+    return Z
+
+
+def gee_embed_csr_workspace_bytes(M: int, N: int, K: int, flags: int, sched=None) -> int:
+    return int(_lib.load().gee_embed_csr_workspace_bytes(M, N, K, flags, _sched_ptr(sched)))

@@ -1,0 +1,79 @@
+"""CPU checks of the C ABI: the library loads and exports every declared entry point,
+and host-side argument checks answer without touching a device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gee.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gee_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2406_03726_amd import _lib
+
+    if not os.path.exists(_lib.LIB):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gee_embed", "gee_embed_ws", "gee_build_csr", "gee_embed_csr", "gee_class_counts",
+                     "gee_get_data_errors", "gee_status_string"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in gee.h but not exported"
+
+
+def test_binding_covers_every_symbol():
+    from paper_2406_03726_amd import _lib
+
+    assert set(declared_functions()) == set(_lib.SYMBOLS)
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "gee.h"\nint main(void){ return GEE_ABI_VERSION == 1 ? 0 : 1; }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", f"-I{os.path.dirname(HEADER)}", "-c", str(src),
+                    "-o", str(tmp_path / "t.o")], check=True)
+
+
+def test_host_only_queries(lib):
+    assert lib.gee_abi_version() == 1
+    assert lib.gee_status_string(0) == b"ok"
+    assert lib.gee_csr_capacity(10, 8) == 20
+    assert lib.gee_csr_capacity(10, 0) == 10
+    # workspace sizing is pure host arithmetic
+    assert lib.gee_embed_workspace_bytes(1000, 100, 3, 15, 1, None) > 0
+    assert lib.gee_embed_workspace_bytes(-1, 100, 3, 15, 1, None) == 0
+    assert lib.gee_embed_workspace_bytes(1000, 100, 0, 15, 1, None) == 0       # K < 1
+    assert lib.gee_embed_workspace_bytes(1000, 100, 129, 15, 1, None) == 0     # K beyond the build
+    assert lib.gee_embed_workspace_bytes(1000, 100, 3, 1 << 9, 1, None) == 0    # unknown flag bit
+    big = lib.gee_embed_workspace_bytes(2 ** 30, 100, 3, 8, 1, None)
+    assert big == 0  # 2^31 entries exceed the int32 CSR
+
+
+def test_schedule_validation(lib):
+    from paper_2406_03726_amd._lib import GeeSchedule
+
+    s = GeeSchedule(0, 0, 0, 0)
+    assert lib.gee_default_schedule(10_000_000, 600_000, 50, 15, ctypes.byref(s)) == 0
+    assert s.wave_entries >= 256 and 1 <= s.waves_per_block <= 4 and s.tile_entries >= 2048
+    bad = GeeSchedule(300, 0, 0, 0)  # not a power of two
+    assert lib.gee_embed_workspace_bytes(1000, 100, 3, 15, 1, ctypes.byref(bad)) == 0
