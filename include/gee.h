@@ -105,8 +105,8 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
    kernel records hipEvent `start_event` on its stream right before the launch and
    `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
    Kernel names: "class_count_partial", "class_count_final", "p1_hist", "p1_scan",
-   "p1_totals", "p1_scatter", "p2_bucket", "prep_from_csr", "fill_empty", "embed_rows",
-   "embed_fixup", "set_meta", "batch_embed_rows", "batch_embed_fixup". The caller owns the
+   "p1_totals", "p1_scatter", "p2_bucket", "zero_steps", "node_rows", "degree_rows", "degree_fixup",
+   "fill_empty", "embed_rows", "embed_fixup", "set_meta". The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);

@@ -7,11 +7,6 @@
 #include "gee.h"
 #include "gee_internal.h"
 
-namespace gee {
-hipError_t launch_set_meta(int *meta, int M, int NW, hipStream_t s);
-size_t embed_lds_per_wave(int K);
-}  // namespace gee
-
 using namespace gee;
 
 namespace {
@@ -154,10 +149,14 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
     if (parts & kPEmbed) {
         w.info = (float2 *)take((size_t)p.N * sizeof(float2));
         w.srow = (float *)take((size_t)p.N * sizeof(float));
-        w.fown = (int *)take((size_t)(p.NWcap + 1) * sizeof(int));
+        w.wrow = (int *)take((size_t)p.NWcap * sizeof(int));
+        w.rstep = (uint8_t *)take((size_t)(p.Mcap > 0 ? p.Mcap : 1));
         w.split = (int *)take((size_t)p.NWcap * sizeof(int));
         w.headp = (float *)take((size_t)p.NWcap * p.K * sizeof(float));
         w.tailp = (float *)take((size_t)p.NWcap * p.K * sizeof(float));
+        w.headd = (float *)take((size_t)p.NWcap * sizeof(float));
+        w.taild = (float *)take((size_t)p.NWcap * sizeof(float));
+        w.dsplit = (int *)take((size_t)p.NWcap * sizeof(int));
     }
     return off;
 }
@@ -178,8 +177,8 @@ namespace gee {
 
 const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "p1_hist", "p1_scan", "p1_totals", "p1_scatter",
-    "p2_bucket", "prep_from_csr", "fill_empty", "embed_rows", "embed_fixup", "set_meta",
-    "batch_embed_rows", "batch_embed_fixup"};
+    "p2_bucket", "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty",
+    "embed_rows", "embed_fixup", "set_meta"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed)) return;
@@ -329,7 +328,7 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
     wk.col = col;
     wk.val = wgt ? val : nullptr;
     hipError_t e = launch_csr_build(src, dst, wgt, p, wk, st, s);
-    if (e == hipSuccess) e = launch_csr_pass2(p, wk, nullptr, false, st, s);
+    if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     return hip_status(e);
 }
 
@@ -375,8 +374,10 @@ int gee_embed_ws(const int32_t *src, const int32_t *dst, const float *wgt, int64
     hipStream_t s = as_stream(stream);
     hipError_t e = launch_class_counts(labels, N, K, p.cnt_blocks, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_csr_build(src, dst, wgt, p, wk, st, s);
-    if (e == hipSuccess) e = launch_csr_pass2(p, wk, labels, true, st, s);
-    if (e == hipSuccess) e = launch_embed(wk.rp, wk.col, p.weighted ? wk.val : nullptr, p, wk, Z, st, s);
+    if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
+    const float *val = p.weighted ? wk.val : nullptr;
+    if (e == hipSuccess) e = launch_node_prep(wk.rp, val, labels, p, wk, st, s);
+    if (e == hipSuccess) e = launch_embed(wk.rp, wk.col, val, p, wk, Z, st, s);
     return hip_status(e);
 }
 
@@ -428,7 +429,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     const int NW = M > 0 ? (int)((M + p.WE - 1) / p.WE) : 1;
     hipError_t e = launch_class_counts(labels, N, K, p.cnt_blocks, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_set_meta(wk.meta, (int)M, NW, s);
-    if (e == hipSuccess) e = launch_embed_prep_from_csr(row_ptr, val, labels, M, p, wk, st, s);
+    if (e == hipSuccess) e = launch_node_prep(row_ptr, val, labels, p, wk, st, s);
     if (e == hipSuccess) e = launch_embed(row_ptr, col, val, p, wk, Z, st, s);
     return hip_status(e);
 }

@@ -228,12 +228,7 @@ __global__ __launch_bounds__(256) void p2_bucket(const uint16_t *__restrict__ tk
                                                  const float *__restrict__ tval,
                                                  const int *__restrict__ bstart, int B, int sb, int N,
                                                  int *__restrict__ rp, int *__restrict__ col,
-                                                 float *__restrict__ val, int prep, unsigned flags,
-                                                 const int *__restrict__ labels, int K,
-                                                 const float *__restrict__ inv_n,
-                                                 float2 *__restrict__ info, float *__restrict__ srow,
-                                                 int *__restrict__ fown, const int *__restrict__ meta,
-                                                 int WE) {
+                                                 float *__restrict__ val) {
     extern __shared__ int smem_i[];
     __shared__ int wsum[4];
     const int R = 1 << sb;
@@ -264,54 +259,6 @@ __global__ __launch_bounds__(256) void p2_bucket(const uint16_t *__restrict__ tk
             col[e0 + pos] = tcol[e];
             if (val) val[e0 + pos] = tval[e];
         }
-    }
-    // After C, row i of the bucket spans [run[i-1], run[i]) relative to e0 (run[-1] = 0).
-    if (!prep) return;
-    __threadfence();
-    __syncthreads();
-    const bool lap = flags & kLap, diag = flags & kDiag;
-    float *degs = reinterpret_cast<float *>(tab);  // [R] (tab is 4R bytes)
-    if (lap) {
-        if (val) {
-            const int lane = lane_id();
-            for (int i = threadIdx.x >> 6; i < Rb; i += 4) {
-                const int lo = e0 + (i ? run[i - 1] : 0), hi = e0 + run[i];
-                float s = 0.0f;
-                for (int e = lo + lane; e < hi; e += 64) s += val[e];
-                s = wave_sum(s);
-                if (lane == 0) degs[i] = s;
-            }
-        } else {
-            for (int i = threadIdx.x; i < Rb; i += blockDim.x) degs[i] = (float)(run[i] - (i ? run[i - 1] : 0));
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < Rb; i += blockDim.x) {
-        const int r = r0 + i;
-        int y = labels[r];
-        if (y < 0 || y >= K) y = -1;
-        float s = 1.0f;
-        if (lap) {
-            const float d = degs[i] + (diag ? 1.0f : 0.0f);
-            s = d > 0.0f ? 1.0f / sqrtf(d) : 0.0f;
-            srow[r] = s;
-        }
-        const float coef = y >= 0 ? s * inv_n[y] : 0.0f;
-        info[r] = make_float2(coef, __int_as_float(y));
-    }
-    // Embed wavefront w owns the rows starting in [w*WE, (w+1)*WE); fown[w] is the first
-    // row whose start is >= w*WE. Rows r0+1 .. r0+Rb claim the wavefronts w with
-    // row_ptr[r-1] < w*WE <= row_ptr[r].
-    const int NW = meta[1];
-    for (int i = threadIdx.x + 1; i <= Rb; i += blockDim.x) {
-        const int64_t lo = e0 + (i - 1 ? run[i - 2] : 0);
-        const int64_t hi = e0 + run[i - 1];
-        const int64_t wa = lo / WE + 1, wb = min(hi / WE, (int64_t)NW - 1);
-        for (int64_t ww = wa; ww <= wb; ++ww) fown[ww] = r0 + i;
-    }
-    if (threadIdx.x == 0) {
-        if (b == 0) fown[0] = 0;
-        if (b == B - 1) fown[NW] = N;
     }
 }
 
@@ -344,15 +291,13 @@ hipError_t launch_csr_build(const int *src, const int *dst, const float *w, cons
     return hipGetLastError();
 }
 
-hipError_t launch_csr_pass2(const Plan &p, const Work &wk, const int *labels, bool embed_prep,
-                            unsigned *status, hipStream_t s) {
+hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
     (void)status;
     const int R = 1 << p.sb;
     prof_begin(kKP2Bucket, s);
     hipLaunchKernelGGL(p2_bucket, dim3(p.B), dim3(256), R * 8, s, wk.tkey, wk.tcol,
                        p.weighted ? wk.tval : nullptr, wk.bstart, p.B, p.sb, p.N, wk.rp, wk.col,
-                       p.weighted ? wk.val : nullptr, embed_prep ? 1 : 0, p.flags, labels, p.K,
-                       wk.inv_n, wk.info, wk.srow, wk.fown, wk.meta, p.WE);
+                       p.weighted ? wk.val : nullptr);
     prof_end(kKP2Bucket, s);
     return hipGetLastError();
 }

@@ -40,18 +40,67 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// DPP lane moves (GFX9 encodings: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143). A lane with no source (or masked off) gets `old`.
+template <int CTRL, int ROWS = 0xF, bool BC = false>
+__device__ __forceinline__ int dpp_i(int x, int old) {
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWS, 0xF, BC);
 }
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f(float x, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROWS,
+                                                       0xF, false));
+}
+__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Inclusive prefix sums over the 64 lanes with DPP (no LDS round trips): shifts of
+// 1, 2, 4, 8 inside each row of 16 lanes, then lane 15 of rows 0/2 into rows 1/3 and
+// lane 31 into rows 2/3. Fixed combination order.
+__device__ __forceinline__ int wave_scan_add(int x) {
+    x += dpp_i<0x111>(x, 0);
+    x += dpp_i<0x112>(x, 0);
+    x += dpp_i<0x114>(x, 0);
+    x += dpp_i<0x118>(x, 0);
+    x += dpp_i<0x142, 0xA>(x, 0);
+    x += dpp_i<0x143, 0xC>(x, 0);
+    return x;
+}
+__device__ __forceinline__ float wave_scan_addf(float x) {
+    x += dpp_f<0x111>(x, 0.0f);
+    x += dpp_f<0x112>(x, 0.0f);
+    x += dpp_f<0x114>(x, 0.0f);
+    x += dpp_f<0x118>(x, 0.0f);
+    x += dpp_f<0x142, 0xA>(x, 0.0f);
+    x += dpp_f<0x143, 0xC>(x, 0.0f);
+    return x;
+}
+// Inclusive prefix sums restarted wherever the key changes (keys non-decreasing).
+__device__ __forceinline__ float wave_seg_scan_addf(float x, int key) {
+#define GEE_SEG_STEP(CTRL, ROWS)                                   \
+    {                                                              \
+        const float xs = dpp_f<CTRL, ROWS>(x, 0.0f);               \
+        const int ks = dpp_i<CTRL, ROWS>(key, INT32_MIN);          \
+        x += (ks == key) ? xs : 0.0f;                              \
+    }
+    GEE_SEG_STEP(0x111, 0xF)
+    GEE_SEG_STEP(0x112, 0xF)
+    GEE_SEG_STEP(0x114, 0xF)
+    GEE_SEG_STEP(0x118, 0xF)
+    GEE_SEG_STEP(0x142, 0xA)
+    GEE_SEG_STEP(0x143, 0xC)
+#undef GEE_SEG_STEP
+    return x;
+}
+// Sum over the whole wavefront, the same value on every lane.
+__device__ __forceinline__ float wave_sum(float v) { return readlane_f(wave_scan_addf(v), 63); }
 __device__ __forceinline__ int wave_max_i(int v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
 }
-__device__ __forceinline__ int readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-
 __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     atomicOr(status, bit);
 }
@@ -93,10 +142,14 @@ struct Work {
     float *val = nullptr;      // [Mcap] (weighted only)
     float2 *info = nullptr;    // [N] {coefficient, label bits}
     float *srow = nullptr;     // [N] D^-1/2 (Laplacian)
-    int *fown = nullptr;       // [NWcap + 1] first row owned by each embed wavefront
+    int *wrow = nullptr;       // [NWcap] row holding each embed wavefront's first entry
+    uint8_t *rstep = nullptr;  // [Mcap] row step from the previous CSR entry (see gee_embed.hip)
     int *split = nullptr;      // [NWcap]
     float *headp = nullptr;    // [NWcap * K]
     float *tailp = nullptr;    // [NWcap * K]
+    float *headd = nullptr;    // [NWcap] degree partials (weighted Laplacian)
+    float *taild = nullptr;    // [NWcap]
+    int *dsplit = nullptr;     // [NWcap]
 };
 
 // ----------------------------------------------------------------------------- profiling
@@ -104,8 +157,8 @@ struct Work {
 // caller's hipEvents on the launch stream right before / after a kernel launch.
 enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKP1Hist, kKP1Scan, kKP1Totals, kKP1Scatter, kKP2Bucket,
-    kKPrepCsr, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKSetMeta, kKBatchEmbed, kKBatchFixup,
-    kKNumKernels
+    kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup, kKFillEmpty, kKEmbedRows, kKEmbedFixup,
+    kKSetMeta, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
@@ -118,12 +171,13 @@ hipError_t launch_class_counts(const int *labels, int N, int K, int nblocks, int
 // gee_csr.hip
 hipError_t launch_csr_build(const int *src, const int *dst, const float *w, const Plan &p,
                             const Work &wk, unsigned *status, hipStream_t s);
-// Pass 2 also prepares the embedding's per-node data when `embed_prep` is set.
-hipError_t launch_csr_pass2(const Plan &p, const Work &wk, const int *labels, bool embed_prep,
-                            unsigned *status, hipStream_t s);
+hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 // gee_embed.hip
-hipError_t launch_embed_prep_from_csr(const int *rp, const float *val, const int *labels, int64_t M,
-                                      const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
+// Per-node data (ownership, degrees, s_i, c_i); meta[0..1] = {M, wavefronts} must be set.
+hipError_t launch_node_prep(const int *rp, const float *val, const int *labels, const Plan &p,
+                            const Work &wk, unsigned *status, hipStream_t s);
+hipError_t launch_set_meta(int *meta, int M, int NW, hipStream_t s);
+size_t embed_lds_per_wave(int K);
 hipError_t launch_embed(const int *rp, const int *col, const float *val, const Plan &p,
                         const Work &wk, float *Z, unsigned *status, hipStream_t s);
 
