@@ -28,8 +28,9 @@ sys.path.insert(0, ROOT)
 METRIC = "edges embedded/sec + % HBM peak; served p50/p99 latency vs plain per-graph loop"
 HBM_PEAK_GBS = 8000.0
 
-KERNELS = ["class_count_partial", "class_count_final", "p1_hist", "p1_scan", "p1_totals", "p1_scatter",
-           "p2_bucket", "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"]
+KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
+           "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps", "node_rows", "degree_rows",
+           "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"]
 
 
 def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
@@ -38,12 +39,16 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
     wv = 4 if weighted else 0
     if name == "class_count_partial":
         return 4 * N
-    if name == "p1_hist":
+    if name == "a_hist":
         return 8 * E
-    if name == "p1_scatter":
-        return (8 + wv) * E + (2 + 4 + wv) * M
-    if name == "p2_bucket":
-        return (2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)
+    if name == "a_scatter":  # edge list in, (row, col[, w]) per entry out
+        return (8 + wv) * E + (4 + 4 + wv) * M
+    if name == "b_hist":
+        return 4 * M
+    if name == "b_scatter":  # (row, col[, w]) in, (row in bucket u16, col[, w]) out
+        return (4 + 4 + wv) * M + (2 + 4 + wv) * M
+    if name == "bucket_sort":  # keys read twice (count, then rank), col/val once; CSR out
+        return (2 + 2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)
     if name == "node_rows":
         return 4 * (N + 1) + 4 * N + 8 * N + 4 * N
     if name == "degree_rows":

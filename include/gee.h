@@ -85,9 +85,10 @@ typedef enum {
 typedef struct {
     int32_t wave_entries;   /* CSR entries per wavefront in the embed kernel (power of 2, 256..16384) */
     int32_t waves_per_block;/* wavefronts per workgroup in the embed kernel (1, 2 or 4) */
-    int32_t tile_entries;   /* edge-list entries per workgroup tile of the CSR partition pass
-                               (power of 2, 2048..65536) */
-    int32_t bucket_rows_log2; /* rows per partition bucket = 2^this (0 = automatic, else 0..12) */
+    int32_t tile_entries;   /* entries per workgroup tile of the CSR partition passes; this
+                               build supports only 4096 (0 = default) */
+    int32_t bucket_rows_log2; /* rows per CSR sort bucket = 2^this (0 = automatic, else 1..12;
+                                 raised to what keeps the bucket count <= 65536) */
 } gee_schedule;
 
 int gee_abi_version(void);
@@ -104,9 +105,10 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
 /* Profiling hook (for benchmarks and tests). From this call on, every launch of the named
    kernel records hipEvent `start_event` on its stream right before the launch and
    `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
-   Kernel names: "class_count_partial", "class_count_final", "p1_hist", "p1_scan",
-   "p1_totals", "p1_scatter", "p2_bucket", "zero_steps", "node_rows", "degree_rows", "degree_fixup",
-   "fill_empty", "embed_rows", "embed_fixup", "set_meta". The caller owns the
+   Kernel names: "class_count_partial", "class_count_final", "a_hist", "digit_scan",
+   "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps",
+   "node_rows", "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup",
+   "set_meta". The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);

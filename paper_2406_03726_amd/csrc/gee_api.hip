@@ -74,38 +74,41 @@ int make_plan(int64_t E, int32_t N, int32_t K, uint32_t flags, bool weighted, co
     p.weighted = weighted;
     p.Mcap = (flags & GEE_SYMMETRIZE) ? 2 * E : E;
     if (p.Mcap > kMaxEntries) return GEE_ERR_TOO_LARGE;
-    // buckets of 2^sb rows: at most 4096 buckets, aiming at ~8k entries per bucket
-    int sb_min = 0;
-    while (((int64_t)N + (1 << sb_min) - 1) >> sb_min > kMaxBuckets) ++sb_min;
+    // buckets of 2^sb rows, about 3000 entries each on average; at most 65536 buckets
+    const int sb_min = ilog2_ceil(N > 0 ? N : 1) > 16 ? ilog2_ceil(N) - 16 : 0;
     if (sb_min > kMaxBucketRowsLog2) return GEE_ERR_TOO_LARGE;
-    int64_t bt = p.Mcap / 8192;
-    bt = bt < 1 ? 1 : (bt > kMaxBuckets ? kMaxBuckets : bt);
-    int sb = ilog2_ceil(((int64_t)N + bt - 1) / bt);
+    int sb = 0;
+    if (p.Mcap > 0) {
+        const double rows = 3000.0 * (double)(N > 0 ? N : 1) / (double)p.Mcap;
+        while (sb < kMaxBucketRowsLog2 && (double)(2 << sb) <= rows) ++sb;
+    } else {
+        sb = kMaxBucketRowsLog2;
+    }
     if (sc && sc->bucket_rows_log2 > 0) sb = sc->bucket_rows_log2;
     if (sb < sb_min) sb = sb_min;
     if (sb > kMaxBucketRowsLog2) sb = kMaxBucketRowsLog2;
     p.sb = sb;
-    p.B = (int32_t)(((int64_t)N + (1 << sb) - 1) >> sb);
-    if (p.B < 1) p.B = 1;
-    p.tile = 16384;
-    if (sc && sc->tile_entries) {
-        if (!is_pow2(sc->tile_entries) || sc->tile_entries < 2048 || sc->tile_entries > 65536)
-            return GEE_ERR_ARG;
-        p.tile = sc->tile_entries;
-    }
-    p.T1 = (p.Mcap + p.tile - 1) / p.tile;
-    if (p.T1 < 1) p.T1 = 1;
+    p.B = (int32_t)(((int64_t)(N > 0 ? N : 1) + (1 << sb) - 1) >> sb);
+    const int nbB = ilog2_ceil(p.B);
+    p.s2 = nbB <= 8 ? 0 : (nbB - 8 > nbB / 2 ? nbB - 8 : nbB / 2);
+    p.DA = (int)(((int64_t)p.B + (1 << p.s2) - 1) >> p.s2);
+    p.tile = 4096;
+    if (sc && sc->tile_entries && sc->tile_entries != p.tile) return GEE_ERR_ARG;
+    p.TA = (p.Mcap + p.tile - 1) / p.tile;
+    if (p.TA < 1) p.TA = 1;
+    p.TBcap = p.s2 > 0 ? p.TA + p.DA : 1;
     // embed: entries per wavefront
-    int we = p.Mcap >= (8 << 20) ? 2048 : (p.Mcap >= (1 << 20) ? 1024 : 512);
+    int we = p.Mcap >= (1 << 20) ? 1024 : 512;
     if (sc && sc->wave_entries) {
         if (!is_pow2(sc->wave_entries) || sc->wave_entries < 256 || sc->wave_entries > 16384)
             return GEE_ERR_ARG;
         we = sc->wave_entries;
     }
     p.WE = we;
+    // one wavefront per workgroup by default: the LDS ring of each wavefront then limits
+    // residency least (more wavefronts in flight per CU)
     const size_t per_wave = embed_lds_per_wave(K);
-    int wpb = (int)(65536 / per_wave);
-    wpb = wpb > 4 ? 4 : (wpb < 1 ? 1 : wpb);
+    int wpb = 1;
     if (sc && sc->waves_per_block) {
         if (sc->waves_per_block < 1 || sc->waves_per_block > 4) return GEE_ERR_ARG;
         if ((size_t)sc->waves_per_block * per_wave <= 65536) wpb = sc->waves_per_block;
@@ -134,10 +137,14 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.cpart = (int *)take((size_t)p.cnt_blocks * p.K * sizeof(int));
     }
     if (parts & kPPart) {
-        w.ghist = (int *)take((size_t)p.B * p.T1 * sizeof(int));
-        w.btot = (int *)take((size_t)p.B * sizeof(int));
+        w.ghA = (int *)take((size_t)p.DA * p.TA * sizeof(int));
+        w.totA = (int *)take((size_t)p.DA * sizeof(int));
+        w.segA = (int *)take((size_t)(p.DA + 1) * sizeof(int));
+        w.tileB = (int *)take((size_t)(p.DA + 1) * sizeof(int));
+        if (p.s2 > 0) w.ghB = (int *)take(((size_t)p.TBcap << p.s2) * sizeof(int));
         w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
-        w.tkey = (uint16_t *)take((size_t)p.Mcap * sizeof(uint16_t));
+        w.akey = (int *)take((size_t)p.Mcap * sizeof(int));
+        if (p.s2 > 0) w.tkey = (uint16_t *)take((size_t)p.Mcap * sizeof(uint16_t));
         w.tcol = (int *)take((size_t)p.Mcap * sizeof(int));
         if (p.weighted) w.tval = (float *)take((size_t)p.Mcap * sizeof(float));
     }
@@ -176,8 +183,8 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 namespace gee {
 
 const char *const kKernelNames[kKNumKernels] = {
-    "class_count_partial", "class_count_final", "p1_hist", "p1_scan", "p1_totals", "p1_scatter",
-    "p2_bucket", "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty",
+    "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
+    "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty",
     "embed_rows", "embed_fixup", "set_meta"};
 
 void prof_begin(int kid, hipStream_t s) {

@@ -3,26 +3,33 @@
 // The adjacency entries of an edge list are the rows themselves and, under
 // symmetrization, their mirrors: virtual entry 2e is (src_e -> dst_e) and 2e+1 is
 // (dst_e -> src_e), the latter absent for a self-loop. The CSR is a stable sort of
-// that sequence by row index, done as a two-level most-significant-digit partition:
+// that sequence by row index. Rows are grouped in buckets of 2^sb consecutive rows
+// (a few thousand entries each); the bucket id is split into a high digit (at most 256
+// values) and a low digit (2^s2 values), and the sort is three stable passes:
 //
-//   pass 1  partition by bucket = row >> sb (at most 4096 buckets):
-//           p1_hist       per-tile bucket histograms (LDS), written bucket-major
-//           p1_scan       exclusive scan of each bucket's tile counts
-//           p1_totals     exclusive scan of bucket totals -> bucket starts, M
-//           p1_scatter    stable in-tile rank per bucket -> partitioned entries
-//   pass 2  one workgroup per bucket: count rows (LDS), scan -> row_ptr, stable rank by
-//           row within the bucket -> col/val at their final CSR slots. When the
-//           embedding follows, the same workgroup also reads back its rows to form the
-//           degrees, the per-node coefficients and the embed wavefront ownership.
+//   pass A  partition the virtual entries by high digit      (a_hist, digit_scan,
+//                                                              a_totals, a_scatter)
+//   pass B  partition each high-digit segment by low digit    (b_hist, b_scan, b_scatter)
+//   pass C  one workgroup per bucket: row counts -> row_ptr, then the entries of the
+//           bucket in row order                               (bucket_sort)
 //
-// Stable ranking never uses global atomics: within a 64-wide wavefront, lanes with
-// the same digit are found by ballots over the digit bits; across the wavefronts of
-// a round a small per-wave count table in LDS gives the offset; the running counts per
-// digit live in LDS for the whole tile/bucket, so the order of equal digits is the
-// input order.
+// With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
+//
+// Every partition pass works on tiles of 4096 entries: the tile's entries are ranked
+// by digit (stable) and staged in LDS in digit order, then written out so that
+// consecutive threads write consecutive addresses of each digit's run; no pass writes
+// scattered single words. Stable ranks never use global atomics: within a 64-wide
+// wavefront, lanes with the same digit are found by ballots over the digit bits;
+// across the wavefronts of a round a small per-wave count table in LDS gives the
+// offset; running counts per digit live in LDS for the whole tile, so equal digits
+// keep the input order. Tile offsets come from per-tile histograms scanned on the
+// device, digit-major, so pass outputs are the same for every launch.
 #include "gee_internal.h"
 
 namespace gee {
+
+constexpr int kTile = 4096;    // entries per partition tile: 16 rounds of 256 threads
+constexpr int kRounds = kTile / 256;
 
 // ----------------------------------------------------------------------------- helpers
 
@@ -94,211 +101,439 @@ __device__ int block_excl_scan_lds(int *a, int n, int *wsum) {
     return total;
 }
 
-// ----------------------------------------------------------------------------- pass 1
+// ----------------------------------------------------------------------------- pass A
 
-__global__ __launch_bounds__(256) void p1_hist(const int *__restrict__ src, const int *__restrict__ dst,
-                                               int64_t E, int N, int sym, int sb, int B, int tile,
-                                               int64_t T1, int *__restrict__ ghist, unsigned *status) {
-    extern __shared__ int hist[];
-    for (int b = threadIdx.x; b < B; b += blockDim.x) hist[b] = 0;
+// Valid virtual entry v: row key, column, weight. Invalid: index out of range, or the
+// mirror of a self-loop under symmetrization.
+__device__ __forceinline__ bool load_virtual(const int *__restrict__ src, const int *__restrict__ dst,
+                                             const float *__restrict__ w, int64_t v, int64_t V, int N,
+                                             int sym, int &key, int &cl, float &val, bool &badw) {
+    if (v >= V) return false;
+    const int64_t e = sym ? (v >> 1) : v;
+    const int side = sym ? (int)(v & 1) : 0;
+    const int s = src[e], d = dst[e];
+    key = side ? d : s;
+    cl = side ? s : d;
+    if (w) {
+        val = w[e];
+        if (side == 0 && !isfinite(val)) badw = true;
+    }
+    return (unsigned)s < (unsigned)N && (unsigned)d < (unsigned)N && (side == 0 || s != d);
+}
+
+// Per tile of virtual entries: histogram of the high digit (row >> shift), written
+// digit-major; index checks.
+__global__ __launch_bounds__(256) void a_hist(const int *__restrict__ src, const int *__restrict__ dst,
+                                              int64_t E, int N, int sym, int shift, int D, int64_t T,
+                                              int *__restrict__ gh, unsigned *status) {
+    __shared__ int hist[256];
+    hist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
     const int64_t V = sym ? 2 * E : E;
-    const int64_t v0 = t * tile;
-    const int64_t v1 = min(v0 + tile, V);
+    const int64_t v0 = t * kTile;
+    const int64_t v1 = min(v0 + kTile, V);
     bool bad = false;
     const int64_t e0 = sym ? v0 / 2 : v0;
     const int64_t e1 = sym ? (v1 + 1) / 2 : v1;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
         const int s = src[e], d = dst[e];
         if ((unsigned)s < (unsigned)N && (unsigned)d < (unsigned)N) {
-            atomicAdd(&hist[s >> sb], 1);
-            if (sym && s != d) atomicAdd(&hist[d >> sb], 1);
+            atomicAdd(&hist[s >> shift], 1);
+            if (sym && s != d) atomicAdd(&hist[d >> shift], 1);
         } else {
             bad = true;
         }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrIndex);
-    for (int b = threadIdx.x; b < B; b += blockDim.x) ghist[(int64_t)b * T1 + t] = hist[b];
+    if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
 }
 
-// One workgroup per bucket: exclusive scan over the bucket's tile counts.
-__global__ __launch_bounds__(256) void p1_scan(int *__restrict__ ghist, int64_t T1,
-                                               int *__restrict__ btot) {
+// One workgroup per digit d: exclusive scan of the row gh[d*T .. d*T+T) in place;
+// tot[d] = its sum.
+__global__ __launch_bounds__(256) void digit_scan(int *__restrict__ gh, int64_t T, int *__restrict__ tot) {
     __shared__ int wsum[4];
-    int *row = ghist + (int64_t)blockIdx.x * T1;
+    int *row = gh + (int64_t)blockIdx.x * T;
     int carry = 0;
     constexpr int IPT = 8;
-    for (int64_t c = 0; c < T1; c += 256 * IPT) {
+    for (int64_t c = 0; c < T; c += 256 * IPT) {
         int vals[IPT];
         int s = 0;
         const int64_t lo = c + (int64_t)threadIdx.x * IPT;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            vals[i] = (lo + i < T1) ? row[lo + i] : 0;
+            vals[i] = (lo + i < T) ? row[lo + i] : 0;
             s += vals[i];
         }
         int total;
         int base = block_excl_scan256(s, wsum, total) + carry;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-            if (lo + i < T1) row[lo + i] = base;
+            if (lo + i < T) row[lo + i] = base;
             base += vals[i];
         }
         carry += total;
     }
-    if (threadIdx.x == 0) btot[blockIdx.x] = carry;
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Single workgroup: bucket starts, total entry count M and the embed wavefront count.
-__global__ __launch_bounds__(256) void p1_totals(const int *__restrict__ btot, int B,
-                                                 int *__restrict__ bstart, int *__restrict__ meta,
-                                                 int WE) {
+// Single workgroup over the D <= 256 high digits: segment starts, the entry count M,
+// the embed wavefront count, and (with a pass B) the pass-B tiles of every segment.
+// Without a pass B the segments are the buckets.
+__global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int D, int with_b, int B,
+                                                int *__restrict__ seg_start, int *__restrict__ tile_off,
+                                                int *__restrict__ bstart, int *__restrict__ meta, int WE) {
     __shared__ int wsum[4];
-    const int per = (B + 255) / 256;
-    const int lo = threadIdx.x * per;
-    int s = 0;
-    for (int i = 0; i < per; ++i)
-        if (lo + i < B) s += btot[lo + i];
+    const int d = threadIdx.x;
+    const int n = d < D ? tot[d] : 0;
     int total;
-    int base = block_excl_scan256(s, wsum, total);
-    for (int i = 0; i < per; ++i)
-        if (lo + i < B) {
-            bstart[lo + i] = base;
-            base += btot[lo + i];
-        }
-    if (threadIdx.x == 0) {
+    const int st = block_excl_scan256(n, wsum, total);
+    const int nt = (n + kTile - 1) / kTile;
+    int ttot;
+    const int to = block_excl_scan256(with_b ? nt : 0, wsum, ttot);
+    if (d < D) {
+        seg_start[d] = st;
+        if (with_b) tile_off[d] = to;
+        if (!with_b && d < B) bstart[d] = st;
+    }
+    if (d == 0) {
+        seg_start[D] = total;
+        if (with_b) tile_off[D] = ttot;
         bstart[B] = total;
         meta[0] = total;
         meta[1] = total > 0 ? (int)(((int64_t)total + WE - 1) / WE) : 1;
     }
 }
 
-__global__ __launch_bounds__(256) void p1_scatter(const int *__restrict__ src, const int *__restrict__ dst,
-                                                  const float *__restrict__ w, int64_t E, int N, int sym,
-                                                  int sb, int B, int nbits, int tile, int64_t T1,
-                                                  const int *__restrict__ ghist,
-                                                  const int *__restrict__ bstart,
-                                                  uint16_t *__restrict__ tkey, int *__restrict__ tcol,
-                                                  float *__restrict__ tval, unsigned *status) {
-    extern __shared__ int smem_i[];
-    int *run = smem_i;                                        // [B]
-    unsigned char *tab = reinterpret_cast<unsigned char *>(run + B);  // [4][B]
-    const int64_t t = blockIdx.x;
-    for (int b = threadIdx.x; b < B; b += blockDim.x) run[b] = bstart[b] + ghist[(int64_t)b * T1 + t];
-    for (int i = threadIdx.x; i < 4 * B; i += blockDim.x) tab[i] = 0;
+// Shared by the partition scatters: this tile's digit counts -> LDS local starts,
+// running ranks and global bases. cnt is this thread's digit count (digit = thread).
+__device__ __forceinline__ int tile_layout(int cnt, int gbase_d, int D, int *lstart, int *run, int *gbase,
+                                           unsigned char *tab, int *wsum) {
+    int total;
+    const int ls = block_excl_scan256(cnt, wsum, total);
+    if ((int)threadIdx.x < D) {
+        lstart[threadIdx.x] = ls;
+        run[threadIdx.x] = ls;
+        gbase[threadIdx.x] = gbase_d;
+    }
+    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) tab[i] = 0;
     __syncthreads();
+    return total;
+}
+
+struct PartLds {
+    int lstart[256], run[256], gbase[256], wsum[4];
+    unsigned char tab[4 * 256];
+    int key[kTile];
+    int col[kTile];
+    float val[kTile];
+};
+
+// Pass A scatter: tile t of the virtual entries, ranked by high digit, staged, and
+// written to seg_start[d] + (scanned tile offset) in runs.
+__global__ __launch_bounds__(256) void a_scatter(const int *__restrict__ src, const int *__restrict__ dst,
+                                                 const float *__restrict__ w, int64_t E, int N, int sym,
+                                                 int shift, int D, int nbits, int64_t T,
+                                                 const int *__restrict__ gh, const int *__restrict__ tot,
+                                                 const int *__restrict__ seg_start, int *__restrict__ okey,
+                                                 int *__restrict__ ocol, float *__restrict__ oval,
+                                                 unsigned *status) {
+    __shared__ PartLds L;
+    const int64_t t = blockIdx.x;
+    int cnt = 0, gb = 0;
+    if ((int)threadIdx.x < D) {
+        const int64_t i = (int64_t)threadIdx.x * T + t;
+        const int cur = gh[i];
+        const int nxt = (t + 1 < T) ? gh[i + 1] : tot[threadIdx.x];
+        cnt = nxt - cur;
+        gb = seg_start[threadIdx.x] + cur;
+    }
+    const int n = tile_layout(cnt, gb, D, L.lstart, L.run, L.gbase, L.tab, L.wsum);
     const int64_t V = sym ? 2 * E : E;
-    const int64_t v0 = t * tile;
-    const int64_t v1 = min(v0 + tile, V);
-    const int lowmask = (1 << sb) - 1;
+    const int64_t v0 = t * kTile;
     bool badw = false;
-    for (int64_t vb = v0; vb < v1; vb += 256) {
-        const int64_t v = vb + threadIdx.x;
-        bool valid = false;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t v = v0 + r * 256 + threadIdx.x;
         int key = 0, cl = 0;
         float val = 1.0f;
-        if (v < v1) {
-            const int64_t e = sym ? (v >> 1) : v;
-            const int side = sym ? (int)(v & 1) : 0;
-            const int s = src[e], d = dst[e];
-            valid = (unsigned)s < (unsigned)N && (unsigned)d < (unsigned)N && (side == 0 || s != d);
-            key = side ? d : s;
-            cl = side ? s : d;
-            if (w) {
-                val = w[e];
-                if (side == 0 && !isfinite(val)) badw = true;
-            }
-        }
-        const int digit = valid ? (key >> sb) : 0;
-        const int pos = block_rank4(digit, valid, nbits, tab, run, B);
+        const bool valid = load_virtual(src, dst, w, v, V, N, sym, key, cl, val, badw);
+        const int digit = valid ? (key >> shift) : 0;
+        const int pos = block_rank4(digit, valid, nbits, L.tab, L.run, D);
         if (valid) {
-            tkey[pos] = (uint16_t)(key & lowmask);
-            tcol[pos] = cl;
-            if (tval) tval[pos] = val;
+            L.key[pos] = key;
+            L.col[pos] = cl;
+            if (oval) L.val[pos] = val;
         }
     }
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int key = L.key[i];
+        const int d = key >> shift;
+        const int64_t g = (int64_t)L.gbase[d] + (i - L.lstart[d]);
+        okey[g] = key;
+        ocol[g] = L.col[i];
+        if (oval) oval[g] = L.val[i];
+    }
 }
 
-// ----------------------------------------------------------------------------- pass 2
+// ----------------------------------------------------------------------------- pass B
 
-__global__ __launch_bounds__(256) void p2_bucket(const uint16_t *__restrict__ tkey,
-                                                 const int *__restrict__ tcol,
-                                                 const float *__restrict__ tval,
-                                                 const int *__restrict__ bstart, int B, int sb, int N,
-                                                 int *__restrict__ rp, int *__restrict__ col,
-                                                 float *__restrict__ val) {
+// Pass-B tile j -> (segment d, tile within segment); returns false past the last tile.
+__device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, int D, int j, int &d, int &jt,
+                                       int &ntd) {
+    if (j >= tile_off[D]) return false;
+    int lo = 0, hi = D;  // last d with tile_off[d] <= j
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    d = lo;
+    jt = j - tile_off[d];
+    ntd = tile_off[d + 1] - tile_off[d];
+    return true;
+}
+
+// Per pass-B tile: histogram of the low digit; segment d's counts are stored
+// low-digit-major at gh + tile_off[d] * 2^s2, [digit][tile].
+__global__ __launch_bounds__(256) void b_hist(const int *__restrict__ akey, int sb, int s2,
+                                              const int *__restrict__ seg_start,
+                                              const int *__restrict__ tile_off, int D, int *__restrict__ gh) {
+    __shared__ int hist[256];
+    int d, jt, ntd;
+    if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
+    const int L = 1 << s2;
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int e0 = seg_start[d] + jt * kTile;
+    const int e1 = min(e0 + kTile, seg_start[d + 1]);
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&hist[(akey[e] >> sb) & (L - 1)], 1);
+    __syncthreads();
+    if ((int)threadIdx.x < L) gh[((int64_t)tile_off[d] << s2) + (int64_t)threadIdx.x * ntd + jt] = hist[threadIdx.x];
+}
+
+// One workgroup per segment d: exclusive scan of its [digit][tile] counts (positions
+// inside the segment) and the bucket starts of its 2^s2 buckets.
+__global__ __launch_bounds__(256) void b_scan(int *__restrict__ gh, int s2, const int *__restrict__ seg_start,
+                                              const int *__restrict__ tile_off, int B,
+                                              int *__restrict__ bstart) {
+    __shared__ int wsum[4];
+    const int d = blockIdx.x;
+    const int ntd = tile_off[d + 1] - tile_off[d];
+    const int L = 1 << s2;
+    const int64_t len = (int64_t)ntd << s2;
+    int *seg = gh + ((int64_t)tile_off[d] << s2);
+    int carry = 0;
+    constexpr int IPT = 8;
+    for (int64_t c = 0; c < len; c += 256 * IPT) {
+        int vals[IPT];
+        int s = 0;
+        const int64_t lo = c + (int64_t)threadIdx.x * IPT;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            vals[i] = (lo + i < len) ? seg[lo + i] : 0;
+            s += vals[i];
+        }
+        int total;
+        int base = block_excl_scan256(s, wsum, total) + carry;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            if (lo + i < len) seg[lo + i] = base;
+            base += vals[i];
+        }
+        carry += total;
+    }
+    __syncthreads();
+    const int s0 = seg_start[d];
+    for (int lo = threadIdx.x; lo < L; lo += blockDim.x) {
+        const int b = (d << s2) + lo;
+        if (b < B) bstart[b] = s0 + (ntd > 0 ? seg[(int64_t)lo * ntd] : 0);
+    }
+}
+
+// Pass B scatter: tile j of segment d, ranked by low digit, staged, written in runs;
+// the key becomes the row inside its bucket.
+__global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, const int *__restrict__ acol,
+                                                 const float *__restrict__ aval, int sb, int s2,
+                                                 const int *__restrict__ gh, const int *__restrict__ seg_start,
+                                                 const int *__restrict__ tile_off, int D,
+                                                 uint16_t *__restrict__ okey, int *__restrict__ ocol,
+                                                 float *__restrict__ oval) {
+    __shared__ PartLds L;
+    int d, jt, ntd;
+    if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
+    const int ND = 1 << s2;
+    const int s0 = seg_start[d];
+    const int nseg = seg_start[d + 1] - s0;
+    const int *seg = gh + ((int64_t)tile_off[d] << s2);
+    int cnt = 0, gb = 0;
+    if ((int)threadIdx.x < ND) {
+        const int64_t i = (int64_t)threadIdx.x * ntd + jt;
+        const int cur = seg[i];
+        const int nxt = (jt + 1 < ntd) ? seg[i + 1] : ((int)threadIdx.x + 1 < ND ? seg[i + 1] : nseg);
+        cnt = nxt - cur;
+        gb = s0 + cur;
+    }
+    const int n = tile_layout(cnt, gb, ND, L.lstart, L.run, L.gbase, L.tab, L.wsum);
+    const int e0 = s0 + jt * kTile;
+    const int e1 = min(e0 + kTile, s0 + nseg);
+    const int rmask = (1 << sb) - 1;
+    for (int r = 0; r < kRounds; ++r) {
+        const int e = e0 + r * 256 + threadIdx.x;
+        const bool valid = e < e1;
+        const int ec = valid ? e : e0;
+        const int key = akey[ec];
+        const int cl = acol[ec];
+        const float val = oval ? aval[ec] : 1.0f;
+        const int digit = valid ? ((key >> sb) & (ND - 1)) : 0;
+        const int pos = block_rank4(digit, valid, s2, L.tab, L.run, ND);
+        if (valid) {
+            L.key[pos] = key;
+            L.col[pos] = cl;
+            if (oval) L.val[pos] = val;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int key = L.key[i];
+        const int dg = (key >> sb) & (ND - 1);
+        const int64_t g = (int64_t)L.gbase[dg] + (i - L.lstart[dg]);
+        okey[g] = (uint16_t)(key & rmask);
+        ocol[g] = L.col[i];
+        if (oval) oval[g] = L.val[i];
+    }
+}
+
+// ----------------------------------------------------------------------------- pass C
+
+// One workgroup per bucket b (rows [b << sb, (b+1) << sb)): row counts in LDS, their
+// scan -> row_ptr, then a stable rank by row. A bucket of at most `cap` entries is
+// staged in LDS and written out contiguously; a larger one (it holds long rows) is
+// written at its ranks directly.
+template <typename KT>
+__global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, const int *__restrict__ tcol,
+                                                   const float *__restrict__ tval,
+                                                   const int *__restrict__ bstart, int B, int sb, int N,
+                                                   int *__restrict__ rp, int *__restrict__ col,
+                                                   float *__restrict__ val, int cap) {
     extern __shared__ int smem_i[];
     __shared__ int wsum[4];
     const int R = 1 << sb;
-    int *run = smem_i;                                        // [R]
+    int *run = smem_i;                                                 // [R]
     unsigned char *tab = reinterpret_cast<unsigned char *>(run + R);  // [4][R]
+    int *scol = reinterpret_cast<int *>(tab + 4 * R);                 // [cap]
+    float *sval = reinterpret_cast<float *>(scol + cap);              // [cap]
     const int b = blockIdx.x;
     const int r0 = b << sb;
     const int Rb = min(R, N - r0);
     const int e0 = bstart[b], e1 = bstart[b + 1];
-    // A: rows' entry counts
+    const int rmask = R - 1;
     for (int i = threadIdx.x; i < R; i += blockDim.x) run[i] = 0;
     for (int i = threadIdx.x; i < 4 * R; i += blockDim.x) tab[i] = 0;
     __syncthreads();
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&run[tkey[e]], 1);
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&run[(int)tkey[e] & rmask], 1);
     __syncthreads();
-    // B: row offsets -> row_ptr
     block_excl_scan_lds(run, R, wsum);
     for (int i = threadIdx.x; i < Rb; i += blockDim.x) rp[r0 + i] = e0 + run[i];
     if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
     __syncthreads();
-    // C: stable placement by row within the bucket
+    const bool staged = e1 - e0 <= cap;
     for (int eb = e0; eb < e1; eb += 256) {
         const int e = eb + threadIdx.x;
         const bool valid = e < e1;
-        const int digit = valid ? (int)tkey[e] : 0;
+        const int ec = valid ? e : e0;
+        const int digit = valid ? ((int)tkey[ec] & rmask) : 0;
+        const int cl = tcol[ec];
+        const float vv = val ? tval[ec] : 0.0f;
         const int pos = block_rank4(digit, valid, sb, tab, run, R);
         if (valid) {
-            col[e0 + pos] = tcol[e];
-            if (val) val[e0 + pos] = tval[e];
+            if (staged) {
+                scol[pos] = cl;
+                if (val) sval[pos] = vv;
+            } else {
+                col[e0 + pos] = cl;
+                if (val) val[e0 + pos] = vv;
+            }
+        }
+    }
+    if (staged) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < e1 - e0; i += blockDim.x) {
+            col[e0 + i] = scol[i];
+            if (val) val[e0 + i] = sval[i];
         }
     }
 }
 
 // ----------------------------------------------------------------------------- launch
 
+// Staging capacity of bucket_sort: the whole workgroup stays within 64 KiB of LDS.
+static int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
+size_t bucket_sort_lds(int sb) { return (size_t)(1 << sb) * 8 + (size_t)bucket_stage_cap(sb) * 8; }
+
 hipError_t launch_csr_build(const int *src, const int *dst, const float *w, const Plan &p,
                             const Work &wk, unsigned *status, hipStream_t s) {
     const int sym = (p.flags & kSym) ? 1 : 0;
+    const bool with_b = p.s2 > 0;
+    const int shift = p.sb + p.s2;
     int nbits = 0;
-    while ((1 << nbits) < p.B) ++nbits;
-    prof_begin(kKP1Hist, s);
-    hipLaunchKernelGGL(p1_hist, dim3((unsigned)p.T1), dim3(256), p.B * sizeof(int), s, src, dst, p.E,
-                       p.N, sym, p.sb, p.B, p.tile, p.T1, wk.ghist, status);
-    prof_end(kKP1Hist, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    prof_begin(kKP1Scan, s);
-    hipLaunchKernelGGL(p1_scan, dim3(p.B), dim3(256), 0, s, wk.ghist, p.T1, wk.btot);
-    prof_end(kKP1Scan, s);
+    while ((1 << nbits) < p.DA) ++nbits;
+    const float *wv = p.weighted ? w : nullptr;
+    // pass A output: final col/val buffers as scratch when a pass B follows
+    int *acol = with_b ? wk.col : wk.tcol;
+    float *aval = p.weighted ? (with_b ? wk.val : wk.tval) : nullptr;
+    hipError_t e;
+    prof_begin(kKAHist, s);
+    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(256), 0, s, src, dst, p.E, p.N, sym, shift, p.DA,
+                       p.TA, wk.ghA, status);
+    prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    prof_begin(kKP1Totals, s);
-    hipLaunchKernelGGL(p1_totals, dim3(1), dim3(256), 0, s, wk.btot, p.B, wk.bstart, wk.meta, p.WE);
-    prof_end(kKP1Totals, s);
+    prof_begin(kKAScan, s);
+    hipLaunchKernelGGL(digit_scan, dim3(p.DA), dim3(256), 0, s, wk.ghA, p.TA, wk.totA);
+    prof_end(kKAScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    prof_begin(kKP1Scatter, s);
-    hipLaunchKernelGGL(p1_scatter, dim3((unsigned)p.T1), dim3(256), p.B * 8, s, src, dst,
-                       p.weighted ? w : nullptr, p.E, p.N, sym, p.sb, p.B, nbits, p.tile, p.T1,
-                       wk.ghist, wk.bstart, wk.tkey, wk.tcol, p.weighted ? wk.tval : nullptr, status);
-    prof_end(kKP1Scatter, s);
+    prof_begin(kKATotals, s);
+    hipLaunchKernelGGL(a_totals, dim3(1), dim3(256), 0, s, wk.totA, p.DA, with_b ? 1 : 0, p.B, wk.segA,
+                       wk.tileB, wk.bstart, wk.meta, p.WE);
+    prof_end(kKATotals, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKAScatter, s);
+    hipLaunchKernelGGL(a_scatter, dim3((unsigned)p.TA), dim3(256), 0, s, src, dst, wv, p.E, p.N, sym, shift,
+                       p.DA, nbits, p.TA, wk.ghA, wk.totA, wk.segA, wk.akey, acol, aval, status);
+    prof_end(kKAScatter, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!with_b) return hipSuccess;
+    prof_begin(kKBHist, s);
+    hipLaunchKernelGGL(b_hist, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA, wk.tileB,
+                       p.DA, wk.ghB);
+    prof_end(kKBHist, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKBScan, s);
+    hipLaunchKernelGGL(b_scan, dim3(p.DA), dim3(256), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart);
+    prof_end(kKBScan, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKBScatter, s);
+    hipLaunchKernelGGL(b_scatter, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval, p.sb, p.s2,
+                       wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol, p.weighted ? wk.tval : nullptr);
+    prof_end(kKBScatter, s);
     return hipGetLastError();
 }
 
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
     (void)status;
-    const int R = 1 << p.sb;
-    prof_begin(kKP2Bucket, s);
-    hipLaunchKernelGGL(p2_bucket, dim3(p.B), dim3(256), R * 8, s, wk.tkey, wk.tcol,
-                       p.weighted ? wk.tval : nullptr, wk.bstart, p.B, p.sb, p.N, wk.rp, wk.col,
-                       p.weighted ? wk.val : nullptr);
-    prof_end(kKP2Bucket, s);
+    const size_t lds = bucket_sort_lds(p.sb);
+    const int cap = bucket_stage_cap(p.sb);
+    const float *tv = p.weighted ? wk.tval : nullptr;
+    float *ov = p.weighted ? wk.val : nullptr;
+    prof_begin(kKBucketSort, s);
+    if (p.s2 > 0) {
+        hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, wk.tkey, wk.tcol, tv, wk.bstart,
+                           p.B, p.sb, p.N, wk.rp, wk.col, ov, cap);
+    } else {
+        hipLaunchKernelGGL(bucket_sort<int>, dim3(p.B), dim3(256), lds, s, wk.akey, wk.tcol, tv, wk.bstart, p.B,
+                           p.sb, p.N, wk.rp, wk.col, ov, cap);
+    }
+    prof_end(kKBucketSort, s);
     return hipGetLastError();
 }
 

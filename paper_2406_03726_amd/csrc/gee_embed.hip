@@ -42,8 +42,9 @@ constexpr int KS = 65;        // padded LDS stride of one class row of the slot 
 constexpr int kStepEsc = 255;  // row-step byte meaning "look the row up in row_ptr"
 constexpr int BW = 4;          // windows per pipeline batch
 
-// LDS floats of one embed wavefront: the slot ring [K][65] and four 64-entry slot tables.
-__host__ __device__ constexpr int embed_lds_floats(int K) { return K * KS + 4 * 64; }
+// LDS floats of one embed wavefront: a 64-entry slot table of float4 and the slot ring
+// [K][65], rounded to 16 bytes.
+__host__ __device__ constexpr int embed_lds_floats(int K) { return 4 * 64 + ((K * KS + 3) & ~3); }
 
 // ----------------------------------------------------------------------------- row steps
 
@@ -330,17 +331,25 @@ __global__ __launch_bounds__(256) void fill_empty(const int *__restrict__ rp, in
 
 // ----------------------------------------------------------------------------- finish a row
 
-// Diagonal term, s_i and correlation for one class value; `kp` consecutive lanes hold
-// one row (a power of two <= 64), which the correlation norm reduces over.
-__device__ __forceinline__ float finish_value(float v, int k, int lab, float coef, float s, int kp,
-                                              bool diag, bool lap, bool cor) {
-    if (diag && k == lab) v += coef;
-    if (lap) v *= s;
-    if (cor) {
-        float ss = v * v;
-        for (int o = kp >> 1; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, 64);
-        if (ss > 0.0f) v *= 1.0f / sqrtf(ss);
+// Sum of v over aligned groups of kp lanes (kp a power of two <= 64), returned on every
+// lane of the group. DPP lane moves only; every lane of the wavefront must take part.
+__device__ __forceinline__ float group_sum(float v, int kp) {
+    if (kp == 64) return wave_sum(v);
+    if (kp == 32) {
+        // prefix sums inside each half (no carry from lane 31 into the upper half, so
+        // neither half's sum is formed as a difference)
+        v += dpp_f<0x111>(v, 0.0f);
+        v += dpp_f<0x112>(v, 0.0f);
+        v += dpp_f<0x114>(v, 0.0f);
+        v += dpp_f<0x118>(v, 0.0f);
+        v += dpp_f<0x142, 0xA>(v, 0.0f);
+        const float s31 = readlane_f(v, 31), s63 = readlane_f(v, 63);
+        return lane_id() < 32 ? s31 : s63;
     }
+    if (kp >= 2) v += dpp_f<0xB1>(v, 0.0f);   // quad_perm [1,0,3,2]
+    if (kp >= 4) v += dpp_f<0x4E>(v, 0.0f);   // quad_perm [2,3,0,1]
+    if (kp >= 8) v += dpp_f<0x141>(v, 0.0f);  // row_half_mirror: the other quad of 8
+    if (kp >= 16) v += dpp_f<0x140>(v, 0.0f); // row_mirror: the other half of 16
     return v;
 }
 
@@ -353,8 +362,8 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
                                                   const float2 *__restrict__ info,
                                                   const float *__restrict__ srow,
                                                   const int *__restrict__ wrow,
-                                                  const int *__restrict__ meta, int N, int K, int kbits,
-                                                  int kp, int WE, unsigned flags, float *__restrict__ Z,
+                                                  const int *__restrict__ meta, int N, int K, int kp,
+                                                  int WE, unsigned flags, float *__restrict__ Z,
                                                   float *__restrict__ headp, float *__restrict__ tailp,
                                                   int *__restrict__ split, unsigned *status) {
     extern __shared__ float smem_f[];
@@ -366,11 +375,9 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
     if (w >= NW) return;  // whole wavefront leaves; no workgroup barrier is used below
     const bool diag = flags & kDiag, lap = flags & kLap, cor = flags & kCor;
 
-    float *acc = smem_f + (size_t)wib * embed_lds_floats(K);  // [K][65]
-    int *slot_row = reinterpret_cast<int *>(acc + K * KS);  // [64]
-    float *slot_coef = reinterpret_cast<float *>(slot_row + 64);
-    int *slot_lab = reinterpret_cast<int *>(slot_coef + 64);
-    float *slot_s = reinterpret_cast<float *>(slot_lab + 64);
+    // per wavefront: slot table [64] {row, c_i, y_i, s_i}, then the ring acc[K][KS]
+    float4 *slot_meta = reinterpret_cast<float4 *>(smem_f + (size_t)wib * embed_lds_floats(K));
+    float *acc = reinterpret_cast<float *>(slot_meta + 64);
     for (int k = 0; k < K; ++k) acc[k * KS + lane] = 0.0f;
     // Finished rows stay in their ring slots ("pending") until drain() stores them:
     // slots [pend_first, pend_first + npend) in ring order, just behind the open row.
@@ -380,93 +387,66 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
     const int b = min(a + WE, M);
     const int last = b - 1;
     const int row_a = min(max(wrow[w], 0), N - 1);
-    const bool head = rstep[a] == 0;  // entry a continues a row begun before the wavefront
+    // entry a continues a row begun before the wavefront / entry b continues the last row
+    const bool head = __builtin_amdgcn_readfirstlane(rstep[a]) == 0;
     const int head_row = head ? row_a : -1;
-    const bool cont_end = b < M && rstep[min(b, M - 1)] == 0;
+    const bool cont_end = b < M && __builtin_amdgcn_readfirstlane(rstep[min(b, M - 1)]) == 0;
     int cur_row = head ? row_a : -1;
     int cur_slot = 63;
-    if (lane == 0) slot_row[63] = cur_row;
-    bool cont = false, priv = false;
-    int row_last = cur_row, slot_last = cur_slot;
+    if (lane == 0) slot_meta[63] = make_float4(__int_as_float(cur_row), 0.0f, __int_as_float(-1), 0.0f);
+    bool cont = false;
 
-    // The open row's per-lane private columns -> its ring slot (fixed order l = 0..63).
-    auto reduce_private = [&](int sl) {
-        wave_lds_fence();
-        for (int k = lane; k < K; k += 64) {
-            float s = 0.0f;
-            for (int l = 0; l < 64; ++l) {
-                s += acc[k * KS + l];
-                acc[k * KS + l] = 0.0f;
-            }
-            acc[k * KS + sl] = s;
-        }
-        wave_lds_fence();
-    };
-    // Finish the pending rows (diagonal term, s_i, correlation; a head row goes out raw)
-    // and store them. This is the only loop with global stores; it runs at the end of a
-    // batch, or before the ring would overflow or a lane-private run begins, where waiting
-    // for outstanding loads costs little.
+    // Finish the pending rows (diagonal term, s_i, correlation; the head row goes out
+    // raw) and store them. kp lanes per row (WIDE: one row, two classes per lane). This
+    // loop holds the only global stores and reads nothing loaded from global memory, so
+    // it never waits for the loads in flight.
     auto drain = [&]() {
         wave_lds_fence();
         const int grp = WIDE ? 1 : 64 / kp;  // rows per pass
         const int g = WIDE ? 0 : lane / kp;
-        const int k = WIDE ? lane : lane - g * kp;
+        const int k = WIDE ? lane : lane & (kp - 1);
+        const int kk = min(k, K - 1);
         for (int j = 0; j < npend; j += grp) {
             const bool has = j + g < npend;
             const int sl = (pend_first + j + g) & 63;
-            const int r = has ? slot_row[sl] : -1;
+            const float4 m = slot_meta[sl];
+            const int r = __float_as_int(m.x);
+            const int lab = __float_as_int(m.z);
             const bool live = has && r >= 0 && r < N;
-            const bool hd = live && r == head_row;
-            float v0 = 0.0f, v1 = 0.0f;
-            if (has && k < K) {
-                v0 = acc[k * KS + sl];
-                acc[k * KS + sl] = 0.0f;
+            float v0 = acc[kk * KS + sl];
+            float v1 = 0.0f;
+            if (WIDE) v1 = acc[min(k + 64, K - 1) * KS + sl];
+            if (has) {
+                acc[kk * KS + sl] = 0.0f;
+                if (WIDE && k + 64 < K) acc[(k + 64) * KS + sl] = 0.0f;
             }
-            if (WIDE && has && k + 64 < K) {
-                v1 = acc[(k + 64) * KS + sl];
-                acc[(k + 64) * KS + sl] = 0.0f;
+            v0 = k < K ? v0 : 0.0f;
+            v1 = (WIDE && k + 64 < K) ? v1 : 0.0f;
+            float z0 = v0, z1 = v1;
+            if (diag && k == lab) z0 += m.y;
+            if (WIDE && diag && k + 64 == lab) z1 += m.y;
+            if (lap) {
+                z0 *= m.w;
+                z1 *= m.w;
             }
-            const float coef = has ? slot_coef[sl] : 0.0f;
-            const int lab = has ? slot_lab[sl] : -1;
-            const float s = has ? slot_s[sl] : 0.0f;
-            float z0, z1 = 0.0f;
-            if (!WIDE) {
-                z0 = finish_value(v0, k, lab, coef, s, kp, diag, lap, cor);
-            } else {
-                z0 = v0;
-                z1 = v1;
-                if (diag && k == lab) z0 += coef;
-                if (diag && k + 64 == lab) z1 += coef;
-                if (lap) {
-                    z0 *= s;
-                    z1 *= s;
-                }
-                if (cor) {
-                    const float ss = wave_sum(z0 * z0 + z1 * z1);
-                    if (ss > 0.0f) {
-                        const float sc = 1.0f / sqrtf(ss);
-                        z0 *= sc;
-                        z1 *= sc;
-                    }
-                }
+            if (cor) {
+                const float ss = WIDE ? wave_sum(z0 * z0 + z1 * z1) : group_sum(z0 * z0, kp);
+                const float sc = ss > 0.0f ? 1.0f / sqrtf(ss) : 1.0f;
+                z0 *= sc;
+                z1 *= sc;
             }
-            if (hd) {
+            if (r == head_row) {
                 z0 = v0;
                 z1 = v1;
             }
             if (live) {
-                float *dst = hd ? headp + (int64_t)w * K : Z + (int64_t)r * K;
+                float *dst = r == head_row ? headp + (int64_t)w * K : Z + (int64_t)r * K;
                 if (k < K) dst[k] = z0;
                 if (WIDE && k + 64 < K) dst[k + 64] = z1;
             }
         }
         npend = 0;
         wave_lds_fence();
-    };
-    // Rows of `nrow` consecutive ring slots have ended: they stay pending in their slots.
-    auto flush = [&](int first_slot, int nrow) {
-        if (npend == 0) pend_first = first_slot;
-        npend += nrow;
     };
 
     // Loads are unconditional (clamped address, value masked afterwards) and are only
@@ -505,6 +485,7 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
         qc[u] = info[rr];
         sc[u] = lap ? srow[rr] : 1.0f;
     }
+    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
 
     for (int i0 = 0; i0 < nwin; i0 += BW) {
         // issue: rows and gathers of batch k+1, col/val/steps of batch k+2
@@ -531,66 +512,30 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
             const int nvalid = min(64, b - p);
             const bool valid = lane < nvalid;
             const int y = __float_as_int(fc[u].y);
-            const bool contrib = valid && y >= 0;
             const float x = vc[u] * fc[u].x;
             const int nxt = (u + 1 < BW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
             cont = (p + nvalid < b) ? (nxt == 0) : cont_end;
-            const uint64_t sm = ballot(valid && dc[u] != 0);
-
-            if (sm == 0) {
-                // The window lies inside the open row: per-lane private columns (every
-                // column but the open row's must be free, so pending rows go out first).
-                if (!priv && npend > 0) drain();
-                if (contrib) atomicAdd(&acc[y * KS + lane], x);
-                priv = true;
-                row_last = cur_row;
-                slot_last = cur_slot;
-                if (!cont) {
-                    reduce_private(cur_slot);
-                    priv = false;
-                    flush(cur_slot, 1);
-                }
-            } else {
-                if (priv) {
-                    reduce_private(cur_slot);
-                    priv = false;
-                }
-                // new rows need free ring slots: pending + open + new <= 64
-                if (npend + 1 + __popcll(sm) > 64) drain();
-                const int row = rc[u];
-                const bool start = valid && dc[u] != 0;
-                const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
-                const int slot = (cur_slot + __popcll(sm & le)) & 63;
-                // lanes of the same row: [last start <= lane, next start > lane)
-                const uint64_t below = sm & le;
-                const uint64_t above = sm & ~le;
-                const int lo = below ? 63 - __clzll(below) : 0;
-                const int hi = above ? __ffsll((unsigned long long)above) - 1 : 64;
-                const uint64_t segm = (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
-                uint64_t peers = ballot(contrib) & segm;
-                for (int bit = 0; bit < kbits; ++bit) {
-                    const bool bb = (y >> bit) & 1;
-                    const uint64_t m = ballot(contrib && bb);
-                    peers &= bb ? m : ~m;
-                }
-                const int rank = count_below(peers);
-                for (int pass = 0;; ++pass) {
-                    if (!ballot(contrib && rank >= pass)) break;
-                    if (contrib && rank == pass) atomicAdd(&acc[y * KS + slot], x);
-                }
-                if (start) {
-                    slot_row[slot] = row;
-                    slot_coef[slot] = qc[u].x;
-                    slot_lab[slot] = __float_as_int(qc[u].y);
-                    slot_s[slot] = sc[u];
-                }
-                row_last = readlane(row, nvalid - 1);
-                slot_last = readlane(slot, nvalid - 1);
-                const int first_slot = readlane(slot, 0);
-                const int nseg = ((slot_last - first_slot) & 63) + 1;
-                flush(first_slot, cont ? nseg - 1 : nseg);
+            const bool start = valid && dc[u] != 0;
+            const uint64_t sm = ballot(start);
+            const int nnew = __popcll(sm);
+            // the open row and the new rows need ring slots next to the pending ones
+            if (npend + 1 + nnew > 64) drain();
+            const int slot = (cur_slot + __popcll(sm & le)) & 63;
+            // Lanes with equal (row, class) add to the same LDS word; the LDS applies
+            // them one after another in a fixed order, so the sums are reproducible.
+            if (valid && y >= 0) atomicAdd(&acc[y * KS + slot], x);
+            if (start) slot_meta[slot] = make_float4(__int_as_float(rc[u]), qc[u].x, qc[u].y, sc[u]);
+            // rows ended in this window: from lane 0's row to the last lane's row, the
+            // latter only if the next entry starts a new row
+            const int first_slot = (sm & 1ull) ? (cur_slot + 1) & 63 : cur_slot;
+            const int slot_last = (cur_slot + nnew) & 63;
+            const int nseg = ((slot_last - first_slot) & 63) + 1;
+            const int nend = cont ? nseg - 1 : nseg;
+            if (nend > 0) {
+                if (npend == 0) pend_first = first_slot;
+                npend += nend;
             }
-            cur_row = row_last;
+            cur_row = nnew ? readlane(rc[u], 63 - __clzll(sm)) : cur_row;
             cur_slot = slot_last;
         }
         drain();
@@ -610,13 +555,12 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
     if (ballot(bad) && lane == 0) raise_error(status, kErrCsr);
 
     // The last row continues past this wavefront: leave its raw partial sums.
-    if (priv) reduce_private(slot_last);
     if (npend > 0) drain();
     int my_split = -1;
     if (cont) {
-        float *dstp = (row_last == head_row) ? headp : tailp;
-        if (row_last != head_row) my_split = row_last;
-        for (int k = lane; k < K; k += 64) dstp[(int64_t)w * K + k] = acc[k * KS + slot_last];
+        float *dstp = (cur_row == head_row) ? headp : tailp;
+        if (cur_row != head_row) my_split = cur_row;
+        for (int k = lane; k < K; k += 64) dstp[(int64_t)w * K + k] = acc[k * KS + cur_slot];
     }
     if (lane == 0) split[w] = my_split;
 }
@@ -716,8 +660,6 @@ hipError_t launch_node_prep(const int *rp, const float *val, const int *labels, 
 hipError_t launch_embed(const int *rp, const int *col, const float *val, const Plan &p,
                         const Work &wk, float *Z, unsigned *status, hipStream_t s) {
     const int K = p.K;
-    int kbits = 0;
-    while ((1 << kbits) < K) ++kbits;
     int kp = 1;
     while (kp < K && kp < 64) kp <<= 1;
     const int wpb = p.wpb;
@@ -733,7 +675,7 @@ hipError_t launch_embed(const int *rp, const int *col, const float *val, const P
     if (e != hipSuccess) return e;
 #define GEE_EMBED_LAUNCH(WT, WD)                                                                   \
     hipLaunchKernelGGL((embed_rows<WT, WD>), dim3(grid), dim3(64 * wpb), lds, s, rp, col, val,     \
-                       wk.rstep, wk.info, wk.srow, wk.wrow, wk.meta, p.N, K, kbits, kp, p.WE,       \
+                       wk.rstep, wk.info, wk.srow, wk.wrow, wk.meta, p.N, K, kp, p.WE,       \
                        p.flags, Z,                                                                 \
                        wk.headp, wk.tailp, wk.split, status)
     prof_begin(kKEmbedRows, s);

@@ -17,8 +17,8 @@ constexpr unsigned kDiag = 1u, kLap = 2u, kCor = 4u, kSym = 8u;
 constexpr unsigned kErrLabel = 1u, kErrIndex = 2u, kErrWeight = 4u, kErrCsr = 8u;
 
 constexpr int kWave = 64;
-constexpr int kMaxBuckets = 4096;      // partition buckets (pass 1 digits)
-constexpr int kMaxBucketRowsLog2 = 12; // rows per bucket (pass 2 digits)
+constexpr int kMaxBuckets = 65536;     // CSR buckets: 256 high digits x 256 low digits
+constexpr int kMaxBucketRowsLog2 = 12; // rows per bucket (the last sort pass ranks by row)
 constexpr int kMaxClasses = 128;
 
 // ----------------------------------------------------------------------------- wave ops
@@ -116,8 +116,11 @@ struct Plan {
     // partition (CSR build)
     int sb = 0;          // rows per bucket = 1 << sb
     int32_t B = 1;       // buckets
-    int tile = 16384;    // virtual entries per pass-1 tile
-    int64_t T1 = 1;      // pass-1 tiles
+    int s2 = 0;          // low digit bits (pass B digits = 1 << s2; 0: no pass B)
+    int DA = 1;          // pass A digits (high digit = bucket >> s2), <= 256
+    int tile = 4096;     // entries per partition tile
+    int64_t TA = 1;      // pass A tiles
+    int64_t TBcap = 1;   // pass B tiles (upper bound)
     // embed
     int WE = 2048;       // CSR entries per embed wavefront
     int wpb = 4;         // wavefronts per embed workgroup
@@ -131,10 +134,14 @@ struct Work {
     float *inv_n = nullptr;    // [K]
     int *cpart = nullptr;      // [cnt_blocks * K]
     int *meta = nullptr;       // [4]: M, NW, ...
-    int *ghist = nullptr;      // [B * T1]
-    int *btot = nullptr;       // [B]
+    int *ghA = nullptr;        // [DA * TA] pass A tile histograms (scanned in place)
+    int *totA = nullptr;       // [DA]
+    int *segA = nullptr;       // [DA + 1] pass A segment starts
+    int *tileB = nullptr;      // [DA + 1] first pass-B tile of each segment
+    int *ghB = nullptr;        // [(1 << s2) * TBcap] pass B tile histograms
     int *bstart = nullptr;     // [B + 1]
-    uint16_t *tkey = nullptr;  // [Mcap] row within bucket
+    int *akey = nullptr;       // [Mcap] pass A output: row
+    uint16_t *tkey = nullptr;  // [Mcap] pass B output: row within bucket
     int *tcol = nullptr;       // [Mcap]
     float *tval = nullptr;     // [Mcap] (weighted only)
     int *rp = nullptr;         // [N + 1]
@@ -156,7 +163,8 @@ struct Work {
 // Kernel ids for the optional event hook (gee_profile_kernel). The hook records a
 // caller's hipEvents on the launch stream right before / after a kernel launch.
 enum KernelId : int {
-    kKCountPartial = 0, kKCountFinal, kKP1Hist, kKP1Scan, kKP1Totals, kKP1Scatter, kKP2Bucket,
+    kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
+    kKBScatter, kKBucketSort,
     kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup, kKFillEmpty, kKEmbedRows, kKEmbedFixup,
     kKSetMeta, kKNumKernels
 };
@@ -172,6 +180,7 @@ hipError_t launch_class_counts(const int *labels, int N, int K, int nblocks, int
 hipError_t launch_csr_build(const int *src, const int *dst, const float *w, const Plan &p,
                             const Work &wk, unsigned *status, hipStream_t s);
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
+size_t bucket_sort_lds(int sb);
 // gee_embed.hip
 // Per-node data (ownership, degrees, s_i, c_i); meta[0..1] = {M, wavefronts} must be set.
 hipError_t launch_node_prep(const int *rp, const float *val, const int *labels, const Plan &p,

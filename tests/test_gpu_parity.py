@@ -69,13 +69,25 @@ def test_csr_sbm_small_bit_exact():
     _check_csr(sbm_small("off"))
 
 
-@pytest.mark.parametrize("sched", [dict(tile_entries=2048, bucket_rows_log2=1),
-                                   dict(tile_entries=65536, bucket_rows_log2=12),
-                                   dict(tile_entries=4096, bucket_rows_log2=7)])
+# bucket sizes: 2 rows (10,000 buckets: both partition passes, tiny buckets), 4096 rows
+# (5 buckets of ~48k entries: one partition pass, buckets too large to stage), 128 rows
+# (157 staged buckets, one partition pass)
+@pytest.mark.parametrize("sched", [dict(tile_entries=4096, bucket_rows_log2=1),
+                                   dict(bucket_rows_log2=12),
+                                   dict(bucket_rows_log2=7)])
 def test_csr_schedules_bit_exact(sched):
     g = random_small_graph(9, N=20_000, E=120_000, K=3, weighted=True)
     _label(f"csr schedule {sched}")
     _check_csr(g, sched=sched)
+
+
+@pytest.mark.parametrize("sb", [3, 9])
+def test_csr_two_partition_passes_with_hubs(sb):
+    """Both partition passes (several hundred buckets and more) on a power-law graph whose
+    hub rows make some buckets too large to stage."""
+    g = powerlaw_10m(N=300_000, E=1_500_000, K=4, dmax=20_000.0)
+    _label(f"csr power-law two passes sb={sb}")
+    _check_csr(g, sched=dict(bucket_rows_log2=sb))
 
 
 def test_csr_empty_and_isolated():
