@@ -29,7 +29,7 @@ METRIC = "edges embedded/sec + % HBM peak; served p50/p99 latency vs plain per-g
 HBM_PEAK_GBS = 8000.0
 
 KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
-           "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps", "node_rows", "degree_rows",
+           "b_hist", "b_scan", "b_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
            "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"]
 
 

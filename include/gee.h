@@ -106,9 +106,9 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
    kernel records hipEvent `start_event` on its stream right before the launch and
    `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
    Kernel names: "class_count_partial", "class_count_final", "a_hist", "digit_scan",
-   "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps",
-   "node_rows", "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup",
-   "set_meta". The caller owns the
+   "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "bucket_sort", "graph_meta",
+   "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty", "embed_rows",
+   "embed_fixup". Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);
@@ -125,7 +125,7 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
 
 /* ---------------------------------------------------------------------------------
  * gee_build_csr - edge list -> CSR (Section 3 layout), built on the device by a stable
- * two-level radix partition on the row index.
+ * sort on the row index (two partition passes, then a sort inside buckets of rows).
  *   src, dst : int32[E] device, node ids in [0, N)
  *   w        : float32[E] device weights, or NULL (every weight is 1)
  *   flags    : only GEE_SYMMETRIZE is meaningful here
@@ -184,6 +184,46 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
                      int32_t N, const int32_t *labels, int32_t K, uint32_t flags, float *Z,
                      const gee_schedule *sched, void *workspace, size_t workspace_bytes,
                      void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batches: gee_embed of G independent graphs in one launch sequence. The graphs are
+ * embedded as the disjoint union of their edge lists (one CSR sort, one pass of each
+ * kernel over all graphs); each graph keeps its own sizes, labels, options, output and
+ * schedule. Every Z of a batch is bitwise identical to that graph's gee_embed_ws with
+ * the same schedule (its schedule is chosen from its own sizes, never from the batch).
+ *   src, dst, w, E, N, labels, K, flags, Z : as for gee_embed, per graph
+ *   sched : zero fields take the graph's defaults; waves_per_block and
+ *           bucket_rows_log2 are taken from graph 0 for the whole batch
+ * Limits: at most 2^20 graphs, 2^28 nodes and 2^31 - 2^16 CSR entries in total; each
+ * graph within the single-graph limits. */
+typedef struct {
+    const int32_t *src, *dst;
+    const float *w;
+    int64_t E;
+    int32_t N;
+    const int32_t *labels;
+    int32_t K;
+    uint32_t flags;
+    float *Z;
+    gee_schedule sched;
+} gee_graph;
+
+/* Caller-workspace form: the graph table is copied to the device (stream-ordered) and the
+ * kernels are enqueued on `stream`; returns 0 bytes for invalid arguments. */
+size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G);
+int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
+                       void *stream);
+
+/* Batch plan: allocates its workspace (hipMalloc) and uploads the graph table once, then
+ * captures the whole launch sequence in a hipGraph. Each gee_batch_plan_launch replays it
+ * on `stream` (one graph launch) and recomputes every Z from the current contents of the
+ * input arrays named at creation. The arrays must stay allocated while the plan exists;
+ * launches of one plan must not overlap (they share the workspace). Create and destroy
+ * on the device the arrays live on. */
+typedef struct gee_batch_plan gee_batch_plan;
+int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **plan);
+int gee_batch_plan_launch(gee_batch_plan *plan, void *stream);
+int gee_batch_plan_destroy(gee_batch_plan *plan);
 
 #ifdef __cplusplus
 }

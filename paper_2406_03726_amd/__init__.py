@@ -6,6 +6,7 @@ of include/gee.h (libgee.so); this package is the thin Python binding over it.
 """
 
 from .gee import (  # noqa: F401
+    BatchPlan,
     GEE_CORRELATION,
     GEE_DATA_CSR,
     GEE_DATA_INDEX,
@@ -22,6 +23,8 @@ from .gee import (  # noqa: F401
     gee_csr_capacity,
     gee_default_schedule,
     gee_embed,
+    gee_embed_batch,
+    gee_embed_batch_workspace_bytes,
     gee_embed_csr,
     gee_embed_csr_workspace_bytes,
     gee_embed_workspace_bytes,

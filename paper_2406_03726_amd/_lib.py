@@ -22,6 +22,13 @@ class GeeSchedule(ctypes.Structure):
                 ("tile_entries", ctypes.c_int32), ("bucket_rows_log2", ctypes.c_int32)]
 
 
+class GeeGraph(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("E", ctypes.c_int64), ("N", ctypes.c_int32), ("labels", ctypes.c_void_p),
+                ("K", ctypes.c_int32), ("flags", ctypes.c_uint32), ("Z", ctypes.c_void_p),
+                ("sched", GeeSchedule)]
+
+
 SYMBOLS = {
     # name: (restype, argtypes)
     "gee_abi_version": (ctypes.c_int, []),
@@ -58,6 +65,13 @@ SYMBOLS = {
                                         ctypes.c_int32, ctypes.c_uint32, c_f32p,
                                         ctypes.POINTER(GeeSchedule), ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "gee_embed_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GeeGraph), ctypes.c_int32]),
+    "gee_embed_batch_ws": (ctypes.c_int, [ctypes.POINTER(GeeGraph), ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]),
+    "gee_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(GeeGraph), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "gee_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gee_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 

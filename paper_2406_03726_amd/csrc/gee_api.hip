@@ -1,8 +1,11 @@
 // gee_api.hip - the C ABI declared in include/gee.h: argument checks, the launch plan,
-// workspace carve-up, the per-device data-error word and the entry points.
+// workspace carve-up, the per-device data-error word, the entry points, and batch
+// plans (one hipGraph per batch).
 #include <atomic>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <vector>
 
 #include "gee.h"
 #include "gee_internal.h"
@@ -14,6 +17,8 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr unsigned kKnownFlags = GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE;
 constexpr int64_t kMaxEntries = (int64_t)INT32_MAX - 65536;
+constexpr int64_t kMaxBatchNodes = (int64_t)1 << 28;
+constexpr int kMaxBatchGraphs = 1 << 20;
 
 int ilog2_ceil(int64_t x) {
     int b = 0;
@@ -62,61 +67,139 @@ struct ProfSlot {
 std::mutex g_prof_mu;
 ProfSlot g_prof[kKNumKernels];
 std::atomic<int> g_prof_active{0};
+thread_local bool t_capturing = false;  // no event records while a batch plan is captured
 
 // ------------------------------------------------------------------------- plan
 
-int make_plan(int64_t E, int32_t N, int32_t K, uint32_t flags, bool weighted, const gee_schedule *sc,
-              Plan &p) {
-    p.E = E;
-    p.N = N;
-    p.K = K;
-    p.flags = flags;
-    p.weighted = weighted;
-    p.Mcap = (flags & GEE_SYMMETRIZE) ? 2 * E : E;
-    if (p.Mcap > kMaxEntries) return GEE_ERR_TOO_LARGE;
-    // buckets of 2^sb rows, about 3000 entries each on average; at most 65536 buckets
-    const int sb_min = ilog2_ceil(N > 0 ? N : 1) > 16 ? ilog2_ceil(N) - 16 : 0;
+// One graph as the caller describes it. For a resident CSR, E is the entry count M.
+struct GraphIn {
+    const int *src = nullptr, *dst = nullptr;
+    const float *w = nullptr;
+    int64_t E = 0;
+    int N = 0;
+    const int *labels = nullptr;
+    int K = 1;
+    unsigned flags = 0;
+    float *Z = nullptr;
+    gee_schedule sc{0, 0, 0, 0};
+};
+
+int check_common(int32_t N, int32_t K, uint32_t flags) {
+    if (N < 0 || K < 1) return GEE_ERR_ARG;
+    if (flags & ~kKnownFlags) return GEE_ERR_ARG;
+    if (N > GEE_MAX_NODES) return GEE_ERR_TOO_LARGE;
+    if (K > GEE_MAX_CLASSES) return GEE_ERR_UNSUPPORTED;
+    return GEE_OK;
+}
+
+int check_schedule(const gee_schedule &sc) {
+    if (sc.wave_entries && (!is_pow2(sc.wave_entries) || sc.wave_entries < 256 || sc.wave_entries > 16384))
+        return GEE_ERR_ARG;
+    if (sc.waves_per_block && (sc.waves_per_block < 1 || sc.waves_per_block > 4)) return GEE_ERR_ARG;
+    if (sc.tile_entries && sc.tile_entries != 4096) return GEE_ERR_ARG;
+    if (sc.bucket_rows_log2 < 0 || sc.bucket_rows_log2 > kMaxBucketRowsLog2) return GEE_ERR_ARG;
+    return GEE_OK;
+}
+
+// Default CSR entries per embed wavefront for a graph with this many entries.
+int default_wave_entries(int64_t Mcap) { return Mcap >= (1 << 20) ? 1024 : 512; }
+
+// Plan of a launch over G graphs. `resident`: the graphs are given as CSRs (E = M).
+int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDesc> &d) {
+    if (G < 1 || G > kMaxBatchGraphs) return GEE_ERR_ARG;
+    p = Plan();
+    p.G = G;
+    d.assign(G, GDesc());
+    int64_t voff = 0, noff = 0, woff = 0, parts = 0, coff = 0, cpo = 0, ktot = 0;
+    int wpb = 0, sb_req = 0;
+    for (int g = 0; g < G; ++g) {
+        const GraphIn &x = gs[g];
+        int rc = check_common(x.N, x.K, x.flags);
+        if (rc) return rc;
+        if (x.E < 0) return GEE_ERR_ARG;
+        if ((rc = check_schedule(x.sc))) return rc;
+        const bool sym = !resident && (x.flags & GEE_SYMMETRIZE);
+        const int64_t mcap = sym ? 2 * x.E : x.E;
+        if (mcap > kMaxEntries) return GEE_ERR_TOO_LARGE;
+        GDesc &o = d[g];
+        o.src = x.src;
+        o.dst = x.dst;
+        o.w = x.w;
+        o.labels = x.labels;
+        o.Z = x.Z;
+        o.voff = voff;
+        o.E = x.E;
+        o.Mcap = mcap;
+        o.N = x.N;
+        o.node_off = (int)noff;
+        o.K = x.K;
+        int kp = 1;
+        while (kp < x.K && kp < 64) kp <<= 1;
+        o.kp = kp;
+        o.class_off = (int)ktot;
+        o.flags = resident ? (x.flags & ~GEE_SYMMETRIZE) : x.flags;
+        o.weighted = x.w != nullptr;
+        o.WE = x.sc.wave_entries ? x.sc.wave_entries : default_wave_entries(mcap);
+        o.NWcap = mcap > 0 ? (int)((mcap + o.WE - 1) / o.WE) : 1;
+        o.wave_off = (int)woff;
+        o.part_off = parts;
+        int64_t cb = ((int64_t)x.N + 4095) / 4096;
+        o.cnt_blocks = (int)(cb < 1 ? 1 : (cb > 512 ? 512 : cb));
+        o.cnt_off = (int)coff;
+        o.cpart_off = cpo;
+        voff += mcap;
+        noff += x.N;
+        woff += o.NWcap;
+        parts += (int64_t)o.NWcap * x.K;
+        coff += o.cnt_blocks;
+        cpo += (int64_t)o.cnt_blocks * x.K;
+        ktot += x.K;
+        if (voff > kMaxEntries || noff > kMaxBatchNodes || woff > INT32_MAX / 2 || coff > INT32_MAX / 2 ||
+            ktot > INT32_MAX / 2)
+            return GEE_ERR_TOO_LARGE;
+        p.Kmax = x.K > p.Kmax ? x.K : p.Kmax;
+        p.weighted = p.weighted || o.weighted;
+        p.any_lap_w = p.any_lap_w || (o.weighted && (x.flags & GEE_LAPLACIAN));
+        if (g == 0) {
+            wpb = x.sc.waves_per_block;
+            sb_req = x.sc.bucket_rows_log2;
+        }
+    }
+    p.Vtot = voff;
+    p.Ntot = noff;
+    p.Ktot = (int)ktot;
+    p.NWtot = woff;
+    p.parts = parts;
+    p.cnt_blocks = (int)coff;
+    p.cparts = cpo;
+    // CSR sort buckets of 2^sb rows, about 3000 entries each on average; at most 65536
+    const int64_t n1 = p.Ntot > 0 ? p.Ntot : 1;
+    const int sb_min = ilog2_ceil(n1) > 16 ? ilog2_ceil(n1) - 16 : 0;
     if (sb_min > kMaxBucketRowsLog2) return GEE_ERR_TOO_LARGE;
     int sb = 0;
-    if (p.Mcap > 0) {
-        const double rows = 3000.0 * (double)(N > 0 ? N : 1) / (double)p.Mcap;
+    if (p.Vtot > 0) {
+        const double rows = 3000.0 * (double)n1 / (double)p.Vtot;
         while (sb < kMaxBucketRowsLog2 && (double)(2 << sb) <= rows) ++sb;
     } else {
         sb = kMaxBucketRowsLog2;
     }
-    if (sc && sc->bucket_rows_log2 > 0) sb = sc->bucket_rows_log2;
+    if (sb_req > 0) sb = sb_req;
     if (sb < sb_min) sb = sb_min;
     if (sb > kMaxBucketRowsLog2) sb = kMaxBucketRowsLog2;
     p.sb = sb;
-    p.B = (int32_t)(((int64_t)(N > 0 ? N : 1) + (1 << sb) - 1) >> sb);
+    p.B = (int32_t)((n1 + (1 << sb) - 1) >> sb);
     const int nbB = ilog2_ceil(p.B);
     p.s2 = nbB <= 8 ? 0 : (nbB - 8 > nbB / 2 ? nbB - 8 : nbB / 2);
     p.DA = (int)(((int64_t)p.B + (1 << p.s2) - 1) >> p.s2);
     p.tile = 4096;
-    if (sc && sc->tile_entries && sc->tile_entries != p.tile) return GEE_ERR_ARG;
-    p.TA = (p.Mcap + p.tile - 1) / p.tile;
+    p.TA = (p.Vtot + p.tile - 1) / p.tile;
     if (p.TA < 1) p.TA = 1;
     p.TBcap = p.s2 > 0 ? p.TA + p.DA : 1;
-    // embed: entries per wavefront
-    int we = p.Mcap >= (1 << 20) ? 1024 : 512;
-    if (sc && sc->wave_entries) {
-        if (!is_pow2(sc->wave_entries) || sc->wave_entries < 256 || sc->wave_entries > 16384)
-            return GEE_ERR_ARG;
-        we = sc->wave_entries;
-    }
-    p.WE = we;
-    // one wavefront per workgroup by default: the LDS ring of each wavefront then limits
-    // residency least (more wavefronts in flight per CU)
-    const size_t per_wave = embed_lds_per_wave(K);
-    int wpb = 1;
-    if (sc && sc->waves_per_block) {
-        if (sc->waves_per_block < 1 || sc->waves_per_block > 4) return GEE_ERR_ARG;
-        if ((size_t)sc->waves_per_block * per_wave <= 65536) wpb = sc->waves_per_block;
-    }
-    p.wpb = wpb;
-    p.NWcap = p.Mcap > 0 ? (p.Mcap + p.WE - 1) / p.WE : 1;
-    int64_t cb = ((int64_t)N + 4095) / 4096;
-    p.cnt_blocks = (int)(cb < 1 ? 1 : (cb > 512 ? 512 : cb));
+    // One wavefront per embed workgroup by default: the LDS ring of each wavefront then
+    // limits residency least. Larger workgroups must stay within 64 KiB of LDS.
+    const size_t per_wave = embed_lds_per_wave(p.Kmax);
+    p.wpb = 1;
+    if (wpb > 1 && (size_t)wpb * per_wave <= 65536) p.wpb = wpb;
     return GEE_OK;
 }
 
@@ -130,11 +213,21 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         off += (bytes + kAlign - 1) / kAlign * kAlign;
         return r;
     };
+    w = Work();
     w.meta = (int *)take(4 * sizeof(int));
+    w.gm = (GMeta *)take((size_t)p.G * sizeof(GMeta));
+    if (p.G > 1) {
+        w.tab = (GDesc *)take((size_t)p.G * sizeof(GDesc));
+        w.node_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
+        w.wave_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
+        w.cnt_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
+        w.class_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
+        w.voffs = (int64_t *)take((size_t)(p.G + 1) * sizeof(int64_t));
+    }
     if (parts & kPCount) {
-        w.counts = (int *)take((size_t)p.K * sizeof(int));
-        w.inv_n = (float *)take((size_t)p.K * sizeof(float));
-        w.cpart = (int *)take((size_t)p.cnt_blocks * p.K * sizeof(int));
+        w.counts = (int *)take((size_t)p.Ktot * sizeof(int));
+        w.inv_n = (float *)take((size_t)p.Ktot * sizeof(float));
+        w.cpart = (int *)take((size_t)p.cparts * sizeof(int));
     }
     if (parts & kPPart) {
         w.ghA = (int *)take((size_t)p.DA * p.TA * sizeof(int));
@@ -143,36 +236,133 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.tileB = (int *)take((size_t)(p.DA + 1) * sizeof(int));
         if (p.s2 > 0) w.ghB = (int *)take(((size_t)p.TBcap << p.s2) * sizeof(int));
         w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
-        w.akey = (int *)take((size_t)p.Mcap * sizeof(int));
-        if (p.s2 > 0) w.tkey = (uint16_t *)take((size_t)p.Mcap * sizeof(uint16_t));
-        w.tcol = (int *)take((size_t)p.Mcap * sizeof(int));
-        if (p.weighted) w.tval = (float *)take((size_t)p.Mcap * sizeof(float));
+        w.akey = (int *)take((size_t)p.Vtot * sizeof(int));
+        if (p.s2 > 0) w.tkey = (uint16_t *)take((size_t)p.Vtot * sizeof(uint16_t));
+        w.tcol = (int *)take((size_t)p.Vtot * sizeof(int));
+        if (p.weighted) w.tval = (float *)take((size_t)p.Vtot * sizeof(float));
     }
     if (parts & kPCsrOut) {
-        w.rp = (int *)take((size_t)(p.N + 1) * sizeof(int));
-        w.col = (int *)take((size_t)p.Mcap * sizeof(int));
-        if (p.weighted) w.val = (float *)take((size_t)p.Mcap * sizeof(float));
+        w.rp = (int *)take((size_t)(p.Ntot + 1) * sizeof(int));
+        w.col = (int *)take((size_t)p.Vtot * sizeof(int));
+        if (p.weighted) w.val = (float *)take((size_t)p.Vtot * sizeof(float));
     }
     if (parts & kPEmbed) {
-        w.info = (float2 *)take((size_t)p.N * sizeof(float2));
-        w.srow = (float *)take((size_t)p.N * sizeof(float));
-        w.wrow = (int *)take((size_t)p.NWcap * sizeof(int));
-        w.rstep = (uint8_t *)take((size_t)(p.Mcap > 0 ? p.Mcap : 1));
-        w.split = (int *)take((size_t)p.NWcap * sizeof(int));
-        w.headp = (float *)take((size_t)p.NWcap * p.K * sizeof(float));
-        w.tailp = (float *)take((size_t)p.NWcap * p.K * sizeof(float));
-        w.headd = (float *)take((size_t)p.NWcap * sizeof(float));
-        w.taild = (float *)take((size_t)p.NWcap * sizeof(float));
-        w.dsplit = (int *)take((size_t)p.NWcap * sizeof(int));
+        w.info = (float2 *)take((size_t)p.Ntot * sizeof(float2));
+        w.srow = (float *)take((size_t)p.Ntot * sizeof(float));
+        w.wrow = (int *)take((size_t)p.NWtot * sizeof(int));
+        w.rstep = (uint8_t *)take((size_t)(p.Vtot > 0 ? p.Vtot : 1));
+        w.split = (int *)take((size_t)p.NWtot * sizeof(int));
+        w.headp = (float *)take((size_t)p.parts * sizeof(float));
+        w.tailp = (float *)take((size_t)p.parts * sizeof(float));
+        w.headd = (float *)take((size_t)p.NWtot * sizeof(float));
+        w.taild = (float *)take((size_t)p.NWtot * sizeof(float));
+        w.dsplit = (int *)take((size_t)p.NWtot * sizeof(int));
     }
     return off;
 }
 
-int check_common(int32_t N, int32_t K, uint32_t flags) {
-    if (N < 0 || K < 1) return GEE_ERR_ARG;
-    if (flags & ~kKnownFlags) return GEE_ERR_ARG;
-    if (N > GEE_MAX_NODES) return GEE_ERR_TOO_LARGE;
-    if (K > GEE_MAX_CLASSES) return GEE_ERR_UNSUPPORTED;
+// Host images of the batch tables, in the carve order of the device copies.
+struct Tables {
+    std::vector<int> node_offs, wave_offs, cnt_offs, class_offs;
+    std::vector<int64_t> voffs;
+};
+Tables make_tables(const std::vector<GDesc> &d) {
+    Tables t;
+    const int G = (int)d.size();
+    t.node_offs.resize(G + 1);
+    t.wave_offs.resize(G + 1);
+    t.cnt_offs.resize(G + 1);
+    t.class_offs.resize(G + 1);
+    t.voffs.resize(G + 1);
+    for (int g = 0; g < G; ++g) {
+        t.node_offs[g] = d[g].node_off;
+        t.wave_offs[g] = d[g].wave_off;
+        t.cnt_offs[g] = d[g].cnt_off;
+        t.class_offs[g] = d[g].class_off;
+        t.voffs[g] = d[g].voff;
+    }
+    const GDesc &l = d[G - 1];
+    t.node_offs[G] = l.node_off + l.N;
+    t.wave_offs[G] = l.wave_off + l.NWcap;
+    t.cnt_offs[G] = l.cnt_off + l.cnt_blocks;
+    t.class_offs[G] = l.class_off + l.K;
+    t.voffs[G] = l.voff + l.Mcap;
+    return t;
+}
+
+// Kernel view of the launch; for G > 1 also writes the tables into the workspace
+// (stream-ordered kernels carrying the bytes as arguments, so no host buffer has to
+// outlive the call; with sync = true they complete before returning).
+hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w, hipStream_t s, bool sync,
+                      Batch &b) {
+    b = Batch();
+    b.G = p.G;
+    b.gm = w.gm;
+    if (p.G == 1) {
+        b.one = d[0];
+        return hipSuccess;
+    }
+    const Tables t = make_tables(d);
+    const size_t n = (size_t)(p.G + 1);
+    struct Copy {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } copies[] = {{w.tab, d.data(), sizeof(GDesc) * p.G},
+                  {w.node_offs, t.node_offs.data(), sizeof(int) * n},
+                  {w.wave_offs, t.wave_offs.data(), sizeof(int) * n},
+                  {w.cnt_offs, t.cnt_offs.data(), sizeof(int) * n},
+                  {w.class_offs, t.class_offs.data(), sizeof(int) * n},
+                  {w.voffs, t.voffs.data(), sizeof(int64_t) * n}};
+    for (const Copy &c : copies) {
+        hipError_t e = launch_upload(c.dst, c.src, c.bytes, s);
+        if (e != hipSuccess) return e;
+    }
+    if (sync) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+    }
+    b.tab = w.tab;
+    b.node_offs = w.node_offs;
+    b.wave_offs = w.wave_offs;
+    b.cnt_offs = w.cnt_offs;
+    b.class_offs = w.class_offs;
+    b.voffs = w.voffs;
+    return hipSuccess;
+}
+
+// Kernel sequence of gee_embed over a batch (edge lists -> Z).
+hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned *st, hipStream_t s) {
+    hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
+    if (e == hipSuccess) e = launch_csr_build(b, p, wk, st, s);
+    if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
+    if (e == hipSuccess) e = launch_graph_meta(b, wk.rp, 0, s);
+    const float *val = p.weighted ? wk.val : nullptr;
+    if (e == hipSuccess) e = launch_node_prep(b, p, wk.rp, val, wk, st, s);
+    if (e == hipSuccess) e = launch_embed(b, p, wk.rp, wk.col, val, wk, st, s);
+    return e;
+}
+
+int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &out) {
+    if (!graphs || G < 1 || G > kMaxBatchGraphs) return GEE_ERR_ARG;
+    out.resize(G);
+    for (int g = 0; g < G; ++g) {
+        const gee_graph &x = graphs[g];
+        GraphIn &o = out[g];
+        o.src = x.src;
+        o.dst = x.dst;
+        o.w = x.w;
+        o.E = x.E;
+        o.N = x.N;
+        o.labels = x.labels;
+        o.K = x.K;
+        o.flags = x.flags;
+        o.Z = x.Z;
+        o.sc = x.sched;
+        if (x.E < 0 || x.N < 0) return GEE_ERR_ARG;
+        if ((x.E > 0 && (!x.src || !x.dst)) || (x.N > 0 && (!x.labels || !x.Z))) return GEE_ERR_ARG;
+        if (x.N == 0 && x.E > 0) return GEE_ERR_ARG;
+    }
     return GEE_OK;
 }
 
@@ -184,22 +374,32 @@ namespace gee {
 
 const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
-    "b_hist", "b_scan", "b_scatter", "bucket_sort", "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty",
-    "embed_rows", "embed_fixup", "set_meta"};
+    "b_hist", "b_scan", "b_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
+    "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"};
 
 void prof_begin(int kid, hipStream_t s) {
-    if (!g_prof_active.load(std::memory_order_relaxed)) return;
+    if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (g_prof[kid].start) (void)hipEventRecord(g_prof[kid].start, s);
 }
 
 void prof_end(int kid, hipStream_t s) {
-    if (!g_prof_active.load(std::memory_order_relaxed)) return;
+    if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (g_prof[kid].stop) (void)hipEventRecord(g_prof[kid].stop, s);
 }
 
 }  // namespace gee
+
+// Batch plan: a workspace, the uploaded tables and the captured launch sequence.
+struct gee_batch_plan {
+    int device = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int G = 0;
+};
 
 // =========================================================================== C ABI
 
@@ -262,12 +462,16 @@ int gee_get_data_errors(void *stream, uint32_t *bits) {
 
 int gee_default_schedule(int64_t E, int32_t N, int32_t K, uint32_t flags, gee_schedule *out) {
     if (!out || E < 0) return GEE_ERR_ARG;
-    int rc = check_common(N, K, flags);
-    if (rc) return rc;
+    GraphIn x;
+    x.E = E;
+    x.N = N;
+    x.K = K;
+    x.flags = flags;
     Plan p;
-    rc = make_plan(E, N, K, flags, true, nullptr, p);
+    std::vector<GDesc> d;
+    int rc = make_plan(&x, 1, false, p, d);
     if (rc) return rc;
-    out->wave_entries = p.WE;
+    out->wave_entries = d[0].WE;
     out->waves_per_block = p.wpb;
     out->tile_entries = p.tile;
     out->bucket_rows_log2 = p.sb;
@@ -287,13 +491,20 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
     if (!counts || (N > 0 && !labels)) return GEE_ERR_ARG;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
+    GraphIn x;
+    x.N = N;
+    x.K = K;
+    x.labels = labels;
     Plan p;
-    if ((rc = make_plan(0, N, K, 0, false, nullptr, p))) return rc;
+    std::vector<GDesc> d;
+    if ((rc = make_plan(&x, 1, false, p, d))) return rc;
+    Batch b;
+    b.one = d[0];
     hipStream_t s = as_stream(stream);
     int *part = nullptr;
-    hipError_t e = hipMallocAsync((void **)&part, (size_t)p.cnt_blocks * K * sizeof(int), s);
+    hipError_t e = hipMallocAsync((void **)&part, (size_t)p.cparts * sizeof(int), s);
     if (e != hipSuccess) return hip_status(e);
-    e = launch_class_counts(labels, N, K, p.cnt_blocks, part, counts, nullptr, st, s);
+    e = launch_class_counts(b, p, part, counts, nullptr, st, s);
     hipError_t e2 = hipFreeAsync(part, s);
     return hip_status(e != hipSuccess ? e : e2);
 }
@@ -301,8 +512,15 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
 // --------------------------------------------------------------------------- CSR build
 
 size_t gee_build_csr_workspace_bytes(int64_t E, int32_t N, uint32_t flags, const gee_schedule *sched) {
+    GraphIn x;
+    x.E = E;
+    x.N = N;
+    x.flags = flags;
+    x.w = reinterpret_cast<const float *>(16);  // sized with weights, so one size serves both
+    if (sched) x.sc = *sched;
     Plan p;
-    if (E < 0 || check_common(N, 1, flags) || make_plan(E, N, 1, flags, true, sched, p)) return 0;
+    std::vector<GDesc> d;
+    if (E < 0 || make_plan(&x, 1, false, p, d)) return 0;
     Work w;
     return carve(p, kPPart, nullptr, w);
 }
@@ -318,23 +536,28 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
     if (N == 0 && E > 0) return GEE_ERR_ARG;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
+    GraphIn x;
+    x.src = src;
+    x.dst = dst;
+    x.w = wgt;
+    x.E = E;
+    x.N = N;
+    x.flags = flags;
+    if (sched) x.sc = *sched;
     Plan p;
-    if ((rc = make_plan(E, N, 1, flags, wgt != nullptr, sched, p))) return rc;
-    // size with weights present so one workspace size serves both cases
-    Plan pw = p;
-    pw.weighted = true;
+    std::vector<GDesc> d;
+    if ((rc = make_plan(&x, 1, false, p, d))) return rc;
+    if (!workspace || workspace_bytes < gee_build_csr_workspace_bytes(E, N, flags, sched)) return GEE_ERR_WORKSPACE;
     Work wk;
-    if (!workspace || workspace_bytes < carve(pw, kPPart, nullptr, wk)) return GEE_ERR_WORKSPACE;
     carve(p, kPPart, (char *)workspace, wk);
     hipStream_t s = as_stream(stream);
-    if (N == 0) {
-        hipError_t e = hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s);
-        return hip_status(e);
-    }
+    if (N == 0) return hip_status(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
     wk.rp = row_ptr;
     wk.col = col;
     wk.val = wgt ? val : nullptr;
-    hipError_t e = launch_csr_build(src, dst, wgt, p, wk, st, s);
+    Batch b;
+    b.one = d[0];
+    hipError_t e = launch_csr_build(b, p, wk, st, s);
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     return hip_status(e);
 }
@@ -342,7 +565,11 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
 int gee_build_csr(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
                   uint32_t flags, int32_t *row_ptr, int32_t *col, float *val, void *stream) {
     size_t bytes = gee_build_csr_workspace_bytes(E, N, flags, nullptr);
-    if (bytes == 0) return E < 0 ? GEE_ERR_ARG : check_common(N, 1, flags) ? check_common(N, 1, flags) : GEE_ERR_TOO_LARGE;
+    if (bytes == 0) {
+        if (E < 0) return GEE_ERR_ARG;
+        const int rc = check_common(N, 1, flags);
+        return rc ? rc : GEE_ERR_TOO_LARGE;
+    }
     hipStream_t s = as_stream(stream);
     void *ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, bytes, s);
@@ -356,8 +583,16 @@ int gee_build_csr(const int32_t *src, const int32_t *dst, const float *wgt, int6
 
 size_t gee_embed_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
                                  const gee_schedule *sched) {
+    GraphIn x;
+    x.E = E;
+    x.N = N;
+    x.K = K;
+    x.flags = flags;
+    x.w = weighted ? reinterpret_cast<const float *>(16) : nullptr;
+    if (sched) x.sc = *sched;
     Plan p;
-    if (E < 0 || check_common(N, K, flags) || make_plan(E, N, K, flags, weighted != 0, sched, p)) return 0;
+    std::vector<GDesc> d;
+    if (E < 0 || make_plan(&x, 1, false, p, d)) return 0;
     Work w;
     return carve(p, kPCount | kPPart | kPCsrOut | kPEmbed, nullptr, w);
 }
@@ -365,27 +600,18 @@ size_t gee_embed_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags
 int gee_embed_ws(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
                  const int32_t *labels, int32_t K, uint32_t flags, float *Z, const gee_schedule *sched,
                  void *workspace, size_t workspace_bytes, void *stream) {
-    if (E < 0) return GEE_ERR_ARG;
-    int rc = check_common(N, K, flags);
-    if (rc) return rc;
-    if ((E > 0 && (!src || !dst)) || (N > 0 && (!labels || !Z))) return GEE_ERR_ARG;
-    if (N == 0) return E > 0 ? GEE_ERR_ARG : GEE_OK;
-    unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
-    Plan p;
-    if ((rc = make_plan(E, N, K, flags, wgt != nullptr, sched, p))) return rc;
-    Work wk;
-    const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
-    if (!workspace || workspace_bytes < carve(p, parts, nullptr, wk)) return GEE_ERR_WORKSPACE;
-    carve(p, parts, (char *)workspace, wk);
-    hipStream_t s = as_stream(stream);
-    hipError_t e = launch_class_counts(labels, N, K, p.cnt_blocks, wk.cpart, wk.counts, wk.inv_n, st, s);
-    if (e == hipSuccess) e = launch_csr_build(src, dst, wgt, p, wk, st, s);
-    if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
-    const float *val = p.weighted ? wk.val : nullptr;
-    if (e == hipSuccess) e = launch_node_prep(wk.rp, val, labels, p, wk, st, s);
-    if (e == hipSuccess) e = launch_embed(wk.rp, wk.col, val, p, wk, Z, st, s);
-    return hip_status(e);
+    gee_graph g;
+    g.src = src;
+    g.dst = dst;
+    g.w = wgt;
+    g.E = E;
+    g.N = N;
+    g.labels = labels;
+    g.K = K;
+    g.flags = flags;
+    g.Z = Z;
+    g.sched = sched ? *sched : gee_schedule{0, 0, 0, 0};
+    return gee_embed_batch_ws(&g, 1, workspace, workspace_bytes, stream);
 }
 
 int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
@@ -405,13 +631,117 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
     return rc ? rc : hip_status(e);
 }
 
+// --------------------------------------------------------------------------- batches
+
+size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G) {
+    std::vector<GraphIn> gs;
+    if (graphs_from_api(graphs, G, gs)) return 0;
+    Plan p;
+    std::vector<GDesc> d;
+    if (make_plan(gs.data(), G, false, p, d)) return 0;
+    Work w;
+    return carve(p, kPCount | kPPart | kPCsrOut | kPEmbed, nullptr, w);
+}
+
+int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
+                       void *stream) {
+    std::vector<GraphIn> gs;
+    int rc = graphs_from_api(graphs, G, gs);
+    if (rc) return rc;
+    Plan p;
+    std::vector<GDesc> d;
+    if ((rc = make_plan(gs.data(), G, false, p, d))) return rc;
+    if (p.Ntot == 0) return GEE_OK;
+    unsigned *st = nullptr;
+    if ((rc = device_status(&st))) return rc;
+    Work wk;
+    const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
+    if (!workspace || workspace_bytes < carve(p, parts, nullptr, wk)) return GEE_ERR_WORKSPACE;
+    carve(p, parts, (char *)workspace, wk);
+    hipStream_t s = as_stream(stream);
+    Batch b;
+    hipError_t e = make_batch(p, d, wk, s, false, b);
+    if (e == hipSuccess) e = enqueue_embed(b, p, wk, st, s);
+    return hip_status(e);
+}
+
+int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **out) {
+    if (!out) return GEE_ERR_ARG;
+    *out = nullptr;
+    std::vector<GraphIn> gs;
+    int rc = graphs_from_api(graphs, G, gs);
+    if (rc) return rc;
+    Plan p;
+    std::vector<GDesc> d;
+    if ((rc = make_plan(gs.data(), G, false, p, d))) return rc;
+    if (p.Ntot == 0) return GEE_ERR_ARG;
+    unsigned *st = nullptr;
+    if ((rc = device_status(&st))) return rc;
+    gee_batch_plan *pl = new (std::nothrow) gee_batch_plan();
+    if (!pl) return GEE_ERR_OOM;
+    pl->G = G;
+    (void)hipGetDevice(&pl->device);
+    Work wk;
+    const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
+    pl->ws_bytes = carve(p, parts, nullptr, wk);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e == hipSuccess) {
+        carve(p, parts, (char *)pl->ws, wk);
+        Batch b;
+        e = make_batch(p, d, wk, nullptr, true, b);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            t_capturing = true;
+            hipError_t e1 = enqueue_embed(b, p, wk, st, cs);
+            t_capturing = false;
+            hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
+            e = e1 != hipSuccess ? e1 : e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        gee_batch_plan_destroy(pl);
+        return hip_status(e);
+    }
+    *out = pl;
+    return GEE_OK;
+}
+
+int gee_batch_plan_launch(gee_batch_plan *plan, void *stream) {
+    if (!plan || !plan->exec) return GEE_ERR_ARG;
+    return hip_status(hipGraphLaunch(plan->exec, as_stream(stream)));
+}
+
+int gee_batch_plan_destroy(gee_batch_plan *plan) {
+    if (!plan) return GEE_OK;
+    hipError_t e = hipSuccess;
+    if (plan->exec) e = hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->ws) {
+        hipError_t e2 = hipFree(plan->ws);
+        if (e == hipSuccess) e = e2;
+    }
+    delete plan;
+    return hip_status(e);
+}
+
 // --------------------------------------------------------------------------- embed from CSR
 
 size_t gee_embed_csr_workspace_bytes(int64_t M, int32_t N, int32_t K, uint32_t flags,
                                      const gee_schedule *sched) {
+    GraphIn x;
+    x.E = M;
+    x.N = N;
+    x.K = K;
+    x.flags = flags;
+    x.w = reinterpret_cast<const float *>(16);
+    if (sched) x.sc = *sched;
     Plan p;
-    if (M < 0 || check_common(N, K, flags) || make_plan(M, N, K, flags & ~GEE_SYMMETRIZE, true, sched, p))
-        return 0;
+    std::vector<GDesc> d;
+    if (M < 0 || make_plan(&x, 1, true, p, d)) return 0;
     Work w;
     return carve(p, kPCount | kPEmbed, nullptr, w);
 }
@@ -426,18 +756,31 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     if (!row_ptr || !labels || !Z || (M > 0 && !col)) return GEE_ERR_ARG;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
+    GraphIn x;
+    x.E = M;
+    x.N = N;
+    x.K = K;
+    x.flags = flags;
+    x.w = val;
+    x.labels = labels;
+    x.Z = Z;
+    if (sched) x.sc = *sched;
     Plan p;
-    if ((rc = make_plan(M, N, K, flags & ~GEE_SYMMETRIZE, val != nullptr, sched, p))) return rc;
+    std::vector<GDesc> d;
+    if ((rc = make_plan(&x, 1, true, p, d))) return rc;
     Work wk;
     const unsigned parts = kPCount | kPEmbed;
-    if (!workspace || workspace_bytes < carve(p, parts, nullptr, wk)) return GEE_ERR_WORKSPACE;
+    if (!workspace || workspace_bytes < gee_embed_csr_workspace_bytes(M, N, K, flags, sched))
+        return GEE_ERR_WORKSPACE;
     carve(p, parts, (char *)workspace, wk);
     hipStream_t s = as_stream(stream);
-    const int NW = M > 0 ? (int)((M + p.WE - 1) / p.WE) : 1;
-    hipError_t e = launch_class_counts(labels, N, K, p.cnt_blocks, wk.cpart, wk.counts, wk.inv_n, st, s);
-    if (e == hipSuccess) e = launch_set_meta(wk.meta, (int)M, NW, s);
-    if (e == hipSuccess) e = launch_node_prep(row_ptr, val, labels, p, wk, st, s);
-    if (e == hipSuccess) e = launch_embed(row_ptr, col, val, p, wk, Z, st, s);
+    Batch b;
+    b.one = d[0];
+    b.gm = wk.gm;
+    hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
+    if (e == hipSuccess) e = launch_graph_meta(b, nullptr, (int)M, s);
+    if (e == hipSuccess) e = launch_node_prep(b, p, row_ptr, val, wk, st, s);
+    if (e == hipSuccess) e = launch_embed(b, p, row_ptr, col, val, wk, st, s);
     return hip_status(e);
 }
 

@@ -3,7 +3,9 @@
 // The adjacency entries of an edge list are the rows themselves and, under
 // symmetrization, their mirrors: virtual entry 2e is (src_e -> dst_e) and 2e+1 is
 // (dst_e -> src_e), the latter absent for a self-loop. The CSR is a stable sort of
-// that sequence by row index. Rows are grouped in buckets of 2^sb consecutive rows
+// that sequence by row index. A batch sorts the concatenation of its graphs' sequences
+// with every graph's rows and columns offset by its first node, so each graph's slice of
+// the result is its own CSR. Rows are grouped in buckets of 2^sb consecutive rows
 // (a few thousand entries each); the bucket id is split into a high digit (at most 256
 // values) and a low digit (2^s2 values), and the sort is three stable passes:
 //
@@ -103,49 +105,55 @@ __device__ int block_excl_scan_lds(int *a, int n, int *wsum) {
 
 // ----------------------------------------------------------------------------- pass A
 
-// Valid virtual entry v: row key, column, weight. Invalid: index out of range, or the
-// mirror of a self-loop under symmetrization.
-__device__ __forceinline__ bool load_virtual(const int *__restrict__ src, const int *__restrict__ dst,
-                                             const float *__restrict__ w, int64_t v, int64_t V, int N,
-                                             int sym, int &key, int &cl, float &val, bool &badw) {
+// Virtual entry v of the batch: its graph, then (row, column[, weight]) with the graph's
+// node offset added. Invalid: index out of range (sets badi), or the mirror of a
+// self-loop under symmetrization. `gd`/`g` cache the graph of the previous call.
+template <bool VAL>
+__device__ __forceinline__ bool load_virtual(const Batch &b, int64_t v, int64_t V, int &g, GDesc &gd,
+                                             int &key, int &cl, float &val, bool &badi, bool &badw) {
     if (v >= V) return false;
-    const int64_t e = sym ? (v >> 1) : v;
-    const int side = sym ? (int)(v & 1) : 0;
-    const int s = src[e], d = dst[e];
-    key = side ? d : s;
-    cl = side ? s : d;
-    if (w) {
-        val = w[e];
-        if (side == 0 && !isfinite(val)) badw = true;
+    if (g < 0 || v >= gd.voff + gd.Mcap) {  // entries of one thread only move forward
+        g = find_graph(b.voffs, b.G, v);
+        gd = load_desc(b, g);
     }
-    return (unsigned)s < (unsigned)N && (unsigned)d < (unsigned)N && (side == 0 || s != d);
+    const int64_t lv = v - gd.voff;
+    const bool sym = gd.flags & kSym;
+    const int64_t e = sym ? (lv >> 1) : lv;
+    const int side = sym ? (int)(lv & 1) : 0;
+    const int s = gd.src[e], d = gd.dst[e];
+    key = (side ? d : s) + gd.node_off;
+    cl = (side ? s : d) + gd.node_off;
+    if (VAL) {
+        val = 1.0f;
+        if (gd.w) {
+            val = gd.w[e];
+            if (side == 0 && !isfinite(val)) badw = true;
+        }
+    }
+    const bool inr = (unsigned)s < (unsigned)gd.N && (unsigned)d < (unsigned)gd.N;
+    if (!inr) badi = true;
+    return inr && (side == 0 || s != d);
 }
 
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
-__global__ __launch_bounds__(256) void a_hist(const int *__restrict__ src, const int *__restrict__ dst,
-                                              int64_t E, int N, int sym, int shift, int D, int64_t T,
+__global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
                                               int *__restrict__ gh, unsigned *status) {
     __shared__ int hist[256];
     hist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
-    const int64_t V = sym ? 2 * E : E;
     const int64_t v0 = t * kTile;
-    const int64_t v1 = min(v0 + kTile, V);
-    bool bad = false;
-    const int64_t e0 = sym ? v0 / 2 : v0;
-    const int64_t e1 = sym ? (v1 + 1) / 2 : v1;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const int s = src[e], d = dst[e];
-        if ((unsigned)s < (unsigned)N && (unsigned)d < (unsigned)N) {
-            atomicAdd(&hist[s >> shift], 1);
-            if (sym && s != d) atomicAdd(&hist[d >> shift], 1);
-        } else {
-            bad = true;
-        }
+    bool badi = false, badw = false;
+    int g = -1;
+    GDesc gd;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t v = v0 + r * 256 + threadIdx.x;
+        int key, cl;
+        float val;
+        if (load_virtual<false>(b, v, V, g, gd, key, cl, val, badi, badw)) atomicAdd(&hist[key >> shift], 1);
     }
-    if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrIndex);
+    if (__syncthreads_or(badi) && threadIdx.x == 0) raise_error(status, kErrIndex);
     if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
 }
 
@@ -178,11 +186,11 @@ __global__ __launch_bounds__(256) void digit_scan(int *__restrict__ gh, int64_t 
 }
 
 // Single workgroup over the D <= 256 high digits: segment starts, the entry count M,
-// the embed wavefront count, and (with a pass B) the pass-B tiles of every segment.
+// and (with a pass B) the pass-B tiles of every segment.
 // Without a pass B the segments are the buckets.
 __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int D, int with_b, int B,
                                                 int *__restrict__ seg_start, int *__restrict__ tile_off,
-                                                int *__restrict__ bstart, int *__restrict__ meta, int WE) {
+                                                int *__restrict__ bstart, int *__restrict__ meta) {
     __shared__ int wsum[4];
     const int d = threadIdx.x;
     const int n = d < D ? tot[d] : 0;
@@ -201,7 +209,6 @@ __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int
         if (with_b) tile_off[D] = ttot;
         bstart[B] = total;
         meta[0] = total;
-        meta[1] = total > 0 ? (int)(((int64_t)total + WE - 1) / WE) : 1;
     }
 }
 
@@ -231,9 +238,7 @@ struct PartLds {
 
 // Pass A scatter: tile t of the virtual entries, ranked by high digit, staged, and
 // written to seg_start[d] + (scanned tile offset) in runs.
-__global__ __launch_bounds__(256) void a_scatter(const int *__restrict__ src, const int *__restrict__ dst,
-                                                 const float *__restrict__ w, int64_t E, int N, int sym,
-                                                 int shift, int D, int nbits, int64_t T,
+__global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
                                                  const int *__restrict__ gh, const int *__restrict__ tot,
                                                  const int *__restrict__ seg_start, int *__restrict__ okey,
                                                  int *__restrict__ ocol, float *__restrict__ oval,
@@ -249,14 +254,15 @@ __global__ __launch_bounds__(256) void a_scatter(const int *__restrict__ src, co
         gb = seg_start[threadIdx.x] + cur;
     }
     const int n = tile_layout(cnt, gb, D, L.lstart, L.run, L.gbase, L.tab, L.wsum);
-    const int64_t V = sym ? 2 * E : E;
     const int64_t v0 = t * kTile;
-    bool badw = false;
+    bool badi = false, badw = false;
+    int g = -1;
+    GDesc gd;
     for (int r = 0; r < kRounds; ++r) {
         const int64_t v = v0 + r * 256 + threadIdx.x;
         int key = 0, cl = 0;
         float val = 1.0f;
-        const bool valid = load_virtual(src, dst, w, v, V, N, sym, key, cl, val, badw);
+        const bool valid = load_virtual<true>(b, v, V, g, gd, key, cl, val, badi, badw);
         const int digit = valid ? (key >> shift) : 0;
         const int pos = block_rank4(digit, valid, nbits, L.tab, L.run, D);
         if (valid) {
@@ -269,10 +275,10 @@ __global__ __launch_bounds__(256) void a_scatter(const int *__restrict__ src, co
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int key = L.key[i];
         const int d = key >> shift;
-        const int64_t g = (int64_t)L.gbase[d] + (i - L.lstart[d]);
-        okey[g] = key;
-        ocol[g] = L.col[i];
-        if (oval) oval[g] = L.val[i];
+        const int64_t g2 = (int64_t)L.gbase[d] + (i - L.lstart[d]);
+        okey[g2] = key;
+        ocol[g2] = L.col[i];
+        if (oval) oval[g2] = L.val[i];
     }
 }
 
@@ -471,21 +477,18 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 static int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
 size_t bucket_sort_lds(int sb) { return (size_t)(1 << sb) * 8 + (size_t)bucket_stage_cap(sb) * 8; }
 
-hipError_t launch_csr_build(const int *src, const int *dst, const float *w, const Plan &p,
-                            const Work &wk, unsigned *status, hipStream_t s) {
-    const int sym = (p.flags & kSym) ? 1 : 0;
+hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
     const bool with_b = p.s2 > 0;
     const int shift = p.sb + p.s2;
     int nbits = 0;
     while ((1 << nbits) < p.DA) ++nbits;
-    const float *wv = p.weighted ? w : nullptr;
     // pass A output: final col/val buffers as scratch when a pass B follows
     int *acol = with_b ? wk.col : wk.tcol;
     float *aval = p.weighted ? (with_b ? wk.val : wk.tval) : nullptr;
     hipError_t e;
     prof_begin(kKAHist, s);
-    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(256), 0, s, src, dst, p.E, p.N, sym, shift, p.DA,
-                       p.TA, wk.ghA, status);
+    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, p.TA, wk.ghA,
+                       status);
     prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScan, s);
@@ -494,12 +497,12 @@ hipError_t launch_csr_build(const int *src, const int *dst, const float *w, cons
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKATotals, s);
     hipLaunchKernelGGL(a_totals, dim3(1), dim3(256), 0, s, wk.totA, p.DA, with_b ? 1 : 0, p.B, wk.segA,
-                       wk.tileB, wk.bstart, wk.meta, p.WE);
+                       wk.tileB, wk.bstart, wk.meta);
     prof_end(kKATotals, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScatter, s);
-    hipLaunchKernelGGL(a_scatter, dim3((unsigned)p.TA), dim3(256), 0, s, src, dst, wv, p.E, p.N, sym, shift,
-                       p.DA, nbits, p.TA, wk.ghA, wk.totA, wk.segA, wk.akey, acol, aval, status);
+    hipLaunchKernelGGL(a_scatter, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits, p.TA,
+                       wk.ghA, wk.totA, wk.segA, wk.akey, acol, aval, status);
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!with_b) return hipSuccess;
@@ -528,10 +531,10 @@ hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hip
     prof_begin(kKBucketSort, s);
     if (p.s2 > 0) {
         hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, wk.tkey, wk.tcol, tv, wk.bstart,
-                           p.B, p.sb, p.N, wk.rp, wk.col, ov, cap);
+                           p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap);
     } else {
         hipLaunchKernelGGL(bucket_sort<int>, dim3(p.B), dim3(256), lds, s, wk.akey, wk.tcol, tv, wk.bstart, p.B,
-                           p.sb, p.N, wk.rp, wk.col, ov, cap);
+                           p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap);
     }
     prof_end(kKBucketSort, s);
     return hipGetLastError();

@@ -7,30 +7,36 @@
 // replaced by D^-1/2 (A + I) D^-1/2: the rescale e_ij s_i s_j is split into the
 // gathered c_j and the per-row s_i, and the identity's entry is the c_i term.
 //
+// Every kernel serves a batch of graphs (a plain call is a batch of one): rows and CSR
+// entries are those of the union, and each work item reads its graph's sizes, options
+// and schedule from the graph descriptor (gee_internal.h). A graph's work is split
+// exactly as when it is embedded alone, so its Z is bit-identical either way.
+//
 // Work split (MI355X, 64-wide wavefronts, HBM-bound, no MFMA since W is one-hot):
+//   * graph_meta   per graph: first CSR entry, entry count, embed wavefront count.
 //   * node_rows    thread per row: the first row of every wavefront, the row step of
 //                  each row's first entry (see below), and the coefficients c_i, s_i
 //                  wherever the degree is a row count or not needed.
 //   * degree_rows  (weighted Laplacian) degrees as segmented sums over entry-balanced
 //                  wavefronts, then c_i and s_i; degree_fixup finishes cut rows.
 //   * fill_empty   rows without entries (zero, or the diagonal term alone).
-//   * embed_rows   wavefront w processes the CSR entries [w*WE, (w+1)*WE) in windows
-//                  of 64, so every wavefront does the same work whatever the degree
-//                  distribution. Rows are found without row_ptr lookups: a byte per
-//                  entry holds the row step from the previous entry (0 inside a row;
-//                  an escape value for steps >= 255), and a wave prefix sum turns the
-//                  steps into row ids. The wavefront works in batches of 4 windows; the
-//                  col/val/step loads of batch k+2 and the gathers of batch k+1 ({c_j,
-//                  y_j} by column, {c_i, y_i, s_i} by row) are in flight while batch k
-//                  is processed, and nothing loaded is consumed in the batch that loads
-//                  it, so the memory pipeline never drains inside a batch.
-//                  Rows get slots of an LDS ring acc[class][slot]. A window inside one
-//                  row adds into per-lane columns (no conflicts, no matching);
-//                  otherwise lanes of one row with the same class are found by ballots
-//                  and take turns in lane order. The summation order is fixed, so
-//                  results are bitwise reproducible. Rows ending in the wavefront are
-//                  finished there (diagonal term, s_i, correlation) and stored with
-//                  coalesced writes; rows cut by wavefront boundaries leave raw partials.
+//   * embed_rows   wavefront w of a graph processes that graph's CSR entries
+//                  [w*WE, (w+1)*WE) in windows of 64, so every wavefront does the same
+//                  work whatever the degree distribution. Rows are found without
+//                  row_ptr lookups: a byte per entry holds the row step from the previous
+//                  entry (0 inside a row; an escape value for steps >= 255), and a wave
+//                  prefix sum turns the steps into row ids. The wavefront works in
+//                  batches of 4 windows; the col/val/step loads of batch k+2 and the
+//                  gathers of batch k+1 ({c_j, y_j} by column, {c_i, y_i, s_i} by row)
+//                  are in flight while batch k is processed, and nothing loaded is
+//                  consumed in the batch that loads it, so the memory pipeline never
+//                  drains inside a batch. Rows get slots of an LDS ring acc[class][slot];
+//                  every lane adds its entry into acc[y_j][slot(row)] with an LDS float
+//                  atomic, and the LDS applies lanes that hit the same word one after
+//                  another in a fixed order, so results are bitwise reproducible. Rows
+//                  ending in the wavefront are finished there (diagonal term, s_i,
+//                  correlation) and stored with coalesced writes; rows cut by wavefront
+//                  boundaries leave raw partials.
 //   * embed_fixup  adds the partials of each cut row in wavefront order and finishes it.
 #include "gee_internal.h"
 
@@ -46,7 +52,17 @@ constexpr int BW = 4;          // windows per pipeline batch
 // [K][65], rounded to 16 bytes.
 __host__ __device__ constexpr int embed_lds_floats(int K) { return 4 * 64 + ((K * KS + 3) & ~3); }
 
-// ----------------------------------------------------------------------------- row steps
+// Graph and local index of embed wavefront w; false if w has no work.
+__device__ __forceinline__ bool wave_graph(const Batch &b, int w, GDesc &d, GMeta &m, int &lw) {
+    const int g = find_graph(b.wave_offs, b.G, w);
+    d = load_desc(b, g);
+    lw = w - d.wave_off;
+    if (lw < 0 || lw >= d.NWcap) return false;
+    m = b.gm[g];
+    return lw < m.NW;
+}
+
+// ----------------------------------------------------------------------------- per graph
 
 __global__ __launch_bounds__(256) void zero_bytes(uint8_t *__restrict__ p, int64_t n) {
     const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 16;
@@ -57,54 +73,79 @@ __global__ __launch_bounds__(256) void zero_bytes(uint8_t *__restrict__ p, int64
     }
 }
 
+// Thread per graph: entry range and wavefront count, from the union's row_ptr or, for a
+// single resident CSR, from its entry count.
+__global__ __launch_bounds__(256) void graph_meta(Batch b, const int *__restrict__ rp, int M1) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.G) return;
+    const GDesc d = load_desc(b, g);
+    GMeta m;
+    if (rp) {
+        m.ent_off = rp[d.node_off];
+        m.M = rp[d.node_off + d.N] - m.ent_off;
+    } else {
+        m.ent_off = 0;
+        m.M = M1;
+    }
+    m.NW = m.M > 0 ? (int)min((int64_t)d.NWcap, ((int64_t)m.M + d.WE - 1) / d.WE) : 0;
+    m.pad = 0;
+    b.gm[g] = m;
+}
+
+// ----------------------------------------------------------------------------- row steps
+
 // Thread per row: the first row of every embed wavefront (wrow), the step byte of each
-// non-empty row's first entry (rows since the previous non-empty row, capped at the
-// escape value), ownership checks, and the per-node data needing no weighted degree
-// (with `skip_nonempty`, a weighted Laplacian, degree_rows fills non-empty rows).
-__global__ __launch_bounds__(256) void node_rows(const int *__restrict__ rp, int N, const int *__restrict__ meta,
-                                                 int WE, const int *__restrict__ labels, int K,
-                                                 const float *__restrict__ inv_n, unsigned flags,
-                                                 int skip_nonempty, float2 *__restrict__ info,
+// non-empty row's first entry (rows since the previous non-empty row of the graph,
+// capped at the escape value), ownership checks, and the per-node data needing no
+// weighted degree (a weighted graph with the Laplacian gets them from degree_rows).
+__global__ __launch_bounds__(256) void node_rows(Batch b, int Ntot, const int *__restrict__ rp,
+                                                 const float *__restrict__ inv_n, float2 *__restrict__ info,
                                                  float *__restrict__ srow, int *__restrict__ wrow,
                                                  uint8_t *__restrict__ rstep, unsigned *status) {
     const int r = blockIdx.x * 256 + threadIdx.x;
-    const int M = meta[0], NW = meta[1];
     bool bad = false;
-    if (r < N) {
+    if (r < Ntot) {
+        const int g = find_graph(b.node_offs, b.G, r);
+        const GDesc d = load_desc(b, g);
+        const GMeta m = b.gm[g];
+        const int rl = r - d.node_off;
         const int lo = rp[r], hi = rp[r + 1];
-        if (lo > hi || lo < 0 || hi > M || (r == 0 && lo != 0) || (r == N - 1 && hi != M)) bad = true;
-        const bool lap = flags & kLap, diag = flags & kDiag;
-        if (!(skip_nonempty && hi > lo)) {
-            int y = labels[r];
-            if (y < 0 || y >= K) y = -1;
+        const int e_lo = m.ent_off, e_hi = m.ent_off + m.M;
+        if (lo > hi || lo < e_lo || hi > e_hi || (rl == 0 && lo != e_lo) || (rl == d.N - 1 && hi != e_hi))
+            bad = true;
+        const bool lap = d.flags & kLap, diag = d.flags & kDiag;
+        const bool skip = d.weighted && lap && hi > lo;
+        if (!skip) {
+            int y = d.labels[rl];
+            if (y < 0 || y >= d.K) y = -1;
             float s = 1.0f;
             if (lap) {
-                const float d = (float)max(hi - lo, 0) + (diag ? 1.0f : 0.0f);
-                s = d > 0.0f ? 1.0f / sqrtf(d) : 0.0f;
+                const float dg = (float)max(hi - lo, 0) + (diag ? 1.0f : 0.0f);
+                s = dg > 0.0f ? 1.0f / sqrtf(dg) : 0.0f;
                 srow[r] = s;
             }
-            info[r] = make_float2(y >= 0 ? s * inv_n[y] : 0.0f, __int_as_float(y));
+            info[r] = make_float2(y >= 0 ? s * inv_n[d.class_off + y] : 0.0f, __int_as_float(y));
         }
-        if (hi > lo && lo >= 0 && hi <= M) {
-            // rows back to the previous non-empty row (row -1 before row 0)
+        if (hi > lo && !bad) {
+            // rows back to the previous non-empty row of the graph (row -1 before row 0)
             int gap = 1;
-            while (gap < kStepEsc && r - gap >= 0 && rp[r - gap] == rp[r - gap + 1]) ++gap;
+            while (gap < kStepEsc && rl - gap >= 0 && rp[r - gap] == rp[r - gap + 1]) ++gap;
             rstep[lo] = (uint8_t)min(gap, kStepEsc);
-            // wavefronts whose first entry lies in this row
-            const int64_t wa = ((int64_t)lo + WE - 1) / WE;
-            const int64_t wb = min(((int64_t)hi - 1) / WE, (int64_t)NW - 1);
-            for (int64_t ww = wa; ww <= wb; ++ww) wrow[ww] = r;
+            // wavefronts of the graph whose first entry lies in this row
+            const int64_t wa = ((int64_t)(lo - e_lo) + d.WE - 1) / d.WE;
+            const int64_t wb = min(((int64_t)(hi - e_lo) - 1) / d.WE, (int64_t)m.NW - 1);
+            for (int64_t ww = wa; ww <= wb; ++ww) wrow[d.wave_off + ww] = r;
         }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrCsr);
 }
 
-// The row holding entry q (last r with rp[r] <= q), by binary search.
-__device__ __forceinline__ int row_of_entry(const int *__restrict__ rp, int N, int q) {
+// The row holding entry q among the graph's rows rp[0..N] (last r with rp[r] <= q).
+__device__ __forceinline__ int row_of_entry(const int *__restrict__ rpg, int N, int q) {
     int lo = 0, hi = N;  // answer in [lo, hi)
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (rp[mid] <= q) lo = mid;
+        if (rpg[mid] <= q) lo = mid;
         else hi = mid;
     }
     return lo;
@@ -113,8 +154,9 @@ __device__ __forceinline__ int row_of_entry(const int *__restrict__ rp, int N, i
 // Rows of the 64 lanes of a window from their step bytes: row = base + inclusive sum of
 // the steps; an escape lane looks its row up and the sum restarts there. `d` must be 0 on
 // lanes past the end. With `force_lane0`, lane 0's step is taken as 0 (its row is `base`).
+// rpg/N/node_off: the graph's rows.
 __device__ __forceinline__ int window_rows(int d, int base, bool force_lane0, int p,
-                                           const int *__restrict__ rp, int N) {
+                                           const int *__restrict__ rpg, int N, int node_off) {
     const int lane = lane_id();
     if (force_lane0 && lane == 0) d = 0;
     const bool esc = d == kStepEsc;
@@ -122,7 +164,7 @@ __device__ __forceinline__ int window_rows(int d, int base, bool force_lane0, in
     const uint64_t em = ballot(esc);
     if (em == 0) return base + S;
     // rare: a run of >= 254 empty rows before some row of this window
-    const int ar = esc ? row_of_entry(rp, N, p + lane) : 0;
+    const int ar = esc ? row_of_entry(rpg, N, p + lane) + node_off : 0;
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
     const uint64_t eb = em & le;
     const int e = eb ? 63 - __clzll(eb) : 0;
@@ -132,46 +174,53 @@ __device__ __forceinline__ int window_rows(int d, int base, bool force_lane0, in
 
 // ----------------------------------------------------------------------------- degrees
 
-__device__ __forceinline__ void finish_node(int r, float d, int y, const float *inv_n_lds, bool diag,
+__device__ __forceinline__ void finish_node(int r, float d, int y, float inv_n_y, bool diag,
                                             float2 *__restrict__ info, float *__restrict__ srow) {
     const float dd = d + (diag ? 1.0f : 0.0f);
     const float s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
     srow[r] = s;
-    info[r] = make_float2(y >= 0 ? s * inv_n_lds[y] : 0.0f, __int_as_float(y));
+    info[r] = make_float2(y >= 0 ? s * inv_n_y : 0.0f, __int_as_float(y));
 }
 
 // Weighted degrees d_i = sum of the row's values, as segmented sums over the same
 // entry-balanced wavefronts and batches as embed_rows (fixed summation order; the open
-// row's running sum is compensated). Then s_i and c_i.
-__global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, const float *__restrict__ val,
+// row's running sum is compensated). Then s_i and c_i. Wavefronts of graphs without
+// weights or without the Laplacian leave at once.
+__global__ __launch_bounds__(256) void degree_rows(Batch b, const int *__restrict__ rp,
+                                                   const float *__restrict__ val,
                                                    const uint8_t *__restrict__ rstep,
-                                                   const int *__restrict__ wrow, const int *__restrict__ meta,
-                                                   int N, int WE, const int *__restrict__ labels, int K,
-                                                   const float *__restrict__ inv_n, unsigned flags,
-                                                   float2 *__restrict__ info, float *__restrict__ srow,
-                                                   float *__restrict__ headd, float *__restrict__ taild,
-                                                   int *__restrict__ dsplit) {
-    __shared__ float invn_s[kMaxClasses];
-    for (int k = threadIdx.x; k < K; k += blockDim.x) invn_s[k] = inv_n[k];
-    __syncthreads();
+                                                   const int *__restrict__ wrow,
+                                                   const float *__restrict__ inv_n, float2 *__restrict__ info,
+                                                   float *__restrict__ srow, float *__restrict__ headd,
+                                                   float *__restrict__ taild, int *__restrict__ dsplit) {
     const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int M = meta[0], NW = meta[1];
-    const int w = blockIdx.x * (blockDim.x >> 6) + wib;
-    if (w >= NW) return;
-    const bool diag = flags & kDiag;
-    const int a = w * WE, b = min(a + WE, M), last = b - 1;
-    const int row_a = min(max(wrow[w], 0), N - 1);
-    const bool head = rstep[a] == 0;
+    const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    GDesc gd;
+    GMeta gm;
+    int lw;
+    if (!wave_graph(b, w, gd, gm, lw)) return;
+    if (!(gd.weighted && (gd.flags & kLap))) return;
+    const bool diag = gd.flags & kDiag;
+    const int N = gd.N, K = gd.K, node_off = gd.node_off;
+    const int *rpg = rp + node_off;
+    const float *invn = inv_n + gd.class_off;
+    const int a = gm.ent_off + lw * gd.WE, b_ = min(a + gd.WE, gm.ent_off + gm.M), last = b_ - 1;
+    const int E_end = gm.ent_off + gm.M;
+    const int row_a = min(max(wrow[w], node_off), node_off + N - 1);
+    const bool head = __builtin_amdgcn_readfirstlane(rstep[a]) == 0;
     const int head_row = head ? row_a : -1;
-    const bool cont_end = b < M && rstep[min(b, M - 1)] == 0;
+    const bool cont_end = b_ < E_end && __builtin_amdgcn_readfirstlane(rstep[min(b_, E_end - 1)]) == 0;
     int cur_row = head ? row_a : -1;
     float carry = 0.0f, comp = 0.0f;  // running sum of the open row and its compensation
     bool cont = false;
-    const int nwin = (b - a + 63) >> 6;
-    auto ld_val = [&](int e) { const float v = val[min(e, last)]; return e < b ? v : 0.0f; };
-    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b ? v : 0; };
-    auto ld_lab = [&](int r) { const int y = labels[min(max(r, 0), N - 1)]; return (y >= 0 && y < K) ? y : -1; };
+    const int nwin = (b_ - a + 63) >> 6;
+    auto ld_val = [&](int e) { const float v = val[min(e, last)]; return e < b_ ? v : 0.0f; };
+    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b_ ? v : 0; };
+    auto ld_lab = [&](int r) {
+        const int y = gd.labels[min(max(r - node_off, 0), N - 1)];
+        return (y >= 0 && y < K) ? y : -1;
+    };
+    auto inv_of = [&](int y) { return y >= 0 ? invn[y] : 0.0f; };
     float vc[BW], vn1[BW], vn2[BW];
     int dc[BW], dn1[BW], dn2[BW], rc[BW], rn1[BW], yc[BW], yn1[BW];
     int base;
@@ -185,14 +234,14 @@ __global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, c
     base = row_a;
 #pragma unroll
     for (int u = 0; u < BW; ++u) {
-        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rp, N);
+        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rpg, N, node_off);
         base = readlane(rc[u], 63);
         yc[u] = ld_lab(rc[u]);
     }
     for (int i0 = 0; i0 < nwin; i0 += BW) {
 #pragma unroll
         for (int u = 0; u < BW; ++u) {
-            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rp, N);
+            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rpg, N, node_off);
             base = readlane(rn1[u], 63);
             yn1[u] = ld_lab(rn1[u]);
             vn2[u] = ld_val(a + (i0 + 2 * BW + u) * 64 + lane);
@@ -203,11 +252,11 @@ __global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, c
             const int i = i0 + u;
             if (i >= nwin) break;
             const int p = a + (i << 6);
-            const int nvalid = min(64, b - p);
+            const int nvalid = min(64, b_ - p);
             const float v = vc[u];
             const int row = rc[u];
             const int nxt = (u + 1 < BW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
-            cont = (p + nvalid < b) ? (nxt == 0) : cont_end;
+            cont = (p + nvalid < b_) ? (nxt == 0) : cont_end;
             const uint64_t sm = ballot(lane < nvalid && dc[u] != 0);
             if (sm == 0) {  // the window lies inside the open row
                 const float t = wave_sum(v) - comp;
@@ -217,8 +266,8 @@ __global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, c
                 if (!cont) {
                     if (lane == 0) {  // every lane holds the open row and its label
                         if (cur_row == head_row) headd[w] = carry;
-                        else if (cur_row >= 0 && cur_row < N)
-                            finish_node(cur_row, carry, yc[u], invn_s, diag, info, srow);
+                        else if (cur_row >= node_off && cur_row < node_off + N)
+                            finish_node(cur_row, carry, yc[u], inv_of(yc[u]), diag, info, srow);
                     }
                     carry = comp = 0.0f;
                 }
@@ -230,12 +279,13 @@ __global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, c
             const bool last_of_seg = lane < nvalid && (lane == nvalid - 1 || nxt_row != row);
             const int row_last = readlane(row, nvalid - 1);
             if (last_of_seg) {
-                float d = x;
-                if (row == cur_row) d = carry + (x - comp);  // the open row's earlier windows first
+                float dsum = x;
+                if (row == cur_row) dsum = carry + (x - comp);  // the open row's earlier windows first
                 const bool ends = !(row == row_last && cont);
                 if (ends) {
-                    if (row == head_row) headd[w] = d;
-                    else if (row >= 0 && row < N) finish_node(row, d, yc[u], invn_s, diag, info, srow);
+                    if (row == head_row) headd[w] = dsum;
+                    else if (row >= node_off && row < node_off + N)
+                        finish_node(row, dsum, yc[u], inv_of(yc[u]), diag, info, srow);
                 }
             }
             const float tail = readlane_f(x, nvalid - 1);
@@ -269,64 +319,53 @@ __global__ __launch_bounds__(256) void degree_rows(const int *__restrict__ rp, c
     if (lane == 0) dsplit[w] = my_split;
 }
 
-__global__ __launch_bounds__(256) void degree_fixup(const int *__restrict__ rp, const int *__restrict__ meta,
-                                                    int N, int WE, const int *__restrict__ labels, int K,
-                                                    const float *__restrict__ inv_n, unsigned flags,
+// Thread per wavefront: the degree of a row cut by wavefront boundaries, in wavefront order.
+__global__ __launch_bounds__(256) void degree_fixup(Batch b, int NWtot, const int *__restrict__ rp,
+                                                    const float *__restrict__ inv_n,
                                                     const float *__restrict__ headd,
                                                     const float *__restrict__ taild,
-                                                    const int *__restrict__ dsplit,
-                                                    float2 *__restrict__ info, float *__restrict__ srow) {
-    const int NW = meta[1];
+                                                    const int *__restrict__ dsplit, float2 *__restrict__ info,
+                                                    float *__restrict__ srow) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= NW) return;
+    if (w >= NWtot) return;
+    GDesc gd;
+    GMeta gm;
+    int lw;
+    if (!wave_graph(b, w, gd, gm, lw)) return;
+    if (!(gd.weighted && (gd.flags & kLap))) return;
     const int r = dsplit[w];
-    if (r < 0 || r >= N) return;
+    if (r < gd.node_off || r >= gd.node_off + gd.N) return;
     const int end = rp[r + 1];
-    const int we = (int)min((int64_t)NW - 1, max((int64_t)w, ((int64_t)end - 1) / WE));
+    const int wl = (int)min((int64_t)gm.NW - 1, max((int64_t)lw, ((int64_t)(end - gm.ent_off) - 1) / gd.WE));
     float d = taild[w];
-    for (int w2 = w + 1; w2 <= we; ++w2) d += headd[w2];
-    int y = labels[r];
-    if (y < 0 || y >= K) y = -1;
-    const float dd = d + ((flags & kDiag) ? 1.0f : 0.0f);
-    const float s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
-    srow[r] = s;
-    info[r] = make_float2(y >= 0 ? s * inv_n[y] : 0.0f, __int_as_float(y));
+    for (int w2 = lw + 1; w2 <= wl; ++w2) d += headd[gd.wave_off + w2];
+    int y = gd.labels[r - gd.node_off];
+    if (y < 0 || y >= gd.K) y = -1;
+    finish_node(r, d, y, y >= 0 ? inv_n[gd.class_off + y] : 0.0f, gd.flags & kDiag, info, srow);
 }
 
 // ----------------------------------------------------------------------------- empty rows
 
-__global__ __launch_bounds__(256) void fill_empty(const int *__restrict__ rp, int N, int K,
-                                                  unsigned flags, const float2 *__restrict__ info,
-                                                  const float *__restrict__ srow,
-                                                  float *__restrict__ Z) {
-    __shared__ int emp[256];
-    __shared__ float dv[256];
-    __shared__ int yy[256];
-    const int r0 = blockIdx.x * 256;
-    const int r = r0 + threadIdx.x;
-    const bool lap = flags & kLap, diag = flags & kDiag, cor = flags & kCor;
-    int e = 0;
-    float d = 0.0f;
+// Thread per row: a row without entries is zero, or holds the diagonal term alone
+// (c_i s_i at its own class; 1 under correlation).
+__global__ __launch_bounds__(256) void fill_empty(Batch b, int Ntot, const int *__restrict__ rp,
+                                                  const float2 *__restrict__ info,
+                                                  const float *__restrict__ srow) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= Ntot || rp[r] != rp[r + 1]) return;
+    const int g = find_graph(b.node_offs, b.G, r);
+    const GDesc d = load_desc(b, g);
+    const bool lap = d.flags & kLap, diag = d.flags & kDiag, cor = d.flags & kCor;
     int y = -1;
-    if (r < N) {
-        e = rp[r] == rp[r + 1];
-        if (e && diag) {
-            const float2 inf = info[r];
-            y = __float_as_int(inf.y);
-            d = inf.x * (lap ? srow[r] : 1.0f);
-            if (cor) d = d != 0.0f ? 1.0f : 0.0f;
-        }
+    float v = 0.0f;
+    if (diag) {
+        const float2 inf = info[r];
+        y = __float_as_int(inf.y);
+        v = inf.x * (lap ? srow[r] : 1.0f);
+        if (cor) v = v != 0.0f ? 1.0f : 0.0f;
     }
-    emp[threadIdx.x] = e;
-    dv[threadIdx.x] = d;
-    yy[threadIdx.x] = y;
-    if (!__syncthreads_or(e)) return;
-    const int nr = min(256, N - r0);
-    const int64_t base = (int64_t)r0 * K;
-    for (int idx = threadIdx.x; idx < nr * K; idx += 256) {
-        const int i = idx / K, k = idx - i * K;
-        if (emp[i]) Z[base + idx] = (k == yy[i]) ? dv[i] : 0.0f;
-    }
+    float *z = d.Z + (int64_t)(r - d.node_off) * d.K;
+    for (int k = 0; k < d.K; ++k) z[k] = (k == y) ? v : 0.0f;
 }
 
 // ----------------------------------------------------------------------------- finish a row
@@ -355,82 +394,90 @@ __device__ __forceinline__ float group_sum(float v, int kp) {
 
 // ----------------------------------------------------------------------------- main kernel
 
-template <bool WEIGHTED, bool WIDE>
-__global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, const int *__restrict__ col,
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict__ rp, const int *__restrict__ col,
                                                   const float *__restrict__ val,
                                                   const uint8_t *__restrict__ rstep,
                                                   const float2 *__restrict__ info,
                                                   const float *__restrict__ srow,
-                                                  const int *__restrict__ wrow,
-                                                  const int *__restrict__ meta, int N, int K, int kp,
-                                                  int WE, unsigned flags, float *__restrict__ Z,
+                                                  const int *__restrict__ wrow, int lds_floats,
                                                   float *__restrict__ headp, float *__restrict__ tailp,
                                                   int *__restrict__ split, unsigned *status) {
     extern __shared__ float smem_f[];
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
-    const int M = meta[0], NW = meta[1];
     const int w = blockIdx.x * wpb + wib;
-    if (w >= NW) return;  // whole wavefront leaves; no workgroup barrier is used below
+    GDesc gd;
+    GMeta gm;
+    int lw;
+    if (!wave_graph(b, w, gd, gm, lw)) return;  // whole wavefront leaves; no workgroup barrier below
+    const unsigned flags = gd.flags;
     const bool diag = flags & kDiag, lap = flags & kLap, cor = flags & kCor;
+    const int N = gd.N, K = gd.K, kp = gd.kp, node_off = gd.node_off;
+    const bool wide = K > 64;
+    const int *rpg = rp + node_off;
+    float *Z = gd.Z;
+    float *headw = headp + gd.part_off + (int64_t)lw * K;
+    float *tailw = tailp + gd.part_off + (int64_t)lw * K;
 
     // per wavefront: slot table [64] {row, c_i, y_i, s_i}, then the ring acc[K][KS]
-    float4 *slot_meta = reinterpret_cast<float4 *>(smem_f + (size_t)wib * embed_lds_floats(K));
+    float4 *slot_meta = reinterpret_cast<float4 *>(smem_f + (size_t)wib * lds_floats);
     float *acc = reinterpret_cast<float *>(slot_meta + 64);
     for (int k = 0; k < K; ++k) acc[k * KS + lane] = 0.0f;
     // Finished rows stay in their ring slots ("pending") until drain() stores them:
     // slots [pend_first, pend_first + npend) in ring order, just behind the open row.
     int npend = 0, pend_first = 0;
 
-    const int a = w * WE;
-    const int b = min(a + WE, M);
-    const int last = b - 1;
-    const int row_a = min(max(wrow[w], 0), N - 1);
+    const int E_end = gm.ent_off + gm.M;
+    const int a = gm.ent_off + lw * gd.WE;
+    const int b_ = min(a + gd.WE, E_end);
+    const int last = b_ - 1;
+    const int row_a = min(max(wrow[w], node_off), node_off + N - 1);
     // entry a continues a row begun before the wavefront / entry b continues the last row
     const bool head = __builtin_amdgcn_readfirstlane(rstep[a]) == 0;
     const int head_row = head ? row_a : -1;
-    const bool cont_end = b < M && __builtin_amdgcn_readfirstlane(rstep[min(b, M - 1)]) == 0;
+    const bool cont_end = b_ < E_end && __builtin_amdgcn_readfirstlane(rstep[min(b_, E_end - 1)]) == 0;
     int cur_row = head ? row_a : -1;
     int cur_slot = 63;
     if (lane == 0) slot_meta[63] = make_float4(__int_as_float(cur_row), 0.0f, __int_as_float(-1), 0.0f);
     bool cont = false;
 
     // Finish the pending rows (diagonal term, s_i, correlation; the head row goes out
-    // raw) and store them. kp lanes per row (WIDE: one row, two classes per lane). This
-    // loop holds the only global stores and reads nothing loaded from global memory, so
-    // it never waits for the loads in flight.
+    // raw) and store them: kp lanes per row, or (K > 64) one row per pass with two
+    // classes per lane. This loop holds the only global stores and reads nothing loaded
+    // from global memory, so it never waits for the loads in flight.
     auto drain = [&]() {
         wave_lds_fence();
-        const int grp = WIDE ? 1 : 64 / kp;  // rows per pass
-        const int g = WIDE ? 0 : lane / kp;
-        const int k = WIDE ? lane : lane & (kp - 1);
+        const int grp = wide ? 1 : 64 / kp;  // rows per pass
+        const int g = wide ? 0 : lane / kp;
+        const int k = wide ? lane : lane & (kp - 1);
         const int kk = min(k, K - 1);
+        const int k2 = min(k + 64, K - 1);
         for (int j = 0; j < npend; j += grp) {
             const bool has = j + g < npend;
             const int sl = (pend_first + j + g) & 63;
             const float4 m = slot_meta[sl];
             const int r = __float_as_int(m.x);
             const int lab = __float_as_int(m.z);
-            const bool live = has && r >= 0 && r < N;
+            const bool live = has && r >= node_off && r < node_off + N;
             float v0 = acc[kk * KS + sl];
-            float v1 = 0.0f;
-            if (WIDE) v1 = acc[min(k + 64, K - 1) * KS + sl];
+            float v1 = wide ? acc[k2 * KS + sl] : 0.0f;
             if (has) {
                 acc[kk * KS + sl] = 0.0f;
-                if (WIDE && k + 64 < K) acc[(k + 64) * KS + sl] = 0.0f;
+                if (wide && k + 64 < K) acc[(k + 64) * KS + sl] = 0.0f;
             }
             v0 = k < K ? v0 : 0.0f;
-            v1 = (WIDE && k + 64 < K) ? v1 : 0.0f;
+            v1 = (wide && k + 64 < K) ? v1 : 0.0f;
             float z0 = v0, z1 = v1;
             if (diag && k == lab) z0 += m.y;
-            if (WIDE && diag && k + 64 == lab) z1 += m.y;
+            if (wide && diag && k + 64 == lab) z1 += m.y;
             if (lap) {
                 z0 *= m.w;
                 z1 *= m.w;
             }
             if (cor) {
-                const float ss = WIDE ? wave_sum(z0 * z0 + z1 * z1) : group_sum(z0 * z0, kp);
+                const float ss = wide ? wave_sum(z0 * z0 + z1 * z1) : group_sum(z0 * z0, kp);
                 const float sc = ss > 0.0f ? 1.0f / sqrtf(ss) : 1.0f;
                 z0 *= sc;
                 z1 *= sc;
@@ -440,9 +487,9 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
                 z1 = v1;
             }
             if (live) {
-                float *dst = r == head_row ? headp + (int64_t)w * K : Z + (int64_t)r * K;
+                float *dst = r == head_row ? headw : Z + (int64_t)(r - node_off) * K;
                 if (k < K) dst[k] = z0;
-                if (WIDE && k + 64 < K) dst[k + 64] = z1;
+                if (wide && k + 64 < K) dst[k + 64] = z1;
             }
         }
         npend = 0;
@@ -451,13 +498,18 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
 
     // Loads are unconditional (clamped address, value masked afterwards) and are only
     // consumed in a later batch.
-    const int nwin = (b - a + 63) >> 6;
-    auto ld_col = [&](int e) { const int v = col[min(e, last)]; return e < b ? v : -1; };
+    const int nwin = (b_ - a + 63) >> 6;
+    auto ld_col = [&](int e) { const int v = col[min(e, last)]; return e < b_ ? v : -1; };
     auto ld_val = [&](int e) { return WEIGHTED ? val[min(e, last)] : 1.0f; };
-    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b ? v : 0; };
+    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b_ ? v : 0; };
     auto gather_col = [&](int j) {
-        const float2 f = info[min(max(j, 0), N - 1)];
-        return (unsigned)j < (unsigned)N ? f : make_float2(0.0f, __int_as_float(-1));
+        const float2 f = info[min(max(j, node_off), node_off + N - 1)];
+        return (unsigned)(j - node_off) < (unsigned)N ? f : make_float2(0.0f, __int_as_float(-1));
+    };
+    auto gather_row = [&](int r, float2 &q, float &sv) {
+        const int rr = min(max(r, node_off), node_off + N - 1);
+        q = info[rr];
+        sv = lap ? srow[rr] : 1.0f;
     };
     int cn1[BW], cn2[BW], dc[BW], dn1[BW], dn2[BW], rc[BW], rn1[BW];
     float vc[BW], vn1[BW], vn2[BW], sc[BW], sn1[BW];
@@ -473,17 +525,15 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
         cn1[u] = ld_col(e1);
         vn1[u] = ld_val(e1);
         dn1[u] = ld_step(e1);
-        bad |= e0 < b && (unsigned)c0 >= (unsigned)N;
+        bad |= e0 < b_ && (unsigned)(c0 - node_off) >= (unsigned)N;
         fc[u] = gather_col(c0);
     }
     base = row_a;
 #pragma unroll
     for (int u = 0; u < BW; ++u) {
-        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rp, N);
+        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rpg, N, node_off);
         base = readlane(rc[u], 63);
-        const int rr = min(max(rc[u], 0), N - 1);
-        qc[u] = info[rr];
-        sc[u] = lap ? srow[rr] : 1.0f;
+        gather_row(rc[u], qc[u], sc[u]);
     }
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
 
@@ -492,13 +542,11 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
 #pragma unroll
         for (int u = 0; u < BW; ++u) {
             const int e1 = a + (i0 + BW + u) * 64 + lane, e2 = a + (i0 + 2 * BW + u) * 64 + lane;
-            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rp, N);
+            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rpg, N, node_off);
             base = readlane(rn1[u], 63);
-            const int rr = min(max(rn1[u], 0), N - 1);
-            bad |= e1 < b && (unsigned)cn1[u] >= (unsigned)N;
+            bad |= e1 < b_ && (unsigned)(cn1[u] - node_off) >= (unsigned)N;
             fn1[u] = gather_col(cn1[u]);
-            qn1[u] = info[rr];
-            sn1[u] = lap ? srow[rr] : 1.0f;
+            gather_row(rn1[u], qn1[u], sn1[u]);
             cn2[u] = ld_col(e2);
             vn2[u] = ld_val(e2);
             dn2[u] = ld_step(e2);
@@ -509,12 +557,12 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
             const int i = i0 + u;
             if (i >= nwin) break;
             const int p = a + (i << 6);
-            const int nvalid = min(64, b - p);
+            const int nvalid = min(64, b_ - p);
             const bool valid = lane < nvalid;
             const int y = __float_as_int(fc[u].y);
             const float x = vc[u] * fc[u].x;
             const int nxt = (u + 1 < BW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
-            cont = (p + nvalid < b) ? (nxt == 0) : cont_end;
+            cont = (p + nvalid < b_) ? (nxt == 0) : cont_end;
             const bool start = valid && dc[u] != 0;
             const uint64_t sm = ballot(start);
             const int nnew = __popcll(sm);
@@ -558,36 +606,41 @@ __global__ __launch_bounds__(256) void embed_rows(const int *__restrict__ rp, co
     if (npend > 0) drain();
     int my_split = -1;
     if (cont) {
-        float *dstp = (cur_row == head_row) ? headp : tailp;
+        float *dstp = (cur_row == head_row) ? headw : tailw;
         if (cur_row != head_row) my_split = cur_row;
-        for (int k = lane; k < K; k += 64) dstp[(int64_t)w * K + k] = acc[k * KS + cur_slot];
+        for (int k = lane; k < K; k += 64) dstp[k] = acc[k * KS + cur_slot];
     }
     if (lane == 0) split[w] = my_split;
 }
 
 // One wavefront per embed wavefront w: finish the row that starts in w and continues.
-__global__ __launch_bounds__(256) void embed_fixup(const int *__restrict__ rp,
+__global__ __launch_bounds__(256) void embed_fixup(Batch b, int NWtot, const int *__restrict__ rp,
                                                    const float2 *__restrict__ info,
                                                    const float *__restrict__ srow,
-                                                   const int *__restrict__ meta, int N, int K, int WE,
-                                                   unsigned flags, const float *__restrict__ headp,
+                                                   const float *__restrict__ headp,
                                                    const float *__restrict__ tailp,
-                                                   const int *__restrict__ split, float *__restrict__ Z) {
+                                                   const int *__restrict__ split) {
     const int lane = lane_id();
     const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int NW = meta[1];
-    if (w >= NW) return;
+    if (w >= NWtot) return;
+    GDesc gd;
+    GMeta gm;
+    int lw;
+    if (!wave_graph(b, w, gd, gm, lw)) return;
     const int r = split[w];
-    if (r < 0 || r >= N) return;
-    const bool diag = flags & kDiag, lap = flags & kLap, cor = flags & kCor;
+    if (r < gd.node_off || r >= gd.node_off + gd.N) return;
+    const bool diag = gd.flags & kDiag, lap = gd.flags & kLap, cor = gd.flags & kCor;
+    const int K = gd.K;
     const int end = rp[r + 1];
-    const int we = (int)min((int64_t)NW - 1, max((int64_t)w, ((int64_t)end - 1) / WE));
+    const int wl = (int)min((int64_t)gm.NW - 1, max((int64_t)lw, ((int64_t)(end - gm.ent_off) - 1) / gd.WE));
+    const float *part = tailp + gd.part_off;
+    const float *heads = headp + gd.part_off;
     float v0 = 0.0f, v1 = 0.0f;
-    if (lane < K) v0 = tailp[(int64_t)w * K + lane];
-    if (lane + 64 < K) v1 = tailp[(int64_t)w * K + lane + 64];
-    for (int w2 = w + 1; w2 <= we; ++w2) {
-        if (lane < K) v0 += headp[(int64_t)w2 * K + lane];
-        if (lane + 64 < K) v1 += headp[(int64_t)w2 * K + lane + 64];
+    if (lane < K) v0 = part[(int64_t)lw * K + lane];
+    if (lane + 64 < K) v1 = part[(int64_t)lw * K + lane + 64];
+    for (int w2 = lw + 1; w2 <= wl; ++w2) {
+        if (lane < K) v0 += heads[(int64_t)w2 * K + lane];
+        if (lane + 64 < K) v1 += heads[(int64_t)w2 * K + lane + 64];
     }
     const float2 inf = info[r];
     const int lab = __float_as_int(inf.y);
@@ -606,90 +659,76 @@ __global__ __launch_bounds__(256) void embed_fixup(const int *__restrict__ rp,
             v1 *= sc;
         }
     }
-    if (lane < K) Z[(int64_t)r * K + lane] = v0;
-    if (lane + 64 < K) Z[(int64_t)r * K + lane + 64] = v1;
+    float *z = gd.Z + (int64_t)(r - gd.node_off) * K;
+    if (lane < K) z[lane] = v0;
+    if (lane + 64 < K) z[lane + 64] = v1;
 }
 
 // ----------------------------------------------------------------------------- launch
 
 size_t embed_lds_per_wave(int K) { return (size_t)embed_lds_floats(K) * sizeof(float); }
 
-__global__ void set_meta(int *meta, int M, int NW) {
-    meta[0] = M;
-    meta[1] = NW;
-}
-
-hipError_t launch_set_meta(int *meta, int M, int NW, hipStream_t s) {
-    prof_begin(kKSetMeta, s);
-    hipLaunchKernelGGL(set_meta, dim3(1), dim3(1), 0, s, meta, M, NW);
-    prof_end(kKSetMeta, s);
+hipError_t launch_graph_meta(const Batch &b, const int *rp_of_union, int M, hipStream_t s) {
+    prof_begin(kKGraphMeta, s);
+    hipLaunchKernelGGL(graph_meta, dim3((unsigned)((b.G + 255) / 256)), dim3(256), 0, s, b, rp_of_union, M);
+    prof_end(kKGraphMeta, s);
     return hipGetLastError();
 }
 
 // Per-node data for the embedding of a CSR: first rows of the wavefronts, row steps,
-// degrees, s_i and c_i. meta[0..1] (M and the wavefront count) must be set beforehand.
-hipError_t launch_node_prep(const int *rp, const float *val, const int *labels, const Plan &p,
-                            const Work &wk, unsigned *status, hipStream_t s) {
-    const bool weighted_lap = val != nullptr && (p.flags & kLap);
-    const int64_t nz = (p.Mcap + 16 * 256 - 1) / (16 * 256);
+// degrees, s_i and c_i. The graph metadata must be set beforehand.
+hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, const Work &wk,
+                            unsigned *status, hipStream_t s) {
+    const int64_t nz = (p.Vtot + 16 * 256 - 1) / (16 * 256);
     prof_begin(kKZeroSteps, s);
-    hipLaunchKernelGGL(zero_bytes, dim3((unsigned)(nz > 0 ? nz : 1)), dim3(256), 0, s, wk.rstep, p.Mcap);
+    hipLaunchKernelGGL(zero_bytes, dim3((unsigned)(nz > 0 ? nz : 1)), dim3(256), 0, s, wk.rstep, p.Vtot);
     prof_end(kKZeroSteps, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const unsigned nblk = (unsigned)((p.Ntot + 255) / 256);
     prof_begin(kKNodeRows, s);
-    hipLaunchKernelGGL(node_rows, dim3((p.N + 255) / 256), dim3(256), 0, s, rp, p.N, wk.meta, p.WE, labels,
-                       p.K, wk.inv_n, p.flags, weighted_lap ? 1 : 0, wk.info, wk.srow, wk.wrow, wk.rstep,
-                       status);
+    hipLaunchKernelGGL(node_rows, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, s, b, (int)p.Ntot, rp, wk.inv_n,
+                       wk.info, wk.srow, wk.wrow, wk.rstep, status);
     prof_end(kKNodeRows, s);
-    if ((e = hipGetLastError()) != hipSuccess || !weighted_lap) return e;
+    if ((e = hipGetLastError()) != hipSuccess || !(val && p.any_lap_w)) return e;
     prof_begin(kKDegreeRows, s);
-    hipLaunchKernelGGL(degree_rows, dim3((unsigned)((p.NWcap + 3) / 4)), dim3(256), 0, s, rp, val, wk.rstep,
-                       wk.wrow, wk.meta, p.N, p.WE, labels, p.K, wk.inv_n, p.flags, wk.info, wk.srow, wk.headd,
-                       wk.taild, wk.dsplit);
+    hipLaunchKernelGGL(degree_rows, dim3((unsigned)((p.NWtot + 3) / 4)), dim3(256), 0, s, b, rp, val, wk.rstep,
+                       wk.wrow, wk.inv_n, wk.info, wk.srow, wk.headd, wk.taild, wk.dsplit);
     prof_end(kKDegreeRows, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKDegreeFixup, s);
-    hipLaunchKernelGGL(degree_fixup, dim3((unsigned)((p.NWcap + 255) / 256)), dim3(256), 0, s, rp, wk.meta,
-                       p.N, p.WE, labels, p.K, wk.inv_n, p.flags, wk.headd, wk.taild, wk.dsplit, wk.info,
-                       wk.srow);
+    hipLaunchKernelGGL(degree_fixup, dim3((unsigned)((p.NWtot + 255) / 256)), dim3(256), 0, s, b, (int)p.NWtot, rp,
+                       wk.inv_n, wk.headd, wk.taild, wk.dsplit, wk.info, wk.srow);
     prof_end(kKDegreeFixup, s);
     return hipGetLastError();
 }
 
-hipError_t launch_embed(const int *rp, const int *col, const float *val, const Plan &p,
-                        const Work &wk, float *Z, unsigned *status, hipStream_t s) {
-    const int K = p.K;
-    int kp = 1;
-    while (kp < K && kp < 64) kp <<= 1;
+hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
+                        const Work &wk, unsigned *status, hipStream_t s) {
     const int wpb = p.wpb;
-    const unsigned grid = (unsigned)((p.NWcap + wpb - 1) / wpb);
-    const size_t lds = embed_lds_per_wave(K) * wpb;
-    const bool wide = K > 64;
-    const bool weighted = val != nullptr;
+    const unsigned grid = (unsigned)((p.NWtot + wpb - 1) / wpb);
+    const int lds_floats = embed_lds_floats(p.Kmax);
+    const size_t lds = (size_t)lds_floats * sizeof(float) * wpb;
+    const unsigned nblk = (unsigned)((p.Ntot + 255) / 256);
     prof_begin(kKFillEmpty, s);
-    hipLaunchKernelGGL(fill_empty, dim3((p.N + 255) / 256), dim3(256), 0, s, rp, p.N, K, p.flags,
-                       wk.info, wk.srow, Z);
+    hipLaunchKernelGGL(fill_empty, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, s, b, (int)p.Ntot, rp, wk.info,
+                       wk.srow);
     prof_end(kKFillEmpty, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define GEE_EMBED_LAUNCH(WT, WD)                                                                   \
-    hipLaunchKernelGGL((embed_rows<WT, WD>), dim3(grid), dim3(64 * wpb), lds, s, rp, col, val,     \
-                       wk.rstep, wk.info, wk.srow, wk.wrow, wk.meta, p.N, K, kp, p.WE,       \
-                       p.flags, Z,                                                                 \
-                       wk.headp, wk.tailp, wk.split, status)
     prof_begin(kKEmbedRows, s);
-    if (weighted) {
-        if (wide) GEE_EMBED_LAUNCH(true, true); else GEE_EMBED_LAUNCH(true, false);
+    if (val) {
+        hipLaunchKernelGGL(embed_rows<true>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, wk.rstep, wk.info,
+                           wk.srow, wk.wrow, lds_floats, wk.headp, wk.tailp, wk.split, status);
     } else {
-        if (wide) GEE_EMBED_LAUNCH(false, true); else GEE_EMBED_LAUNCH(false, false);
+        hipLaunchKernelGGL(embed_rows<false>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, wk.rstep,
+                           wk.info, wk.srow, wk.wrow, lds_floats, wk.headp, wk.tailp, wk.split, status);
     }
     prof_end(kKEmbedRows, s);
-#undef GEE_EMBED_LAUNCH
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKEmbedFixup, s);
-    hipLaunchKernelGGL(embed_fixup, dim3((unsigned)((p.NWcap + 3) / 4)), dim3(256), 0, s, rp, wk.info,
-                       wk.srow, wk.meta, p.N, K, p.WE, p.flags, wk.headp, wk.tailp, wk.split, Z);
+    hipLaunchKernelGGL(embed_fixup, dim3((unsigned)((p.NWtot + 3) / 4)), dim3(256), 0, s, b, (int)p.NWtot, rp,
+                       wk.info, wk.srow, wk.headp, wk.tailp, wk.split);
     prof_end(kKEmbedFixup, s);
     return hipGetLastError();
 }

@@ -105,14 +105,73 @@ __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     atomicOr(status, bit);
 }
 
+// ----------------------------------------------------------------------------- graphs
+
+// One graph of a launch. A plain call is a batch of one graph; a batch is the disjoint
+// union of its graphs: graph g owns rows [node_off, node_off + N) of one CSR, the virtual
+// entries [voff, voff + Mcap) of its edge list (2E under symmetrization, else E), the
+// classes [class_off, class_off + K) of one count array and the embed wavefronts
+// [wave_off, wave_off + NWcap). Every kernel finds a work item's graph by binary search
+// over the offsets and reads the graph's own sizes, options and schedule from here.
+struct GDesc {
+    const int *src = nullptr, *dst = nullptr;  // edge list (device)
+    const float *w = nullptr;                  // weights or nullptr (every e = 1)
+    const int *labels = nullptr;               // [N]
+    float *Z = nullptr;                        // [N * K] row-major
+    int64_t voff = 0, E = 0, Mcap = 0;
+    int N = 0, node_off = 0;
+    int K = 1, kp = 1, class_off = 0;  // kp: lanes per row when finishing (pow2 >= K, <= 64)
+    unsigned flags = 0;                // option bits incl. symmetrize
+    int weighted = 0;
+    int WE = 1024, wave_off = 0, NWcap = 1;
+    int64_t part_off = 0;              // first float of the graph's head/tail partial rows
+    int cnt_off = 0, cnt_blocks = 1;   // class-count partial workgroups
+    int64_t cpart_off = 0;             // first int of the graph's class-count partials
+};
+
+// Set on the device once the CSR exists: first entry, entry count, embed wavefronts.
+struct GMeta {
+    int ent_off, M, NW, pad;
+};
+
+// Kernel-side view of a launch: the descriptor table and the offset arrays (device), or,
+// for a single graph, the descriptor itself (tab == nullptr, offset arrays unused).
+struct Batch {
+    int G = 1;
+    const GDesc *tab = nullptr;
+    GDesc one;
+    const int *node_offs = nullptr;     // [G + 1]
+    const int64_t *voffs = nullptr;     // [G + 1]
+    const int *wave_offs = nullptr;     // [G + 1]
+    const int *cnt_offs = nullptr;      // [G + 1]
+    const int *class_offs = nullptr;    // [G + 1]
+    GMeta *gm = nullptr;                // [G]
+};
+
+// Last g with offs[g] <= x (offs non-decreasing, offs[0] <= x).
+template <typename T>
+__device__ __forceinline__ int find_graph(const T *__restrict__ offs, int G, T x) {
+    if (G <= 1) return 0;
+    int lo = 0, hi = G;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ GDesc load_desc(const Batch &b, int g) { return b.tab ? b.tab[g] : b.one; }
+
 // ----------------------------------------------------------------------------- plan
 
+// Host-side plan of a launch over the union of its graphs.
 struct Plan {
-    int64_t E = 0;       // input rows
-    int32_t N = 0, K = 0;
-    unsigned flags = 0;
-    bool weighted = false;
-    int64_t Mcap = 0;    // upper bound of CSR entries (2E under symmetrization, else E)
+    int G = 1;
+    int64_t Vtot = 0;    // virtual entries (CSR capacity) over all graphs
+    int64_t Ntot = 0;    // rows over all graphs
+    int Kmax = 1, Ktot = 0;
+    bool weighted = false;  // some graph has weights (the CSR then carries val)
+    bool any_lap_w = false; // some weighted graph uses the Laplacian
     // partition (CSR build)
     int sb = 0;          // rows per bucket = 1 << sb
     int32_t B = 1;       // buckets
@@ -122,41 +181,47 @@ struct Plan {
     int64_t TA = 1;      // pass A tiles
     int64_t TBcap = 1;   // pass B tiles (upper bound)
     // embed
-    int WE = 2048;       // CSR entries per embed wavefront
-    int wpb = 4;         // wavefronts per embed workgroup
-    int64_t NWcap = 1;   // embed wavefronts launched (upper bound)
-    int cnt_blocks = 1;  // class-count partial blocks
+    int wpb = 1;         // wavefronts per embed workgroup
+    int64_t NWtot = 1;   // embed wavefronts launched (upper bound, all graphs)
+    int64_t parts = 0;   // floats of head/tail partial rows (all graphs)
+    int cnt_blocks = 1;  // class-count partial workgroups (all graphs)
+    int64_t cparts = 0;  // ints of class-count partials (all graphs)
 };
 
 // Workspace carve-up; every member is a device pointer into one caller buffer.
 struct Work {
-    int *counts = nullptr;     // [K]
-    float *inv_n = nullptr;    // [K]
-    int *cpart = nullptr;      // [cnt_blocks * K]
-    int *meta = nullptr;       // [4]: M, NW, ...
+    // batch tables (G > 1)
+    GDesc *tab = nullptr;
+    int *node_offs = nullptr, *wave_offs = nullptr, *cnt_offs = nullptr, *class_offs = nullptr;
+    int64_t *voffs = nullptr;
+    GMeta *gm = nullptr;       // [G]
+    int *counts = nullptr;     // [Ktot]
+    float *inv_n = nullptr;    // [Ktot]
+    int *cpart = nullptr;      // [cparts]
+    int *meta = nullptr;       // [4]: M (all graphs)
     int *ghA = nullptr;        // [DA * TA] pass A tile histograms (scanned in place)
     int *totA = nullptr;       // [DA]
     int *segA = nullptr;       // [DA + 1] pass A segment starts
     int *tileB = nullptr;      // [DA + 1] first pass-B tile of each segment
     int *ghB = nullptr;        // [(1 << s2) * TBcap] pass B tile histograms
     int *bstart = nullptr;     // [B + 1]
-    int *akey = nullptr;       // [Mcap] pass A output: row
-    uint16_t *tkey = nullptr;  // [Mcap] pass B output: row within bucket
-    int *tcol = nullptr;       // [Mcap]
-    float *tval = nullptr;     // [Mcap] (weighted only)
-    int *rp = nullptr;         // [N + 1]
-    int *col = nullptr;        // [Mcap]
-    float *val = nullptr;      // [Mcap] (weighted only)
-    float2 *info = nullptr;    // [N] {coefficient, label bits}
-    float *srow = nullptr;     // [N] D^-1/2 (Laplacian)
-    int *wrow = nullptr;       // [NWcap] row holding each embed wavefront's first entry
-    uint8_t *rstep = nullptr;  // [Mcap] row step from the previous CSR entry (see gee_embed.hip)
-    int *split = nullptr;      // [NWcap]
-    float *headp = nullptr;    // [NWcap * K]
-    float *tailp = nullptr;    // [NWcap * K]
-    float *headd = nullptr;    // [NWcap] degree partials (weighted Laplacian)
-    float *taild = nullptr;    // [NWcap]
-    int *dsplit = nullptr;     // [NWcap]
+    int *akey = nullptr;       // [Vtot] pass A output: row
+    uint16_t *tkey = nullptr;  // [Vtot] pass B output: row within bucket
+    int *tcol = nullptr;       // [Vtot]
+    float *tval = nullptr;     // [Vtot] (weighted only)
+    int *rp = nullptr;         // [Ntot + 1]
+    int *col = nullptr;        // [Vtot]
+    float *val = nullptr;      // [Vtot] (weighted only)
+    float2 *info = nullptr;    // [Ntot] {coefficient, label bits}
+    float *srow = nullptr;     // [Ntot] D^-1/2 (Laplacian)
+    int *wrow = nullptr;       // [NWtot] row holding each embed wavefront's first entry
+    uint8_t *rstep = nullptr;  // [Vtot] row step from the previous CSR entry (see gee_embed.hip)
+    int *split = nullptr;      // [NWtot]
+    float *headp = nullptr;    // [parts]
+    float *tailp = nullptr;    // [parts]
+    float *headd = nullptr;    // [NWtot] degree partials (weighted Laplacian)
+    float *taild = nullptr;    // [NWtot]
+    int *dsplit = nullptr;     // [NWtot]
 };
 
 // ----------------------------------------------------------------------------- profiling
@@ -164,30 +229,33 @@ struct Work {
 // caller's hipEvents on the launch stream right before / after a kernel launch.
 enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
-    kKBScatter, kKBucketSort,
-    kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup, kKFillEmpty, kKEmbedRows, kKEmbedFixup,
-    kKSetMeta, kKNumKernels
+    kKBScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
+    kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
 
 // ----------------------------------------------------------------------------- launchers
-// gee_count.hip
-hipError_t launch_class_counts(const int *labels, int N, int K, int nblocks, int *part, int *counts,
-                               float *inv_n, unsigned *status, hipStream_t s);
-// gee_csr.hip
-hipError_t launch_csr_build(const int *src, const int *dst, const float *w, const Plan &p,
-                            const Work &wk, unsigned *status, hipStream_t s);
+// gee_count.hip: host bytes -> device memory, stream-ordered, in kernel-argument chunks.
+constexpr int kUploadChunk = 2048;
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+// gee_count.hip: counts[class_off + k] and inv_n (inv_n may be nullptr).
+hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
+                               unsigned *status, hipStream_t s);
+// gee_csr.hip: edge lists -> CSR of the union (rows and columns offset by node_off).
+hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 size_t bucket_sort_lds(int sb);
 // gee_embed.hip
-// Per-node data (ownership, degrees, s_i, c_i); meta[0..1] = {M, wavefronts} must be set.
-hipError_t launch_node_prep(const int *rp, const float *val, const int *labels, const Plan &p,
-                            const Work &wk, unsigned *status, hipStream_t s);
-hipError_t launch_set_meta(int *meta, int M, int NW, hipStream_t s);
+// Per-graph entry ranges and wavefront counts from row_ptr (after a CSR build), or
+// from the given entry count M (a single resident CSR, rp_of_union == nullptr).
+hipError_t launch_graph_meta(const Batch &b, const int *rp_of_union, int M, hipStream_t s);
+// Per-node data (ownership, degrees, s_i, c_i).
+hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, const Work &wk,
+                            unsigned *status, hipStream_t s);
 size_t embed_lds_per_wave(int K);
-hipError_t launch_embed(const int *rp, const int *col, const float *val, const Plan &p,
-                        const Work &wk, float *Z, unsigned *status, hipStream_t s);
+hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
+                        const Work &wk, unsigned *status, hipStream_t s);
 
 }  // namespace gee

@@ -212,3 +212,89 @@ def gee_embed_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: Optional[torch.
 
 def gee_embed_csr_workspace_bytes(M: int, N: int, K: int, flags: int, sched=None) -> int:
     return int(_lib.load().gee_embed_csr_workspace_bytes(M, N, K, flags, _sched_ptr(sched)))
+
+
+# ----------------------------------------------------------------------------- batches
+
+def _graph_struct(g: dict, dev) -> _lib.GeeGraph:
+    """One gee_graph from a dict with src, dst, w (or None), labels, K, flags, Z and an
+    optional sched; N is labels.numel()."""
+    labels = _dev(g["labels"], torch.int32, "labels", dev)
+    src = _dev(g["src"], torch.int32, "src", dev)
+    dst = _dev(g["dst"], torch.int32, "dst", dev)
+    w = _dev(g.get("w"), torch.float32, "w", dev)
+    Z = _dev(g["Z"], torch.float32, "Z", dev)
+    E, N, K = src.numel(), labels.numel(), int(g["K"])
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    if Z.numel() != N * K:
+        raise ValueError("Z must hold N * K floats")
+    sc = g.get("sched")
+    if sc is None:
+        sc = schedule()
+    elif isinstance(sc, dict):
+        sc = schedule(**sc)
+    return _lib.GeeGraph(src.data_ptr(), dst.data_ptr(), None if w is None else w.data_ptr(), E, N,
+                         labels.data_ptr(), K, int(g["flags"]), Z.data_ptr(), sc)
+
+
+def _graph_array(graphs, dev):
+    arr = (_lib.GeeGraph * len(graphs))()
+    for i, g in enumerate(graphs):
+        arr[i] = _graph_struct(g, dev)
+    return arr
+
+
+def gee_embed_batch_workspace_bytes(graphs) -> int:
+    dev = graphs[0]["labels"].device
+    arr = _graph_array(graphs, dev)
+    return int(_lib.load().gee_embed_batch_workspace_bytes(arr, len(graphs)))
+
+
+def gee_embed_batch(graphs, workspace: Optional[torch.Tensor] = None, stream=None):
+    """gee_embed of every graph (dicts: src, dst, w, labels, K, flags, Z[, sched]) in one
+    launch sequence; each Z is written in place."""
+    if not graphs:
+        return
+    dev = graphs[0]["labels"].device
+    arr = _graph_array(graphs, dev)
+    lib = _lib.load()
+    nbytes = lib.gee_embed_batch_workspace_bytes(arr, len(graphs))
+    if nbytes == 0:
+        raise GeeError(GEE_ERR_ARG, "gee_embed_batch_workspace_bytes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _check(lib.gee_embed_batch_ws(arr, len(graphs), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "gee_embed_batch_ws")
+
+
+class BatchPlan:
+    """gee_batch_plan: the graphs' launch sequence captured once in a hipGraph; launch()
+    replays it. The graphs' tensors are kept referenced for the plan's lifetime."""
+
+    def __init__(self, graphs):
+        if not graphs:
+            raise ValueError("a batch plan needs at least one graph")
+        self._graphs = list(graphs)
+        dev = self._graphs[0]["labels"].device
+        arr = _graph_array(self._graphs, dev)
+        h = ctypes.c_void_p()
+        _check(_lib.load().gee_batch_plan_create(arr, len(self._graphs), ctypes.byref(h)),
+               "gee_batch_plan_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        if not self._h:
+            raise RuntimeError("batch plan destroyed")
+        _check(_lib.load().gee_batch_plan_launch(self._h, _stream(stream)), "gee_batch_plan_launch")
+
+    def destroy(self):
+        if self._h:
+            _check(_lib.load().gee_batch_plan_destroy(self._h), "gee_batch_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
