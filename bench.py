@@ -8,6 +8,9 @@ N=600,000, E=10,000,000 undirected weighted edges, K=50 (10% unknown labels), al
 options on.
 
 Prints one JSON line. `value` is edges embedded per second over the timed steps.
+`batched` adds the 512-graph batched form (one captured batch plan against 512 plain
+calls) and `serving` the served form (Poisson requests, budget admission and continuous
+batching against the plain per-request loop, p50/p99 latency).
 `roofline` is for the kernel with the largest share of the step, timed live with HIP
 events recorded around each of its launches on the launch stream (library hook), and
 priced with its algorithmic bytes against the 8 TB/s HBM peak. `cpu_baseline` is the
@@ -135,6 +138,150 @@ def _cpu_model():
     return "unknown"
 
 
+# ----------------------------------------------------------------------------- systems legs
+
+def _gen_batched(g):
+    from gee_workloads.configs import batched_one
+
+    x = batched_one(g)
+    return x.src, x.dst, x.w, x.labels, x.K, (x.diag, x.lap, x.cor, x.sym)
+
+
+def _gen_serving(g, e_max):
+    from gee_workloads.configs import serving_one
+
+    x = serving_one(g, e_max=e_max)
+    return x.src, x.dst, x.w, x.labels, x.K, (x.diag, x.lap, x.cor, x.sym)
+
+
+def gen_parallel(fn, args_list, procs):
+    """Seeded graphs drawn in worker processes (CPU only; they never touch the GPU)."""
+    import multiprocessing as mp
+
+    with mp.get_context("spawn").Pool(procs) as pool:
+        return pool.starmap(fn, args_list, chunksize=1)
+
+
+def _to_items(raw, torch, np, gee, dev, table):
+    items = []
+    for src, dst, w, lab, K, opts in raw:
+        t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
+        it = dict(src=t(src, torch.int32), dst=t(dst, torch.int32), w=t(w, torch.float32),
+                  labels=t(lab, torch.int32), K=int(K), flags=gee.flags_of(*opts))
+        sc = table.lookup(it["src"].numel(), it["labels"].numel(), it["K"], it["flags"]) if table else {}
+        it["sched"] = sc or None
+        items.append(it)
+    return items
+
+
+def batched_leg(torch, np, gee, dev, table, procs, reps=5, G=512):
+    """512 graphs of the batched recipe: one captured batch plan (hipGraph replay) against
+    512 back-to-back plain gee_embed_ws calls on one stream, same per-graph schedules."""
+    t0 = time.perf_counter()
+    raw = gen_parallel(_gen_batched, [(i,) for i in range(G)], procs)
+    gen_s = time.perf_counter() - t0
+    items = _to_items(raw, torch, np, gee, dev, table)
+    del raw
+    for it in items:
+        it["Z"] = torch.empty((it["labels"].numel(), it["K"]), dtype=torch.float32, device=dev)
+    E_tot = sum(it["src"].numel() for it in items)
+    ws_max = max(gee.gee_embed_workspace_bytes(it["src"].numel(), it["labels"].numel(), it["K"], it["flags"],
+                                               it["w"] is not None, it["sched"]) for it in items)
+    ws = torch.empty(ws_max, dtype=torch.uint8, device=dev)
+    Zp = [torch.empty_like(it["Z"]) for it in items]
+
+    def plain_loop():
+        for it, z in zip(items, Zp):
+            gee.gee_embed(it["src"], it["dst"], it["w"], it["labels"], it["K"], it["flags"], Z=z,
+                          sched=it["sched"], workspace=ws)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    plain_ms = timed(plain_loop)
+    plan = gee.BatchPlan(items)
+    batch_ms = timed(lambda: plan.launch())
+    torch.cuda.synchronize()
+    same = all(torch.equal(it["Z"], z) for it, z in zip(items, Zp))
+    plan.destroy()
+    return {"graphs": G, "edges": int(E_tot), "generation_s": round(gen_s, 1),
+            "plain_loop_ms": round(plain_ms, 3), "batch_plan_ms": round(batch_ms, 3),
+            "plain_edges_per_s": round(E_tot / (plain_ms * 1e-3), 1),
+            "batch_edges_per_s": round(E_tot / (batch_ms * 1e-3), 1),
+            "speedup": round(plain_ms / batch_ms, 3), "bitwise_equal_to_plain": same,
+            "schedules": "autotuned table" if table and table.entries else "library defaults"}
+
+
+def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, n_req=400,
+                loads=(0.5, 0.9, 1.5), slots=4, budget_gb=32.0, max_batch=16):
+    """Poisson requests from a pool of serving-recipe graphs: the server (budget admission,
+    continuous batching over `slots` streams) against the plain per-request loop."""
+    from paper_2406_03726_amd.serve import GeeServer, GpuBackend, Request, run_plain, summarize
+
+    t0 = time.perf_counter()
+    raw = gen_parallel(_gen_serving, [(i, e_max) for i in range(pool_n)], procs)
+    gen_s = time.perf_counter() - t0
+    pool = _to_items(raw, torch, np, gee, dev, table)
+    del raw
+    ws_max = max(gee.gee_embed_workspace_bytes(it["src"].numel(), it["labels"].numel(), it["K"], it["flags"],
+                                               it["w"] is not None, it["sched"]) for it in pool)
+    ws = torch.empty(ws_max, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def embed_one(r):
+        g = r.graph
+        r.result = gee.gee_embed(g["src"], g["dst"], g["w"], g["labels"], g["K"], g["flags"],
+                                 sched=g["sched"], workspace=ws, stream=stream)
+        stream.synchronize()
+
+    # plain service time per pool graph -> saturation rate of the plain loop
+    svc = []
+    for it in pool:
+        r = Request(0, it, 0.0)
+        embed_one(r)
+        t1 = time.perf_counter()
+        embed_one(r)
+        svc.append(time.perf_counter() - t1)
+    mu = 1.0 / float(np.mean(svc))
+    rng = np.random.default_rng(20240603)
+    picks = rng.integers(0, pool_n, size=n_req)
+    out = {"pool_graphs": pool_n, "pool_edges_mean": int(np.mean([it["src"].numel() for it in pool])),
+           "generation_s": round(gen_s, 1), "requests_per_load": n_req, "slots": slots,
+           "budget_bytes": int(budget_gb * 2 ** 30), "max_batch": max_batch,
+           "plain_saturation_req_per_s": round(mu, 1), "loads": []}
+    for frac in loads:
+        lam = frac * mu
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+
+        def mk():
+            return [Request(i, pool[int(p)], float(a), E=int(pool[int(p)]["src"].numel()))
+                    for i, (p, a) in enumerate(zip(picks, arr))]
+
+        plain = run_plain(mk(), embed_one)
+        srv = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch)
+        served = srv.run_trace(mk())
+        torch.cuda.synchronize()
+        sp, ss = summarize(plain), summarize(served)
+        same = all(torch.equal(a.result, b.result) for a, b in zip(plain[:16], served[:16]))
+        out["loads"].append({"load_vs_plain_saturation": frac, "rate_req_per_s": round(lam, 1),
+                             "plain": {k: round(v, 3) for k, v in sp.items()},
+                             "served": {k: round(v, 3) for k, v in ss.items()},
+                             "served_peak_bytes": srv.peak_in_use, "served_peak_batches": srv.peak_flights,
+                             "results_equal_alone_sample": same})
+        del plain, served
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +291,10 @@ def main():
                     choices=["powerlaw_10m", "sbm_dense", "sbm_small_all", "sbm_small_off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", default=None, help="also write a detailed JSON report here")
+    ap.add_argument("--legs", default="batched,serving",
+                    help="systems legs to add to the line: batched, serving (comma list, or none)")
+    ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="worker processes that draw the systems legs' graphs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -280,6 +431,18 @@ def main():
                                "edges_per_s": round(E / (resident_ms * 1e-3), 1),
                                "bitwise_equal_to_edge_list_path": same},
     }
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if legs:
+        from paper_2406_03726_amd.autotune import ScheduleTable
+
+        table = ScheduleTable.load()
+        del Zr, ws2
+        if "batched" in legs:
+            out["batched"] = batched_leg(torch, np, gee, dev, table, args.procs)
+            torch.cuda.empty_cache()
+        if "serving" in legs:
+            out["serving"] = serving_leg(torch, np, gee, dev, table, args.procs)
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)
     else:

@@ -209,7 +209,8 @@ typedef struct {
 } gee_graph;
 
 /* Caller-workspace form: the graph table is copied to the device (stream-ordered) and the
- * kernels are enqueued on `stream`; returns 0 bytes for invalid arguments. */
+ * kernels are enqueued on `stream`. The size query reads only sizes, flags, weights-or-not
+ * and schedules (pointers may be NULL there); it returns 0 bytes for invalid arguments. */
 size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G);
 int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
                        void *stream);

@@ -158,6 +158,7 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
             ktot > INT32_MAX / 2)
             return GEE_ERR_TOO_LARGE;
         p.Kmax = x.K > p.Kmax ? x.K : p.Kmax;
+        p.Kmin = x.K < p.Kmin ? x.K : p.Kmin;
         p.weighted = p.weighted || o.weighted;
         p.any_lap_w = p.any_lap_w || (o.weighted && (x.flags & GEE_LAPLACIAN));
         if (g == 0) {
@@ -343,7 +344,8 @@ hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned
     return e;
 }
 
-int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &out) {
+// `sizing`: only sizes are read (workspace queries), device pointers are not checked.
+int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &out, bool sizing = false) {
     if (!graphs || G < 1 || G > kMaxBatchGraphs) return GEE_ERR_ARG;
     out.resize(G);
     for (int g = 0; g < G; ++g) {
@@ -360,7 +362,7 @@ int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &ou
         o.Z = x.Z;
         o.sc = x.sched;
         if (x.E < 0 || x.N < 0) return GEE_ERR_ARG;
-        if ((x.E > 0 && (!x.src || !x.dst)) || (x.N > 0 && (!x.labels || !x.Z))) return GEE_ERR_ARG;
+        if (!sizing && ((x.E > 0 && (!x.src || !x.dst)) || (x.N > 0 && (!x.labels || !x.Z)))) return GEE_ERR_ARG;
         if (x.N == 0 && x.E > 0) return GEE_ERR_ARG;
     }
     return GEE_OK;
@@ -635,7 +637,7 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
 
 size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G) {
     std::vector<GraphIn> gs;
-    if (graphs_from_api(graphs, G, gs)) return 0;
+    if (graphs_from_api(graphs, G, gs, true)) return 0;
     Plan p;
     std::vector<GDesc> d;
     if (make_plan(gs.data(), G, false, p, d)) return 0;

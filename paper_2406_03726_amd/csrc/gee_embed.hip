@@ -26,17 +26,17 @@
 //                  row_ptr lookups: a byte per entry holds the row step from the previous
 //                  entry (0 inside a row; an escape value for steps >= 255), and a wave
 //                  prefix sum turns the steps into row ids. The wavefront works in
-//                  batches of 4 windows; the col/val/step loads of batch k+2 and the
+//                  batches of 2 windows; the col/val/step loads of batch k+2 and the
 //                  gathers of batch k+1 ({c_j, y_j} by column, {c_i, y_i, s_i} by row)
 //                  are in flight while batch k is processed, and nothing loaded is
 //                  consumed in the batch that loads it, so the memory pipeline never
-//                  drains inside a batch. Rows get slots of an LDS ring acc[class][slot];
-//                  every lane adds its entry into acc[y_j][slot(row)] with an LDS float
-//                  atomic, and the LDS applies lanes that hit the same word one after
-//                  another in a fixed order, so results are bitwise reproducible. Rows
-//                  ending in the wavefront are finished there (diagonal term, s_i,
-//                  correlation) and stored with coalesced writes; rows cut by wavefront
-//                  boundaries leave raw partials.
+//                  drains inside a batch. Rows get slots of an LDS ring acc[slot][class];
+//                  a starting row first receives its diagonal term, then every lane adds
+//                  its entry into acc[slot(row)][y_j] with an LDS float atomic, and the
+//                  LDS applies lanes that hit the same word one after another in a fixed
+//                  order, so results are bitwise reproducible. Rows ending in the
+//                  wavefront are finished there (s_i, correlation) and stored with
+//                  coalesced writes; rows cut by wavefront boundaries leave raw partials.
 //   * embed_fixup  adds the partials of each cut row in wavefront order and finishes it.
 #include "gee_internal.h"
 
@@ -44,13 +44,15 @@
 
 namespace gee {
 
-constexpr int KS = 65;        // padded LDS stride of one class row of the slot ring
 constexpr int kStepEsc = 255;  // row-step byte meaning "look the row up in row_ptr"
-constexpr int BW = 4;          // windows per pipeline batch
+constexpr int BW = 4;          // windows per pipeline batch (degree_rows)
+constexpr int EBW = 2;         // windows per pipeline batch (embed_rows)
 
-// LDS floats of one embed wavefront: a 64-entry slot table of float4 and the slot ring
-// [K][65], rounded to 16 bytes.
-__host__ __device__ constexpr int embed_lds_floats(int K) { return 4 * 64 + ((K * KS + 3) & ~3); }
+// Floats per slot of the embed ring: K rounded up to a multiple of 4 (16-byte rows).
+__host__ __device__ constexpr int ring_stride(int K) { return (K + 3) & ~3; }
+// LDS floats of one embed wavefront: the ring [64][ring_stride(K)] and three 64-entry
+// slot tables.
+__host__ __device__ constexpr int embed_lds_floats(int K) { return 64 * ring_stride(K) + 3 * 64; }
 
 // Graph and local index of embed wavefront w; false if w has no work.
 __device__ __forceinline__ bool wave_graph(const Batch &b, int w, GDesc &d, GMeta &m, int &lw) {
@@ -370,26 +372,12 @@ __global__ __launch_bounds__(256) void fill_empty(Batch b, int Ntot, const int *
 
 // ----------------------------------------------------------------------------- finish a row
 
-// Sum of v over aligned groups of kp lanes (kp a power of two <= 64), returned on every
-// lane of the group. DPP lane moves only; every lane of the wavefront must take part.
-__device__ __forceinline__ float group_sum(float v, int kp) {
-    if (kp == 64) return wave_sum(v);
-    if (kp == 32) {
-        // prefix sums inside each half (no carry from lane 31 into the upper half, so
-        // neither half's sum is formed as a difference)
-        v += dpp_f<0x111>(v, 0.0f);
-        v += dpp_f<0x112>(v, 0.0f);
-        v += dpp_f<0x114>(v, 0.0f);
-        v += dpp_f<0x118>(v, 0.0f);
-        v += dpp_f<0x142, 0xA>(v, 0.0f);
-        const float s31 = readlane_f(v, 31), s63 = readlane_f(v, 63);
-        return lane_id() < 32 ? s31 : s63;
-    }
-    if (kp >= 2) v += dpp_f<0xB1>(v, 0.0f);   // quad_perm [1,0,3,2]
-    if (kp >= 4) v += dpp_f<0x4E>(v, 0.0f);   // quad_perm [2,3,0,1]
-    if (kp >= 8) v += dpp_f<0x141>(v, 0.0f);  // row_half_mirror: the other quad of 8
-    if (kp >= 16) v += dpp_f<0x140>(v, 0.0f); // row_mirror: the other half of 16
-    return v;
+// Factor that turns a row's sums u (diagonal term included) into its Z row: s_i without
+// correlation; with it u/|u|, since D^-1/2 scales the whole row by s_i > 0 and the 2-norm
+// removes it (a row with s_i = 0 or u = 0 stays zero).
+__device__ __forceinline__ float row_factor(float s, float ss, bool cor) {
+    if (!cor) return s;
+    return (s > 0.0f && ss > 0.0f) ? 1.0f / sqrtf(ss) : 0.0f;
 }
 
 // ----------------------------------------------------------------------------- main kernel
@@ -414,17 +402,19 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     if (!wave_graph(b, w, gd, gm, lw)) return;  // whole wavefront leaves; no workgroup barrier below
     const unsigned flags = gd.flags;
     const bool diag = flags & kDiag, lap = flags & kLap, cor = flags & kCor;
-    const int N = gd.N, K = gd.K, kp = gd.kp, node_off = gd.node_off;
-    const bool wide = K > 64;
+    const int N = gd.N, K = gd.K, node_off = gd.node_off;
+    const int KP = ring_stride(K);
     const int *rpg = rp + node_off;
     float *Z = gd.Z;
     float *headw = headp + gd.part_off + (int64_t)lw * K;
     float *tailw = tailp + gd.part_off + (int64_t)lw * K;
 
-    // per wavefront: slot table [64] {row, c_i, y_i, s_i}, then the ring acc[K][KS]
-    float4 *slot_meta = reinterpret_cast<float4 *>(smem_f + (size_t)wib * lds_floats);
-    float *acc = reinterpret_cast<float *>(slot_meta + 64);
-    for (int k = 0; k < K; ++k) acc[k * KS + lane] = 0.0f;
+    // per wavefront: the ring acc[64 slots][KP] and per-slot row, s_i and finishing factor
+    float *acc = smem_f + (size_t)wib * lds_floats;
+    int *slot_row = reinterpret_cast<int *>(acc + 64 * KP);
+    float *slot_s = reinterpret_cast<float *>(slot_row + 64);
+    float *slot_f = slot_s + 64;
+    for (int k = 0; k < KP; ++k) acc[lane * KP + k] = 0.0f;
     // Finished rows stay in their ring slots ("pending") until drain() stores them:
     // slots [pend_first, pend_first + npend) in ring order, just behind the open row.
     int npend = 0, pend_first = 0;
@@ -440,56 +430,54 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     const bool cont_end = b_ < E_end && __builtin_amdgcn_readfirstlane(rstep[min(b_, E_end - 1)]) == 0;
     int cur_row = head ? row_a : -1;
     int cur_slot = 63;
-    if (lane == 0) slot_meta[63] = make_float4(__int_as_float(cur_row), 0.0f, __int_as_float(-1), 0.0f);
+    if (lane == 0) slot_row[63] = cur_row;
     bool cont = false;
+    // this lane's (row, class) offset in the flat finishing pass, and its step per pass
+    const int j0 = lane / K, k0 = lane - j0 * K;
+    const int q64 = 64 / K, r64 = 64 - q64 * K;
 
-    // Finish the pending rows (diagonal term, s_i, correlation; the head row goes out
-    // raw) and store them: kp lanes per row, or (K > 64) one row per pass with two
-    // classes per lane. This loop holds the only global stores and reads nothing loaded
-    // from global memory, so it never waits for the loads in flight.
+    // Finish the pending rows and store them. First the factor of every pending row (one
+    // lane per row: its sums read back with 16-byte LDS loads for the 2-norm), then a flat
+    // pass over (row, class) in which consecutive lanes write consecutive words of Z. The
+    // head row goes out raw. This code holds the only global stores and reads nothing
+    // loaded from global memory, so it never waits for the loads in flight.
     auto drain = [&]() {
         wave_lds_fence();
-        const int grp = wide ? 1 : 64 / kp;  // rows per pass
-        const int g = wide ? 0 : lane / kp;
-        const int k = wide ? lane : lane & (kp - 1);
-        const int kk = min(k, K - 1);
-        const int k2 = min(k + 64, K - 1);
-        for (int j = 0; j < npend; j += grp) {
-            const bool has = j + g < npend;
-            const int sl = (pend_first + j + g) & 63;
-            const float4 m = slot_meta[sl];
-            const int r = __float_as_int(m.x);
-            const int lab = __float_as_int(m.z);
-            const bool live = has && r >= node_off && r < node_off + N;
-            float v0 = acc[kk * KS + sl];
-            float v1 = wide ? acc[k2 * KS + sl] : 0.0f;
-            if (has) {
-                acc[kk * KS + sl] = 0.0f;
-                if (wide && k + 64 < K) acc[(k + 64) * KS + sl] = 0.0f;
-            }
-            v0 = k < K ? v0 : 0.0f;
-            v1 = (wide && k + 64 < K) ? v1 : 0.0f;
-            float z0 = v0, z1 = v1;
-            if (diag && k == lab) z0 += m.y;
-            if (wide && diag && k + 64 == lab) z1 += m.y;
-            if (lap) {
-                z0 *= m.w;
-                z1 *= m.w;
-            }
+        if (lane < npend) {
+            const int sl = (pend_first + lane) & 63;
+            float ss = 0.0f;
             if (cor) {
-                const float ss = wide ? wave_sum(z0 * z0 + z1 * z1) : group_sum(z0 * z0, kp);
-                const float sc = ss > 0.0f ? 1.0f / sqrtf(ss) : 1.0f;
-                z0 *= sc;
-                z1 *= sc;
+                const float4 *a4 = reinterpret_cast<const float4 *>(acc + sl * KP);
+                for (int q = 0; q < (KP >> 2); ++q) {
+                    const float4 t = a4[q];
+                    ss += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
+                }
             }
-            if (r == head_row) {
-                z0 = v0;
-                z1 = v1;
+            const float f = row_factor(lap ? slot_s[sl] : 1.0f, ss, cor);
+            slot_f[sl] = slot_row[sl] == head_row ? 1.0f : f;
+        }
+        wave_lds_fence();
+        const int F = npend * K;
+        int jj = j0, kk = k0;
+        for (int f0 = 0; f0 < F; f0 += 64) {
+            const bool has = f0 + lane < F;
+            const int sl = (pend_first + jj) & 63;
+            const int ai = sl * KP + kk;
+            const float v = acc[ai];
+            const int r = slot_row[sl];
+            const float fac = slot_f[sl];
+            if (has) {
+                acc[ai] = 0.0f;
+                if (r >= node_off && r < node_off + N) {
+                    float *dst = r == head_row ? headw + kk : Z + (int64_t)(r - node_off) * K + kk;
+                    *dst = v * fac;
+                }
             }
-            if (live) {
-                float *dst = r == head_row ? headw : Z + (int64_t)(r - node_off) * K;
-                if (k < K) dst[k] = z0;
-                if (wide && k + 64 < K) dst[k + 64] = z1;
+            kk += r64;
+            jj += q64;
+            if (kk >= K) {
+                kk -= K;
+                ++jj;
             }
         }
         npend = 0;
@@ -511,49 +499,64 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         q = info[rr];
         sv = lap ? srow[rr] : 1.0f;
     };
-    int cn1[BW], cn2[BW], dc[BW], dn1[BW], dn2[BW], rc[BW], rn1[BW];
-    float vc[BW], vn1[BW], vn2[BW], sc[BW], sn1[BW];
-    float2 fc[BW], fn1[BW], qc[BW], qn1[BW];  // f: {c_j, y_j} by column; q: {c_i, y_i} by row
+    int cn1[EBW], cn2[EBW], dc[EBW], dn1[EBW], dn2[EBW], rc[EBW], rn1[EBW];
+    float vc[EBW], vn1[EBW], vn2[EBW], sc[EBW], sn1[EBW];
+    float2 fc[EBW], fn1[EBW], qc[EBW], qn1[EBW];  // f: {c_j, y_j} by column; q: {c_i, y_i} by row
     bool bad = false;
     int base;
+    int c0[EBW];
 #pragma unroll
-    for (int u = 0; u < BW; ++u) {
-        const int e0 = a + u * 64 + lane, e1 = a + (BW + u) * 64 + lane;
-        const int c0 = ld_col(e0);
+    for (int u = 0; u < EBW; ++u) {
+        const int e0 = a + u * 64 + lane;
+        c0[u] = ld_col(e0);
         vc[u] = ld_val(e0);
         dc[u] = ld_step(e0);
+    }
+#pragma unroll
+    for (int u = 0; u < EBW; ++u) {
+        const int e1 = a + (EBW + u) * 64 + lane;
         cn1[u] = ld_col(e1);
         vn1[u] = ld_val(e1);
         dn1[u] = ld_step(e1);
-        bad |= e0 < b_ && (unsigned)(c0 - node_off) >= (unsigned)N;
-        fc[u] = gather_col(c0);
+    }
+#pragma unroll
+    for (int u = 0; u < EBW; ++u) {
+        bad |= a + u * 64 + lane < b_ && (unsigned)(c0[u] - node_off) >= (unsigned)N;
+        fc[u] = gather_col(c0[u]);
     }
     base = row_a;
 #pragma unroll
-    for (int u = 0; u < BW; ++u) {
+    for (int u = 0; u < EBW; ++u) {
         rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rpg, N, node_off);
         base = readlane(rc[u], 63);
         gather_row(rc[u], qc[u], sc[u]);
     }
     const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
 
-    for (int i0 = 0; i0 < nwin; i0 += BW) {
-        // issue: rows and gathers of batch k+1, col/val/steps of batch k+2
+    for (int i0 = 0; i0 < nwin; i0 += EBW) {
+        // Issue col/val/steps of batch k+2 first, then the rows and gathers of batch k+1
+        // (which need the col/steps of batch k+1, loaded one iteration earlier). The
+        // memory counter retires in issue order, so waiting for those col/steps here
+        // leaves the gathers of batch k, issued after them, in flight.
 #pragma unroll
-        for (int u = 0; u < BW; ++u) {
-            const int e1 = a + (i0 + BW + u) * 64 + lane, e2 = a + (i0 + 2 * BW + u) * 64 + lane;
-            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rpg, N, node_off);
-            base = readlane(rn1[u], 63);
-            bad |= e1 < b_ && (unsigned)(cn1[u] - node_off) >= (unsigned)N;
-            fn1[u] = gather_col(cn1[u]);
-            gather_row(rn1[u], qn1[u], sn1[u]);
+        for (int u = 0; u < EBW; ++u) {
+            const int e2 = a + (i0 + 2 * EBW + u) * 64 + lane;
             cn2[u] = ld_col(e2);
             vn2[u] = ld_val(e2);
             dn2[u] = ld_step(e2);
         }
+#pragma unroll
+        for (int u = 0; u < EBW; ++u) {
+            const int e1 = a + (i0 + EBW + u) * 64 + lane;
+            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + EBW + u) * 64, rpg, N, node_off);
+            base = readlane(rn1[u], 63);
+            bad |= e1 < b_ && (unsigned)(cn1[u] - node_off) >= (unsigned)N;
+            fn1[u] = gather_col(cn1[u]);
+            gather_row(rn1[u], qn1[u], sn1[u]);
+        }
         // process batch k
 #pragma unroll
-        for (int u = 0; u < BW; ++u) {
+        for (int u = 0; u < EBW; ++u) {
             const int i = i0 + u;
             if (i >= nwin) break;
             const int p = a + (i << 6);
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
             const bool valid = lane < nvalid;
             const int y = __float_as_int(fc[u].y);
             const float x = vc[u] * fc[u].x;
-            const int nxt = (u + 1 < BW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
+            const int nxt = (u + 1 < EBW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
             cont = (p + nvalid < b_) ? (nxt == 0) : cont_end;
             const bool start = valid && dc[u] != 0;
             const uint64_t sm = ballot(start);
@@ -569,10 +572,17 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
             // the open row and the new rows need ring slots next to the pending ones
             if (npend + 1 + nnew > 64) drain();
             const int slot = (cur_slot + __popcll(sm & le)) & 63;
-            // Lanes with equal (row, class) add to the same LDS word; the LDS applies
-            // them one after another in a fixed order, so the sums are reproducible.
-            if (valid && y >= 0) atomicAdd(&acc[y * KS + slot], x);
-            if (start) slot_meta[slot] = make_float4(__int_as_float(rc[u]), qc[u].x, qc[u].y, sc[u]);
+            // A starting row gets its slot and, with augmentation, its diagonal term c_i
+            // before any entry. Lanes with equal (row, class) add to the same LDS word;
+            // the LDS applies them one after another in a fixed order, so the sums are
+            // reproducible.
+            if (start) {
+                slot_row[slot] = rc[u];
+                slot_s[slot] = sc[u];
+                const int yi = __float_as_int(qc[u].y);
+                if (diag && yi >= 0) atomicAdd(&acc[slot * KP + yi], qc[u].x);
+            }
+            if (valid && y >= 0) atomicAdd(&acc[slot * KP + y], x);
             // rows ended in this window: from lane 0's row to the last lane's row, the
             // latter only if the next entry starts a new row
             const int first_slot = (sm & 1ull) ? (cur_slot + 1) & 63 : cur_slot;
@@ -588,7 +598,7 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         }
         drain();
 #pragma unroll
-        for (int u = 0; u < BW; ++u) {
+        for (int u = 0; u < EBW; ++u) {
             vc[u] = vn1[u];
             dc[u] = dn1[u];
             rc[u] = rn1[u];
@@ -606,16 +616,17 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     if (npend > 0) drain();
     int my_split = -1;
     if (cont) {
+        wave_lds_fence();
         float *dstp = (cur_row == head_row) ? headw : tailw;
         if (cur_row != head_row) my_split = cur_row;
-        for (int k = lane; k < K; k += 64) dstp[k] = acc[k * KS + cur_slot];
+        for (int k = lane; k < K; k += 64) dstp[k] = acc[cur_slot * KP + k];
     }
     if (lane == 0) split[w] = my_split;
 }
 
-// One wavefront per embed wavefront w: finish the row that starts in w and continues.
+// One wavefront per embed wavefront w: finish the row that starts in w and continues
+// (its diagonal term is already in the tail partial).
 __global__ __launch_bounds__(256) void embed_fixup(Batch b, int NWtot, const int *__restrict__ rp,
-                                                   const float2 *__restrict__ info,
                                                    const float *__restrict__ srow,
                                                    const float *__restrict__ headp,
                                                    const float *__restrict__ tailp,
@@ -629,7 +640,7 @@ __global__ __launch_bounds__(256) void embed_fixup(Batch b, int NWtot, const int
     if (!wave_graph(b, w, gd, gm, lw)) return;
     const int r = split[w];
     if (r < gd.node_off || r >= gd.node_off + gd.N) return;
-    const bool diag = gd.flags & kDiag, lap = gd.flags & kLap, cor = gd.flags & kCor;
+    const bool lap = gd.flags & kLap, cor = gd.flags & kCor;
     const int K = gd.K;
     const int end = rp[r + 1];
     const int wl = (int)min((int64_t)gm.NW - 1, max((int64_t)lw, ((int64_t)(end - gm.ent_off) - 1) / gd.WE));
@@ -642,26 +653,12 @@ __global__ __launch_bounds__(256) void embed_fixup(Batch b, int NWtot, const int
         if (lane < K) v0 += heads[(int64_t)w2 * K + lane];
         if (lane + 64 < K) v1 += heads[(int64_t)w2 * K + lane + 64];
     }
-    const float2 inf = info[r];
-    const int lab = __float_as_int(inf.y);
     const float s = lap ? srow[r] : 1.0f;
-    if (diag && lane == lab) v0 += inf.x;
-    if (diag && lane + 64 == lab) v1 += inf.x;
-    if (lap) {
-        v0 *= s;
-        v1 *= s;
-    }
-    if (cor) {
-        const float ss = wave_sum(v0 * v0 + v1 * v1);
-        if (ss > 0.0f) {
-            const float sc = 1.0f / sqrtf(ss);
-            v0 *= sc;
-            v1 *= sc;
-        }
-    }
+    const float ss = cor ? wave_sum(v0 * v0 + v1 * v1) : 0.0f;
+    const float f = row_factor(s, ss, cor);
     float *z = gd.Z + (int64_t)(r - gd.node_off) * K;
-    if (lane < K) z[lane] = v0;
-    if (lane + 64 < K) z[lane + 64] = v1;
+    if (lane < K) z[lane] = v0 * f;
+    if (lane + 64 < K) z[lane + 64] = v1 * f;
 }
 
 // ----------------------------------------------------------------------------- launch
@@ -728,7 +725,7 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKEmbedFixup, s);
     hipLaunchKernelGGL(embed_fixup, dim3((unsigned)((p.NWtot + 3) / 4)), dim3(256), 0, s, b, (int)p.NWtot, rp,
-                       wk.info, wk.srow, wk.headp, wk.tailp, wk.split);
+                       wk.srow, wk.headp, wk.tailp, wk.split);
     prof_end(kKEmbedFixup, s);
     return hipGetLastError();
 }

@@ -169,7 +169,7 @@ struct Plan {
     int G = 1;
     int64_t Vtot = 0;    // virtual entries (CSR capacity) over all graphs
     int64_t Ntot = 0;    // rows over all graphs
-    int Kmax = 1, Ktot = 0;
+    int Kmax = 1, Kmin = 1 << 30, Ktot = 0;
     bool weighted = false;  // some graph has weights (the CSR then carries val)
     bool any_lap_w = false; // some weighted graph uses the Laplacian
     // partition (CSR build)

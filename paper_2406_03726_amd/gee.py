@@ -216,39 +216,47 @@ def gee_embed_csr_workspace_bytes(M: int, N: int, K: int, flags: int, sched=None
 
 # ----------------------------------------------------------------------------- batches
 
-def _graph_struct(g: dict, dev) -> _lib.GeeGraph:
+def _graph_struct(g: dict, dev, sizing: bool = False) -> _lib.GeeGraph:
     """One gee_graph from a dict with src, dst, w (or None), labels, K, flags, Z and an
-    optional sched; N is labels.numel()."""
+    optional sched; N is labels.numel(). For workspace sizing Z may be None."""
     labels = _dev(g["labels"], torch.int32, "labels", dev)
     src = _dev(g["src"], torch.int32, "src", dev)
     dst = _dev(g["dst"], torch.int32, "dst", dev)
     w = _dev(g.get("w"), torch.float32, "w", dev)
-    Z = _dev(g["Z"], torch.float32, "Z", dev)
+    Z = g.get("Z")
     E, N, K = src.numel(), labels.numel(), int(g["K"])
     if dst.numel() != E or (w is not None and w.numel() != E):
         raise ValueError("src, dst and w must have the same length")
-    if Z.numel() != N * K:
-        raise ValueError("Z must hold N * K floats")
+    if Z is None and not sizing:
+        raise ValueError("Z is required")
+    if Z is not None:
+        _dev(Z, torch.float32, "Z", dev)
+        if Z.numel() != N * K:
+            raise ValueError("Z must hold N * K floats")
     sc = g.get("sched")
     if sc is None:
         sc = schedule()
     elif isinstance(sc, dict):
         sc = schedule(**sc)
     return _lib.GeeGraph(src.data_ptr(), dst.data_ptr(), None if w is None else w.data_ptr(), E, N,
-                         labels.data_ptr(), K, int(g["flags"]), Z.data_ptr(), sc)
+                         labels.data_ptr(), K, int(g["flags"]), None if Z is None else Z.data_ptr(), sc)
 
 
-def _graph_array(graphs, dev):
+def _graph_array(graphs, dev, sizing: bool = False):
     arr = (_lib.GeeGraph * len(graphs))()
     for i, g in enumerate(graphs):
-        arr[i] = _graph_struct(g, dev)
+        arr[i] = _graph_struct(g, dev, sizing)
     return arr
 
 
 def gee_embed_batch_workspace_bytes(graphs) -> int:
+    """Workspace of gee_embed_batch for these graphs (their Z may be None here)."""
     dev = graphs[0]["labels"].device
-    arr = _graph_array(graphs, dev)
-    return int(_lib.load().gee_embed_batch_workspace_bytes(arr, len(graphs)))
+    arr = _graph_array(graphs, dev, sizing=True)
+    n = int(_lib.load().gee_embed_batch_workspace_bytes(arr, len(graphs)))
+    if n == 0:
+        raise GeeError(GEE_ERR_ARG, "gee_embed_batch_workspace_bytes")
+    return n
 
 
 def gee_embed_batch(graphs, workspace: Optional[torch.Tensor] = None, stream=None):

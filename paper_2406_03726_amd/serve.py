@@ -1,0 +1,299 @@
+"""Serving loop: graph-embedding requests admitted by a device-memory budget and run with
+continuous batching over several HIP streams.
+
+A request is one graph whose inputs are already on the device (edge list, weights,
+labels). The server keeps a FIFO queue. Whenever a stream slot is free it admits the
+longest prefix of the queue whose footprint (the request's own workspace plus its Z)
+fits the free budget, and launches those requests as one batch (gee_embed_batch_ws) on
+that slot's stream. Batches on different streams overlap on the device; a request that
+arrives while others run is admitted as soon as a slot and memory free up. Admission is
+strictly FIFO, so a large request at the head waits for memory rather than being passed
+(no starvation); a request larger than the whole budget is rejected.
+
+Each request's schedule comes from its own sizes (the autotuned table or the library
+default), so its Z is bitwise the same whether it runs alone or batched with others.
+
+The scheduler is host logic over a small backend interface, so it can be driven by the
+GPU backend or, in tests, by a simulated one on a virtual clock.
+"""
+
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Any, Callable, Deque, Dict, List, Optional, Sequence
+
+
+@dataclass
+class Request:
+    rid: int
+    graph: Dict[str, Any]          # src, dst, w (or None), labels, K, flags[, sched]
+    arrival: float                 # scheduled arrival time (server clock, seconds)
+    E: int = 0
+    N: int = 0
+    nbytes: int = 0                # footprint while admitted
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    result: Any = None
+    error: Optional[str] = None
+    cancelled: bool = False
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+class Backend:
+    """What the scheduler needs from a device."""
+
+    slots: int = 1
+
+    def footprint(self, req: Request) -> int:
+        raise NotImplementedError
+
+    def launch(self, reqs: List[Request], slot: int) -> Any:
+        """Start one batch on slot `slot`; returns a handle."""
+        raise NotImplementedError
+
+    def poll(self, handle: Any) -> bool:
+        """True once the batch has finished (results available)."""
+        raise NotImplementedError
+
+    def finish(self, handle: Any, reqs: List[Request]) -> None:
+        """Hand results to the requests and release the batch's resources."""
+        raise NotImplementedError
+
+
+@dataclass
+class _Flight:
+    slot: int
+    handle: Any
+    reqs: List[Request]
+    nbytes: int
+
+
+class GeeServer:
+    def __init__(self, backend: Backend, budget_bytes: int, max_batch: int = 64,
+                 clock: Callable[[], float] = time.perf_counter):
+        if budget_bytes <= 0 or max_batch < 1:
+            raise ValueError("budget and batch size must be positive")
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.queue: Deque[Request] = deque()
+        self.flights: List[_Flight] = []
+        self.free_slots = list(range(backend.slots))
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.peak_flights = 0
+        self.done: List[Request] = []
+        self.launch_log: List[List[int]] = []   # request ids of every batch, in launch order
+
+    # --------------------------------------------------------------------- intake
+    def submit(self, req: Request) -> None:
+        req.nbytes = int(self.backend.footprint(req))
+        if req.nbytes > self.budget:
+            req.error = f"request needs {req.nbytes} bytes, more than the whole budget of {self.budget}"
+            req.t_done = self.clock()
+            self.done.append(req)
+            return
+        self.queue.append(req)
+
+    def cancel(self, rid: int) -> bool:
+        """Cancel a queued (not yet admitted) request."""
+        for r in self.queue:
+            if r.rid == rid:
+                r.cancelled = True
+                return True
+        return False
+
+    # --------------------------------------------------------------------- scheduling
+    def _reap(self) -> int:
+        n = 0
+        still = []
+        for f in self.flights:
+            if self.backend.poll(f.handle):
+                self.backend.finish(f.handle, f.reqs)
+                now = self.clock()
+                for r in f.reqs:
+                    r.t_done = now
+                    self.done.append(r)
+                self.in_use -= f.nbytes
+                self.free_slots.append(f.slot)
+                n += 1
+            else:
+                still.append(f)
+        self.flights = still
+        return n
+
+    def _admit(self) -> int:
+        launched = 0
+        while self.free_slots and self.queue:
+            while self.queue and self.queue[0].cancelled:
+                r = self.queue.popleft()
+                r.error = "cancelled"
+                r.t_done = self.clock()
+                self.done.append(r)
+            if not self.queue:
+                break
+            batch: List[Request] = []
+            nbytes = 0
+            for r in self.queue:
+                if len(batch) >= self.max_batch:
+                    break
+                if r.cancelled:
+                    continue
+                if self.in_use + nbytes + r.nbytes > self.budget:
+                    break  # FIFO: nothing behind a request that does not fit yet
+                batch.append(r)
+                nbytes += r.nbytes
+            if not batch:
+                break
+            ids = {id(r) for r in batch}
+            self.queue = deque(r for r in self.queue if id(r) not in ids)
+            slot = self.free_slots.pop(0)
+            now = self.clock()
+            for r in batch:
+                r.t_admit = now
+            handle = self.backend.launch(batch, slot)
+            self.flights.append(_Flight(slot, handle, batch, nbytes))
+            self.in_use += nbytes
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.peak_flights = max(self.peak_flights, len(self.flights))
+            self.launch_log.append([r.rid for r in batch])
+            launched += 1
+        return launched
+
+    def step(self) -> int:
+        """Reap finished batches, then admit and launch; returns the number of events."""
+        return self._reap() + self._admit()
+
+    @property
+    def idle(self) -> bool:
+        return not self.queue and not self.flights
+
+    # --------------------------------------------------------------------- traces
+    def run_trace(self, reqs: Sequence[Request], sleep: Callable[[float], None] = time.sleep,
+                  poll_interval: float = 20e-6) -> List[Request]:
+        """Feed requests at their arrival times (relative to now) and run until all are done."""
+        t0 = self.clock()
+        pending = sorted(reqs, key=lambda r: r.arrival)
+        for r in pending:
+            r.arrival += t0
+        i = 0
+        while i < len(pending) or not self.idle:
+            now = self.clock()
+            while i < len(pending) and pending[i].arrival <= now:
+                self.submit(pending[i])
+                i += 1
+            if self.step() == 0:
+                nxt = pending[i].arrival - now if i < len(pending) else poll_interval
+                sleep(max(0.0, min(poll_interval, nxt)))
+        return list(reqs)
+
+
+def run_plain(reqs: Sequence[Request], embed_one: Callable[[Request], None],
+              clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+    """The plain per-request loop: one host thread, FIFO, each request embedded alone and
+    waited for before the next one starts."""
+    t0 = clock()
+    order = sorted(reqs, key=lambda r: r.arrival)
+    for r in order:
+        r.arrival += t0
+    for r in order:
+        now = clock()
+        if r.arrival > now:
+            sleep(r.arrival - now)
+        r.t_admit = clock()
+        embed_one(r)
+        r.t_done = clock()
+    return list(reqs)
+
+
+def percentile(xs: Sequence[float], q: float) -> float:
+    """Linear-interpolated percentile (the numpy default), q in [0, 100]."""
+    s = sorted(xs)
+    if not s:
+        return float("nan")
+    pos = (len(s) - 1) * q / 100.0
+    lo = int(pos)
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (pos - lo)
+
+
+def summarize(reqs: Sequence[Request]) -> Dict[str, float]:
+    ok = [r for r in reqs if r.error is None and r.t_done is not None]
+    lat = [r.latency for r in ok]
+    if not ok:
+        return {"completed": 0}
+    span = max(r.t_done for r in ok) - min(r.arrival for r in ok)
+    return {"completed": len(ok), "rejected": sum(1 for r in reqs if r.error is not None),
+            "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+            "mean_ms": sum(lat) / len(lat) * 1e3,
+            "edges_per_s": sum(r.E for r in ok) / span if span > 0 else float("nan")}
+
+
+# ----------------------------------------------------------------------------- GPU backend
+
+class GpuBackend(Backend):
+    """Batches run with gee_embed_batch_ws on `slots` torch streams (default priority).
+    A request's footprint is its own workspace plus its Z; a batch's workspace is carved
+    from one allocation sized for the batch (never more than the sum of its members')."""
+
+    def __init__(self, slots: int = 4, table=None):
+        import torch
+
+        from . import gee
+
+        self._torch = torch
+        self._gee = gee
+        self.slots = slots
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.table = table
+
+    def sched_of(self, g: Dict[str, Any]) -> Optional[Dict[str, int]]:
+        if g.get("sched") is not None:
+            return g["sched"]
+        if self.table is None:
+            return None
+        s = self.table.lookup(g["src"].numel(), g["labels"].numel(), int(g["K"]), int(g["flags"]))
+        return s or None
+
+    def _item(self, r: Request, Z=None):
+        g = r.graph
+        return dict(src=g["src"], dst=g["dst"], w=g.get("w"), labels=g["labels"], K=int(g["K"]),
+                    flags=int(g["flags"]), Z=Z, sched=self.sched_of(g))
+
+    def footprint(self, r: Request) -> int:
+        g = r.graph
+        r.E = int(g["src"].numel())
+        r.N = int(g["labels"].numel())
+        K = int(g["K"])
+        ws = self._gee.gee_embed_batch_workspace_bytes([self._item(r, Z=None)])
+        return int(ws) + 4 * r.N * K
+
+    def launch(self, reqs: List[Request], slot: int):
+        torch = self._torch
+        s = self.streams[slot]
+        dev = reqs[0].graph["labels"].device
+        with torch.cuda.stream(s):
+            items = []
+            for r in reqs:
+                Z = torch.empty((r.N, int(r.graph["K"])), dtype=torch.float32, device=dev)
+                items.append(self._item(r, Z=Z))
+            nbytes = self._gee.gee_embed_batch_workspace_bytes(items)
+            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+            self._gee.gee_embed_batch(items, workspace=ws, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, items, ws)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle, reqs: List[Request]) -> None:
+        _, items, _ = handle
+        for r, it in zip(reqs, items):
+            r.result = it["Z"]

@@ -1,0 +1,72 @@
+"""CPU tests of the schedule autotuner's host logic (bucketing, choice, table format)."""
+
+import json
+
+import pytest
+
+from paper_2406_03726_amd import autotune as at
+
+
+def test_bucketing():
+    assert at.bucket_of(1000, 100, 3, 8) == (10, 1, 0)       # 2000 entries, degree 20
+    assert at.bucket_of(1000, 100, 3, 0) == (9, 1, 0)        # directed: 1000 entries, degree 10
+    assert at.bucket_of(1000, 10, 3, 8) == (10, 3, 0)        # degree 200
+    assert at.bucket_of(1000, 40, 3, 8) == (10, 2, 0)        # degree 50
+    assert at.bucket_of(10_000_000, 600_000, 50, 15)[2] == 1
+    assert at.bucket_of(5, 1_000_000, 128, 15) == (3, 0, 2)
+    assert at.bucket_of(0, 0, 1, 15) == (0, 0, 0)            # empty graph still has a bucket
+
+
+def test_tune_picks_fastest_and_is_deterministic():
+    shapes = [(1000, 100, 3, 15), (1100, 110, 3, 15), (100_000, 2000, 100, 15)]
+
+    def fake_time(shape, sched):
+        # best at 1024 for the small shapes, 4096 for the large one; a tie elsewhere
+        target = 1024 if shape[0] < 50_000 else 4096
+        return abs(sched["wave_entries"] - target) + 1.0
+
+    t = at.tune(shapes, fake_time)
+    assert t.lookup(1000, 100, 3, 15) == {"wave_entries": 1024}
+    assert t.lookup(100_000, 2000, 100, 15) == {"wave_entries": 4096}
+    # ties resolve to the smaller candidate
+    t2 = at.tune([(1000, 100, 3, 15)], lambda s, c: 1.0)
+    assert t2.lookup(1000, 100, 3, 15) == {"wave_entries": 256}
+
+
+def test_lookup_falls_back_to_nearest_and_default():
+    t = at.ScheduleTable()
+    t.entries[(10, 1, 0)] = {"wave_entries": 512}
+    t.entries[(14, 1, 0)] = {"wave_entries": 2048}
+    assert t.lookup(1000, 100, 3, 15) == {"wave_entries": 512}           # exact
+    assert t.lookup(2 ** 11, 200, 3, 8) == {"wave_entries": 512}         # 2^12 entries: nearer 10
+    assert t.lookup(2 ** 12 + 1, 400, 3, 8)["wave_entries"] in (512, 2048)
+    assert t.lookup(2 ** 20, 100, 3, 8) == {}                            # other degree class
+    assert t.lookup(1000, 100, 100, 15) == {}                            # other class-count class
+    assert at.ScheduleTable().lookup(1, 1, 1, 0) == {}
+
+
+def test_table_roundtrip_and_validation(tmp_path):
+    t = at.ScheduleTable()
+    t.entries[(12, 1, 1)] = {"wave_entries": 1024, "bucket_rows_log2": 6}
+    p = tmp_path / "t.json"
+    t.save(str(p))
+    t2 = at.ScheduleTable.load(str(p))
+    assert t2.entries == t.entries
+    d = json.loads(p.read_text())
+    d["entries"][0]["wave_entries"] = 300
+    p.write_text(json.dumps(d))
+    with pytest.raises(ValueError):
+        at.ScheduleTable.load(str(p))
+    d["version"] = 99
+    p.write_text(json.dumps(d))
+    with pytest.raises(ValueError):
+        at.ScheduleTable.load(str(p))
+    assert at.ScheduleTable.load(str(tmp_path / "missing.json")).entries == {}
+
+
+def test_committed_table_is_valid():
+    import os
+
+    if os.path.exists(at.DEFAULT_TABLE):
+        t = at.ScheduleTable.load(at.DEFAULT_TABLE)
+        assert t.entries, "the committed table has no buckets"

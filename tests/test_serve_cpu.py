@@ -1,0 +1,176 @@
+"""CPU tests of the serving scheduler with a simulated backend on a virtual clock: budget
+admission, FIFO without starvation, stream slots, rejection, cancellation, percentiles, and
+that a request's result is the same alone and in the mix (results from the FP64 oracle)."""
+
+import numpy as np
+import pytest
+
+from gee_workloads import random_small_graph
+from oracle import embed_graph as or_embed_graph
+from paper_2406_03726_amd.serve import Backend, GeeServer, Request, percentile, run_plain, summarize
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class FakeBackend(Backend):
+    """Service time = fixed launch cost + cost per edge; every request's result is the
+    oracle embedding of its own graph (a function of that graph only)."""
+
+    def __init__(self, clock, slots=2, launch_cost=1e-3, per_edge=1e-6, footprint_per_edge=10):
+        self.clock = clock
+        self.slots = slots
+        self.launch_cost = launch_cost
+        self.per_edge = per_edge
+        self.fpe = footprint_per_edge
+        self.active = 0
+        self.max_active = 0
+        self.launched = []
+
+    def footprint(self, req):
+        req.E = int(req.graph["g"].E)
+        req.N = int(req.graph["g"].N)
+        return 1000 + self.fpe * req.E
+
+    def launch(self, reqs, slot):
+        self.active += 1
+        self.max_active = max(self.max_active, self.active)
+        self.launched.append([r.rid for r in reqs])
+        end = self.clock() + self.launch_cost + self.per_edge * sum(r.E for r in reqs)
+        return {"end": end, "slot": slot}
+
+    def poll(self, h):
+        return self.clock() >= h["end"]
+
+    def finish(self, h, reqs):
+        self.active -= 1
+        for r in reqs:
+            r.result = or_embed_graph(r.graph["g"])
+
+
+def _reqs(n, seed=0, rate=1000.0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for i in range(n):
+        g = random_small_graph(500 + i, N=int(rng.integers(20, 300)), E=int(rng.integers(0, 2000)),
+                               K=int(rng.integers(1, 9))).with_options(*(bool(x) for x in rng.random(3) < 0.5))
+        out.append(Request(rid=i, graph={"g": g}, arrival=float(t[i])))
+    return out
+
+
+def test_budget_slots_and_fifo():
+    clk = Clock()
+    be = FakeBackend(clk, slots=3)
+    budget = 60_000
+    srv = GeeServer(be, budget, max_batch=4, clock=clk)
+    reqs = _reqs(60, rate=5000.0)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    assert all(r.t_done is not None for r in reqs)
+    assert srv.peak_in_use <= budget
+    assert be.max_active <= 3 and srv.peak_flights <= 3
+    assert all(len(b) <= 4 for b in be.launched)
+    # launches follow arrival order (FIFO), every request exactly once
+    flat = [rid for b in be.launched for rid in b]
+    assert flat == sorted(flat) and len(flat) == len(set(flat)) == 60
+    # requests did overlap (more than one batch in flight at some point)
+    assert be.max_active > 1
+
+
+def test_large_head_request_is_not_starved():
+    clk = Clock()
+    be = FakeBackend(clk, slots=4, footprint_per_edge=100)
+    reqs = _reqs(12, seed=1, rate=1e5)
+    # request 3 needs nearly the whole budget: later requests must wait behind it
+    big = random_small_graph(99, N=200, E=1900, K=3)
+    reqs[3] = Request(rid=3, graph={"g": big}, arrival=reqs[3].arrival)
+    budget = 1000 + 100 * 1900 + 500
+    srv = GeeServer(be, budget, max_batch=8, clock=clk)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    assert reqs[3].error is None and reqs[3].t_done is not None
+    flat = [rid for b in be.launched for rid in b]
+    assert flat == sorted(flat)
+    # while the big request ran, nothing else was in flight with it beyond the budget
+    assert srv.peak_in_use <= budget
+
+
+def test_reject_over_budget_and_cancel():
+    clk = Clock()
+    be = FakeBackend(clk, slots=1, launch_cost=1.0)
+    srv = GeeServer(be, 5000, clock=clk)
+    small = random_small_graph(1, N=30, E=100, K=2)
+    huge = random_small_graph(2, N=300, E=5000, K=2)
+    r0 = Request(0, {"g": small}, 0.0)
+    r1 = Request(1, {"g": huge}, 0.0)
+    r2 = Request(2, {"g": small}, 0.0)
+    r3 = Request(3, {"g": small}, 0.0)
+    for r in (r0, r1, r2, r3):
+        srv.submit(r)
+    assert r1.error and "budget" in r1.error
+    srv.step()                      # r0 launched (one slot), r2/r3 queued
+    assert srv.cancel(3)
+    while not srv.idle:
+        clk.sleep(0.5)
+        srv.step()
+    assert r0.error is None and r2.error is None
+    assert r3.error == "cancelled" and r3.result is None
+    assert [rid for b in be.launched for rid in b] == [0, 2]
+
+
+def test_results_same_alone_and_in_mix():
+    clk = Clock()
+    be = FakeBackend(clk, slots=2)
+    reqs = _reqs(16, seed=3, rate=1e4)
+    srv = GeeServer(be, 10 ** 9, max_batch=5, clock=clk)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    for r in reqs:
+        alone = or_embed_graph(r.graph["g"])
+        assert np.array_equal(r.result, alone)
+    # the plain loop gives the same results, one request at a time
+    plain = _reqs(16, seed=3, rate=1e4)
+    clk2 = Clock()
+
+    def embed_one(r):
+        clk2.sleep(1e-3)
+        r.result = or_embed_graph(r.graph["g"])
+
+    run_plain(plain, embed_one, clock=clk2, sleep=clk2.sleep)
+    for a, b in zip(reqs, plain):
+        assert np.array_equal(a.result, b.result)
+
+
+def test_percentiles_and_summary():
+    xs = [5.0, 1.0, 3.0, 2.0, 4.0]
+    for q in (0, 10, 50, 90, 99, 100):
+        assert percentile(xs, q) == pytest.approx(np.percentile(xs, q))
+    rs = [Request(i, {}, 0.0, E=10, t_done=float(i + 1)) for i in range(4)]
+    s = summarize(rs)
+    assert s["completed"] == 4 and s["p50_ms"] == pytest.approx(2500.0)
+    assert s["edges_per_s"] == pytest.approx(40 / 4.0)
+
+
+def test_server_beats_plain_loop_on_simulated_device():
+    """With a launch cost per batch and enough slots, batching lowers p99 at a load the
+    plain loop cannot sustain (the scheduling policy, independent of any device)."""
+    clk = Clock()
+    be = FakeBackend(clk, slots=4, launch_cost=2e-3, per_edge=2e-7)
+    reqs = _reqs(80, seed=4, rate=800.0)
+    srv = GeeServer(be, 10 ** 9, max_batch=16, clock=clk)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    plain = _reqs(80, seed=4, rate=800.0)
+    clk2 = Clock()
+
+    def embed_one(r):
+        clk2.sleep(2e-3 + 2e-7 * r.graph["g"].E)
+        r.E = r.graph["g"].E
+
+    run_plain(plain, embed_one, clock=clk2, sleep=clk2.sleep)
+    assert summarize(reqs)["p99_ms"] < summarize(plain)["p99_ms"]
