@@ -282,6 +282,107 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
     return out
 
 
+# ----------------------------------------------------------------------------- HBM traffic
+
+PROFILES = os.path.join(ROOT, "profiles")
+CALIB_BYTES = 256 << 20  # device-to-device copy that calibrates the byte counters
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources: traffic figures taken from an older build do not count."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2406_03726_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(kernel: str, workload: str) -> str:
+    return os.path.join(PROFILES, f"hbm_traffic_{kernel}_{workload}.md")
+
+
+def read_traffic(kernel: str, workload: str):
+    """Bytes per launch of `kernel` from its committed counter summary, or None when absent
+    or taken from other sources than the current ones."""
+    path = traffic_path(kernel, workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    i = text.find("```json")
+    if i < 0:
+        return None
+    d = json.loads(text[i + 7:text.index("```", i + 7)])
+    if d.get("source_hash") != source_hash():
+        return None
+    return d
+
+
+def _counter_rows(csv_path: str, counter: str):
+    import csv
+
+    rows = []
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, commands: str) -> str:
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
+    per-launch HBM bytes of `kernel`, each counter scaled by what it reads for a plain
+    device-to-device copy of CALIB_BYTES in the same run."""
+    out = {"kernel": kernel, "workload": workload, "source_hash": source_hash(), "calib_bytes": CALIB_BYTES}
+    for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
+        rows = _counter_rows(path, counter)
+        copies = [v for n, v in rows if "copyBuffer" in n]
+        if not copies:
+            raise SystemExit(f"no copy dispatch in {path}")
+        calib_kib = max(copies)
+        factor = (CALIB_BYTES / 1024.0) / calib_kib
+        mine = [v for n, v in rows if n.split("(")[0].replace("void ", "").split("<")[0].endswith(kernel)]
+        if not mine:
+            raise SystemExit(f"no {kernel} dispatch in {path}")
+        kib = sum(mine) / len(mine)
+        out[f"{key}_kib_per_launch"] = round(kib, 1)
+        out[f"{key}_calibration_factor"] = round(factor, 4)
+        out[f"{key}_bytes_per_launch"] = int(kib * 1024 * factor)
+        out[f"{key}_launches"] = len(mine)
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    path = traffic_path(kernel, workload)
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(path, "w") as f:
+        f.write(f"# HBM traffic of `{kernel}` on `{workload}`\n\n")
+        f.write("Two rocprofv3 counter runs of the same command (FETCH_SIZE, then WRITE_SIZE; KiB per\n"
+                "dispatch), each scaled by what the counter reads for a 256 MiB device-to-device copy\n"
+                "made in the same run. Commands (from /tmp, TMPDIR=/tmp, on the MI355X box):\n\n")
+        f.write("```\n" + commands.strip() + "\n```\n\n")
+        f.write("```json\n" + json.dumps(out, indent=1) + "\n```\n")
+    return path
+
+
+def pmc_target(gee, torch, np):
+    """What the counter runs profile: one calibration copy, then one warmup and one step
+    of the default workload."""
+    dev = torch.device("cuda:0")
+    a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    g = make_workload("powerlaw_10m")
+    t = lambda x, dt: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev, dt)  # noqa
+    src, dst, w, lab = t(g.src, torch.int32), t(g.dst, torch.int32), t(g.w, torch.float32), t(g.labels, torch.int32)
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    for _ in range(2):
+        gee.gee_embed(src, dst, w, lab, g.K, flags)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,7 +396,18 @@ def main():
                     help="systems legs to add to the line: batched, serving (comma list, or none)")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1),
                     help="worker processes that draw the systems legs' graphs")
+    ap.add_argument("--pmc-target", action="store_true",
+                    help="run only what the rocprofv3 counter runs measure (a calibration copy and two steps)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="host only: turn two counter CSVs into the committed traffic summary")
+    ap.add_argument("--traffic-kernel", default="bucket_sort")
+    ap.add_argument("--traffic-commands", default="")
     args = ap.parse_args()
+
+    if args.write_traffic:
+        print(write_traffic(args.write_traffic[0], args.write_traffic[1], args.traffic_kernel,
+                            "chunglu_n600k_e10m_k50", args.traffic_commands))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -315,6 +427,9 @@ def main():
 
         __graft_entry__.build()
     lib = _lib.load()
+    if args.pmc_target:
+        pmc_target(gee, torch, np)
+        return
 
     t_gen = time.perf_counter()
     g = make_workload(args.workload)
@@ -383,9 +498,12 @@ def main():
     dom_avg_ms = float(np.mean(dom_ms))
     alg = algorithmic_bytes(dominant, E, N, K, M, w is not None, n_empty)
     achieved = alg / (dom_avg_ms * 1e-3) / 1e9
+    tr = read_traffic(dominant, g.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
-                "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(dom_avg_ms, 5)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes_per_launch"] if tr else None,
+                "kernel": dominant, "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(dom_avg_ms, 5)}
+    if tr:
+        roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
     # Steady state on a resident CSR (re-embedding, the serving/iterative form).
     Zr = torch.empty_like(Z)

@@ -32,6 +32,9 @@ namespace gee {
 
 constexpr int kTile = 4096;    // entries per partition tile: 16 rounds of 256 threads
 constexpr int kRounds = kTile / 256;
+constexpr int kWaves = 4;                 // wavefronts per partition workgroup
+constexpr int kQuarter = kTile / kWaves;  // items per wavefront per tile
+constexpr int kRoundsW = kQuarter / 64;   // rounds of one wavefront
 
 // ----------------------------------------------------------------------------- helpers
 
@@ -107,12 +110,13 @@ __device__ int block_excl_scan_lds(int *a, int n, int *wsum) {
 
 // Virtual entry v of the batch: its graph, then (row, column[, weight]) with the graph's
 // node offset added. Invalid: index out of range (sets badi), or the mirror of a
-// self-loop under symmetrization. `gd`/`g` cache the graph of the previous call.
+// self-loop under symmetrization. `gd`/`g` cache the graph of the previous call (g < 0:
+// none); any v outside the cached graph's range looks its graph up again.
 template <bool VAL>
 __device__ __forceinline__ bool load_virtual(const Batch &b, int64_t v, int64_t V, int &g, GDesc &gd,
                                              int &key, int &cl, float &val, bool &badi, bool &badw) {
     if (v >= V) return false;
-    if (g < 0 || v >= gd.voff + gd.Mcap) {  // entries of one thread only move forward
+    if (g < 0 || v < gd.voff || v >= gd.voff + gd.Mcap) {  // not in the cached graph
         g = find_graph(b.voffs, b.G, v);
         gd = load_desc(b, g);
     }
@@ -135,6 +139,66 @@ __device__ __forceinline__ bool load_virtual(const Batch &b, int64_t v, int64_t 
     return inr && (side == 0 || s != d);
 }
 
+// A wavefront's quarter of a tile (kRoundsW rounds of 64 virtual entries), loaded into
+// registers with every load issued before any is used. Entry r of this lane is virtual
+// entry vw + 64 r + lane.
+template <bool VAL>
+struct Quarter {
+    int key[16], col[16];
+    float val[16];
+    unsigned valid;  // bit r: entry r is a real adjacency entry
+};
+
+template <bool VAL>
+__device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
+                                             bool &badw) {
+    static_assert(kRoundsW == 16, "Quarter holds 16 rounds");
+    const int lane = lane_id();
+    q.valid = 0;
+    if (vw >= V) return;
+    const int64_t vhi = min(vw + (int64_t)kQuarter, V) - 1;
+    const int g0 = find_graph(b.voffs, b.G, vw), g1 = find_graph(b.voffs, b.G, vhi);
+    if (g0 == g1) {
+        // one graph: clamped unconditional loads, then the checks
+        const GDesc gd = load_desc(b, g0);
+        const bool sym = gd.flags & kSym;
+        int sv[16], dv[16];
+        float wv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t lv = min(vw + r * 64 + lane, vhi) - gd.voff;
+            const int64_t e = sym ? (lv >> 1) : lv;
+            sv[r] = gd.src[e];
+            dv[r] = gd.dst[e];
+            if (VAL) wv[r] = gd.w ? gd.w[e] : 1.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t v = vw + r * 64 + lane;
+            const int side = sym ? (int)((v - gd.voff) & 1) : 0;
+            const bool inb = v <= vhi;
+            const bool inr = (unsigned)sv[r] < (unsigned)gd.N && (unsigned)dv[r] < (unsigned)gd.N;
+            if (inb && !inr) badi = true;
+            if (VAL && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
+            q.key[r] = (side ? dv[r] : sv[r]) + gd.node_off;
+            q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
+            if (VAL) q.val[r] = wv[r];
+            q.valid |= (inb && inr && (side == 0 || sv[r] != dv[r])) ? (1u << r) : 0u;
+        }
+    } else {
+        // the quarter spans graphs (small graphs of a batch): entry by entry
+        int g = -1;
+        GDesc gd;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            float val = 1.0f;
+            const bool ok = load_virtual<VAL>(b, vw + r * 64 + lane, V, g, gd, q.key[r], q.col[r], val, badi, badw);
+            if (VAL) q.val[r] = val;
+            q.valid |= ok ? (1u << r) : 0u;
+        }
+    }
+}
+
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
 __global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
@@ -143,16 +207,13 @@ __global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int
     hist[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
-    const int64_t v0 = t * kTile;
+    const int wv = threadIdx.x >> 6;
     bool badi = false, badw = false;
-    int g = -1;
-    GDesc gd;
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t v = v0 + r * 256 + threadIdx.x;
-        int key, cl;
-        float val;
-        if (load_virtual<false>(b, v, V, g, gd, key, cl, val, badi, badw)) atomicAdd(&hist[key >> shift], 1);
-    }
+    Quarter<false> q;
+    load_quarter<false>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (q.valid >> r & 1u) atomicAdd(&hist[q.key[r] >> shift], 1);
     if (__syncthreads_or(badi) && threadIdx.x == 0) raise_error(status, kErrIndex);
     if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
 }
@@ -212,63 +273,98 @@ __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int
     }
 }
 
-// Shared by the partition scatters: this tile's digit counts -> LDS local starts,
-// running ranks and global bases. cnt is this thread's digit count (digit = thread).
-__device__ __forceinline__ int tile_layout(int cnt, int gbase_d, int D, int *lstart, int *run, int *gbase,
-                                           unsigned char *tab, int *wsum) {
-    int total;
-    const int ls = block_excl_scan256(cnt, wsum, total);
-    if ((int)threadIdx.x < D) {
-        lstart[threadIdx.x] = ls;
-        run[threadIdx.x] = ls;
-        gbase[threadIdx.x] = gbase_d;
-    }
-    for (int i = threadIdx.x; i < 4 * 256; i += blockDim.x) tab[i] = 0;
-    __syncthreads();
-    return total;
-}
+// ----------------------------------------------------------------------------- wave-split ranking
+//
+// A tile is sorted by digit in LDS without a workgroup barrier per round: each of the 4
+// wavefronts owns a contiguous quarter of the tile. The wavefronts first count their
+// items per digit (LDS atomics on their own row of counters), one scan over
+// (digit, wavefront) turns the counts into the first position of every (wavefront,
+// digit) pair, then each wavefront reloads its items and ranks them in order: lanes
+// with the same digit are found by ballots over the digit bits, and a per-digit running
+// position advanced by the last lane of each group keeps the input order.
+
 
 struct PartLds {
-    int lstart[256], run[256], gbase[256], wsum[4];
-    unsigned char tab[4 * 256];
+    int cnt[kWaves][256];  // per-wavefront digit counts, then running positions
+    int lstart[256], gbase[256], wsum[4];
     int key[kTile];
     int col[kTile];
     float val[kTile];
 };
 
-// Pass A scatter: tile t of the virtual entries, ranked by high digit, staged, and
-// written to seg_start[d] + (scanned tile offset) in runs.
-__global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
-                                                 const int *__restrict__ gh, const int *__restrict__ tot,
-                                                 const int *__restrict__ seg_start, int *__restrict__ okey,
-                                                 int *__restrict__ ocol, float *__restrict__ oval,
-                                                 unsigned *status) {
-    __shared__ PartLds L;
-    const int64_t t = blockIdx.x;
-    int cnt = 0, gb = 0;
-    if ((int)threadIdx.x < D) {
-        const int64_t i = (int64_t)threadIdx.x * T + t;
-        const int cur = gh[i];
-        const int nxt = (t + 1 < T) ? gh[i + 1] : tot[threadIdx.x];
-        cnt = nxt - cur;
-        gb = seg_start[threadIdx.x] + cur;
+// Thread d: the tile's first position of digit d (lstart), its global base, and the first
+// position of every wavefront's run of digit d (in cnt). Returns the tile's item count.
+__device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, int *gbase, int *wsum, int D,
+                                                 int gbase_d) {
+    const int d = threadIdx.x;
+    int c[kWaves];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c[w] = d < D ? cnt[w][d] : 0;
+    int total;
+    const int ls = block_excl_scan256(c[0] + c[1] + c[2] + c[3], wsum, total);
+    if (d < D) {
+        lstart[d] = ls;
+        gbase[d] = gbase_d;
+        int run = ls;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            cnt[w][d] = run;
+            run += c[w];
+        }
     }
-    const int n = tile_layout(cnt, gb, D, L.lstart, L.run, L.gbase, L.tab, L.wsum);
-    const int64_t v0 = t * kTile;
+    __syncthreads();
+    return total;
+}
+
+// Stable position of this lane's item among the wavefront's items of the same digit (in
+// round and lane order); the last lane of each digit group advances the digit's running
+// position.
+__device__ __forceinline__ int wave_rank(int *run, int digit, bool valid, int nbits) {
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (digit >> b) & 1;
+        const uint64_t m = ballot(valid && bit);
+        peers &= bit ? m : ~m;
+    }
+    const int below = count_below(peers);
+    const int cntp = __popcll(peers);
+    const int pos = valid ? run[digit] + below : 0;
+    wave_lds_fence();
+    if (valid && below == cntp - 1) run[digit] = pos + 1;
+    wave_lds_fence();
+    return pos;
+}
+
+// Pass A scatter: tile t of the virtual entries, sorted by high digit in LDS (wave-split
+// ranking over the wavefront's registers) and written to seg_start[d] + (scanned tile
+// offset) in runs.
+__global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
+                                                 const int *__restrict__ gh, const int *__restrict__ seg_start,
+                                                 int *__restrict__ okey, int *__restrict__ ocol,
+                                                 float *__restrict__ oval, unsigned *status) {
+    __shared__ PartLds L;
+    const int wv = threadIdx.x >> 6;
+    const int64_t t = blockIdx.x;
     bool badi = false, badw = false;
-    int g = -1;
-    GDesc gd;
-    for (int r = 0; r < kRounds; ++r) {
-        const int64_t v = v0 + r * 256 + threadIdx.x;
-        int key = 0, cl = 0;
-        float val = 1.0f;
-        const bool valid = load_virtual<true>(b, v, V, g, gd, key, cl, val, badi, badw);
-        const int digit = valid ? (key >> shift) : 0;
-        const int pos = block_rank4(digit, valid, nbits, L.tab, L.run, D);
+    Quarter<true> q;
+    load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+    for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (q.valid >> r & 1u) atomicAdd(&L.cnt[wv][q.key[r] >> shift], 1);
+    __syncthreads();
+    const int gb = (int)threadIdx.x < D ? seg_start[threadIdx.x] + gh[(int64_t)threadIdx.x * T + t] : 0;
+    const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const bool valid = q.valid >> r & 1u;
+        const int digit = valid ? (q.key[r] >> shift) : 0;
+        const int pos = wave_rank(L.cnt[wv], digit, valid, nbits);
         if (valid) {
-            L.key[pos] = key;
-            L.col[pos] = cl;
-            if (oval) L.val[pos] = val;
+            L.key[pos] = q.key[r];
+            L.col[pos] = q.col[r];
+            if (oval) L.val[pos] = q.val[r];
         }
     }
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
@@ -313,7 +409,12 @@ __global__ __launch_bounds__(256) void b_hist(const int *__restrict__ akey, int 
     __syncthreads();
     const int e0 = seg_start[d] + jt * kTile;
     const int e1 = min(e0 + kTile, seg_start[d + 1]);
-    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&hist[(akey[e] >> sb) & (L - 1)], 1);
+    int k[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) k[r] = akey[min(e0 + r * 256 + (int)threadIdx.x, e1 - 1)];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[(k[r] >> sb) & (L - 1)], 1);
     __syncthreads();
     if ((int)threadIdx.x < L) gh[((int64_t)tile_off[d] << s2) + (int64_t)threadIdx.x * ntd + jt] = hist[threadIdx.x];
 }
@@ -357,8 +458,8 @@ __global__ __launch_bounds__(256) void b_scan(int *__restrict__ gh, int s2, cons
     }
 }
 
-// Pass B scatter: tile j of segment d, ranked by low digit, staged, written in runs;
-// the key becomes the row inside its bucket.
+// Pass B scatter: tile j of segment d, sorted by low digit in LDS (wave-split ranking),
+// written in runs; the key becomes the row inside its bucket.
 __global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, const int *__restrict__ acol,
                                                  const float *__restrict__ aval, int sb, int s2,
                                                  const int *__restrict__ gh, const int *__restrict__ seg_start,
@@ -368,35 +469,41 @@ __global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, c
     __shared__ PartLds L;
     int d, jt, ntd;
     if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
+    const int wv = threadIdx.x >> 6, lane = lane_id();
     const int ND = 1 << s2;
     const int s0 = seg_start[d];
     const int nseg = seg_start[d + 1] - s0;
     const int *seg = gh + ((int64_t)tile_off[d] << s2);
-    int cnt = 0, gb = 0;
-    if ((int)threadIdx.x < ND) {
-        const int64_t i = (int64_t)threadIdx.x * ntd + jt;
-        const int cur = seg[i];
-        const int nxt = (jt + 1 < ntd) ? seg[i + 1] : ((int)threadIdx.x + 1 < ND ? seg[i + 1] : nseg);
-        cnt = nxt - cur;
-        gb = s0 + cur;
-    }
-    const int n = tile_layout(cnt, gb, ND, L.lstart, L.run, L.gbase, L.tab, L.wsum);
+    for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
+    __syncthreads();
     const int e0 = s0 + jt * kTile;
     const int e1 = min(e0 + kTile, s0 + nseg);
+    const int ew = e0 + wv * kQuarter;
+    int kr[16], cr[16];
+    float vr[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int ec = min(ew + r * 64 + lane, e1 - 1);
+        kr[r] = akey[ec];
+        cr[r] = acol[ec];
+        vr[r] = oval ? aval[ec] : 1.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> sb) & (ND - 1)], 1);
+    __syncthreads();
+    const int gb = (int)threadIdx.x < ND ? s0 + seg[(int64_t)threadIdx.x * ntd + jt] : 0;
+    const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
     const int rmask = (1 << sb) - 1;
-    for (int r = 0; r < kRounds; ++r) {
-        const int e = e0 + r * 256 + threadIdx.x;
-        const bool valid = e < e1;
-        const int ec = valid ? e : e0;
-        const int key = akey[ec];
-        const int cl = acol[ec];
-        const float val = oval ? aval[ec] : 1.0f;
-        const int digit = valid ? ((key >> sb) & (ND - 1)) : 0;
-        const int pos = block_rank4(digit, valid, s2, L.tab, L.run, ND);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const bool valid = ew + r * 64 + lane < e1;
+        const int digit = valid ? ((kr[r] >> sb) & (ND - 1)) : 0;
+        const int pos = wave_rank(L.cnt[wv], digit, valid, s2);
         if (valid) {
-            L.key[pos] = key;
-            L.col[pos] = cl;
-            if (oval) L.val[pos] = val;
+            L.key[pos] = kr[r];
+            L.col[pos] = cr[r];
+            if (oval) L.val[pos] = vr[r];
         }
     }
     __syncthreads();
@@ -434,6 +541,65 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
     const int Rb = min(R, N - r0);
     const int e0 = bstart[b], e1 = bstart[b + 1];
     const int rmask = R - 1;
+    if (R <= 256 && e1 - e0 <= cap) {
+        // Wave-split ranking: each wavefront counts and ranks a contiguous quarter.
+        const int wv = threadIdx.x >> 6, lane = lane_id();
+        int *cnt = smem_i;                                              // [4][R]
+        int *scol2 = cnt + kWaves * R;                                  // [cap]
+        float *sval2 = reinterpret_cast<float *>(scol2 + cap);          // [cap]
+        for (int i = threadIdx.x; i < kWaves * R; i += blockDim.x) cnt[i] = 0;
+        __syncthreads();
+        const int n = e1 - e0;
+        const int q = (((n + kWaves - 1) / kWaves) + 63) & ~63;  // <= 1024: 16 rounds
+        const int ew = e0 + min(n, wv * q), ee = e0 + min(n, (wv + 1) * q);
+        int kr[16] = {0}, cr[16] = {0};
+        float vr[16] = {0.0f};
+        if (ee > ew) {  // this wavefront has entries: clamped loads stay inside [ew, ee)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ec = min(ew + r * 64 + lane, ee - 1);
+                kr[r] = (int)tkey[ec] & rmask;
+                cr[r] = tcol[ec];
+                vr[r] = val ? tval[ec] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (ew + r * 64 + lane < ee) atomicAdd(&cnt[wv * R + kr[r]], 1);
+        __syncthreads();
+        const int r = threadIdx.x;
+        int c[kWaves];
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c[w] = r < R ? cnt[w * R + r] : 0;
+        int total;
+        const int ls = block_excl_scan256(c[0] + c[1] + c[2] + c[3], wsum, total);
+        if (r < Rb) rp[r0 + r] = e0 + ls;
+        if (r < R) {
+            int run2 = ls;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                cnt[w * R + r] = run2;
+                run2 += c[w];
+            }
+        }
+        if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const bool valid = ew + r * 64 + lane < ee;
+            const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid, sb);
+            if (valid) {
+                scol2[pos] = cr[r];
+                if (val) sval2[pos] = vr[r];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            col[e0 + i] = scol2[i];
+            if (val) val[e0 + i] = sval2[i];
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < R; i += blockDim.x) run[i] = 0;
     for (int i = threadIdx.x; i < 4 * R; i += blockDim.x) tab[i] = 0;
     __syncthreads();
@@ -475,7 +641,11 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 
 // Staging capacity of bucket_sort: the whole workgroup stays within 64 KiB of LDS.
 static int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
-size_t bucket_sort_lds(int sb) { return (size_t)(1 << sb) * 8 + (size_t)bucket_stage_cap(sb) * 8; }
+size_t bucket_sort_lds(int sb) {
+    const size_t R = (size_t)1 << sb;
+    const size_t counters = R <= 256 ? kWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
+    return (counters > 8 * R ? counters : 8 * R) + (size_t)bucket_stage_cap(sb) * 8;
+}
 
 hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
     const bool with_b = p.s2 > 0;
@@ -502,7 +672,7 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScatter, s);
     hipLaunchKernelGGL(a_scatter, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits, p.TA,
-                       wk.ghA, wk.totA, wk.segA, wk.akey, acol, aval, status);
+                       wk.ghA, wk.segA, wk.akey, acol, aval, status);
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!with_b) return hipSuccess;
