@@ -32,7 +32,7 @@ METRIC = "edges embedded/sec + % HBM peak; served p50/p99 latency vs plain per-g
 HBM_PEAK_GBS = 8000.0
 
 KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
-           "b_hist", "b_scan", "b_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
+           "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
            "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"]
 
 
@@ -50,8 +50,9 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return 4 * M
     if name == "b_scatter":  # (row, col[, w]) in, (row in bucket u16, col[, w]) out
         return (4 + 4 + wv) * M + (2 + 4 + wv) * M
-    if name == "bucket_sort":  # keys read twice (count, then rank), col/val once; CSR out
-        return (2 + 2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)
+    if name == "bucket_sort":  # all buckets counted as if sorted here (an upper bound when
+        # the largest buckets go to the pass-C tiles): key, col, val in; CSR out
+        return (2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)
     if name == "node_rows":
         return 4 * (N + 1) + 4 * N + 8 * N + 4 * N
     if name == "degree_rows":

@@ -196,6 +196,8 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     p.TA = (p.Vtot + p.tile - 1) / p.tile;
     if (p.TA < 1) p.TA = 1;
     p.TBcap = p.s2 > 0 ? p.TA + p.DA : 1;
+    // pass C: every bucket above the staging capacity holds more than cap entries
+    p.TCcap = p.sb <= 8 ? p.TA + p.Vtot / bucket_stage_cap(p.sb) + 1 : 1;
     // One wavefront per embed workgroup by default: the LDS ring of each wavefront then
     // limits residency least. Larger workgroups must stay within 64 KiB of LDS.
     const size_t per_wave = embed_lds_per_wave(p.Kmax);
@@ -237,6 +239,8 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.tileB = (int *)take((size_t)(p.DA + 1) * sizeof(int));
         if (p.s2 > 0) w.ghB = (int *)take(((size_t)p.TBcap << p.s2) * sizeof(int));
         w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
+        w.tileC = (int *)take((size_t)(p.B + 1) * sizeof(int));
+        w.ghC = (int *)take(((size_t)p.TCcap << p.sb) * sizeof(int));
         w.akey = (int *)take((size_t)p.Vtot * sizeof(int));
         if (p.s2 > 0) w.tkey = (uint16_t *)take((size_t)p.Vtot * sizeof(uint16_t));
         w.tcol = (int *)take((size_t)p.Vtot * sizeof(int));
@@ -376,7 +380,7 @@ namespace gee {
 
 const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
-    "b_hist", "b_scan", "b_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
+    "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"};
 
 void prof_begin(int kid, hipStream_t s) {

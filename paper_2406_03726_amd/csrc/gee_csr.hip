@@ -11,9 +11,13 @@
 //
 //   pass A  partition the virtual entries by high digit      (a_hist, digit_scan,
 //                                                              a_totals, a_scatter)
-//   pass B  partition each high-digit segment by low digit    (b_hist, b_scan, b_scatter)
-//   pass C  one workgroup per bucket: row counts -> row_ptr, then the entries of the
-//           bucket in row order                               (bucket_sort)
+//   pass B  partition each high-digit segment by low digit    (seg_hist, seg_scan,
+//                                                              seg_scatter)
+//   pass C  buckets of at most 4096 entries: one workgroup per bucket, row counts ->
+//           row_ptr, then the entries in row order             (bucket_sort)
+//           larger buckets (they hold hub rows): the segment partition once more with
+//           the row inside the bucket as the digit, over many workgroups (c_tiles,
+//           seg_hist, seg_scan, seg_scatter)
 //
 // With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
 //
@@ -396,40 +400,49 @@ __device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, int D, 
     return true;
 }
 
-// Per pass-B tile: histogram of the low digit; segment d's counts are stored
-// low-digit-major at gh + tile_off[d] * 2^s2, [digit][tile].
-__global__ __launch_bounds__(256) void b_hist(const int *__restrict__ akey, int sb, int s2,
-                                              const int *__restrict__ seg_start,
-                                              const int *__restrict__ tile_off, int D, int *__restrict__ gh) {
+// Segment partitions (pass B, and pass C for buckets too large for one workgroup): the
+// items of segment d (seg_start[d] .. seg_start[d+1]) are split into tiles of kTile;
+// tile_off[d] is the segment's first tile. The digit of a key is
+// (key >> dshift) & (2^dbits - 1).
+
+// Per tile: digit histogram; segment d's counts are stored digit-major at
+// gh + tile_off[d] * 2^dbits, [digit][tile].
+template <typename KT>
+__global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int dshift, int dbits,
+                                                const int *__restrict__ seg_start, const int *__restrict__ tile_off,
+                                                int D, int *__restrict__ gh) {
     __shared__ int hist[256];
     int d, jt, ntd;
     if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
-    const int L = 1 << s2;
+    const int L = 1 << dbits;
     hist[threadIdx.x] = 0;
     __syncthreads();
     const int e0 = seg_start[d] + jt * kTile;
     const int e1 = min(e0 + kTile, seg_start[d + 1]);
     int k[kRounds];
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) k[r] = akey[min(e0 + r * 256 + (int)threadIdx.x, e1 - 1)];
+    for (int r = 0; r < kRounds; ++r) k[r] = (int)key[min(e0 + r * 256 + (int)threadIdx.x, e1 - 1)];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r)
-        if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[(k[r] >> sb) & (L - 1)], 1);
+        if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[(k[r] >> dshift) & (L - 1)], 1);
     __syncthreads();
-    if ((int)threadIdx.x < L) gh[((int64_t)tile_off[d] << s2) + (int64_t)threadIdx.x * ntd + jt] = hist[threadIdx.x];
+    if ((int)threadIdx.x < L) gh[((int64_t)tile_off[d] << dbits) + (int64_t)threadIdx.x * ntd + jt] = hist[threadIdx.x];
 }
 
 // One workgroup per segment d: exclusive scan of its [digit][tile] counts (positions
-// inside the segment) and the bucket starts of its 2^s2 buckets.
-__global__ __launch_bounds__(256) void b_scan(int *__restrict__ gh, int s2, const int *__restrict__ seg_start,
-                                              const int *__restrict__ tile_off, int B,
-                                              int *__restrict__ bstart) {
+// inside the segment), and starts[(d << dbits) + digit] = the first position of each
+// digit (for indices below `limit`). With skip_untiled, segments without tiles are left
+// alone (pass C: those buckets are sorted whole by bucket_sort).
+__global__ __launch_bounds__(256) void seg_scan(int *__restrict__ gh, int dbits, const int *__restrict__ seg_start,
+                                                const int *__restrict__ tile_off, int limit,
+                                                int *__restrict__ starts, int skip_untiled) {
     __shared__ int wsum[4];
     const int d = blockIdx.x;
     const int ntd = tile_off[d + 1] - tile_off[d];
-    const int L = 1 << s2;
-    const int64_t len = (int64_t)ntd << s2;
-    int *seg = gh + ((int64_t)tile_off[d] << s2);
+    if (skip_untiled && ntd == 0) return;
+    const int L = 1 << dbits;
+    const int64_t len = (int64_t)ntd << dbits;
+    int *seg = gh + ((int64_t)tile_off[d] << dbits);
     int carry = 0;
     constexpr int IPT = 8;
     for (int64_t c = 0; c < len; c += 256 * IPT) {
@@ -453,27 +466,30 @@ __global__ __launch_bounds__(256) void b_scan(int *__restrict__ gh, int s2, cons
     __syncthreads();
     const int s0 = seg_start[d];
     for (int lo = threadIdx.x; lo < L; lo += blockDim.x) {
-        const int b = (d << s2) + lo;
-        if (b < B) bstart[b] = s0 + (ntd > 0 ? seg[(int64_t)lo * ntd] : 0);
+        const int64_t b = ((int64_t)d << dbits) + lo;
+        if (b < limit) starts[b] = s0 + (ntd > 0 ? seg[(int64_t)lo * ntd] : 0);
     }
 }
 
-// Pass B scatter: tile j of segment d, sorted by low digit in LDS (wave-split ranking),
-// written in runs; the key becomes the row inside its bucket.
-__global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, const int *__restrict__ acol,
-                                                 const float *__restrict__ aval, int sb, int s2,
-                                                 const int *__restrict__ gh, const int *__restrict__ seg_start,
-                                                 const int *__restrict__ tile_off, int D,
-                                                 uint16_t *__restrict__ okey, int *__restrict__ ocol,
-                                                 float *__restrict__ oval) {
+// Per tile: sorted by digit in LDS (wave-split ranking over registers), written in runs.
+// FINAL = false (pass B): key, column and value go to the next pass, the key reduced to
+// the row inside its bucket (key & kmask). FINAL = true (pass C): column and value go to
+// their CSR slots.
+template <typename KT, bool FINAL>
+__global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, const int *__restrict__ col,
+                                                   const float *__restrict__ val, int dshift, int dbits, int kmask,
+                                                   const int *__restrict__ gh, const int *__restrict__ seg_start,
+                                                   const int *__restrict__ tile_off, int D,
+                                                   uint16_t *__restrict__ okey, int *__restrict__ ocol,
+                                                   float *__restrict__ oval) {
     __shared__ PartLds L;
     int d, jt, ntd;
     if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
     const int wv = threadIdx.x >> 6, lane = lane_id();
-    const int ND = 1 << s2;
+    const int ND = 1 << dbits;
     const int s0 = seg_start[d];
     const int nseg = seg_start[d + 1] - s0;
-    const int *seg = gh + ((int64_t)tile_off[d] << s2);
+    const int *seg = gh + ((int64_t)tile_off[d] << dbits);
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
     __syncthreads();
     const int e0 = s0 + jt * kTile;
@@ -484,22 +500,21 @@ __global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, c
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int ec = min(ew + r * 64 + lane, e1 - 1);
-        kr[r] = akey[ec];
-        cr[r] = acol[ec];
-        vr[r] = oval ? aval[ec] : 1.0f;
+        kr[r] = (int)key[ec];
+        cr[r] = col[ec];
+        vr[r] = oval ? val[ec] : 1.0f;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> sb) & (ND - 1)], 1);
+        if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> dshift) & (ND - 1)], 1);
     __syncthreads();
     const int gb = (int)threadIdx.x < ND ? s0 + seg[(int64_t)threadIdx.x * ntd + jt] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
-    const int rmask = (1 << sb) - 1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const bool valid = ew + r * 64 + lane < e1;
-        const int digit = valid ? ((kr[r] >> sb) & (ND - 1)) : 0;
-        const int pos = wave_rank(L.cnt[wv], digit, valid, s2);
+        const int digit = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
+        const int pos = wave_rank(L.cnt[wv], digit, valid, dbits);
         if (valid) {
             L.key[pos] = kr[r];
             L.col[pos] = cr[r];
@@ -508,13 +523,40 @@ __global__ __launch_bounds__(256) void b_scatter(const int *__restrict__ akey, c
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int key = L.key[i];
-        const int dg = (key >> sb) & (ND - 1);
+        const int k = L.key[i];
+        const int dg = (k >> dshift) & (ND - 1);
         const int64_t g = (int64_t)L.gbase[dg] + (i - L.lstart[dg]);
-        okey[g] = (uint16_t)(key & rmask);
+        if (!FINAL) okey[g] = (uint16_t)(k & kmask);
         ocol[g] = L.col[i];
         if (oval) oval[g] = L.val[i];
     }
+}
+
+// Single workgroup: pass-C tiles of every bucket (buckets above `cap` entries only).
+__global__ __launch_bounds__(256) void c_tiles(const int *__restrict__ bstart, int B, int cap,
+                                               int *__restrict__ tile_off) {
+    __shared__ int wsum[4];
+    const int per = (B + 255) / 256;
+    const int lo = threadIdx.x * per;
+    int s = 0;
+    for (int i = 0; i < per; ++i) {
+        const int b = lo + i;
+        if (b < B) {
+            const int n = bstart[b + 1] - bstart[b];
+            s += n > cap ? (n + kTile - 1) / kTile : 0;
+        }
+    }
+    int total;
+    int base = block_excl_scan256(s, wsum, total);
+    for (int i = 0; i < per; ++i) {
+        const int b = lo + i;
+        if (b < B) {
+            tile_off[b] = base;
+            const int n = bstart[b + 1] - bstart[b];
+            base += n > cap ? (n + kTile - 1) / kTile : 0;
+        }
+    }
+    if (threadIdx.x == 0) tile_off[B] = total;
 }
 
 // ----------------------------------------------------------------------------- pass C
@@ -528,7 +570,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
                                                    const float *__restrict__ tval,
                                                    const int *__restrict__ bstart, int B, int sb, int N,
                                                    int *__restrict__ rp, int *__restrict__ col,
-                                                   float *__restrict__ val, int cap) {
+                                                   float *__restrict__ val, int cap, int pass_c) {
     extern __shared__ int smem_i[];
     __shared__ int wsum[4];
     const int R = 1 << sb;
@@ -541,6 +583,10 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
     const int Rb = min(R, N - r0);
     const int e0 = bstart[b], e1 = bstart[b + 1];
     const int rmask = R - 1;
+    if (pass_c && e1 - e0 > cap) {  // sorted by the pass-C tiles
+        if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
+        return;
+    }
     if (R <= 256 && e1 - e0 <= cap) {
         // Wave-split ranking: each wavefront counts and ranks a contiguous quarter.
         const int wv = threadIdx.x >> 6, lane = lane_id();
@@ -640,7 +686,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 // ----------------------------------------------------------------------------- launch
 
 // Staging capacity of bucket_sort: the whole workgroup stays within 64 KiB of LDS.
-static int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
+int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
 size_t bucket_sort_lds(int sb) {
     const size_t R = (size_t)1 << sb;
     const size_t counters = R <= 256 ? kWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
@@ -677,18 +723,48 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!with_b) return hipSuccess;
     prof_begin(kKBHist, s);
-    hipLaunchKernelGGL(b_hist, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA, wk.tileB,
-                       p.DA, wk.ghB);
+    hipLaunchKernelGGL(seg_hist<int>, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA,
+                       wk.tileB, p.DA, wk.ghB);
     prof_end(kKBHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScan, s);
-    hipLaunchKernelGGL(b_scan, dim3(p.DA), dim3(256), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart);
+    hipLaunchKernelGGL(seg_scan, dim3(p.DA), dim3(256), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart, 0);
     prof_end(kKBScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
-    hipLaunchKernelGGL(b_scatter, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval, p.sb, p.s2,
-                       wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol, p.weighted ? wk.tval : nullptr);
+    hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval,
+                       p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
+                       p.weighted ? wk.tval : nullptr);
     prof_end(kKBScatter, s);
+    return hipGetLastError();
+}
+
+// Pass C for buckets above the staging capacity (their hub rows would serialize one
+// workgroup): the same segment partition with the row inside the bucket as the digit,
+// straight into the CSR; then bucket_sort for all other buckets.
+template <typename KT>
+static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, int cap, hipStream_t s) {
+    const float *tv = p.weighted ? wk.tval : nullptr;
+    float *ov = p.weighted ? wk.val : nullptr;
+    prof_begin(kKCTiles, s);
+    hipLaunchKernelGGL(c_tiles, dim3(1), dim3(256), 0, s, wk.bstart, p.B, cap, wk.tileC);
+    prof_end(kKCTiles, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    prof_begin(kKCHist, s);
+    hipLaunchKernelGGL(seg_hist<KT>, dim3((unsigned)p.TCcap), dim3(256), 0, s, key, 0, p.sb, wk.bstart, wk.tileC,
+                       p.B, wk.ghC);
+    prof_end(kKCHist, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKCScan, s);
+    hipLaunchKernelGGL(seg_scan, dim3(p.B), dim3(256), 0, s, wk.ghC, p.sb, wk.bstart, wk.tileC, (int)p.Ntot, wk.rp,
+                       1);
+    prof_end(kKCScan, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKCScatter, s);
+    hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(256), 0, s, key, wk.tcol, tv, 0, p.sb,
+                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov);
+    prof_end(kKCScatter, s);
     return hipGetLastError();
 }
 
@@ -698,13 +774,19 @@ hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hip
     const int cap = bucket_stage_cap(p.sb);
     const float *tv = p.weighted ? wk.tval : nullptr;
     float *ov = p.weighted ? wk.val : nullptr;
+    const int pass_c = p.sb <= 8 ? 1 : 0;  // pass C ranks rows as digits of at most 8 bits
+    hipError_t e = hipSuccess;
+    if (pass_c) {
+        e = p.s2 > 0 ? launch_pass_c<uint16_t>(wk.tkey, p, wk, cap, s) : launch_pass_c<int>(wk.akey, p, wk, cap, s);
+        if (e != hipSuccess) return e;
+    }
     prof_begin(kKBucketSort, s);
     if (p.s2 > 0) {
         hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, wk.tkey, wk.tcol, tv, wk.bstart,
-                           p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap);
+                           p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
     } else {
         hipLaunchKernelGGL(bucket_sort<int>, dim3(p.B), dim3(256), lds, s, wk.akey, wk.tcol, tv, wk.bstart, p.B,
-                           p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap);
+                           p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
     }
     prof_end(kKBucketSort, s);
     return hipGetLastError();

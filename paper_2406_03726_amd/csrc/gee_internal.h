@@ -180,6 +180,7 @@ struct Plan {
     int tile = 4096;     // entries per partition tile
     int64_t TA = 1;      // pass A tiles
     int64_t TBcap = 1;   // pass B tiles (upper bound)
+    int64_t TCcap = 1;   // pass C tiles (upper bound; buckets above the staging capacity)
     // embed
     int wpb = 1;         // wavefronts per embed workgroup
     int64_t NWtot = 1;   // embed wavefronts launched (upper bound, all graphs)
@@ -205,6 +206,8 @@ struct Work {
     int *tileB = nullptr;      // [DA + 1] first pass-B tile of each segment
     int *ghB = nullptr;        // [(1 << s2) * TBcap] pass B tile histograms
     int *bstart = nullptr;     // [B + 1]
+    int *tileC = nullptr;      // [B + 1] first pass-C tile of each bucket
+    int *ghC = nullptr;        // [TCcap << sb] pass C tile histograms
     int *akey = nullptr;       // [Vtot] pass A output: row
     uint16_t *tkey = nullptr;  // [Vtot] pass B output: row within bucket
     int *tcol = nullptr;       // [Vtot]
@@ -229,7 +232,7 @@ struct Work {
 // caller's hipEvents on the launch stream right before / after a kernel launch.
 enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
-    kKBScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
+    kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
     kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
@@ -247,6 +250,7 @@ hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *co
 hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 size_t bucket_sort_lds(int sb);
+int bucket_stage_cap(int sb);
 // gee_embed.hip
 // Per-graph entry ranges and wavefront counts from row_ptr (after a CSR build), or
 // from the given entry count M (a single resident CSR, rp_of_union == nullptr).
