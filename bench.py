@@ -286,7 +286,7 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
 # ----------------------------------------------------------------------------- HBM traffic
 
 PROFILES = os.path.join(ROOT, "profiles")
-CALIB_BYTES = 256 << 20  # device-to-device copy that calibrates the byte counters
+CALIB_BYTES = 1 << 30  # device-to-device copy that calibrates the byte counters
 
 
 def source_hash() -> str:
@@ -343,7 +343,7 @@ def write_traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, co
         copies = [v for n, v in rows if "copyBuffer" in n]
         if not copies:
             raise SystemExit(f"no copy dispatch in {path}")
-        calib_kib = max(copies)
+        calib_kib = sum(copies)  # the calibration copy may be split over dispatches; others are tiny
         factor = (CALIB_BYTES / 1024.0) / calib_kib
         mine = [v for n, v in rows if n.split("(")[0].replace("void ", "").split("<")[0].endswith(kernel)]
         if not mine:
@@ -359,7 +359,7 @@ def write_traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, co
     with open(path, "w") as f:
         f.write(f"# HBM traffic of `{kernel}` on `{workload}`\n\n")
         f.write("Two rocprofv3 counter runs of the same command (FETCH_SIZE, then WRITE_SIZE; KiB per\n"
-                "dispatch), each scaled by what the counter reads for a 256 MiB device-to-device copy\n"
+                "dispatch), each scaled by what the counter reads for a 1 GiB device-to-device copy\n"
                 "made in the same run. Commands (from /tmp, TMPDIR=/tmp, on the MI355X box):\n\n")
         f.write("```\n" + commands.strip() + "\n```\n\n")
         f.write("```json\n" + json.dumps(out, indent=1) + "\n```\n")
@@ -371,7 +371,7 @@ def pmc_target(gee, torch, np):
     of the default workload."""
     dev = torch.device("cuda:0")
     a = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
-    b = torch.empty_like(a)
+    b = torch.empty_like(a).fill_(2.0)  # also evicts `a` from the caches before the copy
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
