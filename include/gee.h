@@ -86,7 +86,7 @@ typedef struct {
     int32_t wave_entries;   /* CSR entries per wavefront in the embed kernel (power of 2, 256..16384) */
     int32_t waves_per_block;/* wavefronts per workgroup in the embed kernel (1, 2 or 4) */
     int32_t tile_entries;   /* entries per workgroup tile of the CSR partition passes; this
-                               build supports only 4096 (0 = default) */
+                               build supports only 2048 (0 = default) */
     int32_t bucket_rows_log2; /* rows per CSR sort bucket = 2^this (0 = automatic, else 1..12;
                                  raised to what keeps the bucket count <= 65536) */
 } gee_schedule;

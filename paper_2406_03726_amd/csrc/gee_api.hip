@@ -96,7 +96,7 @@ int check_schedule(const gee_schedule &sc) {
     if (sc.wave_entries && (!is_pow2(sc.wave_entries) || sc.wave_entries < 256 || sc.wave_entries > 16384))
         return GEE_ERR_ARG;
     if (sc.waves_per_block && (sc.waves_per_block < 1 || sc.waves_per_block > 4)) return GEE_ERR_ARG;
-    if (sc.tile_entries && sc.tile_entries != 4096) return GEE_ERR_ARG;
+    if (sc.tile_entries && sc.tile_entries != kPartTile) return GEE_ERR_ARG;
     if (sc.bucket_rows_log2 < 0 || sc.bucket_rows_log2 > kMaxBucketRowsLog2) return GEE_ERR_ARG;
     return GEE_OK;
 }
@@ -192,7 +192,7 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     const int nbB = ilog2_ceil(p.B);
     p.s2 = nbB <= 8 ? 0 : (nbB - 8 > nbB / 2 ? nbB - 8 : nbB / 2);
     p.DA = (int)(((int64_t)p.B + (1 << p.s2) - 1) >> p.s2);
-    p.tile = 4096;
+    p.tile = kPartTile;
     p.TA = (p.Vtot + p.tile - 1) / p.tile;
     if (p.TA < 1) p.TA = 1;
     p.TBcap = p.s2 > 0 ? p.TA + p.DA : 1;

@@ -34,19 +34,24 @@ __global__ __launch_bounds__(256) void class_count_partial(Batch b, int *__restr
     for (int k = threadIdx.x; k < K; k += blockDim.x) part[d.cpart_off + (int64_t)jb * K + k] = hist[k];
 }
 
-// Thread per class (all graphs): the graph's partials in workgroup order.
+// Wavefront per class (all graphs): the lanes add the graph's partials (integers, so the
+// order does not matter), then 1/n_k.
 __global__ __launch_bounds__(256) void class_count_final(Batch b, int Ktot, const int *__restrict__ part,
                                                          int *__restrict__ counts, float *__restrict__ inv_n) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (c >= Ktot) return;
+    const int lane = lane_id();
     const int g = find_graph(b.class_offs, b.G, c);
     const GDesc d = load_desc(b, g);
     const int k = c - d.class_off;
     const int *pp = part + d.cpart_off + k;
     int n = 0;
-    for (int j = 0; j < d.cnt_blocks; ++j) n += pp[(int64_t)j * d.K];
-    counts[c] = n;
-    if (inv_n) inv_n[c] = n > 0 ? 1.0f / (float)n : 0.0f;
+    for (int j = lane; j < d.cnt_blocks; j += 64) n += pp[(int64_t)j * d.K];
+    n = readlane(wave_scan_add(n), 63);
+    if (lane == 0) {
+        counts[c] = n;
+        if (inv_n) inv_n[c] = n > 0 ? 1.0f / (float)n : 0.0f;
+    }
 }
 
 // Host bytes to device memory through kernel arguments: each launch carries one chunk.
@@ -79,8 +84,8 @@ hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     prof_begin(kKCountFinal, s);
-    hipLaunchKernelGGL(class_count_final, dim3((unsigned)((p.Ktot + 255) / 256)), dim3(256), 0, s, b, p.Ktot,
-                       part, counts, inv_n);
+    hipLaunchKernelGGL(class_count_final, dim3((unsigned)((p.Ktot + 3) / 4)), dim3(256), 0, s, b, p.Ktot, part,
+                       counts, inv_n);
     prof_end(kKCountFinal, s);
     return hipGetLastError();
 }

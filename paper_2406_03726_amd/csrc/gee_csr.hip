@@ -13,7 +13,7 @@
 //                                                              a_totals, a_scatter)
 //   pass B  partition each high-digit segment by low digit    (seg_hist, seg_scan,
 //                                                              seg_scatter)
-//   pass C  buckets of at most 4096 entries: one workgroup per bucket, row counts ->
+//   pass C  buckets of at most 2048 entries: one workgroup per bucket, row counts ->
 //           row_ptr, then the entries in row order             (bucket_sort)
 //           larger buckets (they hold hub rows): the segment partition once more with
 //           the row inside the bucket as the digit, over many workgroups (c_tiles,
@@ -21,7 +21,7 @@
 //
 // With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
 //
-// Every partition pass works on tiles of 4096 entries: the tile's entries are ranked
+// Every partition pass works on tiles of 2048 entries: the tile's entries are ranked
 // by digit (stable) and staged in LDS in digit order, then written out so that
 // consecutive threads write consecutive addresses of each digit's run; no pass writes
 // scattered single words. Stable ranks never use global atomics: within a 64-wide
@@ -34,7 +34,7 @@
 
 namespace gee {
 
-constexpr int kTile = 4096;    // entries per partition tile: 16 rounds of 256 threads
+constexpr int kTile = kPartTile;  // entries per partition tile
 constexpr int kRounds = kTile / 256;
 constexpr int kWaves = 4;                 // wavefronts per partition workgroup
 constexpr int kQuarter = kTile / kWaves;  // items per wavefront per tile
@@ -148,15 +148,15 @@ __device__ __forceinline__ bool load_virtual(const Batch &b, int64_t v, int64_t 
 // entry vw + 64 r + lane.
 template <bool VAL>
 struct Quarter {
-    int key[16], col[16];
-    float val[16];
+    int key[kRoundsW], col[kRoundsW];
+    float val[kRoundsW];
     unsigned valid;  // bit r: entry r is a real adjacency entry
 };
 
 template <bool VAL>
 __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
                                              bool &badw) {
-    static_assert(kRoundsW == 16, "Quarter holds 16 rounds");
+    static_assert(kRoundsW <= 16, "Quarter holds at most 16 rounds");
     const int lane = lane_id();
     q.valid = 0;
     if (vw >= V) return;
@@ -166,10 +166,10 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
         // one graph: clamped unconditional loads, then the checks
         const GDesc gd = load_desc(b, g0);
         const bool sym = gd.flags & kSym;
-        int sv[16], dv[16];
-        float wv[16];
+        int sv[kRoundsW], dv[kRoundsW];
+        float wv[kRoundsW];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kRoundsW; ++r) {
             const int64_t lv = min(vw + r * 64 + lane, vhi) - gd.voff;
             const int64_t e = sym ? (lv >> 1) : lv;
             sv[r] = gd.src[e];
@@ -177,7 +177,7 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
             if (VAL) wv[r] = gd.w ? gd.w[e] : 1.0f;
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kRoundsW; ++r) {
             const int64_t v = vw + r * 64 + lane;
             const int side = sym ? (int)((v - gd.voff) & 1) : 0;
             const bool inb = v <= vhi;
@@ -194,7 +194,7 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
         int g = -1;
         GDesc gd;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kRoundsW; ++r) {
             float val = 1.0f;
             const bool ok = load_virtual<VAL>(b, vw + r * 64 + lane, V, g, gd, q.key[r], q.col[r], val, badi, badw);
             if (VAL) q.val[r] = val;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int
     Quarter<false> q;
     load_quarter<false>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int r = 0; r < kRoundsW; ++r)
         if (q.valid >> r & 1u) atomicAdd(&hist[q.key[r] >> shift], 1);
     if (__syncthreads_or(badi) && threadIdx.x == 0) raise_error(status, kErrIndex);
     if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
@@ -355,13 +355,13 @@ __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, 
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int r = 0; r < kRoundsW; ++r)
         if (q.valid >> r & 1u) atomicAdd(&L.cnt[wv][q.key[r] >> shift], 1);
     __syncthreads();
     const int gb = (int)threadIdx.x < D ? seg_start[threadIdx.x] + gh[(int64_t)threadIdx.x * T + t] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kRoundsW; ++r) {
         const bool valid = q.valid >> r & 1u;
         const int digit = valid ? (q.key[r] >> shift) : 0;
         const int pos = wave_rank(L.cnt[wv], digit, valid, nbits);
@@ -495,23 +495,23 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
     const int e0 = s0 + jt * kTile;
     const int e1 = min(e0 + kTile, s0 + nseg);
     const int ew = e0 + wv * kQuarter;
-    int kr[16], cr[16];
-    float vr[16];
+    int kr[kRoundsW], cr[kRoundsW];
+    float vr[kRoundsW];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kRoundsW; ++r) {
         const int ec = min(ew + r * 64 + lane, e1 - 1);
         kr[r] = (int)key[ec];
         cr[r] = col[ec];
         vr[r] = oval ? val[ec] : 1.0f;
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
+    for (int r = 0; r < kRoundsW; ++r)
         if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> dshift) & (ND - 1)], 1);
     __syncthreads();
     const int gb = (int)threadIdx.x < ND ? s0 + seg[(int64_t)threadIdx.x * ntd + jt] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kRoundsW; ++r) {
         const bool valid = ew + r * 64 + lane < e1;
         const int digit = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
         const int pos = wave_rank(L.cnt[wv], digit, valid, dbits);
@@ -596,13 +596,13 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         for (int i = threadIdx.x; i < kWaves * R; i += blockDim.x) cnt[i] = 0;
         __syncthreads();
         const int n = e1 - e0;
-        const int q = (((n + kWaves - 1) / kWaves) + 63) & ~63;  // <= 1024: 16 rounds
+        const int q = (((n + kWaves - 1) / kWaves) + 63) & ~63;  // <= kQuarter: kRoundsW rounds
         const int ew = e0 + min(n, wv * q), ee = e0 + min(n, (wv + 1) * q);
-        int kr[16] = {0}, cr[16] = {0};
-        float vr[16] = {0.0f};
+        int kr[kRoundsW] = {0}, cr[kRoundsW] = {0};
+        float vr[kRoundsW] = {0.0f};
         if (ee > ew) {  // this wavefront has entries: clamped loads stay inside [ew, ee)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < kRoundsW; ++r) {
                 const int ec = min(ew + r * 64 + lane, ee - 1);
                 kr[r] = (int)tkey[ec] & rmask;
                 cr[r] = tcol[ec];
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
             }
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
+        for (int r = 0; r < kRoundsW; ++r)
             if (ew + r * 64 + lane < ee) atomicAdd(&cnt[wv * R + kr[r]], 1);
         __syncthreads();
         const int r = threadIdx.x;
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kRoundsW; ++r) {
             const bool valid = ew + r * 64 + lane < ee;
             const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid, sb);
             if (valid) {

@@ -20,6 +20,10 @@ constexpr int kWave = 64;
 constexpr int kMaxBuckets = 65536;     // CSR buckets: 256 high digits x 256 low digits
 constexpr int kMaxBucketRowsLog2 = 12; // rows per bucket (the last sort pass ranks by row)
 constexpr int kMaxClasses = 128;
+#ifndef GEE_PART_TILE
+#define GEE_PART_TILE 2048
+#endif
+constexpr int kPartTile = GEE_PART_TILE;  // entries per CSR partition tile (4 wavefronts)
 
 // ----------------------------------------------------------------------------- wave ops
 
@@ -177,7 +181,7 @@ struct Plan {
     int32_t B = 1;       // buckets
     int s2 = 0;          // low digit bits (pass B digits = 1 << s2; 0: no pass B)
     int DA = 1;          // pass A digits (high digit = bucket >> s2), <= 256
-    int tile = 4096;     // entries per partition tile
+    int tile = kPartTile;  // entries per partition tile
     int64_t TA = 1;      // pass A tiles
     int64_t TBcap = 1;   // pass B tiles (upper bound)
     int64_t TCcap = 1;   // pass C tiles (upper bound; buckets above the staging capacity)

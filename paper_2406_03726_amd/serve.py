@@ -75,12 +75,15 @@ class _Flight:
 
 class GeeServer:
     def __init__(self, backend: Backend, budget_bytes: int, max_batch: int = 64,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, max_batch_edges: Optional[int] = None):
         if budget_bytes <= 0 or max_batch < 1:
             raise ValueError("budget and batch size must be positive")
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
+        # A batch finishes as a whole: a cap on its edges keeps small requests from
+        # waiting for a large one batched with them (a larger request still runs alone).
+        self.max_batch_edges = max_batch_edges
         self.clock = clock
         self.queue: Deque[Request] = deque()
         self.flights: List[_Flight] = []
@@ -140,6 +143,7 @@ class GeeServer:
                 break
             batch: List[Request] = []
             nbytes = 0
+            edges = 0
             for r in self.queue:
                 if len(batch) >= self.max_batch:
                     break
@@ -147,8 +151,11 @@ class GeeServer:
                     continue
                 if self.in_use + nbytes + r.nbytes > self.budget:
                     break  # FIFO: nothing behind a request that does not fit yet
+                if batch and self.max_batch_edges is not None and edges + r.E > self.max_batch_edges:
+                    break  # the next batch starts with this request
                 batch.append(r)
                 nbytes += r.nbytes
+                edges += r.E
             if not batch:
                 break
             ids = {id(r) for r in batch}

@@ -72,7 +72,7 @@ def test_csr_sbm_small_bit_exact():
 # bucket sizes: 2 rows (10,000 buckets: both partition passes, tiny buckets), 4096 rows
 # (5 buckets of ~48k entries: one partition pass, buckets too large to stage), 128 rows
 # (157 staged buckets, one partition pass)
-@pytest.mark.parametrize("sched", [dict(tile_entries=4096, bucket_rows_log2=1),
+@pytest.mark.parametrize("sched", [dict(tile_entries=2048, bucket_rows_log2=1),
                                    dict(bucket_rows_log2=12),
                                    dict(bucket_rows_log2=7)])
 def test_csr_schedules_bit_exact(sched):
@@ -200,7 +200,7 @@ def test_embed_hub_rows_split_across_wavefronts(we):
 
 @pytest.mark.parametrize("sched", [dict(wave_entries=256, waves_per_block=1),
                                    dict(wave_entries=1024, waves_per_block=2),
-                                   dict(wave_entries=8192, waves_per_block=4, tile_entries=4096)])
+                                   dict(wave_entries=8192, waves_per_block=4, tile_entries=2048)])
 def test_embed_schedules(sched):
     g = powerlaw_10m(N=30_000, E=400_000, K=20, dmax=8000.0)
     _label(f"embed schedule {sched}")

@@ -174,3 +174,17 @@ def test_server_beats_plain_loop_on_simulated_device():
 
     run_plain(plain, embed_one, clock=clk2, sleep=clk2.sleep)
     assert summarize(reqs)["p99_ms"] < summarize(plain)["p99_ms"]
+
+
+def test_edge_cap_splits_batches():
+    clk = Clock()
+    be = FakeBackend(clk, slots=1, launch_cost=1e-3)
+    reqs = _reqs(20, seed=6, rate=1e6)
+    cap = 2500
+    srv = GeeServer(be, 10 ** 9, max_batch=16, clock=clk, max_batch_edges=cap)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    E = {r.rid: r.E for r in reqs}
+    for b in be.launched:
+        assert len(b) == 1 or sum(E[i] for i in b) <= cap
+    flat = [rid for b in be.launched for rid in b]
+    assert flat == sorted(flat) and len(flat) == 20
