@@ -91,6 +91,27 @@ __device__ __forceinline__ int block_excl_scan256(int v, int *wsum, int &total) 
     return base + x - v;
 }
 
+// Exclusive scan of one int per thread over a workgroup of NT threads (DPP inside each
+// wavefront, then the wavefront totals); `total` is the sum. wsum needs NT/64 ints.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total) {
+    constexpr int NWV = NT / 64;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int x = wave_scan_add(v);
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) {
+        const int t = wsum[i];
+        base += i < wv ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
 // In-place exclusive scan of a[0..n) in LDS (n <= 4096), 256 threads; returns total.
 __device__ int block_excl_scan_lds(int *a, int n, int *wsum) {
     const int per = (n + 255) / 256;
@@ -224,12 +245,12 @@ __global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int
 
 // One workgroup per digit d: exclusive scan of the row gh[d*T .. d*T+T) in place;
 // tot[d] = its sum.
-__global__ __launch_bounds__(256) void digit_scan(int *__restrict__ gh, int64_t T, int *__restrict__ tot) {
-    __shared__ int wsum[4];
+__global__ __launch_bounds__(1024) void digit_scan(int *__restrict__ gh, int64_t T, int *__restrict__ tot) {
+    __shared__ int wsum[16];
     int *row = gh + (int64_t)blockIdx.x * T;
     int carry = 0;
     constexpr int IPT = 8;
-    for (int64_t c = 0; c < T; c += 256 * IPT) {
+    for (int64_t c = 0; c < T; c += 1024 * IPT) {
         int vals[IPT];
         int s = 0;
         const int64_t lo = c + (int64_t)threadIdx.x * IPT;
@@ -239,7 +260,7 @@ __global__ __launch_bounds__(256) void digit_scan(int *__restrict__ gh, int64_t 
             s += vals[i];
         }
         int total;
-        int base = block_excl_scan256(s, wsum, total) + carry;
+        int base = block_excl_scan<1024>(s, wsum, total) + carry;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if (lo + i < T) row[lo + i] = base;
@@ -433,10 +454,10 @@ __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int 
 // inside the segment), and starts[(d << dbits) + digit] = the first position of each
 // digit (for indices below `limit`). With skip_untiled, segments without tiles are left
 // alone (pass C: those buckets are sorted whole by bucket_sort).
-__global__ __launch_bounds__(256) void seg_scan(int *__restrict__ gh, int dbits, const int *__restrict__ seg_start,
-                                                const int *__restrict__ tile_off, int limit,
-                                                int *__restrict__ starts, int skip_untiled) {
-    __shared__ int wsum[4];
+__global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits, const int *__restrict__ seg_start,
+                                                 const int *__restrict__ tile_off, int limit,
+                                                 int *__restrict__ starts, int skip_untiled) {
+    __shared__ int wsum[16];
     const int d = blockIdx.x;
     const int ntd = tile_off[d + 1] - tile_off[d];
     if (skip_untiled && ntd == 0) return;
@@ -445,7 +466,7 @@ __global__ __launch_bounds__(256) void seg_scan(int *__restrict__ gh, int dbits,
     int *seg = gh + ((int64_t)tile_off[d] << dbits);
     int carry = 0;
     constexpr int IPT = 8;
-    for (int64_t c = 0; c < len; c += 256 * IPT) {
+    for (int64_t c = 0; c < len; c += 1024 * IPT) {
         int vals[IPT];
         int s = 0;
         const int64_t lo = c + (int64_t)threadIdx.x * IPT;
@@ -455,7 +476,7 @@ __global__ __launch_bounds__(256) void seg_scan(int *__restrict__ gh, int dbits,
             s += vals[i];
         }
         int total;
-        int base = block_excl_scan256(s, wsum, total) + carry;
+        int base = block_excl_scan<1024>(s, wsum, total) + carry;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
             if (lo + i < len) seg[lo + i] = base;
@@ -533,10 +554,10 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
 }
 
 // Single workgroup: pass-C tiles of every bucket (buckets above `cap` entries only).
-__global__ __launch_bounds__(256) void c_tiles(const int *__restrict__ bstart, int B, int cap,
-                                               int *__restrict__ tile_off) {
-    __shared__ int wsum[4];
-    const int per = (B + 255) / 256;
+__global__ __launch_bounds__(1024) void c_tiles(const int *__restrict__ bstart, int B, int cap,
+                                                int *__restrict__ tile_off) {
+    __shared__ int wsum[16];
+    const int per = (B + 1023) / 1024;
     const int lo = threadIdx.x * per;
     int s = 0;
     for (int i = 0; i < per; ++i) {
@@ -547,7 +568,7 @@ __global__ __launch_bounds__(256) void c_tiles(const int *__restrict__ bstart, i
         }
     }
     int total;
-    int base = block_excl_scan256(s, wsum, total);
+    int base = block_excl_scan<1024>(s, wsum, total);
     for (int i = 0; i < per; ++i) {
         const int b = lo + i;
         if (b < B) {
@@ -708,7 +729,7 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScan, s);
-    hipLaunchKernelGGL(digit_scan, dim3(p.DA), dim3(256), 0, s, wk.ghA, p.TA, wk.totA);
+    hipLaunchKernelGGL(digit_scan, dim3(p.DA), dim3(1024), 0, s, wk.ghA, p.TA, wk.totA);
     prof_end(kKAScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKATotals, s);
@@ -728,7 +749,7 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_end(kKBHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScan, s);
-    hipLaunchKernelGGL(seg_scan, dim3(p.DA), dim3(256), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart, 0);
+    hipLaunchKernelGGL(seg_scan, dim3(p.DA), dim3(1024), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart, 0);
     prof_end(kKBScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
@@ -747,7 +768,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     const float *tv = p.weighted ? wk.tval : nullptr;
     float *ov = p.weighted ? wk.val : nullptr;
     prof_begin(kKCTiles, s);
-    hipLaunchKernelGGL(c_tiles, dim3(1), dim3(256), 0, s, wk.bstart, p.B, cap, wk.tileC);
+    hipLaunchKernelGGL(c_tiles, dim3(1), dim3(1024), 0, s, wk.bstart, p.B, cap, wk.tileC);
     prof_end(kKCTiles, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -757,7 +778,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     prof_end(kKCHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScan, s);
-    hipLaunchKernelGGL(seg_scan, dim3(p.B), dim3(256), 0, s, wk.ghC, p.sb, wk.bstart, wk.tileC, (int)p.Ntot, wk.rp,
+    hipLaunchKernelGGL(seg_scan, dim3(p.B), dim3(1024), 0, s, wk.ghC, p.sb, wk.bstart, wk.tileC, (int)p.Ntot, wk.rp,
                        1);
     prof_end(kKCScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
