@@ -344,7 +344,7 @@ hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned
     if (e == hipSuccess) e = launch_graph_meta(b, wk.rp, 0, s);
     const float *val = p.weighted ? wk.val : nullptr;
     if (e == hipSuccess) e = launch_node_prep(b, p, wk.rp, val, wk, st, s);
-    if (e == hipSuccess) e = launch_embed(b, p, wk.rp, wk.col, val, wk, st, s);
+    if (e == hipSuccess) e = launch_embed(b, p, wk.rp, wk.col, val, p.Vtot, wk, st, s);
     return e;
 }
 
@@ -786,7 +786,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, nullptr, (int)M, s);
     if (e == hipSuccess) e = launch_node_prep(b, p, row_ptr, val, wk, st, s);
-    if (e == hipSuccess) e = launch_embed(b, p, row_ptr, col, val, wk, st, s);
+    if (e == hipSuccess) e = launch_embed(b, p, row_ptr, col, val, M, wk, st, s);
     return hip_status(e);
 }
 

@@ -21,22 +21,24 @@
 //                  wavefronts, then c_i and s_i; degree_fixup finishes cut rows.
 //   * fill_empty   rows without entries (zero, or the diagonal term alone).
 //   * embed_rows   wavefront w of a graph processes that graph's CSR entries
-//                  [w*WE, (w+1)*WE) in windows of 64, so every wavefront does the same
-//                  work whatever the degree distribution. Rows are found without
-//                  row_ptr lookups: a byte per entry holds the row step from the previous
-//                  entry (0 inside a row; an escape value for steps >= 255), and a wave
-//                  prefix sum turns the steps into row ids. The wavefront works in
-//                  batches of 2 windows; the col/val/step loads of batch k+2 and the
-//                  gathers of batch k+1 ({c_j, y_j} by column, {c_i, y_i, s_i} by row)
-//                  are in flight while batch k is processed, and nothing loaded is
-//                  consumed in the batch that loads it, so the memory pipeline never
-//                  drains inside a batch. Rows get slots of an LDS ring acc[slot][class];
-//                  a starting row first receives its diagonal term, then every lane adds
-//                  its entry into acc[slot(row)][y_j] with an LDS float atomic, and the
-//                  LDS applies lanes that hit the same word one after another in a fixed
-//                  order, so results are bitwise reproducible. Rows ending in the
-//                  wavefront are finished there (s_i, correlation) and stored with
-//                  coalesced writes; rows cut by wavefront boundaries leave raw partials.
+//                  [w*WE, (w+1)*WE) in windows of 256: lane l holds 4 consecutive
+//                  entries, read with 16-byte loads. Every wavefront does the same work
+//                  whatever the degree distribution. Rows are found without row_ptr
+//                  lookups: a byte per entry holds the row step from the previous entry
+//                  (0 inside a row; an escape value for steps >= 255), and one wave prefix
+//                  sum per window turns the steps into row ids and counts the row starts.
+//                  The loads of window k+2 and the gathers of window k+1 ({c_j, y_j} by
+//                  column; {c_i, y_i}, s_i by row for entries that start a row) are in
+//                  flight while window k is added, and nothing loaded is consumed in the
+//                  window that loads it, so the memory pipeline never drains. Rows get
+//                  slots of an LDS ring acc[slot][class] in the order they start; a
+//                  starting row first receives its diagonal term, then every entry adds
+//                  into acc[slot(row)][y_j] with an LDS float atomic, and the LDS applies
+//                  lanes that hit the same word one after another in a fixed order, so
+//                  results are bitwise reproducible. Rows ending in the wavefront are
+//                  finished there (s_i, correlation) when the ring fills or the wavefront
+//                  ends, and stored with coalesced writes; rows cut by wavefront
+//                  boundaries leave raw partials.
 //   * embed_fixup  adds the partials of each cut row in wavefront order and finishes it.
 #include "gee_internal.h"
 
@@ -46,12 +48,13 @@ namespace gee {
 
 constexpr int kStepEsc = 255;  // row-step byte meaning "look the row up in row_ptr"
 constexpr int BW = 4;          // windows per pipeline batch (degree_rows)
-constexpr int EBW = 2;         // windows per pipeline batch (embed_rows)
+constexpr int EPL = 4;          // consecutive CSR entries per lane (embed_rows)
+constexpr int EWIN = 64 * EPL;  // entries per embed window
 
 // Floats per slot of the embed ring: K rounded up to a multiple of 4 (16-byte rows).
 __host__ __device__ constexpr int ring_stride(int K) { return (K + 3) & ~3; }
-// LDS floats of one embed wavefront: the ring [64][ring_stride(K)] and three 64-entry
-// slot tables.
+// LDS floats of one embed wavefront: the ring [64][ring_stride(K)] and the 64 slots'
+// {row, s_i} and finishing factors.
 __host__ __device__ constexpr int embed_lds_floats(int K) { return 64 * ring_stride(K) + 3 * 64; }
 
 // Graph and local index of embed wavefront w; false if w has no work.
@@ -62,6 +65,13 @@ __device__ __forceinline__ bool wave_graph(const Batch &b, int w, GDesc &d, GMet
     if (lw < 0 || lw >= d.NWcap) return false;
     m = b.gm[g];
     return lw < m.NW;
+}
+
+// Per-node table entry {c_i, y_i}. A node without a known label has c_i = 0 and is filed
+// under class 0, so every class index read from the table lies in [0, K) and adding c_i
+// there changes nothing.
+__device__ __forceinline__ float2 node_info(float c, int y) {
+    return make_float2(c, __int_as_float(y >= 0 ? y : 0));
 }
 
 // ----------------------------------------------------------------------------- per graph
@@ -117,16 +127,18 @@ __global__ __launch_bounds__(256) void node_rows(Batch b, int Ntot, const int *_
             bad = true;
         const bool lap = d.flags & kLap, diag = d.flags & kDiag;
         const bool skip = d.weighted && lap && hi > lo;
+        int y = d.labels[rl];
+        if (y < 0 || y >= d.K) y = -1;
         if (!skip) {
-            int y = d.labels[rl];
-            if (y < 0 || y >= d.K) y = -1;
             float s = 1.0f;
             if (lap) {
                 const float dg = (float)max(hi - lo, 0) + (diag ? 1.0f : 0.0f);
                 s = dg > 0.0f ? 1.0f / sqrtf(dg) : 0.0f;
                 srow[r] = s;
             }
-            info[r] = make_float2(y >= 0 ? s * inv_n[d.class_off + y] : 0.0f, __int_as_float(y));
+            info[r] = node_info(y >= 0 ? s * inv_n[d.class_off + y] : 0.0f, y);
+        } else {
+            info[r] = node_info(0.0f, y);  // c_i follows from the weighted degree
         }
         if (hi > lo && !bad) {
             // rows back to the previous non-empty row of the graph (row -1 before row 0)
@@ -181,7 +193,7 @@ __device__ __forceinline__ void finish_node(int r, float d, int y, float inv_n_y
     const float dd = d + (diag ? 1.0f : 0.0f);
     const float s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
     srow[r] = s;
-    info[r] = make_float2(y >= 0 ? s * inv_n_y : 0.0f, __int_as_float(y));
+    info[r] = node_info(y >= 0 ? s * inv_n_y : 0.0f, y);
 }
 
 // Weighted degrees d_i = sum of the row's values, as segmented sums over the same
@@ -382,9 +394,50 @@ __device__ __forceinline__ float row_factor(float s, float ss, bool cor) {
 
 // ----------------------------------------------------------------------------- main kernel
 
+// Buffer resource over `bytes` bytes at p (gfx9 layout: raw, stride 0). Loads past the
+// end return 0 instead of touching memory; offsets are 32-bit.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, int64_t bytes) {
+    const int64_t n = bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(uint32_t)n, 0x00020000);
+}
+__device__ __forceinline__ int4 buf_i4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+// One window of a wavefront as loaded: lane l holds entries p + 4l .. p + 4l + 3.
+struct WinRaw {
+    int4 c;
+    float4 v;
+    unsigned d;  // the four step bytes
+};
+// A window ready to be added: weights, gathered {c_j, y_j} by column, rows, the running
+// count of row starts, and for starting entries {c_i, y_i} and s_i of their row.
+struct WinPrep {
+    float v[EPL];
+    float2 f[EPL];
+    int r[EPL], n[EPL];
+    int stm;  // bit j: entry j starts a row
+    float2 q[EPL];
+    float s[EPL];
+    int nnew;   // row starts in the window
+    int rlast;  // row of the window's last entry
+};
+
 template <bool WEIGHTED>
 __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict__ rp, const int *__restrict__ col,
-                                                  const float *__restrict__ val,
+                                                  const float *__restrict__ val, int64_t n_entries,
                                                   const uint8_t *__restrict__ rstep,
                                                   const float2 *__restrict__ info,
                                                   const float *__restrict__ srow,
@@ -393,7 +446,8 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
                                                   int *__restrict__ split, unsigned *status) {
     extern __shared__ float smem_f[];
     const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
+    // wavefront-uniform (so descriptors, sizes and buffer resources live in SGPRs)
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = blockDim.x >> 6;
     const int w = blockIdx.x * wpb + wib;
     GDesc gd;
@@ -409,20 +463,23 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     float *headw = headp + gd.part_off + (int64_t)lw * K;
     float *tailw = tailp + gd.part_off + (int64_t)lw * K;
 
-    // per wavefront: the ring acc[64 slots][KP] and per-slot row, s_i and finishing factor
+    // per wavefront: the ring acc[64 slots][KP], per slot {row, s_i} and finishing factor
     float *acc = smem_f + (size_t)wib * lds_floats;
-    int *slot_row = reinterpret_cast<int *>(acc + 64 * KP);
-    float *slot_s = reinterpret_cast<float *>(slot_row + 64);
-    float *slot_f = slot_s + 64;
-    for (int k = 0; k < KP; ++k) acc[lane * KP + k] = 0.0f;
+    int2 *slot_meta = reinterpret_cast<int2 *>(acc + 64 * KP);
+    float *slot_f = reinterpret_cast<float *>(slot_meta + 64);
+    {
+        float4 *acc4 = reinterpret_cast<float4 *>(acc);
+        for (int i = lane; i < 16 * KP; i += 64) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     // Finished rows stay in their ring slots ("pending") until drain() stores them:
     // slots [pend_first, pend_first + npend) in ring order, just behind the open row.
+    // Draining only when the ring is full, and at the end, lets one drain serve many rows
+    // (its fixed cost, the lane-per-row norm pass, is paid per drain, not per row).
     int npend = 0, pend_first = 0;
 
     const int E_end = gm.ent_off + gm.M;
     const int a = gm.ent_off + lw * gd.WE;
     const int b_ = min(a + gd.WE, E_end);
-    const int last = b_ - 1;
     const int row_a = min(max(wrow[w], node_off), node_off + N - 1);
     // entry a continues a row begun before the wavefront / entry b continues the last row
     const bool head = __builtin_amdgcn_readfirstlane(rstep[a]) == 0;
@@ -430,7 +487,7 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     const bool cont_end = b_ < E_end && __builtin_amdgcn_readfirstlane(rstep[min(b_, E_end - 1)]) == 0;
     int cur_row = head ? row_a : -1;
     int cur_slot = 63;
-    if (lane == 0) slot_row[63] = cur_row;
+    if (lane == 0) slot_meta[63] = make_int2(cur_row, __float_as_int(1.0f));
     bool cont = false;
     // this lane's (row, class) offset in the flat finishing pass, and its step per pass
     const int j0 = lane / K, k0 = lane - j0 * K;
@@ -438,13 +495,18 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
 
     // Finish the pending rows and store them. First the factor of every pending row (one
     // lane per row: its sums read back with 16-byte LDS loads for the 2-norm), then a flat
-    // pass over (row, class) in which consecutive lanes write consecutive words of Z. The
-    // head row goes out raw. This code holds the only global stores and reads nothing
-    // loaded from global memory, so it never waits for the loads in flight.
+    // pass over (row, class) in which consecutive lanes read (and clear) consecutive
+    // classes and write consecutive words of Z. The head row goes out raw. This code holds the only global stores and reads nothing loaded from global
+    // memory, so it never waits for the loads in flight. Z is written with non-temporal
+    // stores: it is not read again here, and keeping it out of the L2 leaves room for the
+    // gathered per-node table.
     auto drain = [&]() {
         wave_lds_fence();
+        float fac = 0.0f;
+        int rrow = -1;
         if (lane < npend) {
             const int sl = (pend_first + lane) & 63;
+            const int2 m = slot_meta[sl];
             float ss = 0.0f;
             if (cor) {
                 const float4 *a4 = reinterpret_cast<const float4 *>(acc + sl * KP);
@@ -453,9 +515,11 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
                     ss += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
                 }
             }
-            const float f = row_factor(lap ? slot_s[sl] : 1.0f, ss, cor);
-            slot_f[sl] = slot_row[sl] == head_row ? 1.0f : f;
+            rrow = m.x;
+            fac = rrow == head_row ? 1.0f : row_factor(lap ? __int_as_float(m.y) : 1.0f, ss, cor);
         }
+        // flat pass over (row, class): consecutive lanes write consecutive words of Z
+        if (lane < npend) slot_f[(pend_first + lane) & 63] = fac;
         wave_lds_fence();
         const int F = npend * K;
         int jj = j0, kk = k0;
@@ -464,13 +528,13 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
             const int sl = (pend_first + jj) & 63;
             const int ai = sl * KP + kk;
             const float v = acc[ai];
-            const int r = slot_row[sl];
-            const float fac = slot_f[sl];
+            const int r = slot_meta[sl].x;
+            const float fc = slot_f[sl];
             if (has) {
                 acc[ai] = 0.0f;
                 if (r >= node_off && r < node_off + N) {
                     float *dst = r == head_row ? headw + kk : Z + (int64_t)(r - node_off) * K + kk;
-                    *dst = v * fac;
+                    __builtin_nontemporal_store(v * fc, dst);
                 }
             }
             kk += r64;
@@ -484,131 +548,225 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         wave_lds_fence();
     };
 
-    // Loads are unconditional (clamped address, value masked afterwards) and are only
-    // consumed in a later batch.
-    const int nwin = (b_ - a + 63) >> 6;
-    auto ld_col = [&](int e) { const int v = col[min(e, last)]; return e < b_ ? v : -1; };
-    auto ld_val = [&](int e) { return WEIGHTED ? val[min(e, last)] : 1.0f; };
-    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b_ ? v : 0; };
-    auto gather_col = [&](int j) {
-        const float2 f = info[min(max(j, node_off), node_off + N - 1)];
-        return (unsigned)(j - node_off) < (unsigned)N ? f : make_float2(0.0f, __int_as_float(-1));
-    };
-    auto gather_row = [&](int r, float2 &q, float &sv) {
-        const int rr = min(max(r, node_off), node_off + N - 1);
-        q = info[rr];
-        sv = lap ? srow[rr] : 1.0f;
-    };
-    int cn1[EBW], cn2[EBW], dc[EBW], dn1[EBW], dn2[EBW], rc[EBW], rn1[EBW];
-    float vc[EBW], vn1[EBW], vn2[EBW], sc[EBW], sn1[EBW];
-    float2 fc[EBW], fn1[EBW], qc[EBW], qn1[EBW];  // f: {c_j, y_j} by column; q: {c_i, y_i} by row
-    bool bad = false;
-    int base;
-    int c0[EBW];
-#pragma unroll
-    for (int u = 0; u < EBW; ++u) {
-        const int e0 = a + u * 64 + lane;
-        c0[u] = ld_col(e0);
-        vc[u] = ld_val(e0);
-        dc[u] = ld_step(e0);
-    }
-#pragma unroll
-    for (int u = 0; u < EBW; ++u) {
-        const int e1 = a + (EBW + u) * 64 + lane;
-        cn1[u] = ld_col(e1);
-        vn1[u] = ld_val(e1);
-        dn1[u] = ld_step(e1);
-    }
-#pragma unroll
-    for (int u = 0; u < EBW; ++u) {
-        bad |= a + u * 64 + lane < b_ && (unsigned)(c0[u] - node_off) >= (unsigned)N;
-        fc[u] = gather_col(c0[u]);
-    }
-    base = row_a;
-#pragma unroll
-    for (int u = 0; u < EBW; ++u) {
-        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rpg, N, node_off);
-        base = readlane(rc[u], 63);
-        gather_row(rc[u], qc[u], sc[u]);
-    }
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);  // lanes <= this one
+    // Streams over the wavefront's entries and the gathered per-node tables. Offsets are
+    // relative to entry a; a window wholly inside the arrays is read with 16-byte loads,
+    // the others entry by entry (past the end the loads return 0).
+    const __amdgpu_buffer_rsrc_t r_col = buffer_rsrc(col + a, (n_entries - a) * 4);
+    const __amdgpu_buffer_rsrc_t r_val = buffer_rsrc(WEIGHTED ? (const void *)(val + a) : (const void *)(col + a), (n_entries - a) * 4);
+    const __amdgpu_buffer_rsrc_t r_stp = buffer_rsrc(rstep + a, n_entries - a);
+    const __amdgpu_buffer_rsrc_t r_inf = buffer_rsrc(info + node_off, (int64_t)N * 8);
+    const __amdgpu_buffer_rsrc_t r_srw = buffer_rsrc(srow + node_off, (int64_t)N * 4);
+    const int nwin = (b_ - a + EWIN - 1) / EWIN;
 
-    for (int i0 = 0; i0 < nwin; i0 += EBW) {
-        // Issue col/val/steps of batch k+2 first, then the rows and gathers of batch k+1
-        // (which need the col/steps of batch k+1, loaded one iteration earlier). The
-        // memory counter retires in issue order, so waiting for those col/steps here
-        // leaves the gathers of batch k, issued after them, in flight.
-#pragma unroll
-        for (int u = 0; u < EBW; ++u) {
-            const int e2 = a + (i0 + 2 * EBW + u) * 64 + lane;
-            cn2[u] = ld_col(e2);
-            vn2[u] = ld_val(e2);
-            dn2[u] = ld_step(e2);
+    auto load_win = [&](int i, WinRaw &R) {
+        const uint32_t o = (uint32_t)(i * EWIN + EPL * lane);
+        if ((int64_t)a + (int64_t)(i + 1) * EWIN <= n_entries) {
+            R.c = buf_i4(r_col, 4 * o);
+            if (WEIGHTED) R.v = buf_f4(r_val, 4 * o);
+            R.d = buf_u32(r_stp, o);
+        } else {
+            R.c = make_int4((int)buf_u32(r_col, 4 * o), (int)buf_u32(r_col, 4 * o + 4),
+                            (int)buf_u32(r_col, 4 * o + 8), (int)buf_u32(r_col, 4 * o + 12));
+            if (WEIGHTED)
+                R.v = make_float4(__uint_as_float(buf_u32(r_val, 4 * o)), __uint_as_float(buf_u32(r_val, 4 * o + 4)),
+                                  __uint_as_float(buf_u32(r_val, 4 * o + 8)),
+                                  __uint_as_float(buf_u32(r_val, 4 * o + 12)));
+            R.d = buf_u8(r_stp, o) | (buf_u8(r_stp, o + 1) << 8) | (buf_u8(r_stp, o + 2) << 16) |
+                  (buf_u8(r_stp, o + 3) << 24);
         }
+    };
+
+    bool bad = false;
+    int base = row_a;  // row of the last entry of the windows prepared so far
+
+    // Rows, row-start counts and gathers of window i. Entries past b are masked: no step,
+    // no start, a column whose gather returns 0 and a weight of 0, so they add nothing.
+    auto prep_win = [&](int i, const WinRaw &R, WinPrep &P) {
+        const int p = a + i * EWIN;
+        const int e0 = p + EPL * lane;
+        int c[EPL] = {R.c.x, R.c.y, R.c.z, R.c.w};
+        float v[EPL] = {R.v.x, R.v.y, R.v.z, R.v.w};
+        unsigned d = R.d;
+        unsigned u[EPL];
 #pragma unroll
-        for (int u = 0; u < EBW; ++u) {
-            const int e1 = a + (i0 + EBW + u) * 64 + lane;
-            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + EBW + u) * 64, rpg, N, node_off);
-            base = readlane(rn1[u], 63);
-            bad |= e1 < b_ && (unsigned)(cn1[u] - node_off) >= (unsigned)N;
-            fn1[u] = gather_col(cn1[u]);
-            gather_row(rn1[u], qn1[u], sn1[u]);
-        }
-        // process batch k
+        for (int j = 0; j < EPL; ++j) u[j] = (unsigned)(c[j] - node_off);
+        if (p + EWIN <= b_) {
 #pragma unroll
-        for (int u = 0; u < EBW; ++u) {
-            const int i = i0 + u;
-            if (i >= nwin) break;
-            const int p = a + (i << 6);
-            const int nvalid = min(64, b_ - p);
-            const bool valid = lane < nvalid;
-            const int y = __float_as_int(fc[u].y);
-            const float x = vc[u] * fc[u].x;
-            const int nxt = (u + 1 < EBW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
-            cont = (p + nvalid < b_) ? (nxt == 0) : cont_end;
-            const bool start = valid && dc[u] != 0;
-            const uint64_t sm = ballot(start);
-            const int nnew = __popcll(sm);
-            // the open row and the new rows need ring slots next to the pending ones
-            if (npend + 1 + nnew > 64) drain();
-            const int slot = (cur_slot + __popcll(sm & le)) & 63;
-            // A starting row gets its slot and, with augmentation, its diagonal term c_i
-            // before any entry. Lanes with equal (row, class) add to the same LDS word;
-            // the LDS applies them one after another in a fixed order, so the sums are
-            // reproducible.
-            if (start) {
-                slot_row[slot] = rc[u];
-                slot_s[slot] = sc[u];
-                const int yi = __float_as_int(qc[u].y);
-                if (diag && yi >= 0) atomicAdd(&acc[slot * KP + yi], qc[u].x);
+            for (int j = 0; j < EPL; ++j) bad |= u[j] >= (unsigned)N;
+        } else {
+            const int nb = min(max(b_ - e0, 0), EPL);
+            d = nb >= EPL ? d : (d & ((1u << (8 * nb)) - 1u));
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) {
+                if (j < nb) {
+                    bad |= u[j] >= (unsigned)N;
+                } else {
+                    u[j] = 0xFFFFFFFFu;
+                    v[j] = 0.0f;
+                }
             }
-            if (valid && y >= 0) atomicAdd(&acc[slot * KP + y], x);
-            // rows ended in this window: from lane 0's row to the last lane's row, the
-            // latter only if the next entry starts a new row
-            const int first_slot = (sm & 1ull) ? (cur_slot + 1) & 63 : cur_slot;
-            const int slot_last = (cur_slot + nnew) & 63;
-            const int nseg = ((slot_last - first_slot) & 63) + 1;
-            const int nend = cont ? nseg - 1 : nseg;
-            if (nend > 0) {
-                if (npend == 0) pend_first = first_slot;
-                npend += nend;
-            }
-            cur_row = nnew ? readlane(rc[u], 63 - __clzll(sm)) : cur_row;
-            cur_slot = slot_last;
         }
-        drain();
+        // steps: the wavefront's first entry sits in row_a whatever its step says; an
+        // escape step counts as a start and its row is looked up below
+        int sp[EPL], stp[EPL];
+        int stm = 0, escm = 0;
 #pragma unroll
-        for (int u = 0; u < EBW; ++u) {
-            vc[u] = vn1[u];
-            dc[u] = dn1[u];
-            rc[u] = rn1[u];
-            fc[u] = fn1[u];
-            qc[u] = qn1[u];
-            sc[u] = sn1[u];
-            cn1[u] = cn2[u];
-            vn1[u] = vn2[u];
-            dn1[u] = dn2[u];
+        for (int j = 0; j < EPL; ++j) {
+            const int dj = (int)((d >> (8 * j)) & 0xFFu);
+            const bool first = (j == 0) && i == 0 && lane == 0;
+            stm |= (dj != 0) << j;
+            const bool esc = dj == kStepEsc && !first;
+            escm |= esc << j;
+            sp[j] = (esc || first) ? 0 : dj;
         }
+        int rs = 0, cs = 0;
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            rs += sp[j];
+            cs += (stm >> j) & 1;
+            sp[j] = rs;
+            stp[j] = cs;
+        }
+        // one scan for both: row steps in the low 20 bits, starts above
+        const int T = rs | (cs << 20);
+        const int X = wave_scan_add(T);
+        const int Xe = X - T;
+        const int rb = base + (Xe & 0xFFFFF), nb0 = Xe >> 20;
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            P.r[j] = rb + sp[j];
+            P.n[j] = nb0 + stp[j];
+        }
+        uint64_t em = ballot(escm != 0);
+        if (em) {
+            // rare: a run of >= 254 empty rows. Each escaped entry's row comes from row_ptr,
+            // then every later entry of the window moves by the difference, in entry order.
+            int ar[EPL];
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) ar[j] = ((escm >> j) & 1) ? row_of_entry(rpg, N, e0 + j) + node_off : 0;
+            while (em) {
+                const int L = __builtin_ctzll(em);
+                em &= em - 1;
+                const int mL = readlane(escm, L);
+#pragma unroll
+                for (int j = 0; j < EPL; ++j) {
+                    if (!((mL >> j) & 1)) continue;
+                    const int delta = readlane(ar[j], L) - readlane(P.r[j], L);
+#pragma unroll
+                    for (int jj = 0; jj < EPL; ++jj)
+                        if (lane > L || (lane == L && jj >= j)) P.r[jj] += delta;
+                }
+            }
+        }
+        P.stm = stm;
+        P.nnew = readlane(X, 63) >> 20;
+        P.rlast = readlane(P.r[EPL - 1], 63);
+        base = P.rlast;
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            P.v[j] = v[j];
+            P.f[j] = buf_f2(r_inf, u[j] << 3);
+        }
+        if (diag || lap) {
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) {
+                if ((stm >> j) & 1) {
+                    const uint32_t ri = (uint32_t)(P.r[j] - node_off);
+                    if (diag) P.q[j] = buf_f2(r_inf, ri << 3);
+                    if (lap) P.s[j] = __uint_as_float(buf_u32(r_srw, ri << 2));
+                }
+            }
+        }
+    };
+
+    // Adds the entries of lanes [lo, hi) of a prepared window; n0 = row starts before
+    // lane lo. A starting row first gets its slot, s_i and diagonal term c_i, then every
+    // entry adds into acc[slot(row)][y_j] with an LDS float atomic; the LDS applies lanes
+    // that hit the same word one after another in a fixed order, so the sums are
+    // reproducible. Then the rows that ended become pending.
+    auto add_lanes = [&](const WinPrep &P, int lo, int hi, int n0, int nn, bool st0, bool cnt) {
+        if (npend + 1 + nn > 64) drain();
+        if (lane >= lo && lane < hi) {
+            int sl[EPL];
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) sl[j] = (cur_slot + P.n[j] - n0) & 63;
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) {
+                if ((P.stm >> j) & 1) {
+                    slot_meta[sl[j]] = make_int2(P.r[j], __float_as_int(lap ? P.s[j] : 1.0f));
+                    // the slot is clear and no entry of the row has been added yet
+                    if (diag) acc[sl[j] * KP + __float_as_int(P.q[j].y)] = P.q[j].x;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) {
+                const float x = WEIGHTED ? P.v[j] * P.f[j].x : P.f[j].x;
+                atomicAdd(&acc[sl[j] * KP + __float_as_int(P.f[j].y)], x);
+            }
+        }
+        // segments of this range: the open row unless the range starts a row, then the
+        // new rows; all but the last end here, the last unless the next entry continues it
+        const int first_slot = st0 ? (cur_slot + 1) & 63 : cur_slot;
+        const int nseg = nn + (st0 ? 0 : 1);
+        const int nend = cnt ? nseg - 1 : nseg;
+        if (nend > 0) {
+            if (npend == 0) pend_first = first_slot;
+            npend += nend;
+        }
+        cur_slot = (cur_slot + nn) & 63;
+    };
+
+    // Whether the entry at index e (first entry of lane L of the prepared window P, or
+    // b or later) continues the row of the entry before it.
+    auto continues = [&](int e, const WinPrep &P, int L) {
+        return e >= b_ ? cont_end : !(readlane(P.stm, L) & 1);
+    };
+
+    auto process = [&](int i, const WinPrep &P, const WinPrep &Pn) {
+        const int p = a + i * EWIN;
+        const bool st0 = readlane(P.stm, 0) & 1;
+        const bool cw = continues(p + EWIN, Pn, 0);
+        if (P.nnew + (st0 ? 0 : 1) <= 64) {
+            add_lanes(P, 0, 64, 0, P.nnew, st0, cw);
+            cur_row = P.rlast;
+            cont = cw;
+            return;
+        }
+        // more row starts than ring slots: four ranges of 16 lanes, draining in between
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int lo = 16 * g, hi = lo + 16;
+            if (p + EPL * lo >= b_) break;
+            const int n0 = g ? readlane(P.n[EPL - 1], lo - 1) : 0;
+            const int nn = readlane(P.n[EPL - 1], hi - 1) - n0;
+            const bool s0 = readlane(P.stm, lo) & 1;
+            const bool cg = (g < 3) ? continues(p + EPL * hi, P, hi) : cw;
+            add_lanes(P, lo, hi, n0, nn, s0, cg);
+            cur_row = readlane(P.r[EPL - 1], hi - 1);
+            cont = cg;
+        }
+    };
+
+    WinRaw R1, R2;
+    WinPrep P0, P1;
+    R1.v = R2.v = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    load_win(0, R2);
+    if (nwin > 1) load_win(1, R1);
+    prep_win(0, R2, P0);
+    for (int i = 0; i < nwin; ++i) {
+        // Issue the loads of window i+2 first, then the rows and gathers of window i+1
+        // (which need the loads of window i+1, issued one iteration earlier). The memory
+        // counter retires in issue order, so waiting for those leaves the gathers of
+        // window i, issued after them, in flight.
+        if (i + 2 < nwin) load_win(i + 2, R2);
+        if (i + 1 < nwin) {
+            prep_win(i + 1, R1, P1);
+        } else {
+            P1.stm = 0;
+        }
+        process(i, P0, P1);
+        P0 = P1;
+        R1 = R2;
     }
     if (ballot(bad) && lane == 0) raise_error(status, kErrCsr);
 
@@ -701,7 +859,7 @@ hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const 
 }
 
 hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
-                        const Work &wk, unsigned *status, hipStream_t s) {
+                        int64_t n_entries, const Work &wk, unsigned *status, hipStream_t s) {
     const int wpb = p.wpb;
     const unsigned grid = (unsigned)((p.NWtot + wpb - 1) / wpb);
     const int lds_floats = embed_lds_floats(p.Kmax);
@@ -715,10 +873,10 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
     if (e != hipSuccess) return e;
     prof_begin(kKEmbedRows, s);
     if (val) {
-        hipLaunchKernelGGL(embed_rows<true>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, wk.rstep, wk.info,
+        hipLaunchKernelGGL(embed_rows<true>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, n_entries, wk.rstep, wk.info,
                            wk.srow, wk.wrow, lds_floats, wk.headp, wk.tailp, wk.split, status);
     } else {
-        hipLaunchKernelGGL(embed_rows<false>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, wk.rstep,
+        hipLaunchKernelGGL(embed_rows<false>, dim3(grid), dim3(64 * wpb), lds, s, b, rp, col, val, n_entries, wk.rstep,
                            wk.info, wk.srow, wk.wrow, lds_floats, wk.headp, wk.tailp, wk.split, status);
     }
     prof_end(kKEmbedRows, s);

@@ -219,7 +219,7 @@ struct Work {
     int *rp = nullptr;         // [Ntot + 1]
     int *col = nullptr;        // [Vtot]
     float *val = nullptr;      // [Vtot] (weighted only)
-    float2 *info = nullptr;    // [Ntot] {coefficient, label bits}
+    float2 *info = nullptr;    // [Ntot] {c_i, y_i bits}; y_i = 0 (and c_i = 0) without a known label
     float *srow = nullptr;     // [Ntot] D^-1/2 (Laplacian)
     int *wrow = nullptr;       // [NWtot] row holding each embed wavefront's first entry
     uint8_t *rstep = nullptr;  // [Vtot] row step from the previous CSR entry (see gee_embed.hip)
@@ -263,7 +263,8 @@ hipError_t launch_graph_meta(const Batch &b, const int *rp_of_union, int M, hipS
 hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, const Work &wk,
                             unsigned *status, hipStream_t s);
 size_t embed_lds_per_wave(int K);
+// Z from the CSR; n_entries = length of the col/val arrays (entries past it are never read).
 hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
-                        const Work &wk, unsigned *status, hipStream_t s);
+                        int64_t n_entries, const Work &wk, unsigned *status, hipStream_t s);
 
 }  // namespace gee
