@@ -463,10 +463,9 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     float *headw = headp + gd.part_off + (int64_t)lw * K;
     float *tailw = tailp + gd.part_off + (int64_t)lw * K;
 
-    // per wavefront: the ring acc[64 slots][KP], per slot {row, s_i} and finishing factor
+    // per wavefront: the ring acc[64 slots][KP] and per slot its row and s_i
     float *acc = smem_f + (size_t)wib * lds_floats;
-    int2 *slot_meta = reinterpret_cast<int2 *>(acc + 64 * KP);
-    float *slot_f = reinterpret_cast<float *>(slot_meta + 64);
+    int2 *slot_meta = reinterpret_cast<int2 *>(acc + 64 * KP);  // {row, s_i}, then {row, factor}
     {
         float4 *acc4 = reinterpret_cast<float4 *>(acc);
         for (int i = lane; i < 16 * KP; i += 64) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -495,8 +494,9 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
 
     // Finish the pending rows and store them. First the factor of every pending row (one
     // lane per row: its sums read back with 16-byte LDS loads for the 2-norm), then a flat
-    // pass over (row, class) in which consecutive lanes read (and clear) consecutive
-    // classes and write consecutive words of Z. The head row goes out raw. This code holds the only global stores and reads nothing loaded from global
+    // pass over (row, class) in which consecutive lanes read consecutive classes and write
+    // consecutive words of Z, then the drained slots are cleared. The head row goes out
+    // raw. This code holds the only global stores and reads nothing loaded from global
     // memory, so it never waits for the loads in flight. Z is written with non-temporal
     // stores: it is not read again here, and keeping it out of the L2 leaves room for the
     // gathered per-node table.
@@ -518,24 +518,20 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
             rrow = m.x;
             fac = rrow == head_row ? 1.0f : row_factor(lap ? __int_as_float(m.y) : 1.0f, ss, cor);
         }
-        // flat pass over (row, class): consecutive lanes write consecutive words of Z
-        if (lane < npend) slot_f[(pend_first + lane) & 63] = fac;
+        // flat pass over (row, class): consecutive lanes write consecutive words of Z; each
+        // lane reads its row and factor as one pair
+        if (lane < npend) slot_meta[(pend_first + lane) & 63].y = __float_as_int(fac);
         wave_lds_fence();
         const int F = npend * K;
         int jj = j0, kk = k0;
         for (int f0 = 0; f0 < F; f0 += 64) {
             const bool has = f0 + lane < F;
             const int sl = (pend_first + jj) & 63;
-            const int ai = sl * KP + kk;
-            const float v = acc[ai];
-            const int r = slot_meta[sl].x;
-            const float fc = slot_f[sl];
-            if (has) {
-                acc[ai] = 0.0f;
-                if (r >= node_off && r < node_off + N) {
-                    float *dst = r == head_row ? headw + kk : Z + (int64_t)(r - node_off) * K + kk;
-                    __builtin_nontemporal_store(v * fc, dst);
-                }
+            const float v = acc[sl * KP + kk];
+            const int2 m = slot_meta[sl];
+            if (has && m.x >= node_off && m.x < node_off + N) {
+                float *dst = m.x == head_row ? headw + kk : Z + (int64_t)(m.x - node_off) * K + kk;
+                __builtin_nontemporal_store(v * __int_as_float(m.y), dst);
             }
             kk += r64;
             jj += q64;
@@ -543,6 +539,15 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
                 kk -= K;
                 ++jj;
             }
+        }
+        // clear the drained slots (one or two contiguous runs of the ring) with 16-byte writes
+        {
+            const int KQ = KP >> 2;
+            float4 *acc4 = reinterpret_cast<float4 *>(acc);
+            const int n1 = min(npend, 64 - pend_first) * KQ, n2 = npend * KQ - n1;
+            const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int q = lane; q < n1; q += 64) acc4[pend_first * KQ + q] = z4;
+            for (int q = lane; q < n2; q += 64) acc4[q] = z4;
         }
         npend = 0;
         wave_lds_fence();
