@@ -50,12 +50,17 @@ constexpr int kStepEsc = 255;  // row-step byte meaning "look the row up in row_
 constexpr int BW = 4;          // windows per pipeline batch (degree_rows)
 constexpr int EPL = 4;          // consecutive CSR entries per lane (embed_rows)
 constexpr int EWIN = 64 * EPL;  // entries per embed window
+#ifndef GEE_RING_SLOTS
+#define GEE_RING_SLOTS 32
+#endif
+constexpr int RS = GEE_RING_SLOTS;  // row slots of an embed wavefront's LDS ring (16..64)
+static_assert(RS >= 16 && RS <= 64 && (RS & (RS - 1)) == 0, "ring slots: power of two in [16, 64]");
 
 // Floats per slot of the embed ring: K rounded up to a multiple of 4 (16-byte rows).
 __host__ __device__ constexpr int ring_stride(int K) { return (K + 3) & ~3; }
-// LDS floats of one embed wavefront: the ring [64][ring_stride(K)] and the 64 slots'
-// {row, s_i} and finishing factors.
-__host__ __device__ constexpr int embed_lds_floats(int K) { return 64 * ring_stride(K) + 3 * 64; }
+// LDS floats of one embed wavefront: the ring [RS][ring_stride(K)] and per slot its row
+// and s_i (later its finishing factor), with room to spare.
+__host__ __device__ constexpr int embed_lds_floats(int K) { return RS * ring_stride(K) + 3 * RS; }
 
 // Graph and local index of embed wavefront w; false if w has no work.
 __device__ __forceinline__ bool wave_graph(const Batch &b, int w, GDesc &d, GMeta &m, int &lw) {
@@ -435,8 +440,11 @@ struct WinPrep {
     int rlast;  // row of the window's last entry
 };
 
+#ifndef GEE_EMBED_MIN_WAVES
+#define GEE_EMBED_MIN_WAVES 1
+#endif
 template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict__ rp, const int *__restrict__ col,
+__global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, const int *__restrict__ rp, const int *__restrict__ col,
                                                   const float *__restrict__ val, int64_t n_entries,
                                                   const uint8_t *__restrict__ rstep,
                                                   const float2 *__restrict__ info,
@@ -463,12 +471,12 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     float *headw = headp + gd.part_off + (int64_t)lw * K;
     float *tailw = tailp + gd.part_off + (int64_t)lw * K;
 
-    // per wavefront: the ring acc[64 slots][KP] and per slot its row and s_i
+    // per wavefront: the ring acc[RS slots][KP] and per slot its row and s_i
     float *acc = smem_f + (size_t)wib * lds_floats;
-    int2 *slot_meta = reinterpret_cast<int2 *>(acc + 64 * KP);  // {row, s_i}, then {row, factor}
+    int2 *slot_meta = reinterpret_cast<int2 *>(acc + RS * KP);  // {row, s_i}, then {row, factor}
     {
         float4 *acc4 = reinterpret_cast<float4 *>(acc);
-        for (int i = lane; i < 16 * KP; i += 64) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int i = lane; i < ((RS * KP) >> 2); i += 64) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     // Finished rows stay in their ring slots ("pending") until drain() stores them:
     // slots [pend_first, pend_first + npend) in ring order, just behind the open row.
@@ -485,8 +493,8 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     const int head_row = head ? row_a : -1;
     const bool cont_end = b_ < E_end && __builtin_amdgcn_readfirstlane(rstep[min(b_, E_end - 1)]) == 0;
     int cur_row = head ? row_a : -1;
-    int cur_slot = 63;
-    if (lane == 0) slot_meta[63] = make_int2(cur_row, __float_as_int(1.0f));
+    int cur_slot = RS - 1;
+    if (lane == 0) slot_meta[RS - 1] = make_int2(cur_row, __float_as_int(1.0f));
     bool cont = false;
     // this lane's (row, class) offset in the flat finishing pass, and its step per pass
     const int j0 = lane / K, k0 = lane - j0 * K;
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         float fac = 0.0f;
         int rrow = -1;
         if (lane < npend) {
-            const int sl = (pend_first + lane) & 63;
+            const int sl = (pend_first + lane) & (RS - 1);
             const int2 m = slot_meta[sl];
             float ss = 0.0f;
             if (cor) {
@@ -520,13 +528,13 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         }
         // flat pass over (row, class): consecutive lanes write consecutive words of Z; each
         // lane reads its row and factor as one pair
-        if (lane < npend) slot_meta[(pend_first + lane) & 63].y = __float_as_int(fac);
+        if (lane < npend) slot_meta[(pend_first + lane) & (RS - 1)].y = __float_as_int(fac);
         wave_lds_fence();
         const int F = npend * K;
         int jj = j0, kk = k0;
         for (int f0 = 0; f0 < F; f0 += 64) {
             const bool has = f0 + lane < F;
-            const int sl = (pend_first + jj) & 63;
+            const int sl = (pend_first + jj) & (RS - 1);
             const float v = acc[sl * KP + kk];
             const int2 m = slot_meta[sl];
             if (has && m.x >= node_off && m.x < node_off + N) {
@@ -544,7 +552,7 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         {
             const int KQ = KP >> 2;
             float4 *acc4 = reinterpret_cast<float4 *>(acc);
-            const int n1 = min(npend, 64 - pend_first) * KQ, n2 = npend * KQ - n1;
+            const int n1 = min(npend, RS - pend_first) * KQ, n2 = npend * KQ - n1;
             const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             for (int q = lane; q < n1; q += 64) acc4[pend_first * KQ + q] = z4;
             for (int q = lane; q < n2; q += 64) acc4[q] = z4;
@@ -690,11 +698,11 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
     // that hit the same word one after another in a fixed order, so the sums are
     // reproducible. Then the rows that ended become pending.
     auto add_lanes = [&](const WinPrep &P, int lo, int hi, int n0, int nn, bool st0, bool cnt) {
-        if (npend + 1 + nn > 64) drain();
+        if (npend + 1 + nn > RS) drain();
         if (lane >= lo && lane < hi) {
             int sl[EPL];
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) sl[j] = (cur_slot + P.n[j] - n0) & 63;
+            for (int j = 0; j < EPL; ++j) sl[j] = (cur_slot + P.n[j] - n0) & (RS - 1);
 #pragma unroll
             for (int j = 0; j < EPL; ++j) {
                 if ((P.stm >> j) & 1) {
@@ -711,14 +719,14 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         }
         // segments of this range: the open row unless the range starts a row, then the
         // new rows; all but the last end here, the last unless the next entry continues it
-        const int first_slot = st0 ? (cur_slot + 1) & 63 : cur_slot;
+        const int first_slot = st0 ? (cur_slot + 1) & (RS - 1) : cur_slot;
         const int nseg = nn + (st0 ? 0 : 1);
         const int nend = cnt ? nseg - 1 : nseg;
         if (nend > 0) {
             if (npend == 0) pend_first = first_slot;
             npend += nend;
         }
-        cur_slot = (cur_slot + nn) & 63;
+        cur_slot = (cur_slot + nn) & (RS - 1);
     };
 
     // Whether the entry at index e (first entry of lane L of the prepared window P, or
@@ -731,21 +739,23 @@ __global__ __launch_bounds__(256) void embed_rows(Batch b, const int *__restrict
         const int p = a + i * EWIN;
         const bool st0 = readlane(P.stm, 0) & 1;
         const bool cw = continues(p + EWIN, Pn, 0);
-        if (P.nnew + (st0 ? 0 : 1) <= 64) {
+        if (P.nnew + (st0 ? 0 : 1) <= RS) {
             add_lanes(P, 0, 64, 0, P.nnew, st0, cw);
             cur_row = P.rlast;
             cont = cw;
             return;
         }
-        // more row starts than ring slots: four ranges of 16 lanes, draining in between
+        // more row starts than ring slots: ranges of RS / EPL lanes (at most RS entries, so
+        // at most RS starts each), draining in between
+        constexpr int GL = RS / EPL, NG = 64 / GL;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int lo = 16 * g, hi = lo + 16;
+        for (int g = 0; g < NG; ++g) {
+            const int lo = GL * g, hi = lo + GL;
             if (p + EPL * lo >= b_) break;
             const int n0 = g ? readlane(P.n[EPL - 1], lo - 1) : 0;
             const int nn = readlane(P.n[EPL - 1], hi - 1) - n0;
             const bool s0 = readlane(P.stm, lo) & 1;
-            const bool cg = (g < 3) ? continues(p + EPL * hi, P, hi) : cw;
+            const bool cg = (g < NG - 1) ? continues(p + EPL * hi, P, hi) : cw;
             add_lanes(P, lo, hi, n0, nn, s0, cg);
             cur_row = readlane(P.r[EPL - 1], hi - 1);
             cont = cg;
