@@ -413,8 +413,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (see the sharding notes in DESIGN.md)",
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the library has no "
+                                   "multi-GPU (sharded) form",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

@@ -60,10 +60,10 @@ typedef enum {
     GEE_ERR_LABEL = -2,       /* (data error bit) label outside [-1, K) */
     GEE_ERR_INDEX = -3,       /* (data error bit) node index outside [0, N) */
     GEE_ERR_WEIGHT = -4,      /* (data error bit) non-finite weight */
-    GEE_ERR_TOO_LARGE = -5,   /* sizes beyond what this build supports (see below) */
+    GEE_ERR_TOO_LARGE = -5,   /* sizes beyond what the library supports (see below) */
     GEE_ERR_OOM = -6,         /* device allocation failed */
     GEE_ERR_HIP = -7,         /* a HIP runtime call failed */
-    GEE_ERR_UNSUPPORTED = -8, /* valid request this build does not implement */
+    GEE_ERR_UNSUPPORTED = -8, /* valid request the library does not implement */
     GEE_ERR_WORKSPACE = -9    /* caller workspace too small */
 } gee_status;
 
@@ -73,7 +73,7 @@ typedef enum {
 #define GEE_DATA_WEIGHT (1u << 2)
 #define GEE_DATA_CSR (1u << 3)
 
-/* Limits of this build: N <= 2^24, K <= 128, CSR entries M < 2^31 - 2^16.
+/* Limits of the library: N <= 2^24, K <= 128, CSR entries M < 2^31 - 2^16.
    (M = 2E minus self-loops under GEE_SYMMETRIZE, else E.) */
 #define GEE_MAX_NODES (1 << 24)
 #define GEE_MAX_CLASSES 128

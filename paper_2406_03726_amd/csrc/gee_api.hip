@@ -420,7 +420,7 @@ const char *gee_status_string(int st) {
     case GEE_ERR_LABEL: return "label outside [-1, K)";
     case GEE_ERR_INDEX: return "node index outside [0, N)";
     case GEE_ERR_WEIGHT: return "non-finite edge weight";
-    case GEE_ERR_TOO_LARGE: return "sizes beyond this build's limits";
+    case GEE_ERR_TOO_LARGE: return "sizes beyond the library's limits";
     case GEE_ERR_OOM: return "device out of memory";
     case GEE_ERR_HIP: return "HIP runtime error";
     case GEE_ERR_UNSUPPORTED: return "unsupported request";
