@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 
 KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
            "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
-           "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"]
+           "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup"]
 
 
 def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):

@@ -108,7 +108,7 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
    Kernel names: "class_count_partial", "class_count_final", "a_hist", "digit_scan",
    "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan",
    "c_scatter", "bucket_sort", "graph_meta",
-   "zero_steps", "node_rows", "degree_rows", "degree_fixup", "fill_empty", "embed_rows",
+   "zero_steps", "node_rows", "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows",
    "embed_fixup". Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */

@@ -343,7 +343,7 @@ hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, wk.rp, 0, s);
     const float *val = p.weighted ? wk.val : nullptr;
-    if (e == hipSuccess) e = launch_node_prep(b, p, wk.rp, val, wk, st, s);
+    if (e == hipSuccess) e = launch_node_prep(b, p, wk.rp, val, p.Vtot, wk, st, s);
     if (e == hipSuccess) e = launch_embed(b, p, wk.rp, wk.col, val, p.Vtot, wk, st, s);
     return e;
 }
@@ -381,7 +381,7 @@ namespace gee {
 const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
-    "degree_rows", "degree_fixup", "fill_empty", "embed_rows", "embed_fixup"};
+    "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
@@ -785,7 +785,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     b.gm = wk.gm;
     hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, nullptr, (int)M, s);
-    if (e == hipSuccess) e = launch_node_prep(b, p, row_ptr, val, wk, st, s);
+    if (e == hipSuccess) e = launch_node_prep(b, p, row_ptr, val, M, wk, st, s);
     if (e == hipSuccess) e = launch_embed(b, p, row_ptr, col, val, M, wk, st, s);
     return hip_status(e);
 }

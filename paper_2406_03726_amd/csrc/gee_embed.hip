@@ -17,8 +17,9 @@
 //   * node_rows    thread per row: the first row of every wavefront, the row step of
 //                  each row's first entry (see below), and the coefficients c_i, s_i
 //                  wherever the degree is a row count or not needed.
-//   * degree_rows  (weighted Laplacian) degrees as segmented sums over entry-balanced
-//                  wavefronts, then c_i and s_i; degree_fixup finishes cut rows.
+//   * degree_rows  (weighted Laplacian) degrees as segmented sums over the same
+//                  entry-balanced wavefronts and windows, then s_i; degree_fixup
+//                  finishes cut rows and node_coef sets c_i from s_i.
 //   * fill_empty   rows without entries (zero, or the diagonal term alone).
 //   * embed_rows   wavefront w of a graph processes that graph's CSR entries
 //                  [w*WE, (w+1)*WE) in windows of 256: lane l holds 4 consecutive
@@ -47,7 +48,6 @@
 namespace gee {
 
 constexpr int kStepEsc = 255;  // row-step byte meaning "look the row up in row_ptr"
-constexpr int BW = 4;          // windows per pipeline batch (degree_rows)
 constexpr int EPL = 4;          // consecutive CSR entries per lane (embed_rows)
 constexpr int EWIN = 64 * EPL;  // entries per embed window
 #ifndef GEE_RING_SLOTS
@@ -170,61 +170,130 @@ __device__ __forceinline__ int row_of_entry(const int *__restrict__ rpg, int N, 
     return lo;
 }
 
-// Rows of the 64 lanes of a window from their step bytes: row = base + inclusive sum of
-// the steps; an escape lane looks its row up and the sum restarts there. `d` must be 0 on
-// lanes past the end. With `force_lane0`, lane 0's step is taken as 0 (its row is `base`).
-// rpg/N/node_off: the graph's rows.
-__device__ __forceinline__ int window_rows(int d, int base, bool force_lane0, int p,
-                                           const int *__restrict__ rpg, int N, int node_off) {
+// Rows of this lane's EPL consecutive entries e0 .. e0+3 of a window, from their step
+// bytes d (byte j for entry e0 + j; 0 past the wavefront's entries): row = base + the
+// inclusive sum of the steps over the window. In the wavefront's first window
+// (`first_win`) lane 0's first entry keeps row `base` whatever its step says. An escape
+// step's row is looked up in row_ptr and the later entries of the window follow from it.
+// Also the inclusive count of row starts (non-zero steps) in the window, per entry, and
+// stm (bit j: entry j starts a row). Returns the packed inclusive scan of the lane (steps
+// in bits 0..19, starts above), so lane 63 holds the window's totals.
+__device__ __forceinline__ int window_rows4(unsigned d, bool first_win, int base, int e0,
+                                            const int *__restrict__ rpg, int N, int node_off,
+                                            int (&r)[EPL], int (&n)[EPL], int &stm) {
     const int lane = lane_id();
-    if (force_lane0 && lane == 0) d = 0;
-    const bool esc = d == kStepEsc;
-    const int S = wave_scan_add(esc ? 0 : d);
-    const uint64_t em = ballot(esc);
-    if (em == 0) return base + S;
-    // rare: a run of >= 254 empty rows before some row of this window
-    const int ar = esc ? row_of_entry(rpg, N, p + lane) + node_off : 0;
-    const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
-    const uint64_t eb = em & le;
-    const int e = eb ? 63 - __clzll(eb) : 0;
-    const int are = __shfl(ar, e, 64), Se = __shfl(S, e, 64);
-    return eb ? are + (S - Se) : base + S;
+    int sp[EPL], stp[EPL];
+    int escm = 0;
+    stm = 0;
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+        const int dj = (int)((d >> (8 * j)) & 0xFFu);
+        const bool first = (j == 0) && first_win && lane == 0;
+        stm |= (dj != 0) << j;
+        const bool esc = dj == kStepEsc && !first;
+        escm |= esc << j;
+        sp[j] = (esc || first) ? 0 : dj;
+    }
+    int rs = 0, cs = 0;
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+        rs += sp[j];
+        cs += (stm >> j) & 1;
+        sp[j] = rs;
+        stp[j] = cs;
+    }
+    // one scan for both: row steps in the low 20 bits (at most 64 * EPL * 254), starts above
+    const int T = rs | (cs << 20);
+    const int X = wave_scan_add(T);
+    const int Xe = X - T;
+    const int rb = base + (Xe & 0xFFFFF), nb0 = Xe >> 20;
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+        r[j] = rb + sp[j];
+        n[j] = nb0 + stp[j];
+    }
+    uint64_t em = ballot(escm != 0);
+    if (em) {
+        // rare: a run of >= 254 empty rows. Each escaped entry's row comes from row_ptr,
+        // then every later entry of the window moves by the difference, in entry order.
+        int ar[EPL];
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) ar[j] = ((escm >> j) & 1) ? row_of_entry(rpg, N, e0 + j) + node_off : 0;
+        while (em) {
+            const int L = __builtin_ctzll(em);
+            em &= em - 1;
+            const int mL = readlane(escm, L);
+#pragma unroll
+            for (int j = 0; j < EPL; ++j) {
+                if (!((mL >> j) & 1)) continue;
+                const int delta = readlane(ar[j], L) - readlane(r[j], L);
+#pragma unroll
+                for (int jj = 0; jj < EPL; ++jj)
+                    if (lane > L || (lane == L && jj >= j)) r[jj] += delta;
+            }
+        }
+    }
+    return X;
+}
+
+// ----------------------------------------------------------------------------- buffer loads
+
+// Buffer resource over `bytes` bytes at p (gfx9 layout: raw, stride 0). Loads past the
+// end return 0 instead of touching memory; offsets are 32-bit.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, int64_t bytes) {
+    const int64_t n = bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(uint32_t)n, 0x00020000);
+}
+__device__ __forceinline__ int4 buf_i4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
 }
 
 // ----------------------------------------------------------------------------- degrees
 
-__device__ __forceinline__ void finish_node(int r, float d, int y, float inv_n_y, bool diag,
-                                            float2 *__restrict__ info, float *__restrict__ srow) {
+// s_i from a weighted degree d (plus 1 with augmentation); 0 for d <= 0.
+__device__ __forceinline__ void finish_degree(int r, float d, bool diag, float *__restrict__ srow) {
     const float dd = d + (diag ? 1.0f : 0.0f);
-    const float s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
-    srow[r] = s;
-    info[r] = node_info(y >= 0 ? s * inv_n_y : 0.0f, y);
+    srow[r] = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
 }
 
-// Weighted degrees d_i = sum of the row's values, as segmented sums over the same
-// entry-balanced wavefronts and batches as embed_rows (fixed summation order; the open
-// row's running sum is compensated). Then s_i and c_i. Wavefronts of graphs without
-// weights or without the Laplacian leave at once.
+// Weighted degrees d_i = sum of the row's values over the same entry-balanced wavefronts
+// and 256-entry windows as embed_rows (lane l holds 4 consecutive entries). In a window,
+// each lane sums its entries row by row, a segmented wave scan (keyed by row) carries the
+// sums across lanes, and the last entry of every row holds the row's sum over the window;
+// a row open across windows keeps a compensated running sum. Summation order is fixed.
+// Rows ending in the wavefront get s_i; a row cut by the wavefront's ends leaves its
+// partial sums for degree_fixup. Wavefronts of graphs without weights or without the
+// Laplacian leave at once.
 __global__ __launch_bounds__(256) void degree_rows(Batch b, const int *__restrict__ rp,
-                                                   const float *__restrict__ val,
+                                                   const float *__restrict__ val, int64_t n_entries,
                                                    const uint8_t *__restrict__ rstep,
-                                                   const int *__restrict__ wrow,
-                                                   const float *__restrict__ inv_n, float2 *__restrict__ info,
-                                                   float *__restrict__ srow, float *__restrict__ headd,
-                                                   float *__restrict__ taild, int *__restrict__ dsplit) {
+                                                   const int *__restrict__ wrow, float *__restrict__ srow,
+                                                   float *__restrict__ headd, float *__restrict__ taild,
+                                                   int *__restrict__ dsplit) {
     const int lane = lane_id();
-    const int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int w = blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     GDesc gd;
     GMeta gm;
     int lw;
     if (!wave_graph(b, w, gd, gm, lw)) return;
     if (!(gd.weighted && (gd.flags & kLap))) return;
     const bool diag = gd.flags & kDiag;
-    const int N = gd.N, K = gd.K, node_off = gd.node_off;
+    const int N = gd.N, node_off = gd.node_off;
     const int *rpg = rp + node_off;
-    const float *invn = inv_n + gd.class_off;
-    const int a = gm.ent_off + lw * gd.WE, b_ = min(a + gd.WE, gm.ent_off + gm.M), last = b_ - 1;
     const int E_end = gm.ent_off + gm.M;
+    const int a = gm.ent_off + lw * gd.WE, b_ = min(a + gd.WE, E_end);
     const int row_a = min(max(wrow[w], node_off), node_off + N - 1);
     const bool head = __builtin_amdgcn_readfirstlane(rstep[a]) == 0;
     const int head_row = head ? row_a : -1;
@@ -232,99 +301,86 @@ __global__ __launch_bounds__(256) void degree_rows(Batch b, const int *__restric
     int cur_row = head ? row_a : -1;
     float carry = 0.0f, comp = 0.0f;  // running sum of the open row and its compensation
     bool cont = false;
-    const int nwin = (b_ - a + 63) >> 6;
-    auto ld_val = [&](int e) { const float v = val[min(e, last)]; return e < b_ ? v : 0.0f; };
-    auto ld_step = [&](int e) { const int v = rstep[min(e, last)]; return e < b_ ? v : 0; };
-    auto ld_lab = [&](int r) {
-        const int y = gd.labels[min(max(r - node_off, 0), N - 1)];
-        return (y >= 0 && y < K) ? y : -1;
+    const int nwin = (b_ - a + EWIN - 1) / EWIN;
+    const __amdgpu_buffer_rsrc_t r_val = buffer_rsrc(val + a, (n_entries - a) * 4);
+    const __amdgpu_buffer_rsrc_t r_stp = buffer_rsrc(rstep + a, n_entries - a);
+    auto load_win = [&](int i, float4 &v, unsigned &d) {
+        const uint32_t o = (uint32_t)(i * EWIN + EPL * lane);
+        if ((int64_t)a + (int64_t)(i + 1) * EWIN <= n_entries) {
+            v = buf_f4(r_val, 4 * o);
+            d = buf_u32(r_stp, o);
+        } else {
+            v = make_float4(__uint_as_float(buf_u32(r_val, 4 * o)), __uint_as_float(buf_u32(r_val, 4 * o + 4)),
+                            __uint_as_float(buf_u32(r_val, 4 * o + 8)), __uint_as_float(buf_u32(r_val, 4 * o + 12)));
+            d = buf_u8(r_stp, o) | (buf_u8(r_stp, o + 1) << 8) | (buf_u8(r_stp, o + 2) << 16) |
+                (buf_u8(r_stp, o + 3) << 24);
+        }
     };
-    auto inv_of = [&](int y) { return y >= 0 ? invn[y] : 0.0f; };
-    float vc[BW], vn1[BW], vn2[BW];
-    int dc[BW], dn1[BW], dn2[BW], rc[BW], rn1[BW], yc[BW], yn1[BW];
-    int base;
+    float4 v0, v1, v2;
+    unsigned d0, d1 = 0, d2;
+    load_win(0, v0, d0);
+    if (nwin > 1) load_win(1, v1, d1);
+    int base = row_a;
+    for (int i = 0; i < nwin; ++i) {
+        if (i + 2 < nwin) load_win(i + 2, v2, d2);
+        const int p = a + i * EWIN;
+        const int e0 = p + EPL * lane;
+        float v[EPL] = {v0.x, v0.y, v0.z, v0.w};
+        unsigned d = d0;
+        if (p + EWIN > b_) {  // entries past b add nothing and start nothing
+            const int nb = min(max(b_ - e0, 0), EPL);
+            d = nb >= EPL ? d : (d & ((1u << (8 * nb)) - 1u));
 #pragma unroll
-    for (int u = 0; u < BW; ++u) {
-        vc[u] = ld_val(a + u * 64 + lane);
-        dc[u] = ld_step(a + u * 64 + lane);
-        vn1[u] = ld_val(a + (BW + u) * 64 + lane);
-        dn1[u] = ld_step(a + (BW + u) * 64 + lane);
-    }
-    base = row_a;
-#pragma unroll
-    for (int u = 0; u < BW; ++u) {
-        rc[u] = window_rows(dc[u], base, u == 0, a + u * 64, rpg, N, node_off);
-        base = readlane(rc[u], 63);
-        yc[u] = ld_lab(rc[u]);
-    }
-    for (int i0 = 0; i0 < nwin; i0 += BW) {
-#pragma unroll
-        for (int u = 0; u < BW; ++u) {
-            rn1[u] = window_rows(dn1[u], base, false, a + (i0 + BW + u) * 64, rpg, N, node_off);
-            base = readlane(rn1[u], 63);
-            yn1[u] = ld_lab(rn1[u]);
-            vn2[u] = ld_val(a + (i0 + 2 * BW + u) * 64 + lane);
-            dn2[u] = ld_step(a + (i0 + 2 * BW + u) * 64 + lane);
+            for (int j = 0; j < EPL; ++j)
+                if (j >= nb) v[j] = 0.0f;
         }
+        int r[EPL], n[EPL], stm;
+        window_rows4(d, i == 0, base, e0, rpg, N, node_off, r, n, stm);
+        base = readlane(r[EPL - 1], 63);
+        // this lane's sums row by row, then across lanes for the row of its last entry
+        float x[EPL];
+        x[0] = v[0];
 #pragma unroll
-        for (int u = 0; u < BW; ++u) {
-            const int i = i0 + u;
-            if (i >= nwin) break;
-            const int p = a + (i << 6);
-            const int nvalid = min(64, b_ - p);
-            const float v = vc[u];
-            const int row = rc[u];
-            const int nxt = (u + 1 < BW) ? readlane(dc[u + 1], 0) : readlane(dn1[0], 0);
-            cont = (p + nvalid < b_) ? (nxt == 0) : cont_end;
-            const uint64_t sm = ballot(lane < nvalid && dc[u] != 0);
-            if (sm == 0) {  // the window lies inside the open row
-                const float t = wave_sum(v) - comp;
-                const float s = carry + t;
-                comp = (s - carry) - t;
-                carry = s;
-                if (!cont) {
-                    if (lane == 0) {  // every lane holds the open row and its label
-                        if (cur_row == head_row) headd[w] = carry;
-                        else if (cur_row >= node_off && cur_row < node_off + N)
-                            finish_node(cur_row, carry, yc[u], inv_of(yc[u]), diag, info, srow);
-                    }
-                    carry = comp = 0.0f;
-                }
-                continue;
+        for (int j = 1; j < EPL; ++j) x[j] = (r[j] == r[j - 1]) ? x[j - 1] + v[j] : v[j];
+        const float S = wave_seg_scan_addf(x[EPL - 1], r[EPL - 1]);
+        const float Sp = dpp_f<0x138>(S, 0.0f);         // wave_shr:1, lane l gets lane l-1
+        const int rp3 = dpp_i<0x138>(r[EPL - 1], INT32_MIN);
+        const int rn0 = dpp_i<0x130>(r[0], INT32_MAX);  // wave_shl:1, lane l gets lane l+1
+        const bool last_win = p + EWIN >= b_;
+        const bool cw = last_win ? cont_end : ((readlane((int)d1, 0) & 0xFF) == 0);
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            // the sum of row r[j] from the window's start through entry j
+            const float t = (r[j] == rp3 && r[j] == r[0]) ? Sp + x[j] : x[j];
+            const bool ends = (j + 1 < EPL) ? r[j + 1] != r[j] : (lane < 63 ? rn0 != r[j] : !cw);
+            if (ends) {
+                const float dsum = (r[j] == cur_row) ? carry + (t - comp) : t;
+                if (r[j] == head_row) headd[w] = dsum;
+                else if (r[j] >= node_off && r[j] < node_off + N) finish_degree(r[j], dsum, diag, srow);
             }
-            // inclusive segmented scan of the values over lanes of equal rows
-            const float x = wave_seg_scan_addf(v, row);
-            const int nxt_row = dpp_i<0x130>(row, INT32_MIN);  // wave_shl:1, lane l gets lane l+1
-            const bool last_of_seg = lane < nvalid && (lane == nvalid - 1 || nxt_row != row);
-            const int row_last = readlane(row, nvalid - 1);
-            if (last_of_seg) {
-                float dsum = x;
-                if (row == cur_row) dsum = carry + (x - comp);  // the open row's earlier windows first
-                const bool ends = !(row == row_last && cont);
-                if (ends) {
-                    if (row == head_row) headd[w] = dsum;
-                    else if (row >= node_off && row < node_off + N)
-                        finish_node(row, dsum, yc[u], inv_of(yc[u]), diag, info, srow);
-                }
-            }
-            const float tail = readlane_f(x, nvalid - 1);
-            if (cont) {
-                carry = (row_last == cur_row) ? carry + (tail - comp) : tail;
-                comp = 0.0f;
+        }
+        // the row of the window's last entry, when it continues into the next window
+        const float tail = readlane_f(S, 63);
+        const int rl = base;
+        if (cw) {
+            if (rl == cur_row) {
+                const float y = tail - comp;
+                const float tt = carry + y;
+                comp = (tt - carry) - y;
+                carry = tt;
             } else {
-                carry = comp = 0.0f;
+                carry = tail;
+                comp = 0.0f;
             }
-            cur_row = row_last;
+        } else {
+            carry = comp = 0.0f;
         }
-#pragma unroll
-        for (int u = 0; u < BW; ++u) {
-            vc[u] = vn1[u];
-            dc[u] = dn1[u];
-            rc[u] = rn1[u];
-            yc[u] = yn1[u];
-            vn1[u] = vn2[u];
-            dn1[u] = dn2[u];
-        }
+        cur_row = rl;
+        cont = cw;
+        v0 = v1;
+        d0 = d1;
+        v1 = v2;
+        d1 = d2;
     }
     int my_split = -1;
     if (cont && lane == 0) {
@@ -340,11 +396,9 @@ __global__ __launch_bounds__(256) void degree_rows(Batch b, const int *__restric
 
 // Thread per wavefront: the degree of a row cut by wavefront boundaries, in wavefront order.
 __global__ __launch_bounds__(256) void degree_fixup(Batch b, int NWtot, const int *__restrict__ rp,
-                                                    const float *__restrict__ inv_n,
                                                     const float *__restrict__ headd,
                                                     const float *__restrict__ taild,
-                                                    const int *__restrict__ dsplit, float2 *__restrict__ info,
-                                                    float *__restrict__ srow) {
+                                                    const int *__restrict__ dsplit, float *__restrict__ srow) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= NWtot) return;
     GDesc gd;
@@ -358,9 +412,22 @@ __global__ __launch_bounds__(256) void degree_fixup(Batch b, int NWtot, const in
     const int wl = (int)min((int64_t)gm.NW - 1, max((int64_t)lw, ((int64_t)(end - gm.ent_off) - 1) / gd.WE));
     float d = taild[w];
     for (int w2 = lw + 1; w2 <= wl; ++w2) d += headd[gd.wave_off + w2];
-    int y = gd.labels[r - gd.node_off];
-    if (y < 0 || y >= gd.K) y = -1;
-    finish_node(r, d, y, y >= 0 ? inv_n[gd.class_off + y] : 0.0f, gd.flags & kDiag, info, srow);
+    finish_degree(r, d, gd.flags & kDiag, srow);
+}
+
+// Thread per row of a weighted graph with the Laplacian: c_i = s_i / n_{y_i} once the
+// weighted degrees are known (other rows got theirs in node_rows).
+__global__ __launch_bounds__(256) void node_coef(Batch b, int Ntot, const int *__restrict__ rp,
+                                                 const float *__restrict__ inv_n, const float *__restrict__ srow,
+                                                 float2 *__restrict__ info) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= Ntot) return;
+    const int g = find_graph(b.node_offs, b.G, r);
+    const GDesc d = load_desc(b, g);
+    if (!(d.weighted && (d.flags & kLap)) || rp[r] == rp[r + 1]) return;
+    int y = d.labels[r - d.node_off];
+    if (y < 0 || y >= d.K) y = -1;
+    info[r] = node_info(y >= 0 ? srow[r] * inv_n[d.class_off + y] : 0.0f, y);
 }
 
 // ----------------------------------------------------------------------------- empty rows
@@ -398,28 +465,6 @@ __device__ __forceinline__ float row_factor(float s, float ss, bool cor) {
 }
 
 // ----------------------------------------------------------------------------- main kernel
-
-// Buffer resource over `bytes` bytes at p (gfx9 layout: raw, stride 0). Loads past the
-// end return 0 instead of touching memory; offsets are 32-bit.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, int64_t bytes) {
-    const int64_t n = bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes);
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(uint32_t)n, 0x00020000);
-}
-__device__ __forceinline__ int4 buf_i4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
-__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
-__device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-}
-__device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
-}
 
 // One window of a wavefront as loaded: lane l holds entries p + 4l .. p + 4l + 3.
 struct WinRaw {
@@ -619,58 +664,8 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
                 }
             }
         }
-        // steps: the wavefront's first entry sits in row_a whatever its step says; an
-        // escape step counts as a start and its row is looked up below
-        int sp[EPL], stp[EPL];
-        int stm = 0, escm = 0;
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            const int dj = (int)((d >> (8 * j)) & 0xFFu);
-            const bool first = (j == 0) && i == 0 && lane == 0;
-            stm |= (dj != 0) << j;
-            const bool esc = dj == kStepEsc && !first;
-            escm |= esc << j;
-            sp[j] = (esc || first) ? 0 : dj;
-        }
-        int rs = 0, cs = 0;
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            rs += sp[j];
-            cs += (stm >> j) & 1;
-            sp[j] = rs;
-            stp[j] = cs;
-        }
-        // one scan for both: row steps in the low 20 bits, starts above
-        const int T = rs | (cs << 20);
-        const int X = wave_scan_add(T);
-        const int Xe = X - T;
-        const int rb = base + (Xe & 0xFFFFF), nb0 = Xe >> 20;
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            P.r[j] = rb + sp[j];
-            P.n[j] = nb0 + stp[j];
-        }
-        uint64_t em = ballot(escm != 0);
-        if (em) {
-            // rare: a run of >= 254 empty rows. Each escaped entry's row comes from row_ptr,
-            // then every later entry of the window moves by the difference, in entry order.
-            int ar[EPL];
-#pragma unroll
-            for (int j = 0; j < EPL; ++j) ar[j] = ((escm >> j) & 1) ? row_of_entry(rpg, N, e0 + j) + node_off : 0;
-            while (em) {
-                const int L = __builtin_ctzll(em);
-                em &= em - 1;
-                const int mL = readlane(escm, L);
-#pragma unroll
-                for (int j = 0; j < EPL; ++j) {
-                    if (!((mL >> j) & 1)) continue;
-                    const int delta = readlane(ar[j], L) - readlane(P.r[j], L);
-#pragma unroll
-                    for (int jj = 0; jj < EPL; ++jj)
-                        if (lane > L || (lane == L && jj >= j)) P.r[jj] += delta;
-                }
-            }
-        }
+        int stm;
+        const int X = window_rows4(d, i == 0, base, e0, rpg, N, node_off, P.r, P.n, stm);
         P.stm = stm;
         P.nnew = readlane(X, 63) >> 20;
         P.rlast = readlane(P.r[EPL - 1], 63);
@@ -847,8 +842,8 @@ hipError_t launch_graph_meta(const Batch &b, const int *rp_of_union, int M, hipS
 
 // Per-node data for the embedding of a CSR: first rows of the wavefronts, row steps,
 // degrees, s_i and c_i. The graph metadata must be set beforehand.
-hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, const Work &wk,
-                            unsigned *status, hipStream_t s) {
+hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, int64_t n_entries,
+                            const Work &wk, unsigned *status, hipStream_t s) {
     const int64_t nz = (p.Vtot + 16 * 256 - 1) / (16 * 256);
     prof_begin(kKZeroSteps, s);
     hipLaunchKernelGGL(zero_bytes, dim3((unsigned)(nz > 0 ? nz : 1)), dim3(256), 0, s, wk.rstep, p.Vtot);
@@ -862,14 +857,19 @@ hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const 
     prof_end(kKNodeRows, s);
     if ((e = hipGetLastError()) != hipSuccess || !(val && p.any_lap_w)) return e;
     prof_begin(kKDegreeRows, s);
-    hipLaunchKernelGGL(degree_rows, dim3((unsigned)((p.NWtot + 3) / 4)), dim3(256), 0, s, b, rp, val, wk.rstep,
-                       wk.wrow, wk.inv_n, wk.info, wk.srow, wk.headd, wk.taild, wk.dsplit);
+    hipLaunchKernelGGL(degree_rows, dim3((unsigned)((p.NWtot + 3) / 4)), dim3(256), 0, s, b, rp, val, n_entries,
+                       wk.rstep, wk.wrow, wk.srow, wk.headd, wk.taild, wk.dsplit);
     prof_end(kKDegreeRows, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKDegreeFixup, s);
     hipLaunchKernelGGL(degree_fixup, dim3((unsigned)((p.NWtot + 255) / 256)), dim3(256), 0, s, b, (int)p.NWtot, rp,
-                       wk.inv_n, wk.headd, wk.taild, wk.dsplit, wk.info, wk.srow);
+                       wk.headd, wk.taild, wk.dsplit, wk.srow);
     prof_end(kKDegreeFixup, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKNodeCoef, s);
+    hipLaunchKernelGGL(node_coef, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, s, b, (int)p.Ntot, rp, wk.inv_n, wk.srow,
+                       wk.info);
+    prof_end(kKNodeCoef, s);
     return hipGetLastError();
 }
 

@@ -237,7 +237,7 @@ struct Work {
 enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
-    kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKNumKernels
+    kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
@@ -260,8 +260,8 @@ int bucket_stage_cap(int sb);
 // from the given entry count M (a single resident CSR, rp_of_union == nullptr).
 hipError_t launch_graph_meta(const Batch &b, const int *rp_of_union, int M, hipStream_t s);
 // Per-node data (ownership, degrees, s_i, c_i).
-hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, const Work &wk,
-                            unsigned *status, hipStream_t s);
+hipError_t launch_node_prep(const Batch &b, const Plan &p, const int *rp, const float *val, int64_t n_entries,
+                            const Work &wk, unsigned *status, hipStream_t s);
 size_t embed_lds_per_wave(int K);
 // Z from the CSR; n_entries = length of the col/val arrays (entries past it are never read).
 hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
