@@ -93,6 +93,9 @@ typedef struct {
 
 int gee_abi_version(void);
 const char *gee_status_string(int status);
+/* Text of the HIP runtime error behind the last GEE_ERR_HIP (or GEE_ERR_OOM) returned on
+   the calling thread; "" if there was none. The string is static (owned by HIP). */
+const char *gee_last_hip_error(void);
 
 /* Per-device set-up (the data-error word). Called lazily by every entry point; call it
    once up front on each device when later calls run under stream capture. */

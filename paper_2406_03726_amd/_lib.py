@@ -33,6 +33,7 @@ SYMBOLS = {
     # name: (restype, argtypes)
     "gee_abi_version": (ctypes.c_int, []),
     "gee_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gee_last_hip_error": (ctypes.c_char_p, []),
     "gee_init": (ctypes.c_int, []),
     "gee_profile_kernel": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gee_get_data_errors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),

@@ -27,8 +27,11 @@ int ilog2_ceil(int64_t x) {
 }
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+thread_local hipError_t t_last_hip = hipSuccess;  // the last failed HIP call on this thread
+
 int hip_status(hipError_t e) {
     if (e == hipSuccess) return GEE_OK;
+    t_last_hip = e;
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return GEE_ERR_OOM;
     return GEE_ERR_HIP;
 }
@@ -40,7 +43,8 @@ unsigned *g_status[64] = {nullptr};
 
 int device_status(unsigned **out) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return GEE_ERR_HIP;
+    hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return hip_status(ge);
     if (dev < 0 || dev >= 64) return GEE_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_status_mu);
     if (!g_status[dev]) {
@@ -173,14 +177,22 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     p.parts = parts;
     p.cnt_blocks = (int)coff;
     p.cparts = cpo;
-    // CSR sort buckets of 2^sb rows, about 3000 entries each on average; at most 65536
+    // CSR sort buckets of 2^sb rows (at most 65536 buckets). Dense graphs, whose 256-row
+    // buckets average at least twice the staging capacity, take 256-row buckets: nearly
+    // all of them go to the pass-C partition, which costs the same per entry whatever the
+    // bucket size. Otherwise about 3000 entries a bucket, so most fit one workgroup's LDS.
     const int64_t n1 = p.Ntot > 0 ? p.Ntot : 1;
     const int sb_min = ilog2_ceil(n1) > 16 ? ilog2_ceil(n1) - 16 : 0;
     if (sb_min > kMaxBucketRowsLog2) return GEE_ERR_TOO_LARGE;
     int sb = 0;
     if (p.Vtot > 0) {
-        const double rows = 3000.0 * (double)n1 / (double)p.Vtot;
-        while (sb < kMaxBucketRowsLog2 && (double)(2 << sb) <= rows) ++sb;
+        const double per_row = (double)p.Vtot / (double)n1;
+        if (256.0 * per_row >= 2.0 * bucket_stage_cap(8)) {
+            sb = 8;
+        } else {
+            const double rows = 3000.0 / per_row;
+            while (sb < kMaxBucketRowsLog2 && (double)(2 << sb) <= rows) ++sb;
+        }
     } else {
         sb = kMaxBucketRowsLog2;
     }
@@ -373,6 +385,13 @@ int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &ou
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+// Stream of a call about to enqueue kernels. HIP keeps a thread's last error until it is
+// read; one left by the application's own earlier calls is consumed here, so the checks
+// after this call's launches see only this call's launches.
+hipStream_t launch_stream(void *s) {
+    (void)hipGetLastError();
+    return as_stream(s);
+}
 
 }  // namespace
 
@@ -427,6 +446,10 @@ const char *gee_status_string(int st) {
     case GEE_ERR_WORKSPACE: return "workspace too small";
     default: return "unknown status";
     }
+}
+
+const char *gee_last_hip_error(void) {
+    return t_last_hip == hipSuccess ? "" : hipGetErrorString(t_last_hip);
 }
 
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event) {
@@ -506,7 +529,7 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
     if ((rc = make_plan(&x, 1, false, p, d))) return rc;
     Batch b;
     b.one = d[0];
-    hipStream_t s = as_stream(stream);
+    hipStream_t s = launch_stream(stream);
     int *part = nullptr;
     hipError_t e = hipMallocAsync((void **)&part, (size_t)p.cparts * sizeof(int), s);
     if (e != hipSuccess) return hip_status(e);
@@ -556,7 +579,7 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
     if (!workspace || workspace_bytes < gee_build_csr_workspace_bytes(E, N, flags, sched)) return GEE_ERR_WORKSPACE;
     Work wk;
     carve(p, kPPart, (char *)workspace, wk);
-    hipStream_t s = as_stream(stream);
+    hipStream_t s = launch_stream(stream);
     if (N == 0) return hip_status(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s));
     wk.rp = row_ptr;
     wk.col = col;
@@ -664,7 +687,7 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
     const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
     if (!workspace || workspace_bytes < carve(p, parts, nullptr, wk)) return GEE_ERR_WORKSPACE;
     carve(p, parts, (char *)workspace, wk);
-    hipStream_t s = as_stream(stream);
+    hipStream_t s = launch_stream(stream);
     Batch b;
     hipError_t e = make_batch(p, d, wk, s, false, b);
     if (e == hipSuccess) e = enqueue_embed(b, p, wk, st, s);
@@ -695,6 +718,7 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     if (e == hipSuccess) {
         carve(p, parts, (char *)pl->ws, wk);
         Batch b;
+        (void)hipGetLastError();  // see launch_stream
         e = make_batch(p, d, wk, nullptr, true, b);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -779,7 +803,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     if (!workspace || workspace_bytes < gee_embed_csr_workspace_bytes(M, N, K, flags, sched))
         return GEE_ERR_WORKSPACE;
     carve(p, parts, (char *)workspace, wk);
-    hipStream_t s = as_stream(stream);
+    hipStream_t s = launch_stream(stream);
     Batch b;
     b.one = d[0];
     b.gm = wk.gm;

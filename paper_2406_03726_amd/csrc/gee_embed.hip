@@ -432,26 +432,62 @@ __global__ __launch_bounds__(256) void node_coef(Batch b, int Ntot, const int *_
 
 // ----------------------------------------------------------------------------- empty rows
 
-// Thread per row: a row without entries is zero, or holds the diagonal term alone
-// (c_i s_i at its own class; 1 under correlation).
+// Rows without entries: zero, or the diagonal term alone (c_i s_i at its own class; 1
+// under correlation). A workgroup takes 256 consecutive rows; when they belong to one
+// graph (their Z rows are then contiguous) the empty ones are written in one flat pass
+// over (row, class), consecutive threads on consecutive words; else a thread per row.
 __global__ __launch_bounds__(256) void fill_empty(Batch b, int Ntot, const int *__restrict__ rp,
                                                   const float2 *__restrict__ info,
                                                   const float *__restrict__ srow) {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= Ntot || rp[r] != rp[r + 1]) return;
-    const int g = find_graph(b.node_offs, b.G, r);
-    const GDesc d = load_desc(b, g);
-    const bool lap = d.flags & kLap, diag = d.flags & kDiag, cor = d.flags & kCor;
-    int y = -1;
+    __shared__ int s_y[256];
+    __shared__ float s_v[256];
+    const int t = threadIdx.x;
+    const int r0 = blockIdx.x * 256;
+    const int r = r0 + t;
+    const int nrows = min(256, Ntot - r0);
+    const bool empty = r < Ntot && rp[r] == rp[r + 1];
+    int y = -2;  // -2: not empty (nothing to write)
     float v = 0.0f;
-    if (diag) {
-        const float2 inf = info[r];
-        y = __float_as_int(inf.y);
-        v = inf.x * (lap ? srow[r] : 1.0f);
-        if (cor) v = v != 0.0f ? 1.0f : 0.0f;
+    GDesc d;
+    if (empty) {
+        d = load_desc(b, find_graph(b.node_offs, b.G, r));
+        const bool lap = d.flags & kLap, diag = d.flags & kDiag, cor = d.flags & kCor;
+        y = -1;
+        if (diag) {
+            const float2 inf = info[r];
+            y = __float_as_int(inf.y);
+            v = inf.x * (lap ? srow[r] : 1.0f);
+            if (cor) v = v != 0.0f ? 1.0f : 0.0f;
+        }
     }
-    float *z = d.Z + (int64_t)(r - d.node_off) * d.K;
-    for (int k = 0; k < d.K; ++k) z[k] = (k == y) ? v : 0.0f;
+    s_y[t] = y;
+    s_v[t] = v;
+    const int g0 = find_graph(b.node_offs, b.G, r0);
+    const bool one_graph = find_graph(b.node_offs, b.G, r0 + nrows - 1) == g0;
+    if (!__syncthreads_or(empty)) return;
+    if (!one_graph) {
+        if (empty) {
+            float *z = d.Z + (int64_t)(r - d.node_off) * d.K;
+            for (int k = 0; k < d.K; ++k) z[k] = (k == y) ? v : 0.0f;
+        }
+        return;
+    }
+    const GDesc dg = load_desc(b, g0);
+    const int K = dg.K;
+    float *z0 = dg.Z + (int64_t)(r0 - dg.node_off) * K;
+    const int F = nrows * K;
+    const int q = 256 / K, rq = 256 - q * K;
+    int j = t / K, k = t - (t / K) * K;
+    for (int f = t; f < F; f += 256) {
+        const int yj = s_y[j];
+        if (yj != -2) __builtin_nontemporal_store(k == yj ? s_v[j] : 0.0f, z0 + f);
+        k += rq;
+        j += q;
+        if (k >= K) {
+            k -= K;
+            ++j;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------- finish a row

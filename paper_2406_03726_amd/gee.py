@@ -28,14 +28,17 @@ GEE_OK = 0
 GEE_ERR_ARG = -1
 GEE_ERR_TOO_LARGE = -5
 GEE_ERR_OOM = -6
+GEE_ERR_HIP = -7
 GEE_ERR_UNSUPPORTED = -8
 GEE_ERR_WORKSPACE = -9
 
 
 class GeeError(RuntimeError):
     def __init__(self, code: int, where: str):
-        msg = _lib.load().gee_status_string(code).decode()
-        super().__init__(f"{where}: {msg} ({code})")
+        lib = _lib.load()
+        msg = lib.gee_status_string(code).decode()
+        hip = lib.gee_last_hip_error().decode() if code in (GEE_ERR_HIP, GEE_ERR_OOM) else ""
+        super().__init__(f"{where}: {msg} ({code})" + (f": {hip}" if hip else ""))
         self.code = code
 
 

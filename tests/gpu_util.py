@@ -38,8 +38,9 @@ def embed_graph(g, sched=None):
 
 
 def max_rel_error(Z, R):
-    """Elementwise relative error on the oracle's non-zero entries (A15 of the design
-    notes); also asserts exact zeros where the oracle is exactly zero."""
+    """Largest elementwise relative error over the entries where the oracle is non-zero
+    (the 1e-5 bar is relative to each entry); also whether the entries where the oracle is
+    exactly zero are exactly zero."""
     Zg = Z.detach().cpu().double().numpy().reshape(R.shape)
     nz = R != 0
     zero_ok = np.all(Zg[~nz] == 0)

@@ -296,6 +296,25 @@ def test_argument_errors():
         gee.gee_embed(s, d, w, lab, 3, 1 << 9)
 
 
+def test_unread_hip_error_of_the_caller_is_not_a_launch_failure():
+    """A HIP error the application left unread (here: elapsed time of events never
+    recorded) is not taken for a failed launch of the next call."""
+    import ctypes
+    import os
+
+    hip = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipEventCreate(ctypes.byref(a)) == 0 and hip.hipEventCreate(ctypes.byref(b)) == 0
+    ms = ctypes.c_float()
+    assert hip.hipEventElapsedTime(ctypes.byref(ms), a, b) != 0  # leaves the thread's last error set
+    g = random_small_graph(5, N=300, E=2000, K=4).with_options(True, True, True)
+    Z = embed_graph(g)
+    torch.cuda.synchronize()
+    hip.hipEventDestroy(a)
+    hip.hipEventDestroy(b)
+    assert_close(Z, or_embed_graph(g), "after an unread HIP error")
+
+
 # ----------------------------------------------------------------------------- full sizes
 
 def test_sbm_small_both_option_sets():
