@@ -224,7 +224,8 @@ def batched_leg(torch, np, gee, dev, table, procs, reps=5, G=512):
 
 
 def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, n_req=400,
-                loads=(0.5, 0.9, 1.5), slots=4, budget_gb=32.0, max_batch=16, max_batch_edges=2_000_000):
+                loads=(0.5, 0.9, 1.5), slots=4, budget_gb=32.0, max_batch=16, max_batch_edges=2_000_000,
+                max_inflight_edges=None):
     """Poisson requests from a pool of serving-recipe graphs: the server (budget admission,
     continuous batching over `slots` streams) against the plain per-request loop."""
     from paper_2406_03726_amd.serve import GeeServer, GpuBackend, Request, run_plain, summarize
@@ -259,7 +260,15 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
     out = {"pool_graphs": pool_n, "pool_edges_mean": int(np.mean([it["src"].numel() for it in pool])),
            "generation_s": round(gen_s, 1), "requests_per_load": n_req, "slots": slots,
            "budget_bytes": int(budget_gb * 2 ** 30), "max_batch": max_batch, "max_batch_edges": max_batch_edges,
+           "max_inflight_edges": max_inflight_edges,
            "plain_saturation_req_per_s": round(mu, 1), "loads": []}
+    # warm-up of the served path too (the plain loop's was the service-time pass): every
+    # pool graph once through the server, so its streams' allocator caches hold their sizes
+    warm = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
+                     max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges)
+    warm.run_trace([Request(i, it, 0.0, E=int(it["src"].numel())) for i, it in enumerate(pool)])
+    torch.cuda.synchronize()
+    del warm
     for frac in loads:
         lam = frac * mu
         arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
@@ -270,7 +279,7 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
 
         plain = run_plain(mk(), embed_one)
         srv = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
-                        max_batch_edges=max_batch_edges)
+                        max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges)
         served = srv.run_trace(mk())
         torch.cuda.synchronize()
         sp, ss = summarize(plain), summarize(served)

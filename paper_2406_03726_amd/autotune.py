@@ -119,16 +119,19 @@ def _validate(s: Dict[str, int]) -> None:
 
 
 def choose(timings: Dict[Tuple[Tuple[str, int], ...], float]) -> Dict[str, int]:
-    """Fastest candidate; ties go to the earlier (smaller) candidate in sorted order so the
-    choice is deterministic."""
-    best = min(sorted(timings.items()), key=lambda kv: kv[1])
+    """Fastest candidate; a tie goes to the candidate with fewer non-default fields, then
+    to the smaller one in sorted order, so the choice is deterministic."""
+    best = min(timings.items(), key=lambda kv: (kv[1], len(kv[0]), kv[0]))
     return dict(best[0])
 
 
-def candidates(with_bucket_rows: bool = False) -> List[Dict[str, int]]:
+BUCKET_ROWS = (0, 8)  # 0: the library's own rule; 8: 256-row buckets (pass-C partition)
+
+
+def candidates(with_bucket_rows: bool = True) -> List[Dict[str, int]]:
     out = [{"wave_entries": we} for we in WAVE_ENTRIES]
     if with_bucket_rows:
-        out = [dict(c, bucket_rows_log2=sb) for c in out for sb in (0, 5, 7)]
+        out = [dict(c, bucket_rows_log2=sb) for c in out for sb in BUCKET_ROWS]
     return out
 
 
@@ -226,7 +229,7 @@ def main(argv=None):
     t0 = time.time()
     shapes = default_shapes()
     table = tune(shapes, gpu_time_fn(args.reps))
-    table.meta = {"shapes": len(shapes), "candidates": [c["wave_entries"] for c in candidates()],
+    table.meta = {"shapes": len(shapes), "wave_entries": list(WAVE_ENTRIES), "bucket_rows_log2": list(BUCKET_ROWS),
                   "seconds": round(time.time() - t0, 1)}
     table.save(args.out)
     print(f"wrote {len(table.entries)} buckets to {args.out} in {time.time() - t0:.1f} s", flush=True)

@@ -13,6 +13,10 @@ strictly FIFO, so a large request at the head waits for memory rather than being
 Each request's schedule comes from its own sizes (the autotuned table or the library
 default), so its Z is bitwise the same whether it runs alone or batched with others.
 
+Optionally the edges of the batches in flight are capped: a request that would exceed
+the cap waits (FIFO) until enough of the device is free, and runs alone when it exceeds
+the cap by itself.
+
 The scheduler is host logic over a small backend interface, so it can be driven by the
 GPU backend or, in tests, by a simulated one on a virtual clock.
 """
@@ -71,11 +75,13 @@ class _Flight:
     handle: Any
     reqs: List[Request]
     nbytes: int
+    edges: int = 0
 
 
 class GeeServer:
     def __init__(self, backend: Backend, budget_bytes: int, max_batch: int = 64,
-                 clock: Callable[[], float] = time.perf_counter, max_batch_edges: Optional[int] = None):
+                 clock: Callable[[], float] = time.perf_counter, max_batch_edges: Optional[int] = None,
+                 max_inflight_edges: Optional[int] = None):
         if budget_bytes <= 0 or max_batch < 1:
             raise ValueError("budget and batch size must be positive")
         self.backend = backend
@@ -84,6 +90,11 @@ class GeeServer:
         # A batch finishes as a whole: a cap on its edges keeps small requests from
         # waiting for a large one batched with them (a larger request still runs alone).
         self.max_batch_edges = max_batch_edges
+        # Batches in flight share the device: a cap on their edges keeps a large request
+        # from being slowed by others running beside it (it waits for the device to empty,
+        # as it would in the plain loop, and then runs alone).
+        self.max_inflight_edges = max_inflight_edges
+        self.inflight_edges = 0
         self.clock = clock
         self.queue: Deque[Request] = deque()
         self.flights: List[_Flight] = []
@@ -124,6 +135,7 @@ class GeeServer:
                     r.t_done = now
                     self.done.append(r)
                 self.in_use -= f.nbytes
+                self.inflight_edges -= f.edges
                 self.free_slots.append(f.slot)
                 n += 1
             else:
@@ -153,6 +165,9 @@ class GeeServer:
                     break  # FIFO: nothing behind a request that does not fit yet
                 if batch and self.max_batch_edges is not None and edges + r.E > self.max_batch_edges:
                     break  # the next batch starts with this request
+                if (self.max_inflight_edges is not None and (batch or self.flights)
+                        and self.inflight_edges + edges + r.E > self.max_inflight_edges):
+                    break  # FIFO: wait until the device has room for this request
                 batch.append(r)
                 nbytes += r.nbytes
                 edges += r.E
@@ -165,8 +180,9 @@ class GeeServer:
             for r in batch:
                 r.t_admit = now
             handle = self.backend.launch(batch, slot)
-            self.flights.append(_Flight(slot, handle, batch, nbytes))
+            self.flights.append(_Flight(slot, handle, batch, nbytes, edges))
             self.in_use += nbytes
+            self.inflight_edges += edges
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             self.peak_flights = max(self.peak_flights, len(self.flights))
             self.launch_log.append([r.rid for r in batch])

@@ -188,3 +188,29 @@ def test_edge_cap_splits_batches():
         assert len(b) == 1 or sum(E[i] for i in b) <= cap
     flat = [rid for b in be.launched for rid in b]
     assert flat == sorted(flat) and len(flat) == 20
+
+
+def test_inflight_edge_cap():
+    clk = Clock()
+    be = FakeBackend(clk, slots=4, launch_cost=1e-3)
+    reqs = _reqs(30, seed=7, rate=1e6)
+    big = random_small_graph(77, N=250, E=1999, K=3)
+    reqs[5] = Request(rid=5, graph={"g": big}, arrival=reqs[5].arrival)
+    cap = 2500
+    srv = GeeServer(be, 10 ** 9, max_batch=1, clock=clk, max_inflight_edges=cap)
+    seen = []
+    orig_launch = be.launch
+
+    def launch(batch, slot):
+        seen.append((sum(r.E for r in batch), srv.inflight_edges, len(srv.flights)))
+        return orig_launch(batch, slot)
+
+    be.launch = launch
+    srv.run_trace(reqs, sleep=clk.sleep)
+    assert all(r.t_done is not None and r.error is None for r in reqs)
+    for e, inflight, nflights in seen:
+        # a batch joins others only within the cap; one above the cap runs alone
+        assert nflights == 0 or inflight + e <= cap
+    flat = [rid for b in be.launched for rid in b]
+    assert flat == sorted(flat) and len(flat) == 30
+    assert srv.inflight_edges == 0
