@@ -362,10 +362,12 @@ __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid, int nb
 
 // Pass A scatter: tile t of the virtual entries, sorted by high digit in LDS (wave-split
 // ranking over the wavefront's registers) and written to seg_start[d] + (scanned tile
-// offset) in runs.
+// offset) in runs. The key written keeps only the bits the later passes read (amask): the
+// high digit is implied by the segment, so with at most 16 bits left it fits a u16.
+template <typename AK>
 __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
                                                  const int *__restrict__ gh, const int *__restrict__ seg_start,
-                                                 int *__restrict__ okey, int *__restrict__ ocol,
+                                                 AK *__restrict__ okey, int amask, int *__restrict__ ocol,
                                                  float *__restrict__ oval, unsigned *status) {
     __shared__ PartLds L;
     const int wv = threadIdx.x >> 6;
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, 
         const int key = L.key[i];
         const int d = key >> shift;
         const int64_t g2 = (int64_t)L.gbase[d] + (i - L.lstart[d]);
-        okey[g2] = key;
+        okey[g2] = (AK)(key & amask);
         ocol[g2] = L.col[i];
         if (oval) oval[g2] = L.val[i];
     }
@@ -737,15 +739,28 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
                        wk.tileB, wk.bstart, wk.meta);
     prof_end(kKATotals, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // pass A keys: the row's low sb + s2 bits, as u16 when they fit
+    const bool k16 = p.sb + p.s2 <= 16;
+    uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     prof_begin(kKAScatter, s);
-    hipLaunchKernelGGL(a_scatter, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits, p.TA,
-                       wk.ghA, wk.segA, wk.akey, acol, aval, status);
+    if (k16) {
+        hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits,
+                           p.TA, wk.ghA, wk.segA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status);
+    } else {
+        hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits,
+                           p.TA, wk.ghA, wk.segA, wk.akey, -1, acol, aval, status);
+    }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!with_b) return hipSuccess;
     prof_begin(kKBHist, s);
-    hipLaunchKernelGGL(seg_hist<int>, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA,
-                       wk.tileB, p.DA, wk.ghB);
+    if (k16) {
+        hipLaunchKernelGGL(seg_hist<uint16_t>, dim3((unsigned)p.TBcap), dim3(256), 0, s, akey16, p.sb, p.s2,
+                           wk.segA, wk.tileB, p.DA, wk.ghB);
+    } else {
+        hipLaunchKernelGGL(seg_hist<int>, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA,
+                           wk.tileB, p.DA, wk.ghB);
+    }
     prof_end(kKBHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScan, s);
@@ -753,9 +768,15 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_end(kKBScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
-    hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval,
-                       p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                       p.weighted ? wk.tval : nullptr);
+    if (k16) {
+        hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, akey16, acol,
+                           aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
+                           p.weighted ? wk.tval : nullptr);
+    } else {
+        hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval,
+                           p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
+                           p.weighted ? wk.tval : nullptr);
+    }
     prof_end(kKBScatter, s);
     return hipGetLastError();
 }
@@ -796,15 +817,18 @@ hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hip
     const float *tv = p.weighted ? wk.tval : nullptr;
     float *ov = p.weighted ? wk.val : nullptr;
     const int pass_c = p.sb <= 8 ? 1 : 0;  // pass C ranks rows as digits of at most 8 bits
+    const bool k16 = p.sb + p.s2 <= 16;    // pass A wrote u16 keys (see launch_csr_build)
+    const uint16_t *akey16 = reinterpret_cast<const uint16_t *>(wk.akey);
     hipError_t e = hipSuccess;
     if (pass_c) {
-        e = p.s2 > 0 ? launch_pass_c<uint16_t>(wk.tkey, p, wk, cap, s) : launch_pass_c<int>(wk.akey, p, wk, cap, s);
+        e = (p.s2 > 0 || k16) ? launch_pass_c<uint16_t>(p.s2 > 0 ? wk.tkey : akey16, p, wk, cap, s)
+                              : launch_pass_c<int>(wk.akey, p, wk, cap, s);
         if (e != hipSuccess) return e;
     }
     prof_begin(kKBucketSort, s);
-    if (p.s2 > 0) {
-        hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, wk.tkey, wk.tcol, tv, wk.bstart,
-                           p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
+    if (p.s2 > 0 || k16) {
+        hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, p.s2 > 0 ? wk.tkey : akey16, wk.tcol,
+                           tv, wk.bstart, p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
     } else {
         hipLaunchKernelGGL(bucket_sort<int>, dim3(p.B), dim3(256), lds, s, wk.akey, wk.tcol, tv, wk.bstart, p.B,
                            p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
