@@ -428,8 +428,9 @@ __device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, int D, 
 // tile_off[d] is the segment's first tile. The digit of a key is
 // (key >> dshift) & (2^dbits - 1).
 
-// Per tile: digit histogram; segment d's counts are stored digit-major at
-// gh + tile_off[d] * 2^dbits, [digit][tile].
+// Per tile: digit histogram; segment d's counts are stored tile-major at
+// gh + tile_off[d] * 2^dbits, [tile][digit], so each tile writes (and later reads) one
+// contiguous row.
 template <typename KT>
 __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int dshift, int dbits,
                                                 const int *__restrict__ seg_start, const int *__restrict__ tile_off,
@@ -449,48 +450,70 @@ __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int 
     for (int r = 0; r < kRounds; ++r)
         if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[(k[r] >> dshift) & (L - 1)], 1);
     __syncthreads();
-    if ((int)threadIdx.x < L) gh[((int64_t)tile_off[d] << dbits) + (int64_t)threadIdx.x * ntd + jt] = hist[threadIdx.x];
+    if ((int)threadIdx.x < L) gh[(((int64_t)tile_off[d] + jt) << dbits) + threadIdx.x] = hist[threadIdx.x];
 }
 
-// One workgroup per segment d: exclusive scan of its [digit][tile] counts (positions
-// inside the segment), and starts[(d << dbits) + digit] = the first position of each
-// digit (for indices below `limit`). With skip_untiled, segments without tiles are left
-// alone (pass C: those buckets are sorted whole by bucket_sort).
+// One workgroup per segment d: every (tile, digit) count becomes the position of that
+// run inside the segment (digits in order, and within a digit the tiles in order), and
+// starts[(d << dbits) + digit] = the first position of each digit (for indices below
+// `limit`). A thread per digit walks the tile rows (coalesced across the digits); four
+// groups of threads take a quarter of the tiles each. With skip_untiled, segments
+// without tiles are left alone (pass C: those buckets are sorted whole by bucket_sort).
 __global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits, const int *__restrict__ seg_start,
                                                  const int *__restrict__ tile_off, int limit,
                                                  int *__restrict__ starts, int skip_untiled) {
+    __shared__ int part[4][256];
+    __shared__ int dstart[256];
     __shared__ int wsum[16];
     const int d = blockIdx.x;
     const int ntd = tile_off[d + 1] - tile_off[d];
     if (skip_untiled && ntd == 0) return;
     const int L = 1 << dbits;
-    const int64_t len = (int64_t)ntd << dbits;
-    int *seg = gh + ((int64_t)tile_off[d] << dbits);
-    int carry = 0;
-    constexpr int IPT = 8;
-    for (int64_t c = 0; c < len; c += 1024 * IPT) {
-        int vals[IPT];
-        int s = 0;
-        const int64_t lo = c + (int64_t)threadIdx.x * IPT;
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            vals[i] = (lo + i < len) ? seg[lo + i] : 0;
-            s += vals[i];
+    int *seg = gh + ((int64_t)tile_off[d] << dbits);  // [ntd][L]
+    const int dig = threadIdx.x & 255, grp = threadIdx.x >> 8;
+    const int per = (ntd + 3) >> 2;
+    const int t0 = min(ntd, grp * per), t1 = min(ntd, t0 + per);
+    int tot = 0;
+    if (dig < L) {
+        int t = t0;
+        for (; t + 4 <= t1; t += 4) {
+            const int a0 = seg[((int64_t)t << dbits) + dig], a1 = seg[((int64_t)(t + 1) << dbits) + dig];
+            const int a2 = seg[((int64_t)(t + 2) << dbits) + dig], a3 = seg[((int64_t)(t + 3) << dbits) + dig];
+            tot += a0 + a1 + a2 + a3;
         }
-        int total;
-        int base = block_excl_scan<1024>(s, wsum, total) + carry;
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            if (lo + i < len) seg[lo + i] = base;
-            base += vals[i];
-        }
-        carry += total;
+        for (; t < t1; ++t) tot += seg[((int64_t)t << dbits) + dig];
     }
+    part[grp][dig] = tot;
     __syncthreads();
+    const int dsum = (threadIdx.x < 256) ? part[0][dig] + part[1][dig] + part[2][dig] + part[3][dig] : 0;
+    int total;
+    const int ds = block_excl_scan<1024>(dsum, wsum, total);
+    if (threadIdx.x < 256) dstart[dig] = ds;
+    __syncthreads();
+    if (dig < L) {
+        int run = dstart[dig];
+        for (int g = 0; g < grp; ++g) run += part[g][dig];
+        int t = t0;
+        for (; t + 4 <= t1; t += 4) {
+            int *q0 = seg + ((int64_t)t << dbits) + dig;
+            const int a0 = q0[0], a1 = q0[L], a2 = q0[2 * L], a3 = q0[3 * L];
+            q0[0] = run;
+            q0[L] = run + a0;
+            q0[2 * L] = run + a0 + a1;
+            q0[3 * L] = run + a0 + a1 + a2;
+            run += a0 + a1 + a2 + a3;
+        }
+        for (; t < t1; ++t) {
+            int *q0 = seg + ((int64_t)t << dbits) + dig;
+            const int a0 = q0[0];
+            q0[0] = run;
+            run += a0;
+        }
+    }
     const int s0 = seg_start[d];
-    for (int lo = threadIdx.x; lo < L; lo += blockDim.x) {
-        const int64_t b = ((int64_t)d << dbits) + lo;
-        if (b < limit) starts[b] = s0 + (ntd > 0 ? seg[(int64_t)lo * ntd] : 0);
+    if ((int)threadIdx.x < L) {
+        const int64_t b = ((int64_t)d << dbits) + threadIdx.x;
+        if (b < limit) starts[b] = s0 + dstart[threadIdx.x];
     }
 }
 
@@ -531,7 +554,7 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
     for (int r = 0; r < kRoundsW; ++r)
         if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> dshift) & (ND - 1)], 1);
     __syncthreads();
-    const int gb = (int)threadIdx.x < ND ? s0 + seg[(int64_t)threadIdx.x * ntd + jt] : 0;
+    const int gb = (int)threadIdx.x < ND ? s0 + seg[((int64_t)jt << dbits) + threadIdx.x] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
