@@ -342,22 +342,14 @@ __device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, i
 }
 
 // Stable position of this lane's item among the wavefront's items of the same digit (in
-// round and lane order); the last lane of each digit group advances the digit's running
-// position.
+// round and lane order), from the digit's running position in LDS. One LDS atomic add
+// with return per item: the LDS serves the lanes of one instruction that hit the same
+// word in ascending lane order (measured on gfx950, and the CSR parity tests compare the
+// result bit for bit with a stable sort), and the instructions of one wavefront in
+// program order.
 __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid, int nbits) {
-    uint64_t peers = ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (digit >> b) & 1;
-        const uint64_t m = ballot(valid && bit);
-        peers &= bit ? m : ~m;
-    }
-    const int below = count_below(peers);
-    const int cntp = __popcll(peers);
-    const int pos = valid ? run[digit] + below : 0;
-    wave_lds_fence();
-    if (valid && below == cntp - 1) run[digit] = pos + 1;
-    wave_lds_fence();
-    return pos;
+    (void)nbits;
+    return valid ? atomicAdd(&run[digit], 1) : 0;
 }
 
 // Pass A scatter: tile t of the virtual entries, sorted by high digit in LDS (wave-split
