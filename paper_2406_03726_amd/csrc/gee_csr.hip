@@ -347,8 +347,7 @@ __device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, i
 // word in ascending lane order (measured on gfx950, and the CSR parity tests compare the
 // result bit for bit with a stable sort), and the instructions of one wavefront in
 // program order.
-__device__ __forceinline__ int wave_rank(int *run, int digit, bool valid, int nbits) {
-    (void)nbits;
+__device__ __forceinline__ int wave_rank(int *run, int digit, bool valid) {
     return valid ? atomicAdd(&run[digit], 1) : 0;
 }
 
@@ -379,7 +378,7 @@ __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, 
     for (int r = 0; r < kRoundsW; ++r) {
         const bool valid = q.valid >> r & 1u;
         const int digit = valid ? (q.key[r] >> shift) : 0;
-        const int pos = wave_rank(L.cnt[wv], digit, valid, nbits);
+        const int pos = wave_rank(L.cnt[wv], digit, valid);
         if (valid) {
             L.key[pos] = q.key[r];
             L.col[pos] = q.col[r];
@@ -552,7 +551,7 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
     for (int r = 0; r < kRoundsW; ++r) {
         const bool valid = ew + r * 64 + lane < e1;
         const int digit = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
-        const int pos = wave_rank(L.cnt[wv], digit, valid, dbits);
+        const int pos = wave_rank(L.cnt[wv], digit, valid);
         if (valid) {
             L.key[pos] = kr[r];
             L.col[pos] = cr[r];
@@ -625,7 +624,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
         return;
     }
-    if (R <= 256 && e1 - e0 <= cap) {
+    if (R <= 1024 && e1 - e0 <= cap) {
         // Wave-split ranking: each wavefront counts and ranks a contiguous quarter.
         const int wv = threadIdx.x >> 6, lane = lane_id();
         int *cnt = smem_i;                                              // [4][R]
@@ -651,19 +650,26 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         for (int r = 0; r < kRoundsW; ++r)
             if (ew + r * 64 + lane < ee) atomicAdd(&cnt[wv * R + kr[r]], 1);
         __syncthreads();
-        const int r = threadIdx.x;
-        int c[kWaves];
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) c[w] = r < R ? cnt[w * R + r] : 0;
+        // thread t owns rows [t * rpt, (t + 1) * rpt): their counts, one scan, then each
+        // (wavefront, row) pair's first position
+        const int rpt = (R + 255) >> 8;  // at most 4
+        const int rb0 = threadIdx.x * rpt;
+        int csum = 0;
+        for (int i = 0; i < rpt; ++i) {
+            const int r = rb0 + i;
+            if (r < R) csum += cnt[r] + cnt[R + r] + cnt[2 * R + r] + cnt[3 * R + r];
+        }
         int total;
-        const int ls = block_excl_scan256(c[0] + c[1] + c[2] + c[3], wsum, total);
-        if (r < Rb) rp[r0 + r] = e0 + ls;
-        if (r < R) {
-            int run2 = ls;
+        int run2 = block_excl_scan256(csum, wsum, total);
+        for (int i = 0; i < rpt; ++i) {
+            const int r = rb0 + i;
+            if (r >= R) break;
+            if (r < Rb) rp[r0 + r] = e0 + run2;
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
+                const int c = cnt[w * R + r];
                 cnt[w * R + r] = run2;
-                run2 += c[w];
+                run2 += c;
             }
         }
         if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 #pragma unroll
         for (int r = 0; r < kRoundsW; ++r) {
             const bool valid = ew + r * 64 + lane < ee;
-            const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid, sb);
+            const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid);
             if (valid) {
                 scol2[pos] = cr[r];
                 if (val) sval2[pos] = vr[r];
@@ -727,7 +733,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
 size_t bucket_sort_lds(int sb) {
     const size_t R = (size_t)1 << sb;
-    const size_t counters = R <= 256 ? kWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
+    const size_t counters = R <= 1024 ? kWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
     return (counters > 8 * R ? counters : 8 * R) + (size_t)bucket_stage_cap(sb) * 8;
 }
 
