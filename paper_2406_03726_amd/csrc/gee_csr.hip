@@ -24,12 +24,11 @@
 // Every partition pass works on tiles of 2048 entries: the tile's entries are ranked
 // by digit (stable) and staged in LDS in digit order, then written out so that
 // consecutive threads write consecutive addresses of each digit's run; no pass writes
-// scattered single words. Stable ranks never use global atomics: within a 64-wide
-// wavefront, lanes with the same digit are found by ballots over the digit bits;
-// across the wavefronts of a round a small per-wave count table in LDS gives the
-// offset; running counts per digit live in LDS for the whole tile, so equal digits
-// keep the input order. Tile offsets come from per-tile histograms scanned on the
-// device, digit-major, so pass outputs are the same for every launch.
+// scattered single words. Stable ranks never use global atomics: each wavefront owns a
+// contiguous part of the tile and ranks its items against its own per-digit running
+// positions in LDS (see wave_rank), so equal digits keep the input order. Tile offsets
+// come from per-tile histograms scanned on the device, digit-major, so pass outputs are
+// the same for every launch.
 #include "gee_internal.h"
 
 namespace gee {
@@ -304,9 +303,8 @@ __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int
 // wavefronts owns a contiguous quarter of the tile. The wavefronts first count their
 // items per digit (LDS atomics on their own row of counters), one scan over
 // (digit, wavefront) turns the counts into the first position of every (wavefront,
-// digit) pair, then each wavefront reloads its items and ranks them in order: lanes
-// with the same digit are found by ballots over the digit bits, and a per-digit running
-// position advanced by the last lane of each group keeps the input order.
+// digit) pair, then each wavefront ranks its items in round and lane order against the
+// per-digit running positions of its row (wave_rank).
 
 
 struct PartLds {
