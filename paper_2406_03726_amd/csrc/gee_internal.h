@@ -109,6 +109,53 @@ __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     atomicOr(status, bit);
 }
 
+// ----------------------------------------------------------------------------- shared by the embed paths
+
+// Floats per slot of the embed ring: K rounded up to a multiple of 4 (16-byte rows).
+__host__ __device__ constexpr int ring_stride(int K) { return (K + 3) & ~3; }
+// Per-node table entry {c_i, y_i}. A node without a known label has c_i = 0 and is filed
+// under class 0, so every class index read from the table lies in [0, K) and adding c_i
+// there changes nothing.
+__device__ __forceinline__ float2 node_info(float c, int y) {
+    return make_float2(c, __int_as_float(y >= 0 ? y : 0));
+}
+
+// Buffer resource over `bytes` bytes at p (gfx9 layout: raw, stride 0). Loads past the
+// end return 0 instead of touching memory; offsets are 32-bit.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, int64_t bytes) {
+    const int64_t n = bytes < 0 ? 0 : (bytes > 0xFFFFFFFFll ? 0xFFFFFFFFll : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)(uint32_t)n, 0x00020000);
+}
+__device__ __forceinline__ int4 buf_i4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float4 buf_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+// s_i from a weighted degree d (plus 1 with augmentation); 0 for d <= 0.
+__device__ __forceinline__ void finish_degree(int r, float d, bool diag, float *__restrict__ srow) {
+    const float dd = d + (diag ? 1.0f : 0.0f);
+    srow[r] = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
+}
+
+// Factor that turns a row's sums u (diagonal term included) into its Z row: s_i without
+// correlation; with it u/|u|, since D^-1/2 scales the whole row by s_i > 0 and the 2-norm
+// removes it (a row with s_i = 0 or u = 0 stays zero).
+__device__ __forceinline__ float row_factor(float s, float ss, bool cor) {
+    if (!cor) return s;
+    return (s > 0.0f && ss > 0.0f) ? 1.0f / sqrtf(ss) : 0.0f;
+}
+
 // ----------------------------------------------------------------------------- graphs
 
 // One graph of a launch. A plain call is a batch of one graph; a batch is the disjoint
