@@ -83,13 +83,22 @@ typedef enum {
    floating-point rounding order (a schedule is chosen from the graph's own sizes, so
    a graph embedded alone or inside a batch with the same schedule is bit-identical). */
 typedef struct {
-    int32_t wave_entries;   /* CSR entries per wavefront in the embed kernel (power of 2, 256..16384) */
+    int32_t wave_entries;   /* entries per wavefront in the embed kernel (power of 2, 256..16384);
+                               on the bucket path (below) the entries of a bucket part, at least 2048 */
     int32_t waves_per_block;/* wavefronts per workgroup in the embed kernel (1, 2 or 4) */
     int32_t tile_entries;   /* entries per workgroup tile of the CSR partition passes; this
-                               build supports only 2048 (0 = default) */
+                               library supports only 4096 (0 = default) */
     int32_t bucket_rows_log2; /* rows per CSR sort bucket = 2^this (0 = automatic, else 1..12;
-                                 raised to what keeps the bucket count <= 65536) */
+                                 raised to what keeps the bucket count <= 65536); the bucket
+                                 path fixes its own */
 } gee_schedule;
+/* Paths. gee_embed, gee_embed_ws and batches take the bucket path whenever the launch's
+   rows fit 65536 buckets of 64 rows (2^22 rows, batch graphs each rounded up to the
+   bucket size): the entries are partitioned into buckets of 32 consecutive rows (64 when
+   32 would need more than 65536 buckets) and every bucket's class sums are accumulated
+   whole, without building the CSR. Larger launches, and gee_embed_csr, take the CSR path.
+   A graph's Z is bitwise the same alone and in any batch that takes the same path with
+   the same bucket size. */
 
 int gee_abi_version(void);
 const char *gee_status_string(int status);
@@ -112,7 +121,8 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
    "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan",
    "c_scatter", "bucket_sort", "graph_meta",
    "zero_steps", "node_rows", "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows",
-   "embed_fixup". Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
+   "embed_fixup" (CSR path), "bucket_part_count", "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed",
+   "bucket_embed_fix" (bucket path of gee_embed and batches). Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);

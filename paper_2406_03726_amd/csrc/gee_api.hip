@@ -108,14 +108,34 @@ int check_schedule(const gee_schedule &sc) {
 // Default CSR entries per embed wavefront for a graph with this many entries.
 int default_wave_entries(int64_t Mcap) { return Mcap >= (1 << 20) ? 1024 : 512; }
 
+// Bucket path rows per bucket (log2) for a launch of these graphs: 32-row buckets, or 64
+// when 32 would need more than kMaxBuckets; -1 when 64 rows are not enough either. Graph
+// offsets are then aligned to the bucket size, so a graph's buckets are its own.
+#ifndef GEE_BUCKET_SB_MIN
+#define GEE_BUCKET_SB_MIN 5
+#endif
+int bucket_path_sb(const GraphIn *gs, int G) {
+    for (int sb = GEE_BUCKET_SB_MIN; sb <= 6; ++sb) {
+        int64_t n = 0;
+        for (int g = 0; g < G; ++g) n = ((n + (1 << sb) - 1) >> sb << sb) + gs[g].N;
+        if (n <= kMaxBatchNodes && ((n + (1 << sb) - 1) >> sb) <= kMaxBuckets) return sb;
+    }
+    return -1;
+}
+
 // Plan of a launch over G graphs. `resident`: the graphs are given as CSRs (E = M).
-int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDesc> &d) {
+// `edge_embed`: the launch embeds edge lists (gee_embed and batches), which take the
+// bucket path whenever its buckets can hold the launch's rows.
+int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDesc> &d, bool edge_embed = false) {
     if (G < 1 || G > kMaxBatchGraphs) return GEE_ERR_ARG;
     p = Plan();
     p.G = G;
     d.assign(G, GDesc());
     int64_t voff = 0, noff = 0, woff = 0, parts = 0, coff = 0, cpo = 0, ktot = 0;
     int wpb = 0, sb_req = 0;
+    const int sb_bucket = edge_embed && !resident ? bucket_path_sb(gs, G) : -1;
+    p.bucket = sb_bucket >= 0;
+    int64_t bparts = 0;
     for (int g = 0; g < G; ++g) {
         const GraphIn &x = gs[g];
         int rc = check_common(x.N, x.K, x.flags);
@@ -135,6 +155,7 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
         o.E = x.E;
         o.Mcap = mcap;
         o.N = x.N;
+        if (p.bucket) noff = (noff + (1 << sb_bucket) - 1) >> sb_bucket << sb_bucket;
         o.node_off = (int)noff;
         o.K = x.K;
         int kp = 1;
@@ -143,7 +164,14 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
         o.class_off = (int)ktot;
         o.flags = resident ? (x.flags & ~GEE_SYMMETRIZE) : x.flags;
         o.weighted = x.w != nullptr;
-        o.WE = x.sc.wave_entries ? x.sc.wave_entries : default_wave_entries(mcap);
+        if (p.bucket) {
+            // entries of a bucket part (one wavefront of the bucket path)
+            o.WE = x.sc.wave_entries > kBucketMinPart ? x.sc.wave_entries
+                   : x.sc.wave_entries ? kBucketMinPart : kBucketDefaultPart;
+            bparts += mcap / o.WE;
+        } else {
+            o.WE = x.sc.wave_entries ? x.sc.wave_entries : default_wave_entries(mcap);
+        }
         o.NWcap = mcap > 0 ? (int)((mcap + o.WE - 1) / o.WE) : 1;
         o.wave_off = (int)woff;
         o.part_off = parts;
@@ -199,6 +227,7 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     if (sb_req > 0) sb = sb_req;
     if (sb < sb_min) sb = sb_min;
     if (sb > kMaxBucketRowsLog2) sb = kMaxBucketRowsLog2;
+    if (p.bucket) sb = sb_bucket;
     p.sb = sb;
     p.B = (int32_t)((n1 + (1 << sb) - 1) >> sb);
     const int nbB = ilog2_ceil(p.B);
@@ -209,7 +238,11 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     if (p.TA < 1) p.TA = 1;
     p.TBcap = p.s2 > 0 ? p.TA + p.DA : 1;
     // pass C: every bucket above the staging capacity holds more than cap entries
-    p.TCcap = p.sb <= 8 ? p.TA + p.Vtot / bucket_stage_cap(p.sb) + 1 : 1;
+    p.TCcap = p.sb <= 8 && !p.bucket ? p.TA + p.Vtot / bucket_stage_cap(p.sb) + 1 : 1;
+    // bucket path: a bucket of n entries has max(1, ceil(n / P)) <= 1 + floor(n / P) parts;
+    // one of several parts has ceil(n / P) <= 2 floor(n / P) partial slots
+    p.bparts = p.bucket ? p.B + bparts : 0;
+    p.bslots = p.bucket ? 2 * bparts : 0;
     // One wavefront per embed workgroup by default: the LDS ring of each wavefront then
     // limits residency least. Larger workgroups must stay within 64 KiB of LDS.
     const size_t per_wave = embed_lds_per_wave(p.Kmax);
@@ -253,17 +286,34 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
         w.tileC = (int *)take((size_t)(p.B + 1) * sizeof(int));
         w.ghC = (int *)take(((size_t)p.TCcap << p.sb) * sizeof(int));
-        w.akey = (int *)take((size_t)p.Vtot * sizeof(int));
-        if (p.s2 > 0) w.tkey = (uint16_t *)take((size_t)p.Vtot * sizeof(uint16_t));
-        w.tcol = (int *)take((size_t)p.Vtot * sizeof(int));
-        if (p.weighted) w.tval = (float *)take((size_t)p.Vtot * sizeof(float));
+        // one window of entries past the end: the bucket path reads whole windows
+        const size_t vp = (size_t)p.Vtot + kBucketWindowPad;
+        w.akey = (int *)take(vp * sizeof(int));
+        if (p.s2 > 0) w.tkey = (uint16_t *)take(vp * sizeof(uint16_t));
+        w.tcol = (int *)take(vp * sizeof(int));
+        if (p.weighted) w.tval = (float *)take(vp * sizeof(float));
     }
-    if (parts & kPCsrOut) {
+    if ((parts & kPCsrOut) && p.bucket) {
+        // no CSR: col / val only hold pass A's output when a pass B follows
+        if (p.s2 > 0) {
+            w.col = (int *)take((size_t)p.Vtot * sizeof(int));
+            if (p.weighted) w.val = (float *)take((size_t)p.Vtot * sizeof(float));
+        }
+    } else if (parts & kPCsrOut) {
         w.rp = (int *)take((size_t)(p.Ntot + 1) * sizeof(int));
         w.col = (int *)take((size_t)p.Vtot * sizeof(int));
         if (p.weighted) w.val = (float *)take((size_t)p.Vtot * sizeof(float));
     }
-    if (parts & kPEmbed) {
+    if ((parts & kPEmbed) && p.bucket) {
+        w.info = (float2 *)take((size_t)p.Ntot * sizeof(float2));
+        w.srow = (float *)take((size_t)p.Ntot * sizeof(float));
+        w.part = (int4 *)take((size_t)p.bparts * sizeof(int4));
+        w.multi = (int4 *)take((size_t)(p.bslots / 2 + 1) * sizeof(int4));
+        w.ptot = (int *)take(3 * 64 * sizeof(int));
+        w.bmeta = (int *)take(4 * sizeof(int));
+        w.dpart = (float *)take((size_t)p.bslots * 64 * sizeof(float));
+        w.zpart = (float *)take(((size_t)p.bslots << p.sb) * (size_t)p.Kmax * sizeof(float));
+    } else if (parts & kPEmbed) {
         w.info = (float2 *)take((size_t)p.Ntot * sizeof(float2));
         w.srow = (float *)take((size_t)p.Ntot * sizeof(float));
         w.wrow = (int *)take((size_t)p.NWtot * sizeof(int));
@@ -352,6 +402,7 @@ hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w,
 hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned *st, hipStream_t s) {
     hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_csr_build(b, p, wk, st, s);
+    if (p.bucket) return e == hipSuccess ? launch_bucket_embed(b, p, wk, s) : e;
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, wk.rp, 0, s);
     const float *val = p.weighted ? wk.val : nullptr;
@@ -400,7 +451,8 @@ namespace gee {
 const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
-    "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup"};
+    "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
+    "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
@@ -498,7 +550,7 @@ int gee_default_schedule(int64_t E, int32_t N, int32_t K, uint32_t flags, gee_sc
     x.flags = flags;
     Plan p;
     std::vector<GDesc> d;
-    int rc = make_plan(&x, 1, false, p, d);
+    int rc = make_plan(&x, 1, false, p, d, true);
     if (rc) return rc;
     out->wave_entries = d[0].WE;
     out->waves_per_block = p.wpb;
@@ -621,7 +673,7 @@ size_t gee_embed_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags
     if (sched) x.sc = *sched;
     Plan p;
     std::vector<GDesc> d;
-    if (E < 0 || make_plan(&x, 1, false, p, d)) return 0;
+    if (E < 0 || make_plan(&x, 1, false, p, d, true)) return 0;
     Work w;
     return carve(p, kPCount | kPPart | kPCsrOut | kPEmbed, nullptr, w);
 }
@@ -667,7 +719,7 @@ size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G) {
     if (graphs_from_api(graphs, G, gs, true)) return 0;
     Plan p;
     std::vector<GDesc> d;
-    if (make_plan(gs.data(), G, false, p, d)) return 0;
+    if (make_plan(gs.data(), G, false, p, d, true)) return 0;
     Work w;
     return carve(p, kPCount | kPPart | kPCsrOut | kPEmbed, nullptr, w);
 }
@@ -679,7 +731,7 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
     if (rc) return rc;
     Plan p;
     std::vector<GDesc> d;
-    if ((rc = make_plan(gs.data(), G, false, p, d))) return rc;
+    if ((rc = make_plan(gs.data(), G, false, p, d, true))) return rc;
     if (p.Ntot == 0) return GEE_OK;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
@@ -702,7 +754,7 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     if (rc) return rc;
     Plan p;
     std::vector<GDesc> d;
-    if ((rc = make_plan(gs.data(), G, false, p, d))) return rc;
+    if ((rc = make_plan(gs.data(), G, false, p, d, true))) return rc;
     if (p.Ntot == 0) return GEE_ERR_ARG;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;

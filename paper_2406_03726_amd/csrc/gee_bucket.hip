@@ -1,0 +1,529 @@
+// gee_bucket.hip - Z = A W straight from the row buckets of the CSR sort (Eq. 1, Table 1).
+//
+// The edge-list entry points need every row's sums, not the CSR itself. After the first
+// two partition passes of the sort (gee_csr.hip) the entries of each bucket of R
+// consecutive rows (R = 32, or 64 for launches of more than 2^21 rows) lie together, in
+// input order. Each bucket is cut into parts of at most P entries (P = the graph's
+// wave_entries, at least kBucketMinPart), one wavefront per part:
+//
+//   * bucket_part_count / bucket_part_fill  the part table {bucket, entries, partial slot}
+//                    and the list of buckets of several parts (two passes of prefix sums
+//                    over the buckets).
+//   * bucket_degree  (Laplacian) each part's weighted degrees (entry counts without weights)
+//                    of the bucket's rows: LDS float atomics on R row sums; a one-part
+//                    bucket then sets s_i and c_i = s_i / n_{y_i} of its rows, a longer one
+//                    leaves partial sums. Without the Laplacian, c_i = 1 / n_{y_i}.
+//   * bucket_degree_fix  adds the partial degrees of split buckets in part order.
+//   * bucket_embed   the class sums: the wavefront holds acc[R rows][class] in LDS and adds
+//                    every entry's val * c_j into acc[row][y_j] (4 consecutive entries per
+//                    lane, 16-byte loads, the loads of window k+2 and the gathers of window
+//                    k+1 in flight while window k is added). A one-part bucket then
+//                    finishes its rows (diagonal term c_i, factor s_i or the 2-norm) and
+//                    writes them as one contiguous block of Z; a longer one leaves its sums.
+//   * bucket_embed_fix  adds the partial sums of split buckets in part order and finishes
+//                    their rows.
+//
+// A wavefront adds its entries in a fixed order (windows in order; the LDS applies the
+// lanes of one instruction that hit one word in lane order) and parts are combined in
+// part order, so Z is bitwise reproducible. Buckets never straddle graphs (each graph's
+// first row is aligned to R), and a graph's buckets and parts depend on that graph alone,
+// so its Z is the same alone and in a batch with the same R. The diagonal term is added
+// after the entries of its row.
+#include "gee_internal.h"
+
+namespace gee {
+
+constexpr int BEPL = 4;          // consecutive entries per lane in a window
+constexpr int BWIN = 64 * BEPL;  // entries per window
+constexpr int kFixThreads = 256; // threads per split bucket when combining class sums
+
+// LDS of one class-sum workgroup: R rows of ring_stride(K) floats and 64 row factors.
+static size_t bucket_lds(int sb, int Kmax) {
+    return ((size_t)ring_stride(Kmax) << sb) * sizeof(float) + 64 * sizeof(float);
+}
+
+__device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
+
+// ----------------------------------------------------------------------------- part table
+
+// One thread per bucket: per-workgroup totals of parts, partial slots and split buckets.
+__global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__restrict__ bstart, int B, int sb,
+                                                          int *__restrict__ ptot) {
+    __shared__ int wsum[16];
+    const int bk = blockIdx.x * 1024 + threadIdx.x;
+    int k = 0;
+    if (bk < B) k = parts_of(bstart[bk + 1] - bstart[bk], load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE);
+    int t0, t1, t2;
+    (void)block_excl_scan<1024>(k, wsum, t0);
+    (void)block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
+    (void)block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
+    if (threadIdx.x == 0) {
+        ptot[3 * blockIdx.x] = t0;
+        ptot[3 * blockIdx.x + 1] = t1;
+        ptot[3 * blockIdx.x + 2] = t2;
+    }
+}
+
+// One thread per bucket again: its parts {bucket, first entry, end entry, slot} (slot -1
+// for a bucket of one part, else the bucket's first slot + part index), and for a split
+// bucket its entry {bucket, first slot, parts} in `multi`. bmeta = {parts, split buckets}.
+// At most 64 workgroups (B <= 65536).
+__global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
+                                                         const int *__restrict__ ptot, int4 *__restrict__ part,
+                                                         int4 *__restrict__ multi, int *__restrict__ bmeta) {
+    __shared__ int wsum[16];
+    __shared__ int base[3];
+    if (threadIdx.x < 64) {
+        int a0 = 0, a1 = 0, a2 = 0;
+        if ((int)threadIdx.x < (int)blockIdx.x) {
+            a0 = ptot[3 * threadIdx.x];
+            a1 = ptot[3 * threadIdx.x + 1];
+            a2 = ptot[3 * threadIdx.x + 2];
+        }
+        a0 = readlane(wave_scan_add(a0), 63);
+        a1 = readlane(wave_scan_add(a1), 63);
+        a2 = readlane(wave_scan_add(a2), 63);
+        if (threadIdx.x == 0) {
+            base[0] = a0;
+            base[1] = a1;
+            base[2] = a2;
+        }
+    }
+    __syncthreads();
+    const int bk = blockIdx.x * 1024 + threadIdx.x;
+    int k = 0, P = 1, s0 = 0, s1 = 0;
+    if (bk < B) {
+        P = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
+        s0 = bstart[bk];
+        s1 = bstart[bk + 1];
+        k = parts_of(s1 - s0, P);
+    }
+    int t0, t1, t2;
+    const int pp = base[0] + block_excl_scan<1024>(k, wsum, t0);
+    const int ss = base[1] + block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
+    const int mm = base[2] + block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
+    for (int q = 0; q < k; ++q)
+        part[pp + q] = make_int4(bk, s0 + q * P, min(s0 + (q + 1) * P, s1), k > 1 ? ss + q : -1);
+    if (k > 1) multi[mm] = make_int4(bk, ss, k, 0);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        bmeta[0] = base[0] + t0;
+        bmeta[1] = base[2] + t2;
+    }
+}
+
+// s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count).
+__device__ __forceinline__ void set_row_coef(const GDesc &gd, const float *__restrict__ inv_n, int r, float d,
+                                             float *__restrict__ srow, float2 *__restrict__ info) {
+    float s = 1.0f;
+    if (gd.flags & kLap) {
+        const float dd = d + ((gd.flags & kDiag) ? 1.0f : 0.0f);
+        s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
+    }
+    srow[r] = s;
+    int y = gd.labels[r - gd.node_off];
+    if (y < 0 || y >= gd.K) y = -1;
+    info[r] = node_info(y >= 0 ? s * inv_n[gd.class_off + y] : 0.0f, y);
+}
+
+// ----------------------------------------------------------------------------- windows
+
+// Entries [a, a + nwin*BWIN) of the bucketed arrays in windows of BWIN: lane l holds
+// entries a + i*BWIN + 4l .. +3 of window i, read with one 8- or 16-byte load per array.
+// The arrays are allocated kBucketWindowPad entries past their end, so every window of a
+// part lies inside them; the buffer range ends with the part's last window, so windows
+// past it read as 0 without touching memory. Entries past the part's end are masked by
+// the caller. Every load is unconditional, which keeps the compiler's counter waits exact
+// in the pipelined loops.
+template <typename KT, bool WEIGHTED, bool COLS>
+struct Windows {
+    __amdgpu_buffer_rsrc_t rk, rc, rv;
+    struct Raw {
+        int4 k, c;
+        float4 v;
+    };
+    __device__ __forceinline__ Windows(const KT *key, const int *col, const float *val, int a, int nwin) {
+        const int64_t n = (int64_t)nwin * BWIN;
+        rk = buffer_rsrc(key + a, n * (int64_t)sizeof(KT));
+        rc = buffer_rsrc(COLS ? (const void *)(col + a) : (const void *)key, COLS ? n * 4 : 0);
+        rv = buffer_rsrc(WEIGHTED ? (const void *)(val + a) : (const void *)key, WEIGHTED ? n * 4 : 0);
+    }
+    __device__ __forceinline__ void load(int i, int lane, Raw &r) const {
+        const uint32_t o = (uint32_t)(i * BWIN + BEPL * lane);
+        if (sizeof(KT) == 2) {
+            const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rk, 2 * o, 0, 0));
+            r.k = make_int4((int)(q.x & 0xFFFFu), (int)(q.x >> 16), (int)(q.y & 0xFFFFu), (int)(q.y >> 16));
+        } else {
+            r.k = buf_i4(rk, 4 * o);
+        }
+        if (COLS) r.c = buf_i4(rc, 4 * o);
+        r.v = WEIGHTED ? buf_f4(rv, 4 * o) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    }
+};
+
+// The part a wavefront works on (false past the last part) and its graph.
+__device__ __forceinline__ bool part_view(const Batch &b, int j, const int4 *__restrict__ part,
+                                          const int *__restrict__ bmeta, int sb, int4 &pt, GDesc &gd) {
+    if (j >= bmeta[0]) return false;
+    pt = part[j];
+    gd = load_desc(b, find_graph(b.node_offs, b.G, pt.x << sb));
+    return true;
+}
+
+// ----------------------------------------------------------------------------- degrees
+
+// Four independent wavefronts per workgroup, one part each. The R row sums are kept in
+// kDegCopies = 32 private copies per wavefront (rows padded to R + 1 so the copies of a
+// row sit in different banks): lanes l and l + 32 own copy l, the low half of the
+// wavefront adds its entries with plain LDS read-modify-writes, then the high half. A
+// window's 256 entries fall on only R rows, and LDS float atomics on shared sums run at a
+// small fraction of the plain LDS rate. The copies are added in copy order at the end.
+constexpr int kDegCopies = 32;
+template <typename KT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restrict__ key,
+                                                     const float *__restrict__ val,
+                                                     const int4 *__restrict__ part, const int *__restrict__ bmeta,
+                                                     int sb, const float *__restrict__ inv_n,
+                                                     float *__restrict__ dpart, float *__restrict__ srow,
+                                                     float2 *__restrict__ info) {
+    extern __shared__ float dsum_all[];  // [4][kDegCopies][R + 1]
+    const int lane = lane_id();
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int4 pt;
+    GDesc gd;
+    if (!part_view(b, blockIdx.x * 4 + wib, part, bmeta, sb, pt, gd)) return;
+    const bool lap = gd.flags & kLap;
+    const int R = 1 << sb, r = (pt.x << sb) + lane;
+    const bool own = lane < R && r >= gd.node_off && r < gd.node_off + gd.N;
+    if (!lap) {
+        // c_i = 1 / n_{y_i}; a split bucket's rows are set by bucket_degree_fix
+        if (pt.w < 0 && own) set_row_coef(gd, inv_n, r, 0.0f, srow, info);
+        return;
+    }
+    const int RS = R + 1;
+    float *dsum = dsum_all + wib * kDegCopies * RS;
+    for (int i = lane; i < kDegCopies * RS; i += 64) dsum[i] = 0.0f;
+    wave_lds_fence();
+    float *mine = dsum + (lane & (kDegCopies - 1)) * RS;
+    const bool wt = WEIGHTED && gd.weighted;
+    const int rmask = R - 1;
+    using W = Windows<KT, WEIGHTED, false>;
+    const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
+    const W win(key, nullptr, val, pt.y, nwin);
+    // window i: entries masked past the part's end add 0
+    auto add = [&](int i, const typename W::Raw &q) {
+        const int nv = min(BEPL, max(0, pt.z - (pt.y + i * BWIN + BEPL * lane)));
+        const int kk[BEPL] = {q.k.x, q.k.y, q.k.z, q.k.w};
+        const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
+        float x[BEPL];
+        int rw[BEPL];
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) {
+            x[j] = j < nv ? (wt ? vv[j] : 1.0f) : 0.0f;
+            rw[j] = kk[j] & rmask;
+        }
+        if (lane < 32) {
+#pragma unroll
+            for (int j = 0; j < BEPL; ++j) mine[rw[j]] += x[j];
+        }
+        wave_lds_fence();
+        if (lane >= 32) {
+#pragma unroll
+            for (int j = 0; j < BEPL; ++j) mine[rw[j]] += x[j];
+        }
+        wave_lds_fence();
+    };
+    // two register sets with fixed roles (no copies that would wait for loads in flight):
+    // the loads of window i+1 are in flight while window i is added
+    typename W::Raw A, Bw;
+    win.load(0, lane, A);
+    // (scheduling barriers keep each window's loads issued before the previous window's
+    // adds, which wait for their own loads only)
+    for (int i = 0; i < nwin; i += 2) {
+        win.load(i + 1, lane, Bw);
+        __builtin_amdgcn_sched_barrier(0);
+        add(i, A);
+        __builtin_amdgcn_sched_barrier(0);
+        win.load(i + 2, lane, A);
+        __builtin_amdgcn_sched_barrier(0);
+        add(i + 1, Bw);  // past the last window every entry is masked (adds 0)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_lds_fence();
+    float d = 0.0f;
+    if (lane < R)
+        for (int c = 0; c < kDegCopies; ++c) d += dsum[c * RS + lane];
+    if (pt.w >= 0) {
+        dpart[(int64_t)pt.w * 64 + lane] = d;
+        return;
+    }
+    if (own) set_row_coef(gd, inv_n, r, d, srow, info);
+}
+
+// One wavefront per split bucket: degrees = the parts' partial sums in part order (the
+// Laplacian), then s_i and c_i of the bucket's rows.
+__global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__restrict__ multi,
+                                                         const int *__restrict__ bmeta, int sb,
+                                                         const float *__restrict__ inv_n,
+                                                         const float *__restrict__ dpart, float *__restrict__ srow,
+                                                         float2 *__restrict__ info) {
+    const int lane = lane_id();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= bmeta[1]) return;
+    const int4 m = multi[i];
+    const int r0 = m.x << sb;
+    const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
+    float d = 0.0f;
+    if (gd.flags & kLap) {
+        const float *dp = dpart + (int64_t)m.y * 64 + lane;
+        int k = 0;
+        for (; k + 4 <= m.z; k += 4) {
+            const float x0 = dp[(int64_t)k * 64], x1 = dp[(int64_t)(k + 1) * 64];
+            const float x2 = dp[(int64_t)(k + 2) * 64], x3 = dp[(int64_t)(k + 3) * 64];
+            d += x0;
+            d += x1;
+            d += x2;
+            d += x3;
+        }
+        for (; k < m.z; ++k) d += dp[(int64_t)k * 64];
+    }
+    const int r = r0 + lane;
+    if (lane < (1 << sb) && r >= gd.node_off && r < gd.node_off + gd.N) set_row_coef(gd, inv_n, r, d, srow, info);
+}
+
+// ----------------------------------------------------------------------------- class sums
+
+// Lane-per-row finish of bucket rows r0 .. r0+R-1 held in acc[R][KP]: diagonal term, then
+// fac[row] = s_i, or 1/|row| under correlation (class columns K .. KP-1 are zero).
+__device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int KP, float *acc, float *fac,
+                                            const float2 *__restrict__ info, const float *__restrict__ srow,
+                                            int lane) {
+    const int r = r0 + lane;
+    if (lane < R && r >= gd.node_off && r < gd.node_off + gd.N) {
+        float *row = acc + lane * KP;
+        if (gd.flags & kDiag) {
+            const float2 q = info[r];
+            row[__float_as_int(q.y)] += q.x;
+        }
+        float ss = 0.0f;
+        const bool cor = gd.flags & kCor;
+        if (cor) {
+            const float4 *a4 = reinterpret_cast<const float4 *>(row);
+            for (int q = 0; q < (KP >> 2); ++q) {
+                const float4 t = a4[q];
+                ss += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
+            }
+        }
+        fac[lane] = row_factor((gd.flags & kLap) ? srow[r] : 1.0f, ss, cor);
+    }
+}
+
+// Z rows r0 .. of the bucket (those of the graph) as one flat run of floats, thread t of
+// nt writing floats t, t + nt, ... (non-temporal: Z is not read again here).
+__device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int KP, const float *acc,
+                                           const float *fac, int t, int nt) {
+    const int K = gd.K;
+    const int nv = max(0, min(R, gd.node_off + gd.N - r0));
+    const int F = nv * K;
+    float *z = gd.Z + (int64_t)(r0 - gd.node_off) * K;
+    const int qn = nt / K, rn = nt - qn * K;
+    int jj = t / K, kk = t - (t / K) * K;
+    for (int f = t; f < F; f += nt) {
+        __builtin_nontemporal_store(acc[jj * KP + kk] * fac[jj], z + f);
+        kk += rn;
+        jj += qn;
+        if (kk >= K) {
+            kk -= K;
+            ++jj;
+        }
+    }
+}
+
+template <typename KT, bool WEIGHTED>
+__global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict__ key, const int *__restrict__ col,
+                                                   const float *__restrict__ val,
+                                                   const int4 *__restrict__ part, const int *__restrict__ bmeta,
+                                                   int sb, const float2 *__restrict__ info,
+                                                   const float *__restrict__ srow, float *__restrict__ zpart, int zs) {
+    extern __shared__ float smem_b[];
+    const int lane = lane_id();
+    int4 pt;
+    GDesc gd;
+    if (!part_view(b, blockIdx.x, part, bmeta, sb, pt, gd)) return;
+    const int K = gd.K, KP = ring_stride(K), node_off = gd.node_off;
+    const int R = 1 << sb, rmask = R - 1;
+    float *acc = smem_b;           // [R][KP]
+    float *fac = smem_b + R * KP;  // [64] row factors
+    {
+        float4 *a4 = reinterpret_cast<float4 *>(acc);
+        for (int i = lane; i < ((R * KP) >> 2); i += 64) a4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    wave_lds_fence();
+
+    using W = Windows<KT, WEIGHTED, true>;
+    const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
+    const W win(key, col, val, pt.y, nwin);
+    const __amdgpu_buffer_rsrc_t r_inf = buffer_rsrc(info + node_off, (int64_t)gd.N * 8);
+    struct Prep {
+        int row[BEPL];
+        float x[BEPL];   // val, 0 when masked
+        float2 f[BEPL];  // {c_j, y_j}; masked entries read past the table: {0, class 0}
+    };
+    auto prep = [&](int i, const typename W::Raw &q, Prep &P) {
+        const int nv = min(BEPL, max(0, pt.z - (pt.y + i * BWIN + BEPL * lane)));
+        const int kk[BEPL] = {q.k.x, q.k.y, q.k.z, q.k.w};
+        const int cc[BEPL] = {q.c.x, q.c.y, q.c.z, q.c.w};
+        const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) {
+            const unsigned u = j < nv ? (unsigned)(cc[j] - node_off) : 0xFFFFFFFFu;
+            P.row[j] = kk[j] & rmask;
+            P.x[j] = j < nv ? vv[j] : 0.0f;
+            P.f[j] = buf_f2(r_inf, u << 3);
+        }
+    };
+    auto add = [&](const Prep &P) {
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) atomicAdd(&acc[P.row[j] * KP + __float_as_int(P.f[j].y)], P.x[j] * P.f[j].x);
+    };
+    // Three stages, two register sets each with fixed roles (no copies that would wait for
+    // loads in flight): the loads of window i+2 are issued first, then the gathers of
+    // window i+1 (which wait only for its loads, issued one step earlier), then window i
+    // is added (its gathers were issued one step earlier). The counter retires in issue
+    // order, so every wait leaves the younger loads in flight.
+    typename W::Raw R0, R1;
+    Prep P0, P1;
+    win.load(0, lane, R0);
+    win.load(1, lane, R1);
+    prep(0, R0, P0);
+    // (scheduling barriers keep that issue order)
+    for (int i = 0; i < nwin; i += 2) {
+        win.load(i + 2, lane, R0);
+        __builtin_amdgcn_sched_barrier(0);
+        prep(i + 1, R1, P1);
+        __builtin_amdgcn_sched_barrier(0);
+        add(P0);
+        __builtin_amdgcn_sched_barrier(0);
+        win.load(i + 3, lane, R1);
+        __builtin_amdgcn_sched_barrier(0);
+        prep(i + 2, R0, P0);
+        __builtin_amdgcn_sched_barrier(0);
+        add(P1);  // past the last window every entry is masked (adds 0)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_lds_fence();
+    const int r0 = pt.x << sb;
+    if (pt.w < 0) {
+        finish_rows(gd, r0, R, KP, acc, fac, info, srow, lane);
+        wave_lds_fence();
+        write_rows(gd, r0, R, KP, acc, fac, lane, 64);
+        return;
+    }
+    // a part of a split bucket: its raw sums of the R rows, flat [R][K]
+    float *zp = zpart + (int64_t)pt.w * zs;
+    const int q64 = 64 / K, r64 = 64 - q64 * K;
+    int jj = lane / K, kk = lane - (lane / K) * K;
+    for (int f = lane; f < R * K; f += 64) {
+        zp[f] = acc[jj * KP + kk];
+        kk += r64;
+        jj += q64;
+        if (kk >= K) {
+            kk -= K;
+            ++jj;
+        }
+    }
+}
+
+// One workgroup per split bucket: the parts' raw sums added in part order (four partial
+// loads in flight per thread), then the rows finished as in bucket_embed.
+__global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const int4 *__restrict__ multi,
+                                                                const int *__restrict__ bmeta, int sb,
+                                                                const float2 *__restrict__ info,
+                                                                const float *__restrict__ srow,
+                                                                const float *__restrict__ zpart, int zs) {
+    extern __shared__ float smem_b[];
+    if ((int)blockIdx.x >= bmeta[1]) return;
+    const int4 m = multi[blockIdx.x];
+    const int r0 = m.x << sb;
+    const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
+    const int K = gd.K, KP = ring_stride(K), R = 1 << sb;
+    const int t = threadIdx.x;
+    float *acc = smem_b;
+    float *fac = smem_b + R * KP;
+    {
+        // class columns K .. KP-1 stay zero (the norm reads whole 16-byte groups)
+        float4 *a4 = reinterpret_cast<float4 *>(acc);
+        for (int i = t; i < ((R * KP) >> 2); i += kFixThreads) a4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    __syncthreads();
+    const float *zp = zpart + (int64_t)m.y * zs;
+    for (int f = t; f < R * K; f += kFixThreads) {
+        const float *q = zp + f;
+        float s = 0.0f;
+        int k = 0;
+        for (; k + 4 <= m.z; k += 4) {
+            const float x0 = q[(int64_t)k * zs], x1 = q[(int64_t)(k + 1) * zs];
+            const float x2 = q[(int64_t)(k + 2) * zs], x3 = q[(int64_t)(k + 3) * zs];
+            s += x0;
+            s += x1;
+            s += x2;
+            s += x3;
+        }
+        for (; k < m.z; ++k) s += q[(int64_t)k * zs];
+        acc[(f / K) * KP + f % K] = s;
+    }
+    __syncthreads();
+    if (t < 64) finish_rows(gd, r0, R, KP, acc, fac, info, srow, t);
+    __syncthreads();
+    write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
+}
+
+// ----------------------------------------------------------------------------- launch
+
+template <typename KT, bool WEIGHTED>
+static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, const KT *key, hipStream_t s) {
+    const unsigned nbp = (unsigned)p.bparts;
+    const float *val = WEIGHTED ? wk.tval : nullptr;
+    prof_begin(kKBucketDegree, s);
+    const size_t dlds = (size_t)4 * kDegCopies * ((1 << p.sb) + 1) * sizeof(float);
+    hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key, val,
+                       wk.part, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info);
+    prof_end(kKBucketDegree, s);
+    const unsigned nm = (unsigned)(p.bslots / 2 + 1);
+    prof_begin(kKBucketDegreeFix, s);
+    hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
+                       wk.dpart, wk.srow, wk.info);
+    prof_end(kKBucketDegreeFix, s);
+    const size_t lds = bucket_lds(p.sb, p.Kmax);
+    const int zs = p.Kmax << p.sb;  // floats per partial slot
+    prof_begin(kKBucketEmbed, s);
+    hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
+                       wk.part, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs);
+    prof_end(kKBucketEmbed, s);
+    prof_begin(kKBucketEmbedFix, s);
+    hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
+                       wk.srow, wk.zpart, zs);
+    prof_end(kKBucketEmbedFix, s);
+}
+
+hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s) {
+    // keys of the bucketed entries: pass B's u16 row-in-bucket, else pass A's key (u16
+    // when the row's low bits fit, else the whole row)
+    const bool with_b = p.s2 > 0;
+    const bool key16 = with_b || p.sb + p.s2 <= 16;
+    const void *key = with_b ? (const void *)wk.tkey : (const void *)wk.akey;
+    const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
+    prof_begin(kKBucketPartCount, s);
+    hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot);
+    prof_end(kKBucketPartCount, s);
+    prof_begin(kKBucketPartFill, s);
+    hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
+                       wk.multi, wk.bmeta);
+    prof_end(kKBucketPartFill, s);
+    if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s);
+    else if (key16) launch_bucket_sums<uint16_t, false>(b, p, wk, (const uint16_t *)key, s);
+    else if (p.weighted) launch_bucket_sums<int, true>(b, p, wk, (const int *)key, s);
+    else launch_bucket_sums<int, false>(b, p, wk, (const int *)key, s);
+    return hipGetLastError();
+}
+
+}  // namespace gee

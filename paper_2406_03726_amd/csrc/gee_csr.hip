@@ -90,27 +90,6 @@ __device__ __forceinline__ int block_excl_scan256(int v, int *wsum, int &total) 
     return base + x - v;
 }
 
-// Exclusive scan of one int per thread over a workgroup of NT threads (DPP inside each
-// wavefront, then the wavefront totals); `total` is the sum. wsum needs NT/64 ints.
-template <int NT>
-__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total) {
-    constexpr int NWV = NT / 64;
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    const int x = wave_scan_add(v);
-    if (lane == 63) wsum[wv] = x;
-    __syncthreads();
-    int base = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < NWV; ++i) {
-        const int t = wsum[i];
-        base += i < wv ? t : 0;
-        tot += t;
-    }
-    total = tot;
-    __syncthreads();
-    return base + x - v;
-}
-
 // In-place exclusive scan of a[0..n) in LDS (n <= 4096), 256 threads; returns total.
 __device__ int block_excl_scan_lds(int *a, int n, int *wsum) {
     const int per = (n + 255) / 256;

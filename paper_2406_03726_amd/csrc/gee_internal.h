@@ -21,7 +21,7 @@ constexpr int kMaxBuckets = 65536;     // CSR buckets: 256 high digits x 256 low
 constexpr int kMaxBucketRowsLog2 = 12; // rows per bucket (the last sort pass ranks by row)
 constexpr int kMaxClasses = 128;
 #ifndef GEE_PART_TILE
-#define GEE_PART_TILE 2048
+#define GEE_PART_TILE 4096
 #endif
 constexpr int kPartTile = GEE_PART_TILE;  // entries per CSR partition tile (4 wavefronts)
 
@@ -105,6 +105,27 @@ __device__ __forceinline__ int wave_max_i(int v) {
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
 }
+// Exclusive scan of one int per thread over a workgroup of NT threads (DPP inside each
+// wavefront, then the wavefront totals); `total` is the sum. wsum needs NT/64 ints.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total) {
+    constexpr int NWV = NT / 64;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int x = wave_scan_add(v);
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) {
+        const int t = wsum[i];
+        base += i < wv ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
 __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     atomicOr(status, bit);
 }
@@ -137,6 +158,9 @@ __device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off)
 }
 __device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ unsigned buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 }
 __device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
@@ -238,6 +262,11 @@ struct Plan {
     int64_t parts = 0;   // floats of head/tail partial rows (all graphs)
     int cnt_blocks = 1;  // class-count partial workgroups (all graphs)
     int64_t cparts = 0;  // ints of class-count partials (all graphs)
+    // bucket path (edge lists straight to Z, gee_bucket.hip): every graph's first row is
+    // aligned to the 2^sb-row buckets; bparts / bslots bound the wavefront parts and the
+    // partial slots of buckets cut into several parts
+    bool bucket = false;
+    int64_t bparts = 0, bslots = 0;
 };
 
 // Workspace carve-up; every member is a device pointer into one caller buffer.
@@ -276,6 +305,13 @@ struct Work {
     float *headd = nullptr;    // [NWtot] degree partials (weighted Laplacian)
     float *taild = nullptr;    // [NWtot]
     int *dsplit = nullptr;     // [NWtot]
+    // bucket path
+    int4 *part = nullptr;      // [bparts] {bucket, first entry, end entry, partial slot or -1}
+    int4 *multi = nullptr;     // [bslots / 2] {bucket, first slot, parts} of buckets of several parts
+    int *ptot = nullptr;       // [3 * 64] per-workgroup totals of the part count
+    int *bmeta = nullptr;      // [4]: parts, buckets of several parts
+    float *dpart = nullptr;    // [bslots * 64] partial degrees
+    float *zpart = nullptr;    // [bslots << sb * Kmax] partial class sums
 };
 
 // ----------------------------------------------------------------------------- profiling
@@ -284,7 +320,8 @@ struct Work {
 enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
-    kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKNumKernels
+    kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKBucketPartCount, kKBucketPartFill, kKBucketDegree,
+    kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
@@ -313,5 +350,11 @@ size_t embed_lds_per_wave(int K);
 // Z from the CSR; n_entries = length of the col/val arrays (entries past it are never read).
 hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int *col, const float *val,
                         int64_t n_entries, const Work &wk, unsigned *status, hipStream_t s);
+// gee_bucket.hip: Z straight from the row buckets of the first two sort passes
+// (launch_csr_build), for plans with p.bucket.
+constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
+constexpr int kBucketDefaultPart = 4096;
+constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end
+hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s);
 
 }  // namespace gee

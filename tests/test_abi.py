@@ -74,6 +74,6 @@ def test_schedule_validation(lib):
 
     s = GeeSchedule(0, 0, 0, 0)
     assert lib.gee_default_schedule(10_000_000, 600_000, 50, 15, ctypes.byref(s)) == 0
-    assert s.wave_entries >= 256 and 1 <= s.waves_per_block <= 4 and s.tile_entries == 2048
+    assert s.wave_entries >= 256 and 1 <= s.waves_per_block <= 4 and s.tile_entries == 4096
     bad = GeeSchedule(300, 0, 0, 0)  # not a power of two
     assert lib.gee_embed_workspace_bytes(1000, 100, 3, 15, 1, ctypes.byref(bad)) == 0
