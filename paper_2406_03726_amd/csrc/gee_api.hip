@@ -231,7 +231,11 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
     p.sb = sb;
     p.B = (int32_t)((n1 + (1 << sb) - 1) >> sb);
     const int nbB = ilog2_ceil(p.B);
-    p.s2 = nbB <= 8 ? 0 : (nbB - 8 > nbB / 2 ? nbB - 8 : nbB / 2);
+#ifndef GEE_A_BITS_MAX
+#define GEE_A_BITS_MAX 8
+#endif
+    p.s2 = nbB <= 8 ? 0 : (nbB - GEE_A_BITS_MAX > nbB / 2 ? nbB - GEE_A_BITS_MAX : nbB / 2);
+    if (p.s2 > 8) p.s2 = 8;
     p.DA = (int)(((int64_t)p.B + (1 << p.s2) - 1) >> p.s2);
     p.tile = kPartTile;
     p.TA = (p.Vtot + p.tile - 1) / p.tile;

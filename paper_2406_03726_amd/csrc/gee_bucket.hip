@@ -36,10 +36,14 @@ namespace gee {
 constexpr int BEPL = 4;          // consecutive entries per lane in a window
 constexpr int BWIN = 64 * BEPL;  // entries per window
 constexpr int kFixThreads = 256; // threads per split bucket when combining class sums
+#ifndef GEE_EMBED_SCHED_BARRIER
+#define GEE_EMBED_SCHED_BARRIER 1
+#endif
 
-// LDS of one class-sum workgroup: R rows of ring_stride(K) floats and 64 row factors.
+// LDS of one class-sum workgroup: R rows of ring_stride(K) floats, 64 row factors and
+// (bucket_embed) a byte tag per class sum.
 static size_t bucket_lds(int sb, int Kmax) {
-    return ((size_t)ring_stride(Kmax) << sb) * sizeof(float) + 64 * sizeof(float);
+    return ((size_t)ring_stride(Kmax) << sb) * (sizeof(float) + 1) + 64 * sizeof(float);
 }
 
 __device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
@@ -160,11 +164,13 @@ struct Windows {
     }
 };
 
-// The part a wavefront works on (false past the last part) and its graph.
-__device__ __forceinline__ bool part_view(const Batch &b, int j, const int4 *__restrict__ part,
+// The part a wavefront works on (false past the last part) and its graph. The entry is
+// loaded together with the part count (from an index clamped to the table's capacity).
+__device__ __forceinline__ bool part_view(const Batch &b, int j, const int4 *__restrict__ part, int cap,
                                           const int *__restrict__ bmeta, int sb, int4 &pt, GDesc &gd) {
-    if (j >= bmeta[0]) return false;
-    pt = part[j];
+    const int n = bmeta[0];
+    pt = part[min(j, cap - 1)];
+    if (j >= n) return false;
     gd = load_desc(b, find_graph(b.node_offs, b.G, pt.x << sb));
     return true;
 }
@@ -181,8 +187,9 @@ constexpr int kDegCopies = 32;
 template <typename KT, bool WEIGHTED>
 __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restrict__ key,
                                                      const float *__restrict__ val,
-                                                     const int4 *__restrict__ part, const int *__restrict__ bmeta,
-                                                     int sb, const float *__restrict__ inv_n,
+                                                     const int4 *__restrict__ part, int cap,
+                                                     const int *__restrict__ bmeta, int sb,
+                                                     const float *__restrict__ inv_n,
                                                      float *__restrict__ dpart, float *__restrict__ srow,
                                                      float2 *__restrict__ info) {
     extern __shared__ float dsum_all[];  // [4][kDegCopies][R + 1]
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int4 pt;
     GDesc gd;
-    if (!part_view(b, blockIdx.x * 4 + wib, part, bmeta, sb, pt, gd)) return;
+    if (!part_view(b, blockIdx.x * 4 + wib, part, cap, bmeta, sb, pt, gd)) return;
     const bool lap = gd.flags & kLap;
     const int R = 1 << sb, r = (pt.x << sb) + lane;
     const bool own = lane < R && r >= gd.node_off && r < gd.node_off + gd.N;
@@ -294,16 +301,13 @@ __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__
 
 // Lane-per-row finish of bucket rows r0 .. r0+R-1 held in acc[R][KP]: diagonal term, then
 // fac[row] = s_i, or 1/|row| under correlation (class columns K .. KP-1 are zero).
+// q = {c_i, y_i} and s of the lane's row, loaded by the caller.
 __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int KP, float *acc, float *fac,
-                                            const float2 *__restrict__ info, const float *__restrict__ srow,
-                                            int lane) {
+                                            float2 q, float s, int lane) {
     const int r = r0 + lane;
     if (lane < R && r >= gd.node_off && r < gd.node_off + gd.N) {
         float *row = acc + lane * KP;
-        if (gd.flags & kDiag) {
-            const float2 q = info[r];
-            row[__float_as_int(q.y)] += q.x;
-        }
+        if (gd.flags & kDiag) row[__float_as_int(q.y)] += q.x;
         float ss = 0.0f;
         const bool cor = gd.flags & kCor;
         if (cor) {
@@ -313,7 +317,7 @@ __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int 
                 ss += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
             }
         }
-        fac[lane] = row_factor((gd.flags & kLap) ? srow[r] : 1.0f, ss, cor);
+        fac[lane] = row_factor((gd.flags & kLap) ? s : 1.0f, ss, cor);
     }
 }
 
@@ -341,18 +345,25 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
 template <typename KT, bool WEIGHTED>
 __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val,
-                                                   const int4 *__restrict__ part, const int *__restrict__ bmeta,
-                                                   int sb, const float2 *__restrict__ info,
+                                                   const int4 *__restrict__ part, int cap,
+                                                   const int *__restrict__ bmeta, int sb,
+                                                   const float2 *__restrict__ info,
                                                    const float *__restrict__ srow, float *__restrict__ zpart, int zs) {
     extern __shared__ float smem_b[];
     const int lane = lane_id();
     int4 pt;
     GDesc gd;
-    if (!part_view(b, blockIdx.x, part, bmeta, sb, pt, gd)) return;
+    if (!part_view(b, blockIdx.x, part, cap, bmeta, sb, pt, gd)) return;
     const int K = gd.K, KP = ring_stride(K), node_off = gd.node_off;
     const int R = 1 << sb, rmask = R - 1;
     float *acc = smem_b;           // [R][KP]
     float *fac = smem_b + R * KP;  // [64] row factors
+    unsigned char *tag = reinterpret_cast<unsigned char *>(fac + 64);  // [R][KP] entry ids
+    // the lane's row {c_i, y_i} and s_i, needed at the end, loaded now
+    const int r0 = pt.x << sb, rl = r0 + lane;
+    const bool own = lane < R && rl >= node_off && rl < node_off + gd.N;
+    const float2 q_own = own ? info[rl] : make_float2(0.0f, 0.0f);
+    const float s_own = own ? srow[rl] : 0.0f;
     {
         float4 *a4 = reinterpret_cast<float4 *>(acc);
         for (int i = lane; i < ((R * KP) >> 2); i += 64) a4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -381,9 +392,38 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             P.f[j] = buf_f2(r_inf, u << 3);
         }
     };
+    // Window update without LDS float atomics for most entries (they run at a small
+    // fraction of the plain LDS rate): every entry with a non-zero term writes its id
+    // (4 * lane + j) into the byte tag of its (row, class) word; exactly one entry per word
+    // reads its own id back, and those entries (all at distinct words) add with plain
+    // reads and writes; the others then add with atomics. Zero terms are skipped (adding
+    // them changes nothing: the sums start at +0 and never hold -0). The order in which a
+    // word receives its terms is fixed by the entries' places in the window.
     auto add = [&](const Prep &P) {
+        int ad[BEPL];
+        float xv[BEPL];
 #pragma unroll
-        for (int j = 0; j < BEPL; ++j) atomicAdd(&acc[P.row[j] * KP + __float_as_int(P.f[j].y)], P.x[j] * P.f[j].x);
+        for (int j = 0; j < BEPL; ++j) {
+            ad[j] = P.row[j] * KP + __float_as_int(P.f[j].y);
+            xv[j] = P.x[j] * P.f[j].x;
+        }
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j)
+            if (xv[j] != 0.0f) tag[ad[j]] = (unsigned char)(BEPL * lane + j);
+        wave_lds_fence();
+        bool win[BEPL];
+        float old[BEPL];
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) win[j] = xv[j] != 0.0f && tag[ad[j]] == (unsigned char)(BEPL * lane + j);
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) old[j] = win[j] ? acc[ad[j]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j)
+            if (win[j]) acc[ad[j]] = old[j] + xv[j];
+        wave_lds_fence();
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j)
+            if (xv[j] != 0.0f && !win[j]) atomicAdd(&acc[ad[j]], xv[j]);
     };
     // Three stages, two register sets each with fixed roles (no copies that would wait for
     // loads in flight): the loads of window i+2 are issued first, then the gathers of
@@ -396,24 +436,29 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     win.load(1, lane, R1);
     prep(0, R0, P0);
     // (scheduling barriers keep that issue order)
+#if GEE_EMBED_SCHED_BARRIER
+#define EMB_SB() __builtin_amdgcn_sched_barrier(0)
+#else
+#define EMB_SB() (void)0
+#endif
     for (int i = 0; i < nwin; i += 2) {
         win.load(i + 2, lane, R0);
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
         prep(i + 1, R1, P1);
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
         add(P0);
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
         win.load(i + 3, lane, R1);
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
         prep(i + 2, R0, P0);
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
         add(P1);  // past the last window every entry is masked (adds 0)
-        __builtin_amdgcn_sched_barrier(0);
+        EMB_SB();
     }
+#undef EMB_SB
     wave_lds_fence();
-    const int r0 = pt.x << sb;
     if (pt.w < 0) {
-        finish_rows(gd, r0, R, KP, acc, fac, info, srow, lane);
+        finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, lane);
         wave_lds_fence();
         write_rows(gd, r0, R, KP, acc, fac, lane, 64);
         return;
@@ -472,7 +517,11 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
         acc[(f / K) * KP + f % K] = s;
     }
     __syncthreads();
-    if (t < 64) finish_rows(gd, r0, R, KP, acc, fac, info, srow, t);
+    if (t < 64) {
+        const int rl = r0 + t;
+        const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
+        finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t);
+    }
     __syncthreads();
     write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
 }
@@ -486,7 +535,7 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     prof_begin(kKBucketDegree, s);
     const size_t dlds = (size_t)4 * kDegCopies * ((1 << p.sb) + 1) * sizeof(float);
     hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key, val,
-                       wk.part, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info);
+                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info);
     prof_end(kKBucketDegree, s);
     const unsigned nm = (unsigned)(p.bslots / 2 + 1);
     prof_begin(kKBucketDegreeFix, s);
@@ -497,7 +546,7 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     const int zs = p.Kmax << p.sb;  // floats per partial slot
     prof_begin(kKBucketEmbed, s);
     hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
-                       wk.part, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs);
+                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
     hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
