@@ -439,6 +439,59 @@ int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &ou
     return GEE_OK;
 }
 
+// A batch as consecutive chunks, each launched on its own (one after the other on the
+// stream) so that every graph takes the path and bucket size it takes alone: graphs are
+// packed in order while their rows, each graph rounded up to 32-row buckets, total at most
+// kMaxBuckets * 32 (the bucket path then uses 32-row buckets, as every such graph alone);
+// a graph of more rows forms a chunk of its own. The summation order, and so every bit of
+// Z, depends on the bucket size, so this keeps batched and plain results identical.
+struct Chunk {
+    int g0 = 0, g1 = 0;
+    Plan p;
+    std::vector<GDesc> d;
+    size_t off = 0;  // workspace offset
+};
+constexpr unsigned kEmbedParts = kPCount | kPPart | kPCsrOut | kPEmbed;
+int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t &total) {
+    const int64_t cap = (int64_t)kMaxBuckets << 5;
+    const int G = (int)gs.size();
+    std::vector<std::pair<int, int>> ranges;
+    int b = 0;
+    int64_t rows = 0;
+    for (int g = 0; g < G; ++g) {
+        const int64_t n = gs[g].N;
+        if (n > cap) {
+            if (b < g) ranges.push_back({b, g});
+            ranges.push_back({g, g + 1});
+            b = g + 1;
+            rows = 0;
+            continue;
+        }
+        const int64_t next = ((rows + 31) >> 5 << 5) + n;
+        if (b < g && next > cap) {
+            ranges.push_back({b, g});
+            b = g;
+            rows = n;
+        } else {
+            rows = next;
+        }
+    }
+    if (b < G) ranges.push_back({b, G});
+    out.assign(ranges.size(), Chunk());
+    total = 0;
+    for (size_t i = 0; i < ranges.size(); ++i) {
+        Chunk &c = out[i];
+        c.g0 = ranges[i].first;
+        c.g1 = ranges[i].second;
+        int rc = make_plan(gs.data() + c.g0, c.g1 - c.g0, false, c.p, c.d, true);
+        if (rc) return rc;
+        Work w;
+        c.off = total;
+        total += (carve(c.p, kEmbedParts, nullptr, w) + kAlign - 1) / kAlign * kAlign;
+    }
+    return GEE_OK;
+}
+
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 // Stream of a call about to enqueue kernels. HIP keeps a thread's last error until it is
 // read; one left by the application's own earlier calls is consumed here, so the checks
@@ -721,11 +774,10 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
 size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G) {
     std::vector<GraphIn> gs;
     if (graphs_from_api(graphs, G, gs, true)) return 0;
-    Plan p;
-    std::vector<GDesc> d;
-    if (make_plan(gs.data(), G, false, p, d, true)) return 0;
-    Work w;
-    return carve(p, kPCount | kPPart | kPCsrOut | kPEmbed, nullptr, w);
+    std::vector<Chunk> ch;
+    size_t total = 0;
+    if (plan_chunks(gs, ch, total)) return 0;
+    return total;
 }
 
 int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
@@ -733,20 +785,26 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
     std::vector<GraphIn> gs;
     int rc = graphs_from_api(graphs, G, gs);
     if (rc) return rc;
-    Plan p;
-    std::vector<GDesc> d;
-    if ((rc = make_plan(gs.data(), G, false, p, d, true))) return rc;
-    if (p.Ntot == 0) return GEE_OK;
+    std::vector<Chunk> ch;
+    size_t total = 0;
+    if ((rc = plan_chunks(gs, ch, total))) return rc;
+    int64_t rows = 0;
+    for (const Chunk &c : ch) rows += c.p.Ntot;
+    if (rows == 0) return GEE_OK;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
-    Work wk;
-    const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
-    if (!workspace || workspace_bytes < carve(p, parts, nullptr, wk)) return GEE_ERR_WORKSPACE;
-    carve(p, parts, (char *)workspace, wk);
+    if (!workspace || workspace_bytes < total) return GEE_ERR_WORKSPACE;
     hipStream_t s = launch_stream(stream);
-    Batch b;
-    hipError_t e = make_batch(p, d, wk, s, false, b);
-    if (e == hipSuccess) e = enqueue_embed(b, p, wk, st, s);
+    hipError_t e = hipSuccess;
+    for (const Chunk &c : ch) {
+        if (c.p.Ntot == 0) continue;
+        Work wk;
+        carve(c.p, kEmbedParts, (char *)workspace + c.off, wk);
+        Batch b;
+        e = make_batch(c.p, c.d, wk, s, false, b);
+        if (e == hipSuccess) e = enqueue_embed(b, c.p, wk, st, s);
+        if (e != hipSuccess) break;
+    }
     return hip_status(e);
 }
 
@@ -756,37 +814,42 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     std::vector<GraphIn> gs;
     int rc = graphs_from_api(graphs, G, gs);
     if (rc) return rc;
-    Plan p;
-    std::vector<GDesc> d;
-    if ((rc = make_plan(gs.data(), G, false, p, d, true))) return rc;
-    if (p.Ntot == 0) return GEE_ERR_ARG;
+    std::vector<Chunk> ch;
+    size_t total = 0;
+    if ((rc = plan_chunks(gs, ch, total))) return rc;
+    int64_t rows = 0;
+    for (const Chunk &c : ch) rows += c.p.Ntot;
+    if (rows == 0) return GEE_ERR_ARG;
     unsigned *st = nullptr;
     if ((rc = device_status(&st))) return rc;
     gee_batch_plan *pl = new (std::nothrow) gee_batch_plan();
     if (!pl) return GEE_ERR_OOM;
     pl->G = G;
     (void)hipGetDevice(&pl->device);
-    Work wk;
-    const unsigned parts = kPCount | kPPart | kPCsrOut | kPEmbed;
-    pl->ws_bytes = carve(p, parts, nullptr, wk);
+    pl->ws_bytes = total;
     hipStream_t cs = nullptr;
     hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
-    if (e == hipSuccess) {
-        carve(p, parts, (char *)pl->ws, wk);
-        Batch b;
-        (void)hipGetLastError();  // see launch_stream
-        e = make_batch(p, d, wk, nullptr, true, b);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            t_capturing = true;
-            hipError_t e1 = enqueue_embed(b, p, wk, st, cs);
-            t_capturing = false;
-            hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
-            e = e1 != hipSuccess ? e1 : e2;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    // every chunk has its own workspace region, so all tables are written before capture
+    std::vector<Batch> bs(ch.size());
+    std::vector<Work> wks(ch.size());
+    (void)hipGetLastError();  // see launch_stream
+    for (size_t i = 0; i < ch.size() && e == hipSuccess; ++i) {
+        if (ch[i].p.Ntot == 0) continue;
+        carve(ch[i].p, kEmbedParts, (char *)pl->ws + ch[i].off, wks[i]);
+        e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i]);
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        hipError_t e1 = hipSuccess;
+        for (size_t i = 0; i < ch.size() && e1 == hipSuccess; ++i)
+            if (ch[i].p.Ntot > 0) e1 = enqueue_embed(bs[i], ch[i].p, wks[i], st, cs);
+        t_capturing = false;
+        hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
+        e = e1 != hipSuccess ? e1 : e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         gee_batch_plan_destroy(pl);

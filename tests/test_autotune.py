@@ -21,16 +21,16 @@ def test_tune_picks_fastest_and_is_deterministic():
     shapes = [(1000, 100, 3, 15), (1100, 110, 3, 15), (100_000, 2000, 100, 15)]
 
     def fake_time(shape, sched):
-        # best at 1024 for the small shapes, 4096 for the large one; a tie elsewhere
-        target = 1024 if shape[0] < 50_000 else 4096
+        # best at 4096 for the small shapes, 16384 for the large one; a tie elsewhere
+        target = 4096 if shape[0] < 50_000 else 16384
         return abs(sched["wave_entries"] - target) + 1.0
 
     t = at.tune(shapes, fake_time)
-    assert t.lookup(1000, 100, 3, 15) == {"wave_entries": 1024}
-    assert t.lookup(100_000, 2000, 100, 15) == {"wave_entries": 4096}
+    assert t.lookup(1000, 100, 3, 15) == {"wave_entries": 4096}
+    assert t.lookup(100_000, 2000, 100, 15) == {"wave_entries": 16384}
     # ties resolve to the smaller candidate
     t2 = at.tune([(1000, 100, 3, 15)], lambda s, c: 1.0)
-    assert t2.lookup(1000, 100, 3, 15) == {"wave_entries": 256}
+    assert t2.lookup(1000, 100, 3, 15) == {"wave_entries": 2048}
 
 
 def test_lookup_falls_back_to_nearest_and_default():

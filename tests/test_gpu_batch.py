@@ -132,3 +132,29 @@ def test_batch_single_and_errors():
     gee.gee_embed_batch(items)
     torch.cuda.synchronize()
     assert torch.equal(items[0]["Z"], items[2]["Z"])
+
+
+def test_batch_beyond_one_bucket_size_keeps_plain_bits():
+    """A batch of more than 2^21 rows (one graph alone above it): every graph still takes
+    the bucket size it takes alone, so batched, planned and plain Z agree bit for bit."""
+    sizes = [(700_000, 1_400_000, 8), (2_300_000, 3_000_000, 5), (900_000, 1_000_000, 12),
+             (600_000, 900_000, 3), (50, 120, 2)]
+    gs = [random_small_graph(500 + i, N=N, E=E, K=K, weighted=bool(i % 2), sym=True).with_options(True, True, True)
+          for i, (N, E, K) in enumerate(sizes)]
+    _label(f"batch beyond 2^21 rows: {sum(g.N for g in gs)} rows")
+    items = _dev_graphs(gs)
+    gee.gee_embed_batch(items)
+    torch.cuda.synchronize()
+    plain = _plain(items)
+    for i, (it, zp) in enumerate(zip(items, plain)):
+        assert torch.equal(it["Z"], zp), f"graph {i} (N={gs[i].N})"
+    plan = gee.BatchPlan(items)
+    for it in items:
+        it["Z"].fill_(float("nan"))
+    plan.launch()
+    torch.cuda.synchronize()
+    for i, (it, zp) in enumerate(zip(items, plain)):
+        assert torch.equal(it["Z"], zp), f"planned graph {i}"
+    plan.destroy()
+    assert_close(items[4]["Z"], or_embed_graph(gs[4]), "small graph vs oracle")
+    assert_close(items[3]["Z"], or_embed_graph(gs[3]), "600k-row graph vs oracle")
