@@ -45,12 +45,12 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return 4 * N
     if name == "a_hist":
         return 8 * E
-    if name == "a_scatter":  # edge list in, (row, col[, w]) per entry out
-        return (8 + wv) * E + (4 + 4 + wv) * M
+    if name == "a_scatter":  # edge list in, (low row bits u16, col[, w]) per entry out
+        return (8 + wv) * E + (2 + 4 + wv) * M
     if name == "b_hist":
-        return 4 * M
-    if name == "b_scatter":  # (row, col[, w]) in, (row in bucket u16, col[, w]) out
-        return (4 + 4 + wv) * M + (2 + 4 + wv) * M
+        return 2 * M
+    if name == "b_scatter":  # (low row bits u16, col[, w]) in, (row in bucket u16, col[, w]) out
+        return 2 * (2 + 4 + wv) * M
     if name == "bucket_sort":  # all buckets counted as if sorted here (an upper bound when
         # the largest buckets go to the pass-C tiles): key, col, val in; CSR out
         return (2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)

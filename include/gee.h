@@ -94,11 +94,11 @@ typedef struct {
 } gee_schedule;
 /* Paths. gee_embed, gee_embed_ws and batches take the bucket path whenever the launch's
    rows fit 65536 buckets of 64 rows (2^22 rows, batch graphs each rounded up to the
-   bucket size): the entries are partitioned into buckets of 32 consecutive rows (64 when
-   32 would need more than 65536 buckets) and every bucket's class sums are accumulated
+   bucket size): the entries are partitioned into buckets of 64 consecutive rows (32 when a
+   graph has K > 64 and 32 rows suffice) and every bucket's class sums are accumulated
    whole, without building the CSR. Larger launches, and gee_embed_csr, take the CSR path.
-   A graph's Z is bitwise the same alone and in any batch that takes the same path with
-   the same bucket size. */
+   Batches run as chunks that give every graph the path and bucket size it gets alone, so a
+   graph's Z is bitwise the same alone and in any batch. */
 
 int gee_abi_version(void);
 const char *gee_status_string(int status);

@@ -108,14 +108,19 @@ int check_schedule(const gee_schedule &sc) {
 // Default CSR entries per embed wavefront for a graph with this many entries.
 int default_wave_entries(int64_t Mcap) { return Mcap >= (1 << 20) ? 1024 : 512; }
 
-// Bucket path rows per bucket (log2) for a launch of these graphs: 32-row buckets, or 64
-// when 32 would need more than kMaxBuckets; -1 when 64 rows are not enough either. Graph
-// offsets are then aligned to the bucket size, so a graph's buckets are its own.
+// Bucket path rows per bucket (log2) for a launch of these graphs: 64-row buckets when
+// every graph's class sums fit 64 floats a row (the wavefront's LDS block stays at most
+// 16 KiB), else 32-row buckets, raised to 64 when 32 would need more than kMaxBuckets; -1
+// when 64 rows are not enough either. Graph offsets are then aligned to the bucket size,
+// so a graph's buckets are its own.
 #ifndef GEE_BUCKET_SB_MIN
 #define GEE_BUCKET_SB_MIN 5
 #endif
+int preferred_bucket_sb(int K) { return ring_stride(K) <= 64 ? 6 : GEE_BUCKET_SB_MIN; }
 int bucket_path_sb(const GraphIn *gs, int G) {
-    for (int sb = GEE_BUCKET_SB_MIN; sb <= 6; ++sb) {
+    int sb0 = 6;
+    for (int g = 0; g < G; ++g) sb0 = preferred_bucket_sb(gs[g].K) < sb0 ? preferred_bucket_sb(gs[g].K) : sb0;
+    for (int sb = sb0; sb <= 6; ++sb) {
         int64_t n = 0;
         for (int g = 0; g < G; ++g) n = ((n + (1 << sb) - 1) >> sb << sb) + gs[g].N;
         if (n <= kMaxBatchNodes && ((n + (1 << sb) - 1) >> sb) <= kMaxBuckets) return sb;
@@ -439,51 +444,57 @@ int graphs_from_api(const gee_graph *graphs, int32_t G, std::vector<GraphIn> &ou
     return GEE_OK;
 }
 
-// A batch as consecutive chunks, each launched on its own (one after the other on the
-// stream) so that every graph takes the path and bucket size it takes alone: graphs are
-// packed in order while their rows, each graph rounded up to 32-row buckets, total at most
-// kMaxBuckets * 32 (the bucket path then uses 32-row buckets, as every such graph alone);
-// a graph of more rows forms a chunk of its own. The summation order, and so every bit of
-// Z, depends on the bucket size, so this keeps batched and plain results identical.
+// A batch as chunks, each launched on its own (one after the other on the stream) so that
+// every graph takes the path and bucket size it takes alone: graphs are grouped by their
+// preferred bucket size (64 rows for K <= 64, else 32) and packed in order while their
+// rows, each graph rounded up to that bucket size, total at most kMaxBuckets buckets; a
+// graph of more rows forms a chunk of its own. The summation order, and so every bit of Z,
+// depends on the bucket size, so this keeps batched and plain results identical.
 struct Chunk {
-    int g0 = 0, g1 = 0;
+    std::vector<GraphIn> gs;
     Plan p;
     std::vector<GDesc> d;
     size_t off = 0;  // workspace offset
 };
 constexpr unsigned kEmbedParts = kPCount | kPPart | kPCsrOut | kPEmbed;
 int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t &total) {
-    const int64_t cap = (int64_t)kMaxBuckets << 5;
-    const int G = (int)gs.size();
-    std::vector<std::pair<int, int>> ranges;
-    int b = 0;
-    int64_t rows = 0;
-    for (int g = 0; g < G; ++g) {
-        const int64_t n = gs[g].N;
-        if (n > cap) {
-            if (b < g) ranges.push_back({b, g});
-            ranges.push_back({g, g + 1});
-            b = g + 1;
+    out.clear();
+    for (int sbp : {6, GEE_BUCKET_SB_MIN}) {
+        const int64_t cap = (int64_t)kMaxBuckets << sbp;
+        std::vector<GraphIn> cur;
+        int64_t rows = 0;
+        auto flush = [&]() {
+            if (!cur.empty()) {
+                out.emplace_back();
+                out.back().gs.swap(cur);
+            }
+            cur.clear();
             rows = 0;
-            continue;
+        };
+        for (const GraphIn &x : gs) {
+            if (preferred_bucket_sb(x.K) != sbp) continue;
+            const int64_t n = x.N;
+            if (n > cap) {
+                flush();
+                cur.push_back(x);
+                flush();
+                continue;
+            }
+            const int64_t next = ((rows + (1 << sbp) - 1) >> sbp << sbp) + n;
+            if (!cur.empty() && next > cap) {
+                flush();
+                rows = n;
+            } else {
+                rows = next;
+            }
+            cur.push_back(x);
         }
-        const int64_t next = ((rows + 31) >> 5 << 5) + n;
-        if (b < g && next > cap) {
-            ranges.push_back({b, g});
-            b = g;
-            rows = n;
-        } else {
-            rows = next;
-        }
+        flush();
+        if (sbp == GEE_BUCKET_SB_MIN) break;
     }
-    if (b < G) ranges.push_back({b, G});
-    out.assign(ranges.size(), Chunk());
     total = 0;
-    for (size_t i = 0; i < ranges.size(); ++i) {
-        Chunk &c = out[i];
-        c.g0 = ranges[i].first;
-        c.g1 = ranges[i].second;
-        int rc = make_plan(gs.data() + c.g0, c.g1 - c.g0, false, c.p, c.d, true);
+    for (Chunk &c : out) {
+        int rc = make_plan(c.gs.data(), (int)c.gs.size(), false, c.p, c.d, true);
         if (rc) return rc;
         Work w;
         c.off = total;

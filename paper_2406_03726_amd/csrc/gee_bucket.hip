@@ -2,9 +2,10 @@
 //
 // The edge-list entry points need every row's sums, not the CSR itself. After the first
 // two partition passes of the sort (gee_csr.hip) the entries of each bucket of R
-// consecutive rows (R = 32, or 64 for launches of more than 2^21 rows) lie together, in
-// input order. Each bucket is cut into parts of at most P entries (P = the graph's
-// wave_entries, at least kBucketMinPart), one wavefront per part:
+// consecutive rows (R = 64; 32 when a graph of the launch has K > 64 and 32-row buckets
+// hold the launch's rows) lie together, in input order. Each bucket is cut into parts of
+// at most P entries (P = the graph's wave_entries, at least kBucketMinPart), one
+// wavefront per part:
 //
 //   * bucket_part_count / bucket_part_fill  the part table {bucket, entries, partial slot}
 //                    and the list of buckets of several parts (two passes of prefix sums
