@@ -30,6 +30,8 @@
 // first row is aligned to R), and a graph's buckets and parts depend on that graph alone,
 // so its Z is the same alone and in a batch with the same R. The diagonal term is added
 // after the entries of its row.
+#include <algorithm>
+
 #include "gee_internal.h"
 
 namespace gee {
@@ -267,35 +269,36 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
     if (own) set_row_coef(gd, inv_n, r, d, srow, info);
 }
 
-// One wavefront per split bucket: degrees = the parts' partial sums in part order (the
-// Laplacian), then s_i and c_i of the bucket's rows.
+// Wavefronts take the split buckets in turn: degrees = the parts' partial sums in part
+// order (the Laplacian), then s_i and c_i of the bucket's rows.
 __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__restrict__ multi,
                                                          const int *__restrict__ bmeta, int sb,
                                                          const float *__restrict__ inv_n,
                                                          const float *__restrict__ dpart, float *__restrict__ srow,
                                                          float2 *__restrict__ info) {
     const int lane = lane_id();
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= bmeta[1]) return;
-    const int4 m = multi[i];
-    const int r0 = m.x << sb;
-    const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
-    float d = 0.0f;
-    if (gd.flags & kLap) {
-        const float *dp = dpart + (int64_t)m.y * 64 + lane;
-        int k = 0;
-        for (; k + 4 <= m.z; k += 4) {
-            const float x0 = dp[(int64_t)k * 64], x1 = dp[(int64_t)(k + 1) * 64];
-            const float x2 = dp[(int64_t)(k + 2) * 64], x3 = dp[(int64_t)(k + 3) * 64];
-            d += x0;
-            d += x1;
-            d += x2;
-            d += x3;
+    const int nmulti = bmeta[1];
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nmulti; i += gridDim.x * 4) {
+        const int4 m = multi[i];
+        const int r0 = m.x << sb;
+        const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
+        float d = 0.0f;
+        if (gd.flags & kLap) {
+            const float *dp = dpart + (int64_t)m.y * 64 + lane;
+            int k = 0;
+            for (; k + 4 <= m.z; k += 4) {
+                const float x0 = dp[(int64_t)k * 64], x1 = dp[(int64_t)(k + 1) * 64];
+                const float x2 = dp[(int64_t)(k + 2) * 64], x3 = dp[(int64_t)(k + 3) * 64];
+                d += x0;
+                d += x1;
+                d += x2;
+                d += x3;
+            }
+            for (; k < m.z; ++k) d += dp[(int64_t)k * 64];
         }
-        for (; k < m.z; ++k) d += dp[(int64_t)k * 64];
+        const int r = r0 + lane;
+        if (lane < (1 << sb) && r >= gd.node_off && r < gd.node_off + gd.N) set_row_coef(gd, inv_n, r, d, srow, info);
     }
-    const int r = r0 + lane;
-    if (lane < (1 << sb) && r >= gd.node_off && r < gd.node_off + gd.N) set_row_coef(gd, inv_n, r, d, srow, info);
 }
 
 // ----------------------------------------------------------------------------- class sums
@@ -479,52 +482,56 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     }
 }
 
-// One workgroup per split bucket: the parts' raw sums added in part order (four partial
-// loads in flight per thread), then the rows finished as in bucket_embed.
+// Workgroups take the split buckets in turn (the grid is sized for the largest possible
+// count; far fewer are split): the parts' raw sums added in part order (four partial loads
+// in flight per thread), then the rows finished as in bucket_embed.
 __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const int4 *__restrict__ multi,
                                                                 const int *__restrict__ bmeta, int sb,
                                                                 const float2 *__restrict__ info,
                                                                 const float *__restrict__ srow,
                                                                 const float *__restrict__ zpart, int zs) {
     extern __shared__ float smem_b[];
-    if ((int)blockIdx.x >= bmeta[1]) return;
-    const int4 m = multi[blockIdx.x];
-    const int r0 = m.x << sb;
-    const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
-    const int K = gd.K, KP = ring_stride(K), R = 1 << sb;
-    const int t = threadIdx.x;
-    float *acc = smem_b;
-    float *fac = smem_b + R * KP;
-    {
-        // class columns K .. KP-1 stay zero (the norm reads whole 16-byte groups)
-        float4 *a4 = reinterpret_cast<float4 *>(acc);
-        for (int i = t; i < ((R * KP) >> 2); i += kFixThreads) a4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    __syncthreads();
-    const float *zp = zpart + (int64_t)m.y * zs;
-    for (int f = t; f < R * K; f += kFixThreads) {
-        const float *q = zp + f;
-        float s = 0.0f;
-        int k = 0;
-        for (; k + 4 <= m.z; k += 4) {
-            const float x0 = q[(int64_t)k * zs], x1 = q[(int64_t)(k + 1) * zs];
-            const float x2 = q[(int64_t)(k + 2) * zs], x3 = q[(int64_t)(k + 3) * zs];
-            s += x0;
-            s += x1;
-            s += x2;
-            s += x3;
+    const int nmulti = bmeta[1];
+    for (int i = blockIdx.x; i < nmulti; i += gridDim.x) {
+        const int4 m = multi[i];
+        const int r0 = m.x << sb;
+        const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
+        const int K = gd.K, KP = ring_stride(K), R = 1 << sb;
+        const int t = threadIdx.x;
+        float *acc = smem_b;
+        float *fac = smem_b + R * KP;
+        __syncthreads();  // the previous bucket's rows are written
+        {
+            // class columns K .. KP-1 stay zero (the norm reads whole 16-byte groups)
+            float4 *a4 = reinterpret_cast<float4 *>(acc);
+            for (int q = t; q < ((R * KP) >> 2); q += kFixThreads) a4[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-        for (; k < m.z; ++k) s += q[(int64_t)k * zs];
-        acc[(f / K) * KP + f % K] = s;
+        __syncthreads();
+        const float *zp = zpart + (int64_t)m.y * zs;
+        for (int f = t; f < R * K; f += kFixThreads) {
+            const float *q = zp + f;
+            float s = 0.0f;
+            int k = 0;
+            for (; k + 4 <= m.z; k += 4) {
+                const float x0 = q[(int64_t)k * zs], x1 = q[(int64_t)(k + 1) * zs];
+                const float x2 = q[(int64_t)(k + 2) * zs], x3 = q[(int64_t)(k + 3) * zs];
+                s += x0;
+                s += x1;
+                s += x2;
+                s += x3;
+            }
+            for (; k < m.z; ++k) s += q[(int64_t)k * zs];
+            acc[(f / K) * KP + f % K] = s;
+        }
+        __syncthreads();
+        if (t < 64) {
+            const int rl = r0 + t;
+            const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
+            finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t);
+        }
+        __syncthreads();
+        write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
     }
-    __syncthreads();
-    if (t < 64) {
-        const int rl = r0 + t;
-        const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
-        finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t);
-    }
-    __syncthreads();
-    write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
 }
 
 // ----------------------------------------------------------------------------- launch
@@ -538,7 +545,8 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key, val,
                        wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info);
     prof_end(kKBucketDegree, s);
-    const unsigned nm = (unsigned)(p.bslots / 2 + 1);
+    // split buckets, at most (the grids of the two fix kernels loop over the actual count)
+    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);
     prof_begin(kKBucketDegreeFix, s);
     hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
                        wk.dpart, wk.srow, wk.info);

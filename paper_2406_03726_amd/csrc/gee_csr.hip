@@ -286,10 +286,12 @@ __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int
 // per-digit running positions of its row (wave_rank).
 
 
+template <typename KS>
 struct PartLds {
     int cnt[kWaves][256];  // per-wavefront digit counts, then running positions
     int lstart[256], gbase[256], wsum[4];
-    int key[kTile];
+    KS key[kTile];            // the key as written out
+    unsigned char dig[kTile]; // its digit (at most 256 digits)
     int col[kTile];
     float val[kTile];
 };
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, 
                                                  const int *__restrict__ gh, const int *__restrict__ seg_start,
                                                  AK *__restrict__ okey, int amask, int *__restrict__ ocol,
                                                  float *__restrict__ oval, unsigned *status) {
-    __shared__ PartLds L;
+    __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = blockIdx.x;
     bool badi = false, badw = false;
@@ -357,17 +359,17 @@ __global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, 
         const int digit = valid ? (q.key[r] >> shift) : 0;
         const int pos = wave_rank(L.cnt[wv], digit, valid);
         if (valid) {
-            L.key[pos] = q.key[r];
+            L.key[pos] = (AK)(q.key[r] & amask);
+            L.dig[pos] = (unsigned char)digit;
             L.col[pos] = q.col[r];
             if (oval) L.val[pos] = q.val[r];
         }
     }
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int key = L.key[i];
-        const int d = key >> shift;
+        const int d = L.dig[i];
         const int64_t g2 = (int64_t)L.gbase[d] + (i - L.lstart[d]);
-        okey[g2] = (AK)(key & amask);
+        okey[g2] = L.key[i];
         ocol[g2] = L.col[i];
         if (oval) oval[g2] = L.val[i];
     }
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
                                                    const int *__restrict__ tile_off, int D,
                                                    uint16_t *__restrict__ okey, int *__restrict__ ocol,
                                                    float *__restrict__ oval) {
-    __shared__ PartLds L;
+    __shared__ PartLds<uint16_t> L;
     int d, jt, ntd;
     if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
     const int wv = threadIdx.x >> 6, lane = lane_id();
@@ -530,17 +532,17 @@ __global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, c
         const int digit = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
         const int pos = wave_rank(L.cnt[wv], digit, valid);
         if (valid) {
-            L.key[pos] = kr[r];
+            if (!FINAL) L.key[pos] = (uint16_t)(kr[r] & kmask);
+            L.dig[pos] = (unsigned char)digit;
             L.col[pos] = cr[r];
             if (oval) L.val[pos] = vr[r];
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int k = L.key[i];
-        const int dg = (k >> dshift) & (ND - 1);
+        const int dg = L.dig[i];
         const int64_t g = (int64_t)L.gbase[dg] + (i - L.lstart[dg]);
-        if (!FINAL) okey[g] = (uint16_t)(k & kmask);
+        if (!FINAL) okey[g] = L.key[i];
         ocol[g] = L.col[i];
         if (oval) oval[g] = L.val[i];
     }
