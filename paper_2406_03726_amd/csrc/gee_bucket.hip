@@ -74,26 +74,33 @@ __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__
 // One thread per bucket again: its parts {bucket, first entry, end entry, slot} (slot -1
 // for a bucket of one part, else the bucket's first slot + part index), and for a split
 // bucket its entry {bucket, first slot, parts} in `multi`. bmeta = {parts, split buckets}.
+// The parts of split buckets (the largest) come first in the table, at the index of their
+// slot, so their wavefronts start first; the one-part buckets follow in bucket order.
 // At most 64 workgroups (B <= 65536).
 __global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                          const int *__restrict__ ptot, int4 *__restrict__ part,
                                                          int4 *__restrict__ multi, int *__restrict__ bmeta) {
     __shared__ int wsum[16];
-    __shared__ int base[3];
+    __shared__ int base[4];  // parts, slots, split buckets before this workgroup; all slots
     if (threadIdx.x < 64) {
-        int a0 = 0, a1 = 0, a2 = 0;
-        if ((int)threadIdx.x < (int)blockIdx.x) {
-            a0 = ptot[3 * threadIdx.x];
-            a1 = ptot[3 * threadIdx.x + 1];
-            a2 = ptot[3 * threadIdx.x + 2];
+        int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        if ((int)threadIdx.x < (int)gridDim.x) {
+            a3 = ptot[3 * threadIdx.x + 1];
+            if ((int)threadIdx.x < (int)blockIdx.x) {
+                a0 = ptot[3 * threadIdx.x];
+                a1 = a3;
+                a2 = ptot[3 * threadIdx.x + 2];
+            }
         }
         a0 = readlane(wave_scan_add(a0), 63);
         a1 = readlane(wave_scan_add(a1), 63);
         a2 = readlane(wave_scan_add(a2), 63);
+        a3 = readlane(wave_scan_add(a3), 63);
         if (threadIdx.x == 0) {
             base[0] = a0;
             base[1] = a1;
             base[2] = a2;
+            base[3] = a3;
         }
     }
     __syncthreads();
@@ -109,9 +116,12 @@ __global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__r
     const int pp = base[0] + block_excl_scan<1024>(k, wsum, t0);
     const int ss = base[1] + block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
     const int mm = base[2] + block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
-    for (int q = 0; q < k; ++q)
-        part[pp + q] = make_int4(bk, s0 + q * P, min(s0 + (q + 1) * P, s1), k > 1 ? ss + q : -1);
-    if (k > 1) multi[mm] = make_int4(bk, ss, k, 0);
+    if (k > 1) {
+        for (int q = 0; q < k; ++q) part[ss + q] = make_int4(bk, s0 + q * P, min(s0 + (q + 1) * P, s1), ss + q);
+        multi[mm] = make_int4(bk, ss, k, 0);
+    } else if (k == 1) {
+        part[base[3] + (pp - ss)] = make_int4(bk, s0, s1, -1);  // after all split parts
+    }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         bmeta[0] = base[0] + t0;
         bmeta[1] = base[2] + t2;
