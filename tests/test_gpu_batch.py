@@ -158,3 +158,21 @@ def test_batch_beyond_one_bucket_size_keeps_plain_bits():
     plan.destroy()
     assert_close(items[4]["Z"], or_embed_graph(gs[4]), "small graph vs oracle")
     assert_close(items[3]["Z"], or_embed_graph(gs[3]), "600k-row graph vs oracle")
+
+
+def test_path_routing_beyond_bucket_limits():
+    """gee_embed of a graph above 2^22 rows (the CSR path) and of a graph with K > 64 above
+    2^21 rows (64-row buckets with a 100-float class stride), alone and batched with a small
+    graph: vs the oracle, and batched equal to plain bit for bit."""
+    gs = [random_small_graph(700, N=4_300_000, E=250_000, K=3, weighted=True, sym=True).with_options(True, True, True),
+          random_small_graph(701, N=2_200_000, E=300_000, K=100, weighted=False, sym=True).with_options(False, True, True),
+          random_small_graph(702, N=3000, E=20_000, K=100, weighted=True, sym=False).with_options(True, False, True)]
+    _label("path routing: 4.3M rows K=3, 2.2M rows K=100, small K=100")
+    items = _dev_graphs(gs)
+    plain = _plain(items)
+    for i in range(3):
+        assert_close(plain[i], or_embed_graph(gs[i]), f"graph {i} alone vs oracle")
+    gee.gee_embed_batch(items)
+    torch.cuda.synchronize()
+    for i, (it, zp) in enumerate(zip(items, plain)):
+        assert torch.equal(it["Z"], zp), f"graph {i}"
