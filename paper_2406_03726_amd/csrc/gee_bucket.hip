@@ -11,22 +11,23 @@
 //                    and the list of buckets of several parts (two passes of prefix sums
 //                    over the buckets).
 //   * bucket_degree  (Laplacian) each part's weighted degrees (entry counts without weights)
-//                    of the bucket's rows: LDS float atomics on R row sums; a one-part
-//                    bucket then sets s_i and c_i = s_i / n_{y_i} of its rows, a longer one
-//                    leaves partial sums. Without the Laplacian, c_i = 1 / n_{y_i}.
+//                    of the bucket's rows, summed in private LDS copies; a one-part bucket
+//                    then sets s_i and c_i = s_i / n_{y_i} of its rows, a longer one leaves
+//                    partial sums. Without the Laplacian, c_i = 1 / n_{y_i}.
 //   * bucket_degree_fix  adds the partial degrees of split buckets in part order.
 //   * bucket_embed   the class sums: the wavefront holds acc[R rows][class] in LDS and adds
 //                    every entry's val * c_j into acc[row][y_j] (4 consecutive entries per
 //                    lane, 16-byte loads, the loads of window k+2 and the gathers of window
-//                    k+1 in flight while window k is added). A one-part bucket then
+//                    k+1 in flight while window k is added; most entries add without
+//                    LDS float atomics, see the tag rule below). A one-part bucket then
 //                    finishes its rows (diagonal term c_i, factor s_i or the 2-norm) and
 //                    writes them as one contiguous block of Z; a longer one leaves its sums.
 //   * bucket_embed_fix  adds the partial sums of split buckets in part order and finishes
 //                    their rows.
 //
-// A wavefront adds its entries in a fixed order (windows in order; the LDS applies the
-// lanes of one instruction that hit one word in lane order) and parts are combined in
-// part order, so Z is bitwise reproducible. Buckets never straddle graphs (each graph's
+// A wavefront adds its entries in a fixed order (windows in order; within a window the tag
+// rule and the LDS's lane order for atomics on one word are fixed) and parts are combined
+// in part order, so Z is bitwise reproducible. Buckets never straddle graphs (each graph's
 // first row is aligned to R), and a graph's buckets and parts depend on that graph alone,
 // so its Z is the same alone and in a batch with the same R. The diagonal term is added
 // after the entries of its row.
