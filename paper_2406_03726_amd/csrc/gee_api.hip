@@ -318,7 +318,7 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.srow = (float *)take((size_t)p.Ntot * sizeof(float));
         w.part = (int4 *)take((size_t)p.bparts * sizeof(int4));
         w.multi = (int4 *)take((size_t)(p.bslots / 2 + 1) * sizeof(int4));
-        w.ptot = (int *)take(3 * 64 * sizeof(int));
+        w.ptot = (int *)take(4 * 64 * sizeof(int));
         w.bmeta = (int *)take(4 * sizeof(int));
         w.dpart = (float *)take((size_t)p.bslots * 64 * sizeof(float));
         w.zpart = (float *)take(((size_t)p.bslots << p.sb) * (size_t)p.Kmax * sizeof(float));

@@ -54,55 +54,66 @@ __device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 
 
 // ----------------------------------------------------------------------------- part table
 
-// One thread per bucket: per-workgroup totals of parts, partial slots and split buckets.
+// Part table order: the parts of split buckets first (at the index of their partial slot),
+// then the one-part buckets of more than P/4 entries, then the rest, each group in bucket
+// order, so the longest wavefronts start first.
+__device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 1 && 4 * n > P; }
+
+// One thread per bucket: per-workgroup totals of parts, partial slots, split buckets and
+// large one-part buckets.
 __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                           int *__restrict__ ptot) {
     __shared__ int wsum[16];
     const int bk = blockIdx.x * 1024 + threadIdx.x;
-    int k = 0;
-    if (bk < B) k = parts_of(bstart[bk + 1] - bstart[bk], load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE);
-    int t0, t1, t2;
+    int k = 0, n = 0, P = 1;
+    if (bk < B) {
+        n = bstart[bk + 1] - bstart[bk];
+        P = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
+        k = parts_of(n, P);
+    }
+    int t0, t1, t2, t3;
     (void)block_excl_scan<1024>(k, wsum, t0);
     (void)block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
     (void)block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
+    (void)block_excl_scan<1024>(large_single(n, k, P) ? 1 : 0, wsum, t3);
     if (threadIdx.x == 0) {
-        ptot[3 * blockIdx.x] = t0;
-        ptot[3 * blockIdx.x + 1] = t1;
-        ptot[3 * blockIdx.x + 2] = t2;
+        ptot[4 * blockIdx.x] = t0;
+        ptot[4 * blockIdx.x + 1] = t1;
+        ptot[4 * blockIdx.x + 2] = t2;
+        ptot[4 * blockIdx.x + 3] = t3;
     }
 }
 
 // One thread per bucket again: its parts {bucket, first entry, end entry, slot} (slot -1
-// for a bucket of one part, else the bucket's first slot + part index), and for a split
-// bucket its entry {bucket, first slot, parts} in `multi`. bmeta = {parts, split buckets}.
-// The parts of split buckets (the largest) come first in the table, at the index of their
-// slot, so their wavefronts start first; the one-part buckets follow in bucket order.
-// At most 64 workgroups (B <= 65536).
+// for a bucket of one part, else the bucket's first slot + part index) in the order above,
+// and for a split bucket its entry {bucket, first slot, parts} in `multi`.
+// bmeta = {parts, split buckets}. At most 64 workgroups (B <= 65536).
 __global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                          const int *__restrict__ ptot, int4 *__restrict__ part,
                                                          int4 *__restrict__ multi, int *__restrict__ bmeta) {
     __shared__ int wsum[16];
-    __shared__ int base[4];  // parts, slots, split buckets before this workgroup; all slots
+    // before this workgroup: parts, slots, split buckets, large one-part buckets, small
+    // one-part buckets; over all workgroups: slots, large one-part buckets
+    __shared__ int base[7];
     if (threadIdx.x < 64) {
-        int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        int v[7] = {0, 0, 0, 0, 0, 0, 0};
         if ((int)threadIdx.x < (int)gridDim.x) {
-            a3 = ptot[3 * threadIdx.x + 1];
+            const int q0 = ptot[4 * threadIdx.x], q1 = ptot[4 * threadIdx.x + 1];
+            const int q2 = ptot[4 * threadIdx.x + 2], q3 = ptot[4 * threadIdx.x + 3];
+            v[5] = q1;
+            v[6] = q3;
             if ((int)threadIdx.x < (int)blockIdx.x) {
-                a0 = ptot[3 * threadIdx.x];
-                a1 = a3;
-                a2 = ptot[3 * threadIdx.x + 2];
+                v[0] = q0;
+                v[1] = q1;
+                v[2] = q2;
+                v[3] = q3;
+                v[4] = q0 - q1 - q3;  // one-part buckets that are not large
             }
         }
-        a0 = readlane(wave_scan_add(a0), 63);
-        a1 = readlane(wave_scan_add(a1), 63);
-        a2 = readlane(wave_scan_add(a2), 63);
-        a3 = readlane(wave_scan_add(a3), 63);
-        if (threadIdx.x == 0) {
-            base[0] = a0;
-            base[1] = a1;
-            base[2] = a2;
-            base[3] = a3;
-        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = readlane(wave_scan_add(v[c]), 63);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 7; ++c) base[c] = v[c];
     }
     __syncthreads();
     const int bk = blockIdx.x * 1024 + threadIdx.x;
@@ -113,15 +124,21 @@ __global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__r
         s1 = bstart[bk + 1];
         k = parts_of(s1 - s0, P);
     }
-    int t0, t1, t2;
-    const int pp = base[0] + block_excl_scan<1024>(k, wsum, t0);
+    const bool large = large_single(s1 - s0, k, P);
+    const bool small = k == 1 && !large;
+    int t0, t1, t2, t3, t4;
+    (void)block_excl_scan<1024>(k, wsum, t0);
     const int ss = base[1] + block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
     const int mm = base[2] + block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
+    const int ll = base[3] + block_excl_scan<1024>(large ? 1 : 0, wsum, t3);
+    const int sm = base[4] + block_excl_scan<1024>(small ? 1 : 0, wsum, t4);
     if (k > 1) {
         for (int q = 0; q < k; ++q) part[ss + q] = make_int4(bk, s0 + q * P, min(s0 + (q + 1) * P, s1), ss + q);
         multi[mm] = make_int4(bk, ss, k, 0);
-    } else if (k == 1) {
-        part[base[3] + (pp - ss)] = make_int4(bk, s0, s1, -1);  // after all split parts
+    } else if (large) {
+        part[base[5] + ll] = make_int4(bk, s0, s1, -1);
+    } else if (small) {
+        part[base[5] + base[6] + sm] = make_int4(bk, s0, s1, -1);
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         bmeta[0] = base[0] + t0;

@@ -308,7 +308,7 @@ struct Work {
     // bucket path
     int4 *part = nullptr;      // [bparts] {bucket, first entry, end entry, partial slot or -1}
     int4 *multi = nullptr;     // [bslots / 2] {bucket, first slot, parts} of buckets of several parts
-    int *ptot = nullptr;       // [3 * 64] per-workgroup totals of the part count
+    int *ptot = nullptr;       // [4 * 64] per-workgroup totals of the part count
     int *bmeta = nullptr;      // [4]: parts, buckets of several parts
     float *dpart = nullptr;    // [bslots * 64] partial degrees
     float *zpart = nullptr;    // [bslots << sb * Kmax] partial class sums
@@ -353,7 +353,7 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
 // gee_bucket.hip: Z straight from the row buckets of the first two sort passes
 // (launch_csr_build), for plans with p.bucket.
 constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
-constexpr int kBucketDefaultPart = 4096;
+constexpr int kBucketDefaultPart = 8192;
 constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end
 hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s);
 
