@@ -424,13 +424,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             P.f[j] = buf_f2(r_inf, u << 3);
         }
     };
-    // Window update without LDS float atomics for most entries (they run at a small
-    // fraction of the plain LDS rate): every entry with a non-zero term writes its id
-    // (4 * lane + j) into the byte tag of its (row, class) word; exactly one entry per word
-    // reads its own id back, and those entries (all at distinct words) add with plain
-    // reads and writes; the others then add with atomics. Zero terms are skipped (adding
-    // them changes nothing: the sums start at +0 and never hold -0). The order in which a
-    // word receives its terms is fixed by the entries' places in the window.
+    // window update: see lds_tag_add
     auto add = [&](const Prep &P) {
         int ad[BEPL];
         float xv[BEPL];
@@ -439,23 +433,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             ad[j] = P.row[j] * KP + __float_as_int(P.f[j].y);
             xv[j] = P.x[j] * P.f[j].x;
         }
-#pragma unroll
-        for (int j = 0; j < BEPL; ++j)
-            if (xv[j] != 0.0f) tag[ad[j]] = (unsigned char)(BEPL * lane + j);
-        wave_lds_fence();
-        bool win[BEPL];
-        float old[BEPL];
-#pragma unroll
-        for (int j = 0; j < BEPL; ++j) win[j] = xv[j] != 0.0f && tag[ad[j]] == (unsigned char)(BEPL * lane + j);
-#pragma unroll
-        for (int j = 0; j < BEPL; ++j) old[j] = win[j] ? acc[ad[j]] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < BEPL; ++j)
-            if (win[j]) acc[ad[j]] = old[j] + xv[j];
-        wave_lds_fence();
-#pragma unroll
-        for (int j = 0; j < BEPL; ++j)
-            if (xv[j] != 0.0f && !win[j]) atomicAdd(&acc[ad[j]], xv[j]);
+        lds_tag_add<BEPL>(acc, tag, ad, xv, lane);
     };
     // Three stages, two register sets each with fixed roles (no copies that would wait for
     // loads in flight): the loads of window i+2 are issued first, then the gathers of

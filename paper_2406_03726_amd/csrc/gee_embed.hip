@@ -58,7 +58,10 @@ static_assert(RS >= 16 && RS <= 64 && (RS & (RS - 1)) == 0, "ring slots: power o
 
 // LDS floats of one embed wavefront: the ring [RS][ring_stride(K)] and per slot its row
 // and s_i (later its finishing factor), with room to spare.
-__host__ __device__ constexpr int embed_lds_floats(int K) { return RS * ring_stride(K) + 3 * RS; }
+// The ring acc[RS][KP], its slot metadata (3 RS words) and a byte tag per ring word.
+__host__ __device__ constexpr int embed_lds_floats(int K) {
+    return RS * ring_stride(K) + 3 * RS + (RS * ring_stride(K) + 3) / 4;
+}
 
 // Graph and local index of embed wavefront w; false if w has no work.
 __device__ __forceinline__ bool wave_graph(const Batch &b, int w, GDesc &d, GMeta &m, int &lw) {
@@ -509,6 +512,7 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
     // per wavefront: the ring acc[RS slots][KP] and per slot its row and s_i
     float *acc = smem_f + (size_t)wib * lds_floats;
     int2 *slot_meta = reinterpret_cast<int2 *>(acc + RS * KP);  // {row, s_i}, then {row, factor}
+    unsigned char *tag = reinterpret_cast<unsigned char *>(acc + RS * KP + 3 * RS);  // [RS * KP]
     {
         float4 *acc4 = reinterpret_cast<float4 *>(acc);
         for (int i = lane; i < ((RS * KP) >> 2); i += 64) acc4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -678,16 +682,17 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
     };
 
     // Adds the entries of lanes [lo, hi) of a prepared window; n0 = row starts before
-    // lane lo. A starting row first gets its slot, s_i and diagonal term c_i, then every
-    // entry adds into acc[slot(row)][y_j] with an LDS float atomic; the LDS applies lanes
-    // that hit the same word one after another in a fixed order, so the sums are
-    // reproducible. Then the rows that ended become pending.
+    // lane lo. A starting row first gets its slot, s_i and diagonal term c_i (a plain
+    // write: LDS operations of a wavefront take effect in order), then every entry adds
+    // into acc[slot(row)][y_j] (lds_tag_add: a fixed order per word, so the sums are
+    // reproducible). Then the rows that ended become pending.
     auto add_lanes = [&](const WinPrep &P, int lo, int hi, int n0, int nn, bool st0, bool cnt) {
         if (npend + 1 + nn > RS) drain();
-        if (lane >= lo && lane < hi) {
-            int sl[EPL];
+        const bool act = lane >= lo && lane < hi;
+        int sl[EPL];
 #pragma unroll
-            for (int j = 0; j < EPL; ++j) sl[j] = (cur_slot + P.n[j] - n0) & (RS - 1);
+        for (int j = 0; j < EPL; ++j) sl[j] = (cur_slot + P.n[j] - n0) & (RS - 1);
+        if (act) {
 #pragma unroll
             for (int j = 0; j < EPL; ++j) {
                 if ((P.stm >> j) & 1) {
@@ -696,11 +701,16 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
                     if (diag) acc[sl[j] * KP + __float_as_int(P.q[j].y)] = P.q[j].x;
                 }
             }
+        }
+        {
+            int ad[EPL];
+            float xv[EPL];
 #pragma unroll
             for (int j = 0; j < EPL; ++j) {
-                const float x = WEIGHTED ? P.v[j] * P.f[j].x : P.f[j].x;
-                atomicAdd(&acc[sl[j] * KP + __float_as_int(P.f[j].y)], x);
+                ad[j] = sl[j] * KP + __float_as_int(P.f[j].y);
+                xv[j] = act ? (WEIGHTED ? P.v[j] * P.f[j].x : P.f[j].x) : 0.0f;
             }
+            lds_tag_add<EPL>(acc, tag, ad, xv, lane);
         }
         // segments of this range: the open row unless the range starts a row, then the
         // new rows; all but the last end here, the last unless the next entry continues it

@@ -166,6 +166,37 @@ __device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t of
     return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
 }
 
+// Adds xv[j] into acc[ad[j]] for the N entries of every lane of one wavefront (N <= 4)
+// without LDS float atomics for most of them (those run at a small fraction of the plain
+// LDS rate on gfx950): every entry with a non-zero term writes its id (N * lane + j) into
+// the byte tag of its word; exactly one entry per word reads its own id back, and those
+// entries (all at distinct words) add with plain reads and writes; the others then add
+// with atomics. Zero terms are skipped: the sums start at +0 and never hold -0, so adding
+// a zero changes nothing. The order in which a word receives its terms is fixed by the
+// entries' places, so the sums are reproducible.
+template <int N>
+__device__ __forceinline__ void lds_tag_add(float *acc, unsigned char *tag, const int (&ad)[N],
+                                            const float (&xv)[N], int lane) {
+    static_assert(N <= 4, "entry ids must fit a byte");
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (xv[j] != 0.0f) tag[ad[j]] = (unsigned char)(N * lane + j);
+    wave_lds_fence();
+    bool win[N];
+    float old[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) win[j] = xv[j] != 0.0f && tag[ad[j]] == (unsigned char)(N * lane + j);
+#pragma unroll
+    for (int j = 0; j < N; ++j) old[j] = win[j] ? acc[ad[j]] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (win[j]) acc[ad[j]] = old[j] + xv[j];
+    wave_lds_fence();
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (xv[j] != 0.0f && !win[j]) atomicAdd(&acc[ad[j]], xv[j]);
+}
+
 // s_i from a weighted degree d (plus 1 with augmentation); 0 for d <= 0.
 __device__ __forceinline__ void finish_degree(int r, float d, bool diag, float *__restrict__ srow) {
     const float dd = d + (diag ? 1.0f : 0.0f);
