@@ -45,9 +45,11 @@ constexpr int kFixThreads = 256; // threads per split bucket when combining clas
 #endif
 
 // LDS of one class-sum workgroup: R rows of ring_stride(K) floats, 64 row factors and
-// (bucket_embed) a byte tag per class sum.
+// (bucket_embed) a 1 KB hash table of entry tags (lds_tag_add), which leaves room for more
+// resident wavefronts than a tag per class sum.
+constexpr int kTagBytes = 1024;
 static size_t bucket_lds(int sb, int Kmax) {
-    return ((size_t)ring_stride(Kmax) << sb) * (sizeof(float) + 1) + 64 * sizeof(float);
+    return ((size_t)ring_stride(Kmax) << sb) * sizeof(float) + 64 * sizeof(float) + kTagBytes;
 }
 
 __device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     const int R = 1 << sb, rmask = R - 1;
     float *acc = smem_b;           // [R][KP]
     float *fac = smem_b + R * KP;  // [64] row factors
-    unsigned char *tag = reinterpret_cast<unsigned char *>(fac + 64);  // [R][KP] entry ids
+    unsigned char *tag = reinterpret_cast<unsigned char *>(fac + 64);  // [kTagBytes] entry ids
     // the lane's row {c_i, y_i} and s_i, needed at the end, loaded now
     const int r0 = pt.x << sb, rl = r0 + lane;
     const bool own = lane < R && rl >= node_off && rl < node_off + gd.N;
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             ad[j] = P.row[j] * KP + __float_as_int(P.f[j].y);
             xv[j] = P.x[j] * P.f[j].x;
         }
-        lds_tag_add<BEPL>(acc, tag, ad, xv, lane);
+        lds_tag_add<BEPL>(acc, tag, ad, xv, lane, kTagBytes - 1);
     };
     // Three stages, two register sets each with fixed roles (no copies that would wait for
     // loads in flight): the loads of window i+2 are issued first, then the gathers of

@@ -173,19 +173,21 @@ __device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t of
 // entries (all at distinct words) add with plain reads and writes; the others then add
 // with atomics. Zero terms are skipped: the sums start at +0 and never hold -0, so adding
 // a zero changes nothing. The order in which a word receives its terms is fixed by the
-// entries' places, so the sums are reproducible.
+// entries' places, so the sums are reproducible. With tmask, the tags are a hash table of
+// tmask + 1 bytes indexed by word & tmask: entries of two words that share a tag can only
+// lose, and losing costs an atomic, never a wrong sum.
 template <int N>
 __device__ __forceinline__ void lds_tag_add(float *acc, unsigned char *tag, const int (&ad)[N],
-                                            const float (&xv)[N], int lane) {
+                                            const float (&xv)[N], int lane, int tmask = -1) {
     static_assert(N <= 4, "entry ids must fit a byte");
 #pragma unroll
     for (int j = 0; j < N; ++j)
-        if (xv[j] != 0.0f) tag[ad[j]] = (unsigned char)(N * lane + j);
+        if (xv[j] != 0.0f) tag[ad[j] & tmask] = (unsigned char)(N * lane + j);
     wave_lds_fence();
     bool win[N];
     float old[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) win[j] = xv[j] != 0.0f && tag[ad[j]] == (unsigned char)(N * lane + j);
+    for (int j = 0; j < N; ++j) win[j] = xv[j] != 0.0f && tag[ad[j] & tmask] == (unsigned char)(N * lane + j);
 #pragma unroll
     for (int j = 0; j < N; ++j) old[j] = win[j] ? acc[ad[j]] : 0.0f;
 #pragma unroll
