@@ -355,17 +355,47 @@ __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int 
     }
 }
 
-// Z rows r0 .. of the bucket (those of the graph) as one flat run of floats, thread t of
-// nt writing floats t, t + nt, ... (non-temporal: Z is not read again here).
+// Z rows r0 .. of the bucket (those of the graph) as one flat run of floats, written by
+// threads t of nt with non-temporal stores (Z is not read again here): when the run starts
+// on a 16-byte boundary (Z's base permitting: the run starts at a multiple of R rows),
+// thread t writes floats 4t .. 4t+3, 4(t+nt) .., one 16-byte store each, and the last
+// F mod 4 floats one by one; otherwise every float one by one.
 __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int KP, const float *acc,
                                            const float *fac, int t, int nt) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
     const int K = gd.K;
     const int nv = max(0, min(R, gd.node_off + gd.N - r0));
     const int F = nv * K;
     float *z = gd.Z + (int64_t)(r0 - gd.node_off) * K;
+    int f0 = 0;
+    if ((reinterpret_cast<uintptr_t>(z) & 15) == 0) {
+        const int F4 = F & ~3, step = 4 * nt;
+        const int qn = step / K, rn = step - qn * K;
+        int jj = (4 * t) / K, kk = 4 * t - ((4 * t) / K) * K;
+        for (int f = 4 * t; f < F4; f += step) {
+            v4 v;
+            int j2 = jj, k2 = kk;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = acc[j2 * KP + k2] * fac[j2];
+                if (++k2 == K) {
+                    k2 = 0;
+                    ++j2;
+                }
+            }
+            __builtin_nontemporal_store(v, reinterpret_cast<v4 *>(z + f));
+            kk += rn;
+            jj += qn;
+            if (kk >= K) {
+                kk -= K;
+                ++jj;
+            }
+        }
+        f0 = F4;
+    }
     const int qn = nt / K, rn = nt - qn * K;
-    int jj = t / K, kk = t - (t / K) * K;
-    for (int f = t; f < F; f += nt) {
+    int jj = (f0 + t) / K, kk = f0 + t - ((f0 + t) / K) * K;
+    for (int f = f0 + t; f < F; f += nt) {
         __builtin_nontemporal_store(acc[jj * KP + kk] * fac[jj], z + f);
         kk += rn;
         jj += qn;
