@@ -35,9 +35,16 @@ namespace gee {
 
 constexpr int kTile = kPartTile;  // entries per partition tile
 constexpr int kRounds = kTile / 256;
-constexpr int kWaves = 4;                 // wavefronts per partition workgroup
+#ifndef GEE_PART_WAVES
+#define GEE_PART_WAVES 4
+#endif
+constexpr int kWaves = GEE_PART_WAVES;    // wavefronts per partition workgroup
+constexpr int kThreads = kWaves * 64;
 constexpr int kQuarter = kTile / kWaves;  // items per wavefront per tile
 constexpr int kRoundsW = kQuarter / 64;   // rounds of one wavefront
+static_assert(kTile % (kWaves * 64) == 0 && kRoundsW <= 16 && kThreads >= 256, "partition tile shape");
+// bucket_sort's wave-split path: 4 wavefronts of at most 16 rounds (kSortCap entries)
+constexpr int kSortWaves = 4, kSortRoundsW = 16, kSortCap = kSortWaves * kSortRoundsW * 64;
 
 // ----------------------------------------------------------------------------- helpers
 
@@ -204,10 +211,10 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
 
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
-__global__ __launch_bounds__(256) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
-                                              int *__restrict__ gh, unsigned *status) {
+__global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
+                                                   int *__restrict__ gh, unsigned *status) {
     __shared__ int hist[256];
-    hist[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < 256; i += kThreads) hist[i] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
     const int wv = threadIdx.x >> 6;
@@ -289,7 +296,7 @@ __global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int
 template <typename KS>
 struct PartLds {
     int cnt[kWaves][256];  // per-wavefront digit counts, then running positions
-    int lstart[256], gbase[256], wsum[4];
+    int lstart[256], gbase[256], wsum[kWaves];
     KS key[kTile];            // the key as written out
     unsigned char dig[kTile]; // its digit (at most 256 digits)
     int col[kTile];
@@ -301,11 +308,14 @@ struct PartLds {
 __device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, int *gbase, int *wsum, int D,
                                                  int gbase_d) {
     const int d = threadIdx.x;
-    int c[kWaves];
+    int c[kWaves], csum = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c[w] = d < D ? cnt[w][d] : 0;
+    for (int w = 0; w < kWaves; ++w) {
+        c[w] = d < D ? cnt[w][d] : 0;
+        csum += c[w];
+    }
     int total;
-    const int ls = block_excl_scan256(c[0] + c[1] + c[2] + c[3], wsum, total);
+    const int ls = block_excl_scan<kThreads>(csum, wsum, total);
     if (d < D) {
         lstart[d] = ls;
         gbase[d] = gbase_d;
@@ -335,7 +345,7 @@ __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid) {
 // offset) in runs. The key written keeps only the bits the later passes read (amask): the
 // high digit is implied by the segment, so with at most 16 bits left it fits a u16.
 template <typename AK>
-__global__ __launch_bounds__(256) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
+__global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
                                                  const int *__restrict__ gh, const int *__restrict__ seg_start,
                                                  AK *__restrict__ okey, int amask, int *__restrict__ ocol,
                                                  float *__restrict__ oval, unsigned *status) {
@@ -492,7 +502,7 @@ __global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits
 // the row inside its bucket (key & kmask). FINAL = true (pass C): column and value go to
 // their CSR slots.
 template <typename KT, bool FINAL>
-__global__ __launch_bounds__(256) void seg_scatter(const KT *__restrict__ key, const int *__restrict__ col,
+__global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val, int dshift, int dbits, int kmask,
                                                    const int *__restrict__ gh, const int *__restrict__ seg_start,
                                                    const int *__restrict__ tile_off, int D,
@@ -607,18 +617,19 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         // Wave-split ranking: each wavefront counts and ranks a contiguous quarter.
         const int wv = threadIdx.x >> 6, lane = lane_id();
         int *cnt = smem_i;                                              // [4][R]
-        int *scol2 = cnt + kWaves * R;                                  // [cap]
+        int *scol2 = cnt + kSortWaves * R;                              // [cap]
         float *sval2 = reinterpret_cast<float *>(scol2 + cap);          // [cap]
-        for (int i = threadIdx.x; i < kWaves * R; i += blockDim.x) cnt[i] = 0;
+        for (int i = threadIdx.x; i < kSortWaves * R; i += blockDim.x) cnt[i] = 0;
         __syncthreads();
         const int n = e1 - e0;
-        const int q = (((n + kWaves - 1) / kWaves) + 63) & ~63;  // <= kQuarter: kRoundsW rounds
+        // <= kSortCap / kSortWaves: kSortRoundsW rounds
+        const int q = (((n + kSortWaves - 1) / kSortWaves) + 63) & ~63;
         const int ew = e0 + min(n, wv * q), ee = e0 + min(n, (wv + 1) * q);
-        int kr[kRoundsW] = {0}, cr[kRoundsW] = {0};
-        float vr[kRoundsW] = {0.0f};
+        int kr[kSortRoundsW] = {0}, cr[kSortRoundsW] = {0};
+        float vr[kSortRoundsW] = {0.0f};
         if (ee > ew) {  // this wavefront has entries: clamped loads stay inside [ew, ee)
 #pragma unroll
-            for (int r = 0; r < kRoundsW; ++r) {
+            for (int r = 0; r < kSortRoundsW; ++r) {
                 const int ec = min(ew + r * 64 + lane, ee - 1);
                 kr[r] = (int)tkey[ec] & rmask;
                 cr[r] = tcol[ec];
@@ -626,7 +637,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
             }
         }
 #pragma unroll
-        for (int r = 0; r < kRoundsW; ++r)
+        for (int r = 0; r < kSortRoundsW; ++r)
             if (ew + r * 64 + lane < ee) atomicAdd(&cnt[wv * R + kr[r]], 1);
         __syncthreads();
         // thread t owns rows [t * rpt, (t + 1) * rpt): their counts, one scan, then each
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
             if (r >= R) break;
             if (r < Rb) rp[r0 + r] = e0 + run2;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < kSortWaves; ++w) {
                 const int c = cnt[w * R + r];
                 cnt[w * R + r] = run2;
                 run2 += c;
@@ -654,7 +665,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kRoundsW; ++r) {
+        for (int r = 0; r < kSortRoundsW; ++r) {
             const bool valid = ew + r * 64 + lane < ee;
             const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid);
             if (valid) {
@@ -709,10 +720,10 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
 // ----------------------------------------------------------------------------- launch
 
 // Staging capacity of bucket_sort: the whole workgroup stays within 64 KiB of LDS.
-int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : kTile; }
+int bucket_stage_cap(int sb) { return sb >= 12 ? 2048 : (kTile < kSortCap ? kTile : kSortCap); }
 size_t bucket_sort_lds(int sb) {
     const size_t R = (size_t)1 << sb;
-    const size_t counters = R <= 1024 ? kWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
+    const size_t counters = R <= 1024 ? kSortWaves * R * 4 : 8 * R;  // wave-split path : block-rank path
     return (counters > 8 * R ? counters : 8 * R) + (size_t)bucket_stage_cap(sb) * 8;
 }
 
@@ -726,7 +737,7 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     float *aval = p.weighted ? (with_b ? wk.val : wk.tval) : nullptr;
     hipError_t e;
     prof_begin(kKAHist, s);
-    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, p.TA, wk.ghA,
+    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, p.TA, wk.ghA,
                        status);
     prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -744,10 +755,10 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     prof_begin(kKAScatter, s);
     if (k16) {
-        hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits,
+        hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.segA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status);
     } else {
-        hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(256), 0, s, b, p.Vtot, shift, p.DA, nbits,
+        hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.segA, wk.akey, -1, acol, aval, status);
     }
     prof_end(kKAScatter, s);
@@ -769,11 +780,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
     if (k16) {
-        hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, akey16, acol,
+        hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
                            aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
                            p.weighted ? wk.tval : nullptr);
     } else {
-        hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, acol, aval,
+        hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
                            p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
                            p.weighted ? wk.tval : nullptr);
     }
@@ -804,7 +815,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     prof_end(kKCScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);
-    hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(256), 0, s, key, wk.tcol, tv, 0, p.sb,
+    hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(kThreads), 0, s, key, wk.tcol, tv, 0, p.sb,
                        0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov);
     prof_end(kKCScatter, s);
     return hipGetLastError();
