@@ -100,11 +100,6 @@ __device__ __forceinline__ float wave_seg_scan_addf(float x, int key) {
 }
 // Sum over the whole wavefront, the same value on every lane.
 __device__ __forceinline__ float wave_sum(float v) { return readlane_f(wave_scan_addf(v), 63); }
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
 // Exclusive scan of one int per thread over a workgroup of NT threads (DPP inside each
 // wavefront, then the wavefront totals); `total` is the sum. wsum needs NT/64 ints.
 template <int NT>
@@ -158,9 +153,6 @@ __device__ __forceinline__ float2 buf_f2(__amdgpu_buffer_rsrc_t r, uint32_t off)
 }
 __device__ __forceinline__ unsigned buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-}
-__device__ __forceinline__ unsigned buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 }
 __device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
