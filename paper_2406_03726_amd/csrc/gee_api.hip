@@ -409,8 +409,13 @@ hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w,
 
 // Kernel sequence of gee_embed over a batch (edge lists -> Z).
 hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned *st, hipStream_t s) {
-    hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
-    if (e == hipSuccess) e = launch_csr_build(b, p, wk, st, s);
+    CountJob job;
+    job.part = wk.cpart;
+    job.counts = wk.counts;
+    job.inv_n = wk.inv_n;
+    job.slices = p.cnt_blocks;
+    job.classes = p.Ktot;
+    hipError_t e = launch_csr_build(b, p, wk, st, s, &job);
     if (p.bucket) return e == hipSuccess ? launch_bucket_embed(b, p, wk, s) : e;
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, wk.rp, 0, s);

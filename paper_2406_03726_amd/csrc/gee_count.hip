@@ -1,9 +1,6 @@
-// gee_count.hip - class sizes n_k and 1/n_k (Section 2: W row j holds 1/n_{y_j}).
-//
-// Two launches, no global atomics on the counts: every workgroup histograms a
-// contiguous slice of one graph's labels in LDS and writes its K partial counts; a
-// second launch adds each class's partials in workgroup order (integers, so the order
-// cannot change the result) and forms 1/n_k in float32 (0 for an empty class).
+// gee_count.hip - class sizes n_k and 1/n_k (Section 2: W row j holds 1/n_{y_j}) as two
+// launches of their own (class_count_slice, class_count_total), for gee_class_counts and
+// the resident-CSR path; the edge-list paths run them inside the partition launches.
 #include "gee_internal.h"
 
 #include <cstring>
@@ -13,45 +10,15 @@ namespace gee {
 __global__ __launch_bounds__(256) void class_count_partial(Batch b, int *__restrict__ part,
                                                            unsigned *status) {
     __shared__ int hist[kMaxClasses];
-    const int g = find_graph(b.cnt_offs, b.G, (int)blockIdx.x);
-    const GDesc d = load_desc(b, g);
-    const int jb = blockIdx.x - d.cnt_off;
-    const int K = d.K;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) hist[k] = 0;
-    __syncthreads();
-    const int64_t per = ((int64_t)d.N + d.cnt_blocks - 1) / d.cnt_blocks;
-    const int64_t lo = (int64_t)jb * per;
-    const int64_t hi = min((int64_t)d.N, lo + per);
-    bool bad = false;
-    for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-        const int y = d.labels[j];
-        if (y >= 0 && y < K)
-            atomicAdd(&hist[y], 1);
-        else if (y != -1)
-            bad = true;
-    }
-    if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrLabel);
-    for (int k = threadIdx.x; k < K; k += blockDim.x) part[d.cpart_off + (int64_t)jb * K + k] = hist[k];
+    class_count_slice(b, blockIdx.x, part, status, hist);
 }
 
-// Wavefront per class (all graphs): the lanes add the graph's partials (integers, so the
-// order does not matter), then 1/n_k.
+// Wavefront per class (all graphs).
 __global__ __launch_bounds__(256) void class_count_final(Batch b, int Ktot, const int *__restrict__ part,
                                                          int *__restrict__ counts, float *__restrict__ inv_n) {
     const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (c >= Ktot) return;
-    const int lane = lane_id();
-    const int g = find_graph(b.class_offs, b.G, c);
-    const GDesc d = load_desc(b, g);
-    const int k = c - d.class_off;
-    const int *pp = part + d.cpart_off + k;
-    int n = 0;
-    for (int j = lane; j < d.cnt_blocks; j += 64) n += pp[(int64_t)j * d.K];
-    n = readlane(wave_scan_add(n), 63);
-    if (lane == 0) {
-        counts[c] = n;
-        if (inv_n) inv_n[c] = n > 0 ? 1.0f / (float)n : 0.0f;
-    }
+    class_count_total(b, c, part, counts, inv_n);
 }
 
 // Host bytes to device memory through kernel arguments: each launch carries one chunk.

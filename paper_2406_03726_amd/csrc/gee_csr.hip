@@ -13,15 +13,15 @@
 //                                                              a_totals, a_scatter)
 //   pass B  partition each high-digit segment by low digit    (seg_hist, seg_scan,
 //                                                              seg_scatter)
-//   pass C  buckets of at most 2048 entries: one workgroup per bucket, row counts ->
-//           row_ptr, then the entries in row order             (bucket_sort)
+//   pass C  buckets within the staging capacity (bucket_stage_cap): one workgroup per
+//           bucket, row counts -> row_ptr, then the entries in row order (bucket_sort)
 //           larger buckets (they hold hub rows): the segment partition once more with
 //           the row inside the bucket as the digit, over many workgroups (c_tiles,
 //           seg_hist, seg_scan, seg_scatter)
 //
 // With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
 //
-// Every partition pass works on tiles of 2048 entries: the tile's entries are ranked
+// Every partition pass works on tiles of kPartTile entries: the tile's entries are ranked
 // by digit (stable) and staged in LDS in digit order, then written out so that
 // consecutive threads write consecutive addresses of each digit's run; no pass writes
 // scattered single words. Stable ranks never use global atomics: each wavefront owns a
@@ -211,9 +211,14 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
 
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
+// Workgroups past the T tiles are label slices of the class counts.
 __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
-                                                   int *__restrict__ gh, unsigned *status) {
+                                                   int *__restrict__ gh, unsigned *status, int *__restrict__ cpart) {
     __shared__ int hist[256];
+    if ((int64_t)blockIdx.x >= T) {
+        class_count_slice(b, (int)(blockIdx.x - T), cpart, status, hist);
+        return;
+    }
     for (int i = threadIdx.x; i < 256; i += kThreads) hist[i] = 0;
     __syncthreads();
     const int64_t t = blockIdx.x;
@@ -230,7 +235,15 @@ __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift
 
 // One workgroup per digit d: exclusive scan of the row gh[d*T .. d*T+T) in place;
 // tot[d] = its sum.
-__global__ __launch_bounds__(1024) void digit_scan(int *__restrict__ gh, int64_t T, int *__restrict__ tot) {
+// Workgroups past the D digits take 16 classes of the class totals each.
+__global__ __launch_bounds__(1024) void digit_scan(int *__restrict__ gh, int64_t T, int *__restrict__ tot, int D,
+                                                   Batch b, int Ktot, const int *__restrict__ cpart,
+                                                   int *__restrict__ counts, float *__restrict__ inv_n) {
+    if ((int)blockIdx.x >= D) {
+        const int c = ((int)blockIdx.x - D) * 16 + (int)(threadIdx.x >> 6);
+        if (c < Ktot) class_count_total(b, c, cpart, counts, inv_n);
+        return;
+    }
     __shared__ int wsum[16];
     int *row = gh + (int64_t)blockIdx.x * T;
     int carry = 0;
@@ -727,7 +740,10 @@ size_t bucket_sort_lds(int sb) {
     return (counters > 8 * R ? counters : 8 * R) + (size_t)bucket_stage_cap(sb) * 8;
 }
 
-hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
+hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s,
+                            const CountJob *job) {
+    const unsigned xslices = job ? (unsigned)job->slices : 0u;
+    const unsigned xclass = job ? (unsigned)((job->classes + 15) / 16) : 0u;
     const bool with_b = p.s2 > 0;
     const int shift = p.sb + p.s2;
     int nbits = 0;
@@ -737,12 +753,14 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     float *aval = p.weighted ? (with_b ? wk.val : wk.tval) : nullptr;
     hipError_t e;
     prof_begin(kKAHist, s);
-    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, p.TA, wk.ghA,
-                       status);
+    hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA + xslices), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, p.TA,
+                       wk.ghA, status, job ? job->part : nullptr);
     prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScan, s);
-    hipLaunchKernelGGL(digit_scan, dim3(p.DA), dim3(1024), 0, s, wk.ghA, p.TA, wk.totA);
+    hipLaunchKernelGGL(digit_scan, dim3((unsigned)p.DA + xclass), dim3(1024), 0, s, wk.ghA, p.TA, wk.totA, p.DA, b,
+                       job ? job->classes : 0, job ? job->part : nullptr, job ? job->counts : nullptr,
+                       job ? job->inv_n : nullptr);
     prof_end(kKAScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKATotals, s);

@@ -339,6 +339,63 @@ struct Work {
     float *zpart = nullptr;    // [bslots << sb * Kmax] partial class sums
 };
 
+// ----------------------------------------------------------------------------- class counts
+// (Section 2: W row j holds 1/n_{y_j}). No global atomics on the counts: workgroup j of the
+// label slices histograms a contiguous slice of one graph's labels in LDS and writes its K
+// partial counts; then one wavefront per class adds the partials (integers, so the order
+// cannot change the result) and forms 1/n_k in float32 (0 for an empty class).
+
+// The whole workgroup: label slice j (hist: LDS of at least kMaxClasses ints).
+__device__ __forceinline__ void class_count_slice(const Batch &b, int j, int *__restrict__ part,
+                                                  unsigned *status, int *hist) {
+    const int g = find_graph(b.cnt_offs, b.G, j);
+    const GDesc d = load_desc(b, g);
+    const int jb = j - d.cnt_off;
+    const int K = d.K;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    const int64_t per = ((int64_t)d.N + d.cnt_blocks - 1) / d.cnt_blocks;
+    const int64_t lo = (int64_t)jb * per;
+    const int64_t hi = min((int64_t)d.N, lo + per);
+    bool bad = false;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const int y = d.labels[i];
+        if (y >= 0 && y < K)
+            atomicAdd(&hist[y], 1);
+        else if (y != -1)
+            bad = true;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrLabel);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) part[d.cpart_off + (int64_t)jb * K + k] = hist[k];
+}
+
+// One wavefront: class c of the launch (all graphs' classes in order).
+__device__ __forceinline__ void class_count_total(const Batch &b, int c, const int *__restrict__ part,
+                                                  int *__restrict__ counts, float *__restrict__ inv_n) {
+    const int lane = lane_id();
+    const int g = find_graph(b.class_offs, b.G, c);
+    const GDesc d = load_desc(b, g);
+    const int k = c - d.class_off;
+    const int *pp = part + d.cpart_off + k;
+    int n = 0;
+    for (int j = lane; j < d.cnt_blocks; j += 64) n += pp[(int64_t)j * d.K];
+    n = readlane(wave_scan_add(n), 63);
+    if (lane == 0) {
+        counts[c] = n;
+        if (inv_n) inv_n[c] = n > 0 ? 1.0f / (float)n : 0.0f;
+    }
+}
+
+// Class counts run inside the first partition launches (a_hist takes the label slices as
+// extra workgroups, digit_scan the class totals): both are independent of the partition.
+struct CountJob {
+    int *part = nullptr;
+    int *counts = nullptr;
+    float *inv_n = nullptr;
+    int slices = 0;  // label-slice workgroups (Plan::cnt_blocks)
+    int classes = 0; // Plan::Ktot
+};
+
 // ----------------------------------------------------------------------------- profiling
 // Kernel ids for the optional event hook (gee_profile_kernel). The hook records a
 // caller's hipEvents on the launch stream right before / after a kernel launch.
@@ -360,7 +417,9 @@ hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s
 hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
                                unsigned *status, hipStream_t s);
 // gee_csr.hip: edge lists -> CSR of the union (rows and columns offset by node_off).
-hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
+// With job, the class counts of the launch run in the same launches.
+hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s,
+                            const CountJob *job = nullptr);
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s);
 size_t bucket_sort_lds(int sb);
 int bucket_stage_cap(int sb);
