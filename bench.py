@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "edges embedded/sec + % HBM peak; served p50/p99 latency vs plain per-graph loop"
 HBM_PEAK_GBS = 8000.0
 
-KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
+KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_scatter",
            "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
            "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count", "bucket_part_fill", "bucket_degree",
            "bucket_degree_fix", "bucket_embed", "bucket_embed_fix"]
@@ -43,8 +43,8 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
     wv = 4 if weighted else 0
     if name == "class_count_partial":
         return 4 * N
-    if name == "a_hist":
-        return 8 * E
+    if name == "a_hist":  # edge list; on the edge-list paths also the labels (class counts)
+        return 8 * E + 4 * N
     if name == "a_scatter":  # edge list in, (low row bits u16, col[, w]) per entry out
         return (8 + wv) * E + (2 + 4 + wv) * M
     if name == "b_hist":

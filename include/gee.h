@@ -118,7 +118,7 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
    kernel records hipEvent `start_event` on its stream right before the launch and
    `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
    Kernel names: "class_count_partial", "class_count_final", "a_hist", "digit_scan",
-   "a_totals", "a_scatter", "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan",
+   "a_scatter", "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan",
    "c_scatter", "bucket_sort", "graph_meta",
    "zero_steps", "node_rows", "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows",
    "embed_fixup" (CSR path), "bucket_part_count", "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed",

@@ -522,7 +522,7 @@ hipStream_t launch_stream(void *s) {
 namespace gee {
 
 const char *const kKernelNames[kKNumKernels] = {
-    "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_totals", "a_scatter",
+    "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_scatter",
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
     "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix"};

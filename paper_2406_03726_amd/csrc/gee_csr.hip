@@ -10,7 +10,7 @@
 // values) and a low digit (2^s2 values), and the sort is three stable passes:
 //
 //   pass A  partition the virtual entries by high digit      (a_hist, digit_scan,
-//                                                              a_totals, a_scatter)
+//                                                              a_scatter)
 //   pass B  partition each high-digit segment by low digit    (seg_hist, seg_scan,
 //                                                              seg_scatter)
 //   pass C  buckets within the staging capacity (bucket_stage_cap): one workgroup per
@@ -269,33 +269,6 @@ __global__ __launch_bounds__(1024) void digit_scan(int *__restrict__ gh, int64_t
     if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Single workgroup over the D <= 256 high digits: segment starts, the entry count M,
-// and (with a pass B) the pass-B tiles of every segment.
-// Without a pass B the segments are the buckets.
-__global__ __launch_bounds__(256) void a_totals(const int *__restrict__ tot, int D, int with_b, int B,
-                                                int *__restrict__ seg_start, int *__restrict__ tile_off,
-                                                int *__restrict__ bstart, int *__restrict__ meta) {
-    __shared__ int wsum[4];
-    const int d = threadIdx.x;
-    const int n = d < D ? tot[d] : 0;
-    int total;
-    const int st = block_excl_scan256(n, wsum, total);
-    const int nt = (n + kTile - 1) / kTile;
-    int ttot;
-    const int to = block_excl_scan256(with_b ? nt : 0, wsum, ttot);
-    if (d < D) {
-        seg_start[d] = st;
-        if (with_b) tile_off[d] = to;
-        if (!with_b && d < B) bstart[d] = st;
-    }
-    if (d == 0) {
-        seg_start[D] = total;
-        if (with_b) tile_off[D] = ttot;
-        bstart[B] = total;
-        meta[0] = total;
-    }
-}
-
 // ----------------------------------------------------------------------------- wave-split ranking
 //
 // A tile is sorted by digit in LDS without a workgroup barrier per round: each of the 4
@@ -359,9 +332,11 @@ __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid) {
 // high digit is implied by the segment, so with at most 16 bits left it fits a u16.
 template <typename AK>
 __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int shift, int D, int nbits, int64_t T,
-                                                 const int *__restrict__ gh, const int *__restrict__ seg_start,
-                                                 AK *__restrict__ okey, int amask, int *__restrict__ ocol,
-                                                 float *__restrict__ oval, unsigned *status) {
+                                                      const int *__restrict__ gh, const int *__restrict__ tot,
+                                                      AK *__restrict__ okey, int amask, int *__restrict__ ocol,
+                                                      float *__restrict__ oval, unsigned *status, int with_b, int B,
+                                                      int *__restrict__ seg_start, int *__restrict__ tile_off,
+                                                      int *__restrict__ bstart, int *__restrict__ meta) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = blockIdx.x;
@@ -374,7 +349,29 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     for (int r = 0; r < kRoundsW; ++r)
         if (q.valid >> r & 1u) atomicAdd(&L.cnt[wv][q.key[r] >> shift], 1);
     __syncthreads();
-    const int gb = (int)threadIdx.x < D ? seg_start[threadIdx.x] + gh[(int64_t)threadIdx.x * T + t] : 0;
+    // segment starts: exclusive scan of the digit totals, in every workgroup (workgroup 0
+    // also writes them, the entry count M, the pass-B tiles of every segment and, without
+    // a pass B, the bucket starts, for the later launches)
+    const int dn = (int)threadIdx.x < D ? tot[threadIdx.x] : 0;
+    int total;
+    const int st = block_excl_scan<kThreads>(dn, L.wsum, total);
+    if (blockIdx.x == 0) {
+        int ttot;
+        const int to = block_excl_scan<kThreads>(with_b ? (dn + kTile - 1) / kTile : 0, L.wsum, ttot);
+        const int d = threadIdx.x;
+        if (d < D) {
+            seg_start[d] = st;
+            if (with_b) tile_off[d] = to;
+            if (!with_b && d < B) bstart[d] = st;
+        }
+        if (d == 0) {
+            seg_start[D] = total;
+            if (with_b) tile_off[D] = ttot;
+            bstart[B] = total;
+            meta[0] = total;
+        }
+    }
+    const int gb = (int)threadIdx.x < D ? st + gh[(int64_t)threadIdx.x * T + t] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
@@ -763,21 +760,19 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
                        job ? job->inv_n : nullptr);
     prof_end(kKAScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    prof_begin(kKATotals, s);
-    hipLaunchKernelGGL(a_totals, dim3(1), dim3(256), 0, s, wk.totA, p.DA, with_b ? 1 : 0, p.B, wk.segA,
-                       wk.tileB, wk.bstart, wk.meta);
-    prof_end(kKATotals, s);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // pass A keys: the row's low sb + s2 bits, as u16 when they fit
     const bool k16 = p.sb + p.s2 <= 16;
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     prof_begin(kKAScatter, s);
+    const int wb = with_b ? 1 : 0;
     if (k16) {
         hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
-                           p.TA, wk.ghA, wk.segA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status);
+                           p.TA, wk.ghA, wk.totA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status, wb, p.B,
+                           wk.segA, wk.tileB, wk.bstart, wk.meta);
     } else {
         hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
-                           p.TA, wk.ghA, wk.segA, wk.akey, -1, acol, aval, status);
+                           p.TA, wk.ghA, wk.totA, wk.akey, -1, acol, aval, status, wb, p.B, wk.segA, wk.tileB,
+                           wk.bstart, wk.meta);
     }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -400,7 +400,7 @@ struct CountJob {
 // Kernel ids for the optional event hook (gee_profile_kernel). The hook records a
 // caller's hipEvents on the launch stream right before / after a kernel launch.
 enum KernelId : int {
-    kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKATotals, kKAScatter, kKBHist, kKBScan,
+    kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKAScatter, kKBHist, kKBScan,
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
     kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKBucketPartCount, kKBucketPartFill, kKBucketDegree,
     kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKNumKernels
