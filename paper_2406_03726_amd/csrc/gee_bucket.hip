@@ -372,15 +372,25 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
         const int F4 = F & ~3, step = 4 * nt;
         const int qn = step / K, rn = step - qn * K;
         int jj = (4 * t) / K, kk = 4 * t - ((4 * t) / K) * K;
+        const bool whole = (K & 3) == 0;  // every group of 4 lies in one row, 16-byte aligned in LDS
         for (int f = 4 * t; f < F4; f += step) {
             v4 v;
-            int j2 = jj, k2 = kk;
+            if (whole) {
+                const float4 a = *reinterpret_cast<const float4 *>(acc + jj * KP + kk);
+                const float g = fac[jj];
+                v[0] = a.x * g;
+                v[1] = a.y * g;
+                v[2] = a.z * g;
+                v[3] = a.w * g;
+            } else {
+                int j2 = jj, k2 = kk;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = acc[j2 * KP + k2] * fac[j2];
-                if (++k2 == K) {
-                    k2 = 0;
-                    ++j2;
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = acc[j2 * KP + k2] * fac[j2];
+                    if (++k2 == K) {
+                        k2 = 0;
+                        ++j2;
+                    }
                 }
             }
             __builtin_nontemporal_store(v, reinterpret_cast<v4 *>(z + f));
