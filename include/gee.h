@@ -117,12 +117,15 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
 /* Profiling hook (for benchmarks and tests). From this call on, every launch of the named
    kernel records hipEvent `start_event` on its stream right before the launch and
    `stop_event` right after (both hipEvent_t passed as void*; both NULL removes the hook).
-   Kernel names: "class_count_partial", "class_count_final", "a_hist", "digit_scan",
-   "a_scatter", "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan",
-   "c_scatter", "bucket_sort", "graph_meta",
-   "zero_steps", "node_rows", "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows",
-   "embed_fixup" (CSR path), "bucket_part_count", "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed",
-   "bucket_embed_fix" (bucket path of gee_embed and batches). Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
+   Kernel names:
+     class counts: "class_count_partial", "class_count_final";
+     partition passes: "a_hist", "digit_scan", "a_scatter", "b_hist", "b_scan", "b_scatter",
+       "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort";
+     CSR path: "graph_meta", "zero_steps", "node_rows", "degree_rows", "degree_fixup",
+       "node_coef", "fill_empty", "embed_rows", "embed_fixup";
+     bucket path (gee_embed and batches): "bucket_part_count", "bucket_part_fill",
+       "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix".
+   Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
 int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event);
