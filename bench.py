@@ -11,6 +11,10 @@ Prints one JSON line. `value` is edges embedded per second over the timed steps.
 `batched` adds the 512-graph batched form (one captured batch plan against 512 plain
 calls) and `serving` the served form (Poisson requests, budget admission and continuous
 batching against the plain per-request loop, p50/p99 latency).
+`original` adds the original, edge-list form of GEE (gee_embed_atomic: one pass of float
+atomics over the edge list, no CSR) on the same workload and, as in the paper's GEE
+against sparse GEE comparison, both forms on the 2,000-node SBM graph with the options
+off and all on.
 `roofline` is for the kernel with the largest share of the step, timed live with HIP
 events recorded around each of its launches on the launch stream (library hook), and
 priced with its algorithmic bytes against the 8 TB/s HBM peak. `cpu_baseline` is the
@@ -66,7 +70,99 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return (2 + wv) * M + 4 * N + 4 * N + 8 * N
     if name == "bucket_embed":  # bucketed (row-in-bucket u16, col[, w]) in, {c_j, y_j} and s_i once, Z out
         return (2 + 4 + wv) * M + 8 * N + 4 * N + 4 * N * K
+    if name == "edge_scatter":  # edge list in, {c_j, y_j} once, Z written once
+        return (8 + wv) * E + 8 * N + 4 * N * K
+    if name == "edge_prep":  # labels; under the Laplacian the edge list and the degrees
+        return 4 * N + (8 + wv) * E + 4 * N
+    if name == "edge_init":
+        return 4 * N * K + 4 * N
+    if name == "edge_coef":
+        return 4 * N + 4 * N + 4 * N + 8 * N
+    if name == "edge_finish":
+        return 2 * 4 * N * K + 4 * N + 8 * N
     return 0
+
+
+EDGE_KERNELS = ["edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish"]
+
+
+def _time_calls(torch, fn, reps, warmup=3):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def original_leg(torch, np, gee, lib, dev, g, tens, Z_sparse, steps, ev):
+    """The original GEE form against the sparse path: the benchmark workload, then the
+    2,000-node SBM graph with options off and all on (launch-bound sizes)."""
+    src, dst, w, lab = tens
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    E, N, K = g.E, g.N, g.K
+    Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(1, gee.gee_embed_atomic_workspace_bytes(N, K, flags)), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        gee.gee_embed_atomic(src, dst, w, lab, K, flags, Z=Z, workspace=ws, stream=stream)
+
+    ms = _time_calls(torch, call, steps)
+    if gee.gee_get_data_errors() != 0:
+        raise RuntimeError("device reported a data error in the original form")
+    kernels = {}
+    for name in EDGE_KERNELS:
+        a, b = ev.create(), ev.create()
+        lib.gee_profile_kernel(name.encode(), a, b)
+        call()
+        torch.cuda.synchronize()
+        lib.gee_profile_kernel(name.encode(), None, None)
+        try:
+            kms = ev.elapsed_ms(a, b)
+            nb = algorithmic_bytes(name, E, N, K, 0, w is not None, 0)
+            kernels[name] = {"ms": round(kms, 5), "algorithmic_bytes": int(nb),
+                             "GB_per_s": round(nb / (kms * 1e-3) / 1e9, 1) if kms > 0 else None}
+        except RuntimeError:  # not launched for this workload
+            pass
+        ev.destroy(a)
+        ev.destroy(b)
+    nz = Z_sparse != 0
+    rel = float(((Z - Z_sparse).abs()[nz] / Z_sparse.abs()[nz]).max().item()) if bool(nz.any()) else 0.0
+    out = {"ms_per_call": round(ms, 5), "edges_per_s": round(E / (ms * 1e-3), 1),
+           "max_rel_diff_to_sparse_path": rel, "same_zero_entries_as_sparse_path": bool(torch.equal(Z != 0, nz)),
+           "kernels": kernels}
+    del Z, ws
+    small = []
+    for opt in ("off", "all"):
+        gs = make_workload(f"sbm_small_{opt}")
+        t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
+        s2, d2, w2, l2 = t(gs.src, torch.int32), t(gs.dst, torch.int32), t(gs.w, torch.float32), t(gs.labels, torch.int32)
+        f2 = gee.flags_of(gs.diag, gs.lap, gs.cor, gs.sym)
+        Zs = torch.empty((gs.N, gs.K), dtype=torch.float32, device=dev)
+        Za = torch.empty_like(Zs)
+        wss = torch.empty(max(1, gee.gee_embed_workspace_bytes(gs.E, gs.N, gs.K, f2, w2 is not None)),
+                          dtype=torch.uint8, device=dev)
+        wsa = torch.empty(max(1, gee.gee_embed_atomic_workspace_bytes(gs.N, gs.K, f2)), dtype=torch.uint8,
+                          device=dev)
+        sp_ms = _time_calls(torch, lambda: gee.gee_embed(s2, d2, w2, l2, gs.K, f2, Z=Zs, workspace=wss,
+                                                          stream=stream), 200)
+        at_ms = _time_calls(torch, lambda: gee.gee_embed_atomic(s2, d2, w2, l2, gs.K, f2, Z=Za, workspace=wsa,
+                                                                 stream=stream), 200)
+        nz2 = Zs != 0
+        small.append({"workload": gs.name, "E": gs.E, "options": opt, "sparse_ms_per_call": round(sp_ms, 5),
+                      "original_ms_per_call": round(at_ms, 5),
+                      "max_rel_diff": float(((Za - Zs).abs()[nz2] / Zs.abs()[nz2]).max().item())})
+    out["sbm_n2000"] = small
+    return out
+
+
+def _progress(msg):
+    """One line on stderr when a phase of the run has finished (the JSON line stays alone
+    on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def make_workload(name):
@@ -408,8 +504,8 @@ def main():
                     choices=["powerlaw_10m", "sbm_dense", "sbm_small_all", "sbm_small_off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", default=None, help="also write a detailed JSON report here")
-    ap.add_argument("--legs", default="batched,serving",
-                    help="systems legs to add to the line: batched, serving (comma list, or none)")
+    ap.add_argument("--legs", default="original,batched,serving",
+                    help="legs to add to the line: original, batched, serving (comma list, or none)")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1),
                     help="worker processes that draw the systems legs' graphs")
     ap.add_argument("--pmc-target", action="store_true",
@@ -450,6 +546,7 @@ def main():
     t_gen = time.perf_counter()
     g = make_workload(args.workload)
     t_gen = time.perf_counter() - t_gen
+    _progress(f"workload {g.name} generated in {t_gen:.1f} s")
     dev = torch.device("cuda:0")
     t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
     src, dst, w, lab = t(g.src, torch.int32), t(g.dst, torch.int32), t(g.w, torch.float32), t(g.labels, torch.int32)
@@ -492,6 +589,7 @@ def main():
         ev.destroy(a)
         ev.destroy(b)
     dominant = max(per_kernel, key=per_kernel.get)
+    _progress(f"per-kernel pass done; dominant kernel {dominant}")
 
     # Timed region: K steps; HIP events around every launch of the dominant kernel.
     pairs = [(ev.create(), ev.create()) for _ in range(args.steps)]
@@ -509,6 +607,7 @@ def main():
         ev.destroy(b)
 
     elapsed = t1 - t0
+    _progress(f"timed {args.steps} steps: {elapsed / args.steps * 1e3:.4f} ms per step")
     ms_per_step = elapsed / args.steps * 1e3
     value = E * args.steps / elapsed
     dom_avg_ms = float(np.mean(dom_ms))
@@ -569,6 +668,11 @@ def main():
                                "same_zero_entries_as_edge_list_path": zeros_same},
     }
     legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if "original" in legs:
+        out["original_gee_form"] = original_leg(torch, np, gee, lib, dev, g, (src, dst, w, lab), Z, args.steps, ev)
+        _progress("original-form leg done")
+        torch.cuda.empty_cache()
+    legs = [x for x in legs if x != "original"]
     if legs:
         from paper_2406_03726_amd.autotune import ScheduleTable
 
@@ -576,9 +680,11 @@ def main():
         del Zr, ws2
         if "batched" in legs:
             out["batched"] = batched_leg(torch, np, gee, dev, table, args.procs)
+            _progress("batched leg done")
             torch.cuda.empty_cache()
         if "serving" in legs:
             out["serving"] = serving_leg(torch, np, gee, dev, table, args.procs)
+            _progress("serving leg done")
             torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)

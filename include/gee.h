@@ -30,7 +30,9 @@
  *     item is skipped, Z is then unspecified, and a sticky per-device bit is raised
  *     that gee_get_data_errors() reads and clears.
  *   - Results are deterministic: the same inputs give bitwise identical Z, CSR and
- *     class counts on every call. No floating-point global atomics are used.
+ *     class counts on every call. No floating-point global atomics are used. The one
+ *     exception is gee_embed_atomic (the original, edge-list form of the method), whose Z
+ *     may differ from call to call in the last bits.
  *   - Calls on different streams may run concurrently. The data-error word is per
  *     device, so concurrent calls share it.
  */
@@ -124,7 +126,9 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
      CSR path: "graph_meta", "zero_steps", "node_rows", "degree_rows", "degree_fixup",
        "node_coef", "fill_empty", "embed_rows", "embed_fixup";
      bucket path (gee_embed and batches): "bucket_part_count", "bucket_part_fill",
-       "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix".
+       "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix";
+     original GEE form (gee_embed_atomic): "edge_init", "edge_prep", "edge_coef",
+       "edge_scatter", "edge_finish".
    Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
@@ -201,6 +205,31 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
                      int32_t N, const int32_t *labels, int32_t K, uint32_t flags, float *Z,
                      const gee_schedule *sched, void *workspace, size_t workspace_bytes,
                      void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_embed_atomic - the original GEE form (Section 2): Z computed straight from the edge
+ * list in one pass over its rows, with no CSR and no sort, the form the paper compares
+ * sparse GEE against (Section 4, Tables 3-4, Figure 3). Same result as gee_embed (Eq. 1
+ * with the Table 1 options, diagonal augmentation before the Laplacian) up to float32
+ * rounding, but NOT deterministic: every row adds its term to Z with a float atomic, so
+ * the summation order, and the last bits of Z, may change from call to call.
+ *   src, dst, w, E, N, labels, K, flags, Z : as for gee_embed
+ * Steps, all on the device: Z = 0; class counts; under the Laplacian, weighted degrees by
+ * float atomics (d_i = 1 + row sum under diagonal augmentation); per node s_j = d_j^-1/2
+ * (0 for d_j <= 0) and c_j = s_j / n_{y_j}; per edge row Z[src, y_dst] += w c_dst (and,
+ * under GEE_SYMMETRIZE, Z[dst, y_src] += w c_src, a self-loop once); per Z row the
+ * diagonal term, the factor s_i and the correlation 2-norm.
+ * Data errors as for gee_embed: offending rows or labels are skipped and flagged.
+ * gee_embed_atomic allocates its scratch with hipMallocAsync/hipFreeAsync on `stream`; the
+ * _ws variant takes caller scratch of gee_embed_atomic_workspace_bytes() bytes (0 for
+ * invalid sizes) and allocates nothing. Limits as for gee_embed except that E has no
+ * upper bound beyond int64 (no CSR is formed). */
+size_t gee_embed_atomic_workspace_bytes(int32_t N, int32_t K, uint32_t flags);
+int gee_embed_atomic(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                     const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream);
+int gee_embed_atomic_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                        const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * Batches: gee_embed of G independent graphs in one launch sequence. The graphs are

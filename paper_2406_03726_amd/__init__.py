@@ -23,6 +23,8 @@ from .gee import (  # noqa: F401
     gee_csr_capacity,
     gee_default_schedule,
     gee_embed,
+    gee_embed_atomic,
+    gee_embed_atomic_workspace_bytes,
     gee_embed_batch,
     gee_embed_batch_workspace_bytes,
     gee_embed_csr,

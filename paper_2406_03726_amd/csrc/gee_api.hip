@@ -525,7 +525,8 @@ const char *const kKernelNames[kKNumKernels] = {
     "class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_scatter",
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
-    "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix"};
+    "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix",
+    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
@@ -781,6 +782,44 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return hip_status(e);
     rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Z, nullptr, ws, bytes, stream);
+    e = hipFreeAsync(ws, s);
+    return rc ? rc : hip_status(e);
+}
+
+// --------------------------------------------------------------------------- original GEE form
+
+size_t gee_embed_atomic_workspace_bytes(int32_t N, int32_t K, uint32_t flags) {
+    if (check_common(N, K, flags)) return 0;
+    return edge_workspace_bytes(N, K, flags);
+}
+
+int gee_embed_atomic_ws(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
+                        const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+    if (E < 0) return GEE_ERR_ARG;
+    int rc = check_common(N, K, flags);
+    if (rc) return rc;
+    if (N == 0) return E > 0 ? GEE_ERR_ARG : GEE_OK;
+    if (!labels || !Z || (E > 0 && (!src || !dst))) return GEE_ERR_ARG;
+    if (!workspace || workspace_bytes < edge_workspace_bytes(N, K, flags)) return GEE_ERR_WORKSPACE;
+    unsigned *st = nullptr;
+    if ((rc = device_status(&st))) return rc;
+    hipStream_t s = launch_stream(stream);
+    return hip_status(launch_edge_embed(src, dst, wgt, E, N, labels, K, flags, Z, workspace, st, s));
+}
+
+int gee_embed_atomic(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
+                     const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream) {
+    if (E < 0) return GEE_ERR_ARG;
+    int rc = check_common(N, K, flags);
+    if (rc) return rc;
+    if (N == 0) return E > 0 ? GEE_ERR_ARG : GEE_OK;
+    const size_t bytes = edge_workspace_bytes(N, K, flags);
+    hipStream_t s = as_stream(stream);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, bytes, s);
+    if (e != hipSuccess) return hip_status(e);
+    rc = gee_embed_atomic_ws(src, dst, wgt, E, N, labels, K, flags, Z, ws, bytes, stream);
     e = hipFreeAsync(ws, s);
     return rc ? rc : hip_status(e);
 }

@@ -403,7 +403,8 @@ enum KernelId : int {
     kKCountPartial = 0, kKCountFinal, kKAHist, kKAScan, kKAScatter, kKBHist, kKBScan,
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
     kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKBucketPartCount, kKBucketPartFill, kKBucketDegree,
-    kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKNumKernels
+    kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKEdgeInit, kKEdgePrep, kKEdgeCoef, kKEdgeScatter,
+    kKEdgeFinish, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
@@ -440,5 +441,10 @@ constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
 constexpr int kBucketDefaultPart = 8192;
 constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end
 hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s);
+// Original GEE form (edge-list scatter with float atomics; gee_edge.hip): workspace bytes
+// and the whole launch sequence for one graph.
+size_t edge_workspace_bytes(int N, int K, unsigned flags);
+hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int64_t E, int N, const int *labels,
+                             int K, unsigned flags, float *Z, void *ws, unsigned *status, hipStream_t s);
 
 }  // namespace gee

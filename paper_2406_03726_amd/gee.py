@@ -217,6 +217,40 @@ def gee_embed_csr_workspace_bytes(M: int, N: int, K: int, flags: int, sched=None
     return int(_lib.load().gee_embed_csr_workspace_bytes(M, N, K, flags, _sched_ptr(sched)))
 
 
+def gee_embed_atomic_workspace_bytes(N: int, K: int, flags: int) -> int:
+    return int(_lib.load().gee_embed_atomic_workspace_bytes(N, K, flags))
+
+
+def gee_embed_atomic(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], labels: torch.Tensor,
+                     K: int, flags: int, Z: Optional[torch.Tensor] = None,
+                     workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Z (float32, N x K) of the edge list by the original, edge-list form of GEE (float
+    atomics: the last bits of Z may differ between calls); N is labels.numel()."""
+    labels = _dev(labels, torch.int32, "labels")
+    dev = labels.device
+    src = _dev(src, torch.int32, "src", dev)
+    dst = _dev(dst, torch.int32, "dst", dev)
+    w = _dev(w, torch.float32, "w", dev)
+    E = src.numel()
+    N = labels.numel()
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    if Z is None:
+        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    _dev(Z, torch.float32, "Z", dev)
+    if Z.numel() != N * K:
+        raise ValueError("Z must hold N * K floats")
+    lib = _lib.load()
+    nbytes = lib.gee_embed_atomic_workspace_bytes(N, K, flags)
+    if nbytes == 0 and N > 0:
+        raise GeeError(GEE_ERR_ARG, "gee_embed_atomic_workspace_bytes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib.gee_embed_atomic_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z),
+                                   _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed_atomic")
+    return Z
+
+
 # ----------------------------------------------------------------------------- batches
 
 def _graph_struct(g: dict, dev, sizing: bool = False) -> _lib.GeeGraph:

@@ -67,6 +67,14 @@ def test_host_only_queries(lib):
     assert lib.gee_embed_workspace_bytes(1000, 100, 3, 1 << 9, 1, None) == 0    # unknown flag bit
     big = lib.gee_embed_workspace_bytes(2 ** 30, 100, 3, 8, 1, None)
     assert big == 0  # 2^31 entries exceed the int32 CSR
+    # original GEE form: counts, per-node table and (Laplacian) degrees, each 256-byte aligned
+    assert lib.gee_embed_atomic_workspace_bytes(1000, 3, 8) == 256 + 8192
+    assert lib.gee_embed_atomic_workspace_bytes(1000, 3, 15) == 256 + 8192 + 4096
+    assert lib.gee_embed_atomic_workspace_bytes(1000, 0, 15) == 0
+    assert lib.gee_embed_atomic_workspace_bytes(1000, 129, 15) == 0
+    assert lib.gee_embed_atomic_workspace_bytes(-1, 3, 15) == 0
+    assert lib.gee_embed_atomic_workspace_bytes(1000, 3, 1 << 9) == 0
+    assert lib.gee_embed_atomic_workspace_bytes(2 ** 24 + 1, 3, 15) == 0  # beyond the node limit
 
 
 def test_schedule_validation(lib):
