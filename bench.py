@@ -15,6 +15,7 @@ batching against the plain per-request loop, p50/p99 latency).
 atomics over the edge list, no CSR) on the same workload and, as in the paper's GEE
 against sparse GEE comparison, both forms on the 2,000-node SBM graph with the options
 off and all on.
+`sparse` adds Z in sparse storage (gee_embed_sparse) on the same workload.
 `roofline` is for the kernel with the largest share of the step, timed live with HIP
 events recorded around each of its launches on the launch stream (library hook), and
 priced with its algorithmic bytes against the 8 TB/s HBM peak. `cpu_baseline` is the
@@ -81,6 +82,45 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
     if name == "edge_finish":
         return 2 * 4 * N * K + 4 * N + 8 * N
     return 0
+
+
+def sparse_leg(torch, np, gee, lib, dev, g, tens, Z_dense, steps, ev):
+    """Z in sparse storage (gee_embed_sparse) on the benchmark workload: time per call against
+    the dense call, stored entries and bytes, and the compaction kernels' own times."""
+    src, dst, w, lab = tens
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    E, N, K = g.E, g.N, g.K
+    rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(N * K, dtype=torch.int32, device=dev)
+    val = torch.empty(N * K, dtype=torch.float32, device=dev)
+    ws = torch.empty(gee.gee_embed_sparse_workspace_bytes(E, N, K, flags, w is not None), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        gee.gee_embed_sparse(src, dst, w, lab, K, flags, row_ptr=rp, col=col, val=val, workspace=ws, stream=stream)
+
+    ms = _time_calls(torch, call, steps)
+    nnz = int(rp[-1].item())
+    kernels = {}
+    for name in ("zs_count", "zs_write"):
+        a, b = ev.create(), ev.create()
+        lib.gee_profile_kernel(name.encode(), a, b)
+        call()
+        torch.cuda.synchronize()
+        lib.gee_profile_kernel(name.encode(), None, None)
+        kms = ev.elapsed_ms(a, b)
+        nb = 4 * N * K + (4 * (N + 1) + 8 * nnz if name == "zs_write" else 0)
+        kernels[name] = {"ms": round(kms, 5), "algorithmic_bytes": int(nb), "GB_per_s": round(nb / (kms * 1e-3) / 1e9, 1)}
+        ev.destroy(a)
+        ev.destroy(b)
+    same = bool(torch.equal(Z_dense.reshape(-1)[(torch.repeat_interleave(
+        torch.arange(N, device=dev), (rp[1:] - rp[:-1]).long()) * K + col[:nnz].long())], val[:nnz]))
+    out = {"ms_per_call": round(ms, 5), "edges_per_s": round(E / (ms * 1e-3), 1), "nnz": nnz,
+           "density": round(nnz / (N * K), 4), "sparse_bytes": 4 * (N + 1) + 8 * nnz, "dense_bytes": 4 * N * K,
+           "values_equal_dense_call": same, "kernels": kernels}
+    del rp, col, val, ws
+    return out
 
 
 EDGE_KERNELS = ["edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish"]
@@ -504,8 +544,8 @@ def main():
                     choices=["powerlaw_10m", "sbm_dense", "sbm_small_all", "sbm_small_off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", default=None, help="also write a detailed JSON report here")
-    ap.add_argument("--legs", default="original,batched,serving",
-                    help="legs to add to the line: original, batched, serving (comma list, or none)")
+    ap.add_argument("--legs", default="original,sparse,batched,serving",
+                    help="legs to add to the line: original, sparse, batched, serving (comma list, or none)")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1),
                     help="worker processes that draw the systems legs' graphs")
     ap.add_argument("--pmc-target", action="store_true",
@@ -672,7 +712,11 @@ def main():
         out["original_gee_form"] = original_leg(torch, np, gee, lib, dev, g, (src, dst, w, lab), Z, args.steps, ev)
         _progress("original-form leg done")
         torch.cuda.empty_cache()
-    legs = [x for x in legs if x != "original"]
+    if "sparse" in legs:
+        out["sparse_z"] = sparse_leg(torch, np, gee, lib, dev, g, (src, dst, w, lab), Z, args.steps, ev)
+        torch.cuda.empty_cache()
+        _progress("sparse-Z leg done")
+    legs = [x for x in legs if x not in ("original", "sparse")]
     if legs:
         from paper_2406_03726_amd.autotune import ScheduleTable
 

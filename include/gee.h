@@ -128,7 +128,8 @@ int gee_get_data_errors(void *stream, uint32_t *bits);
      bucket path (gee_embed and batches): "bucket_part_count", "bucket_part_fill",
        "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix";
      original GEE form (gee_embed_atomic): "edge_init", "edge_prep", "edge_coef",
-       "edge_scatter", "edge_finish".
+       "edge_scatter", "edge_finish";
+     sparse Z (gee_embed_sparse): "zs_count", "zs_write".
    Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
@@ -205,6 +206,33 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
                      int32_t N, const int32_t *labels, int32_t K, uint32_t flags, float *Z,
                      const gee_schedule *sched, void *workspace, size_t workspace_bytes,
                      void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_embed_sparse - gee_embed with Z returned in sparse storage, as the paper keeps the
+ * embedding matrix (Section 3: a CSR of index pointers, column indices and data; most
+ * entries of Z are zero, since W is one-hot).
+ *   src, dst, w, E, N, labels, K, flags : as for gee_embed (N * K must be below 2^31)
+ *   row_ptr  : int32[N + 1] device output; row i's non-zero entries of Z are entries
+ *              row_ptr[i] .. row_ptr[i+1]-1; row_ptr[N] = nnz, the number of non-zero entries
+ *   col      : int32[capacity] device output, the class k of each entry, increasing in a row
+ *   val      : float32[capacity] device output, Z[i, k] (exactly the values gee_embed writes)
+ *   capacity : entries col and val can hold. Only the first min(nnz, capacity) entries are
+ *              written; row_ptr is always complete, so a caller that finds row_ptr[N] >
+ *              capacity can call again with larger arrays (capacity N * K always suffices).
+ *              capacity 0 with col and val NULL computes row_ptr alone.
+ * An entry is stored when its float32 value is not zero (a -0.0 is not stored).
+ * gee_embed_sparse allocates its scratch (which includes a dense Z) with hipMallocAsync /
+ * hipFreeAsync on `stream`; the _ws variant takes caller scratch of
+ * gee_embed_sparse_workspace_bytes() bytes (0 for invalid sizes) and a schedule. */
+size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
+                                        const gee_schedule *sched);
+int gee_embed_sparse(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                     const int32_t *labels, int32_t K, uint32_t flags, int32_t *row_ptr, int32_t *col,
+                     float *val, int64_t capacity, void *stream);
+int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                        const int32_t *labels, int32_t K, uint32_t flags, int32_t *row_ptr, int32_t *col,
+                        float *val, int64_t capacity, const gee_schedule *sched, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * gee_embed_atomic - the original GEE form (Section 2): Z computed straight from the edge

@@ -8,6 +8,7 @@ no code with the HIP implementation.
 * ``class_counts`` - exact integer n_k (C).
 * ``degrees``      - row sums of A (or A + I), float64 (C).
 * ``csr``          - the canonical CSR of an edge list (numpy stable sort).
+* ``sparse_rows``  - Z in sparse storage (its non-zero entries in the Section 3 CSR layout).
 """
 
 from .oracle import (  # noqa: F401
@@ -19,3 +20,4 @@ from .oracle import (  # noqa: F401
     lib_path,
 )
 from .csr_ref import csr, csr_graph  # noqa: F401
+from .zsparse import dense_of, sparse_rows  # noqa: F401

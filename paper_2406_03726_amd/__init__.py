@@ -25,6 +25,8 @@ from .gee import (  # noqa: F401
     gee_embed,
     gee_embed_atomic,
     gee_embed_atomic_workspace_bytes,
+    gee_embed_sparse,
+    gee_embed_sparse_workspace_bytes,
     gee_embed_batch,
     gee_embed_batch_workspace_bytes,
     gee_embed_csr,

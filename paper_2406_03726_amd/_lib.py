@@ -66,6 +66,16 @@ SYMBOLS = {
                                         ctypes.c_int32, ctypes.c_uint32, c_f32p,
                                         ctypes.POINTER(GeeSchedule), ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "gee_embed_sparse_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                            ctypes.c_uint32, ctypes.c_int,
+                                                            ctypes.POINTER(GeeSchedule)]),
+    "gee_embed_sparse": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,
+                                        ctypes.c_int32, ctypes.c_uint32, c_i32p, c_i32p, c_f32p,
+                                        ctypes.c_int64, ctypes.c_void_p]),
+    "gee_embed_sparse_ws": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,
+                                           ctypes.c_int32, ctypes.c_uint32, c_i32p, c_i32p, c_f32p,
+                                           ctypes.c_int64, ctypes.POINTER(GeeSchedule), ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p]),
     "gee_embed_atomic_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
     "gee_embed_atomic": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,
                                         ctypes.c_int32, ctypes.c_uint32, c_f32p, ctypes.c_void_p]),

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgee.so")
-SOURCES = ["gee_count.hip", "gee_csr.hip", "gee_embed.hip", "gee_bucket.hip", "gee_edge.hip", "gee_api.hip"]
+SOURCES = ["gee_count.hip", "gee_csr.hip", "gee_embed.hip", "gee_bucket.hip", "gee_edge.hip", "gee_zsparse.hip", "gee_api.hip"]
 ARCH = "gfx950"
 
 # Packed fp32 VALU ops are kept off (hipcc still vectorizes scalar code without them).

@@ -526,7 +526,7 @@ const char *const kKernelNames[kKNumKernels] = {
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
     "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix",
-    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish"};
+    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish", "zs_count", "zs_write"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
@@ -782,6 +782,62 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
     hipError_t e = hipMallocAsync(&ws, bytes, s);
     if (e != hipSuccess) return hip_status(e);
     rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Z, nullptr, ws, bytes, stream);
+    e = hipFreeAsync(ws, s);
+    return rc ? rc : hip_status(e);
+}
+
+// --------------------------------------------------------------------------- sparse Z
+
+size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
+                                        const gee_schedule *sched) {
+    if (E < 0 || check_common(N, K, flags) || (int64_t)N * K > INT32_MAX) return 0;
+    if (N == 0) return kAlign;
+    const size_t eb = gee_embed_workspace_bytes(E, N, K, flags, weighted, sched);
+    if (eb == 0) return 0;
+    auto up = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
+    return up(eb) + up((size_t)N * K * sizeof(float)) + up((size_t)zsparse_tiles(N) * sizeof(int));
+}
+
+int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
+                        const int32_t *labels, int32_t K, uint32_t flags, int32_t *row_ptr, int32_t *col,
+                        float *val, int64_t capacity, const gee_schedule *sched, void *workspace,
+                        size_t workspace_bytes, void *stream) {
+    if (E < 0 || capacity < 0) return GEE_ERR_ARG;
+    int rc = check_common(N, K, flags);
+    if (rc) return rc;
+    if ((int64_t)N * K > INT32_MAX) return GEE_ERR_TOO_LARGE;
+    if (!row_ptr || (capacity > 0 && (!col || !val))) return GEE_ERR_ARG;
+    if (N == 0) {
+        if (E > 0) return GEE_ERR_ARG;
+        return hip_status(hipMemsetAsync(row_ptr, 0, sizeof(int32_t), launch_stream(stream)));
+    }
+    const size_t need = gee_embed_sparse_workspace_bytes(E, N, K, flags, wgt != nullptr, sched);
+    if (need == 0) return GEE_ERR_TOO_LARGE;
+    if (!workspace || workspace_bytes < need) return GEE_ERR_WORKSPACE;
+    auto up = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
+    const size_t eb = up(gee_embed_workspace_bytes(E, N, K, flags, wgt != nullptr, sched));
+    char *base = static_cast<char *>(workspace);
+    float *Zd = reinterpret_cast<float *>(base + eb);
+    int *tile = reinterpret_cast<int *>(base + eb + up((size_t)N * K * sizeof(float)));
+    rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Zd, sched, workspace, eb, stream);
+    if (rc) return rc;
+    return hip_status(launch_zsparse(Zd, N, K, tile, row_ptr, col, val, capacity, as_stream(stream)));
+}
+
+int gee_embed_sparse(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
+                     const int32_t *labels, int32_t K, uint32_t flags, int32_t *row_ptr, int32_t *col,
+                     float *val, int64_t capacity, void *stream) {
+    if (E < 0 || capacity < 0) return GEE_ERR_ARG;
+    int rc = check_common(N, K, flags);
+    if (rc) return rc;
+    const size_t bytes = gee_embed_sparse_workspace_bytes(E, N, K, flags, wgt != nullptr, nullptr);
+    if (bytes == 0) return GEE_ERR_TOO_LARGE;
+    hipStream_t s = as_stream(stream);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, bytes, s);
+    if (e != hipSuccess) return hip_status(e);
+    rc = gee_embed_sparse_ws(src, dst, wgt, E, N, labels, K, flags, row_ptr, col, val, capacity, nullptr, ws,
+                             bytes, stream);
     e = hipFreeAsync(ws, s);
     return rc ? rc : hip_status(e);
 }

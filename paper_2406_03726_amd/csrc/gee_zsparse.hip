@@ -1,0 +1,173 @@
+// gee_zsparse.hip - the embedding in sparse storage: Z's non-zero entries kept row by row in
+// the CSR layout of Section 3 (index pointers of N + 1 entries, then the class index and the
+// value of each non-zero entry, row after row, classes increasing), as the paper stores the
+// embedding matrix. Z is dense float32 N x K on entry (the class-scatter kernels write it).
+//
+// Rows are taken in tiles of kZT; inside a tile, groups of L lanes (the power of two at or
+// above min(K, 64)) take one row each, a lane the columns sub and sub + L.
+//   zs_count  per tile: number of non-zero entries
+//   zs_scan   one workgroup: exclusive scan of the tile counts, total into row_ptr[N]
+//   zs_write  per tile: the rows' counts again, their scan in LDS, then row_ptr and the
+//             compacted (class, value) pairs at each lane's rank within its row
+#include "gee_internal.h"
+
+namespace gee {
+namespace {
+
+constexpr int kZT = 1024;  // rows per tile
+constexpr int kZB = 256;   // threads per workgroup of the tile kernels
+
+// Bits of `m` that belong to this lane's group of L lanes, shifted down to bit 0.
+template <int L>
+__device__ __forceinline__ uint64_t group_bits(uint64_t m, int lane) {
+    if constexpr (L == 64) {
+        return m;
+    } else {
+        return (m >> (lane & ~(L - 1))) & ((1ull << L) - 1);
+    }
+}
+
+// Loads the lane's two columns of row i (zero past K or for i >= N) and returns the row's
+// non-zero masks over its group (bit sub: column sub, and column sub + L).
+template <int L>
+__device__ __forceinline__ void row_nonzeros(const float *__restrict__ Z, int64_t i, int N, int K, int sub,
+                                            int lane, float &z0, float &z1, uint64_t &m0, uint64_t &m1) {
+    z0 = 0.0f;
+    z1 = 0.0f;
+    if (i < N) {
+        const float *row = Z + i * K;
+        if (sub < K) z0 = row[sub];
+        if (sub + L < K) z1 = row[sub + L];
+    }
+    m0 = group_bits<L>(ballot(z0 != 0.0f), lane);
+    m1 = group_bits<L>(ballot(z1 != 0.0f), lane);
+}
+
+template <int L>
+__global__ __launch_bounds__(kZB) void zs_count(const float *__restrict__ Z, int N, int K, int *__restrict__ tile_tot) {
+    __shared__ int wsum[kZB / 64];
+    const int lane = lane_id(), sub = threadIdx.x % L, grp = threadIdx.x / L;
+    constexpr int G = kZB / L;
+    const int64_t base = (int64_t)blockIdx.x * kZT;
+    int n = 0;
+    for (int r = grp; r < kZT; r += G) {  // the same trip count for every group of a wavefront
+        float z0, z1;
+        uint64_t m0, m1;
+        row_nonzeros<L>(Z, base + r, N, K, sub, lane, z0, z1, m0, m1);
+        if (sub == 0) n += __popcll(m0) + __popcll(m1);
+    }
+    int tot = 0;
+    (void)block_excl_scan<kZB>(n, wsum, tot);
+    if (threadIdx.x == 0) tile_tot[blockIdx.x] = tot;
+}
+
+// One workgroup of 1024 threads: tile_tot becomes exclusive offsets; the total is row_ptr[N].
+__global__ __launch_bounds__(1024) void zs_scan(int *__restrict__ tile_tot, int T, int *__restrict__ row_ptr, int N) {
+    __shared__ int wsum[1024 / 64];
+    int carry = 0;
+    for (int b0 = 0; b0 < T; b0 += 1024) {
+        const int b = b0 + (int)threadIdx.x;
+        const int v = b < T ? tile_tot[b] : 0;
+        int tot = 0;
+        const int x = block_excl_scan<1024>(v, wsum, tot);
+        if (b < T) tile_tot[b] = carry + x;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) row_ptr[N] = carry;
+}
+
+template <int L>
+__global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int N, int K,
+                                              const int *__restrict__ tile_off, int *__restrict__ row_ptr,
+                                              int *__restrict__ col, float *__restrict__ val, int64_t cap) {
+    __shared__ int cnt[kZT];
+    __shared__ int wsum[kZB / 64];
+    const int lane = lane_id(), sub = threadIdx.x % L, grp = threadIdx.x / L;
+    constexpr int G = kZB / L;
+    const int64_t base = (int64_t)blockIdx.x * kZT;
+    for (int r = grp; r < kZT; r += G) {
+        float z0, z1;
+        uint64_t m0, m1;
+        row_nonzeros<L>(Z, base + r, N, K, sub, lane, z0, z1, m0, m1);
+        if (sub == 0) cnt[r] = __popcll(m0) + __popcll(m1);
+    }
+    __syncthreads();
+    // exclusive scan of the tile's kZT row counts: four consecutive rows per thread
+    constexpr int PER = kZT / kZB;
+    int c[PER], s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        c[q] = cnt[threadIdx.x * PER + q];
+        s += c[q];
+    }
+    int tot = 0;
+    int x = block_excl_scan<kZB>(s, wsum, tot);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        cnt[threadIdx.x * PER + q] = x;
+        x += c[q];
+    }
+    __syncthreads();
+    const int64_t off = tile_off[blockIdx.x];
+    for (int r = grp; r < kZT; r += G) {
+        const int64_t i = base + r;
+        float z0, z1;
+        uint64_t m0, m1;
+        row_nonzeros<L>(Z, i, N, K, sub, lane, z0, z1, m0, m1);
+        if (i >= N) continue;
+        const int64_t start = off + cnt[r];
+        if (sub == 0) row_ptr[i] = (int)start;
+        const uint64_t below = (1ull << sub) - 1;  // sub < L <= 64; sub = 63 gives 2^63 - 1
+        if (z0 != 0.0f) {
+            const int64_t p = start + __popcll(m0 & below);
+            if (p < cap) {
+                col[p] = sub;
+                val[p] = z0;
+            }
+        }
+        if (z1 != 0.0f) {
+            const int64_t p = start + __popcll(m0) + __popcll(m1 & below);
+            if (p < cap) {
+                col[p] = sub + L;
+                val[p] = z1;
+            }
+        }
+    }
+}
+
+template <int L>
+hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *row_ptr, int *col, float *val, int64_t cap,
+                     hipStream_t s) {
+    prof_begin(kKZsCount, s);
+    hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, tile);
+    prof_end(kKZsCount, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zs_scan, dim3(1), dim3(1024), 0, s, tile, T, row_ptr, N);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKZsWrite, s);
+    hipLaunchKernelGGL(zs_write<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, tile, row_ptr, col, val, cap);
+    prof_end(kKZsWrite, s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int zsparse_tiles(int N) { return (N + kZT - 1) / kZT; }
+
+hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *row_ptr, int *col, float *val, int64_t cap,
+                          hipStream_t s) {
+    const int T = zsparse_tiles(N);
+    const int L = K > 32 ? 64 : K > 16 ? 32 : K > 8 ? 16 : K > 4 ? 8 : K > 2 ? 4 : K > 1 ? 2 : 1;
+    switch (L) {
+        case 64: return launch_zs<64>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 32: return launch_zs<32>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 16: return launch_zs<16>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 8: return launch_zs<8>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 4: return launch_zs<4>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 2: return launch_zs<2>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        default: return launch_zs<1>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+    }
+}
+
+}  // namespace gee

@@ -217,6 +217,51 @@ def gee_embed_csr_workspace_bytes(M: int, N: int, K: int, flags: int, sched=None
     return int(_lib.load().gee_embed_csr_workspace_bytes(M, N, K, flags, _sched_ptr(sched)))
 
 
+def gee_embed_sparse_workspace_bytes(E: int, N: int, K: int, flags: int, weighted: bool, sched=None) -> int:
+    return int(_lib.load().gee_embed_sparse_workspace_bytes(E, N, K, flags, int(weighted), _sched_ptr(sched)))
+
+
+def gee_embed_sparse(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], labels: torch.Tensor,
+                     K: int, flags: int, capacity: Optional[int] = None, row_ptr: Optional[torch.Tensor] = None,
+                     col: Optional[torch.Tensor] = None, val: Optional[torch.Tensor] = None, sched=None,
+                     workspace: Optional[torch.Tensor] = None, stream=None):
+    """Z in sparse storage: (row_ptr int32[N + 1], col int32[capacity], val float32[capacity]).
+    The number of stored entries is row_ptr[N]; capacity defaults to N * K (always enough)."""
+    labels = _dev(labels, torch.int32, "labels")
+    dev = labels.device
+    src = _dev(src, torch.int32, "src", dev)
+    dst = _dev(dst, torch.int32, "dst", dev)
+    w = _dev(w, torch.float32, "w", dev)
+    E = src.numel()
+    N = labels.numel()
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    if capacity is None:
+        capacity = N * K if col is None else col.numel()
+    if row_ptr is None:
+        row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    if col is None and capacity > 0:
+        col = torch.empty(capacity, dtype=torch.int32, device=dev)
+    if val is None and capacity > 0:
+        val = torch.empty(capacity, dtype=torch.float32, device=dev)
+    _dev(row_ptr, torch.int32, "row_ptr", dev)
+    _dev(col, torch.int32, "col", dev)
+    _dev(val, torch.float32, "val", dev)
+    if row_ptr.numel() != N + 1 or (capacity > 0 and (col.numel() < capacity or val.numel() < capacity)):
+        raise ValueError("row_ptr must have N + 1 entries and col/val at least capacity")
+    lib = _lib.load()
+    sp = _sched_ptr(sched)
+    nbytes = lib.gee_embed_sparse_workspace_bytes(E, N, K, flags, int(w is not None), sp)
+    if nbytes == 0:
+        raise GeeError(GEE_ERR_ARG if E >= 0 else GEE_ERR_TOO_LARGE, "gee_embed_sparse_workspace_bytes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    _check(lib.gee_embed_sparse_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(row_ptr),
+                                   _ptr(col), _ptr(val), capacity, sp, _ptr(workspace), workspace.numel(),
+                                   _stream(stream)), "gee_embed_sparse")
+    return row_ptr, col, val
+
+
 def gee_embed_atomic_workspace_bytes(N: int, K: int, flags: int) -> int:
     return int(_lib.load().gee_embed_atomic_workspace_bytes(N, K, flags))
 

@@ -54,6 +54,25 @@ def test_atomic_class_counts_range(K):
         assert_close(embed_atomic(gg), or_embed_graph(gg), f"K={K} opts={opts}")
 
 
+@pytest.mark.parametrize("N,K", [(96, 128), (1500, 5), (4096, 3), (4097, 3), (12288, 1), (12289, 1)])
+def test_atomic_small_graphs(N, K):
+    """Small graphs with many edge rows per node (contended degree and Z atomics)."""
+    base = random_small_graph(N + K, N=N, E=8 * N, K=K, weighted=True, unknown_frac=0.1)
+    for d, l, c in FLAG_COMBOS:
+        g = base.with_options(d, l, c)
+        _label(f"atomic small N={N} K={K} opts={(d, l, c)}")
+        assert_close(embed_atomic(g), or_embed_graph(g), f"N={N} K={K} opts={(d, l, c)}")
+
+
+def test_atomic_small_graph_dense():
+    """800 nodes, 400k edge rows: every degree and Z word takes hundreds of atomics."""
+    g = random_small_graph(11, N=800, E=400_000, K=4, weighted=True, unknown_frac=0.05)
+    for opts in ((False, False, False), (True, True, True)):
+        gg = g.with_options(*opts)
+        _label(f"atomic small many parts opts={opts}")
+        assert_close(embed_atomic(gg), or_embed_graph(gg), f"opts={opts}")
+
+
 def test_atomic_edge_cases():
     _label("atomic edge cases")
     e0 = np.zeros(0, np.int32)
