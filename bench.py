@@ -199,6 +199,28 @@ def original_leg(torch, np, gee, lib, dev, g, tens, Z_sparse, steps, ev):
     return out
 
 
+def copy_ceiling(torch, dev, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of `nbytes`, the
+    practical HBM ceiling on this GPU beside the spec peak; None if it cannot be measured."""
+    try:
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        del a, b
+        torch.cuda.empty_cache()
+        return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    except Exception:  # noqa: BLE001 - a missing ceiling must not cost the benchmark line
+        return None
+
+
 def _progress(msg):
     """One line on stderr when a phase of the run has finished (the JSON line stays alone
     on stdout)."""
@@ -657,6 +679,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes_per_launch"] if tr else None,
                 "kernel": dominant, "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(dom_avg_ms, 5)}
+    roofline["copy_ceiling_GBps"] = copy_ceiling(torch, dev)
     if tr:
         roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
 
