@@ -795,7 +795,8 @@ size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_
     const size_t eb = gee_embed_workspace_bytes(E, N, K, flags, weighted, sched);
     if (eb == 0) return 0;
     auto up = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
-    return up(eb) + up((size_t)N * K * sizeof(float)) + up((size_t)zsparse_tiles(N) * sizeof(int));
+    return up(eb) + up((size_t)N * K * sizeof(float)) + up((size_t)zsparse_tiles(N) * sizeof(int)) +
+           up((size_t)N * sizeof(int));
 }
 
 int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
@@ -819,9 +820,10 @@ int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt
     char *base = static_cast<char *>(workspace);
     float *Zd = reinterpret_cast<float *>(base + eb);
     int *tile = reinterpret_cast<int *>(base + eb + up((size_t)N * K * sizeof(float)));
+    int *rcnt = tile + up((size_t)zsparse_tiles(N) * sizeof(int)) / sizeof(int);
     rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Zd, sched, workspace, eb, stream);
     if (rc) return rc;
-    return hip_status(launch_zsparse(Zd, N, K, tile, row_ptr, col, val, capacity, as_stream(stream)));
+    return hip_status(launch_zsparse(Zd, N, K, tile, rcnt, row_ptr, col, val, capacity, as_stream(stream)));
 }
 
 int gee_embed_sparse(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,

@@ -446,10 +446,10 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
 size_t edge_workspace_bytes(int N, int K, unsigned flags);
 hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int64_t E, int N, const int *labels,
                              int K, unsigned flags, float *Z, void *ws, unsigned *status, hipStream_t s);
-// Sparse storage of a dense Z (gee_zsparse.hip): tiles of rows (one int of scratch each),
-// then row_ptr[N + 1] and at most `cap` (class, value) pairs.
+// Sparse storage of a dense Z (gee_zsparse.hip): scratch of one int per tile of rows and
+// one per row, then row_ptr[N + 1] and at most `cap` (class, value) pairs.
 int zsparse_tiles(int N);
-hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *row_ptr, int *col, float *val, int64_t cap,
-                          hipStream_t s);
+hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
+                          int64_t cap, hipStream_t s);
 
 }  // namespace gee

@@ -5,16 +5,16 @@
 //
 // Rows are taken in tiles of kZT; inside a tile, groups of L lanes (the power of two at or
 // above min(K, 64)) take one row each, a lane the columns sub and sub + L.
-//   zs_count  per tile: number of non-zero entries
+//   zs_count  per tile: each row's number of non-zero entries (kept), and the tile's total
 //   zs_scan   one workgroup: exclusive scan of the tile counts, total into row_ptr[N]
-//   zs_write  per tile: the rows' counts again, their scan in LDS, then row_ptr and the
-//             compacted (class, value) pairs at each lane's rank within its row
+//   zs_write  per tile: the rows' counts scanned in LDS, then row_ptr and the compacted
+//             (class, value) pairs at each lane's rank within its row (one pass over Z)
 #include "gee_internal.h"
 
 namespace gee {
 namespace {
 
-constexpr int kZT = 1024;  // rows per tile
+constexpr int kZT = 256;   // rows per tile
 constexpr int kZB = 256;   // threads per workgroup of the tile kernels
 
 // Bits of `m` that belong to this lane's group of L lanes, shifted down to bit 0.
@@ -44,17 +44,23 @@ __device__ __forceinline__ void row_nonzeros(const float *__restrict__ Z, int64_
 }
 
 template <int L>
-__global__ __launch_bounds__(kZB) void zs_count(const float *__restrict__ Z, int N, int K, int *__restrict__ tile_tot) {
+__global__ __launch_bounds__(kZB) void zs_count(const float *__restrict__ Z, int N, int K, int *__restrict__ row_cnt,
+                                              int *__restrict__ tile_tot) {
     __shared__ int wsum[kZB / 64];
     const int lane = lane_id(), sub = threadIdx.x % L, grp = threadIdx.x / L;
     constexpr int G = kZB / L;
     const int64_t base = (int64_t)blockIdx.x * kZT;
     int n = 0;
+#pragma unroll 4
     for (int r = grp; r < kZT; r += G) {  // the same trip count for every group of a wavefront
         float z0, z1;
         uint64_t m0, m1;
         row_nonzeros<L>(Z, base + r, N, K, sub, lane, z0, z1, m0, m1);
-        if (sub == 0) n += __popcll(m0) + __popcll(m1);
+        const int c = __popcll(m0) + __popcll(m1);
+        if (sub == 0) {
+            n += c;
+            if (base + r < N) row_cnt[base + r] = c;
+        }
     }
     int tot = 0;
     (void)block_excl_scan<kZB>(n, wsum, tot);
@@ -78,21 +84,17 @@ __global__ __launch_bounds__(1024) void zs_scan(int *__restrict__ tile_tot, int 
 
 template <int L>
 __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int N, int K,
-                                              const int *__restrict__ tile_off, int *__restrict__ row_ptr,
-                                              int *__restrict__ col, float *__restrict__ val, int64_t cap) {
+                                              const int *__restrict__ row_cnt, const int *__restrict__ tile_off,
+                                              int *__restrict__ row_ptr, int *__restrict__ col,
+                                              float *__restrict__ val, int64_t cap) {
     __shared__ int cnt[kZT];
     __shared__ int wsum[kZB / 64];
     const int lane = lane_id(), sub = threadIdx.x % L, grp = threadIdx.x / L;
     constexpr int G = kZB / L;
     const int64_t base = (int64_t)blockIdx.x * kZT;
-    for (int r = grp; r < kZT; r += G) {
-        float z0, z1;
-        uint64_t m0, m1;
-        row_nonzeros<L>(Z, base + r, N, K, sub, lane, z0, z1, m0, m1);
-        if (sub == 0) cnt[r] = __popcll(m0) + __popcll(m1);
-    }
+    for (int r = threadIdx.x; r < kZT; r += kZB) cnt[r] = base + r < N ? row_cnt[base + r] : 0;
     __syncthreads();
-    // exclusive scan of the tile's kZT row counts: four consecutive rows per thread
+    // exclusive scan of the tile's kZT row counts: kZT / kZB consecutive rows per thread
     constexpr int PER = kZT / kZB;
     int c[PER], s = 0;
 #pragma unroll
@@ -109,6 +111,7 @@ __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int
     }
     __syncthreads();
     const int64_t off = tile_off[blockIdx.x];
+#pragma unroll 4
     for (int r = grp; r < kZT; r += G) {
         const int64_t i = base + r;
         float z0, z1;
@@ -136,17 +139,17 @@ __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int
 }
 
 template <int L>
-hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *row_ptr, int *col, float *val, int64_t cap,
-                     hipStream_t s) {
+hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
+                     int64_t cap, hipStream_t s) {
     prof_begin(kKZsCount, s);
-    hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, tile);
+    hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile);
     prof_end(kKZsCount, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zs_scan, dim3(1), dim3(1024), 0, s, tile, T, row_ptr, N);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKZsWrite, s);
-    hipLaunchKernelGGL(zs_write<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, tile, row_ptr, col, val, cap);
+    hipLaunchKernelGGL(zs_write<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile, row_ptr, col, val, cap);
     prof_end(kKZsWrite, s);
     return hipGetLastError();
 }
@@ -155,18 +158,18 @@ hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *row_pt
 
 int zsparse_tiles(int N) { return (N + kZT - 1) / kZT; }
 
-hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *row_ptr, int *col, float *val, int64_t cap,
-                          hipStream_t s) {
+hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
+                          int64_t cap, hipStream_t s) {
     const int T = zsparse_tiles(N);
     const int L = K > 32 ? 64 : K > 16 ? 32 : K > 8 ? 16 : K > 4 ? 8 : K > 2 ? 4 : K > 1 ? 2 : 1;
     switch (L) {
-        case 64: return launch_zs<64>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        case 32: return launch_zs<32>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        case 16: return launch_zs<16>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        case 8: return launch_zs<8>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        case 4: return launch_zs<4>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        case 2: return launch_zs<2>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
-        default: return launch_zs<1>(Z, N, K, T, tile, row_ptr, col, val, cap, s);
+        case 64: return launch_zs<64>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 32: return launch_zs<32>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 16: return launch_zs<16>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 8: return launch_zs<8>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 4: return launch_zs<4>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 2: return launch_zs<2>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        default: return launch_zs<1>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
     }
 }
 

@@ -48,7 +48,7 @@ def check_sparse(g, capacity=None):
 
 @pytest.mark.parametrize("K", [1, 2, 3, 5, 9, 17, 33, 50, 64, 65, 128])
 def test_sparse_class_counts_range(K):
-    # 5,003 rows: five 1024-row tiles and a ragged last one
+    # 5,003 rows: nineteen 256-row tiles and a ragged last one
     g = random_small_graph(K, N=5003, E=20_000, K=K, weighted=True, unknown_frac=0.1)
     for opts in ((False, False, False), (True, True, True)):
         _label(f"sparse Z K={K} opts={opts}")
