@@ -13,8 +13,8 @@ calls) and `serving` the served form (Poisson requests, budget admission and con
 batching against the plain per-request loop, p50/p99 latency).
 `original` adds the original, edge-list form of GEE (gee_embed_atomic: one pass of float
 atomics over the edge list, no CSR) on the same workload and, as in the paper's GEE
-against sparse GEE comparison, both forms on the 2,000-node SBM graph with the options
-off and all on.
+against sparse GEE comparison, both forms on the 2,000- and 10,000-node SBM graphs with the
+options off and all on.
 `sparse` adds Z in sparse storage (gee_embed_sparse) on the same workload.
 `roofline` is for the kernel with the largest share of the step, timed live with HIP
 events recorded around each of its launches on the launch stream (library hook), and
@@ -139,7 +139,8 @@ def _time_calls(torch, fn, reps, warmup=3):
 
 def original_leg(torch, np, gee, lib, dev, g, tens, Z_sparse, steps, ev):
     """The original GEE form against the sparse path: the benchmark workload, then the
-    2,000-node SBM graph with options off and all on (launch-bound sizes)."""
+    2,000-node SBM graph (launch-bound sizes) and the 10,000-node SBM graph, each with the
+    options off and all on."""
     src, dst, w, lab = tens
     flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
     E, N, K = g.E, g.N, g.K
@@ -175,9 +176,7 @@ def original_leg(torch, np, gee, lib, dev, g, tens, Z_sparse, steps, ev):
            "max_rel_diff_to_sparse_path": rel, "same_zero_entries_as_sparse_path": bool(torch.equal(Z != 0, nz)),
            "kernels": kernels}
     del Z, ws
-    small = []
-    for opt in ("off", "all"):
-        gs = make_workload(f"sbm_small_{opt}")
+    def compare(gs, opt, reps):
         t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
         s2, d2, w2, l2 = t(gs.src, torch.int32), t(gs.dst, torch.int32), t(gs.w, torch.float32), t(gs.labels, torch.int32)
         f2 = gee.flags_of(gs.diag, gs.lap, gs.cor, gs.sym)
@@ -188,14 +187,18 @@ def original_leg(torch, np, gee, lib, dev, g, tens, Z_sparse, steps, ev):
         wsa = torch.empty(max(1, gee.gee_embed_atomic_workspace_bytes(gs.N, gs.K, f2)), dtype=torch.uint8,
                           device=dev)
         sp_ms = _time_calls(torch, lambda: gee.gee_embed(s2, d2, w2, l2, gs.K, f2, Z=Zs, workspace=wss,
-                                                          stream=stream), 200)
+                                                          stream=stream), reps)
         at_ms = _time_calls(torch, lambda: gee.gee_embed_atomic(s2, d2, w2, l2, gs.K, f2, Z=Za, workspace=wsa,
-                                                                 stream=stream), 200)
+                                                                 stream=stream), reps)
         nz2 = Zs != 0
-        small.append({"workload": gs.name, "E": gs.E, "options": opt, "sparse_ms_per_call": round(sp_ms, 5),
-                      "original_ms_per_call": round(at_ms, 5),
-                      "max_rel_diff": float(((Za - Zs).abs()[nz2] / Zs.abs()[nz2]).max().item())})
-    out["sbm_n2000"] = small
+        return {"workload": gs.name, "E": gs.E, "options": opt, "sparse_ms_per_call": round(sp_ms, 5),
+                "original_ms_per_call": round(at_ms, 5),
+                "max_rel_diff": float(((Za - Zs).abs()[nz2] / Zs.abs()[nz2]).max().item())}
+
+    out["sbm_n2000"] = [compare(make_workload(f"sbm_small_{opt}"), opt, 200) for opt in ("off", "all")]
+    gd = make_workload("sbm_dense")  # all options; the paper's 10,000-node SBM graph
+    out["sbm_n10000"] = [compare(gd.with_options(False, False, False, name=gd.name + "_off"), "off", 20),
+                         compare(gd, "all", 20)]
     return out
 
 
