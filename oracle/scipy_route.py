@@ -1,0 +1,42 @@
+"""The paper's own design on the CPU: sparse GEE as scipy.sparse CSR matrices and sparse
+products (Section 3; Table 1's formulas with A, D, I and W all sparse).
+
+TEST INFRASTRUCTURE ONLY. It is a second CPU route, written independently of the C edge
+loop in gee_oracle.c (library sparse products instead of a loop over the entries): the
+tests pin the oracle against it, and the benchmark's CPU-baseline leg times it as the
+paper's design on the host. The product path never imports it.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def scipy_route(src, dst, w, N, labels, K, diag, lap, cor, sym):
+    """The paper's own library design: CSR matrices and sparse products (Section 3)."""
+    E = len(src)
+    wv = np.ones(E) if w is None else np.asarray(w, dtype=np.float64)
+    A = sp.coo_matrix((wv, (np.asarray(src), np.asarray(dst))), shape=(N, N)).tocsr()
+    A.sum_duplicates()
+    if sym:
+        A = (A + A.T - sp.diags(A.diagonal())).tocsr()
+    if diag:
+        A = (A + sp.identity(N, format="csr")).tocsr()
+    if lap:
+        deg = np.asarray(A.sum(axis=1)).ravel()
+        dm = np.zeros(N)
+        pos = deg > 0
+        dm[pos] = 1.0 / np.sqrt(deg[pos])
+        Dm = sp.diags(dm)
+        A = (Dm @ A @ Dm).tocsr()
+    lab = np.asarray(labels)
+    nk = np.bincount(lab[lab >= 0], minlength=K).astype(np.float64)
+    rows = np.flatnonzero(lab >= 0)
+    W = sp.csr_matrix((1.0 / nk[lab[rows]], (rows, lab[rows])), shape=(N, K))
+    Z = (A @ W).toarray()
+    if cor:
+        nr = np.sqrt((Z * Z).sum(axis=1))
+        pos = nr > 0
+        Z[pos] /= nr[pos, None]
+    return Z

@@ -16,10 +16,10 @@ import json
 import os
 
 import numpy as np
-import scipy.sparse as sp
 
 from gee_workloads import random_small_graph
 from oracle import oracle as orc
+from oracle.scipy_route import scipy_route
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -51,35 +51,6 @@ def dense_brute_force(src, dst, w, N, labels, K, diag, lap, cor, sym):
     if cor:
         nr = np.linalg.norm(Z, axis=1, keepdims=True)
         Z = np.where(nr > 0, Z / np.where(nr > 0, nr, 1.0), 0.0)
-    return Z
-
-
-def scipy_route(src, dst, w, N, labels, K, diag, lap, cor, sym):
-    """The paper's own library design: CSR matrices and sparse products (Section 3)."""
-    E = len(src)
-    wv = np.ones(E) if w is None else np.asarray(w, dtype=np.float64)
-    A = sp.coo_matrix((wv, (np.asarray(src), np.asarray(dst))), shape=(N, N)).tocsr()
-    A.sum_duplicates()
-    if sym:
-        A = (A + A.T - sp.diags(A.diagonal())).tocsr()
-    if diag:
-        A = (A + sp.identity(N, format="csr")).tocsr()
-    if lap:
-        deg = np.asarray(A.sum(axis=1)).ravel()
-        dm = np.zeros(N)
-        pos = deg > 0
-        dm[pos] = 1.0 / np.sqrt(deg[pos])
-        Dm = sp.diags(dm)
-        A = (Dm @ A @ Dm).tocsr()
-    lab = np.asarray(labels)
-    nk = np.bincount(lab[lab >= 0], minlength=K).astype(np.float64)
-    rows = np.flatnonzero(lab >= 0)
-    W = sp.csr_matrix((1.0 / nk[lab[rows]], (rows, lab[rows])), shape=(N, K))
-    Z = (A @ W).toarray()
-    if cor:
-        nr = np.sqrt((Z * Z).sum(axis=1))
-        pos = nr > 0
-        Z[pos] /= nr[pos, None]
     return Z
 
 
