@@ -14,7 +14,7 @@ from gee_workloads import powerlaw_10m, random_small_graph, sbm_small
 from gee_workloads.generators import Graph
 from oracle import embed_graph as or_embed_graph
 
-from gpu_util import assert_close, flags, graph_tensors, max_rel_error, to_dev
+from gpu_util import assert_close, flags, graph_tensors, max_rel_error
 
 pytestmark = pytest.mark.gpu
 
