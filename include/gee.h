@@ -27,14 +27,17 @@
  *     on the host before anything is enqueued. A data error found on the device
  *     (a label outside [-1, K), a node index outside [0, N), a non-finite weight, a
  *     malformed CSR) never makes a kernel read or write out of bounds: the offending
- *     item is skipped, Z is then unspecified, and a sticky per-device bit is raised
- *     that gee_get_data_errors() reads and clears.
+ *     item is skipped, Z is then unspecified, and a sticky bit is raised in the data-error
+ *     word of the call's stream, which gee_get_data_errors(stream) reads and clears.
+ *     Each stream of a device has a word of its own (up to 1023 streams per device; any
+ *     further streams share one more word), so an error is reported on the stream whose
+ *     call found it and on no other. A call recorded into a graph by stream capture
+ *     reports to the word of the stream it was captured on.
  *   - Results are deterministic: the same inputs give bitwise identical Z, CSR and
  *     class counts on every call. No floating-point global atomics are used. The one
  *     exception is gee_embed_atomic (the original, edge-list form of the method), whose Z
  *     may differ from call to call in the last bits.
- *   - Calls on different streams may run concurrently. The data-error word is per
- *     device, so concurrent calls share it.
+ *   - Calls on different streams may run concurrently.
  */
 #ifndef GEE_H
 #define GEE_H
@@ -54,6 +57,10 @@ extern "C" {
 #define GEE_CORRELATION (1u << 2) /* each row of Z divided by its 2-norm (zero rows stay 0) */
 #define GEE_SYMMETRIZE (1u << 3)  /* each input row (s, d, w) is an undirected edge:
                                      A[s,d] and A[d,s] (a self-loop once) */
+#define GEE_NO_VALIDATE (1u << 8) /* skip the checks that only report (non-finite weights)
+                                     and raise no data-error bits; items that would address
+                                     memory out of bounds (indices, labels) are still skipped,
+                                     silently, and Z is then unspecified */
 
 /* Status codes. */
 typedef enum {
@@ -108,12 +115,14 @@ const char *gee_status_string(int status);
    the calling thread; "" if there was none. The string is static (owned by HIP). */
 const char *gee_last_hip_error(void);
 
-/* Per-device set-up (the data-error word). Called lazily by every entry point; call it
-   once up front on each device when later calls run under stream capture. */
+/* Per-device set-up: finds the device address of the library's data-error words on the
+   current device. Allocates nothing. Called lazily by every entry
+   point; call it once up front on each device when later calls run under stream capture. */
 int gee_init(void);
 
-/* Reads and clears the current device's sticky data-error bits (GEE_DATA_*). Waits for
-   `stream` to finish first. */
+/* Takes (reads and clears, atomically and in stream order) the sticky data-error bits
+   (GEE_DATA_*) of `stream` on the current device and waits for `stream` to reach that point.
+   Bits raised by calls on other streams are not seen and not cleared. */
 int gee_get_data_errors(void *stream, uint32_t *bits);
 
 /* Profiling hook (for benchmarks and tests). From this call on, every launch of the named
@@ -294,7 +303,8 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
  * on `stream` (one graph launch) and recomputes every Z from the current contents of the
  * input arrays named at creation. The arrays must stay allocated while the plan exists;
  * launches of one plan must not overlap (they share the workspace). Create and destroy
- * on the device the arrays live on. */
+ * on the device the arrays live on. Data errors found by a launch are reported on the
+ * launch's stream (gee_get_data_errors). */
 typedef struct gee_batch_plan gee_batch_plan;
 int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **plan);
 int gee_batch_plan_launch(gee_batch_plan *plan, void *stream);

@@ -14,6 +14,7 @@ from .gee import (  # noqa: F401
     GEE_DATA_WEIGHT,
     GEE_DIAG,
     GEE_LAPLACIAN,
+    GEE_NO_VALIDATE,
     GEE_SYMMETRIZE,
     GeeError,
     flags_of,

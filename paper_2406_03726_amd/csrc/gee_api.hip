@@ -15,7 +15,7 @@ using namespace gee;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr unsigned kKnownFlags = GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE;
+constexpr unsigned kKnownFlags = GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE | GEE_NO_VALIDATE;
 constexpr int64_t kMaxEntries = (int64_t)INT32_MAX - 65536;
 constexpr int64_t kMaxBatchNodes = (int64_t)1 << 28;
 constexpr int kMaxBatchGraphs = 1 << 20;
@@ -36,31 +36,81 @@ int hip_status(hipError_t e) {
     return GEE_ERR_HIP;
 }
 
-// ------------------------------------------------------------------------- data-error word
+// ------------------------------------------------------------------------- data-error words
 
+// One data-error word per (device, stream): calls on one stream raise bits in that stream's
+// word, so a bad request on one stream is never reported on another. The words live in a
+// file-scope device array (no allocation, so every entry point can run under stream capture
+// once gee_init has run on the device); a stream gets a slot the first time a call uses it,
+// by a hash of its handle with linear probing. Past kStatusSlots - 1 distinct streams on a
+// device the rest share the last slot. A slot is 64 bytes: the word and, beside it, the
+// value gee_get_data_errors took from it.
+constexpr int kStatusSlots = 1024;
+constexpr int kStatusStride = 16;  // unsigned per slot
+static __device__ __align__(256) unsigned status_words[kStatusSlots * kStatusStride];
+
+struct DevState {
+    bool ready = false;
+    unsigned *words = nullptr;   // device address of status_words on this device
+    const void *key[kStatusSlots];
+    bool used[kStatusSlots];
+};
 std::mutex g_status_mu;
-unsigned *g_status[64] = {nullptr};
+DevState g_dev[64];
 
-int device_status(unsigned **out) {
+// Device address of the data-error words for the current device (once per device; the
+// array's name is a host-side stand-in that kernels must never be given).
+int device_state(DevState **out) {
     int dev = 0;
     hipError_t ge = hipGetDevice(&dev);
     if (ge != hipSuccess) return hip_status(ge);
     if (dev < 0 || dev >= 64) return GEE_ERR_UNSUPPORTED;
-    std::lock_guard<std::mutex> lk(g_status_mu);
-    if (!g_status[dev]) {
-        unsigned *p = nullptr;
-        hipError_t e = hipMalloc(&p, 256);
+    DevState &ds = g_dev[dev];
+    if (!ds.ready) {
+        void *w = nullptr;
+        hipError_t e = hipGetSymbolAddress(&w, HIP_SYMBOL(status_words));
         if (e != hipSuccess) return hip_status(e);
-        e = hipMemset(p, 0, 256);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e != hipSuccess) {
-            (void)hipFree(p);
-            return hip_status(e);
+        ds.words = static_cast<unsigned *>(w);
+        for (int i = 0; i < kStatusSlots; ++i) {
+            ds.key[i] = nullptr;
+            ds.used[i] = false;
         }
-        g_status[dev] = p;
+        ds.ready = true;
     }
-    *out = g_status[dev];
+    *out = &ds;
     return GEE_OK;
+}
+
+// The data-error word of `stream` on the current device.
+int stream_status(hipStream_t stream, unsigned **out) {
+    std::lock_guard<std::mutex> lk(g_status_mu);
+    DevState *ds = nullptr;
+    int rc = device_state(&ds);
+    if (rc) return rc;
+    const void *key = reinterpret_cast<const void *>(stream);
+    const uint64_t h = (uint64_t)reinterpret_cast<uintptr_t>(key) * 0x9E3779B97F4A7C15ull;
+    int slot = kStatusSlots - 1;  // shared once the table is full
+    for (int i = 0; i < kStatusSlots - 1; ++i) {
+        const int j = (int)((h >> 40) + (uint64_t)i) % (kStatusSlots - 1);
+        if (ds->used[j] && ds->key[j] == key) {
+            slot = j;
+            break;
+        }
+        if (!ds->used[j]) {
+            ds->used[j] = true;
+            ds->key[j] = key;
+            slot = j;
+            break;
+        }
+    }
+    *out = ds->words + (size_t)slot * kStatusStride;
+    return GEE_OK;
+}
+
+__global__ void status_take(unsigned *word) { word[1] = atomicExch(word, 0u); }
+__global__ void status_fold(unsigned *from, unsigned *to) {
+    const unsigned v = atomicExch(from, 0u);
+    if (v) atomicOr(to, v);
 }
 
 // ------------------------------------------------------------------------- profiling hook
@@ -545,6 +595,7 @@ void prof_end(int kid, hipStream_t s) {
 // Batch plan: a workspace, the uploaded tables and the captured launch sequence.
 struct gee_batch_plan {
     int device = 0;
+    unsigned *status = nullptr;  // the plan's data-error word (in ws)
     void *ws = nullptr;
     size_t ws_bytes = 0;
     hipGraph_t graph = nullptr;
@@ -594,22 +645,23 @@ int gee_profile_kernel(const char *kernel, void *start_event, void *stop_event) 
 }
 
 int gee_init(void) {
-    unsigned *st = nullptr;
-    return device_status(&st);
+    std::lock_guard<std::mutex> lk(g_status_mu);
+    DevState *ds = nullptr;
+    return device_state(&ds);
 }
 
 int gee_get_data_errors(void *stream, uint32_t *bits) {
     if (!bits) return GEE_ERR_ARG;
     unsigned *st = nullptr;
-    int rc = device_status(&st);
+    int rc = stream_status(as_stream(stream), &st);
     if (rc) return rc;
-    hipError_t e = hipStreamSynchronize(as_stream(stream));
-    if (e != hipSuccess) return hip_status(e);
+    // take the word (atomically, in stream order), then copy what was taken
+    hipStream_t s = launch_stream(stream);
+    hipLaunchKernelGGL(status_take, dim3(1), dim3(1), 0, s, st);
+    hipError_t e = hipGetLastError();
     unsigned h = 0;
-    e = hipMemcpy(&h, st, sizeof(unsigned), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_status(e);
-    e = hipMemset(st, 0, sizeof(unsigned));
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, st + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_status(e);
     *bits = h;
     return GEE_OK;
@@ -645,7 +697,7 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
     if (rc) return rc;
     if (!counts || (N > 0 && !labels)) return GEE_ERR_ARG;
     unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    if ((rc = stream_status(as_stream(stream), &st))) return rc;
     GraphIn x;
     x.N = N;
     x.K = K;
@@ -690,7 +742,7 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
     if (!row_ptr || (E > 0 && (!src || !dst || !col)) || (wgt && E > 0 && !val)) return GEE_ERR_ARG;
     if (N == 0 && E > 0) return GEE_ERR_ARG;
     unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    if ((rc = stream_status(as_stream(stream), &st))) return rc;
     GraphIn x;
     x.src = src;
     x.dst = dst;
@@ -861,7 +913,7 @@ int gee_embed_atomic_ws(const int32_t *src, const int32_t *dst, const float *wgt
     if (!labels || !Z || (E > 0 && (!src || !dst))) return GEE_ERR_ARG;
     if (!workspace || workspace_bytes < edge_workspace_bytes(N, K, flags)) return GEE_ERR_WORKSPACE;
     unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    if ((rc = stream_status(as_stream(stream), &st))) return rc;
     hipStream_t s = launch_stream(stream);
     return hip_status(launch_edge_embed(src, dst, wgt, E, N, labels, K, flags, Z, workspace, st, s));
 }
@@ -905,7 +957,7 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
     for (const Chunk &c : ch) rows += c.p.Ntot;
     if (rows == 0) return GEE_OK;
     unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    if ((rc = stream_status(as_stream(stream), &st))) return rc;
     if (!workspace || workspace_bytes < total) return GEE_ERR_WORKSPACE;
     hipStream_t s = launch_stream(stream);
     hipError_t e = hipSuccess;
@@ -933,22 +985,33 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     int64_t rows = 0;
     for (const Chunk &c : ch) rows += c.p.Ntot;
     if (rows == 0) return GEE_ERR_ARG;
-    unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_status_mu);
+        DevState *ds = nullptr;
+        if ((rc = device_state(&ds))) return rc;
+    }
     gee_batch_plan *pl = new (std::nothrow) gee_batch_plan();
     if (!pl) return GEE_ERR_OOM;
     pl->G = G;
     (void)hipGetDevice(&pl->device);
-    pl->ws_bytes = total;
+    // the plan's own data-error word (first kAlign bytes), then the chunks' workspaces
+    pl->ws_bytes = kAlign + total;
     hipStream_t cs = nullptr;
     hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
+    unsigned *st = static_cast<unsigned *>(pl->ws);
+    pl->status = st;
+    char *wsb = static_cast<char *>(pl->ws) + kAlign;
     // every chunk has its own workspace region, so all tables are written before capture
     std::vector<Batch> bs(ch.size());
     std::vector<Work> wks(ch.size());
     (void)hipGetLastError();  // see launch_stream
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(status_take, dim3(1), dim3(1), 0, nullptr, st);  // word = 0
+        e = hipGetLastError();
+    }
     for (size_t i = 0; i < ch.size() && e == hipSuccess; ++i) {
         if (ch[i].p.Ntot == 0) continue;
-        carve(ch[i].p, kEmbedParts, (char *)pl->ws + ch[i].off, wks[i]);
+        carve(ch[i].p, kEmbedParts, wsb + ch[i].off, wks[i]);
         e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i]);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -974,7 +1037,17 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
 
 int gee_batch_plan_launch(gee_batch_plan *plan, void *stream) {
     if (!plan || !plan->exec) return GEE_ERR_ARG;
-    return hip_status(hipGraphLaunch(plan->exec, as_stream(stream)));
+    unsigned *st = nullptr;
+    int rc = stream_status(as_stream(stream), &st);
+    if (rc) return rc;
+    hipStream_t s = launch_stream(stream);
+    hipError_t e = hipGraphLaunch(plan->exec, s);
+    // the plan's data errors move to the launch stream's word
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(status_fold, dim3(1), dim3(1), 0, s, plan->status, st);
+        e = hipGetLastError();
+    }
+    return hip_status(e);
 }
 
 int gee_batch_plan_destroy(gee_batch_plan *plan) {
@@ -1017,7 +1090,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     if (N == 0) return M > 0 ? GEE_ERR_ARG : GEE_OK;
     if (!row_ptr || !labels || !Z || (M > 0 && !col)) return GEE_ERR_ARG;
     unsigned *st = nullptr;
-    if ((rc = device_status(&st))) return rc;
+    if ((rc = stream_status(as_stream(stream), &st))) return rc;
     GraphIn x;
     x.E = M;
     x.N = N;

@@ -141,11 +141,11 @@ __device__ __forceinline__ bool load_virtual(const Batch &b, int64_t v, int64_t 
         val = 1.0f;
         if (gd.w) {
             val = gd.w[e];
-            if (side == 0 && !isfinite(val)) badw = true;
+            if (side == 0 && validates(gd) && !isfinite(val)) badw = true;
         }
     }
     const bool inr = (unsigned)s < (unsigned)gd.N && (unsigned)d < (unsigned)gd.N;
-    if (!inr) badi = true;
+    if (!inr && validates(gd)) badi = true;
     return inr && (side == 0 || s != d);
 }
 
@@ -172,6 +172,7 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
         // one graph: clamped unconditional loads, then the checks
         const GDesc gd = load_desc(b, g0);
         const bool sym = gd.flags & kSym;
+        const bool chk = validates(gd);
         int sv[kRoundsW], dv[kRoundsW];
         float wv[kRoundsW];
 #pragma unroll
@@ -188,8 +189,8 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
             const int side = sym ? (int)((v - gd.voff) & 1) : 0;
             const bool inb = v <= vhi;
             const bool inr = (unsigned)sv[r] < (unsigned)gd.N && (unsigned)dv[r] < (unsigned)gd.N;
-            if (inb && !inr) badi = true;
-            if (VAL && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
+            if (chk && inb && !inr) badi = true;
+            if (VAL && chk && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
             q.key[r] = (side ? dv[r] : sv[r]) + gd.node_off;
             q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
             if (VAL) q.val[r] = wv[r];

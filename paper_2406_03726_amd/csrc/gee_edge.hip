@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kEB) void edge_scatter(const int *__restrict__ src,
             if ((unsigned)s[u] >= (unsigned)N || (unsigned)d[u] >= (unsigned)N) {
                 bad_i = true;
                 s[u] = -1;
-            } else if (!finite_f(x[u])) {
+            } else if (status && !finite_f(x[u])) {
                 bad_w = true;
                 s[u] = -1;
             }
@@ -210,6 +210,7 @@ hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int
     float *deg = (flags & kLap) ? reinterpret_cast<float *>(p) : nullptr;
     const bool sym = flags & kSym, diag = flags & kDiag, cor = flags & kCor;
     const int64_t nz = (int64_t)N * K;
+    if (flags & kNoValidate) status = nullptr;  // no checks that only report, no bits raised
 
     prof_begin(kKEdgeInit, s);
     hipLaunchKernelGGL(edge_init, dim3((unsigned)grid_for(nz / 4 + 1, 4, 16384)), dim3(kEB), 0, s, Z, nz, deg, N,

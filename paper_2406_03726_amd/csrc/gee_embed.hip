@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void node_rows(Batch b, int Ntot, const int *_
         const int lo = rp[r], hi = rp[r + 1];
         const int e_lo = m.ent_off, e_hi = m.ent_off + m.M;
         if (lo > hi || lo < e_lo || hi > e_hi || (rl == 0 && lo != e_lo) || (rl == d.N - 1 && hi != e_hi))
-            bad = true;
+            bad = true;  // (the row is skipped either way; only the report depends on validation)
         const bool lap = d.flags & kLap, diag = d.flags & kDiag;
         const bool skip = d.weighted && lap && hi > lo;
         int y = d.labels[rl];
@@ -150,7 +150,8 @@ __global__ __launch_bounds__(256) void node_rows(Batch b, int Ntot, const int *_
             for (int64_t ww = wa; ww <= wb; ++ww) wrow[d.wave_off + ww] = r;
         }
     }
-    if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrCsr);
+    const bool report = bad && validates(load_desc(b, find_graph(b.node_offs, b.G, min(r, Ntot - 1))));
+    if (__syncthreads_or(report) && threadIdx.x == 0) raise_error(status, kErrCsr);
 }
 
 // The row holding entry q among the graph's rows rp[0..N] (last r with rp[r] <= q).
@@ -778,7 +779,7 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
         P0 = P1;
         R1 = R2;
     }
-    if (ballot(bad) && lane == 0) raise_error(status, kErrCsr);
+    if (ballot(bad) && lane == 0 && validates(gd)) raise_error(status, kErrCsr);
 
     // The last row continues past this wavefront: leave its raw partial sums.
     if (npend > 0) drain();

@@ -15,6 +15,8 @@ namespace gee {
 constexpr unsigned kDiag = 1u, kLap = 2u, kCor = 4u, kSym = 8u;
 // Device data-error bits (same values as the public GEE_DATA_* bits).
 constexpr unsigned kErrLabel = 1u, kErrIndex = 2u, kErrWeight = 4u, kErrCsr = 8u;
+// GEE_NO_VALIDATE: the graph's checks raise nothing (memory-safety guards stay).
+constexpr unsigned kNoValidate = 1u << 8;
 
 constexpr int kWave = 64;
 constexpr int kMaxBuckets = 65536;     // CSR buckets: 256 high digits x 256 low digits
@@ -122,7 +124,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total) {
 }
 
 __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
-    atomicOr(status, bit);
+    if (status) atomicOr(status, bit);
 }
 
 // ----------------------------------------------------------------------------- shared by the embed paths
@@ -248,6 +250,8 @@ struct Batch {
     GMeta *gm = nullptr;                // [G]
 };
 
+__device__ __forceinline__ bool validates(const GDesc &d) { return !(d.flags & kNoValidate); }
+
 // Last g with offs[g] <= x (offs non-decreasing, offs[0] <= x).
 template <typename T>
 __device__ __forceinline__ int find_graph(const T *__restrict__ offs, int G, T x) {
@@ -362,7 +366,7 @@ __device__ __forceinline__ void class_count_slice(const Batch &b, int j, int *__
         const int y = d.labels[i];
         if (y >= 0 && y < K)
             atomicAdd(&hist[y], 1);
-        else if (y != -1)
+        else if (y != -1 && validates(d))
             bad = true;
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrLabel);

@@ -7,6 +7,7 @@ the embedding runs in the library's HIP kernels; there is no CPU path.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from typing import Optional
 
@@ -18,6 +19,7 @@ GEE_DIAG = 1 << 0
 GEE_LAPLACIAN = 1 << 1
 GEE_CORRELATION = 1 << 2
 GEE_SYMMETRIZE = 1 << 3
+GEE_NO_VALIDATE = 1 << 8
 
 GEE_DATA_LABEL = 1 << 0
 GEE_DATA_INDEX = 1 << 1
@@ -76,6 +78,13 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _on(stream):
+    """Allocations made by a call belong to the stream its kernels run on: torch's caching
+    allocator then hands their memory to another stream only after that stream's work on
+    it is done (a workspace freed when the call returns is not reused under the kernels)."""
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
+
+
 def schedule(wave_entries=0, waves_per_block=0, tile_entries=0, bucket_rows_log2=0) -> _lib.GeeSchedule:
     return _lib.GeeSchedule(wave_entries, waves_per_block, tile_entries, bucket_rows_log2)
 
@@ -111,11 +120,12 @@ def gee_default_schedule(E: int, N: int, K: int, flags: int) -> dict:
 def gee_class_counts(labels: torch.Tensor, K: int, counts: Optional[torch.Tensor] = None,
                      stream=None) -> torch.Tensor:
     labels = _dev(labels, torch.int32, "labels")
-    if counts is None:
-        counts = torch.empty(K, dtype=torch.int32, device=labels.device)
-    _dev(counts, torch.int32, "counts", labels.device)
-    _check(_lib.load().gee_class_counts(_ptr(labels), labels.numel(), K, _ptr(counts), _stream(stream)),
-           "gee_class_counts")
+    with _on(stream):
+        if counts is None:
+            counts = torch.empty(K, dtype=torch.int32, device=labels.device)
+        _dev(counts, torch.int32, "counts", labels.device)
+        _check(_lib.load().gee_class_counts(_ptr(labels), labels.numel(), K, _ptr(counts), _stream(stream)),
+               "gee_class_counts")
     return counts
 
 
@@ -136,20 +146,21 @@ def gee_build_csr(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor
         raise ValueError("src, dst and w must have the same length")
     cap = gee_csr_capacity(E, flags)
     dev = src.device
-    if row_ptr is None:
-        row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
-    if col is None:
-        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    if val is None and w is not None:
-        val = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
     lib = _lib.load()
     sp = _sched_ptr(sched)
     nbytes = lib.gee_build_csr_workspace_bytes(E, N, flags, sp)
     if nbytes == 0:
         raise GeeError(GEE_ERR_ARG, "gee_build_csr_workspace_bytes")
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    _check(lib.gee_build_csr_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, flags, _ptr(row_ptr), _ptr(col),
-                                _ptr(val), sp, _ptr(ws), nbytes, _stream(stream)), "gee_build_csr")
+    with _on(stream):
+        if row_ptr is None:
+            row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
+        if col is None:
+            col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if val is None and w is not None:
+            val = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _check(lib.gee_build_csr_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, flags, _ptr(row_ptr), _ptr(col),
+                                    _ptr(val), sp, _ptr(ws), nbytes, _stream(stream)), "gee_build_csr")
     return row_ptr, col, val
 
 
@@ -166,20 +177,21 @@ def gee_embed(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], l
     N = labels.numel()
     if dst.numel() != E or (w is not None and w.numel() != E):
         raise ValueError("src, dst and w must have the same length")
-    if Z is None:
-        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
-    _dev(Z, torch.float32, "Z", dev)
-    if Z.numel() != N * K:
-        raise ValueError("Z must hold N * K floats")
     lib = _lib.load()
     sp = _sched_ptr(sched)
     nbytes = lib.gee_embed_workspace_bytes(E, N, K, flags, int(w is not None), sp)
     if nbytes == 0 and N > 0:
         raise GeeError(GEE_ERR_ARG if E >= 0 else GEE_ERR_TOO_LARGE, "gee_embed_workspace_bytes")
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    _check(lib.gee_embed_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z), sp,
-                            _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed")
+    with _on(stream):
+        if Z is None:
+            Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+        _dev(Z, torch.float32, "Z", dev)
+        if Z.numel() != N * K:
+            raise ValueError("Z must hold N * K floats")
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _check(lib.gee_embed_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z), sp,
+                                _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed")
     return Z
 
 
@@ -199,17 +211,18 @@ def gee_embed_csr(row_ptr: torch.Tensor, col: torch.Tensor, val: Optional[torch.
     N = labels.numel()
     if row_ptr.numel() != N + 1 or col.numel() < M or (val is not None and val.numel() < M):
         raise ValueError("row_ptr must have N + 1 entries and col/val at least M")
-    if Z is None:
-        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
-    _dev(Z, torch.float32, "Z", dev)
     lib = _lib.load()
     sp = _sched_ptr(sched)
     nbytes = lib.gee_embed_csr_workspace_bytes(M, N, K, flags, sp)
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    _check(lib.gee_embed_csr_ws(_ptr(row_ptr), _ptr(col), _ptr(val), M, N, _ptr(labels), K, flags,
-                                _ptr(Z), sp, _ptr(workspace), workspace.numel(), _stream(stream)),
-           "gee_embed_csr")
+    with _on(stream):
+        if Z is None:
+            Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+        _dev(Z, torch.float32, "Z", dev)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _check(lib.gee_embed_csr_ws(_ptr(row_ptr), _ptr(col), _ptr(val), M, N, _ptr(labels), K, flags,
+                                    _ptr(Z), sp, _ptr(workspace), workspace.numel(), _stream(stream)),
+               "gee_embed_csr")
     return Z
 
 
@@ -238,27 +251,28 @@ def gee_embed_sparse(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Ten
         raise ValueError("src, dst and w must have the same length")
     if capacity is None:
         capacity = N * K if col is None else col.numel()
-    if row_ptr is None:
-        row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
-    if col is None and capacity > 0:
-        col = torch.empty(capacity, dtype=torch.int32, device=dev)
-    if val is None and capacity > 0:
-        val = torch.empty(capacity, dtype=torch.float32, device=dev)
-    _dev(row_ptr, torch.int32, "row_ptr", dev)
-    _dev(col, torch.int32, "col", dev)
-    _dev(val, torch.float32, "val", dev)
-    if row_ptr.numel() != N + 1 or (capacity > 0 and (col.numel() < capacity or val.numel() < capacity)):
-        raise ValueError("row_ptr must have N + 1 entries and col/val at least capacity")
     lib = _lib.load()
     sp = _sched_ptr(sched)
     nbytes = lib.gee_embed_sparse_workspace_bytes(E, N, K, flags, int(w is not None), sp)
     if nbytes == 0:
         raise GeeError(GEE_ERR_ARG if E >= 0 else GEE_ERR_TOO_LARGE, "gee_embed_sparse_workspace_bytes")
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    _check(lib.gee_embed_sparse_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(row_ptr),
-                                   _ptr(col), _ptr(val), capacity, sp, _ptr(workspace), workspace.numel(),
-                                   _stream(stream)), "gee_embed_sparse")
+    with _on(stream):
+        if row_ptr is None:
+            row_ptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
+        if col is None and capacity > 0:
+            col = torch.empty(capacity, dtype=torch.int32, device=dev)
+        if val is None and capacity > 0:
+            val = torch.empty(capacity, dtype=torch.float32, device=dev)
+        _dev(row_ptr, torch.int32, "row_ptr", dev)
+        _dev(col, torch.int32, "col", dev)
+        _dev(val, torch.float32, "val", dev)
+        if row_ptr.numel() != N + 1 or (capacity > 0 and (col.numel() < capacity or val.numel() < capacity)):
+            raise ValueError("row_ptr must have N + 1 entries and col/val at least capacity")
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _check(lib.gee_embed_sparse_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags,
+                                       _ptr(row_ptr), _ptr(col), _ptr(val), capacity, sp, _ptr(workspace),
+                                       workspace.numel(), _stream(stream)), "gee_embed_sparse")
     return row_ptr, col, val
 
 
@@ -280,19 +294,20 @@ def gee_embed_atomic(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Ten
     N = labels.numel()
     if dst.numel() != E or (w is not None and w.numel() != E):
         raise ValueError("src, dst and w must have the same length")
-    if Z is None:
-        Z = torch.empty((N, K), dtype=torch.float32, device=dev)
-    _dev(Z, torch.float32, "Z", dev)
-    if Z.numel() != N * K:
-        raise ValueError("Z must hold N * K floats")
     lib = _lib.load()
     nbytes = lib.gee_embed_atomic_workspace_bytes(N, K, flags)
     if nbytes == 0 and N > 0:
         raise GeeError(GEE_ERR_ARG, "gee_embed_atomic_workspace_bytes")
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    _check(lib.gee_embed_atomic_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z),
-                                   _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed_atomic")
+    with _on(stream):
+        if Z is None:
+            Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+        _dev(Z, torch.float32, "Z", dev)
+        if Z.numel() != N * K:
+            raise ValueError("Z must hold N * K floats")
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _check(lib.gee_embed_atomic_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z),
+                                       _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed_atomic")
     return Z
 
 
@@ -331,6 +346,27 @@ def _graph_array(graphs, dev, sizing: bool = False):
     return arr
 
 
+def batch_workspace_bytes_of_sizes(sizes) -> int:
+    """Workspace of gee_embed_batch for graphs given by sizes alone: tuples (E, N, K, flags,
+    weighted[, sched]). Host-only (no device, no tensors): the library's size query reads only
+    sizes, flags, weights-or-not and schedules."""
+    arr = (_lib.GeeGraph * len(sizes))()
+    for i, t in enumerate(sizes):
+        E, N, K, fl, weighted = t[:5]
+        sc = t[5] if len(t) > 5 else None
+        if sc is None:
+            sc = schedule()
+        elif isinstance(sc, dict):
+            sc = schedule(**sc)
+        # a non-NULL weight pointer marks a weighted graph; the size query never reads it
+        arr[i] = _lib.GeeGraph(None, None, 16 if weighted else None, int(E), int(N), None, int(K), int(fl),
+                               None, sc)
+    n = int(_lib.load().gee_embed_batch_workspace_bytes(arr, len(sizes)))
+    if n == 0:
+        raise GeeError(GEE_ERR_ARG, "gee_embed_batch_workspace_bytes")
+    return n
+
+
 def gee_embed_batch_workspace_bytes(graphs) -> int:
     """Workspace of gee_embed_batch for these graphs (their Z may be None here)."""
     dev = graphs[0]["labels"].device
@@ -352,10 +388,11 @@ def gee_embed_batch(graphs, workspace: Optional[torch.Tensor] = None, stream=Non
     nbytes = lib.gee_embed_batch_workspace_bytes(arr, len(graphs))
     if nbytes == 0:
         raise GeeError(GEE_ERR_ARG, "gee_embed_batch_workspace_bytes")
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    _check(lib.gee_embed_batch_ws(arr, len(graphs), _ptr(workspace), workspace.numel(), _stream(stream)),
-           "gee_embed_batch_ws")
+    with _on(stream):
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _check(lib.gee_embed_batch_ws(arr, len(graphs), _ptr(workspace), workspace.numel(), _stream(stream)),
+               "gee_embed_batch_ws")
 
 
 class BatchPlan:

@@ -3,10 +3,11 @@ continuous batching over several HIP streams.
 
 A request is one graph whose inputs are already on the device (edge list, weights,
 labels). The server keeps a FIFO queue. Whenever a stream slot is free it admits the
-longest prefix of the queue whose footprint (the request's own workspace plus its Z)
-fits the free budget, and launches those requests as one batch (gee_embed_batch_ws) on
-that slot's stream. Batches on different streams overlap on the device; a request that
-arrives while others run is admitted as soon as a slot and memory free up. Admission is
+longest prefix of the queue whose batch footprint (the workspace the library needs for
+exactly that batch, plus the batch's Z outputs) fits the free budget, and launches those
+requests as one batch (gee_embed_batch_ws) on that slot's stream. Batches on different
+streams overlap on the device; a request that arrives while others run is admitted as
+soon as a slot and memory free up. Admission is
 strictly FIFO, so a large request at the head waits for memory rather than being passed
 (no starvation); a request larger than the whole budget is rejected.
 
@@ -55,6 +56,12 @@ class Backend:
 
     def footprint(self, req: Request) -> int:
         raise NotImplementedError
+
+    def batch_footprint(self, reqs: List[Request]) -> int:
+        """Bytes a batch of these requests holds while it runs. A batch's workspace can exceed
+        the sum of its members' own (its tables are sized by the batch's largest class count
+        and partition digits), so a backend that knows better says so here."""
+        return sum(r.nbytes for r in reqs)
 
     def launch(self, reqs: List[Request], slot: int) -> Any:
         """Start one batch on slot `slot`; returns a handle."""
@@ -161,7 +168,9 @@ class GeeServer:
                     break
                 if r.cancelled:
                     continue
-                if self.in_use + nbytes + r.nbytes > self.budget:
+                # the batch is charged what it holds with r in it, not the sum of its members
+                need = self.backend.batch_footprint(batch + [r]) if batch else r.nbytes
+                if self.in_use + need > self.budget:
                     break  # FIFO: nothing behind a request that does not fit yet
                 if batch and self.max_batch_edges is not None and edges + r.E > self.max_batch_edges:
                     break  # the next batch starts with this request
@@ -169,7 +178,7 @@ class GeeServer:
                         and self.inflight_edges + edges + r.E > self.max_inflight_edges):
                     break  # FIFO: wait until the device has room for this request
                 batch.append(r)
-                nbytes += r.nbytes
+                nbytes = need
                 edges += r.E
             if not batch:
                 break
@@ -262,8 +271,11 @@ def summarize(reqs: Sequence[Request]) -> Dict[str, float]:
 
 class GpuBackend(Backend):
     """Batches run with gee_embed_batch_ws on `slots` torch streams (default priority).
-    A request's footprint is its own workspace plus its Z; a batch's workspace is carved
-    from one allocation sized for the batch (never more than the sum of its members')."""
+    A batch is charged the library's workspace size for exactly that batch plus its Z
+    outputs; the bytes each batch actually allocates are tracked too (peak_actual).
+    A batch's data errors are read from its stream's data-error word when it finishes; when
+    a batch of several requests reports one, each request is embedded again alone to find
+    the ones that carry it, and only those get an error."""
 
     def __init__(self, slots: int = 4, table=None):
         import torch
@@ -273,8 +285,16 @@ class GpuBackend(Backend):
         self._torch = torch
         self._gee = gee
         self.slots = slots
-        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self._streams = None  # made at the first launch (sizing needs no device)
         self.table = table
+        self.in_use_actual = 0
+        self.peak_actual = 0
+
+    @property
+    def streams(self):
+        if self._streams is None:
+            self._streams = [self._torch.cuda.Stream() for _ in range(self.slots)]
+        return self._streams
 
     def sched_of(self, g: Dict[str, Any]) -> Optional[Dict[str, int]]:
         if g.get("sched") is not None:
@@ -289,18 +309,26 @@ class GpuBackend(Backend):
         return dict(src=g["src"], dst=g["dst"], w=g.get("w"), labels=g["labels"], K=int(g["K"]),
                     flags=int(g["flags"]), Z=Z, sched=self.sched_of(g))
 
+    def _sizes(self, r: Request):
+        g = r.graph
+        return (r.E, r.N, int(g["K"]), int(g["flags"]), g.get("w") is not None, self.sched_of(g))
+
     def footprint(self, r: Request) -> int:
         g = r.graph
         r.E = int(g["src"].numel())
         r.N = int(g["labels"].numel())
-        K = int(g["K"])
-        ws = self._gee.gee_embed_batch_workspace_bytes([self._item(r, Z=None)])
-        return int(ws) + 4 * r.N * K
+        return self.batch_footprint([r])
+
+    def batch_footprint(self, reqs: List[Request]) -> int:
+        ws = self._gee.batch_workspace_bytes_of_sizes([self._sizes(r) for r in reqs])
+        return int(ws) + sum(4 * r.N * int(r.graph["K"]) for r in reqs)
 
     def launch(self, reqs: List[Request], slot: int):
         torch = self._torch
         s = self.streams[slot]
         dev = reqs[0].graph["labels"].device
+        # the requests' inputs were made on the submitting stream
+        s.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(s):
             items = []
             for r in reqs:
@@ -311,12 +339,30 @@ class GpuBackend(Backend):
             self._gee.gee_embed_batch(items, workspace=ws, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, items, ws)
+        held = ws.numel() + sum(it["Z"].numel() * 4 for it in items)
+        self.in_use_actual += held
+        self.peak_actual = max(self.peak_actual, self.in_use_actual)
+        return (ev, items, ws, s, held)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle, reqs: List[Request]) -> None:
-        _, items, _ = handle
+        _, items, _, s, held = handle
+        self.in_use_actual -= held
+        bits = self._gee.gee_get_data_errors(s)
         for r, it in zip(reqs, items):
             r.result = it["Z"]
+        if not bits:
+            return
+        if len(reqs) == 1:
+            reqs[0].error = f"data error (bits {bits:#x})"
+            reqs[0].result = None
+            return
+        for r, it in zip(reqs, items):
+            with self._torch.cuda.stream(s):
+                self._gee.gee_embed_batch([it], stream=s)
+            b = self._gee.gee_get_data_errors(s)
+            if b:
+                r.error = f"data error (bits {b:#x})"
+                r.result = None

@@ -40,7 +40,10 @@ def test_served_equals_alone(table):
     srv.run_trace(reqs)
     torch.cuda.synchronize()
     assert srv.peak_in_use <= budget
-    assert gee.gee_get_data_errors() == 0
+    assert be.peak_actual <= budget  # bytes the batches really allocated
+    assert any(len(b) > 1 for b in srv.launch_log), "no batch of several requests"
+    assert srv.peak_flights > 1, "batches never overlapped"
+    assert all(r.error is None for r in reqs)
     s = summarize(reqs)
     assert s["completed"] == len(reqs)
     for i, (r, g, d) in enumerate(zip(reqs, gs, dev)):

@@ -214,3 +214,70 @@ def test_inflight_edge_cap():
     flat = [rid for b in be.launched for rid in b]
     assert flat == sorted(flat) and len(flat) == 30
     assert srv.inflight_edges == 0
+
+
+class _SizingBackend:
+    """The GPU backend's own footprints (library size queries, host only) with launches
+    simulated on the virtual clock."""
+
+    def __new__(cls, clock, slots=3):
+        from paper_2406_03726_amd.serve import GpuBackend
+
+        class Sized(GpuBackend):
+            def __init__(self):
+                super().__init__(slots=slots)
+                self.clock = clock
+                self.charged = []
+
+            def launch(self, reqs, slot):
+                self.charged.append((self.batch_footprint(reqs), [self._sizes(r) for r in reqs],
+                                     sum(4 * r.N * int(r.graph["K"]) for r in reqs)))
+                return {"end": self.clock() + 1e-4 * len(reqs)}
+
+            def poll(self, h):
+                return self.clock() >= h["end"]
+
+            def finish(self, h, reqs):
+                pass
+
+        return Sized()
+
+
+def _sized_reqs(n, seed):
+    """Requests with mixed class counts (one K = 64 among many K = 2 makes a batch's workspace
+    far larger than the sum of its members' own)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        E = int(rng.integers(1000, 200_000))
+        N = int(max(16, E // int(rng.integers(3, 60))))
+        K = 64 if i % 9 == 0 else int(rng.choice([2, 2, 3, 5, 17]))
+        g = dict(src=torch.empty(E, dtype=torch.int32), dst=torch.empty(E, dtype=torch.int32),
+                 w=torch.empty(E) if rng.random() < 0.6 else None, labels=torch.empty(N, dtype=torch.int32),
+                 K=K, flags=int(rng.integers(0, 16)))
+        out.append(Request(rid=i, graph=g, arrival=float(i) * 1e-5))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_admission_charges_each_batch_what_the_library_needs(seed):
+    from paper_2406_03726_amd import gee
+
+    clk = Clock()
+    be = _SizingBackend(clk)
+    reqs = _sized_reqs(120, seed)
+    one = [be.footprint(r) for r in reqs]
+    budget = int(np.sum(one) // 6)
+    srv = GeeServer(be, budget, max_batch=16, clock=clk)
+    srv.run_trace(reqs, sleep=clk.sleep)
+    assert all(r.t_done is not None and r.error is None for r in reqs)
+    assert srv.peak_in_use <= budget
+    assert any(len(s) > 1 for _, s, _ in be.charged), "no batch of several requests was formed"
+    for charged, sizes, zbytes in be.charged:
+        need = gee.batch_workspace_bytes_of_sizes(sizes) + zbytes
+        assert charged >= need
+    # the sum of the members' own footprints undercounts some batches of mixed class counts
+    assert any(charged > sum(be.batch_footprint([r]) for r in reqs if be._sizes(r) in sizes)
+               for charged, sizes, _ in be.charged if len(sizes) > 1)
