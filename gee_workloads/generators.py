@@ -45,6 +45,7 @@ class Graph:
     lap: bool = False
     cor: bool = False
     sym: bool = True  # each row is one undirected edge
+    deg_io: bool = False  # Laplacian with out-degrees on the left, in-degrees on the right
     name: str = ""
     meta: dict = dataclasses.field(default_factory=dict)
 

@@ -25,6 +25,11 @@
  *   - a class with n_k = 0 gives an all-zero column.
  *   - diagonal augmentation is applied first and the Laplacian then uses the degrees of
  *     A + I (row sums, weighted).
+ *   - "D the degree matrix" names no side for a directed graph. By default both factors
+ *     take the row sums (out-degrees). With the directed-degree option the left factor
+ *     takes each node's out-degree (row sum) and the right factor its in-degree (column
+ *     sum): D_out^-1/2 A D_in^-1/2, both with A + I under augmentation. For a symmetric A
+ *     the two coincide.
  *   - a node with degree <= 0 gets D^-1/2 = 0.
  *   - correlation is a plain row 2-norm division (no centering); zero rows stay zero.
  *
@@ -40,6 +45,7 @@
 #define OR_LAPLACIAN 2u
 #define OR_CORRELATION 4u
 #define OR_SYMMETRIZE 8u
+#define OR_DIRECTED_DEGREES 16u
 
 /* Class sizes n_k = #{j : y_j = k} (Section 2). Also checks the label range. */
 int gee_oracle_class_counts(const int32_t *labels, int64_t N, int32_t K, int64_t *counts)
@@ -137,6 +143,27 @@ int gee_oracle_degrees(const int32_t *src, const int32_t *dst, const double *w, 
 }
 
 /*
+ * In-degrees of the (possibly augmented) adjacency: the column sums, din_j = sum of the
+ * values in column j. Exposed for tests. `deg` has N slots.
+ */
+int gee_oracle_in_degrees(const int32_t *src, const int32_t *dst, const double *w, int64_t E,
+                          int64_t N, uint32_t flags, double *deg)
+{
+    if (E < 0 || N < 0 || (E > 0 && (!src || !dst)) || (N > 0 && !deg))
+        return -1;
+    entry_list L;
+    int rc = build_entries(src, dst, w, E, N, flags, &L);
+    if (rc == 0) {
+        for (int64_t j = 0; j < N; ++j)
+            deg[j] = 0.0;
+        for (int64_t t = 0; t < L.n; ++t)
+            deg[L.j[t]] += L.v[t];
+    }
+    free_entries(&L);
+    return rc;
+}
+
+/*
  * The embedding Z (row-major N x K, float64), with the options of Section 2 / Table 1.
  */
 int gee_oracle_embed(const int32_t *src, const int32_t *dst, const double *w, int64_t E,
@@ -144,7 +171,7 @@ int gee_oracle_embed(const int32_t *src, const int32_t *dst, const double *w, in
 {
     if (E < 0 || N < 0 || K < 1 || (E > 0 && (!src || !dst)) || (N > 0 && (!labels || !Z)))
         return -1;
-    if (flags & ~(OR_DIAG | OR_LAPLACIAN | OR_CORRELATION | OR_SYMMETRIZE))
+    if (flags & ~(OR_DIAG | OR_LAPLACIAN | OR_CORRELATION | OR_SYMMETRIZE | OR_DIRECTED_DEGREES))
         return -1;
 
     /* n_k and the non-zero value of each W row (Section 2). */
@@ -165,25 +192,42 @@ int gee_oracle_embed(const int32_t *src, const int32_t *dst, const double *w, in
         return rc;
     }
 
-    /* Laplacian normalization: v_ij <- v_ij * d_i^-1/2 * d_j^-1/2. */
+    /* Laplacian normalization: v_ij <- v_ij * d_i^-1/2 * d_j^-1/2 with d the row sums;
+       with directed degrees the column factor takes the in-degree (column sum) of j:
+       v_ij <- v_ij * dout_i^-1/2 * din_j^-1/2. */
     if (flags & OR_LAPLACIAN) {
-        double *deg = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
-        double *dinv = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
-        if (!deg || !dinv) {
+        size_t n1 = (size_t)(N > 0 ? N : 1);
+        double *deg = (double *)calloc(n1, sizeof(double));
+        double *dinv = (double *)calloc(n1, sizeof(double));
+        double *degc = (double *)calloc(n1, sizeof(double));
+        double *dinvc = (double *)calloc(n1, sizeof(double));
+        if (!deg || !dinv || !degc || !dinvc) {
             free(deg);
             free(dinv);
+            free(degc);
+            free(dinvc);
             free_entries(&L);
             free(nk);
             return -6;
         }
         for (int64_t t = 0; t < L.n; ++t)
             deg[L.i[t]] += L.v[t];
+        for (int64_t t = 0; t < L.n; ++t)
+            degc[L.j[t]] += L.v[t];
         for (int64_t i = 0; i < N; ++i)
             dinv[i] = deg[i] > 0.0 ? 1.0 / sqrt(deg[i]) : 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            if (flags & OR_DIRECTED_DEGREES)
+                dinvc[j] = degc[j] > 0.0 ? 1.0 / sqrt(degc[j]) : 0.0;
+            else
+                dinvc[j] = dinv[j];
+        }
         for (int64_t t = 0; t < L.n; ++t)
-            L.v[t] = L.v[t] * dinv[L.i[t]] * dinv[L.j[t]];
+            L.v[t] = L.v[t] * dinv[L.i[t]] * dinvc[L.j[t]];
         free(deg);
         free(dinv);
+        free(degc);
+        free(dinvc);
     }
 
     /* Z = A W, one pass over the entries: Z[i, y_j] += v_ij * (1 / n_{y_j}). */

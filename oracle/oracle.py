@@ -18,6 +18,7 @@ OR_DIAG = 1
 OR_LAPLACIAN = 2
 OR_CORRELATION = 4
 OR_SYMMETRIZE = 8
+OR_DIRECTED_DEGREES = 16
 
 _ERRORS = {-1: "bad argument", -2: "label out of range", -3: "node index out of range",
            -4: "non-finite weight", -6: "out of host memory"}
@@ -59,6 +60,9 @@ def _bind(lib):
     lib.gee_oracle_degrees.argtypes = [i32p, i32p, f64p, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_uint32, f64p]
     lib.gee_oracle_degrees.restype = ctypes.c_int
+    lib.gee_oracle_in_degrees.argtypes = [i32p, i32p, f64p, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_uint32, f64p]
+    lib.gee_oracle_in_degrees.restype = ctypes.c_int
     lib.gee_oracle_embed.argtypes = [i32p, i32p, f64p, ctypes.c_int64, ctypes.c_int64, i32p,
                                      ctypes.c_int32, ctypes.c_uint32, f64p]
     lib.gee_oracle_embed.restype = ctypes.c_int
@@ -71,9 +75,10 @@ def _ptr(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def _flags(diag, lap, cor, sym):
+def _flags(diag, lap, cor, sym, deg_io=False):
     return ((OR_DIAG if diag else 0) | (OR_LAPLACIAN if lap else 0)
-            | (OR_CORRELATION if cor else 0) | (OR_SYMMETRIZE if sym else 0))
+            | (OR_CORRELATION if cor else 0) | (OR_SYMMETRIZE if sym else 0)
+            | (OR_DIRECTED_DEGREES if deg_io else 0))
 
 
 class OracleError(ValueError):
@@ -112,16 +117,30 @@ def degrees(src, dst, w, N: int, diag=False, sym=True, lib=None) -> np.ndarray:
     return out[:N]
 
 
+def in_degrees(src, dst, w, N: int, diag=False, sym=True, lib=None) -> np.ndarray:
+    """Column sums of A (+ I): the in-degrees of the directed-degree Laplacian."""
+    lib = lib or load()
+    src, dst, w64 = _prep(src, dst, w)
+    out = np.zeros(max(N, 1), dtype=np.float64)
+    rc = lib.gee_oracle_in_degrees(_ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
+                                   _ptr(w64, ctypes.c_double), src.shape[0], N,
+                                   _flags(diag, False, False, sym), _ptr(out, ctypes.c_double))
+    if rc:
+        raise OracleError(rc)
+    return out[:N]
+
+
 def embed(src, dst, w, N: int, labels, K: int, diag=False, lap=False, cor=False, sym=True,
-          lib=None) -> np.ndarray:
-    """Z (float64, N x K) for one edge list; `w` None means every weight is 1."""
+          lib=None, deg_io=False) -> np.ndarray:
+    """Z (float64, N x K) for one edge list; `w` None means every weight is 1. `deg_io`:
+    under the Laplacian, out-degrees on the left and in-degrees on the right."""
     lib = lib or load()
     src, dst, w64 = _prep(src, dst, w)
     labels = np.ascontiguousarray(labels, dtype=np.int32)
     Z = np.zeros((max(N, 0), K), dtype=np.float64)
     rc = lib.gee_oracle_embed(_ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
                               _ptr(w64, ctypes.c_double), src.shape[0], N,
-                              _ptr(labels, ctypes.c_int32), K, _flags(diag, lap, cor, sym),
+                              _ptr(labels, ctypes.c_int32), K, _flags(diag, lap, cor, sym, deg_io),
                               _ptr(Z, ctypes.c_double))
     if rc:
         raise OracleError(rc)
@@ -131,4 +150,4 @@ def embed(src, dst, w, N: int, labels, K: int, diag=False, lap=False, cor=False,
 def embed_graph(g, lib=None) -> np.ndarray:
     """`embed` for a gee_workloads.Graph."""
     return embed(g.src, g.dst, g.w, g.N, g.labels, g.K, diag=g.diag, lap=g.lap, cor=g.cor,
-                 sym=g.sym, lib=lib)
+                 sym=g.sym, lib=lib, deg_io=getattr(g, "deg_io", False))

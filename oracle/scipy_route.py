@@ -13,8 +13,9 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def scipy_route(src, dst, w, N, labels, K, diag, lap, cor, sym):
-    """The paper's own library design: CSR matrices and sparse products (Section 3)."""
+def scipy_route(src, dst, w, N, labels, K, diag, lap, cor, sym, deg_io=False):
+    """The paper's own library design: CSR matrices and sparse products (Section 3).
+    `deg_io`: the Laplacian as D_out^-1/2 A D_in^-1/2 (row sums left, column sums right)."""
     E = len(src)
     wv = np.ones(E) if w is None else np.asarray(w, dtype=np.float64)
     A = sp.coo_matrix((wv, (np.asarray(src), np.asarray(dst))), shape=(N, N)).tocsr()
@@ -24,12 +25,15 @@ def scipy_route(src, dst, w, N, labels, K, diag, lap, cor, sym):
     if diag:
         A = (A + sp.identity(N, format="csr")).tocsr()
     if lap:
-        deg = np.asarray(A.sum(axis=1)).ravel()
-        dm = np.zeros(N)
-        pos = deg > 0
-        dm[pos] = 1.0 / np.sqrt(deg[pos])
-        Dm = sp.diags(dm)
-        A = (Dm @ A @ Dm).tocsr()
+        def inv_sqrt(d):
+            out = np.zeros(N)
+            pos = d > 0
+            out[pos] = 1.0 / np.sqrt(d[pos])
+            return out
+
+        Dl = sp.diags(inv_sqrt(np.asarray(A.sum(axis=1)).ravel()))
+        Dr = sp.diags(inv_sqrt(np.asarray(A.sum(axis=0)).ravel())) if deg_io else Dl
+        A = (Dl @ A @ Dr).tocsr()
     lab = np.asarray(labels)
     nk = np.bincount(lab[lab >= 0], minlength=K).astype(np.float64)
     rows = np.flatnonzero(lab >= 0)

@@ -28,8 +28,9 @@ FLAG_COMBOS = [(d, l, c) for d in (False, True) for l in (False, True) for c in 
 
 # ----------------------------------------------------------------------------- references
 
-def dense_brute_force(src, dst, w, N, labels, K, diag, lap, cor, sym):
-    """Table 1 in matrix form with dense numpy arrays (N small)."""
+def dense_brute_force(src, dst, w, N, labels, K, diag, lap, cor, sym, deg_io=False):
+    """Table 1 in matrix form with dense numpy arrays (N small). `deg_io`: the Laplacian
+    takes the row sums on the left and the column sums on the right."""
     A = np.zeros((N, N), dtype=np.float64)
     wv = np.ones(len(src)) if w is None else np.asarray(w, dtype=np.float64)
     for s, d, v in zip(src, dst, wv):
@@ -39,9 +40,12 @@ def dense_brute_force(src, dst, w, N, labels, K, diag, lap, cor, sym):
     if diag:
         A = A + np.eye(N)
     if lap:
-        deg = A.sum(axis=1)
-        dm = np.where(deg > 0, 1.0 / np.sqrt(np.where(deg > 0, deg, 1.0)), 0.0)
-        A = np.diag(dm) @ A @ np.diag(dm)
+        def inv_sqrt(deg):
+            return np.where(deg > 0, 1.0 / np.sqrt(np.where(deg > 0, deg, 1.0)), 0.0)
+
+        left = inv_sqrt(A.sum(axis=1))
+        right = inv_sqrt(A.sum(axis=0)) if deg_io else left
+        A = np.diag(left) @ A @ np.diag(right)
     W = np.zeros((N, K), dtype=np.float64)
     nk = np.array([(labels == k).sum() for k in range(K)], dtype=np.float64)
     for j in range(N):
@@ -55,7 +59,7 @@ def dense_brute_force(src, dst, w, N, labels, K, diag, lap, cor, sym):
 
 
 def _embed(lib, g, **over):
-    kw = dict(diag=g.diag, lap=g.lap, cor=g.cor, sym=g.sym)
+    kw = dict(diag=g.diag, lap=g.lap, cor=g.cor, sym=g.sym, deg_io=g.deg_io)
     kw.update(over)
     return orc.embed(g.src, g.dst, g.w, g.N, g.labels, g.K, lib=lib, **kw)
 
@@ -79,17 +83,20 @@ def pin_brute_force(lib, seeds=range(6)):
                 g = random_small_graph(seed, N=23, E=70, K=4, weighted=weighted, signed=signed,
                                        sym=sym, unknown_frac=0.15)
                 for diag, lap, cor in FLAG_COMBOS:
-                    Z = _embed(lib, g, diag=diag, lap=lap, cor=cor)
-                    R = dense_brute_force(g.src, g.dst, g.w, g.N, g.labels, g.K, diag, lap, cor, sym)
-                    _close(Z, R, 1e-11, f"brute force seed={seed} sym={sym} w={weighted} "
-                                        f"signed={signed} opts={(diag, lap, cor)}")
+                    for io in ((False, True) if lap else (False,)):
+                        Z = _embed(lib, g, diag=diag, lap=lap, cor=cor, deg_io=io)
+                        R = dense_brute_force(g.src, g.dst, g.w, g.N, g.labels, g.K, diag, lap, cor, sym,
+                                              deg_io=io)
+                        _close(Z, R, 1e-11, f"brute force seed={seed} sym={sym} w={weighted} "
+                                            f"signed={signed} opts={(diag, lap, cor)} in/out={io}")
 
 
 def pin_scipy_route(lib, graphs):
     """P2: oracle == scipy.sparse CSR products (the paper's library) on given graphs."""
     for g in graphs:
         Z = _embed(lib, g)
-        R = scipy_route(g.src, g.dst, g.w, g.N, g.labels, g.K, g.diag, g.lap, g.cor, g.sym)
+        R = scipy_route(g.src, g.dst, g.w, g.N, g.labels, g.K, g.diag, g.lap, g.cor, g.sym,
+                        deg_io=g.deg_io)
         _close(Z, R, 1e-10, f"scipy route {g.name}")
 
 
@@ -115,6 +122,33 @@ def pin_hand_worked(lib):
         Z = orc.embed(r[:, 0], r[:, 1], None, dg["N"], np.array(dg["labels"], np.int32), dg["K"],
                       lap=l, sym=False, lib=lib)
         _close(Z, fx["directed"]["expect"][name], 1e-12, f"hand worked directed {name}")
+
+
+def pin_directed_degrees(lib):
+    """The two degree readings of the Laplacian on a directed graph, worked by hand
+    (tests/golden/directed_degrees.json), the in-degrees themselves, and that on symmetric
+    input the in/out reading equals the row-sum reading."""
+    with open(os.path.join(GOLDEN, "directed_degrees.json")) as f:
+        fx = json.load(f)
+    gg = fx["graph"]
+    rows = np.array(gg["directed_rows"], dtype=np.float64)
+    s, d, w = rows[:, 0].astype(np.int32), rows[:, 1].astype(np.int32), rows[:, 2]
+    lab = np.array(gg["labels"], dtype=np.int32)
+    N, K = gg["N"], gg["K"]
+    cases = {"lap_rowsum": (False, False), "lap_inout": (False, True), "diag_lap_inout": (True, True)}
+    for name, (diag, io) in cases.items():
+        Z = orc.embed(s, d, w, N, lab, K, diag=diag, lap=True, sym=False, deg_io=io, lib=lib)
+        _close(Z, fx["expect"][name], 1e-12, f"directed degrees {name}")
+    _close(orc.in_degrees(s, d, w, N, sym=False, lib=lib), fx["expect"]["in_degrees"], 1e-14, "in-degrees")
+    _close(orc.in_degrees(s, d, w, N, diag=True, sym=False, lib=lib), fx["expect"]["in_degrees_diag"], 1e-14,
+           "in-degrees with A + I")
+    for seed in range(3):
+        g = random_small_graph(seed, N=40, E=150, K=3, weighted=True, sym=True)
+        for diag, cor in ((False, False), (True, True)):
+            a = orc.embed(g.src, g.dst, g.w, g.N, g.labels, g.K, diag=diag, lap=True, cor=cor, lib=lib)
+            b = orc.embed(g.src, g.dst, g.w, g.N, g.labels, g.K, diag=diag, lap=True, cor=cor, deg_io=True,
+                          lib=lib)
+            _close(a, b, 1e-12, "in/out degrees on symmetric input")
 
 
 def pin_closed_forms(lib):
@@ -306,4 +340,4 @@ def pin_sbm_statistics(lib, g, B_in, B_out):
 
 
 ALL_CHEAP_PINS = ("pin_brute_force", "pin_hand_worked", "pin_closed_forms", "pin_laplacian_symmetric",
-                  "pin_degrees")
+                  "pin_degrees", "pin_directed_degrees")

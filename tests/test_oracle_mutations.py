@@ -23,14 +23,19 @@ MUTATIONS = [
     ("self_loop_twice", "if ((flags & OR_SYMMETRIZE) && s != d) {", "if ((flags & OR_SYMMETRIZE)) {"),
     ("drop_diagonal", "if (flags & OR_DIAG) {", "if (0) {"),
     ("diag_value_two", "L->v[L->n] = 1.0;", "L->v[L->n] = 2.0;"),
-    ("rescale_row_twice", "L.v[t] * dinv[L.i[t]] * dinv[L.j[t]]", "L.v[t] * dinv[L.i[t]] * dinv[L.i[t]]"),
-    ("rescale_drop_col", "L.v[t] * dinv[L.i[t]] * dinv[L.j[t]]", "L.v[t] * dinv[L.i[t]]"),
+    ("rescale_row_twice", "L.v[t] * dinv[L.i[t]] * dinvc[L.j[t]]", "L.v[t] * dinv[L.i[t]] * dinv[L.i[t]]"),
+    ("rescale_drop_col", "L.v[t] * dinv[L.i[t]] * dinvc[L.j[t]]", "L.v[t] * dinv[L.i[t]]"),
+    ("in_out_swapped", "L.v[t] * dinv[L.i[t]] * dinvc[L.j[t]]", "L.v[t] * dinvc[L.i[t]] * dinv[L.j[t]]"),
+    ("directed_degrees_ignored", "if (flags & OR_DIRECTED_DEGREES)", "if (0)"),
+    ("in_degree_by_row", "degc[L.j[t]] += L.v[t];", "degc[L.i[t]] += L.v[t];"),
+    ("in_degree_inverse_not_sqrt", "dinvc[j] = degc[j] > 0.0 ? 1.0 / sqrt(degc[j]) : 0.0;",
+     "dinvc[j] = degc[j] > 0.0 ? 1.0 / degc[j] : 0.0;"),
     ("inverse_not_sqrt", "dinv[i] = deg[i] > 0.0 ? 1.0 / sqrt(deg[i]) : 0.0;",
      "dinv[i] = deg[i] > 0.0 ? 1.0 / deg[i] : 0.0;"),
     ("zero_degree_one", "dinv[i] = deg[i] > 0.0 ? 1.0 / sqrt(deg[i]) : 0.0;",
      "dinv[i] = deg[i] > 0.0 ? 1.0 / sqrt(deg[i]) : 1.0;"),
-    ("degree_by_column", "        for (int64_t t = 0; t < L.n; ++t)\n            deg[L.i[t]] += L.v[t];\n        for (int64_t i = 0; i < N; ++i)\n            dinv",
-     "        for (int64_t t = 0; t < L.n; ++t)\n            deg[L.j[t]] += L.v[t];\n        for (int64_t i = 0; i < N; ++i)\n            dinv"),
+    ("degree_by_column", "        for (int64_t t = 0; t < L.n; ++t)\n            deg[L.i[t]] += L.v[t];\n        for (int64_t t = 0; t < L.n; ++t)\n            degc",
+     "        for (int64_t t = 0; t < L.n; ++t)\n            deg[L.j[t]] += L.v[t];\n        for (int64_t t = 0; t < L.n; ++t)\n            degc"),
     ("class_of_row_node", "int32_t k = labels[j];", "int32_t k = labels[i] < 0 ? labels[j] : labels[i];"),
     ("wrong_class_size", "Z[i * K + k] += L.v[t] * (1.0 / (double)nk[k]);",
      "Z[i * K + k] += L.v[t] * (1.0 / (double)(nk[k] + 1));"),

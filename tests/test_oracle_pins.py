@@ -1,5 +1,7 @@
 """The FP64 oracle pinned against references outside itself (CPU only)."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -23,6 +25,19 @@ def test_hand_worked(lib):
 
 def test_closed_forms(lib):
     pins.pin_closed_forms(lib)
+
+
+def test_directed_degrees(lib):
+    pins.pin_directed_degrees(lib)
+
+
+def test_scipy_route_directed_degrees(lib):
+    gs = []
+    for seed in range(3):
+        g = random_small_graph(seed, N=150, E=1200, K=4, weighted=True, sym=False)
+        for d, c in ((False, False), (True, False), (True, True)):
+            gs.append(dataclasses.replace(g.with_options(d, True, c, name=f"io{seed}{d}{c}"), deg_io=True))
+    pins.pin_scipy_route(lib, gs)
 
 
 def test_laplacian_symmetric(lib):
