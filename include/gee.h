@@ -57,6 +57,18 @@ extern "C" {
 #define GEE_CORRELATION (1u << 2) /* each row of Z divided by its 2-norm (zero rows stay 0) */
 #define GEE_SYMMETRIZE (1u << 3)  /* each input row (s, d, w) is an undirected edge:
                                      A[s,d] and A[d,s] (a self-loop once) */
+#define GEE_DIRECTED_DEGREES (1u << 4) /* with GEE_LAPLACIAN on directed input: the left factor
+                                     takes each node's out-degree (row sum of A, + 1 with
+                                     GEE_DIAG) and the right factor its in-degree (column sum):
+                                     D_out^-1/2 A D_in^-1/2 (Section 2 options, Table 1: the
+                                     paper's "degree matrix" names no side for a directed
+                                     graph). Without it both sides take the row sums. No effect
+                                     with GEE_SYMMETRIZE (A is symmetric) or without the
+                                     Laplacian. The edge-list entry points compute the column
+                                     sums from one more partition pass over the transposed
+                                     entries; gee_embed_csr returns GEE_ERR_UNSUPPORTED for it
+                                     (a resident CSR has no column sums), and so do graphs past
+                                     the bucket path's limit (2^22 rows) */
 #define GEE_NO_VALIDATE (1u << 8) /* skip the checks that only report (non-finite weights)
                                      and raise no data-error bits; items that would address
                                      memory out of bounds (indices, labels) are still skipped,

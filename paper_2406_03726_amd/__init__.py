@@ -13,6 +13,7 @@ from .gee import (  # noqa: F401
     GEE_DATA_LABEL,
     GEE_DATA_WEIGHT,
     GEE_DIAG,
+    GEE_DIRECTED_DEGREES,
     GEE_LAPLACIAN,
     GEE_NO_VALIDATE,
     GEE_SYMMETRIZE,

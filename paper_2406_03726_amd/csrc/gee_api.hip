@@ -15,7 +15,8 @@ using namespace gee;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr unsigned kKnownFlags = GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE | GEE_NO_VALIDATE;
+constexpr unsigned kKnownFlags =
+    GEE_DIAG | GEE_LAPLACIAN | GEE_CORRELATION | GEE_SYMMETRIZE | GEE_DIRECTED_DEGREES | GEE_NO_VALIDATE;
 constexpr int64_t kMaxEntries = (int64_t)INT32_MAX - 65536;
 constexpr int64_t kMaxBatchNodes = (int64_t)1 << 28;
 constexpr int kMaxBatchGraphs = 1 << 20;
@@ -253,6 +254,8 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
             sb_req = x.sc.bucket_rows_log2;
         }
     }
+    p.io = edge_embed && !resident;
+    for (int g = 0; g < G && p.io; ++g) p.io = in_degree_pass(gs[g].flags);
     p.Vtot = voff;
     p.Ntot = noff;
     p.Ktot = (int)ktot;
@@ -325,6 +328,7 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
     w.gm = (GMeta *)take((size_t)p.G * sizeof(GMeta));
     if (p.G > 1) {
         w.tab = (GDesc *)take((size_t)p.G * sizeof(GDesc));
+        if (p.io) w.tabT = (GDesc *)take((size_t)p.G * sizeof(GDesc));
         w.node_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
         w.wave_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
         w.cnt_offs = (int *)take((size_t)(p.G + 1) * sizeof(int));
@@ -416,16 +420,30 @@ Tables make_tables(const std::vector<GDesc> &d) {
     return t;
 }
 
+// The descriptors with src and dst swapped: the transposed entries, whose row sums are the
+// column sums (in-degrees) of the graphs.
+std::vector<GDesc> transposed(const std::vector<GDesc> &d) {
+    std::vector<GDesc> t = d;
+    for (GDesc &x : t) std::swap(x.src, x.dst);
+    return t;
+}
+
 // Kernel view of the launch; for G > 1 also writes the tables into the workspace
 // (stream-ordered kernels carrying the bytes as arguments, so no host buffer has to
-// outlive the call; with sync = true they complete before returning).
+// outlive the call; with sync = true they complete before returning). With bT (plans with
+// Plan::io) also the view of the transposed entries.
 hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w, hipStream_t s, bool sync,
-                      Batch &b) {
+                      Batch &b, Batch *bT = nullptr) {
     b = Batch();
     b.G = p.G;
     b.gm = w.gm;
+    const std::vector<GDesc> dt = p.io ? transposed(d) : std::vector<GDesc>();
     if (p.G == 1) {
         b.one = d[0];
+        if (bT) {
+            *bT = b;
+            if (p.io) bT->one = dt[0];
+        }
         return hipSuccess;
     }
     const Tables t = make_tables(d);
@@ -435,12 +453,14 @@ hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w,
         const void *src;
         size_t bytes;
     } copies[] = {{w.tab, d.data(), sizeof(GDesc) * p.G},
+                  {w.tabT, p.io ? dt.data() : nullptr, p.io ? sizeof(GDesc) * p.G : 0},
                   {w.node_offs, t.node_offs.data(), sizeof(int) * n},
                   {w.wave_offs, t.wave_offs.data(), sizeof(int) * n},
                   {w.cnt_offs, t.cnt_offs.data(), sizeof(int) * n},
                   {w.class_offs, t.class_offs.data(), sizeof(int) * n},
                   {w.voffs, t.voffs.data(), sizeof(int64_t) * n}};
     for (const Copy &c : copies) {
+        if (!c.bytes) continue;
         hipError_t e = launch_upload(c.dst, c.src, c.bytes, s);
         if (e != hipSuccess) return e;
     }
@@ -454,17 +474,33 @@ hipError_t make_batch(const Plan &p, const std::vector<GDesc> &d, const Work &w,
     b.cnt_offs = w.cnt_offs;
     b.class_offs = w.class_offs;
     b.voffs = w.voffs;
+    if (bT) {
+        *bT = b;
+        if (p.io) bT->tab = w.tabT;
+    }
     return hipSuccess;
 }
 
-// Kernel sequence of gee_embed over a batch (edge lists -> Z).
-hipError_t enqueue_embed(const Batch &b, const Plan &p, const Work &wk, unsigned *st, hipStream_t s) {
+// Kernel sequence of gee_embed over a batch (edge lists -> Z). bT: the view of the
+// transposed entries (used when p.io).
+hipError_t enqueue_embed(const Batch &b, const Batch &bT, const Plan &p, const Work &wk, unsigned *st,
+                         hipStream_t s) {
     CountJob job;
     job.part = wk.cpart;
     job.counts = wk.counts;
     job.inv_n = wk.inv_n;
     job.slices = p.cnt_blocks;
     job.classes = p.Ktot;
+    if (p.io) {
+        // in-degrees: the transposed entries partitioned by their rows (the columns), c_j from
+        // their sums; then the entries themselves, s_i from the out-degrees, and the class sums
+        if (!p.bucket) return hipErrorNotSupported;  // excluded on the host (plan_chunks)
+        hipError_t e = launch_csr_build(bT, p, wk, st, s, &job);
+        if (e == hipSuccess) e = launch_bucket_embed(bT, p, wk, s, kDegIn, false);
+        if (e == hipSuccess) e = launch_csr_build(b, p, wk, st, s, nullptr);
+        if (e == hipSuccess) e = launch_bucket_embed(b, p, wk, s, kDegOut, true);
+        return e;
+    }
     hipError_t e = launch_csr_build(b, p, wk, st, s, &job);
     if (p.bucket) return e == hipSuccess ? launch_bucket_embed(b, p, wk, s) : e;
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
@@ -526,31 +562,36 @@ int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t 
             cur.clear();
             rows = 0;
         };
-        for (const GraphIn &x : gs) {
-            if (preferred_bucket_sb(x.K) != sbp) continue;
-            const int64_t n = x.N;
-            if (n > cap) {
-                flush();
+        // graphs that need the transposed pass (in-degrees) form chunks of their own
+        for (int io = 0; io < 2; ++io) {
+            for (const GraphIn &x : gs) {
+                if (preferred_bucket_sb(x.K) != sbp || (int)in_degree_pass(x.flags) != io) continue;
+                const int64_t n = x.N;
+                if (n > cap) {
+                    flush();
+                    cur.push_back(x);
+                    flush();
+                    continue;
+                }
+                const int64_t next = ((rows + (1 << sbp) - 1) >> sbp << sbp) + n;
+                if (!cur.empty() && next > cap) {
+                    flush();
+                    rows = n;
+                } else {
+                    rows = next;
+                }
                 cur.push_back(x);
-                flush();
-                continue;
             }
-            const int64_t next = ((rows + (1 << sbp) - 1) >> sbp << sbp) + n;
-            if (!cur.empty() && next > cap) {
-                flush();
-                rows = n;
-            } else {
-                rows = next;
-            }
-            cur.push_back(x);
+            flush();
         }
-        flush();
         if (sbp == GEE_BUCKET_SB_MIN) break;
     }
     total = 0;
     for (Chunk &c : out) {
         int rc = make_plan(c.gs.data(), (int)c.gs.size(), false, c.p, c.d, true);
         if (rc) return rc;
+        // in-degrees come from the bucket path's transposed pass only
+        if (c.p.io && !c.p.bucket) return GEE_ERR_UNSUPPORTED;
         Work w;
         c.off = total;
         total += (carve(c.p, kEmbedParts, nullptr, w) + kAlign - 1) / kAlign * kAlign;
@@ -966,8 +1007,9 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
         Work wk;
         carve(c.p, kEmbedParts, (char *)workspace + c.off, wk);
         Batch b;
-        e = make_batch(c.p, c.d, wk, s, false, b);
-        if (e == hipSuccess) e = enqueue_embed(b, c.p, wk, st, s);
+        Batch bT;
+        e = make_batch(c.p, c.d, wk, s, false, b, &bT);
+        if (e == hipSuccess) e = enqueue_embed(b, bT, c.p, wk, st, s);
         if (e != hipSuccess) break;
     }
     return hip_status(e);
@@ -1002,7 +1044,7 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     pl->status = st;
     char *wsb = static_cast<char *>(pl->ws) + kAlign;
     // every chunk has its own workspace region, so all tables are written before capture
-    std::vector<Batch> bs(ch.size());
+    std::vector<Batch> bs(ch.size()), bTs(ch.size());
     std::vector<Work> wks(ch.size());
     (void)hipGetLastError();  // see launch_stream
     if (e == hipSuccess) {
@@ -1012,7 +1054,7 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     for (size_t i = 0; i < ch.size() && e == hipSuccess; ++i) {
         if (ch[i].p.Ntot == 0) continue;
         carve(ch[i].p, kEmbedParts, wsb + ch[i].off, wks[i]);
-        e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i]);
+        e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i], &bTs[i]);
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1020,7 +1062,7 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
         t_capturing = true;
         hipError_t e1 = hipSuccess;
         for (size_t i = 0; i < ch.size() && e1 == hipSuccess; ++i)
-            if (ch[i].p.Ntot > 0) e1 = enqueue_embed(bs[i], ch[i].p, wks[i], st, cs);
+            if (ch[i].p.Ntot > 0) e1 = enqueue_embed(bs[i], bTs[i], ch[i].p, wks[i], st, cs);
         t_capturing = false;
         hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
         e = e1 != hipSuccess ? e1 : e2;
@@ -1081,12 +1123,16 @@ size_t gee_embed_csr_workspace_bytes(int64_t M, int32_t N, int32_t K, uint32_t f
     return carve(p, kPCount | kPEmbed, nullptr, w);
 }
 
+// A resident CSR carries no column sums: the directed-degree Laplacian needs the edge list.
+bool csr_unsupported(uint32_t flags) { return (flags & GEE_DIRECTED_DEGREES) && (flags & GEE_LAPLACIAN); }
+
 int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *val, int64_t M, int32_t N,
                      const int32_t *labels, int32_t K, uint32_t flags, float *Z,
                      const gee_schedule *sched, void *workspace, size_t workspace_bytes, void *stream) {
     if (M < 0) return GEE_ERR_ARG;
     int rc = check_common(N, K, flags);
     if (rc) return rc;
+    if (csr_unsupported(flags)) return GEE_ERR_UNSUPPORTED;
     if (N == 0) return M > 0 ? GEE_ERR_ARG : GEE_OK;
     if (!row_ptr || !labels || !Z || (M > 0 && !col)) return GEE_ERR_ARG;
     unsigned *st = nullptr;
@@ -1124,6 +1170,7 @@ int gee_embed_csr(const int32_t *row_ptr, const int32_t *col, const float *val, 
     if (M < 0) return GEE_ERR_ARG;
     int rc = check_common(N, K, flags);
     if (rc) return rc;
+    if (csr_unsupported(flags)) return GEE_ERR_UNSUPPORTED;
     if (N == 0) return M > 0 ? GEE_ERR_ARG : GEE_OK;
     size_t bytes = gee_embed_csr_workspace_bytes(M, N, K, flags, nullptr);
     if (bytes == 0) return GEE_ERR_TOO_LARGE;

@@ -148,15 +148,18 @@ __global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__r
     }
 }
 
-// s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count).
+// s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count); the
+// mode says which of them this pass owns (kDegIn: d is an in-degree, from the transposed
+// entries, and sets c_i only; kDegOut: d is an out-degree and sets s_i only).
 __device__ __forceinline__ void set_row_coef(const GDesc &gd, const float *__restrict__ inv_n, int r, float d,
-                                             float *__restrict__ srow, float2 *__restrict__ info) {
+                                             float *__restrict__ srow, float2 *__restrict__ info, int mode) {
     float s = 1.0f;
     if (gd.flags & kLap) {
         const float dd = d + ((gd.flags & kDiag) ? 1.0f : 0.0f);
         s = dd > 0.0f ? 1.0f / sqrtf(dd) : 0.0f;
     }
-    srow[r] = s;
+    if (mode != kDegIn) srow[r] = s;
+    if (mode == kDegOut) return;
     int y = gd.labels[r - gd.node_off];
     if (y < 0 || y >= gd.K) y = -1;
     info[r] = node_info(y >= 0 ? s * inv_n[gd.class_off + y] : 0.0f, y);
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
                                                      const int *__restrict__ bmeta, int sb,
                                                      const float *__restrict__ inv_n,
                                                      float *__restrict__ dpart, float *__restrict__ srow,
-                                                     float2 *__restrict__ info) {
+                                                     float2 *__restrict__ info, int mode) {
     extern __shared__ float dsum_all[];  // [4][kDegCopies][R + 1]
     const int lane = lane_id();
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
     const bool own = lane < R && r >= gd.node_off && r < gd.node_off + gd.N;
     if (!lap) {
         // c_i = 1 / n_{y_i}; a split bucket's rows are set by bucket_degree_fix
-        if (pt.w < 0 && own) set_row_coef(gd, inv_n, r, 0.0f, srow, info);
+        if (pt.w < 0 && own) set_row_coef(gd, inv_n, r, 0.0f, srow, info, mode);
         return;
     }
     const int RS = R + 1;
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
         dpart[(int64_t)pt.w * 64 + lane] = d;
         return;
     }
-    if (own) set_row_coef(gd, inv_n, r, d, srow, info);
+    if (own) set_row_coef(gd, inv_n, r, d, srow, info, mode);
 }
 
 // Wavefronts take the split buckets in turn: degrees = the parts' partial sums in part
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__
                                                          const int *__restrict__ bmeta, int sb,
                                                          const float *__restrict__ inv_n,
                                                          const float *__restrict__ dpart, float *__restrict__ srow,
-                                                         float2 *__restrict__ info) {
+                                                         float2 *__restrict__ info, int mode) {
     const int lane = lane_id();
     const int nmulti = bmeta[1];
     for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nmulti; i += gridDim.x * 4) {
@@ -327,7 +330,8 @@ __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__
             for (; k < m.z; ++k) d += dp[(int64_t)k * 64];
         }
         const int r = r0 + lane;
-        if (lane < (1 << sb) && r >= gd.node_off && r < gd.node_off + gd.N) set_row_coef(gd, inv_n, r, d, srow, info);
+        if (lane < (1 << sb) && r >= gd.node_off && r < gd.node_off + gd.N)
+            set_row_coef(gd, inv_n, r, d, srow, info, mode);
     }
 }
 
@@ -585,20 +589,22 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
 // ----------------------------------------------------------------------------- launch
 
 template <typename KT, bool WEIGHTED>
-static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, const KT *key, hipStream_t s) {
+static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, const KT *key, hipStream_t s, int mode,
+                               bool sums) {
     const unsigned nbp = (unsigned)p.bparts;
     const float *val = WEIGHTED ? wk.tval : nullptr;
     prof_begin(kKBucketDegree, s);
     const size_t dlds = (size_t)4 * kDegCopies * ((1 << p.sb) + 1) * sizeof(float);
     hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key, val,
-                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info);
+                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info, mode);
     prof_end(kKBucketDegree, s);
     // split buckets, at most (the grids of the two fix kernels loop over the actual count)
     const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);
     prof_begin(kKBucketDegreeFix, s);
     hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
-                       wk.dpart, wk.srow, wk.info);
+                       wk.dpart, wk.srow, wk.info, mode);
     prof_end(kKBucketDegreeFix, s);
+    if (!sums) return;
     const size_t lds = bucket_lds(p.sb, p.Kmax);
     const int zs = p.Kmax << p.sb;  // floats per partial slot
     prof_begin(kKBucketEmbed, s);
@@ -611,7 +617,7 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     prof_end(kKBucketEmbedFix, s);
 }
 
-hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s) {
+hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s, int mode, bool sums) {
     // keys of the bucketed entries: pass B's u16 row-in-bucket, else pass A's key (u16
     // when the row's low bits fit, else the whole row)
     const bool with_b = p.s2 > 0;
@@ -625,10 +631,10 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
     hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
                        wk.multi, wk.bmeta);
     prof_end(kKBucketPartFill, s);
-    if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s);
-    else if (key16) launch_bucket_sums<uint16_t, false>(b, p, wk, (const uint16_t *)key, s);
-    else if (p.weighted) launch_bucket_sums<int, true>(b, p, wk, (const int *)key, s);
-    else launch_bucket_sums<int, false>(b, p, wk, (const int *)key, s);
+    if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s, mode, sums);
+    else if (key16) launch_bucket_sums<uint16_t, false>(b, p, wk, (const uint16_t *)key, s, mode, sums);
+    else if (p.weighted) launch_bucket_sums<int, true>(b, p, wk, (const int *)key, s, mode, sums);
+    else launch_bucket_sums<int, false>(b, p, wk, (const int *)key, s, mode, sums);
     return hipGetLastError();
 }
 

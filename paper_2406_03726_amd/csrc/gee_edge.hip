@@ -6,9 +6,11 @@
 // Launches (all grid-stride, 256 threads):
 //   edge_init     Z = 0, degrees = 1 under diagonal augmentation (else 0), class counts = 0
 //   edge_prep     class counts (label range check) in the first workgroups; under the
-//                 Laplacian, weighted degrees d_i = sum_j (A [+ I])_ij by float atomics
+//                 Laplacian, weighted degrees d_i = sum_j (A [+ I])_ij by float atomics (and,
+//                 with directed degrees, the in-degrees sum_i (A [+ I])_ij as well)
 //   edge_coef     per node: s_j = d_j^-1/2 (0 for d_j <= 0; 1 without the Laplacian) and
-//                 c_j = s_j / n_{y_j} (0 for an unknown label or an empty class)
+//                 c_j = s_j / n_{y_j} (0 for an unknown label or an empty class); with
+//                 directed degrees c_j takes the in-degree's inverse square root instead
 //   edge_scatter  per edge row: Z[s, y_d] += e c_d and, for undirected input, Z[d, y_s] += e c_s
 //   edge_finish   per Z row: the diagonal term c_i at k = y_i, the row factor s_i (Table 1,
 //                 Laplacian row) and the row 2-norm (correlation)
@@ -25,8 +27,9 @@ constexpr int kEB = 256;  // threads per workgroup of every launch here
 __device__ __forceinline__ bool finite_f(float x) { return (__float_as_uint(x) & 0x7f800000u) != 0x7f800000u; }
 
 // Z = 0 (16-byte stores on the aligned body), degrees = d0, class counts = 0.
-__global__ __launch_bounds__(kEB) void edge_init(float *__restrict__ Z, int64_t nz, float *__restrict__ deg, int N,
-                                               float d0, int *__restrict__ counts, int K) {
+__global__ __launch_bounds__(kEB) void edge_init(float *__restrict__ Z, int64_t nz, float *__restrict__ deg,
+                                               float *__restrict__ degin, int N, float d0, int *__restrict__ counts,
+                                               int K) {
     const int64_t tid = (int64_t)blockIdx.x * kEB + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * kEB;
     const int64_t head = (int64_t)((16u - ((unsigned)(uintptr_t)Z & 15u)) & 15u) / 4;  // Z is 4-byte aligned
@@ -40,6 +43,8 @@ __global__ __launch_bounds__(kEB) void edge_init(float *__restrict__ Z, int64_t 
     if (tid < nz - t0) Z[t0 + tid] = 0.f;
     if (deg)
         for (int64_t i = tid; i < N; i += nth) deg[i] = d0;
+    if (degin)
+        for (int64_t i = tid; i < N; i += nth) degin[i] = d0;
     if (tid < K) counts[tid] = 0;
 }
 
@@ -51,7 +56,7 @@ __global__ __launch_bounds__(kEB) void edge_prep(const int *__restrict__ labels,
                                                int *__restrict__ counts, const int *__restrict__ src,
                                                const int *__restrict__ dst, const float *__restrict__ w,
                                                int64_t E, bool sym, float *__restrict__ deg,
-                                               unsigned *status) {
+                                               float *__restrict__ degin, unsigned *status) {
     __shared__ int hist[kMaxClasses];
     if ((int)blockIdx.x < cblocks) {
         for (int k = threadIdx.x; k < K; k += kEB) hist[k] = 0;
@@ -80,6 +85,7 @@ __global__ __launch_bounds__(kEB) void edge_prep(const int *__restrict__ labels,
         if ((unsigned)s >= (unsigned)N || (unsigned)d >= (unsigned)N || !finite_f(x)) continue;
         unsafeAtomicAdd(&deg[s], x);
         if (sym && s != d) unsafeAtomicAdd(&deg[d], x);
+        if (degin) unsafeAtomicAdd(&degin[d], x);
     }
 }
 
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(kEB) void edge_prep(const int *__restrict__ labels,
 // written over the degree in place.
 __global__ __launch_bounds__(kEB) void edge_coef(const int *__restrict__ labels, int N, int K,
                                                const int *__restrict__ counts, float *__restrict__ deg_s,
-                                               float2 *__restrict__ info) {
+                                               const float *__restrict__ degin, float2 *__restrict__ info) {
     const int64_t nth = (int64_t)gridDim.x * kEB;
     for (int64_t j = (int64_t)blockIdx.x * kEB + threadIdx.x; j < N; j += nth) {
         const int y = labels[j];
@@ -98,6 +104,10 @@ __global__ __launch_bounds__(kEB) void edge_coef(const int *__restrict__ labels,
             const float d = deg_s[j];
             s = d > 0.0f ? 1.0f / sqrtf(d) : 0.0f;
             deg_s[j] = s;
+        }
+        if (degin) {
+            const float d = degin[j];
+            s = d > 0.0f ? 1.0f / sqrtf(d) : 0.0f;  // the column factor (in-degree)
         }
         const float c = n > 0 ? s / (float)n : 0.0f;
         info[j] = make_float2(c, __int_as_float(known && c != 0.0f ? y : -1));
@@ -196,7 +206,8 @@ void launch_finish(int blocks, hipStream_t s, float *Z, int N, int K, const floa
 
 size_t edge_workspace_bytes(int N, int K, unsigned flags) {
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return up((size_t)K * 4) + up((size_t)N * 8) + ((flags & kLap) ? up((size_t)N * 4) : 0);
+    return up((size_t)K * 4) + up((size_t)N * 8) + ((flags & kLap) ? up((size_t)N * 4) : 0) +
+           (in_degree_pass(flags) ? up((size_t)N * 4) : 0);
 }
 
 hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int64_t E, int N, const int *labels,
@@ -208,13 +219,15 @@ hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int
     float2 *info = reinterpret_cast<float2 *>(p);
     p += up((size_t)N * 8);
     float *deg = (flags & kLap) ? reinterpret_cast<float *>(p) : nullptr;
+    if (deg) p += up((size_t)N * 4);
+    float *degin = in_degree_pass(flags) ? reinterpret_cast<float *>(p) : nullptr;
     const bool sym = flags & kSym, diag = flags & kDiag, cor = flags & kCor;
     const int64_t nz = (int64_t)N * K;
     if (flags & kNoValidate) status = nullptr;  // no checks that only report, no bits raised
 
     prof_begin(kKEdgeInit, s);
-    hipLaunchKernelGGL(edge_init, dim3((unsigned)grid_for(nz / 4 + 1, 4, 16384)), dim3(kEB), 0, s, Z, nz, deg, N,
-                       diag ? 1.0f : 0.0f, counts, K);
+    hipLaunchKernelGGL(edge_init, dim3((unsigned)grid_for(nz / 4 + 1, 4, 16384)), dim3(kEB), 0, s, Z, nz, deg, degin,
+                       N, diag ? 1.0f : 0.0f, counts, K);
     prof_end(kKEdgeInit, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -223,13 +236,13 @@ hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int
     const int dblocks = deg && E > 0 ? grid_for(E, 4, 16384) : 0;
     prof_begin(kKEdgePrep, s);
     hipLaunchKernelGGL(edge_prep, dim3((unsigned)(cblocks + dblocks)), dim3(kEB), 0, s, labels, N, K, cblocks,
-                       counts, src, dst, w, E, sym, deg, status);
+                       counts, src, dst, w, E, sym, deg, degin, status);
     prof_end(kKEdgePrep, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     prof_begin(kKEdgeCoef, s);
     hipLaunchKernelGGL(edge_coef, dim3((unsigned)grid_for(N, 4, 16384)), dim3(kEB), 0, s, labels, N, K, counts, deg,
-                       info);
+                       degin, info);
     prof_end(kKEdgeCoef, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 

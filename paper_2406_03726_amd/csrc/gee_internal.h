@@ -12,7 +12,12 @@
 namespace gee {
 
 // Option bits (same values as the public GEE_* flags).
-constexpr unsigned kDiag = 1u, kLap = 2u, kCor = 4u, kSym = 8u;
+constexpr unsigned kDiag = 1u, kLap = 2u, kCor = 4u, kSym = 8u, kDirDeg = 16u;
+// A graph whose Laplacian takes in-degrees on the right (directed input with the
+// directed-degree option): its column sums come from a pass over the transposed entries.
+__host__ __device__ constexpr bool in_degree_pass(unsigned f) {
+    return (f & kLap) && (f & kDirDeg) && !(f & kSym);
+}
 // Device data-error bits (same values as the public GEE_DATA_* bits).
 constexpr unsigned kErrLabel = 1u, kErrIndex = 2u, kErrWeight = 4u, kErrCsr = 8u;
 // GEE_NO_VALIDATE: the graph's checks raise nothing (memory-safety guards stay).
@@ -296,12 +301,15 @@ struct Plan {
     // partial slots of buckets cut into several parts
     bool bucket = false;
     int64_t bparts = 0, bslots = 0;
+    // every graph of the launch needs in-degrees (in_degree_pass): the partition and the
+    // degree kernels run first over the transposed entries
+    bool io = false;
 };
 
 // Workspace carve-up; every member is a device pointer into one caller buffer.
 struct Work {
-    // batch tables (G > 1)
-    GDesc *tab = nullptr;
+    // batch tables (G > 1); tabT: the descriptors with src and dst swapped (Plan::io)
+    GDesc *tab = nullptr, *tabT = nullptr;
     int *node_offs = nullptr, *wave_offs = nullptr, *cnt_offs = nullptr, *class_offs = nullptr;
     int64_t *voffs = nullptr;
     GMeta *gm = nullptr;       // [G]
@@ -444,10 +452,15 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
 constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
 constexpr int kBucketDefaultPart = 8192;
 constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end
-hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s);
+// Degree kernels' outputs: s_i into srow and c_i = s_i / n_{y_i} into info (both), c_i alone
+// from the in-degrees of a transposed pass (in), s_i alone from the out-degrees (out).
+enum DegreeMode : int { kDegBoth = 0, kDegIn = 1, kDegOut = 2 };
+// sums = false: the part table and the degrees only (the transposed pass).
+hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s, int mode = kDegBoth,
+                               bool sums = true);
 // Original GEE form (edge-list scatter with float atomics; gee_edge.hip): workspace bytes
 // and the whole launch sequence for one graph.
-size_t edge_workspace_bytes(int N, int K, unsigned flags);
+size_t edge_workspace_bytes(int N, int K, unsigned flags);  // (+ N floats of in-degrees for in_degree_pass)
 hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int64_t E, int N, const int *labels,
                              int K, unsigned flags, float *Z, void *ws, unsigned *status, hipStream_t s);
 // Sparse storage of a dense Z (gee_zsparse.hip): scratch of one int per tile of rows and

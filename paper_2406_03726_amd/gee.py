@@ -19,6 +19,7 @@ GEE_DIAG = 1 << 0
 GEE_LAPLACIAN = 1 << 1
 GEE_CORRELATION = 1 << 2
 GEE_SYMMETRIZE = 1 << 3
+GEE_DIRECTED_DEGREES = 1 << 4
 GEE_NO_VALIDATE = 1 << 8
 
 GEE_DATA_LABEL = 1 << 0
@@ -44,9 +45,10 @@ class GeeError(RuntimeError):
         self.code = code
 
 
-def flags_of(diag=False, lap=False, cor=False, sym=True) -> int:
+def flags_of(diag=False, lap=False, cor=False, sym=True, deg_io=False) -> int:
     return ((GEE_DIAG if diag else 0) | (GEE_LAPLACIAN if lap else 0)
-            | (GEE_CORRELATION if cor else 0) | (GEE_SYMMETRIZE if sym else 0))
+            | (GEE_CORRELATION if cor else 0) | (GEE_SYMMETRIZE if sym else 0)
+            | (GEE_DIRECTED_DEGREES if deg_io else 0))
 
 
 def _check(rc: int, where: str):

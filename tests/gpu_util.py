@@ -27,7 +27,7 @@ def graph_tensors(g):
 
 
 def flags(g):
-    return gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    return gee.flags_of(g.diag, g.lap, g.cor, g.sym, getattr(g, "deg_io", False))
 
 
 def embed_graph(g, sched=None):
