@@ -85,7 +85,9 @@ typedef enum {
     GEE_ERR_OOM = -6,         /* device allocation failed */
     GEE_ERR_HIP = -7,         /* a HIP runtime call failed */
     GEE_ERR_UNSUPPORTED = -8, /* valid request the library does not implement */
-    GEE_ERR_WORKSPACE = -9    /* caller workspace too small */
+    GEE_ERR_WORKSPACE = -9,   /* caller workspace too small */
+    GEE_ERR_SCRATCH = -10     /* gee_embed_noalloc: the request's workspace exceeds the
+                                 library's fixed scratch (gee_scratch_bytes) */
 } gee_status;
 
 /* Device data-error bits returned by gee_get_data_errors. */
@@ -127,8 +129,8 @@ const char *gee_status_string(int status);
    the calling thread; "" if there was none. The string is static (owned by HIP). */
 const char *gee_last_hip_error(void);
 
-/* Per-device set-up: finds the device address of the library's data-error words on the
-   current device. Allocates nothing. Called lazily by every entry
+/* Per-device set-up: finds the device addresses of the library's data-error words and
+   fixed scratch on the current device. Allocates nothing. Called lazily by every entry
    point; call it once up front on each device when later calls run under stream capture. */
 int gee_init(void);
 
@@ -209,6 +211,26 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *w, int64_t E,
 int gee_embed_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
                  const int32_t *labels, int32_t K, uint32_t flags, float *Z,
                  const gee_schedule *sched, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * gee_embed_noalloc - gee_embed for callers that cannot allocate device memory: code under
+ * stream capture (HIP graphs), tight serving loops, harnesses that forbid allocation.
+ *   Arguments, results, determinism and data errors: exactly those of gee_embed (the same
+ *   kernels; Z is bitwise the Z of gee_embed_ws with the default schedule).
+ *   Workspace: the library's fixed scratch, a file-scope device array of gee_scratch_bytes()
+ *   bytes (256 MiB) that every device the library runs on holds until the process ends. The
+ *   call allocates nothing. A request whose gee_embed_workspace_bytes() (default schedule)
+ *   exceeds it returns GEE_ERR_SCRATCH and enqueues nothing: up to about 14M CSR entries
+ *   unweighted or 10M weighted fit (M = 2E under GEE_SYMMETRIZE; the 10,000-node SBM graph
+ *   of 5.57M edges needs 90 MiB).
+ *   Concurrency: every call on one device uses the same scratch, so calls whose work
+ *   overlaps on one device (different streams, or host threads) race and give wrong
+ *   results; order them on one stream or synchronize between them. Nothing in the scratch
+ *   needs to start at zero, so the contents a previous call left do not matter.
+ * Call gee_init() once on the device before capturing a call into a graph. */
+size_t gee_scratch_bytes(void);
+int gee_embed_noalloc(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,
+                      const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream);
 
 /* ---------------------------------------------------------------------------------
  * gee_embed_csr - Z from a resident CSR (for example one built by gee_build_csr).

@@ -34,6 +34,8 @@ from .gee import (  # noqa: F401
     gee_embed_csr,
     gee_embed_csr_workspace_bytes,
     gee_embed_workspace_bytes,
+    gee_embed_noalloc,
+    gee_scratch_bytes,
     gee_get_data_errors,
     gee_init,
     schedule,

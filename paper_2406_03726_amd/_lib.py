@@ -58,6 +58,9 @@ SYMBOLS = {
     "gee_embed_ws": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,
                                     ctypes.c_int32, ctypes.c_uint32, c_f32p, ctypes.POINTER(GeeSchedule),
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "gee_scratch_bytes": (ctypes.c_size_t, []),
+    "gee_embed_noalloc": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,
+                                         ctypes.c_int32, ctypes.c_uint32, c_f32p, ctypes.c_void_p]),
     "gee_embed_csr_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                          ctypes.c_uint32, ctypes.POINTER(GeeSchedule)]),
     "gee_embed_csr": (ctypes.c_int, [c_i32p, c_i32p, c_f32p, ctypes.c_int64, ctypes.c_int32, c_i32p,

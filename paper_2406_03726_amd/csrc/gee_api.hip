@@ -50,17 +50,23 @@ constexpr int kStatusSlots = 1024;
 constexpr int kStatusStride = 16;  // unsigned per slot
 static __device__ __align__(256) unsigned status_words[kStatusSlots * kStatusStride];
 
+// Fixed-size scratch of gee_embed_noalloc (device memory the library owns for the life of
+// the process, one copy per device): the workspace of requests up to kScratchBytes.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct DevState {
     bool ready = false;
     unsigned *words = nullptr;   // device address of status_words on this device
+    void *scratch = nullptr;     // device address of scratch on this device
     const void *key[kStatusSlots];
     bool used[kStatusSlots];
 };
 std::mutex g_status_mu;
 DevState g_dev[64];
 
-// Device address of the data-error words for the current device (once per device; the
-// array's name is a host-side stand-in that kernels must never be given).
+// Device addresses of the file-scope arrays for the current device (once per device; the
+// names of the arrays are host-side stand-ins that kernels must never be given).
 int device_state(DevState **out) {
     int dev = 0;
     hipError_t ge = hipGetDevice(&dev);
@@ -68,10 +74,12 @@ int device_state(DevState **out) {
     if (dev < 0 || dev >= 64) return GEE_ERR_UNSUPPORTED;
     DevState &ds = g_dev[dev];
     if (!ds.ready) {
-        void *w = nullptr;
+        void *w = nullptr, *sc = nullptr;
         hipError_t e = hipGetSymbolAddress(&w, HIP_SYMBOL(status_words));
+        if (e == hipSuccess) e = hipGetSymbolAddress(&sc, HIP_SYMBOL(scratch));
         if (e != hipSuccess) return hip_status(e);
         ds.words = static_cast<unsigned *>(w);
+        ds.scratch = sc;
         for (int i = 0; i < kStatusSlots; ++i) {
             ds.key[i] = nullptr;
             ds.used[i] = false;
@@ -662,6 +670,7 @@ const char *gee_status_string(int st) {
     case GEE_ERR_HIP: return "HIP runtime error";
     case GEE_ERR_UNSUPPORTED: return "unsupported request";
     case GEE_ERR_WORKSPACE: return "workspace too small";
+    case GEE_ERR_SCRATCH: return "request needs more than the library's fixed scratch (gee_scratch_bytes)";
     default: return "unknown status";
     }
 }
@@ -707,6 +716,8 @@ int gee_get_data_errors(void *stream, uint32_t *bits) {
     *bits = h;
     return GEE_OK;
 }
+
+size_t gee_scratch_bytes(void) { return kScratchBytes; }
 
 int gee_default_schedule(int64_t E, int32_t N, int32_t K, uint32_t flags, gee_schedule *out) {
     if (!out || E < 0) return GEE_ERR_ARG;
@@ -877,6 +888,27 @@ int gee_embed(const int32_t *src, const int32_t *dst, const float *wgt, int64_t 
     rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Z, nullptr, ws, bytes, stream);
     e = hipFreeAsync(ws, s);
     return rc ? rc : hip_status(e);
+}
+
+// --------------------------------------------------------------------------- without allocation
+
+int gee_embed_noalloc(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
+                      const int32_t *labels, int32_t K, uint32_t flags, float *Z, void *stream) {
+    if (E < 0) return GEE_ERR_ARG;
+    int rc = check_common(N, K, flags);
+    if (rc) return rc;
+    if (N == 0) return E > 0 ? GEE_ERR_ARG : GEE_OK;
+    const size_t need = gee_embed_workspace_bytes(E, N, K, flags, wgt != nullptr, nullptr);
+    if (need == 0) return GEE_ERR_TOO_LARGE;
+    if (need > kScratchBytes) return GEE_ERR_SCRATCH;
+    void *sc = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_status_mu);
+        DevState *ds = nullptr;
+        if ((rc = device_state(&ds))) return rc;
+        sc = ds->scratch;
+    }
+    return gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Z, nullptr, sc, kScratchBytes, stream);
 }
 
 // --------------------------------------------------------------------------- sparse Z

@@ -34,6 +34,7 @@ GEE_ERR_OOM = -6
 GEE_ERR_HIP = -7
 GEE_ERR_UNSUPPORTED = -8
 GEE_ERR_WORKSPACE = -9
+GEE_ERR_SCRATCH = -10
 
 
 class GeeError(RuntimeError):
@@ -194,6 +195,32 @@ def gee_embed(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], l
             workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
         _check(lib.gee_embed_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z), sp,
                                 _ptr(workspace), workspace.numel(), _stream(stream)), "gee_embed")
+    return Z
+
+
+def gee_scratch_bytes() -> int:
+    """Size of the library's fixed scratch (the most workspace gee_embed_noalloc can use)."""
+    return int(_lib.load().gee_scratch_bytes())
+
+
+def gee_embed_noalloc(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], labels: torch.Tensor,
+                      K: int, flags: int, Z: torch.Tensor, stream=None) -> torch.Tensor:
+    """gee_embed into a caller's Z with the library's fixed scratch as workspace: nothing is
+    allocated (neither by the library nor here). Calls overlapping on one device race."""
+    labels = _dev(labels, torch.int32, "labels")
+    dev = labels.device
+    src = _dev(src, torch.int32, "src", dev)
+    dst = _dev(dst, torch.int32, "dst", dev)
+    w = _dev(w, torch.float32, "w", dev)
+    _dev(Z, torch.float32, "Z", dev)
+    E = src.numel()
+    N = labels.numel()
+    if dst.numel() != E or (w is not None and w.numel() != E):
+        raise ValueError("src, dst and w must have the same length")
+    if Z.numel() != N * K:
+        raise ValueError("Z must hold N * K floats")
+    _check(_lib.load().gee_embed_noalloc(_ptr(src), _ptr(dst), _ptr(w), E, N, _ptr(labels), K, flags, _ptr(Z),
+                                         _stream(stream)), "gee_embed_noalloc")
     return Z
 
 
