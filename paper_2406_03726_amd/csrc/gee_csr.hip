@@ -21,7 +21,9 @@
 //
 // With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
 //
-// Every partition pass works on tiles of kPartTile entries: the tile's entries are ranked
+// Tiles are numbered so that each XCD takes one contiguous range of them (xcd_order): the
+// runs that neighbouring tiles write end and start in the same cache lines, which one L2
+// then merges. Every partition pass works on tiles of kPartTile entries: the tile's entries are ranked
 // by digit (stable) and staged in LDS in digit order, then written out so that
 // consecutive threads write consecutive addresses of each digit's run; no pass writes
 // scattered single words. Stable ranks never use global atomics: each wavefront owns a
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift
     }
     for (int i = threadIdx.x; i < 256; i += kThreads) hist[i] = 0;
     __syncthreads();
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_order(blockIdx.x, T);
     const int wv = threadIdx.x >> 6;
     bool badi = false, badw = false;
     Quarter<false> q;
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
                                                       int *__restrict__ bstart, int *__restrict__ meta) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_order(blockIdx.x, T);
     bool badi = false, badw = false;
     Quarter<true> q;
     load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
                                                    float *__restrict__ oval) {
     __shared__ PartLds<uint16_t> L;
     int d, jt, ntd;
-    if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
+    if (!b_tile(tile_off, D, (int)xcd_order(blockIdx.x, tile_off[D]), d, jt, ntd)) return;
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const int ND = 1 << dbits;
     const int s0 = seg_start[d];

@@ -128,6 +128,26 @@ __device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total) {
     return base + x - v;
 }
 
+// Workgroups of a launch are dealt to the 8 XCDs in turn (workgroup i runs on XCD i mod 8),
+// and every XCD has an L2 of its own. xcd_order(i, n) renumbers the first n workgroups so
+// that each XCD takes one contiguous range of tiles, in order: neighbouring tiles, whose
+// output runs end and start inside the same cache lines, then meet in one L2, which merges
+// those partial lines before they are written back. Workgroups i >= n keep their number.
+#ifndef GEE_XCD_REMAP
+#define GEE_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_order(int64_t i, int64_t n) {
+#if GEE_XCD_REMAP
+    if (i >= n) return i;
+    const int64_t x = i % kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + i / kXcds;
+#else
+    (void)n;
+    return i;
+#endif
+}
+
 __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     if (status) atomicOr(status, bit);
 }
