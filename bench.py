@@ -84,6 +84,99 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
     return 0
 
 
+# Bytes each step of the path must move at minimum, from its definition (inputs read once,
+# outputs written once), independent of this library's layouts: the edge list, the CSR of
+# Section 3 (row_ptr, col, val), labels, the per-node coefficients and Z.
+STEPS = ("a1", "a2", "a3", "a4_a6", "embed", "e2e")
+
+
+def step_bytes(step, E, N, K, M, weighted):
+    """a1 class counts; a2 edge list -> CSR; a3 degrees from the CSR; a4_a6 rescale, class
+    scatter and correlation from the CSR (row_ptr, col, val, labels, gathered c, Z); embed =
+    a3 + a4_a6; e2e = the whole call's minimum (edge list and labels in, Z out)."""
+    wv = 4 if weighted else 0
+    if step == "a1":
+        return 4 * N + 8 * K
+    if step == "a2":
+        return (8 + wv) * E + 4 * (N + 1) + (4 + wv) * M
+    if step == "a3":
+        return 4 * (N + 1) + wv * M + 4 * N
+    if step == "a4_a6":
+        return 4 * (N + 1) + (4 + wv) * M + 4 * N + 4 * N + 4 * N * K
+    if step == "embed":
+        return step_bytes("a3", E, N, K, M, weighted) + step_bytes("a4_a6", E, N, K, M, weighted)
+    if step == "e2e":
+        return (8 + wv) * E + 4 * N + 4 * N * K
+    raise ValueError(step)
+
+
+# Which step each kernel of the edge-list paths belongs to.
+KERNEL_STEP = {
+    "class_count_partial": "a1", "class_count_final": "a1",
+    "a_hist": "a2", "digit_scan": "a2", "a_scatter": "a2", "b_hist": "a2", "b_scan": "a2", "b_scatter": "a2",
+    "c_tiles": "a2", "c_hist": "a2", "c_scan": "a2", "c_scatter": "a2", "bucket_sort": "a2",
+    "bucket_part_count": "a2", "bucket_part_fill": "a2", "graph_meta": "a2", "zero_steps": "a2",
+    "node_rows": "a3", "degree_rows": "a3", "degree_fixup": "a3", "node_coef": "a3",
+    "bucket_degree": "a3", "bucket_degree_fix": "a3",
+    "fill_empty": "a4_a6", "embed_rows": "a4_a6", "embed_fixup": "a4_a6",
+    "bucket_embed": "a4_a6", "bucket_embed_fix": "a4_a6",
+}
+
+
+def call_times(torch, fn, reps=30, warmup=5, cold=None):
+    """hipEvent time of fn() on the current stream: median, p10 and p90 over `reps` calls
+    after `warmup`. With cold (a device tensor of at least 512 MiB), the tensor is
+    overwritten before every call, outside the timed events, which evicts the inputs from
+    the 256 MB last-level cache (MALL)."""
+    import numpy as np
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for i in range(reps):
+        if cold is not None:
+            cold.fill_(float(i))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return {"median_ms": round(float(np.median(ts)), 5), "p10_ms": round(float(np.percentile(ts, 10)), 5),
+            "p90_ms": round(float(np.percentile(ts, 90)), 5), "reps": reps}
+
+
+def graph_times(torch, fn, reps=30, cold=None, out=None):
+    """The same call captured once in a hipGraph (torch.cuda.CUDAGraph) and replayed: what a
+    launch-bound caller pays per call once the host's launch work is gone. fn must launch on
+    the current stream. With `out` (a float tensor fn writes), one replay first checks that
+    the graph does write it. An error entry when the call cannot be captured."""
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()  # warm the call on the capture stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn()
+        torch.cuda.synchronize()
+        if out is not None:
+            out.fill_(float("nan"))
+            gr.replay()
+            torch.cuda.synchronize()
+            if bool(torch.isnan(out).any()):
+                return {"error": "the captured graph did not write the output"}
+        res = call_times(torch, gr.replay, reps=reps, warmup=3, cold=cold)
+        del gr
+        return res
+    except Exception as e:  # noqa: BLE001 - a missing variant must not cost the benchmark line
+        torch.cuda.synchronize()
+        return {"error": repr(e)[:200]}
+
+
 def sparse_leg(torch, np, gee, lib, dev, g, tens, Z_dense, steps, ev):
     """Z in sparse storage (gee_embed_sparse) on the benchmark workload: time per call against
     the dense call, stored entries and bytes, and the compaction kernels' own times."""
@@ -279,20 +372,31 @@ class HipEvents:
 
 
 def cpu_baseline(g, budget_s=12.0, max_reps=30):
-    """The FP64 oracle (single-threaded C edge-list loop) on this host's cores."""
+    """The FP64 oracle (single-threaded C edge-list loop) on one host core: the process is
+    pinned to the first core it may run on while the oracle (and then the scipy route) is
+    timed, and unpinned afterwards."""
     from oracle import oracle as orc
 
     orc.load()
-    reps, total = 0, 0.0
-    while reps < max_reps and (total < budget_s or reps < 1):
-        t0 = time.perf_counter()
-        orc.embed_graph(g)
-        total += time.perf_counter() - t0
-        reps += 1
-    out = {"value": g.E * reps / total, "unit": "edges/s", "cores": 1, "kind": "oracle",
-           "sample": f"the full workload edge list, {reps} repetition(s), {total:.1f} s of CPU time",
-           "host_cpu": _cpu_model(), "host_threads": os.cpu_count()}
-    out["scipy_route"] = scipy_baseline(g)
+    allowed = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    core = min(allowed) if allowed else None
+    if core is not None:
+        os.sched_setaffinity(0, {core})
+    try:
+        reps, total = 0, 0.0
+        while reps < max_reps and (total < budget_s or reps < 1):
+            t0 = time.perf_counter()
+            orc.embed_graph(g)
+            total += time.perf_counter() - t0
+            reps += 1
+        out = {"value": g.E * reps / total, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full workload edge list, {reps} repetition(s), {total:.1f} s of CPU time",
+               "pinned_core": core, "host_cpu": _cpu_model(), "host_threads": os.cpu_count(),
+               "host_threads_allowed": len(allowed) if allowed else None}
+        out["scipy_route"] = scipy_baseline(g)
+    finally:
+        if allowed:
+            os.sched_setaffinity(0, allowed)
     return out
 
 
@@ -396,24 +500,47 @@ def batched_leg(torch, np, gee, dev, table, procs, reps=5, G=512):
         return float(np.median(ts))
 
     plain_ms = timed(plain_loop)
+    # the same 512 plain calls captured in one hipGraph: the plain loop without its host
+    # launch work, which separates the gain of batching from the host's per-call cost
+    plain_graph = graph_times(torch, plain_loop, reps=reps, out=Zp[-1])
     plan = gee.BatchPlan(items)
     batch_ms = timed(lambda: plan.launch())
     torch.cuda.synchronize()
     same = all(torch.equal(it["Z"], z) for it, z in zip(items, Zp))
     plan.destroy()
+    # the same batch with the library's default schedules (what the tuned table gains)
+    dflt = [dict(it, sched=None, Z=torch.empty_like(it["Z"])) for it in items]
+    plan_d = gee.BatchPlan(dflt)
+    default_ms = timed(lambda: plan_d.launch())
+    plan_d.destroy()
+    del dflt
+    e2e = sum(step_bytes("e2e", it["src"].numel(), it["labels"].numel(), it["K"], 0, it["w"] is not None)
+              for it in items)
     return {"graphs": G, "edges": int(E_tot), "generation_s": round(gen_s, 1),
             "plain_loop_ms": round(plain_ms, 3), "batch_plan_ms": round(batch_ms, 3),
+            "plain_loop_graph_captured": plain_graph,
             "plain_edges_per_s": round(E_tot / (plain_ms * 1e-3), 1),
             "batch_edges_per_s": round(E_tot / (batch_ms * 1e-3), 1),
-            "speedup": round(plain_ms / batch_ms, 3), "bitwise_equal_to_plain": same,
+            "batch_plan_default_schedules_ms": round(default_ms, 3),
+            "tuned_gain_vs_default": round(default_ms / batch_ms, 3),
+            "speedup": round(plain_ms / batch_ms, 3),
+            "speedup_vs_captured_plain": round(plain_graph["median_ms"] / batch_ms, 3)
+            if "median_ms" in plain_graph else None,
+            "e2e_min_bytes": int(e2e), "batch_e2e_hbm_frac": round(e2e / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bitwise_equal_to_plain": same,
             "schedules": "autotuned table" if table and table.entries else "library defaults"}
 
 
-def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, n_req=400,
-                loads=(0.5, 0.9, 1.5), slots=4, budget_gb=32.0, max_batch=16, max_batch_edges=2_000_000,
-                max_inflight_edges=None):
+def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, n_req=10_000,
+                loads=(0.3, 0.5, 0.7, 0.9, 1.1, 1.5), slots=4, budget_gb=32.0, max_batch=16,
+                max_batch_edges=2_000_000, max_inflight_edges=None, n_check=1_000):
     """Poisson requests from a pool of serving-recipe graphs: the server (budget admission,
-    continuous batching over `slots` streams) against the plain per-request loop."""
+    continuous batching over `slots` streams) against the plain per-request loop, n_req
+    requests per load. Success criterion: with L* the plain loop's p99 at 0.5 x its
+    saturation rate, the server keeps p99 <= L* up to a higher load than the plain loop.
+    Every result of a separate untimed burst of n_check requests (all arriving at once, so
+    batches are as full and overlapped as they get) is compared bitwise with the plain
+    result of its graph."""
     from paper_2406_03726_amd.serve import GeeServer, GpuBackend, Request, run_plain, summarize
 
     t0 = time.perf_counter()
@@ -432,29 +559,74 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
                                  sched=g["sched"], workspace=ws, stream=stream)
         stream.synchronize()
 
-    # plain service time per pool graph -> saturation rate of the plain loop
-    svc = []
+    # plain service time per pool graph -> saturation rate of the plain loop; the second
+    # call's result is the graph's reference result
+    svc, refs = [], []
     for it in pool:
         r = Request(0, it, 0.0)
         embed_one(r)
         t1 = time.perf_counter()
         embed_one(r)
         svc.append(time.perf_counter() - t1)
+        refs.append(r.result)
     mu = 1.0 / float(np.mean(svc))
+    # the pool's plain service time with the library's default schedules instead
+    svc_d = []
+    for it in pool:
+        r = Request(0, dict(it, sched=None), 0.0)
+        embed_one(r)
+        t1 = time.perf_counter()
+        embed_one(r)
+        svc_d.append(time.perf_counter() - t1)
+    r = None
     rng = np.random.default_rng(20240603)
-    picks = rng.integers(0, pool_n, size=n_req)
     out = {"pool_graphs": pool_n, "pool_edges_mean": int(np.mean([it["src"].numel() for it in pool])),
            "generation_s": round(gen_s, 1), "requests_per_load": n_req, "slots": slots,
            "budget_bytes": int(budget_gb * 2 ** 30), "max_batch": max_batch, "max_batch_edges": max_batch_edges,
            "max_inflight_edges": max_inflight_edges,
-           "plain_saturation_req_per_s": round(mu, 1), "loads": []}
-    # warm-up of the served path too (the plain loop's was the service-time pass): every
-    # pool graph once through the server, so its streams' allocator caches hold their sizes
-    warm = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
-                     max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges)
-    warm.run_trace([Request(i, it, 0.0, E=int(it["src"].numel())) for i, it in enumerate(pool)])
+           "plain_saturation_req_per_s": round(mu, 1),
+           "pool_plain_ms_tuned": round(float(np.sum(svc)) * 1e3, 3),
+           "pool_plain_ms_default_schedules": round(float(np.sum(svc_d)) * 1e3, 3),
+           "schedules": "autotuned table" if table and table.entries else "library defaults", "loads": []}
+
+    def server():
+        return GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
+                         max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges,
+                         on_done=drop)
+
+    def drop(r):
+        r.result = None  # results are not kept through the timed runs
+
+    # warm-up of the served path (the plain loop's was the service-time pass): every pool
+    # graph once through the server, so its streams' allocator caches hold their sizes
+    server().run_trace([Request(i, it, 0.0, E=int(it["src"].numel())) for i, it in enumerate(pool)], busy_poll=True)
     torch.cuda.synchronize()
-    del warm
+
+    # equality pass: every served result against its graph's plain result
+    picks = rng.integers(0, pool_n, size=n_check)
+    bad = []
+    multi = []
+
+    def check(r):
+        if r.error is None and not torch.equal(r.result, refs[r.graph["_pool"]]):
+            bad.append(r.rid)
+        r.result = None
+
+    for i, it in enumerate(pool):
+        it["_pool"] = i
+    chk = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
+                    max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges, on_done=check)
+    chk.run_trace([Request(i, pool[int(p)], 0.0, E=int(pool[int(p)]["src"].numel())) for i, p in enumerate(picks)],
+                  busy_poll=True)
+    torch.cuda.synchronize()
+    multi = [len(b) for b in chk.launch_log]
+    out["equality_check"] = {"requests": n_check, "mismatches": len(bad), "batches": len(multi),
+                             "largest_batch": max(multi) if multi else 0,
+                             "batches_of_several": sum(1 for m in multi if m > 1),
+                             "peak_batches_in_flight": chk.peak_flights}
+    _progress(f"serving equality pass: {len(bad)} mismatches over {n_check} requests")
+
+    picks = rng.integers(0, pool_n, size=n_req)
     for frac in loads:
         lam = frac * mu
         arr = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
@@ -463,19 +635,33 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=32, e_max=20_000_000, 
             return [Request(i, pool[int(p)], float(a), E=int(pool[int(p)]["src"].numel()))
                     for i, (p, a) in enumerate(zip(picks, arr))]
 
-        plain = run_plain(mk(), embed_one)
-        srv = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
-                        max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges)
-        served = srv.run_trace(mk())
+        plain = run_plain(mk(), embed_one, on_done=drop, busy_poll=True)
+        srv = server()
+        served = srv.run_trace(mk(), busy_poll=True)
         torch.cuda.synchronize()
         sp, ss = summarize(plain), summarize(served)
-        same = all(torch.equal(a.result, b.result) for a, b in zip(plain[:16], served[:16]))
         out["loads"].append({"load_vs_plain_saturation": frac, "rate_req_per_s": round(lam, 1),
                              "plain": {k: round(v, 3) for k, v in sp.items()},
                              "served": {k: round(v, 3) for k, v in ss.items()},
                              "served_peak_bytes": srv.peak_in_use, "served_peak_batches": srv.peak_flights,
-                             "results_equal_alone_sample": same})
+                             "served_batches": len(srv.launch_log)})
+        _progress(f"serving load {frac}: plain p99 {sp['p99_ms']:.2f} ms, served p99 {ss['p99_ms']:.2f} ms")
         del plain, served
+    # L*: the plain loop's p99 at half its saturation rate
+    lstar = next((x["plain"]["p99_ms"] for x in out["loads"] if x["load_vs_plain_saturation"] == 0.5), None)
+    if lstar is not None:
+        def max_load(side):
+            ok = [x["load_vs_plain_saturation"] for x in out["loads"] if x[side]["p99_ms"] <= lstar]
+            return max(ok) if ok else None
+
+        pm, sm = max_load("plain"), max_load("served")
+        out["Lstar_ms"] = lstar
+        out["plain_max_load_within_Lstar"] = pm
+        out["served_max_load_within_Lstar"] = sm
+        out["served_p99_at_or_below_plain_every_load"] = all(x["served"]["p99_ms"] <= x["plain"]["p99_ms"]
+                                                             for x in out["loads"])
+        out["success"] = bool(sm is not None and (pm is None or sm > pm))
+    del refs, ws
     return out
 
 
@@ -498,14 +684,94 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_path(kernel: str, workload: str) -> str:
-    return os.path.join(PROFILES, f"hbm_traffic_{kernel}_{workload}.md")
+def traffic_path(workload: str) -> str:
+    return os.path.join(PROFILES, f"hbm_traffic_gee_embed_{workload}.md")
 
 
-def read_traffic(kernel: str, workload: str):
-    """Bytes per launch of `kernel` from its committed counter summary, or None when absent
+# Counters of the two rocprofv3 --pmc passes (at most 4 TCC counters a pass). Bytes come
+# from request counts by size, so no calibration factor is needed: reads are the 32-, 64-
+# and 128-byte read requests the L2 sends to the fabric, writes the 32- and 64-byte write
+# requests; the DRAM-bound counts (in 32-byte units) are reported beside them.
+PMC_PASSES = (("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum"),
+              ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_DRAM_32B_sum",
+               "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"))
+
+
+def kernel_key(name: str) -> str:
+    """Hook name of a kernel from the name rocprofv3 prints (the partition passes' shared
+    segment kernels are pass B on the bucket path, pass C when they write the CSR)."""
+    base = name.split("(")[0].replace("void ", "").strip()
+    tmpl = base[base.index("<"):] if "<" in base else ""
+    base = base.split("<")[0].split("::")[-1]
+    if "copyBuffer" in base:
+        return "copy"
+    if base == "seg_hist":
+        return "b_hist"
+    if base == "seg_scan":
+        return "b_scan"
+    if base == "seg_scatter":
+        return "c_scatter" if "true" in tmpl else "b_scatter"
+    return base
+
+
+def _counter_means(csv_path: str):
+    """{kernel: {counter: mean value per dispatch}, ...} and {kernel: dispatches}."""
+    import csv
+
+    vals, disp = {}, {}
+    with open(csv_path) as f:
+        for r in csv.DictReader(f):
+            k = kernel_key(r["Kernel_Name"])
+            vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            disp.setdefault(k, set()).add(r.get("Dispatch_Id", r.get("Correlation_Id")))
+    means = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}
+    return means, {k: len(v) for k, v in disp.items()}
+
+
+def write_traffic(csv_a: str, csv_b: str, workload: str, commands: str) -> str:
+    """Turns the two counter passes over `bench.py --pmc-target` (a 1 GiB copy, then two
+    gee_embed calls) into the per-launch HBM bytes of every kernel of the call."""
+    ma, na = _counter_means(csv_a)
+    mb, _ = _counter_means(csv_b)
+    kernels = {}
+    for k in sorted(set(ma) & set(mb)):
+        a, b = ma[k], mb[k]
+        rd = 32 * a["TCC_EA0_RDREQ_32B_sum"] + 64 * a["TCC_EA0_RDREQ_64B_sum"] + 128 * a["TCC_EA0_RDREQ_128B_sum"]
+        wr = 32 * (b["TCC_EA0_WRREQ_sum"] - b["TCC_EA0_WRREQ_64B_sum"]) + 64 * b["TCC_EA0_WRREQ_64B_sum"]
+        kernels[k] = {"launches": na[k], "read_bytes": int(rd), "write_bytes": int(wr),
+                      "bytes": int(rd + wr), "dram_read_bytes": int(32 * b["TCC_EA0_RDREQ_DRAM_32B_sum"]),
+                      "dram_write_bytes": int(32 * b["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]),
+                      "read_requests": int(a["TCC_EA0_RDREQ_sum"]),
+                      "read_requests_by_size": [int(a["TCC_EA0_RDREQ_32B_sum"]), int(a["TCC_EA0_RDREQ_64B_sum"]),
+                                                int(a["TCC_EA0_RDREQ_128B_sum"])]}
+    copy = kernels.pop("copy", None)
+    known = set(KERNELS) | set(EDGE_KERNELS) | {"zs_count", "zs_write"}
+    kernels = {k: v for k, v in kernels.items() if k in known}  # the library's kernels only
+    out = {"workload": workload, "source_hash": source_hash(), "calib_bytes": CALIB_BYTES,
+           "copy_check": copy, "kernels": kernels}
+    path = traffic_path(workload)
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(path, "w") as f:
+        f.write(f"# HBM traffic of every kernel of one `gee_embed` call on `{workload}`\n\n")
+        f.write("Two rocprofv3 counter passes over the same command (a 1 GiB device-to-device copy, then two\n"
+                "calls). Bytes per launch from the L2's fabric requests by size: reads = 32/64/128-byte read\n"
+                "requests, writes = 32/64-byte write requests; the DRAM-bound counts (32-byte units) beside\n"
+                "them. The copy row checks the method: it should read and write about 1 GiB each.\n"
+                "Commands (from /tmp, TMPDIR=/tmp, on the MI355X box):\n\n")
+        f.write("```\n" + commands.strip() + "\n```\n\n")
+        f.write("| kernel | launches | read MB | write MB | DRAM read MB | DRAM write MB |\n|---|---|---|---|---|---|\n")
+        rows = ([("copy (check)", copy)] if copy else []) + sorted(kernels.items(), key=lambda kv: -kv[1]["bytes"])
+        for k, d in rows:
+            f.write(f"| `{k}` | {d['launches']} | {d['read_bytes'] / 1e6:.1f} | {d['write_bytes'] / 1e6:.1f} | "
+                    f"{d['dram_read_bytes'] / 1e6:.1f} | {d['dram_write_bytes'] / 1e6:.1f} |\n")
+        f.write("\n```json\n" + json.dumps(out, indent=1) + "\n```\n")
+    return path
+
+
+def read_traffic(workload: str):
+    """Per-kernel bytes per launch from the committed counter summary, or None when absent
     or taken from other sources than the current ones."""
-    path = traffic_path(kernel, workload)
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -516,50 +782,6 @@ def read_traffic(kernel: str, workload: str):
     if d.get("source_hash") != source_hash():
         return None
     return d
-
-
-def _counter_rows(csv_path: str, counter: str):
-    import csv
-
-    rows = []
-    with open(csv_path) as f:
-        for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter:
-                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
-    return rows
-
-
-def write_traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, commands: str) -> str:
-    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
-    per-launch HBM bytes of `kernel`, each counter scaled by what it reads for a plain
-    device-to-device copy of CALIB_BYTES in the same run."""
-    out = {"kernel": kernel, "workload": workload, "source_hash": source_hash(), "calib_bytes": CALIB_BYTES}
-    for counter, path, key in (("FETCH_SIZE", fetch_csv, "fetch"), ("WRITE_SIZE", write_csv, "write")):
-        rows = _counter_rows(path, counter)
-        copies = [v for n, v in rows if "copyBuffer" in n]
-        if not copies:
-            raise SystemExit(f"no copy dispatch in {path}")
-        calib_kib = sum(copies)  # the calibration copy may be split over dispatches; others are tiny
-        factor = (CALIB_BYTES / 1024.0) / calib_kib
-        mine = [v for n, v in rows if n.split("(")[0].replace("void ", "").split("<")[0].endswith(kernel)]
-        if not mine:
-            raise SystemExit(f"no {kernel} dispatch in {path}")
-        kib = sum(mine) / len(mine)
-        out[f"{key}_kib_per_launch"] = round(kib, 1)
-        out[f"{key}_calibration_factor"] = round(factor, 4)
-        out[f"{key}_bytes_per_launch"] = int(kib * 1024 * factor)
-        out[f"{key}_launches"] = len(mine)
-    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
-    path = traffic_path(kernel, workload)
-    os.makedirs(PROFILES, exist_ok=True)
-    with open(path, "w") as f:
-        f.write(f"# HBM traffic of `{kernel}` on `{workload}`\n\n")
-        f.write("Two rocprofv3 counter runs of the same command (FETCH_SIZE, then WRITE_SIZE; KiB per\n"
-                "dispatch), each scaled by what the counter reads for a 1 GiB device-to-device copy\n"
-                "made in the same run. Commands (from /tmp, TMPDIR=/tmp, on the MI355X box):\n\n")
-        f.write("```\n" + commands.strip() + "\n```\n\n")
-        f.write("```json\n" + json.dumps(out, indent=1) + "\n```\n")
-    return path
 
 
 def pmc_target(gee, torch, np):
@@ -580,6 +802,62 @@ def pmc_target(gee, torch, np):
     torch.cuda.synchronize()
 
 
+def config_leg(torch, np, gee, dev, name, cold, reps=30):
+    """One of the plain single-graph configurations (the 2,000-node SBM graph with the options
+    off and all on, the 10,000-node SBM graph): hipEvent times warm and cold, the call
+    captured in a hipGraph, edges/s and the HBM fractions of the whole call."""
+    g = make_workload(name)
+    t = lambda a, dt: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa
+    src, dst, w, lab = t(g.src, torch.int32), t(g.dst, torch.int32), t(g.w, torch.float32), t(g.labels, torch.int32)
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    E, N, K = g.E, g.N, g.K
+    Z = torch.empty((N, K), dtype=torch.float32, device=dev)
+    ws = torch.empty(gee.gee_embed_workspace_bytes(E, N, K, flags, w is not None), dtype=torch.uint8, device=dev)
+
+    def fn():
+        gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, workspace=ws, stream=torch.cuda.current_stream())
+
+    warm = call_times(torch, fn, reps=reps)
+    coldt = call_times(torch, fn, reps=reps, cold=cold)
+    graph = graph_times(torch, fn, reps=reps, out=Z)
+    rp, _, _ = gee.gee_build_csr(src, dst, w, N, flags)
+    torch.cuda.synchronize()
+    M = int(rp[-1].item())
+    e2e, emb = step_bytes("e2e", E, N, K, M, w is not None), step_bytes("embed", E, N, K, M, w is not None)
+    out = {"workload": g.name, "N": N, "E": E, "K": K, "M_csr_entries": M, "weighted": w is not None,
+           "options": "+".join(o for o, on in (("diag", g.diag), ("laplacian", g.lap), ("correlation", g.cor)) if on)
+           or "none", "warm": warm, "cold": coldt, "graph_captured": graph,
+           "edges_per_s": round(E / (warm["median_ms"] * 1e-3), 1),
+           "e2e_min_bytes": int(e2e), "embed_bytes": int(emb),
+           "e2e_hbm_frac_warm": round(e2e / (warm["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "e2e_hbm_frac_cold": round(e2e / (coldt["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del Z, ws, rp
+    return out
+
+
+def csr_build_leg(torch, np, gee, g, tens, M, cold, reps=30):
+    """gee_build_csr (the CSR of Section 3, bit-exact) on the benchmark workload."""
+    src, dst, w, lab = tens
+    flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
+    dev = src.device
+    N = g.N
+    rp = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(M, dtype=torch.int32, device=dev)
+    val = torch.empty(M, dtype=torch.float32, device=dev) if w is not None else None
+    ws = torch.empty(gee.gee_build_csr_workspace_bytes(g.E, N, flags), dtype=torch.uint8, device=dev)
+
+    def fn():
+        gee.gee_build_csr(src, dst, w, N, flags, row_ptr=rp, col=col, val=val, workspace=ws)
+
+    warm = call_times(torch, fn, reps=reps)
+    coldt = call_times(torch, fn, reps=reps, cold=cold)
+    b = step_bytes("a2", g.E, N, g.K, M, w is not None)
+    out = {"warm": warm, "cold": coldt, "edges_per_s": round(g.E / (warm["median_ms"] * 1e-3), 1),
+           "algorithmic_bytes": int(b), "hbm_frac_warm": round(b / (warm["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del rp, col, val, ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,21 +867,21 @@ def main():
                     choices=["powerlaw_10m", "sbm_dense", "sbm_small_all", "sbm_small_off"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--report", default=None, help="also write a detailed JSON report here")
-    ap.add_argument("--legs", default="original,sparse,batched,serving",
-                    help="legs to add to the line: original, sparse, batched, serving (comma list, or none)")
+    ap.add_argument("--legs", default="configs,csr,original,sparse,batched,serving",
+                    help="legs to add to the line: configs, csr, original, sparse, batched, serving "
+                         "(comma list, or none)")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1),
                     help="worker processes that draw the systems legs' graphs")
     ap.add_argument("--pmc-target", action="store_true",
                     help="run only what the rocprofv3 counter runs measure (a calibration copy and two steps)")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="host only: turn two counter CSVs into the committed traffic summary")
-    ap.add_argument("--traffic-kernel", default="bucket_sort")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("PASS1_CSV", "PASS2_CSV"),
+                    help="host only: turn the two counter passes into the committed traffic summary")
     ap.add_argument("--traffic-commands", default="")
     args = ap.parse_args()
 
     if args.write_traffic:
-        print(write_traffic(args.write_traffic[0], args.write_traffic[1], args.traffic_kernel,
-                            "chunglu_n600k_e10m_k50", args.traffic_commands))
+        print(write_traffic(args.write_traffic[0], args.write_traffic[1], "chunglu_n600k_e10m_k50",
+                            args.traffic_commands))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -637,13 +915,15 @@ def main():
     src, dst, w, lab = t(g.src, torch.int32), t(g.dst, torch.int32), t(g.w, torch.float32), t(g.labels, torch.int32)
     flags = gee.flags_of(g.diag, g.lap, g.cor, g.sym)
     E, N, K = g.E, g.N, g.K
+    weighted = w is not None
     Z = torch.empty((N, K), dtype=torch.float32, device=dev)
-    ws_bytes = gee.gee_embed_workspace_bytes(E, N, K, flags, w is not None)
+    ws_bytes = gee.gee_embed_workspace_bytes(E, N, K, flags, weighted)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
-        gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, workspace=ws, stream=stream)
+        # (on the stream current at the call, so that the captured variant records it)
+        gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, workspace=ws, stream=torch.cuda.current_stream())
 
     for _ in range(args.warmup):
         step()
@@ -670,7 +950,7 @@ def main():
         try:
             per_kernel[name] = ev.elapsed_ms(a, b)
         except RuntimeError:  # not launched for this workload
-            pass
+            ev.hip.hipGetLastError()  # (the failed query leaves its error for the next HIP call)
         ev.destroy(a)
         ev.destroy(b)
     dominant = max(per_kernel, key=per_kernel.get)
@@ -696,15 +976,57 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     value = E * args.steps / elapsed
     dom_avg_ms = float(np.mean(dom_ms))
-    alg = algorithmic_bytes(dominant, E, N, K, M, w is not None, n_empty)
+    # The dominant kernel is priced with the bytes of the step it carries out, from the
+    # step's definition (for the class-scatter kernels: row_ptr, col, val, labels, the
+    # gathered coefficients and Z), not with this library's own layout.
+    dstep = KERNEL_STEP.get(dominant)
+    alg = step_bytes(dstep, E, N, K, M, weighted) if dstep else algorithmic_bytes(dominant, E, N, K, M, weighted,
+                                                                                   n_empty)
+    layout = algorithmic_bytes(dominant, E, N, K, M, weighted, n_empty)
     achieved = alg / (dom_avg_ms * 1e-3) / 1e9
-    tr = read_traffic(dominant, g.name)
+    trf = read_traffic(g.name)
+    tk = trf["kernels"].get(dominant) if trf else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes_per_launch"] if tr else None,
-                "kernel": dominant, "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(dom_avg_ms, 5)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tk["bytes"] if tk else None,
+                "kernel": dominant, "step": dstep, "algorithmic_bytes_per_launch": int(alg),
+                "layout_bytes_per_launch": int(layout),
+                "layout_frac": round(layout / (dom_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "avg_launch_ms": round(dom_avg_ms, 5)}
     roofline["copy_ceiling_GBps"] = copy_ceiling(torch, dev)
-    if tr:
-        roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    if tk:
+        roofline["traffic_unit"] = "bytes per launch (L2 fabric read + write requests by size)"
+        roofline["traffic_read"] = tk["read_bytes"]
+        roofline["traffic_write"] = tk["write_bytes"]
+        roofline["traffic_over_algorithmic"] = round(tk["bytes"] / alg, 3)
+
+    # The whole call: hipEvent times warm and cold (a 512 MiB overwrite before each call
+    # evicts the last-level cache), the call captured in a hipGraph, the HBM fractions of
+    # its minimum bytes, and the counter bytes of its kernels over their summed durations.
+    cold = torch.empty((512 << 20) // 4, dtype=torch.float32, device=dev)
+    warm_t = call_times(torch, step)
+    cold_t = call_times(torch, step, cold=cold)
+    graph_t = graph_times(torch, step, out=Z)
+    e2e_min_bytes = step_bytes("e2e", E, N, K, M, weighted)
+    embed_bytes = step_bytes("embed", E, N, K, M, weighted)
+    embed_ms = sum(ms for k, ms in per_kernel.items() if KERNEL_STEP.get(k) in ("a3", "a4_a6"))
+    call = {"warm": warm_t, "cold": cold_t, "graph_captured": graph_t,
+            "e2e_min_bytes": int(e2e_min_bytes),
+            "e2e_hbm_frac_warm": round(e2e_min_bytes / (warm_t["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "e2e_hbm_frac_cold": round(e2e_min_bytes / (cold_t["median_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "embed_bytes": int(embed_bytes), "embed_kernels_ms": round(embed_ms, 5),
+            "embed_hbm_frac": round(embed_bytes / (embed_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if embed_ms else None}
+    if trf:
+        ks = [k for k in per_kernel if k in trf["kernels"]]
+        cb = sum(trf["kernels"][k]["bytes"] for k in ks)
+        cms = sum(per_kernel[k] for k in ks)
+        call.update({"counter_bytes": int(cb), "counter_kernels_ms": round(cms, 5),
+                     "call_counter_GBps": round(cb / (cms * 1e-3) / 1e9, 1),
+                     "call_counter_frac": round(cb / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "counter_kernels": len(ks), "kernels_without_counters": sorted(set(per_kernel) - set(ks))})
+    else:
+        call.update({"counter_bytes": None, "call_counter_GBps": None,
+                     "counter_note": "no counter summary for the current HIP sources"})
+    _progress("call timings done")
 
     # Steady state on a resident CSR (re-embedding, the serving/iterative form).
     Zr = torch.empty_like(Z)
@@ -720,13 +1042,17 @@ def main():
     nzm = Z != 0
     rel_diff = float(((Z - Zr).abs()[nzm] / Z.abs()[nzm]).max().item()) if bool(nzm.any()) else 0.0
     zeros_same = bool(torch.equal(Z == 0, Zr == 0))
+    del Zr, ws2
 
     kernels = {}
     for name, ms in per_kernel.items():
-        b = algorithmic_bytes(name, E, N, K, M, w is not None, n_empty)
-        kernels[name] = {"ms": round(ms, 5), "algorithmic_bytes": int(b),
-                         "GB_per_s": round(b / (ms * 1e-3) / 1e9, 1) if (b and ms > 0) else None}
-    e2e_min_bytes = (8 + (4 if w is not None else 0)) * E + 4 * N + 4 * N * K
+        b = algorithmic_bytes(name, E, N, K, M, weighted, n_empty)
+        kernels[name] = {"ms": round(ms, 5), "step": KERNEL_STEP.get(name), "layout_bytes": int(b),
+                         "layout_GB_per_s": round(b / (ms * 1e-3) / 1e9, 1) if (b and ms > 0) else None}
+        if trf and name in trf["kernels"]:
+            cb = trf["kernels"][name]["bytes"]
+            kernels[name]["counter_bytes"] = cb
+            kernels[name]["counter_GB_per_s"] = round(cb / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
 
     out = {
         "metric": METRIC,
@@ -744,8 +1070,9 @@ def main():
         "config": {"workload": g.name, "N": N, "E": E, "M_csr_entries": M, "K": K,
                    "options": "+".join(o for o, on in (("diag", g.diag), ("laplacian", g.lap),
                                                        ("correlation", g.cor)) if on) or "none",
-                   "weighted": w is not None, "symmetrize": g.sym, "schedule": gee.gee_default_schedule(E, N, K, flags)},
+                   "weighted": weighted, "symmetrize": g.sym, "schedule": gee.gee_default_schedule(E, N, K, flags)},
         "roofline": roofline,
+        "call": call,
         "e2e_hbm_frac_min_bytes": round(e2e_min_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": kernels,
         "resident_csr_embed": {"ms_per_call": round(resident_ms, 5),
@@ -754,6 +1081,15 @@ def main():
                                "same_zero_entries_as_edge_list_path": zeros_same},
     }
     legs = [x for x in args.legs.split(",") if x and x != "none"]
+    if "csr" in legs:
+        out["csr_build"] = csr_build_leg(torch, np, gee, g, (src, dst, w, lab), M, cold)
+        _progress("CSR-build leg done")
+    del rp, col, val
+    if "configs" in legs:
+        out["configs"] = {nm: config_leg(torch, np, gee, dev, nm, cold)
+                          for nm in ("sbm_small_off", "sbm_small_all", "sbm_dense")}
+        torch.cuda.empty_cache()
+        _progress("configs leg done")
     if "original" in legs:
         out["original_gee_form"] = original_leg(torch, np, gee, lib, dev, g, (src, dst, w, lab), Z, args.steps, ev)
         _progress("original-form leg done")
@@ -762,12 +1098,12 @@ def main():
         out["sparse_z"] = sparse_leg(torch, np, gee, lib, dev, g, (src, dst, w, lab), Z, args.steps, ev)
         torch.cuda.empty_cache()
         _progress("sparse-Z leg done")
-    legs = [x for x in legs if x not in ("original", "sparse")]
+    del cold
+    legs = [x for x in legs if x in ("batched", "serving")]
     if legs:
         from paper_2406_03726_amd.autotune import ScheduleTable
 
         table = ScheduleTable.load()
-        del Zr, ws2
         if "batched" in legs:
             out["batched"] = batched_leg(torch, np, gee, dev, table, args.procs)
             _progress("batched leg done")

@@ -34,42 +34,84 @@ def test_algorithmic_bytes_of_the_10m_edge_workload():
     assert bench.algorithmic_bytes("no_such_kernel", E, N, K, M, True, 0) == 0
 
 
-def _counter_csv(path, counter, rows):
+def test_step_bytes_follow_the_definitions():
+    E, N, K, M = 10_000_000, 600_000, 50, 20_000_000
+    # a4-a6 from a CSR: row_ptr + col + val + labels + gathered c + Z
+    assert bench.step_bytes("a4_a6", E, N, K, M, True) == 4 * (N + 1) + 8 * M + 4 * N + 4 * N + 4 * N * K
+    assert round(bench.step_bytes("a4_a6", E, N, K, M, True) / 1e6, 1) == 287.2
+    # degrees: row_ptr + val in, s out; embed = degrees + a4-a6 (372 MB on this workload)
+    assert round(bench.step_bytes("a3", E, N, K, M, True) / 1e6, 1) == 84.8
+    assert round(bench.step_bytes("embed", E, N, K, M, True) / 1e6) == 372
+    # the whole call's minimum: edge list + labels in, Z out
+    assert bench.step_bytes("e2e", E, N, K, M, True) == 12 * E + 4 * N + 4 * N * K
+    assert bench.step_bytes("e2e", E, N, K, M, False) == 8 * E + 4 * N + 4 * N * K
+    assert bench.KERNEL_STEP["bucket_embed"] == "a4_a6" and bench.KERNEL_STEP["bucket_degree"] == "a3"
+
+
+def _counter_csv(path, rows):
     with open(path, "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
         w.writeheader()
-        for i, (name, v) in enumerate(rows):
-            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+        for i, (disp, name, counter, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
 
 
-def test_traffic_calibration(tmp_path, monkeypatch):
+def test_traffic_from_request_counts(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path / "profiles"))
-    gib_kib = (1 << 30) / 1024.0
-    fetch, write = tmp_path / "f.csv", tmp_path / "w.csv"
-    # the counter reads half of the copied bytes on fetch, all of them on write
-    _counter_csv(fetch, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", gib_kib / 2),
-                                       ("void gee::bucket_embed<unsigned short, true>(...)", 1000.0),
-                                       ("void gee::bucket_embed<unsigned short, true>(...)", 3000.0),
-                                       ("gee::bucket_embed_fix(...)", 99999.0)])
-    _counter_csv(write, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", gib_kib),
-                                       ("void gee::bucket_embed<unsigned short, true>(...)", 500.0),
-                                       ("void gee::bucket_embed<unsigned short, true>(...)", 500.0)])
-    path = bench.write_traffic(str(fetch), str(write), "bucket_embed", "wl", "cmd")
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    emb = "void gee::bucket_embed<unsigned short, true>(gee::Batch, ...)"
+    seg = "void gee::seg_scatter<unsigned short, false>(...)"
+    rows_a, rows_b = [], []
+    # a 1 GiB copy: 2^23 read requests of 128 bytes, 2^24 write requests of 64 bytes
+    for c, v in (("TCC_EA0_RDREQ_32B_sum", 0), ("TCC_EA0_RDREQ_64B_sum", 0), ("TCC_EA0_RDREQ_128B_sum", 1 << 23),
+                 ("TCC_EA0_RDREQ_sum", 1 << 23)):
+        rows_a.append((1, "__amd_rocclr_copyBuffer", c, v))
+    for c, v in (("TCC_EA0_WRREQ_sum", 1 << 24), ("TCC_EA0_WRREQ_64B_sum", 1 << 24),
+                 ("TCC_EA0_RDREQ_DRAM_32B_sum", 1 << 25), ("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 1 << 25)):
+        rows_b.append((1, "__amd_rocclr_copyBuffer", c, v))
+    # two launches of bucket_embed (per-launch means), one of pass B's segment scatter
+    for disp, scale in ((2, 1), (3, 3)):
+        for c, v in (("TCC_EA0_RDREQ_32B_sum", 10), ("TCC_EA0_RDREQ_64B_sum", 20), ("TCC_EA0_RDREQ_128B_sum", 30),
+                     ("TCC_EA0_RDREQ_sum", 60)):
+            rows_a.append((disp, emb, c, v * scale))
+        for c, v in (("TCC_EA0_WRREQ_sum", 50), ("TCC_EA0_WRREQ_64B_sum", 40), ("TCC_EA0_RDREQ_DRAM_32B_sum", 7),
+                     ("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 9)):
+            rows_b.append((disp, emb, c, v * scale))
+    for c in ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum"):
+        rows_a.append((4, seg, c, 1))
+    for c in ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_DRAM_32B_sum",
+              "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"):
+        rows_b.append((4, seg, c, 1))
+    _counter_csv(a, rows_a)
+    _counter_csv(b, rows_b)
+    path = bench.write_traffic(str(a), str(b), "wl", "cmd")
     assert path.startswith(str(tmp_path))
-    d = bench.read_traffic("bucket_embed", "wl")
-    assert d["fetch_launches"] == 2 and d["write_launches"] == 2  # bucket_embed_fix is another kernel
-    assert d["fetch_calibration_factor"] == pytest.approx(2.0)
-    assert d["fetch_bytes_per_launch"] == 2000 * 1024 * 2
-    assert d["write_bytes_per_launch"] == 500 * 1024
-    assert d["bytes_per_launch"] == d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+    d = bench.read_traffic("wl")
+    assert d["copy_check"]["read_bytes"] == 1 << 30 and d["copy_check"]["write_bytes"] == 1 << 30
+    k = d["kernels"]["bucket_embed"]
+    assert k["launches"] == 2
+    # means of the two launches: 20 x 32 + 40 x 64 + 60 x 128 read; 40 x 64 + 20 x 32 written
+    assert k["read_bytes"] == 20 * 32 + 40 * 64 + 60 * 128
+    assert k["write_bytes"] == 80 * 64 + 20 * 32
+    assert k["bytes"] == k["read_bytes"] + k["write_bytes"]
+    assert k["dram_read_bytes"] == 14 * 32 and k["dram_write_bytes"] == 18 * 32
+    assert "b_scatter" in d["kernels"] and "seg_scatter" not in d["kernels"]
     # figures taken from other sources do not count
     monkeypatch.setattr(bench, "source_hash", lambda: "0000000000000000")
-    assert bench.read_traffic("bucket_embed", "wl") is None
+    assert bench.read_traffic("wl") is None
+
+
+def test_kernel_names_map_to_the_hook_names():
+    assert bench.kernel_key("void gee::a_scatter<unsigned short>(gee::Batch, long)") == "a_scatter"
+    assert bench.kernel_key("void gee::seg_scatter<unsigned short, true>(...)") == "c_scatter"
+    assert bench.kernel_key("gee::seg_hist(...)") == "b_hist"
+    assert bench.kernel_key("__amd_rocclr_copyBuffer") == "copy"
 
 
 def test_committed_traffic_is_at_least_the_algorithmic_bytes():
-    d = bench.read_traffic("bucket_embed", "chunglu_n600k_e10m_k50")
+    d = bench.read_traffic("chunglu_n600k_e10m_k50")
     if d is None:
         pytest.skip("the committed counter summary was taken from other HIP sources")
-    assert d["bytes_per_launch"] > bench.algorithmic_bytes("bucket_embed", 10_000_000, 600_000, 50, 20_000_000,
-                                                            True, 0)
+    assert d["copy_check"]["read_bytes"] == pytest.approx(1 << 30, rel=0.01)
+    emb = d["kernels"]["bucket_embed"]["bytes"]
+    assert emb > bench.step_bytes("a4_a6", 10_000_000, 600_000, 50, 20_000_000, True)
