@@ -112,8 +112,10 @@ typedef struct {
     int32_t tile_entries;   /* entries per workgroup tile of the CSR partition passes; this
                                library supports only 4096 (0 = default) */
     int32_t bucket_rows_log2; /* rows per CSR sort bucket = 2^this (0 = automatic, else 1..12;
-                                 raised to what keeps the bucket count <= 65536); the bucket
-                                 path fixes its own */
+                                 raised to what keeps the bucket count <= 65536); on the
+                                 bucket path 5 or 6 chooses 32- or 64-row buckets (raised to
+                                 64 when 32 would need more than 65536), other values leave
+                                 the choice to the class-count rule */
 } gee_schedule;
 /* Paths. gee_embed, gee_embed_ws and batches take the bucket path whenever the launch's
    rows fit 65536 buckets of 64 rows (2^22 rows, batch graphs each rounded up to the
@@ -138,6 +140,13 @@ int gee_init(void);
    (GEE_DATA_*) of `stream` on the current device and waits for `stream` to reach that point.
    Bits raised by calls on other streams are not seen and not cleared. */
 int gee_get_data_errors(void *stream, uint32_t *bits);
+/* The same take without waiting: enqueues on `stream` a kernel that moves the stream's
+   data-error bits into *dst and clears the word. dst must be device-writable at the same
+   address (device memory, or pinned host memory from hipHostMalloc); *dst holds the bits of
+   the calls enqueued on `stream` before this one once the stream has passed this point
+   (for example once an event recorded after it has completed). For serving loops that
+   read the bits of each batch without a stream synchronization. */
+int gee_take_data_errors_async(void *stream, uint32_t *dst);
 
 /* Profiling hook (for benchmarks and tests). From this call on, every launch of the named
    kernel records hipEvent `start_event` on its stream right before the launch and
@@ -309,8 +318,9 @@ int gee_embed_atomic_ws(const int32_t *src, const int32_t *dst, const float *w, 
  * schedule. Every Z of a batch is bitwise identical to that graph's gee_embed_ws with
  * the same schedule (its schedule is chosen from its own sizes, never from the batch).
  *   src, dst, w, E, N, labels, K, flags, Z : as for gee_embed, per graph
- *   sched : zero fields take the graph's defaults; waves_per_block and
- *           bucket_rows_log2 are taken from graph 0 for the whole batch
+ *   sched : zero fields take the graph's defaults; waves_per_block and the CSR path's
+ *           bucket_rows_log2 are taken from graph 0 for the whole batch (the bucket
+ *           path's 32/64-row choice is per graph)
  * Limits: at most 2^20 graphs, 2^28 nodes and 2^31 - 2^16 CSR entries in total; each
  * graph within the single-graph limits. */
 typedef struct {
@@ -335,12 +345,32 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
 /* Batch plan: allocates its workspace (hipMalloc) and uploads the graph table once, then
  * captures the whole launch sequence in a hipGraph. Each gee_batch_plan_launch replays it
  * on `stream` (one graph launch) and recomputes every Z from the current contents of the
- * input arrays named at creation. The arrays must stay allocated while the plan exists;
+ * input arrays named at creation (or at the last gee_batch_plan_update). The arrays must
+ * stay allocated while the plan holds them;
  * launches of one plan must not overlap (they share the workspace). Create and destroy
  * on the device the arrays live on. Data errors found by a launch are reported on the
  * launch's stream (gee_get_data_errors). */
 typedef struct gee_batch_plan gee_batch_plan;
 int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **plan);
+/* As gee_batch_plan_create, with a workspace of at least min_workspace_bytes (room for
+ * later, larger graph sets given to gee_batch_plan_update); 0 sizes it for `graphs`. */
+int gee_batch_plan_create_ws(const gee_graph *graphs, int32_t G, size_t min_workspace_bytes,
+                             gee_batch_plan **plan);
+/* Bytes of the plan's workspace (what gee_embed_batch_workspace_bytes of a new graph set
+ * may be at most for gee_batch_plan_update); 0 for NULL. */
+size_t gee_batch_plan_workspace_bytes(const gee_batch_plan *plan);
+/* Replaces the plan's graphs with `graphs` (any sizes, classes, options and schedules
+ * within the batch limits) without allocating: the new tables are written into the plan's
+ * workspace (completed before returning) and the launch sequence is captured again; the
+ * executable graph takes the new kernel arguments in place when the sequence has the same
+ * kernels (hipGraphExecUpdate), else it is instantiated again. Every later launch embeds
+ * the new graphs, with Z bitwise equal to gee_embed_batch_ws on them. The caller must not
+ * update a plan while a launch of it may still run (synchronize its stream first).
+ * Returns GEE_ERR_WORKSPACE, leaving the plan unchanged, when the new set needs more than
+ * gee_batch_plan_workspace_bytes; argument errors also leave it unchanged. After
+ * GEE_ERR_HIP or GEE_ERR_OOM the plan cannot be launched any more and must be destroyed.
+ * Call on the device the plan was created on. */
+int gee_batch_plan_update(gee_batch_plan *plan, const gee_graph *graphs, int32_t G);
 int gee_batch_plan_launch(gee_batch_plan *plan, void *stream);
 int gee_batch_plan_destroy(gee_batch_plan *plan);
 

@@ -13,6 +13,7 @@ from .gee import (  # noqa: F401
     GEE_DATA_LABEL,
     GEE_DATA_WEIGHT,
     GEE_DIAG,
+    GEE_ERR_WORKSPACE,
     GEE_DIRECTED_DEGREES,
     GEE_LAPLACIAN,
     GEE_NO_VALIDATE,
@@ -21,6 +22,7 @@ from .gee import (  # noqa: F401
     flags_of,
     gee_abi_version,
     gee_build_csr,
+    gee_build_csr_workspace_bytes,
     gee_class_counts,
     gee_csr_capacity,
     gee_default_schedule,
@@ -37,6 +39,7 @@ from .gee import (  # noqa: F401
     gee_embed_noalloc,
     gee_scratch_bytes,
     gee_get_data_errors,
+    gee_take_data_errors_async,
     gee_init,
     schedule,
 )

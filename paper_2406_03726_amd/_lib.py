@@ -37,6 +37,7 @@ SYMBOLS = {
     "gee_init": (ctypes.c_int, []),
     "gee_profile_kernel": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p]),
     "gee_get_data_errors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "gee_take_data_errors_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gee_default_schedule": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_uint32, ctypes.POINTER(GeeSchedule)]),
     "gee_class_counts": (ctypes.c_int, [c_i32p, ctypes.c_int32, ctypes.c_int32, c_i32p,
@@ -90,6 +91,10 @@ SYMBOLS = {
                                           ctypes.c_size_t, ctypes.c_void_p]),
     "gee_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(GeeGraph), ctypes.c_int32,
                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "gee_batch_plan_create_ws": (ctypes.c_int, [ctypes.POINTER(GeeGraph), ctypes.c_int32, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_void_p)]),
+    "gee_batch_plan_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "gee_batch_plan_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(GeeGraph), ctypes.c_int32]),
     "gee_batch_plan_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gee_batch_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }

@@ -117,6 +117,7 @@ int stream_status(hipStream_t stream, unsigned **out) {
 }
 
 __global__ void status_take(unsigned *word) { word[1] = atomicExch(word, 0u); }
+__global__ void status_take_to(unsigned *word, unsigned *dst) { *dst = atomicExch(word, 0u); }
 __global__ void status_fold(unsigned *from, unsigned *to) {
     const unsigned v = atomicExch(from, 0u);
     if (v) atomicOr(to, v);
@@ -175,10 +176,15 @@ int default_wave_entries(int64_t Mcap) { return Mcap >= (1 << 20) ? 1024 : 512; 
 #ifndef GEE_BUCKET_SB_MIN
 #define GEE_BUCKET_SB_MIN 5
 #endif
-int preferred_bucket_sb(int K) { return ring_stride(K) <= 64 ? 6 : GEE_BUCKET_SB_MIN; }
+// A schedule's bucket_rows_log2 of 5 or 6 chooses the graph's bucket size on this path
+// (32 or 64 rows); other values leave it to the class-count rule.
+int preferred_bucket_sb(const GraphIn &x) {
+    if (x.sc.bucket_rows_log2 == 5 || x.sc.bucket_rows_log2 == 6) return x.sc.bucket_rows_log2;
+    return ring_stride(x.K) <= 64 ? 6 : GEE_BUCKET_SB_MIN;
+}
 int bucket_path_sb(const GraphIn *gs, int G) {
     int sb0 = 6;
-    for (int g = 0; g < G; ++g) sb0 = preferred_bucket_sb(gs[g].K) < sb0 ? preferred_bucket_sb(gs[g].K) : sb0;
+    for (int g = 0; g < G; ++g) sb0 = preferred_bucket_sb(gs[g]) < sb0 ? preferred_bucket_sb(gs[g]) : sb0;
     for (int sb = sb0; sb <= 6; ++sb) {
         int64_t n = 0;
         for (int g = 0; g < G; ++g) n = ((n + (1 << sb) - 1) >> sb << sb) + gs[g].N;
@@ -573,7 +579,7 @@ int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t 
         // graphs that need the transposed pass (in-degrees) form chunks of their own
         for (int io = 0; io < 2; ++io) {
             for (const GraphIn &x : gs) {
-                if (preferred_bucket_sb(x.K) != sbp || (int)in_degree_pass(x.flags) != io) continue;
+                if (preferred_bucket_sb(x) != sbp || (int)in_degree_pass(x.flags) != io) continue;
                 const int64_t n = x.N;
                 if (n > cap) {
                     flush();
@@ -715,6 +721,16 @@ int gee_get_data_errors(void *stream, uint32_t *bits) {
     if (e != hipSuccess) return hip_status(e);
     *bits = h;
     return GEE_OK;
+}
+
+int gee_take_data_errors_async(void *stream, uint32_t *dst) {
+    if (!dst) return GEE_ERR_ARG;
+    unsigned *st = nullptr;
+    int rc = stream_status(as_stream(stream), &st);
+    if (rc) return rc;
+    hipStream_t s = launch_stream(stream);
+    hipLaunchKernelGGL(status_take_to, dim3(1), dim3(1), 0, s, st, dst);
+    return hip_status(hipGetLastError());
 }
 
 size_t gee_scratch_bytes(void) { return kScratchBytes; }
@@ -1047,7 +1063,64 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
     return hip_status(e);
 }
 
-int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **out) {
+}  // extern "C"
+
+namespace {
+
+// Lays the chunks of `graphs` out in the plan's workspace (after its data-error word),
+// uploads their tables (completed before returning) and captures their launch sequence in
+// a new hipGraph. The plan's workspace must hold them (GEE_ERR_WORKSPACE otherwise, with
+// nothing changed).
+int plan_capture(gee_batch_plan *pl, const gee_graph *graphs, int32_t G, hipGraph_t *out) {
+    *out = nullptr;
+    std::vector<GraphIn> gs;
+    int rc = graphs_from_api(graphs, G, gs);
+    if (rc) return rc;
+    std::vector<Chunk> ch;
+    size_t total = 0;
+    if ((rc = plan_chunks(gs, ch, total))) return rc;
+    int64_t rows = 0;
+    for (const Chunk &c : ch) rows += c.p.Ntot;
+    if (rows == 0) return GEE_ERR_ARG;
+    if (kAlign + total > pl->ws_bytes) return GEE_ERR_WORKSPACE;
+    unsigned *st = pl->status;
+    char *wsb = static_cast<char *>(pl->ws) + kAlign;
+    // every chunk has its own workspace region, so all tables are written before capture
+    std::vector<Batch> bs(ch.size()), bTs(ch.size());
+    std::vector<Work> wks(ch.size());
+    (void)hipGetLastError();  // see launch_stream
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ch.size() && e == hipSuccess; ++i) {
+        if (ch[i].p.Ntot == 0) continue;
+        carve(ch[i].p, kEmbedParts, wsb + ch[i].off, wks[i]);
+        e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i], &bTs[i]);
+    }
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        t_capturing = true;
+        hipError_t e1 = hipSuccess;
+        for (size_t i = 0; i < ch.size() && e1 == hipSuccess; ++i)
+            if (ch[i].p.Ntot > 0) e1 = enqueue_embed(bs[i], bTs[i], ch[i].p, wks[i], st, cs);
+        t_capturing = false;
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        e = e1 != hipSuccess ? e1 : e2;
+        if (e == hipSuccess) *out = g;
+        else if (g) (void)hipGraphDestroy(g);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e == hipSuccess) pl->G = G;
+    return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gee_batch_plan_create_ws(const gee_graph *graphs, int32_t G, size_t min_workspace_bytes,
+                             gee_batch_plan **out) {
     if (!out) return GEE_ERR_ARG;
     *out = nullptr;
     std::vector<GraphIn> gs;
@@ -1066,46 +1139,72 @@ int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **o
     }
     gee_batch_plan *pl = new (std::nothrow) gee_batch_plan();
     if (!pl) return GEE_ERR_OOM;
-    pl->G = G;
     (void)hipGetDevice(&pl->device);
     // the plan's own data-error word (first kAlign bytes), then the chunks' workspaces
-    pl->ws_bytes = kAlign + total;
-    hipStream_t cs = nullptr;
+    pl->ws_bytes = kAlign + (total > min_workspace_bytes ? total : min_workspace_bytes);
     hipError_t e = hipMalloc(&pl->ws, pl->ws_bytes);
-    unsigned *st = static_cast<unsigned *>(pl->ws);
-    pl->status = st;
-    char *wsb = static_cast<char *>(pl->ws) + kAlign;
-    // every chunk has its own workspace region, so all tables are written before capture
-    std::vector<Batch> bs(ch.size()), bTs(ch.size());
-    std::vector<Work> wks(ch.size());
-    (void)hipGetLastError();  // see launch_stream
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(status_take, dim3(1), dim3(1), 0, nullptr, st);  // word = 0
-        e = hipGetLastError();
-    }
-    for (size_t i = 0; i < ch.size() && e == hipSuccess; ++i) {
-        if (ch[i].p.Ntot == 0) continue;
-        carve(ch[i].p, kEmbedParts, wsb + ch[i].off, wks[i]);
-        e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i], &bTs[i]);
-    }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        t_capturing = true;
-        hipError_t e1 = hipSuccess;
-        for (size_t i = 0; i < ch.size() && e1 == hipSuccess; ++i)
-            if (ch[i].p.Ntot > 0) e1 = enqueue_embed(bs[i], bTs[i], ch[i].p, wks[i], st, cs);
-        t_capturing = false;
-        hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
-        e = e1 != hipSuccess ? e1 : e2;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
-    if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         gee_batch_plan_destroy(pl);
         return hip_status(e);
     }
+    pl->status = static_cast<unsigned *>(pl->ws);
+    (void)hipGetLastError();  // see launch_stream
+    hipLaunchKernelGGL(status_take, dim3(1), dim3(1), 0, nullptr, pl->status);  // word = 0
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        gee_batch_plan_destroy(pl);
+        return hip_status(e);
+    }
+    hipGraph_t g = nullptr;
+    rc = plan_capture(pl, graphs, G, &g);
+    if (rc == GEE_OK) {
+        pl->graph = g;
+        rc = hip_status(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+    }
+    if (rc != GEE_OK) {
+        gee_batch_plan_destroy(pl);
+        return rc;
+    }
     *out = pl;
+    return GEE_OK;
+}
+
+int gee_batch_plan_create(const gee_graph *graphs, int32_t G, gee_batch_plan **out) {
+    return gee_batch_plan_create_ws(graphs, G, 0, out);
+}
+
+size_t gee_batch_plan_workspace_bytes(const gee_batch_plan *plan) { return plan ? plan->ws_bytes - kAlign : 0; }
+
+int gee_batch_plan_update(gee_batch_plan *plan, const gee_graph *graphs, int32_t G) {
+    if (!plan || !plan->exec) return GEE_ERR_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return GEE_ERR_ARG;
+    hipGraph_t g = nullptr;
+    int rc = plan_capture(plan, graphs, G, &g);
+    if (rc == GEE_ERR_HIP || rc == GEE_ERR_OOM) {
+        // the tables in the workspace may be half rewritten: the plan cannot run any more
+        (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = nullptr;
+    }
+    if (rc != GEE_OK) return rc;
+    // same launch sequence (the same chunks, paths and kernels): the executable graph takes
+    // the new kernel arguments and grids in place; otherwise it is instantiated again
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    hipError_t e = hipGraphExecUpdate(plan->exec, g, &bad, &res);
+    if (e != hipSuccess || res != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();  // the failed in-place update is not the caller's error
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_status(e);
+        }
+        (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = x;
+    }
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->graph = g;
     return GEE_OK;
 }
 

@@ -114,6 +114,17 @@ def gee_get_data_errors(stream=None) -> int:
     return int(bits.value)
 
 
+def gee_take_data_errors_async(dst: torch.Tensor, stream=None) -> None:
+    """Enqueue the take of the stream's data-error bits into dst[0] (an int32 tensor in
+    device memory or pinned host memory); read dst once the stream has passed this point."""
+    if dst.dtype != torch.int32 or dst.numel() < 1:
+        raise ValueError("dst must hold an int32")
+    if not dst.is_cuda and not dst.is_pinned():
+        raise ValueError("dst must be device memory or pinned host memory")
+    _check(_lib.load().gee_take_data_errors_async(_stream(stream), ctypes.c_void_p(dst.data_ptr())),
+           "gee_take_data_errors_async")
+
+
 def gee_default_schedule(E: int, N: int, K: int, flags: int) -> dict:
     s = _lib.GeeSchedule()
     _check(_lib.load().gee_default_schedule(E, N, K, flags, ctypes.byref(s)), "gee_default_schedule")
@@ -138,7 +149,8 @@ def gee_csr_capacity(E: int, flags: int) -> int:
 
 def gee_build_csr(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], N: int, flags: int,
                   row_ptr: Optional[torch.Tensor] = None, col: Optional[torch.Tensor] = None,
-                  val: Optional[torch.Tensor] = None, sched=None, stream=None):
+                  val: Optional[torch.Tensor] = None, sched=None, stream=None,
+                  workspace: Optional[torch.Tensor] = None):
     """Returns (row_ptr, col, val) with col/val at full capacity; the entry count is
     row_ptr[N] (read it with row_ptr[-1].item() when needed)."""
     src = _dev(src, torch.int32, "src")
@@ -161,10 +173,15 @@ def gee_build_csr(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor
             col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
         if val is None and w is not None:
             val = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        ws = workspace if workspace is not None and workspace.numel() >= nbytes else \
+            torch.empty(nbytes, dtype=torch.uint8, device=dev)
         _check(lib.gee_build_csr_ws(_ptr(src), _ptr(dst), _ptr(w), E, N, flags, _ptr(row_ptr), _ptr(col),
-                                    _ptr(val), sp, _ptr(ws), nbytes, _stream(stream)), "gee_build_csr")
+                                    _ptr(val), sp, _ptr(ws), ws.numel(), _stream(stream)), "gee_build_csr")
     return row_ptr, col, val
+
+
+def gee_build_csr_workspace_bytes(E: int, N: int, flags: int, sched=None) -> int:
+    return int(_lib.load().gee_build_csr_workspace_bytes(E, N, flags, _sched_ptr(sched)))
 
 
 def gee_embed(src: torch.Tensor, dst: torch.Tensor, w: Optional[torch.Tensor], labels: torch.Tensor,
@@ -426,18 +443,35 @@ def gee_embed_batch(graphs, workspace: Optional[torch.Tensor] = None, stream=Non
 
 class BatchPlan:
     """gee_batch_plan: the graphs' launch sequence captured once in a hipGraph; launch()
-    replays it. The graphs' tensors are kept referenced for the plan's lifetime."""
+    replays it, update() gives the plan another set of graphs (no allocation; the plan's
+    workspace must hold them: workspace_bytes reserves room for larger sets). The graphs'
+    tensors are kept referenced while the plan holds them."""
 
-    def __init__(self, graphs):
+    def __init__(self, graphs, workspace_bytes: int = 0):
         if not graphs:
             raise ValueError("a batch plan needs at least one graph")
         self._graphs = list(graphs)
         dev = self._graphs[0]["labels"].device
         arr = _graph_array(self._graphs, dev)
         h = ctypes.c_void_p()
-        _check(_lib.load().gee_batch_plan_create(arr, len(self._graphs), ctypes.byref(h)),
+        _check(_lib.load().gee_batch_plan_create_ws(arr, len(self._graphs), int(workspace_bytes), ctypes.byref(h)),
                "gee_batch_plan_create")
         self._h = h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.load().gee_batch_plan_workspace_bytes(self._h)) if self._h else 0
+
+    def update(self, graphs):
+        """Replace the plan's graphs (the caller has synchronized the plan's last launch)."""
+        if not self._h:
+            raise RuntimeError("batch plan destroyed")
+        graphs = list(graphs)
+        if not graphs:
+            raise ValueError("a batch plan needs at least one graph")
+        arr = _graph_array(graphs, graphs[0]["labels"].device)
+        _check(_lib.load().gee_batch_plan_update(self._h, arr, len(graphs)), "gee_batch_plan_update")
+        self._graphs = graphs
 
     def launch(self, stream=None):
         if not self._h:

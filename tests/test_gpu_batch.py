@@ -98,6 +98,66 @@ def test_batch_plan_replays():
     plan.destroy()
 
 
+def test_batch_plan_update_to_other_graph_sets():
+    """One plan replayed over three different graph sets (other sizes, classes, options and
+    counts; the second set changes the launch sequence, the third keeps it): after every
+    update the replay equals the plain calls bit for bit and the oracle within tolerance.
+    A set that needs more workspace than the plan holds is refused and leaves the plan as
+    it was."""
+    sets = [_mixed_graphs(12, 21), _mixed_graphs(30, 22), _mixed_graphs(12, 23)]
+    big = max(gee.gee_embed_batch_workspace_bytes(_dev_graphs(gs)) for gs in sets)
+    _label(f"batch plan update over 3 graph sets (workspace {big} bytes)")
+    first = _dev_graphs(sets[0])
+    plan = gee.BatchPlan(first, workspace_bytes=big)
+    assert plan.workspace_bytes >= big
+    for k, gs in enumerate(sets):
+        items = first if k == 0 else _dev_graphs(gs)
+        if k > 0:
+            plan.update(items)
+        for rep in range(2):
+            for it in items:
+                it["Z"].fill_(float("nan"))
+            plan.launch()
+            torch.cuda.synchronize()
+            assert gee.gee_get_data_errors() == 0
+            plain = _plain(items)
+            for i, (it, zp) in enumerate(zip(items, plain)):
+                assert torch.equal(it["Z"], zp), f"set {k} replay {rep} graph {i}"
+        for i in range(0, len(gs), 4):
+            assert_close(items[i]["Z"], or_embed_graph(gs[i]), f"set {k} graph {i} vs oracle")
+    # too large for the plan: refused, and the plan still embeds its last set
+    huge = [random_small_graph(900, N=200_000, E=2_000_000, K=64, weighted=True, sym=True)
+            .with_options(True, True, True)]
+    hi = _dev_graphs(huge)
+    assert gee.gee_embed_batch_workspace_bytes(hi) > plan.workspace_bytes
+    with pytest.raises(gee.GeeError) as ei:
+        plan.update(hi)
+    assert ei.value.code == gee.GEE_ERR_WORKSPACE
+    for it in items:
+        it["Z"].fill_(float("nan"))
+    plan.launch()
+    torch.cuda.synchronize()
+    for i, (it, zp) in enumerate(zip(items, _plain(items))):
+        assert torch.equal(it["Z"], zp), f"after a refused update, graph {i}"
+    plan.destroy()
+
+
+def test_batch_plan_update_reports_data_errors_of_the_new_set():
+    g = random_small_graph(31, N=300, E=2000, K=4).with_options(True, True, True)
+    bad = random_small_graph(32, N=200, E=800, K=3)
+    bad.labels[11] = 7
+    items = _dev_graphs([g, g])
+    plan = gee.BatchPlan(items, workspace_bytes=1 << 24)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert gee.gee_get_data_errors() == 0
+    plan.update(_dev_graphs([g, bad]))
+    plan.launch()
+    torch.cuda.synchronize()
+    assert gee.gee_get_data_errors() & gee.GEE_DATA_LABEL
+    plan.destroy()
+
+
 def test_batch_recipe_sample():
     """Graphs of the 512-graph batched workload recipe (a sample of them), batched vs plain
     bitwise and vs the oracle."""

@@ -153,3 +153,39 @@ def test_served_request_errors_are_per_request():
         else:
             assert r.error is None
             assert_close(r.result, or_embed_graph(gs[i]), f"request {i}")
+
+
+def test_take_data_errors_async_into_pinned_memory():
+    """The stream-ordered take without a wait: the bits land in pinned host memory once the
+    stream passes the take, per stream, and the word is cleared."""
+    _label("async data-error take")
+    g = _graph(21)
+    s, d, w, lab = graph_tensors(g)
+    bad = lab.clone()
+    bad[3] = g.K
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for st in (s1, s2):
+        st.wait_stream(torch.cuda.current_stream())
+        gee.gee_get_data_errors(st)
+    h1 = torch.full((1,), -1, dtype=torch.int32, pin_memory=True)
+    h2 = torch.full((1,), -1, dtype=torch.int32, pin_memory=True)
+    gee.gee_embed(s, d, w, lab, g.K, flags(g), stream=s1)
+    gee.gee_embed(s, d, w, bad, g.K, flags(g), stream=s2)
+    gee.gee_take_data_errors_async(h1, stream=s1)
+    gee.gee_take_data_errors_async(h2, stream=s2)
+    e1, e2 = torch.cuda.Event(), torch.cuda.Event()
+    e1.record(s1)
+    e2.record(s2)
+    e1.synchronize()
+    e2.synchronize()
+    assert int(h1[0]) == 0
+    assert int(h2[0]) == gee.GEE_DATA_LABEL
+    assert gee.gee_get_data_errors(s2) == 0  # the take cleared the word
+    # into device memory too
+    dv = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    gee.gee_embed(s, d, w, bad, g.K, flags(g), stream=s1)
+    gee.gee_take_data_errors_async(dv, stream=s1)
+    s1.synchronize()
+    assert int(dv.item()) == gee.GEE_DATA_LABEL
+    with pytest.raises(ValueError):
+        gee.gee_take_data_errors_async(torch.zeros(1, dtype=torch.int32))  # pageable host memory
