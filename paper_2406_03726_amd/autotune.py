@@ -1,10 +1,18 @@
-"""Schedule autotuner: per graph-statistics bucket, the embed schedule (the part size of
-gee_embed's bucket path) that measured fastest on this device, kept as a JSON table.
+"""Schedule autotuner: per graph-statistics bucket, the schedules that measured fastest on
+this device, kept as a JSON table, for the two paths a graph takes:
+
+* edge lists (gee_embed, batches, serving): the bucket path's part size (entries per
+  wavefront, `wave_entries`) crossed with its bucket size (32 or 64 rows,
+  `bucket_rows_log2` 5 or 6);
+* a resident CSR (gee_embed_csr, re-embedding with new labels): the embed kernel's
+  entries per wavefront crossed with its wavefronts per workgroup (`waves_per_block`).
 
 A graph is bucketed by (log2 of its CSR entry count, average-degree class, class-count
-class). For every bucket the tuner embeds a few seeded synthetic graphs of that shape with
-each candidate schedule, times the calls with HIP events, and keeps the fastest. Lookups of
-a bucket the table lacks fall back to the library's own default (zero fields).
+class). For every bucket the tuner embeds seeded synthetic graphs of that shape with each
+candidate, times the calls with HIP events, and keeps the fastest. Candidates that give a
+graph the same launch as another (a part size at least the graph's entry count) are not
+timed twice. Lookups of a bucket the table lacks take the nearest tuned bucket of the same
+degree and class-count classes, else the library's own default (zero fields).
 
 The schedule changes only speed and floating-point summation order; a graph gets the
 same schedule whether it is embedded alone or inside a batch (the lookup depends on the
@@ -24,12 +32,17 @@ from dataclasses import dataclass, field
 from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 GEE_SYMMETRIZE = 1 << 3
-TABLE_VERSION = 1
+TABLE_VERSION = 2
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules_gfx950.json")
 
 # entries per bucket part of gee_embed's bucket path (the library raises anything below
-# 2048 to 2048 there)
+# 2048 to 2048 there), and its bucket sizes (log2 rows)
 WAVE_ENTRIES = (2048, 4096, 8192, 16384)
+BUCKET_SB = (5, 6)
+# resident-CSR embed: entries per wavefront and wavefronts per workgroup
+CSR_WAVE_ENTRIES = (256, 512, 1024, 2048, 4096)
+CSR_WAVES_PER_BLOCK = (1, 2, 4)
+PATHS = ("edge", "csr")
 DEG_EDGES = (8.0, 32.0, 128.0)   # average degree classes: <8, <32, <128, >=128
 K_EDGES = (16, 64)               # class-count classes: <=16, <=64, >64
 
@@ -53,29 +66,39 @@ def bucket_of(E: int, N: int, K: int, flags: int) -> Key:
 
 @dataclass
 class ScheduleTable:
-    """Bucket -> schedule fields (wave_entries, bucket_rows_log2); missing fields and
-    buckets mean the library default."""
+    """Bucket -> schedule fields, per path ("edge": edge lists, "csr": a resident CSR);
+    missing fields and buckets mean the library default."""
     entries: Dict[Key, Dict[str, int]] = field(default_factory=dict)
+    csr_entries: Dict[Key, Dict[str, int]] = field(default_factory=dict)
     device: str = "gfx950"
     meta: Dict[str, object] = field(default_factory=dict)
 
-    def lookup(self, E: int, N: int, K: int, flags: int) -> Dict[str, int]:
+    def _of(self, path: str) -> Dict[Key, Dict[str, int]]:
+        if path not in PATHS:
+            raise ValueError(f"unknown path {path!r}")
+        return self.entries if path == "edge" else self.csr_entries
+
+    def lookup(self, E: int, N: int, K: int, flags: int, path: str = "edge") -> Dict[str, int]:
         """The bucket's schedule; else the tuned bucket of the same degree and class-count
-        classes nearest in size (the smaller one on a tie); else {} (library default)."""
+        classes nearest in size (the smaller one on a tie); else {} (library default). For
+        path "csr", E is the CSR's entry count and flags carry no symmetrization."""
+        tab = self._of(path)
         key = bucket_of(E, N, K, flags)
-        e = self.entries.get(key)
+        e = tab.get(key)
         if e is None:
-            near = [k for k in self.entries if k[1:] == key[1:]]
+            near = [k for k in tab if k[1:] == key[1:]]
             if near:
-                e = self.entries[min(near, key=lambda k: (abs(k[0] - key[0]), k[0]))]
+                e = tab[min(near, key=lambda k: (abs(k[0] - key[0]), k[0]))]
         return dict(e) if e else {}
 
     def to_json(self) -> str:
-        rows = [{"log2_entries": k[0], "degree_class": k[1], "class_count_class": k[2], **v}
-                for k, v in sorted(self.entries.items())]
+        def rows(tab):
+            return [{"log2_entries": k[0], "degree_class": k[1], "class_count_class": k[2], **v}
+                    for k, v in sorted(tab.items())]
+
         return json.dumps({"version": TABLE_VERSION, "device": self.device, "meta": self.meta,
                            "degree_class_edges": list(DEG_EDGES), "class_count_class_edges": list(K_EDGES),
-                           "entries": rows}, indent=1)
+                           "entries": rows(self.entries), "csr_entries": rows(self.csr_entries)}, indent=1)
 
     @classmethod
     def from_json(cls, text: str) -> "ScheduleTable":
@@ -86,11 +109,12 @@ class ScheduleTable:
                 tuple(d.get("class_count_class_edges", K_EDGES)) != K_EDGES:
             raise ValueError("schedule table uses other bucket edges")
         t = cls(device=d.get("device", "gfx950"), meta=d.get("meta", {}))
-        for r in d["entries"]:
-            key = (int(r["log2_entries"]), int(r["degree_class"]), int(r["class_count_class"]))
-            sched = {f: int(r[f]) for f in ("wave_entries", "waves_per_block", "bucket_rows_log2") if f in r}
-            _validate(sched)
-            t.entries[key] = sched
+        for name, tab in (("entries", t.entries), ("csr_entries", t.csr_entries)):
+            for r in d.get(name, []):
+                key = (int(r["log2_entries"]), int(r["degree_class"]), int(r["class_count_class"]))
+                sched = {f: int(r[f]) for f in ("wave_entries", "waves_per_block", "bucket_rows_log2") if f in r}
+                _validate(sched)
+                tab[key] = sched
         return t
 
     def save(self, path: str) -> None:
@@ -127,35 +151,46 @@ def choose(timings: Dict[Tuple[Tuple[str, int], ...], float]) -> Dict[str, int]:
     return dict(best[0])
 
 
-BUCKET_ROWS = (0, 8)  # CSR sort only: 0 the library's rule, 8 256-row buckets (pass-C partition)
-
-
-def candidates(with_bucket_rows: bool = False) -> List[Dict[str, int]]:
-    """Part sizes; with_bucket_rows also crosses them with CSR-sort bucket sizes (which
-    gee_embed's bucket path does not read: it fixes its own bucket size)."""
-    out = [{"wave_entries": we} for we in WAVE_ENTRIES]
-    if with_bucket_rows:
-        out = [dict(c, bucket_rows_log2=sb) for c in out for sb in BUCKET_ROWS]
-    return out
+def candidates(path: str = "edge", entries: Optional[int] = None) -> List[Dict[str, int]]:
+    """The schedules timed for a shape. Edge lists: part sizes x 32/64-row buckets; part
+    sizes at or above the shape's entry count all give one part per bucket, so only the
+    smallest of them is kept. Resident CSR: wavefront sizes x wavefronts per workgroup,
+    wavefronts larger than the graph's entries dropped the same way."""
+    if path == "edge":
+        we = list(WAVE_ENTRIES)
+        if entries is not None:
+            we = [w for w in we if w < entries] + [w for w in we if w >= entries][:1]
+        return [{"wave_entries": w, "bucket_rows_log2": sb} for w in we for sb in BUCKET_SB]
+    if path == "csr":
+        we = list(CSR_WAVE_ENTRIES)
+        if entries is not None:
+            we = [w for w in we if w < entries] + [w for w in we if w >= entries][:1]
+        return [{"wave_entries": w, "waves_per_block": b} for w in we for b in CSR_WAVES_PER_BLOCK]
+    raise ValueError(path)
 
 
 def tune(shapes: Iterable[Tuple[int, int, int, int]], time_fn: Callable[[Tuple[int, int, int, int], Dict[str, int]], float],
-         cands: Optional[List[Dict[str, int]]] = None, table: Optional[ScheduleTable] = None) -> ScheduleTable:
+         cands: Optional[List[Dict[str, int]]] = None, table: Optional[ScheduleTable] = None,
+         path: str = "edge") -> ScheduleTable:
     """For each (E, N, K, flags) shape, time every candidate with `time_fn(shape, sched)`
     (seconds, lower is better) and store the fastest for the shape's bucket. Several shapes
-    of one bucket add their times."""
+    of one bucket add their times over the candidates they all timed. Without `cands`, each
+    shape takes candidates(path, its entry count)."""
     table = table or ScheduleTable()
-    cands = cands or candidates()
-    per_bucket: Dict[Key, Dict[Tuple[Tuple[str, int], ...], float]] = {}
+    tab = table._of(path)
+    per_bucket: Dict[Key, Dict[Tuple[Tuple[str, int], ...], List[float]]] = {}
     for shape in shapes:
         key = bucket_of(*shape)
         acc = per_bucket.setdefault(key, {})
-        for c in cands:
+        cs = cands or candidates(path, entries_of(shape[0], shape[3]))
+        for c in cs:
             t = float(time_fn(shape, c))
             ck = tuple(sorted((k, v) for k, v in c.items() if v))
-            acc[ck] = acc.get(ck, 0.0) + t
+            acc.setdefault(ck, []).append(t)
     for key, timings in per_bucket.items():
-        table.entries[key] = choose(timings)
+        n = max(len(v) for v in timings.values())
+        full = {k: sum(v) for k, v in timings.items() if len(v) == n}
+        tab[key] = choose(full)
     return table
 
 
@@ -175,9 +210,10 @@ def default_shapes() -> List[Tuple[int, int, int, int]]:
     return shapes
 
 
-def gpu_time_fn(reps: int = 5):
+def gpu_time_fn(reps: int = 5, path: str = "edge"):
     """time_fn for tune(): seeded Chung-Lu graph of the shape on cuda:0, median of `reps`
-    gee_embed_ws calls measured with HIP events (after one warmup)."""
+    calls measured with HIP events (after one warmup): gee_embed_ws for the edge-list path,
+    gee_embed_csr_ws on the graph's CSR (built once) for the resident path."""
     import numpy as np
     import torch
 
@@ -202,21 +238,40 @@ def gpu_time_fn(reps: int = 5):
             s, d, w = shuffle_and_orient(s, d, w, rng)
             lab = rng.integers(0, K, size=N).astype(np.int32)
             t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
-            cache[shape] = (t(s, torch.int32), t(d, torch.int32), t(w, torch.float32), t(lab, torch.int32),
-                            torch.empty((N, K), dtype=torch.float32, device=dev))
+            g = (t(s, torch.int32), t(d, torch.int32), t(w, torch.float32), t(lab, torch.int32),
+                 torch.empty((N, K), dtype=torch.float32, device=dev))
+            if path == "csr":
+                rp, col, val = gee.gee_build_csr(g[0], g[1], g[2], N, flags)
+                torch.cuda.synchronize()
+                g = g + (rp, col, val, int(rp[-1].item()))
+            cache.clear()  # one graph at a time (the shapes come in order)
+            cache[shape] = g
         return cache[shape]
 
     def time_fn(shape, sched):
-        src, dst, w, lab, Z = graph(shape)
+        g = graph(shape)
+        src, dst, w, lab, Z = g[:5]
         K, flags = shape[2], shape[3]
-        nbytes = gee.gee_embed_workspace_bytes(src.numel(), lab.numel(), K, flags, True, sched)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, sched=sched, workspace=ws)
+        if path == "csr":
+            rp, col, val, M = g[5:]
+            f2 = flags & ~GEE_SYMMETRIZE
+            ws = torch.empty(max(1, gee.gee_embed_csr_workspace_bytes(M, lab.numel(), K, f2, sched)),
+                             dtype=torch.uint8, device=dev)
+
+            def call():
+                gee.gee_embed_csr(rp, col, val, M, lab, K, f2, Z=Z, sched=sched, workspace=ws)
+        else:
+            nbytes = gee.gee_embed_workspace_bytes(src.numel(), lab.numel(), K, flags, True, sched)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+            def call():
+                gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, sched=sched, workspace=ws)
+        call()
         ts = []
         for _ in range(reps):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            gee.gee_embed(src, dst, w, lab, K, flags, Z=Z, sched=sched, workspace=ws)
+            call()
             b.record()
             b.synchronize()
             ts.append(a.elapsed_time(b) * 1e-3)
@@ -225,17 +280,38 @@ def gpu_time_fn(reps: int = 5):
     return time_fn
 
 
+def csr_shape(shape: Tuple[int, int, int, int]) -> Tuple[int, int, int, int]:
+    """The resident-CSR lookup key of an edge-list shape: (CSR entries, N, K, flags
+    without symmetrization)."""
+    E, N, K, flags = shape
+    return (entries_of(E, flags), N, K, flags & ~GEE_SYMMETRIZE)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune embed schedules on this GPU and write the table.")
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--paths", default="edge,csr")
     args = ap.parse_args(argv)
     t0 = time.time()
     shapes = default_shapes()
-    table = tune(shapes, gpu_time_fn(args.reps))
-    table.meta = {"shapes": len(shapes), "wave_entries": list(WAVE_ENTRIES), "seconds": round(time.time() - t0, 1)}
+    table = ScheduleTable()
+    for path in args.paths.split(","):
+        tp = time.time()
+        if path == "edge":
+            tune(shapes, gpu_time_fn(args.reps, "edge"), table=table, path="edge")
+        else:
+            # timed on the edge-list shape's graph, filed under its CSR's key
+            fn = gpu_time_fn(args.reps, "csr")
+            by_csr = {csr_shape(s): s for s in shapes}
+            tune(list(by_csr), lambda cs, sched: fn(by_csr[cs], sched), table=table, path="csr")
+        print(f"tuned the {path} path in {time.time() - tp:.1f} s", flush=True)
+    table.meta = {"shapes": len(shapes), "wave_entries": list(WAVE_ENTRIES), "bucket_rows_log2": list(BUCKET_SB),
+                  "csr_wave_entries": list(CSR_WAVE_ENTRIES), "csr_waves_per_block": list(CSR_WAVES_PER_BLOCK),
+                  "seconds": round(time.time() - t0, 1)}
     table.save(args.out)
-    print(f"wrote {len(table.entries)} buckets to {args.out} in {time.time() - t0:.1f} s", flush=True)
+    print(f"wrote {len(table.entries)} + {len(table.csr_entries)} buckets to {args.out} in "
+          f"{time.time() - t0:.1f} s", flush=True)
 
 
 if __name__ == "__main__":
