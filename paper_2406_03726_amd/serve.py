@@ -88,7 +88,8 @@ class _Flight:
 class GeeServer:
     def __init__(self, backend: Backend, budget_bytes: int, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter, max_batch_edges: Optional[int] = None,
-                 max_inflight_edges: Optional[int] = None):
+                 max_inflight_edges: Optional[int] = None,
+                 on_done: Optional[Callable[[Request], None]] = None):
         if budget_bytes <= 0 or max_batch < 1:
             raise ValueError("budget and batch size must be positive")
         self.backend = backend
@@ -103,6 +104,8 @@ class GeeServer:
         self.max_inflight_edges = max_inflight_edges
         self.inflight_edges = 0
         self.clock = clock
+        # called once per request as it completes (e.g. to check and release its result)
+        self.on_done = on_done
         self.queue: Deque[Request] = deque()
         self.flights: List[_Flight] = []
         self.free_slots = list(range(backend.slots))
@@ -113,8 +116,21 @@ class GeeServer:
         self.launch_log: List[List[int]] = []   # request ids of every batch, in launch order
 
     # --------------------------------------------------------------------- intake
+    def hold(self, nbytes: int) -> None:
+        """Takes bytes out of the request budget for as long as something else holds them
+        (a resident CSR, say); a negative value gives them back."""
+        self.budget -= int(nbytes)
+        if self.budget <= 0:
+            raise ValueError("holding more than the whole budget")
+
     def submit(self, req: Request) -> None:
-        req.nbytes = int(self.backend.footprint(req))
+        try:
+            req.nbytes = int(self.backend.footprint(req))
+        except (KeyError, ValueError) as e:  # e.g. a re-embedding of a graph not resident
+            req.error = f"invalid request: {e!r}"
+            req.t_done = self.clock()
+            self.done.append(req)
+            return
         if req.nbytes > self.budget:
             req.error = f"request needs {req.nbytes} bytes, more than the whole budget of {self.budget}"
             req.t_done = self.clock()
@@ -141,6 +157,8 @@ class GeeServer:
                 for r in f.reqs:
                     r.t_done = now
                     self.done.append(r)
+                    if self.on_done is not None:
+                        self.on_done(r)
                 self.in_use -= f.nbytes
                 self.inflight_edges -= f.edges
                 self.free_slots.append(f.slot)
@@ -208,8 +226,11 @@ class GeeServer:
 
     # --------------------------------------------------------------------- traces
     def run_trace(self, reqs: Sequence[Request], sleep: Callable[[float], None] = time.sleep,
-                  poll_interval: float = 20e-6) -> List[Request]:
-        """Feed requests at their arrival times (relative to now) and run until all are done."""
+                  poll_interval: float = 20e-6, busy_poll: bool = False) -> List[Request]:
+        """Feed requests at their arrival times (relative to now) and run until all are done.
+        With busy_poll (a real clock), the loop polls the batches in flight without sleeping
+        and waits for the next arrival with wait_until, so neither a completion nor an
+        arrival is seen late by a sleep's overshoot."""
         t0 = self.clock()
         pending = sorted(reqs, key=lambda r: r.arrival)
         for r in pending:
@@ -221,15 +242,35 @@ class GeeServer:
                 self.submit(pending[i])
                 i += 1
             if self.step() == 0:
+                if busy_poll:
+                    if self.flights or i >= len(pending):
+                        continue
+                    if not self.queue:
+                        wait_until(pending[i].arrival, self.clock, sleep)
+                        continue
                 nxt = pending[i].arrival - now if i < len(pending) else poll_interval
                 sleep(max(0.0, min(poll_interval, nxt)))
         return list(reqs)
 
 
+def wait_until(t: float, clock: Callable[[], float] = time.perf_counter,
+               sleep: Callable[[float], None] = time.sleep, spin: float = 300e-6) -> None:
+    """Returns at clock() >= t: sleeps until `spin` seconds before t (a sleep can overshoot
+    by tens of microseconds), then polls the clock."""
+    while True:
+        dt = t - clock()
+        if dt <= 0:
+            return
+        if dt > spin:
+            sleep(dt - spin)
+
+
 def run_plain(reqs: Sequence[Request], embed_one: Callable[[Request], None],
-              clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
+              clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+              on_done: Optional[Callable[[Request], None]] = None, busy_poll: bool = False):
     """The plain per-request loop: one host thread, FIFO, each request embedded alone and
-    waited for before the next one starts."""
+    waited for before the next one starts (with busy_poll, arrivals are waited for with
+    wait_until)."""
     t0 = clock()
     order = sorted(reqs, key=lambda r: r.arrival)
     for r in order:
@@ -237,10 +278,15 @@ def run_plain(reqs: Sequence[Request], embed_one: Callable[[Request], None],
     for r in order:
         now = clock()
         if r.arrival > now:
-            sleep(r.arrival - now)
+            if busy_poll:
+                wait_until(r.arrival, clock, sleep)
+            else:
+                sleep(r.arrival - now)
         r.t_admit = clock()
         embed_one(r)
         r.t_done = clock()
+        if on_done is not None:
+            on_done(r)
     return list(reqs)
 
 
@@ -273,9 +319,15 @@ class GpuBackend(Backend):
     """Batches run with gee_embed_batch_ws on `slots` torch streams (default priority).
     A batch is charged the library's workspace size for exactly that batch plus its Z
     outputs; the bytes each batch actually allocates are tracked too (peak_actual).
-    A batch's data errors are read from its stream's data-error word when it finishes; when
-    a batch of several requests reports one, each request is embedded again alone to find
-    the ones that carry it, and only those get an error."""
+    A batch's data errors are taken in stream order into pinned memory (no stream wait)
+    and read when it finishes; when a batch of several requests reports one, each request
+    is embedded again alone to find the ones that carry it, and only those get an error.
+
+    Re-embedding: make_resident(gid, ...) builds a graph's CSR (gee_build_csr) and keeps it
+    on the device; a request whose graph dict holds {"resident": gid, "labels", "K",
+    "flags"} is then embedded from that CSR with its own labels (gee_embed_csr: class
+    counts, degrees and the class scatter, no sort), the iterative use of GEE with changing
+    labels. Such requests run in the same batches, on the same stream, one call each."""
 
     def __init__(self, slots: int = 4, table=None):
         import torch
@@ -286,15 +338,46 @@ class GpuBackend(Backend):
         self._gee = gee
         self.slots = slots
         self._streams = None  # made at the first launch (sizing needs no device)
+        self._errs = None     # per slot: pinned int32 the batch's data-error bits land in
         self.table = table
         self.in_use_actual = 0
         self.peak_actual = 0
+        self.resident: Dict[Any, Dict[str, Any]] = {}
 
     @property
     def streams(self):
         if self._streams is None:
             self._streams = [self._torch.cuda.Stream() for _ in range(self.slots)]
+            self._errs = [self._torch.zeros(1, dtype=self._torch.int32, pin_memory=True) for _ in range(self.slots)]
         return self._streams
+
+    # --------------------------------------------------------------- resident CSRs
+    def make_resident(self, gid, src, dst, w, N: int, flags: int) -> int:
+        """Builds and keeps the CSR of an edge list under `gid`; returns the bytes it holds
+        (a server can hold them out of its request budget with GeeServer.hold)."""
+        torch = self._torch
+        rp, col, val = self._gee.gee_build_csr(src, dst, w, N, flags)
+        torch.cuda.synchronize()
+        if self._gee.gee_get_data_errors() != 0:
+            raise ValueError(f"graph {gid!r}: the edge list has data errors")
+        M = int(rp[-1].item())
+        col = col[:M].clone()
+        val = val[:M].clone() if val is not None else None
+        nbytes = rp.numel() * 4 + col.numel() * 4 + (val.numel() * 4 if val is not None else 0)
+        self.resident[gid] = dict(rp=rp, col=col, val=val, M=M, N=N, nbytes=nbytes)
+        return nbytes
+
+    def release(self, gid) -> int:
+        """Drops a resident CSR; returns the bytes it held."""
+        return self.resident.pop(gid)["nbytes"]
+
+    def _csr_sched(self, g: Dict[str, Any], res: Dict[str, Any]):
+        if g.get("sched") is not None:
+            return g["sched"]
+        if self.table is None:
+            return None
+        s = self.table.lookup(res["M"], res["N"], int(g["K"]), int(g["flags"]) & ~8, path="csr")
+        return s or None
 
     def sched_of(self, g: Dict[str, Any]) -> Optional[Dict[str, int]]:
         if g.get("sched") is not None:
@@ -313,15 +396,37 @@ class GpuBackend(Backend):
         g = r.graph
         return (r.E, r.N, int(g["K"]), int(g["flags"]), g.get("w") is not None, self.sched_of(g))
 
+    def _csr_ws_bytes(self, r: Request) -> int:
+        g = r.graph
+        res = self.resident[g["resident"]]
+        return int(self._gee.gee_embed_csr_workspace_bytes(res["M"], res["N"], int(g["K"]),
+                                                           int(g["flags"]) & ~8, self._csr_sched(g, res)))
+
     def footprint(self, r: Request) -> int:
         g = r.graph
-        r.E = int(g["src"].numel())
-        r.N = int(g["labels"].numel())
+        if "resident" in g:
+            if (int(g["flags"]) & 16) and (int(g["flags"]) & 2):
+                raise ValueError("a resident CSR has no column sums for the directed-degree Laplacian")
+            res = self.resident[g["resident"]]
+            r.E, r.N = res["M"], res["N"]
+        else:
+            r.E = int(g["src"].numel())
+            r.N = int(g["labels"].numel())
         return self.batch_footprint([r])
 
     def batch_footprint(self, reqs: List[Request]) -> int:
-        ws = self._gee.batch_workspace_bytes_of_sizes([self._sizes(r) for r in reqs])
+        edge = [r for r in reqs if "resident" not in r.graph]
+        ws = self._gee.batch_workspace_bytes_of_sizes([self._sizes(r) for r in edge]) if edge else 0
+        ws += sum(self._csr_ws_bytes(r) for r in reqs if "resident" in r.graph)
         return int(ws) + sum(4 * r.N * int(r.graph["K"]) for r in reqs)
+
+    def _embed_resident(self, r: Request, Z, s):
+        g = r.graph
+        res = self.resident[g["resident"]]
+        ws = self._torch.empty(max(1, self._csr_ws_bytes(r)), dtype=self._torch.uint8, device=Z.device)
+        self._gee.gee_embed_csr(res["rp"], res["col"], res["val"], res["M"], g["labels"], int(g["K"]),
+                                int(g["flags"]) & ~8, Z=Z, sched=self._csr_sched(g, res), workspace=ws, stream=s)
+        return ws
 
     def launch(self, reqs: List[Request], slot: int):
         torch = self._torch
@@ -330,27 +435,37 @@ class GpuBackend(Backend):
         # the requests' inputs were made on the submitting stream
         s.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(s):
-            items = []
+            items, held_ws = [], []
             for r in reqs:
                 Z = torch.empty((r.N, int(r.graph["K"])), dtype=torch.float32, device=dev)
-                items.append(self._item(r, Z=Z))
-            nbytes = self._gee.gee_embed_batch_workspace_bytes(items)
-            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-            self._gee.gee_embed_batch(items, workspace=ws, stream=s)
+                items.append(self._item(r, Z=Z) if "resident" not in r.graph else dict(Z=Z))
+            edge = [it for r, it in zip(reqs, items) if "resident" not in r.graph]
+            if edge:
+                nbytes = self._gee.gee_embed_batch_workspace_bytes(edge)
+                ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+                self._gee.gee_embed_batch(edge, workspace=ws, stream=s)
+                held_ws.append(ws)
+            for r, it in zip(reqs, items):
+                if "resident" in r.graph:
+                    held_ws.append(self._embed_resident(r, it["Z"], s))
+            # the batch's data-error bits, taken in stream order into pinned memory, so the
+            # host reads them at completion without synchronizing the stream
+            err = self._errs[slot]
+            self._gee.gee_take_data_errors_async(err, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        held = ws.numel() + sum(it["Z"].numel() * 4 for it in items)
+        held = sum(w.numel() for w in held_ws) + sum(it["Z"].numel() * 4 for it in items)
         self.in_use_actual += held
         self.peak_actual = max(self.peak_actual, self.in_use_actual)
-        return (ev, items, ws, s, held)
+        return (ev, items, held_ws, s, held, err)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle, reqs: List[Request]) -> None:
-        _, items, _, s, held = handle
+        _, items, _, s, held, err = handle
         self.in_use_actual -= held
-        bits = self._gee.gee_get_data_errors(s)
+        bits = int(err[0])
         for r, it in zip(reqs, items):
             r.result = it["Z"]
         if not bits:
@@ -361,7 +476,10 @@ class GpuBackend(Backend):
             return
         for r, it in zip(reqs, items):
             with self._torch.cuda.stream(s):
-                self._gee.gee_embed_batch([it], stream=s)
+                if "resident" in r.graph:
+                    self._embed_resident(r, it["Z"], s)
+                else:
+                    self._gee.gee_embed_batch([it], stream=s)
             b = self._gee.gee_get_data_errors(s)
             if b:
                 r.error = f"data error (bits {b:#x})"

@@ -90,6 +90,14 @@ def test_csr_two_partition_passes_with_hubs(sb):
     _check_csr(g, sched=dict(bucket_rows_log2=sb))
 
 
+def test_csr_powerlaw_10m_full_bit_exact():
+    """gee_build_csr of the 10M-edge power-law workload (20M entries, hub rows of tens of
+    thousands of entries) in its default schedule, bit for bit against the stable sort."""
+    g = powerlaw_10m()
+    _label(f"csr powerlaw N={g.N} E={g.E}")
+    _check_csr(g)
+
+
 def test_csr_empty_and_isolated():
     _label("csr empty")
     g = Graph(src=np.zeros(0, np.int32), dst=np.zeros(0, np.int32), w=None, N=7,
