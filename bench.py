@@ -589,10 +589,16 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, 
            "pool_plain_ms_default_schedules": round(float(np.sum(svc_d)) * 1e3, 3),
            "schedules": "autotuned table" if table and table.entries else "library defaults", "loads": []}
 
-    def server():
-        return GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
+    # one backend for every run (its streams, per-slot workspaces and the graphs' cached sizing
+    # outlive each server); the pool is staged and complete, so batches need not wait for the
+    # submitting stream
+    torch.cuda.synchronize()
+    backend = GpuBackend(slots=slots, table=table, sync_inputs=False)
+
+    def server(on_done=None):
+        return GeeServer(backend, int(budget_gb * 2 ** 30), max_batch=max_batch,
                          max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges,
-                         on_done=drop)
+                         on_done=on_done or drop)
 
     def drop(r):
         r.result = None  # results are not kept through the timed runs
@@ -614,8 +620,7 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, 
 
     for i, it in enumerate(pool):
         it["_pool"] = i
-    chk = GeeServer(GpuBackend(slots=slots, table=table), int(budget_gb * 2 ** 30), max_batch=max_batch,
-                    max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges, on_done=check)
+    chk = server(on_done=check)
     chk.run_trace([Request(i, pool[int(p)], 0.0, E=int(pool[int(p)]["src"].numel())) for i, p in enumerate(picks)],
                   busy_poll=True)
     torch.cuda.synchronize()
@@ -768,6 +773,53 @@ def write_traffic(csv_a: str, csv_b: str, workload: str, commands: str) -> str:
     return path
 
 
+def write_trace(trace_csv: str, workload: str, commands: str) -> str:
+    """Turns a rocprofv3 --kernel-trace CSV of `bench.py --legs none` into the per-kernel
+    durations of one gee_embed call on the benchmark workload: the calls are the runs from
+    a_hist to bucket_embed_fix, each kernel's median over them, and the calls' median span
+    (first start to last end)."""
+    import csv
+    import statistics
+
+    seq = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            seq.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), kernel_key(r["Kernel_Name"])))
+    seq.sort()
+    calls, cur = [], None
+    for st, en, k in seq:
+        if k == "a_hist":
+            cur = [(st, en, k)]
+        elif cur is not None:
+            cur.append((st, en, k))
+            if k == "bucket_embed_fix":
+                calls.append(cur)
+                cur = None
+    if not calls:
+        raise SystemExit(f"no gee_embed call in {trace_csv}")
+    names = [k for _, _, k in calls[0]]
+    per = {k: statistics.median([(c[i][1] - c[i][0]) / 1e3 for c in calls if len(c) == len(names)])
+           for i, k in enumerate(names)}
+    span = statistics.median([(c[-1][1] - c[0][0]) / 1e3 for c in calls])
+    out = {"workload": workload, "source_hash": source_hash(), "calls": len(calls), "span_us": round(span, 1),
+           "kernels_us": {k: round(v, 1) for k, v in per.items()}}
+    path = os.path.join(PROFILES, f"kernel_trace_gee_embed_{workload}.md")
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(path, "w") as f:
+        f.write(f"# Kernel trace of `gee_embed` on `{workload}`\n\n")
+        f.write("rocprofv3 kernel trace of the benchmark without its extra legs; every call of the path\n"
+                "(a_hist through bucket_embed_fix) is taken, and each kernel's median duration over them.\n"
+                "Command (from /tmp, TMPDIR=/tmp, on the MI355X box):\n\n")
+        f.write("```\n" + commands.strip() + "\n```\n\n")
+        f.write(f"{len(calls)} calls; median span of one call (first start to last end): {span:.1f} us.\n\n")
+        f.write("| kernel | median us | share |\n|---|---|---|\n")
+        tot = sum(per.values())
+        for k, v in per.items():
+            f.write(f"| `{k}` | {v:.1f} | {v / tot * 100:.1f} % |\n")
+        f.write("\n```json\n" + json.dumps(out, indent=1) + "\n```\n")
+    return path
+
+
 def read_traffic(workload: str):
     """Per-kernel bytes per launch from the committed counter summary, or None when absent
     or taken from other sources than the current ones."""
@@ -877,7 +929,13 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("PASS1_CSV", "PASS2_CSV"),
                     help="host only: turn the two counter passes into the committed traffic summary")
     ap.add_argument("--traffic-commands", default="")
+    ap.add_argument("--write-trace", metavar="KERNEL_TRACE_CSV",
+                    help="host only: turn a rocprofv3 kernel trace into the committed per-kernel summary")
     args = ap.parse_args()
+
+    if args.write_trace:
+        print(write_trace(args.write_trace, "chunglu_n600k_e10m_k50", args.traffic_commands))
+        return
 
     if args.write_traffic:
         print(write_traffic(args.write_traffic[0], args.write_traffic[1], "chunglu_n600k_e10m_k50",

@@ -95,6 +95,10 @@ typedef enum {
 #define GEE_DATA_INDEX (1u << 1)
 #define GEE_DATA_WEIGHT (1u << 2)
 #define GEE_DATA_CSR (1u << 3)
+/* Raised only by builds with GEE_DEBUG=1 (internal-consistency checks of the kernels' own
+   index arithmetic): a computed LDS slot or staging/output position outside its array was
+   skipped. Never raised by a release build. */
+#define GEE_DATA_INTERNAL (1u << 30)
 
 /* Limits of the library: N <= 2^24, K <= 128, CSR entries M < 2^31 - 2^16.
    (M = 2E minus self-loops under GEE_SYMMETRIZE, else E.) */

@@ -10,6 +10,7 @@ from .gee import (  # noqa: F401
     GEE_CORRELATION,
     GEE_DATA_CSR,
     GEE_DATA_INDEX,
+    GEE_DATA_INTERNAL,
     GEE_DATA_LABEL,
     GEE_DATA_WEIGHT,
     GEE_DIAG,

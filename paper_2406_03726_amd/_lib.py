@@ -101,7 +101,9 @@ SYMBOLS = {
 
 
 def lib_path() -> str:
-    return LIB
+    """libgee.so in the package, or the build GEE_LIBRARY names (e.g. the GEE_DEBUG build
+    libgee_debug.so beside it)."""
+    return os.environ.get("GEE_LIBRARY") or LIB
 
 
 def load():
@@ -109,11 +111,12 @@ def load():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB):
+            path = lib_path()
+            if not os.path.exists(path):
                 raise RuntimeError(
-                    f"{LIB} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                    f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
                     "(or python -m paper_2406_03726_amd.build). The GEE path has no CPU fallback.")
-            lib = ctypes.CDLL(LIB)
+            lib = ctypes.CDLL(path)
             for name, (res, args) in SYMBOLS.items():
                 fn = getattr(lib, name)
                 fn.restype = res

@@ -210,10 +210,34 @@ def default_shapes() -> List[Tuple[int, int, int, int]]:
     return shapes
 
 
-def gpu_time_fn(reps: int = 5, path: str = "edge"):
-    """time_fn for tune(): seeded Chung-Lu graph of the shape on cuda:0, median of `reps`
-    calls measured with HIP events (after one warmup): gee_embed_ws for the edge-list path,
-    gee_embed_csr_ws on the graph's CSR (built once) for the resident path."""
+def recipe_graphs(n_batched: int = 48, n_serving: int = 24, procs: int = 8):
+    """Graphs drawn from the batched and the serving recipes (seeds of their own, not the
+    benchmark's), as {(E, N, K, flags): Graph}: the tuner times these graphs themselves, so
+    the buckets the two systems forms fall into are tuned on graphs of their kind (SBM and
+    power-law, their degrees and class counts)."""
+    import multiprocessing as mp
+
+    with mp.get_context("spawn").Pool(procs) as pool:
+        gs = pool.starmap(_recipe_graph, [("batched", 1000 + i) for i in range(n_batched)] +
+                          [("serving", 1000 + i) for i in range(n_serving)], chunksize=1)
+    out = {}
+    for g in gs:
+        f = (1 if g.diag else 0) | (2 if g.lap else 0) | (4 if g.cor else 0) | (GEE_SYMMETRIZE if g.sym else 0)
+        out[(g.E, g.N, g.K, f)] = g
+    return out
+
+
+def _recipe_graph(kind: str, i: int):
+    from gee_workloads.configs import batched_one, serving_one
+
+    return batched_one(i) if kind == "batched" else serving_one(i)
+
+
+def gpu_time_fn(reps: int = 5, path: str = "edge", given=None):
+    """time_fn for tune(): seeded Chung-Lu graph of the shape (or the graph `given` holds
+    for it) on cuda:0, median of `reps` calls measured with HIP events (after one warmup):
+    gee_embed_ws for the edge-list path, gee_embed_csr_ws on the graph's CSR (built once)
+    for the resident path."""
     import numpy as np
     import torch
 
@@ -226,17 +250,22 @@ def gpu_time_fn(reps: int = 5, path: str = "edge"):
     def graph(shape):
         if shape not in cache:
             E, N, K, flags = shape
-            rng = rng_for(90, hash(shape) % (2 ** 31))
-            E = min(E, N * (N - 1) // 4)
-            dmax = min(N - 1.0, max(math.sqrt(N * 2.0 * E / N) * 4.0, 8.0))
-            try:
-                s, d = chung_lu_edges(N, E, 2.1, dmax, rng)
-            except ValueError:  # degree too close to N for a power law: uniform endpoints
-                s = rng.integers(0, N, size=E).astype(np.int32)
-                d = rng.integers(0, N, size=E).astype(np.int32)
-            w = uniform_weights(s.shape[0], rng)
-            s, d, w = shuffle_and_orient(s, d, w, rng)
-            lab = rng.integers(0, K, size=N).astype(np.int32)
+            if given is not None and shape in given:
+                x = given[shape]
+                s, d, lab = x.src, x.dst, x.labels
+                w = x.w if x.w is not None else np.ones(x.E, np.float32)
+            else:
+                rng = rng_for(90, hash(shape) % (2 ** 31))
+                E = min(E, N * (N - 1) // 4)
+                dmax = min(N - 1.0, max(math.sqrt(N * 2.0 * E / N) * 4.0, 8.0))
+                try:
+                    s, d = chung_lu_edges(N, E, 2.1, dmax, rng)
+                except ValueError:  # degree too close to N for a power law: uniform endpoints
+                    s = rng.integers(0, N, size=E).astype(np.int32)
+                    d = rng.integers(0, N, size=E).astype(np.int32)
+                w = uniform_weights(s.shape[0], rng)
+                s, d, w = shuffle_and_orient(s, d, w, rng)
+                lab = rng.integers(0, K, size=N).astype(np.int32)
             t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
             g = (t(s, torch.int32), t(d, torch.int32), t(w, torch.float32), t(lab, torch.int32),
                  torch.empty((N, K), dtype=torch.float32, device=dev))
@@ -292,21 +321,26 @@ def main(argv=None):
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--paths", default="edge,csr")
+    ap.add_argument("--no-recipes", action="store_true", help="synthetic shapes only")
     args = ap.parse_args(argv)
     t0 = time.time()
-    shapes = default_shapes()
+    given = {} if args.no_recipes else recipe_graphs()
+    shapes = default_shapes() + list(given)
+    print(f"{len(shapes)} shapes ({len(given)} drawn from the batched and serving recipes) in "
+          f"{time.time() - t0:.1f} s", flush=True)
     table = ScheduleTable()
     for path in args.paths.split(","):
         tp = time.time()
         if path == "edge":
-            tune(shapes, gpu_time_fn(args.reps, "edge"), table=table, path="edge")
+            tune(shapes, gpu_time_fn(args.reps, "edge", given), table=table, path="edge")
         else:
             # timed on the edge-list shape's graph, filed under its CSR's key
-            fn = gpu_time_fn(args.reps, "csr")
+            fn = gpu_time_fn(args.reps, "csr", given)
             by_csr = {csr_shape(s): s for s in shapes}
             tune(list(by_csr), lambda cs, sched: fn(by_csr[cs], sched), table=table, path="csr")
         print(f"tuned the {path} path in {time.time() - tp:.1f} s", flush=True)
-    table.meta = {"shapes": len(shapes), "wave_entries": list(WAVE_ENTRIES), "bucket_rows_log2": list(BUCKET_SB),
+    table.meta = {"shapes": len(shapes), "recipe_graphs": len(given),
+                  "wave_entries": list(WAVE_ENTRIES), "bucket_rows_log2": list(BUCKET_SB),
                   "csr_wave_entries": list(CSR_WAVE_ENTRIES), "csr_waves_per_block": list(CSR_WAVES_PER_BLOCK),
                   "seconds": round(time.time() - t0, 1)}
     table.save(args.out)

@@ -614,6 +614,8 @@ int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t 
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+int embed_batch(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes, void *stream,
+                int *rcnt = nullptr, bool *counts_given = nullptr);
 // Stream of a call about to enqueue kernels. HIP keeps a thread's last error until it is
 // read; one left by the application's own earlier calls is consumed here, so the checks
 // after this call's launches see only this call's launches.
@@ -775,6 +777,7 @@ int gee_class_counts(const int32_t *labels, int32_t N, int32_t K, int32_t *count
     if ((rc = make_plan(&x, 1, false, p, d))) return rc;
     Batch b;
     b.one = d[0];
+    b.status = st;
     hipStream_t s = launch_stream(stream);
     int *part = nullptr;
     hipError_t e = hipMallocAsync((void **)&part, (size_t)p.cparts * sizeof(int), s);
@@ -832,6 +835,7 @@ int gee_build_csr_ws(const int32_t *src, const int32_t *dst, const float *wgt, i
     wk.val = wgt ? val : nullptr;
     Batch b;
     b.one = d[0];
+    b.status = st;
     hipError_t e = launch_csr_build(b, p, wk, st, s);
     if (e == hipSuccess) e = launch_csr_pass2(p, wk, st, s);
     return hip_status(e);
@@ -962,9 +966,24 @@ int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt
     float *Zd = reinterpret_cast<float *>(base + eb);
     int *tile = reinterpret_cast<int *>(base + eb + up((size_t)N * K * sizeof(float)));
     int *rcnt = tile + up((size_t)zsparse_tiles(N) * sizeof(int)) / sizeof(int);
-    rc = gee_embed_ws(src, dst, wgt, E, N, labels, K, flags, Zd, sched, workspace, eb, stream);
+    // the class-scatter kernels count each row's non-zero entries as they write it (bucket
+    // path), so the compaction reads Z once
+    gee_graph g;
+    g.src = src;
+    g.dst = dst;
+    g.w = wgt;
+    g.E = E;
+    g.N = N;
+    g.labels = labels;
+    g.K = K;
+    g.flags = flags;
+    g.Z = Zd;
+    g.sched = sched ? *sched : gee_schedule{0, 0, 0, 0};
+    bool counts_given = false;
+    rc = embed_batch(&g, 1, workspace, eb, stream, rcnt, &counts_given);
     if (rc) return rc;
-    return hip_status(launch_zsparse(Zd, N, K, tile, rcnt, row_ptr, col, val, capacity, as_stream(stream)));
+    return hip_status(launch_zsparse(Zd, N, K, tile, rcnt, row_ptr, col, val, capacity, counts_given,
+                                     as_stream(stream)));
 }
 
 int gee_embed_sparse(const int32_t *src, const int32_t *dst, const float *wgt, int64_t E, int32_t N,
@@ -1034,8 +1053,16 @@ size_t gee_embed_batch_workspace_bytes(const gee_graph *graphs, int32_t G) {
     return total;
 }
 
-int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
-                       void *stream) {
+}  // extern "C"
+
+namespace {
+
+// gee_embed_batch_ws; with rcnt (a single graph), the class-scatter kernels also write each Z
+// row's number of non-zero entries there when the graph takes the bucket path, and
+// *counts_given says whether they did.
+int embed_batch(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes, void *stream,
+                int *rcnt, bool *counts_given) {
+    if (counts_given) *counts_given = false;
     std::vector<GraphIn> gs;
     int rc = graphs_from_api(graphs, G, gs);
     if (rc) return rc;
@@ -1054,13 +1081,27 @@ int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size
         if (c.p.Ntot == 0) continue;
         Work wk;
         carve(c.p, kEmbedParts, (char *)workspace + c.off, wk);
+        if (rcnt && G == 1 && c.p.bucket) {
+            wk.rcnt = rcnt;
+            *counts_given = true;
+        }
         Batch b;
         Batch bT;
         e = make_batch(c.p, c.d, wk, s, false, b, &bT);
+        b.status = bT.status = st;
         if (e == hipSuccess) e = enqueue_embed(b, bT, c.p, wk, st, s);
         if (e != hipSuccess) break;
     }
     return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gee_embed_batch_ws(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes,
+                       void *stream) {
+    return embed_batch(graphs, G, workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"
@@ -1094,6 +1135,7 @@ int plan_capture(gee_batch_plan *pl, const gee_graph *graphs, int32_t G, hipGrap
         if (ch[i].p.Ntot == 0) continue;
         carve(ch[i].p, kEmbedParts, wsb + ch[i].off, wks[i]);
         e = make_batch(ch[i].p, ch[i].d, wks[i], nullptr, true, bs[i], &bTs[i]);
+        bs[i].status = bTs[i].status = st;
     }
     hipStream_t cs = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -1288,6 +1330,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     hipStream_t s = launch_stream(stream);
     Batch b;
     b.one = d[0];
+    b.status = st;
     b.gm = wk.gm;
     hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, nullptr, (int)M, s);

@@ -339,13 +339,15 @@ __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__
 
 // Lane-per-row finish of bucket rows r0 .. r0+R-1 held in acc[R][KP]: diagonal term, then
 // fac[row] = s_i, or 1/|row| under correlation (class columns K .. KP-1 are zero).
-// q = {c_i, y_i} and s of the lane's row, loaded by the caller.
+// q = {c_i, y_i} and s of the lane's row, loaded by the caller. With rcnt (sparse Z of one
+// graph), also the row's number of non-zero entries of Z, acc * fac exactly as written.
 __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int KP, float *acc, float *fac,
-                                            float2 q, float s, int lane) {
+                                            float2 q, float s, int lane, unsigned *status, int *rcnt) {
     const int r = r0 + lane;
     if (lane < R && r >= gd.node_off && r < gd.node_off + gd.N) {
         float *row = acc + lane * KP;
-        if (gd.flags & kDiag) row[__float_as_int(q.y)] += q.x;
+        const int y = __float_as_int(q.y);
+        if ((gd.flags & kDiag) && dbg_ok(y >= 0 && y < KP, status)) row[y] += q.x;
         float ss = 0.0f;
         const bool cor = gd.flags & kCor;
         if (cor) {
@@ -355,7 +357,17 @@ __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int 
                 ss += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
             }
         }
-        fac[lane] = row_factor((gd.flags & kLap) ? s : 1.0f, ss, cor);
+        const float f = row_factor((gd.flags & kLap) ? s : 1.0f, ss, cor);
+        fac[lane] = f;
+        if (rcnt) {
+            int nz = 0;
+            const float4 *a4 = reinterpret_cast<const float4 *>(row);
+            for (int q4 = 0; q4 < (KP >> 2); ++q4) {  // columns K .. KP-1 hold 0
+                const float4 t = a4[q4];
+                nz += (t.x * f != 0.0f) + (t.y * f != 0.0f) + (t.z * f != 0.0f) + (t.w * f != 0.0f);
+            }
+            rcnt[r - gd.node_off] = nz;
+        }
     }
 }
 
@@ -426,7 +438,8 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
                                                    const int4 *__restrict__ part, int cap,
                                                    const int *__restrict__ bmeta, int sb,
                                                    const float2 *__restrict__ info,
-                                                   const float *__restrict__ srow, float *__restrict__ zpart, int zs) {
+                                                   const float *__restrict__ srow, float *__restrict__ zpart, int zs,
+                                                   int *__restrict__ rcnt) {
     extern __shared__ float smem_b[];
     const int lane = lane_id();
     int4 pt;
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             ad[j] = P.row[j] * KP + __float_as_int(P.f[j].y);
             xv[j] = P.x[j] * P.f[j].x;
         }
-        lds_tag_add<BEPL>(acc, tag, ad, xv, lane, kTagBytes - 1);
+        lds_tag_add<BEPL>(acc, tag, ad, xv, lane, kTagBytes - 1, R * KP, b.status);
     };
     // Three stages, two register sets each with fixed roles (no copies that would wait for
     // loads in flight): the loads of window i+2 are issued first, then the gathers of
@@ -514,7 +527,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
 #undef EMB_SB
     wave_lds_fence();
     if (pt.w < 0) {
-        finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, lane);
+        finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, lane, b.status, rcnt);
         wave_lds_fence();
         write_rows(gd, r0, R, KP, acc, fac, lane, 64);
         return;
@@ -541,7 +554,8 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
                                                                 const int *__restrict__ bmeta, int sb,
                                                                 const float2 *__restrict__ info,
                                                                 const float *__restrict__ srow,
-                                                                const float *__restrict__ zpart, int zs) {
+                                                                const float *__restrict__ zpart, int zs,
+                                                                int *__restrict__ rcnt) {
     extern __shared__ float smem_b[];
     const int nmulti = bmeta[1];
     for (int i = blockIdx.x; i < nmulti; i += gridDim.x) {
@@ -579,7 +593,8 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
         if (t < 64) {
             const int rl = r0 + t;
             const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
-            finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t);
+            finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t,
+                        b.status, rcnt);
         }
         __syncthreads();
         write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
@@ -609,11 +624,11 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     const int zs = p.Kmax << p.sb;  // floats per partial slot
     prof_begin(kKBucketEmbed, s);
     hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
-                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs);
+                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
     hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
-                       wk.srow, wk.zpart, zs);
+                       wk.srow, wk.zpart, zs, wk.rcnt);
     prof_end(kKBucketEmbedFix, s);
 }
 

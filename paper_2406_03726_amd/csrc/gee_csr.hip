@@ -215,8 +215,17 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
 // Workgroups past the T tiles are label slices of the class counts.
+// With vec (one graph whose src and dst are 16-byte aligned and fit 32-bit buffer offsets)
+// each thread reads 4 edges per 16-byte load instead of one virtual entry per lane: the
+// tile's edges are the same (virtual entries 2e and 2e+1 are edge e under symmetrization),
+// so are its counts.
+#ifndef GEE_AHIST_EDGES
+#define GEE_AHIST_EDGES 1
+#endif
+static_assert(kTile % (kThreads * 8) == 0 && kTile / kThreads <= 16, "a_hist: whole 16-byte loads of edges per thread");
 __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
-                                                   int *__restrict__ gh, unsigned *status, int *__restrict__ cpart) {
+                                                   int *__restrict__ gh, unsigned *status, int *__restrict__ cpart,
+                                                   int vec) {
     __shared__ int hist[256];
     if ((int64_t)blockIdx.x >= T) {
         class_count_slice(b, (int)(blockIdx.x - T), cpart, status, hist);
@@ -225,13 +234,49 @@ __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift
     for (int i = threadIdx.x; i < 256; i += kThreads) hist[i] = 0;
     __syncthreads();
     const int64_t t = xcd_order(blockIdx.x, T);
-    const int wv = threadIdx.x >> 6;
-    bool badi = false, badw = false;
-    Quarter<false> q;
-    load_quarter<false>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+    bool badi = false;
+    if (GEE_AHIST_EDGES && vec) {
+        const GDesc &gd = b.one;
+        const bool sym = gd.flags & kSym;
+        const bool chk = validates(gd);
+        const unsigned N = (unsigned)gd.N;
+        const int per = sym ? kTile / kThreads / 2 : kTile / kThreads;  // edges per thread (8 or 16)
+        const int64_t e0 = t * (sym ? kTile / 2 : kTile) + (int64_t)threadIdx.x * per;
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(gd.src, gd.E * 4), rd = buffer_rsrc(gd.dst, gd.E * 4);
+        int4 sv[4], dv[4];
 #pragma unroll
-    for (int r = 0; r < kRoundsW; ++r)
-        if (q.valid >> r & 1u) atomicAdd(&hist[q.key[r] >> shift], 1);
+        for (int k = 0; k < 4; ++k) {
+            if (4 * k < per) {
+                sv[k] = buf_i4(rs, (uint32_t)((e0 + 4 * k) * 4));
+                dv[k] = buf_i4(rd, (uint32_t)((e0 + 4 * k) * 4));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (4 * k >= per) break;
+            const int ss[4] = {sv[k].x, sv[k].y, sv[k].z, sv[k].w};
+            const int dd[4] = {dv[k].x, dv[k].y, dv[k].z, dv[k].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (e0 + 4 * k + j >= gd.E) continue;
+                const bool inr = (unsigned)ss[j] < N && (unsigned)dd[j] < N;
+                if (!inr) {
+                    badi |= chk;
+                    continue;
+                }
+                atomicAdd(&hist[(ss[j] + gd.node_off) >> shift], 1);
+                if (sym && ss[j] != dd[j]) atomicAdd(&hist[(dd[j] + gd.node_off) >> shift], 1);
+            }
+        }
+    } else {
+        const int wv = threadIdx.x >> 6;
+        bool badw = false;
+        Quarter<false> q;
+        load_quarter<false>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r)
+            if (q.valid >> r & 1u) atomicAdd(&hist[q.key[r] >> shift], 1);
+    }
     if (__syncthreads_or(badi) && threadIdx.x == 0) raise_error(status, kErrIndex);
     if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
 }
@@ -329,6 +374,49 @@ __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid) {
     return valid ? atomicAdd(&run[digit], 1) : 0;
 }
 
+// Positions of a wavefront's R rounds of items (round r: digit[r], valid bit r), in round
+// and lane order. Without bal, wave_rank per item. With bal, the same stable positions
+// without relying on the order in which the LDS serves the lanes of one atomic instruction
+// that hit one word: the lanes of a round with the same digit find each other by ballots
+// over the digit's nbits bits; the last of them alone adds their count to the digit's
+// running position (so no two lanes of an instruction touch one word), and each peer takes
+// the returned base, read from that lane, plus the number of peers below it. The LDS
+// operations of one wavefront take effect in program order, so each round sees the
+// additions of the rounds before it; all rounds' adds are issued before any base is read,
+// so no round waits for the previous one's LDS round trip. The CSR build (its bit-exact
+// contract) ranks this way; the bucket path, whose entry order only sets the
+// floating-point summation order, takes wave_rank.
+#ifndef GEE_CSR_RANK_BALLOT
+#define GEE_CSR_RANK_BALLOT 1
+#endif
+template <int R>
+__device__ __forceinline__ void wave_ranks(int *run, const int (&digit)[R], unsigned valid, int nbits, int bal,
+                                           int (&pos)[R]) {
+    if (!bal) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) pos[r] = wave_rank(run, digit[r], valid >> r & 1u);
+        return;
+    }
+    int below[R], last[R], b0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool v = valid >> r & 1u;
+        uint64_t peers = ballot(v);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (digit[r] >> b) & 1;
+            const uint64_t m = ballot(v && bit);
+            peers &= bit ? m : ~m;
+        }
+        below[r] = count_below(peers);
+        const int cnt = __popcll(peers);
+        last[r] = v ? 63 - __clzll(peers) : lane_id();
+        b0[r] = 0;
+        if (v && below[r] == cnt - 1) b0[r] = atomicAdd(&run[digit[r]], cnt);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) pos[r] = __shfl(b0[r], last[r], 64) + below[r];
+}
+
 // Pass A scatter: tile t of the virtual entries, sorted by high digit in LDS (wave-split
 // ranking over the wavefront's registers) and written to seg_start[d] + (scanned tile
 // offset) in runs. The key written keeps only the bits the later passes read (amask): the
@@ -339,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
                                                       AK *__restrict__ okey, int amask, int *__restrict__ ocol,
                                                       float *__restrict__ oval, unsigned *status, int with_b, int B,
                                                       int *__restrict__ seg_start, int *__restrict__ tile_off,
-                                                      int *__restrict__ bstart, int *__restrict__ meta) {
+                                                      int *__restrict__ bstart, int *__restrict__ meta, int bal) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = xcd_order(blockIdx.x, T);
@@ -376,22 +464,24 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     }
     const int gb = (int)threadIdx.x < D ? st + gh[(int64_t)threadIdx.x * T + t] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
+    int dg[kRoundsW], pos[kRoundsW];
+#pragma unroll
+    for (int r = 0; r < kRoundsW; ++r) dg[r] = (q.valid >> r & 1u) ? (q.key[r] >> shift) : 0;
+    wave_ranks<kRoundsW>(L.cnt[wv], dg, q.valid, nbits, bal, pos);
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
-        const bool valid = q.valid >> r & 1u;
-        const int digit = valid ? (q.key[r] >> shift) : 0;
-        const int pos = wave_rank(L.cnt[wv], digit, valid);
-        if (valid) {
-            L.key[pos] = (AK)(q.key[r] & amask);
-            L.dig[pos] = (unsigned char)digit;
-            L.col[pos] = q.col[r];
-            if (oval) L.val[pos] = q.val[r];
+        if ((q.valid >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
+            L.key[pos[r]] = (AK)(q.key[r] & amask);
+            L.dig[pos[r]] = (unsigned char)dg[r];
+            L.col[pos[r]] = q.col[r];
+            if (oval) L.val[pos[r]] = q.val[r];
         }
     }
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int d = L.dig[i];
         const int64_t g2 = (int64_t)L.gbase[d] + (i - L.lstart[d]);
+        if (!dbg_ok(g2 >= 0 && g2 < V, status)) continue;
         okey[g2] = L.key[i];
         ocol[g2] = L.col[i];
         if (oval) oval[g2] = L.val[i];
@@ -520,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
                                                    const int *__restrict__ gh, const int *__restrict__ seg_start,
                                                    const int *__restrict__ tile_off, int D,
                                                    uint16_t *__restrict__ okey, int *__restrict__ ocol,
-                                                   float *__restrict__ oval) {
+                                                   float *__restrict__ oval, unsigned *status, int bal) {
     __shared__ PartLds<uint16_t> L;
     int d, jt, ntd;
     if (!b_tile(tile_off, D, (int)xcd_order(blockIdx.x, tile_off[D]), d, jt, ntd)) return;
@@ -549,22 +639,29 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
     __syncthreads();
     const int gb = (int)threadIdx.x < ND ? s0 + seg[((int64_t)jt << dbits) + threadIdx.x] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
+    int dg[kRoundsW], pos[kRoundsW];
+    unsigned vmask = 0;
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
         const bool valid = ew + r * 64 + lane < e1;
-        const int digit = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
-        const int pos = wave_rank(L.cnt[wv], digit, valid);
-        if (valid) {
-            if (!FINAL) L.key[pos] = (uint16_t)(kr[r] & kmask);
-            L.dig[pos] = (unsigned char)digit;
-            L.col[pos] = cr[r];
-            if (oval) L.val[pos] = vr[r];
+        vmask |= valid ? (1u << r) : 0u;
+        dg[r] = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
+    }
+    wave_ranks<kRoundsW>(L.cnt[wv], dg, vmask, dbits, bal, pos);
+#pragma unroll
+    for (int r = 0; r < kRoundsW; ++r) {
+        if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
+            if (!FINAL) L.key[pos[r]] = (uint16_t)(kr[r] & kmask);
+            L.dig[pos[r]] = (unsigned char)dg[r];
+            L.col[pos[r]] = cr[r];
+            if (oval) L.val[pos[r]] = vr[r];
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int dg = L.dig[i];
         const int64_t g = (int64_t)L.gbase[dg] + (i - L.lstart[dg]);
+        if (!dbg_ok(g >= s0 && g < (int64_t)s0 + nseg, status)) continue;
         if (!FINAL) okey[g] = L.key[i];
         ocol[g] = L.col[i];
         if (oval) oval[g] = L.val[i];
@@ -609,7 +706,8 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
                                                    const float *__restrict__ tval,
                                                    const int *__restrict__ bstart, int B, int sb, int N,
                                                    int *__restrict__ rp, int *__restrict__ col,
-                                                   float *__restrict__ val, int cap, int pass_c) {
+                                                   float *__restrict__ val, int cap, int pass_c, unsigned *status,
+                                                   int bal) {
     extern __shared__ int smem_i[];
     __shared__ int wsum[4];
     const int R = 1 << sb;
@@ -677,13 +775,20 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         }
         if (b == B - 1 && threadIdx.x == 0) rp[N] = e1;
         __syncthreads();
+        int dg[kSortRoundsW], pos[kSortRoundsW];
+        unsigned vmask = 0;
 #pragma unroll
         for (int r = 0; r < kSortRoundsW; ++r) {
             const bool valid = ew + r * 64 + lane < ee;
-            const int pos = wave_rank(cnt + wv * R, valid ? kr[r] : 0, valid);
-            if (valid) {
-                scol2[pos] = cr[r];
-                if (val) sval2[pos] = vr[r];
+            vmask |= valid ? (1u << r) : 0u;
+            dg[r] = valid ? kr[r] : 0;
+        }
+        wave_ranks<kSortRoundsW>(cnt + wv * R, dg, vmask, sb, bal, pos);
+#pragma unroll
+        for (int r = 0; r < kSortRoundsW; ++r) {
+            if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < n, status)) {
+                scol2[pos[r]] = cr[r];
+                if (val) sval2[pos[r]] = vr[r];
             }
         }
         __syncthreads();
@@ -711,7 +816,7 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         const int cl = tcol[ec];
         const float vv = val ? tval[ec] : 0.0f;
         const int pos = block_rank4(digit, valid, sb, tab, run, R);
-        if (valid) {
+        if (valid && dbg_ok(pos >= 0 && pos < e1 - e0, status)) {
             if (staged) {
                 scol[pos] = cl;
                 if (val) sval[pos] = vv;
@@ -753,8 +858,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     float *aval = p.weighted ? (with_b ? wk.val : wk.tval) : nullptr;
     hipError_t e;
     prof_begin(kKAHist, s);
+    // one graph with 16-byte aligned src and dst: a_hist reads 4 edges per load
+    const bool vec = b.tab == nullptr && ((reinterpret_cast<uintptr_t>(b.one.src) | reinterpret_cast<uintptr_t>(b.one.dst)) & 15) == 0 &&
+                     b.one.E * 4 + 64 < (int64_t)0xFFFFFFFF;
     hipLaunchKernelGGL(a_hist, dim3((unsigned)p.TA + xslices), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, p.TA,
-                       wk.ghA, status, job ? job->part : nullptr);
+                       wk.ghA, status, job ? job->part : nullptr, vec ? 1 : 0);
     prof_end(kKAHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKAScan, s);
@@ -765,17 +873,20 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // pass A keys: the row's low sb + s2 bits, as u16 when they fit
     const bool k16 = p.sb + p.s2 <= 16;
+    // ranks: the CSR build keeps its bit-exact stable order without relying on the LDS's
+    // lane order (wave_ranks with bal); the bucket path takes the faster wave_rank
+    const int bal = p.bucket ? 0 : GEE_CSR_RANK_BALLOT;
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     prof_begin(kKAScatter, s);
     const int wb = with_b ? 1 : 0;
     if (k16) {
         hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status, wb, p.B,
-                           wk.segA, wk.tileB, wk.bstart, wk.meta);
+                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal);
     } else {
         hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, wk.akey, -1, acol, aval, status, wb, p.B, wk.segA, wk.tileB,
-                           wk.bstart, wk.meta);
+                           wk.bstart, wk.meta, bal);
     }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -798,11 +909,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if (k16) {
         hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
                            aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr);
+                           p.weighted ? wk.tval : nullptr, status, bal);
     } else {
         hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
                            p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr);
+                           p.weighted ? wk.tval : nullptr, status, bal);
     }
     prof_end(kKBScatter, s);
     return hipGetLastError();
@@ -812,7 +923,8 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
 // workgroup): the same segment partition with the row inside the bucket as the digit,
 // straight into the CSR; then bucket_sort for all other buckets.
 template <typename KT>
-static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, int cap, hipStream_t s) {
+static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, int cap, unsigned *status,
+                                hipStream_t s) {
     const float *tv = p.weighted ? wk.tval : nullptr;
     float *ov = p.weighted ? wk.val : nullptr;
     prof_begin(kKCTiles, s);
@@ -832,13 +944,12 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);
     hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(kThreads), 0, s, key, wk.tcol, tv, 0, p.sb,
-                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov);
+                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT);
     prof_end(kKCScatter, s);
     return hipGetLastError();
 }
 
 hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hipStream_t s) {
-    (void)status;
     const size_t lds = bucket_sort_lds(p.sb);
     const int cap = bucket_stage_cap(p.sb);
     const float *tv = p.weighted ? wk.tval : nullptr;
@@ -848,17 +959,17 @@ hipError_t launch_csr_pass2(const Plan &p, const Work &wk, unsigned *status, hip
     const uint16_t *akey16 = reinterpret_cast<const uint16_t *>(wk.akey);
     hipError_t e = hipSuccess;
     if (pass_c) {
-        e = (p.s2 > 0 || k16) ? launch_pass_c<uint16_t>(p.s2 > 0 ? wk.tkey : akey16, p, wk, cap, s)
-                              : launch_pass_c<int>(wk.akey, p, wk, cap, s);
+        e = (p.s2 > 0 || k16) ? launch_pass_c<uint16_t>(p.s2 > 0 ? wk.tkey : akey16, p, wk, cap, status, s)
+                              : launch_pass_c<int>(wk.akey, p, wk, cap, status, s);
         if (e != hipSuccess) return e;
     }
     prof_begin(kKBucketSort, s);
     if (p.s2 > 0 || k16) {
         hipLaunchKernelGGL(bucket_sort<uint16_t>, dim3(p.B), dim3(256), lds, s, p.s2 > 0 ? wk.tkey : akey16, wk.tcol,
-                           tv, wk.bstart, p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
+                           tv, wk.bstart, p.B, p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c, status, GEE_CSR_RANK_BALLOT);
     } else {
         hipLaunchKernelGGL(bucket_sort<int>, dim3(p.B), dim3(256), lds, s, wk.akey, wk.tcol, tv, wk.bstart, p.B,
-                           p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c);
+                           p.sb, (int)p.Ntot, wk.rp, wk.col, ov, cap, pass_c, status, GEE_CSR_RANK_BALLOT);
     }
     prof_end(kKBucketSort, s);
     return hipGetLastError();

@@ -699,7 +699,8 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
                 if ((P.stm >> j) & 1) {
                     slot_meta[sl[j]] = make_int2(P.r[j], __float_as_int(lap ? P.s[j] : 1.0f));
                     // the slot is clear and no entry of the row has been added yet
-                    if (diag) acc[sl[j] * KP + __float_as_int(P.q[j].y)] = P.q[j].x;
+                    const int ya = sl[j] * KP + __float_as_int(P.q[j].y);
+                    if (diag && dbg_ok(ya >= 0 && ya < RS * KP, status)) acc[ya] = P.q[j].x;
                 }
             }
         }
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(256, GEE_EMBED_MIN_WAVES) void embed_rows(Batch b, 
                 ad[j] = sl[j] * KP + __float_as_int(P.f[j].y);
                 xv[j] = act ? (WEIGHTED ? P.v[j] * P.f[j].x : P.f[j].x) : 0.0f;
             }
-            lds_tag_add<EPL>(acc, tag, ad, xv, lane);
+            lds_tag_add<EPL>(acc, tag, ad, xv, lane, -1, RS * KP, status);
         }
         // segments of this range: the open row unless the range starts a row, then the
         // new rows; all but the last end here, the last unless the next entry continues it

@@ -152,6 +152,25 @@ __device__ __forceinline__ void raise_error(unsigned *status, unsigned bit) {
     if (status) atomicOr(status, bit);
 }
 
+// Internal-consistency checks of GEE_DEBUG=1 builds: before an LDS slot, a staging position
+// or an output position that the kernels compute themselves is used, it is checked against
+// its array; a violation skips the access and raises kErrInternal (GEE_DATA_INTERNAL) in the
+// call's data-error word. Release builds compile the checks away (dbg_ok is true).
+#ifndef GEE_DEBUG
+#define GEE_DEBUG 0
+#endif
+constexpr unsigned kErrInternal = 1u << 30;
+__device__ __forceinline__ bool dbg_ok(bool cond, unsigned *status) {
+#if GEE_DEBUG
+    if (!cond) raise_error(status, kErrInternal);
+    return cond;
+#else
+    (void)cond;
+    (void)status;
+    return true;
+#endif
+}
+
 // ----------------------------------------------------------------------------- shared by the embed paths
 
 // Floats per slot of the embed ring: K rounded up to a multiple of 4 (16-byte rows).
@@ -197,8 +216,13 @@ __device__ __forceinline__ unsigned buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t of
 // lose, and losing costs an atomic, never a wrong sum.
 template <int N>
 __device__ __forceinline__ void lds_tag_add(float *acc, unsigned char *tag, const int (&ad)[N],
-                                            const float (&xv)[N], int lane, int tmask = -1) {
+                                            const float (&xv0)[N], int lane, int tmask = -1,
+                                            int limit = 0x7FFFFFFF, unsigned *status = nullptr) {
     static_assert(N <= 4, "entry ids must fit a byte");
+    float xv[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j)  // (GEE_DEBUG: words outside acc[0, limit) are dropped and reported)
+        xv[j] = (xv0[j] != 0.0f && !dbg_ok(ad[j] >= 0 && ad[j] < limit, status)) ? 0.0f : xv0[j];
 #pragma unroll
     for (int j = 0; j < N; ++j)
         if (xv[j] != 0.0f) tag[ad[j] & tmask] = (unsigned char)(N * lane + j);
@@ -273,6 +297,7 @@ struct Batch {
     const int *cnt_offs = nullptr;      // [G + 1]
     const int *class_offs = nullptr;    // [G + 1]
     GMeta *gm = nullptr;                // [G]
+    unsigned *status = nullptr;         // the call's data-error word (kernels without their own)
 };
 
 __device__ __forceinline__ bool validates(const GDesc &d) { return !(d.flags & kNoValidate); }
@@ -369,6 +394,7 @@ struct Work {
     int *bmeta = nullptr;      // [4]: parts, buckets of several parts
     float *dpart = nullptr;    // [bslots * 64] partial degrees
     float *zpart = nullptr;    // [bslots << sb * Kmax] partial class sums
+    int *rcnt = nullptr;       // [N] non-zero entries of each Z row (sparse Z of one graph), or nullptr
 };
 
 // ----------------------------------------------------------------------------- class counts
@@ -486,7 +512,9 @@ hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int
 // Sparse storage of a dense Z (gee_zsparse.hip): scratch of one int per tile of rows and
 // one per row, then row_ptr[N + 1] and at most `cap` (class, value) pairs.
 int zsparse_tiles(int N);
+// counts_given: rcnt already holds every row's non-zero count (written by the class-scatter
+// kernels), so the count pass over Z is skipped.
 hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
-                          int64_t cap, hipStream_t s);
+                          int64_t cap, bool counts_given, hipStream_t s);
 
 }  // namespace gee

@@ -67,6 +67,18 @@ __global__ __launch_bounds__(kZB) void zs_count(const float *__restrict__ Z, int
     if (threadIdx.x == 0) tile_tot[blockIdx.x] = tot;
 }
 
+// Per tile, with the row counts already known (written by the class-scatter kernels): the
+// tile's total alone (4 bytes a row instead of a pass over Z).
+__global__ __launch_bounds__(kZB) void zs_tile_sum(const int *__restrict__ row_cnt, int N, int *__restrict__ tile_tot) {
+    __shared__ int wsum[kZB / 64];
+    const int64_t base = (int64_t)blockIdx.x * kZT;
+    int n = 0;
+    for (int r = threadIdx.x; r < kZT; r += kZB) n += base + r < N ? row_cnt[base + r] : 0;
+    int tot = 0;
+    (void)block_excl_scan<kZB>(n, wsum, tot);
+    if (threadIdx.x == 0) tile_tot[blockIdx.x] = tot;
+}
+
 // One workgroup of 1024 threads: tile_tot becomes exclusive offsets; the total is row_ptr[N].
 __global__ __launch_bounds__(1024) void zs_scan(int *__restrict__ tile_tot, int T, int *__restrict__ row_ptr, int N) {
     __shared__ int wsum[1024 / 64];
@@ -140,9 +152,12 @@ __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int
 
 template <int L>
 hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
-                     int64_t cap, hipStream_t s) {
+                     int64_t cap, bool counts_given, hipStream_t s) {
     prof_begin(kKZsCount, s);
-    hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile);
+    if (counts_given)
+        hipLaunchKernelGGL(zs_tile_sum, dim3((unsigned)T), dim3(kZB), 0, s, rcnt, N, tile);
+    else
+        hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile);
     prof_end(kKZsCount, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -159,17 +174,17 @@ hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, 
 int zsparse_tiles(int N) { return (N + kZT - 1) / kZT; }
 
 hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
-                          int64_t cap, hipStream_t s) {
+                          int64_t cap, bool counts_given, hipStream_t s) {
     const int T = zsparse_tiles(N);
     const int L = K > 32 ? 64 : K > 16 ? 32 : K > 8 ? 16 : K > 4 ? 8 : K > 2 ? 4 : K > 1 ? 2 : 1;
     switch (L) {
-        case 64: return launch_zs<64>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        case 32: return launch_zs<32>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        case 16: return launch_zs<16>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        case 8: return launch_zs<8>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        case 4: return launch_zs<4>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        case 2: return launch_zs<2>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
-        default: return launch_zs<1>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, s);
+        case 64: return launch_zs<64>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        case 32: return launch_zs<32>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        case 16: return launch_zs<16>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        case 8: return launch_zs<8>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        case 4: return launch_zs<4>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        case 2: return launch_zs<2>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
+        default: return launch_zs<1>(Z, N, K, T, tile, rcnt, row_ptr, col, val, cap, counts_given, s);
     }
 }
 

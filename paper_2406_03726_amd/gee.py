@@ -22,6 +22,7 @@ GEE_SYMMETRIZE = 1 << 3
 GEE_DIRECTED_DEGREES = 1 << 4
 GEE_NO_VALIDATE = 1 << 8
 
+GEE_DATA_INTERNAL = 1 << 30  # GEE_DEBUG builds only
 GEE_DATA_LABEL = 1 << 0
 GEE_DATA_INDEX = 1 << 1
 GEE_DATA_WEIGHT = 1 << 2

@@ -24,6 +24,7 @@ GPU backend or, in tests, by a simulated one on a virtual clock.
 
 from __future__ import annotations
 
+import ctypes
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -329,12 +330,26 @@ class GpuBackend(Backend):
     counts, degrees and the class scatter, no sort), the iterative use of GEE with changing
     labels. Such requests run in the same batches, on the same stream, one call each."""
 
-    def __init__(self, slots: int = 4, table=None):
+    def __init__(self, slots: int = 4, table=None, use_plans: bool = False, plan_reserve: int = 256 << 20,
+                 sync_inputs: bool = True):
         import torch
 
-        from . import gee
+        from . import _lib, gee
 
         self._torch = torch
+        self._lib = _lib
+        # sync_inputs: each batch's stream first waits for the submitting stream (the requests'
+        # inputs may still be in flight there); a caller whose inputs are all complete before
+        # they are submitted (a staged pool) can turn it off
+        self.sync_inputs = sync_inputs
+        # use_plans: each slot keeps one batch plan (a captured launch sequence) and gives it
+        # every batch of edge-list requests with gee_batch_plan_update (no allocation while
+        # the batch fits the plan's workspace, reserved at plan_reserve bytes or more)
+        self.use_plans = use_plans
+        self.plan_reserve = int(plan_reserve)
+        self._plans = [None] * slots
+        # host seconds spent in launch() and finish(), and their calls (for measurements)
+        self.host_s = {"launch": 0.0, "finish": 0.0, "launches": 0}
         self._gee = gee
         self.slots = slots
         self._streams = None  # made at the first launch (sizing needs no device)
@@ -343,6 +358,7 @@ class GpuBackend(Backend):
         self.in_use_actual = 0
         self.peak_actual = 0
         self.resident: Dict[Any, Dict[str, Any]] = {}
+        self._ws = [None] * slots  # per slot: grow-only workspace (one batch per slot at a time)
 
     @property
     def streams(self):
@@ -384,8 +400,23 @@ class GpuBackend(Backend):
             return g["sched"]
         if self.table is None:
             return None
-        s = self.table.lookup(g["src"].numel(), g["labels"].numel(), int(g["K"]), int(g["flags"]))
-        return s or None
+        # the lookup depends on the graph's sizes alone: kept with the graph
+        key = ("_gee_sched", id(self.table))
+        if key not in g:
+            g[key] = self.table.lookup(g["src"].numel(), g["labels"].numel(), int(g["K"]), int(g["flags"])) or None
+        return g[key]
+
+    def _struct(self, r: Request, Z):
+        """The request's gee_graph with its output Z: the graph's part is checked and built
+        once (by the binding) and kept with the graph."""
+        g = r.graph
+        key = ("_gee_struct", id(self.table))
+        if key not in g:
+            g[key] = self._gee._graph_struct(dict(g, Z=None, sched=self.sched_of(g)), g["labels"].device,
+                                             sizing=True)
+        st = self._lib.GeeGraph.from_buffer_copy(g[key])
+        st.Z = Z.data_ptr()
+        return st
 
     def _item(self, r: Request, Z=None):
         g = r.graph
@@ -414,11 +445,29 @@ class GpuBackend(Backend):
             r.N = int(g["labels"].numel())
         return self.batch_footprint([r])
 
-    def batch_footprint(self, reqs: List[Request]) -> int:
+    def _ws_bytes(self, reqs: List[Request]) -> int:
+        """Workspace of a batch: the library's size for exactly these graphs (a graph alone
+        keeps its own size with it)."""
         edge = [r for r in reqs if "resident" not in r.graph]
-        ws = self._gee.batch_workspace_bytes_of_sizes([self._sizes(r) for r in edge]) if edge else 0
-        ws += sum(self._csr_ws_bytes(r) for r in reqs if "resident" in r.graph)
-        return int(ws) + sum(4 * r.N * int(r.graph["K"]) for r in reqs)
+        if len(edge) == 1:
+            g = edge[0].graph
+            key = ("_gee_ws1", id(self.table))
+            if key not in g:
+                g[key] = int(self._gee.batch_workspace_bytes_of_sizes([self._sizes(edge[0])]))
+            ws = g[key]
+        else:
+            ws = int(self._gee.batch_workspace_bytes_of_sizes([self._sizes(r) for r in edge])) if edge else 0
+        return ws + sum(self._csr_ws_bytes(r) for r in reqs if "resident" in r.graph)
+
+    def batch_footprint(self, reqs: List[Request]) -> int:
+        return self._ws_bytes(reqs) + sum(4 * r.N * int(r.graph["K"]) for r in reqs)
+
+    def _workspace(self, slot: int, nbytes: int, dev):
+        w = self._ws[slot]
+        if w is None or w.numel() < nbytes:
+            w = self._torch.empty(max(nbytes, 1), dtype=self._torch.uint8, device=dev)
+            self._ws[slot] = w
+        return w
 
     def _embed_resident(self, r: Request, Z, s):
         g = r.graph
@@ -429,22 +478,50 @@ class GpuBackend(Backend):
         return ws
 
     def launch(self, reqs: List[Request], slot: int):
+        t0 = time.perf_counter()
+        h = self._launch(reqs, slot)
+        self.host_s["launch"] += time.perf_counter() - t0
+        self.host_s["launches"] += 1
+        return h
+
+    def _launch(self, reqs: List[Request], slot: int):
         torch = self._torch
         s = self.streams[slot]
         dev = reqs[0].graph["labels"].device
         # the requests' inputs were made on the submitting stream
-        s.wait_stream(torch.cuda.current_stream(dev))
+        if self.sync_inputs:
+            s.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(s):
             items, held_ws = [], []
             for r in reqs:
                 Z = torch.empty((r.N, int(r.graph["K"])), dtype=torch.float32, device=dev)
                 items.append(self._item(r, Z=Z) if "resident" not in r.graph else dict(Z=Z))
             edge = [it for r, it in zip(reqs, items) if "resident" not in r.graph]
-            if edge:
-                nbytes = self._gee.gee_embed_batch_workspace_bytes(edge)
-                ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-                self._gee.gee_embed_batch(edge, workspace=ws, stream=s)
-                held_ws.append(ws)
+            if edge and self.use_plans:
+                # the slot's batch plan takes this batch (the previous one on this slot has
+                # finished); a plan too small for it is replaced by a larger one
+                nbytes = self._ws_bytes([r for r in reqs if "resident" not in r.graph])
+                plan = self._plans[slot]
+                if plan is not None and plan.workspace_bytes >= nbytes:
+                    plan.update(edge)
+                else:
+                    if plan is not None:
+                        plan.destroy()
+                    plan = self._gee.BatchPlan(edge, workspace_bytes=max(nbytes, self.plan_reserve))
+                    self._plans[slot] = plan
+                plan.launch(stream=s)
+            elif edge:
+                # the slot's own workspace, grown to this batch's size (the library's size
+                # for exactly these graphs; the previous batch on this slot has finished)
+                er = [r for r in reqs if "resident" not in r.graph]
+                nbytes = self._ws_bytes(er)
+                ws = self._workspace(slot, nbytes, dev)
+                arr = (self._lib.GeeGraph * len(er))(*[self._struct(r, it["Z"]) for r, it in zip(er, edge)])
+                rc = self._lib.load().gee_embed_batch_ws(arr, len(er), ws.data_ptr(), nbytes,
+                                                         ctypes.c_void_p(s.cuda_stream))
+                if rc != 0:
+                    raise self._gee.GeeError(rc, "gee_embed_batch_ws")
+                held_ws.append(ws[:nbytes])
             for r, it in zip(reqs, items):
                 if "resident" in r.graph:
                     held_ws.append(self._embed_resident(r, it["Z"], s))
@@ -463,6 +540,13 @@ class GpuBackend(Backend):
         return handle[0].query()
 
     def finish(self, handle, reqs: List[Request]) -> None:
+        t0 = time.perf_counter()
+        try:
+            self._finish(handle, reqs)
+        finally:
+            self.host_s["finish"] += time.perf_counter() - t0
+
+    def _finish(self, handle, reqs: List[Request]) -> None:
         _, items, _, s, held, err = handle
         self.in_use_actual -= held
         bits = int(err[0])

@@ -115,3 +115,25 @@ def test_committed_traffic_is_at_least_the_algorithmic_bytes():
     assert d["copy_check"]["read_bytes"] == pytest.approx(1 << 30, rel=0.01)
     emb = d["kernels"]["bucket_embed"]["bytes"]
     assert emb > bench.step_bytes("a4_a6", 10_000_000, 600_000, 50, 20_000_000, True)
+
+
+def test_kernel_trace_summary(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path / "profiles"))
+    p = tmp_path / "trace.csv"
+    names = ["gee::a_hist(...)", "void gee::a_scatter<unsigned short>(...)", "gee::bucket_embed_fix(...)"]
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        t = 1000
+        for call, durs in enumerate(([10_000, 50_000, 5_000], [12_000, 70_000, 5_000], [11_000, 60_000, 7_000])):
+            for n, d in zip(names, durs):
+                w.writerow({"Kernel_Name": n, "Start_Timestamp": t, "End_Timestamp": t + d})
+                t += d + 500
+            w.writerow({"Kernel_Name": "void at::native::fill(...)", "Start_Timestamp": t, "End_Timestamp": t + 9})
+            t += 100_000
+    path = bench.write_trace(str(p), "wl", "cmd")
+    text = open(path).read()
+    d = json.loads(text[text.index("```json") + 7:text.rindex("```")])
+    assert d["calls"] == 3
+    assert d["kernels_us"] == {"a_hist": 11.0, "a_scatter": 60.0, "bucket_embed_fix": 5.0}
+    assert d["span_us"] == 79.0  # spans 66, 88 and 79 us

@@ -158,6 +158,29 @@ def test_batch_plan_update_reports_data_errors_of_the_new_set():
     plan.destroy()
 
 
+def test_batch_all_512_recipe_graphs_vs_oracle():
+    """Every graph of the 512-graph batched workload (about 232M edges), embedded in one
+    batch plan, against the FP64 oracle; a sample also against its plain call bitwise."""
+    import multiprocessing as mp
+
+    with mp.get_context("spawn").Pool(min(16, mp.cpu_count())) as pool:
+        gs = pool.map(batched_one, range(512), chunksize=4)
+    _label(f"all 512 batched graphs: {sum(g.E for g in gs)} edges")
+    items = _dev_graphs(gs)
+    plan = gee.BatchPlan(items)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert gee.gee_get_data_errors() == 0
+    plan.destroy()
+    worst = 0.0
+    for i, (it, g) in enumerate(zip(items, gs)):
+        worst = max(worst, assert_close(it["Z"], or_embed_graph(g), f"graph {i}"))
+    _label(f"all 512 batched graphs: max relative error {worst:.3e}")
+    sample = items[::37]
+    for i, (it, zp) in enumerate(zip(sample, _plain(sample))):
+        assert torch.equal(it["Z"], zp), f"sample {i}"
+
+
 def test_batch_recipe_sample():
     """Graphs of the 512-graph batched workload recipe (a sample of them), batched vs plain
     bitwise and vs the oracle."""

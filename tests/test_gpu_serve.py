@@ -127,3 +127,23 @@ def test_reembed_requests_on_resident_csrs():
             torch.cuda.synchronize()
             assert torch.equal(r.result, alone), f"re-embedding {i}"
         assert_close(r.result, or_embed_graph(x), f"request {i} vs oracle")
+
+
+def test_served_through_batch_plans_equals_alone():
+    """The backend's plan mode: every batch of a slot goes through that slot's batch plan
+    (gee_batch_plan_update, then a graph launch); results equal the plain calls bitwise."""
+    gs, dev = _pool(12, 200_000)
+    print("[gpu-test] serving through batch plans", flush=True)
+    be = GpuBackend(slots=2, use_plans=True, plan_reserve=64 << 20)
+    srv = GeeServer(be, 1 << 34, max_batch=5)
+    rng = np.random.default_rng(3)
+    reqs = [Request(i, d, float(a)) for i, (d, a) in enumerate(zip(dev + dev, np.cumsum(rng.exponential(2e-4, 24))))]
+    srv.run_trace(reqs, busy_poll=True)
+    torch.cuda.synchronize()
+    assert any(len(b) > 1 for b in srv.launch_log)
+    for i, r in enumerate(reqs):
+        d = r.graph
+        assert r.error is None
+        alone = gee.gee_embed(d["src"], d["dst"], d["w"], d["labels"], d["K"], d["flags"])
+        torch.cuda.synchronize()
+        assert torch.equal(r.result, alone), f"request {i}"
