@@ -633,7 +633,7 @@ const char *const kKernelNames[kKNumKernels] = {
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
     "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix",
-    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish", "zs_count", "zs_write"};
+    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish", "zs_count", "zs_write", "zs_tile_sum"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;

@@ -462,7 +462,7 @@ enum KernelId : int {
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
     kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKBucketPartCount, kKBucketPartFill, kKBucketDegree,
     kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKEdgeInit, kKEdgePrep, kKEdgeCoef, kKEdgeScatter,
-    kKEdgeFinish, kKZsCount, kKZsWrite, kKNumKernels
+    kKEdgeFinish, kKZsCount, kKZsWrite, kKZsTileSum, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);

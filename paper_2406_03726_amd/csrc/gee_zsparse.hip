@@ -153,12 +153,13 @@ __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int
 template <int L>
 hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
                      int64_t cap, bool counts_given, hipStream_t s) {
-    prof_begin(kKZsCount, s);
+    const int kid = counts_given ? kKZsTileSum : kKZsCount;
+    prof_begin(kid, s);
     if (counts_given)
         hipLaunchKernelGGL(zs_tile_sum, dim3((unsigned)T), dim3(kZB), 0, s, rcnt, N, tile);
     else
         hipLaunchKernelGGL(zs_count<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile);
-    prof_end(kKZsCount, s);
+    prof_end(kid, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zs_scan, dim3(1), dim3(1024), 0, s, tile, T, row_ptr, N);
