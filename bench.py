@@ -566,26 +566,27 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, 
                                  sched=g["sched"], workspace=ws, stream=stream)
         stream.synchronize()
 
-    # plain service time per pool graph -> saturation rate of the plain loop; the second
-    # call's result is the graph's reference result
-    svc, refs = [], []
-    for it in pool:
+    def service_ms(it, reps=3):
+        """Median of `reps` plain calls after one warm call; the last result is kept."""
         r = Request(0, it, 0.0)
         embed_one(r)
-        t1 = time.perf_counter()
-        embed_one(r)
-        svc.append(time.perf_counter() - t1)
-        refs.append(r.result)
-    mu = 1.0 / float(np.mean(svc))
-    # the pool's plain service time with the library's default schedules instead
-    svc_d = []
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            embed_one(r)
+            ts.append(time.perf_counter() - t1)
+        return float(np.median(ts)), r.result
+
+    # plain service time per pool graph -> saturation rate of the plain loop (its result is
+    # the graph's reference result), and beside it the same graph with the library's default
+    # schedules, measured the same way right after it
+    svc, svc_d, refs = [], [], []
     for it in pool:
-        r = Request(0, dict(it, sched=None), 0.0)
-        embed_one(r)
-        t1 = time.perf_counter()
-        embed_one(r)
-        svc_d.append(time.perf_counter() - t1)
-    r = None
+        t, z = service_ms(it)
+        svc.append(t)
+        refs.append(z)
+        svc_d.append(service_ms(dict(it, sched=None))[0])
+    mu = 1.0 / float(np.mean(svc))
     rng = np.random.default_rng(20240603)
     out = {"pool_graphs": pool_n, "pool_edges_mean": int(np.mean([it["src"].numel() for it in pool])),
            "generation_s": round(gen_s, 1), "requests_per_load": n_req, "slots": slots,
