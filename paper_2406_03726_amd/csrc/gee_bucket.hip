@@ -39,7 +39,8 @@ namespace gee {
 
 constexpr int BEPL = 4;          // consecutive entries per lane in a window
 constexpr int BWIN = 64 * BEPL;  // entries per window
-constexpr int kFixThreads = 256; // threads per split bucket when combining class sums
+constexpr int kFixThreads = 1024;  // threads per split bucket when combining class sums
+constexpr int kFixUnroll = 4;      // class sums per thread in flight together (R * K <= 4096)
 #ifndef GEE_EMBED_SCHED_BARRIER
 #define GEE_EMBED_SCHED_BARRIER 1
 #endif
@@ -52,17 +53,15 @@ static size_t bucket_lds(int sb, int Kmax) {
     return ((size_t)ring_stride(Kmax) << sb) * sizeof(float) + 64 * sizeof(float) + kTagBytes;
 }
 
-__device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
-
 // ----------------------------------------------------------------------------- part table
 
 // Part table order: the parts of split buckets first (at the index of their partial slot),
-// then the one-part buckets of more than P/4 entries, then the rest, each group in bucket
-// order, so the longest wavefronts start first.
-__device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 1 && 4 * n > P; }
+// then the one-part buckets of more than P/4 entries (large_single), then the rest, each
+// group in bucket order, so the longest wavefronts start first.
 
 // One thread per bucket: per-workgroup totals of parts, partial slots, split buckets and
-// large one-part buckets.
+// large one-part buckets (bucket_part_totals). After a pass B the pass-B scan has formed
+// them already (seg_scan) and this launch is skipped.
 __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                           int *__restrict__ ptot) {
     __shared__ int wsum[16];
@@ -77,7 +76,7 @@ __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__
     (void)block_excl_scan<1024>(k, wsum, t0);
     (void)block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
     (void)block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
-    (void)block_excl_scan<1024>(large_single(n, k, P) ? 1 : 0, wsum, t3);
+    (void)block_excl_scan<1024>(large_single(n, k, P) ? 1 : 0, wsum, t3);  // (the four totals of bucket_part_totals)
     if (threadIdx.x == 0) {
         ptot[4 * blockIdx.x] = t0;
         ptot[4 * blockIdx.x + 1] = t1;
@@ -548,8 +547,10 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
 }
 
 // Workgroups take the split buckets in turn (the grid is sized for the largest possible
-// count; far fewer are split): the parts' raw sums added in part order (four partial loads
-// in flight per thread), then the rows finished as in bucket_embed.
+// count; far fewer are split): the parts' raw sums added in part order, then the rows
+// finished as in bucket_embed. A thread takes kFixUnroll class sums of the bucket, and the
+// loads of four parts of all of them are in flight together; the finishing lanes load their
+// rows' coefficients first, so a bucket costs few dependent memory round trips.
 __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const int4 *__restrict__ multi,
                                                                 const int *__restrict__ bmeta, int sb,
                                                                 const float2 *__restrict__ info,
@@ -564,6 +565,10 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
         const GDesc gd = load_desc(b, find_graph(b.node_offs, b.G, r0));
         const int K = gd.K, KP = ring_stride(K), R = 1 << sb;
         const int t = threadIdx.x;
+        const int rl = r0 + t;
+        const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
+        const float2 q_own = own ? info[rl] : make_float2(0.0f, 0.0f);
+        const float s_own = own ? srow[rl] : 0.0f;
         float *acc = smem_b;
         float *fac = smem_b + R * KP;
         __syncthreads();  // the previous bucket's rows are written
@@ -574,28 +579,40 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
         }
         __syncthreads();
         const float *zp = zpart + (int64_t)m.y * zs;
-        for (int f = t; f < R * K; f += kFixThreads) {
-            const float *q = zp + f;
-            float s = 0.0f;
+        const int n = R * K;
+        for (int f0 = t; f0 < n; f0 += kFixUnroll * kFixThreads) {
+            float sum[kFixUnroll];
+#pragma unroll
+            for (int u = 0; u < kFixUnroll; ++u) sum[u] = 0.0f;
             int k = 0;
             for (; k + 4 <= m.z; k += 4) {
-                const float x0 = q[(int64_t)k * zs], x1 = q[(int64_t)(k + 1) * zs];
-                const float x2 = q[(int64_t)(k + 2) * zs], x3 = q[(int64_t)(k + 3) * zs];
-                s += x0;
-                s += x1;
-                s += x2;
-                s += x3;
+                float x[kFixUnroll][4];
+#pragma unroll
+                for (int u = 0; u < kFixUnroll; ++u) {
+                    const int f = min(f0 + u * kFixThreads, n - 1);  // (past n: a sum that is not kept)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x[u][j] = zp[(int64_t)(k + j) * zs + f];
+                }
+#pragma unroll
+                for (int u = 0; u < kFixUnroll; ++u)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sum[u] += x[u][j];
             }
-            for (; k < m.z; ++k) s += q[(int64_t)k * zs];
-            acc[(f / K) * KP + f % K] = s;
+            for (; k < m.z; ++k) {
+                float x[kFixUnroll];
+#pragma unroll
+                for (int u = 0; u < kFixUnroll; ++u) x[u] = zp[(int64_t)k * zs + min(f0 + u * kFixThreads, n - 1)];
+#pragma unroll
+                for (int u = 0; u < kFixUnroll; ++u) sum[u] += x[u];
+            }
+#pragma unroll
+            for (int u = 0; u < kFixUnroll; ++u) {
+                const int f = f0 + u * kFixThreads;
+                if (f < n) acc[(f / K) * KP + f % K] = sum[u];
+            }
         }
         __syncthreads();
-        if (t < 64) {
-            const int rl = r0 + t;
-            const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
-            finish_rows(gd, r0, R, KP, acc, fac, own ? info[rl] : make_float2(0.0f, 0.0f), own ? srow[rl] : 0.0f, t,
-                        b.status, rcnt);
-        }
+        if (t < 64) finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, t, b.status, rcnt);
         __syncthreads();
         write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
     }
@@ -639,9 +656,11 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
     const bool key16 = with_b || p.sb + p.s2 <= 16;
     const void *key = with_b ? (const void *)wk.tkey : (const void *)wk.akey;
     const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
-    prof_begin(kKBucketPartCount, s);
-    hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot);
-    prof_end(kKBucketPartCount, s);
+    if (!with_b) {  // (after a pass B its scan has written the block totals)
+        prof_begin(kKBucketPartCount, s);
+        hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot);
+        prof_end(kKBucketPartCount, s);
+    }
     prof_begin(kKBucketPartFill, s);
     hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
                        wk.multi, wk.bmeta);

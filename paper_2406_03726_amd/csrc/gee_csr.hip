@@ -214,7 +214,8 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
 
 // Per tile of virtual entries: histogram of the high digit (row >> shift), written
 // digit-major; index checks.
-// Workgroups past the T tiles are label slices of the class counts.
+// The first gridDim.x - T workgroups are label slices of the class counts (first, so that
+// their longer loops overlap the tiles instead of ending the launch).
 // With vec (one graph whose src and dst are 16-byte aligned and fit 32-bit buffer offsets)
 // each thread reads 4 edges per 16-byte load instead of one virtual entry per lane: the
 // tile's edges are the same (virtual entries 2e and 2e+1 are edge e under symmetrization),
@@ -223,17 +224,34 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
 #define GEE_AHIST_EDGES 1
 #endif
 static_assert(kTile % (kThreads * 8) == 0 && kTile / kThreads <= 16, "a_hist: whole 16-byte loads of edges per thread");
+// The tile histograms (a_hist, seg_hist) count into kHistCopies interleaved copies of each
+// digit's counter (word digit * kHistCopies + lane mod kHistCopies), summed at the end: lanes
+// of one instruction that hit the same digit then mostly hit different words, which the LDS
+// serves in one pass instead of one lane after another.
+#ifndef GEE_HIST_COPIES
+#define GEE_HIST_COPIES 4
+#endif
+constexpr int kHistCopies = GEE_HIST_COPIES;
+static_assert(kHistCopies >= 1 && kHistCopies <= 16 && (kHistCopies & (kHistCopies - 1)) == 0, "histogram copies");
+__device__ __forceinline__ int hist_sum(const int *hist, int d) {
+    int s = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) s += hist[d * kHistCopies + c];
+    return s;
+}
 __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift, int D, int64_t T,
                                                    int *__restrict__ gh, unsigned *status, int *__restrict__ cpart,
                                                    int vec) {
-    __shared__ int hist[256];
-    if ((int64_t)blockIdx.x >= T) {
-        class_count_slice(b, (int)(blockIdx.x - T), cpart, status, hist);
+    __shared__ int hist_all[256 * kHistCopies];
+    const int64_t nslices = (int64_t)gridDim.x - T;
+    if ((int64_t)blockIdx.x < nslices) {
+        class_count_slice(b, (int)blockIdx.x, cpart, status, hist_all);
         return;
     }
-    for (int i = threadIdx.x; i < 256; i += kThreads) hist[i] = 0;
+    for (int i = threadIdx.x; i < 256 * kHistCopies; i += kThreads) hist_all[i] = 0;
     __syncthreads();
-    const int64_t t = xcd_order(blockIdx.x, T);
+    int *hist = hist_all + (threadIdx.x & (kHistCopies - 1));  // digit d at hist[d * kHistCopies]
+    const int64_t t = xcd_order((int64_t)blockIdx.x - nslices, T);
     bool badi = false;
     if (GEE_AHIST_EDGES && vec) {
         const GDesc &gd = b.one;
@@ -264,8 +282,8 @@ __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift
                     badi |= chk;
                     continue;
                 }
-                atomicAdd(&hist[(ss[j] + gd.node_off) >> shift], 1);
-                if (sym && ss[j] != dd[j]) atomicAdd(&hist[(dd[j] + gd.node_off) >> shift], 1);
+                atomicAdd(&hist[((ss[j] + gd.node_off) >> shift) * kHistCopies], 1);
+                if (sym && ss[j] != dd[j]) atomicAdd(&hist[((dd[j] + gd.node_off) >> shift) * kHistCopies], 1);
             }
         }
     } else {
@@ -275,10 +293,10 @@ __global__ __launch_bounds__(kThreads) void a_hist(Batch b, int64_t V, int shift
         load_quarter<false>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
 #pragma unroll
         for (int r = 0; r < kRoundsW; ++r)
-            if (q.valid >> r & 1u) atomicAdd(&hist[q.key[r] >> shift], 1);
+            if (q.valid >> r & 1u) atomicAdd(&hist[(q.key[r] >> shift) * kHistCopies], 1);
     }
     if (__syncthreads_or(badi) && threadIdx.x == 0) raise_error(status, kErrIndex);
-    if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist[threadIdx.x];
+    if (threadIdx.x < D) gh[(int64_t)threadIdx.x * T + t] = hist_sum(hist_all, threadIdx.x);
 }
 
 // One workgroup per digit d: exclusive scan of the row gh[d*T .. d*T+T) in place;
@@ -427,7 +445,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
                                                       AK *__restrict__ okey, int amask, int *__restrict__ ocol,
                                                       float *__restrict__ oval, unsigned *status, int with_b, int B,
                                                       int *__restrict__ seg_start, int *__restrict__ tile_off,
-                                                      int *__restrict__ bstart, int *__restrict__ meta, int bal) {
+                                                      int *__restrict__ bstart, int *__restrict__ meta, int bal,
+                                                      int *__restrict__ ptot) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = xcd_order(blockIdx.x, T);
@@ -461,6 +480,7 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
             bstart[B] = total;
             meta[0] = total;
         }
+        if (ptot) ptot[d] = 0;  // 64 blocks x 4 totals, formed by the pass-B scan
     }
     const int gb = (int)threadIdx.x < D ? st + gh[(int64_t)threadIdx.x * T + t] : 0;
     const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
@@ -518,12 +538,13 @@ template <typename KT>
 __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int dshift, int dbits,
                                                 const int *__restrict__ seg_start, const int *__restrict__ tile_off,
                                                 int D, int *__restrict__ gh) {
-    __shared__ int hist[256];
+    __shared__ int hist_all[256 * kHistCopies];
     int d, jt, ntd;
     if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
     const int L = 1 << dbits;
-    hist[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < 256 * kHistCopies; i += 256) hist_all[i] = 0;
     __syncthreads();
+    int *hist = hist_all + (threadIdx.x & (kHistCopies - 1));
     const int e0 = seg_start[d] + jt * kTile;
     const int e1 = min(e0 + kTile, seg_start[d + 1]);
     int k[kRounds];
@@ -531,9 +552,9 @@ __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int 
     for (int r = 0; r < kRounds; ++r) k[r] = (int)key[min(e0 + r * 256 + (int)threadIdx.x, e1 - 1)];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r)
-        if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[(k[r] >> dshift) & (L - 1)], 1);
+        if (e0 + r * 256 + (int)threadIdx.x < e1) atomicAdd(&hist[((k[r] >> dshift) & (L - 1)) * kHistCopies], 1);
     __syncthreads();
-    if ((int)threadIdx.x < L) gh[(((int64_t)tile_off[d] + jt) << dbits) + threadIdx.x] = hist[threadIdx.x];
+    if ((int)threadIdx.x < L) gh[(((int64_t)tile_off[d] + jt) << dbits) + threadIdx.x] = hist_sum(hist_all, threadIdx.x);
 }
 
 // One workgroup per segment d: every (tile, digit) count becomes the position of that
@@ -542,9 +563,15 @@ __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int 
 // `limit`). A thread per digit walks the tile rows (coalesced across the digits); four
 // groups of threads take a quarter of the tiles each. With skip_untiled, segments
 // without tiles are left alone (pass C: those buckets are sorted whole by bucket_sort).
+//
+// With ptot (pass B of the bucket path), the segment's buckets (2^dbits of them, inside one
+// block of 1024 buckets) also add their part-table totals to that block's four counters
+// (parts, partial slots, split buckets, large one-part buckets; integer atomics, so the sums
+// do not depend on the order); ptot was cleared by the pass-A scatter.
 __global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits, const int *__restrict__ seg_start,
                                                  const int *__restrict__ tile_off, int limit,
-                                                 int *__restrict__ starts, int skip_untiled) {
+                                                 int *__restrict__ starts, int skip_untiled, Batch b, int sb,
+                                                 int *__restrict__ ptot) {
     __shared__ int part[4][256];
     __shared__ int dstart[256];
     __shared__ int wsum[16];
@@ -595,8 +622,27 @@ __global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits
     }
     const int s0 = seg_start[d];
     if ((int)threadIdx.x < L) {
-        const int64_t b = ((int64_t)d << dbits) + threadIdx.x;
-        if (b < limit) starts[b] = s0 + dstart[threadIdx.x];
+        const int64_t bk = ((int64_t)d << dbits) + threadIdx.x;
+        if (bk < limit) starts[bk] = s0 + dstart[threadIdx.x];
+    }
+    if (ptot && threadIdx.x < 256) {
+        const int bk = (d << dbits) + dig;
+        int k = 0, n = 0, P = 1;
+        if (dig < L && bk < limit) {
+            n = dsum;
+            P = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
+            k = parts_of(n, P);
+        }
+        const int v0 = readlane(wave_scan_add(k), 63), v1 = readlane(wave_scan_add(k > 1 ? k : 0), 63);
+        const int v2 = readlane(wave_scan_add(k > 1 ? 1 : 0), 63);
+        const int v3 = readlane(wave_scan_add(large_single(n, k, P) ? 1 : 0), 63);
+        if (lane_id() == 0 && (v0 | v1 | v2 | v3)) {
+            int *q = ptot + 4 * ((d << dbits) >> 10);
+            atomicAdd(q, v0);
+            atomicAdd(q + 1, v1);
+            atomicAdd(q + 2, v2);
+            atomicAdd(q + 3, v3);
+        }
     }
 }
 
@@ -877,16 +923,18 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     // lane order (wave_ranks with bal); the bucket path takes the faster wave_rank
     const int bal = p.bucket ? 0 : GEE_CSR_RANK_BALLOT;
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
+    // the bucket path's part-table block totals, formed by the pass-B scan
+    int *ptot = (p.bucket && with_b) ? wk.ptot : nullptr;
     prof_begin(kKAScatter, s);
     const int wb = with_b ? 1 : 0;
     if (k16) {
         hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status, wb, p.B,
-                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal);
+                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal, ptot);
     } else {
         hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, wk.akey, -1, acol, aval, status, wb, p.B, wk.segA, wk.tileB,
-                           wk.bstart, wk.meta, bal);
+                           wk.bstart, wk.meta, bal, ptot);
     }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -902,7 +950,8 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_end(kKBHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScan, s);
-    hipLaunchKernelGGL(seg_scan, dim3(p.DA), dim3(1024), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart, 0);
+    hipLaunchKernelGGL(seg_scan, dim3(p.DA), dim3(1024), 0, s, wk.ghB, p.s2, wk.segA, wk.tileB, p.B, wk.bstart, 0, b,
+                       p.sb, ptot);
     prof_end(kKBScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
@@ -939,7 +988,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScan, s);
     hipLaunchKernelGGL(seg_scan, dim3(p.B), dim3(1024), 0, s, wk.ghC, p.sb, wk.bstart, wk.tileC, (int)p.Ntot, wk.rp,
-                       1);
+                       1, Batch{}, 0, nullptr);
     prof_end(kKCScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);

@@ -416,16 +416,31 @@ __device__ __forceinline__ void class_count_slice(const Batch &b, int j, int *__
     const int64_t lo = (int64_t)jb * per;
     const int64_t hi = min((int64_t)d.N, lo + per);
     bool bad = false;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const int y = d.labels[i];
-        if (y >= 0 && y < K)
-            atomicAdd(&hist[y], 1);
-        else if (y != -1 && validates(d))
-            bad = true;
+    // 8 labels per thread in flight together (positions past the slice read as unknown)
+    constexpr int U = 8;
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (int64_t)U * blockDim.x) {
+        int y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            y[u] = i < hi ? d.labels[i] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (y[u] >= 0 && y[u] < K)
+                atomicAdd(&hist[y[u]], 1);
+            else if (y[u] != -1 && validates(d))
+                bad = true;
+        }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) raise_error(status, kErrLabel);
     for (int k = threadIdx.x; k < K; k += blockDim.x) part[d.cpart_off + (int64_t)jb * K + k] = hist[k];
 }
+
+// Parts of a bucket of n entries with part size P, and whether it is a one-part bucket of
+// more than P/4 entries (listed before the short ones in the part table).
+__device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
+__device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 1 && 4 * n > P; }
 
 // One wavefront: class c of the launch (all graphs' classes in order).
 __device__ __forceinline__ void class_count_total(const Batch &b, int c, const int *__restrict__ part,
