@@ -360,6 +360,7 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         w.segA = (int *)take((size_t)(p.DA + 1) * sizeof(int));
         w.tileB = (int *)take((size_t)(p.DA + 1) * sizeof(int));
         if (p.s2 > 0) w.ghB = (int *)take(((size_t)p.TBcap << p.s2) * sizeof(int));
+        if (p.s2 > 0) w.segB = (int *)take((size_t)p.TBcap * sizeof(int));
         w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
         w.tileC = (int *)take((size_t)(p.B + 1) * sizeof(int));
         w.ghC = (int *)take(((size_t)p.TCcap << p.sb) * sizeof(int));

@@ -348,17 +348,17 @@ __global__ __launch_bounds__(1024) void digit_scan(int *__restrict__ gh, int64_t
 template <typename KS>
 struct PartLds {
     int cnt[kWaves][256];  // per-wavefront digit counts, then running positions
-    int lstart[256], gbase[256], wsum[kWaves];
+    int gdelta[256], wsum[kWaves];  // gdelta[d]: global position of the tile's digit-d run minus its tile position
     KS key[kTile];            // the key as written out
     unsigned char dig[kTile]; // its digit (at most 256 digits)
     int col[kTile];
     float val[kTile];
 };
 
-// Thread d: the tile's first position of digit d (lstart), its global base, and the first
-// position of every wavefront's run of digit d (in cnt). Returns the tile's item count.
-__device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, int *gbase, int *wsum, int D,
-                                                 int gbase_d) {
+// Thread d: the offset from a tile position of digit d to its global position (gdelta =
+// the run's global base minus the tile's first position of d), and the first position of
+// every wavefront's run of digit d (in cnt). Returns the tile's item count.
+__device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *gdelta, int *wsum, int D, int gbase_d) {
     const int d = threadIdx.x;
     int c[kWaves], csum = 0;
 #pragma unroll
@@ -369,8 +369,7 @@ __device__ __forceinline__ int wave_split_layout(int (*cnt)[256], int *lstart, i
     int total;
     const int ls = block_excl_scan<kThreads>(csum, wsum, total);
     if (d < D) {
-        lstart[d] = ls;
-        gbase[d] = gbase_d;
+        gdelta[d] = gbase_d - ls;
         int run = ls;
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
@@ -446,10 +445,14 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
                                                       float *__restrict__ oval, unsigned *status, int with_b, int B,
                                                       int *__restrict__ seg_start, int *__restrict__ tile_off,
                                                       int *__restrict__ bstart, int *__restrict__ meta, int bal,
-                                                      int *__restrict__ ptot) {
+                                                      int *__restrict__ ptot, int *__restrict__ tile_seg) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = xcd_order(blockIdx.x, T);
+    // the digit totals and this tile's scanned offsets, loaded before the entries (they do
+    // not depend on them)
+    const int dn = (int)threadIdx.x < D ? tot[threadIdx.x] : 0;
+    const int gtile = (int)threadIdx.x < D ? gh[(int64_t)threadIdx.x * T + t] : 0;
     bool badi = false, badw = false;
     Quarter<true> q;
     load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
@@ -462,7 +465,6 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     // segment starts: exclusive scan of the digit totals, in every workgroup (workgroup 0
     // also writes them, the entry count M, the pass-B tiles of every segment and, without
     // a pass B, the bucket starts, for the later launches)
-    const int dn = (int)threadIdx.x < D ? tot[threadIdx.x] : 0;
     int total;
     const int st = block_excl_scan<kThreads>(dn, L.wsum, total);
     if (blockIdx.x == 0) {
@@ -473,6 +475,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
             seg_start[d] = st;
             if (with_b) tile_off[d] = to;
             if (!with_b && d < B) bstart[d] = st;
+            if (with_b && tile_seg)
+                for (int j = 0, nt = (dn + kTile - 1) / kTile; j < nt; ++j) tile_seg[to + j] = d;
         }
         if (d == 0) {
             seg_start[D] = total;
@@ -482,8 +486,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
         }
         if (ptot) ptot[d] = 0;  // 64 blocks x 4 totals, formed by the pass-B scan
     }
-    const int gb = (int)threadIdx.x < D ? st + gh[(int64_t)threadIdx.x * T + t] : 0;
-    const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, D, gb);
+    const int gb = (int)threadIdx.x < D ? st + gtile : 0;
+    const int n = wave_split_layout(L.cnt, L.gdelta, L.wsum, D, gb);
     int dg[kRoundsW], pos[kRoundsW];
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) dg[r] = (q.valid >> r & 1u) ? (q.key[r] >> shift) : 0;
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int d = L.dig[i];
-        const int64_t g2 = (int64_t)L.gbase[d] + (i - L.lstart[d]);
+        const int64_t g2 = (int64_t)L.gdelta[d] + i;
         if (!dbg_ok(g2 >= 0 && g2 < V, status)) continue;
         okey[g2] = L.key[i];
         ocol[g2] = L.col[i];
@@ -511,16 +515,24 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
 // ----------------------------------------------------------------------------- pass B
 
 // Pass-B tile j -> (segment d, tile within segment); returns false past the last tile.
-__device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, int D, int j, int &d, int &jt,
-                                       int &ntd) {
-    if (j >= tile_off[D]) return false;
-    int lo = 0, hi = D;  // last d with tile_off[d] <= j
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tile_off[mid] <= j) lo = mid;
-        else hi = mid;
+// With tile_seg (pass B: the segment of every tile, written by the pass-A scatter) one
+// lookup, else a binary search over the segments' first tiles (pass C).
+__device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, const int *__restrict__ tile_seg, int D,
+                                       int j, int &d, int &jt, int &ntd) {
+    if (tile_seg) {
+        const int tb = tile_off[D], dj = tile_seg[j];  // (j < the grid's tile capacity: in bounds)
+        if (j >= tb) return false;
+        d = dj;
+    } else {
+        if (j >= tile_off[D]) return false;
+        int lo = 0, hi = D;  // last d with tile_off[d] <= j
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= j) lo = mid;
+            else hi = mid;
+        }
+        d = lo;
     }
-    d = lo;
     jt = j - tile_off[d];
     ntd = tile_off[d + 1] - tile_off[d];
     return true;
@@ -537,10 +549,10 @@ __device__ __forceinline__ bool b_tile(const int *__restrict__ tile_off, int D, 
 template <typename KT>
 __global__ __launch_bounds__(256) void seg_hist(const KT *__restrict__ key, int dshift, int dbits,
                                                 const int *__restrict__ seg_start, const int *__restrict__ tile_off,
-                                                int D, int *__restrict__ gh) {
+                                                int D, int *__restrict__ gh, const int *__restrict__ tile_seg) {
     __shared__ int hist_all[256 * kHistCopies];
     int d, jt, ntd;
-    if (!b_tile(tile_off, D, blockIdx.x, d, jt, ntd)) return;
+    if (!b_tile(tile_off, tile_seg, D, blockIdx.x, d, jt, ntd)) return;
     const int L = 1 << dbits;
     for (int i = threadIdx.x; i < 256 * kHistCopies; i += 256) hist_all[i] = 0;
     __syncthreads();
@@ -656,15 +668,20 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
                                                    const int *__restrict__ gh, const int *__restrict__ seg_start,
                                                    const int *__restrict__ tile_off, int D,
                                                    uint16_t *__restrict__ okey, int *__restrict__ ocol,
-                                                   float *__restrict__ oval, unsigned *status, int bal) {
+                                                   float *__restrict__ oval, unsigned *status, int bal,
+                                                   const int *__restrict__ tile_seg) {
     __shared__ PartLds<uint16_t> L;
     int d, jt, ntd;
-    if (!b_tile(tile_off, D, (int)xcd_order(blockIdx.x, tile_off[D]), d, jt, ntd)) return;
+    // (with the tile map, tiles are ordered over the grid's capacity, which spares a load)
+    const int64_t jn = tile_seg ? (int64_t)gridDim.x : (int64_t)tile_off[D];
+    if (!b_tile(tile_off, tile_seg, D, (int)xcd_order(blockIdx.x, jn), d, jt, ntd)) return;
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const int ND = 1 << dbits;
     const int s0 = seg_start[d];
     const int nseg = seg_start[d + 1] - s0;
     const int *seg = gh + ((int64_t)tile_off[d] << dbits);
+    // this tile's scanned run offsets, loaded before the entries (they do not depend on them)
+    const int gtile = (int)threadIdx.x < ND ? seg[((int64_t)jt << dbits) + threadIdx.x] : 0;
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
     __syncthreads();
     const int e0 = s0 + jt * kTile;
@@ -683,8 +700,8 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
     for (int r = 0; r < kRoundsW; ++r)
         if (ew + r * 64 + lane < e1) atomicAdd(&L.cnt[wv][(kr[r] >> dshift) & (ND - 1)], 1);
     __syncthreads();
-    const int gb = (int)threadIdx.x < ND ? s0 + seg[((int64_t)jt << dbits) + threadIdx.x] : 0;
-    const int n = wave_split_layout(L.cnt, L.lstart, L.gbase, L.wsum, ND, gb);
+    const int gb = (int)threadIdx.x < ND ? s0 + gtile : 0;
+    const int n = wave_split_layout(L.cnt, L.gdelta, L.wsum, ND, gb);
     int dg[kRoundsW], pos[kRoundsW];
     unsigned vmask = 0;
 #pragma unroll
@@ -706,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int dg = L.dig[i];
-        const int64_t g = (int64_t)L.gbase[dg] + (i - L.lstart[dg]);
+        const int64_t g = (int64_t)L.gdelta[dg] + i;
         if (!dbg_ok(g >= s0 && g < (int64_t)s0 + nseg, status)) continue;
         if (!FINAL) okey[g] = L.key[i];
         ocol[g] = L.col[i];
@@ -930,11 +947,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if (k16) {
         hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status, wb, p.B,
-                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal, ptot);
+                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal, ptot, wk.segB);
     } else {
         hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, wk.akey, -1, acol, aval, status, wb, p.B, wk.segA, wk.tileB,
-                           wk.bstart, wk.meta, bal, ptot);
+                           wk.bstart, wk.meta, bal, ptot, wk.segB);
     }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -942,10 +959,10 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_begin(kKBHist, s);
     if (k16) {
         hipLaunchKernelGGL(seg_hist<uint16_t>, dim3((unsigned)p.TBcap), dim3(256), 0, s, akey16, p.sb, p.s2,
-                           wk.segA, wk.tileB, p.DA, wk.ghB);
+                           wk.segA, wk.tileB, p.DA, wk.ghB, wk.segB);
     } else {
         hipLaunchKernelGGL(seg_hist<int>, dim3((unsigned)p.TBcap), dim3(256), 0, s, wk.akey, p.sb, p.s2, wk.segA,
-                           wk.tileB, p.DA, wk.ghB);
+                           wk.tileB, p.DA, wk.ghB, wk.segB);
     }
     prof_end(kKBHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -958,11 +975,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if (k16) {
         hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
                            aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal);
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB);
     } else {
         hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
                            p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal);
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB);
     }
     prof_end(kKBScatter, s);
     return hipGetLastError();
@@ -983,7 +1000,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if (e != hipSuccess) return e;
     prof_begin(kKCHist, s);
     hipLaunchKernelGGL(seg_hist<KT>, dim3((unsigned)p.TCcap), dim3(256), 0, s, key, 0, p.sb, wk.bstart, wk.tileC,
-                       p.B, wk.ghC);
+                       p.B, wk.ghC, nullptr);
     prof_end(kKCHist, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScan, s);
@@ -993,7 +1010,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);
     hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(kThreads), 0, s, key, wk.tcol, tv, 0, p.sb,
-                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT);
+                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT, nullptr);
     prof_end(kKCScatter, s);
     return hipGetLastError();
 }

@@ -367,6 +367,7 @@ struct Work {
     int *segA = nullptr;       // [DA + 1] pass A segment starts
     int *tileB = nullptr;      // [DA + 1] first pass-B tile of each segment
     int *ghB = nullptr;        // [(1 << s2) * TBcap] pass B tile histograms
+    int *segB = nullptr;       // [TBcap] segment of each pass-B tile
     int *bstart = nullptr;     // [B + 1]
     int *tileC = nullptr;      // [B + 1] first pass-C tile of each bucket
     int *ghC = nullptr;        // [TCcap << sb] pass C tile histograms
