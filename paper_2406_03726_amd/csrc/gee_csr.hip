@@ -44,6 +44,10 @@ constexpr int kWaves = GEE_PART_WAVES;    // wavefronts per partition workgroup
 constexpr int kThreads = kWaves * 64;
 constexpr int kQuarter = kTile / kWaves;  // items per wavefront per tile
 constexpr int kRoundsW = kQuarter / 64;   // rounds of one wavefront
+#ifndef GEE_OUT_UNROLL
+#define GEE_OUT_UNROLL 4
+#endif
+constexpr int kOutUnroll = GEE_OUT_UNROLL;  // staged items per thread in flight in a tile's write-out
 static_assert(kTile % (kWaves * 64) == 0 && kRoundsW <= 16 && kThreads >= 256, "partition tile shape");
 // bucket_sort's wave-split path: 4 wavefronts of at most 16 rounds (kSortCap entries)
 constexpr int kSortWaves = 4, kSortRoundsW = 16, kSortCap = kSortWaves * kSortRoundsW * 64;
@@ -502,13 +506,21 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
         }
     }
     if (__syncthreads_or(badw) && threadIdx.x == 0) raise_error(status, kErrWeight);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int d = L.dig[i];
-        const int64_t g2 = (int64_t)L.gdelta[d] + i;
-        if (!dbg_ok(g2 >= 0 && g2 < V, status)) continue;
-        okey[g2] = L.key[i];
-        ocol[g2] = L.col[i];
-        if (oval) oval[g2] = L.val[i];
+    // kOutUnroll items per thread at a time, so their LDS reads overlap
+    for (int i0 = threadIdx.x; i0 < n; i0 += kOutUnroll * kThreads) {
+        int dd[kOutUnroll];
+#pragma unroll
+        for (int u = 0; u < kOutUnroll; ++u) dd[u] = L.dig[min(i0 + u * kThreads, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kOutUnroll; ++u) {
+            const int i = i0 + u * kThreads;
+            if (i >= n) break;
+            const int64_t g2 = (int64_t)L.gdelta[dd[u]] + i;
+            if (!dbg_ok(g2 >= 0 && g2 < V, status)) continue;
+            okey[g2] = L.key[i];
+            ocol[g2] = L.col[i];
+            if (oval) oval[g2] = L.val[i];
+        }
     }
 }
 
@@ -721,13 +733,20 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int dg = L.dig[i];
-        const int64_t g = (int64_t)L.gdelta[dg] + i;
-        if (!dbg_ok(g >= s0 && g < (int64_t)s0 + nseg, status)) continue;
-        if (!FINAL) okey[g] = L.key[i];
-        ocol[g] = L.col[i];
-        if (oval) oval[g] = L.val[i];
+    for (int i0 = threadIdx.x; i0 < n; i0 += kOutUnroll * kThreads) {
+        int dd[kOutUnroll];
+#pragma unroll
+        for (int u = 0; u < kOutUnroll; ++u) dd[u] = L.dig[min(i0 + u * kThreads, n - 1)];
+#pragma unroll
+        for (int u = 0; u < kOutUnroll; ++u) {
+            const int i = i0 + u * kThreads;
+            if (i >= n) break;
+            const int64_t g = (int64_t)L.gdelta[dd[u]] + i;
+            if (!dbg_ok(g >= s0 && g < (int64_t)s0 + nseg, status)) continue;
+            if (!FINAL) okey[g] = L.key[i];
+            ocol[g] = L.col[i];
+            if (oval) oval[g] = L.val[i];
+        }
     }
 }
 
