@@ -172,8 +172,9 @@ __device__ __forceinline__ void set_row_coef(const GDesc &gd, const float *__res
 // part lies inside them; the buffer range ends with the part's last window, so windows
 // past it read as 0 without touching memory. Entries past the part's end are masked by
 // the caller. Every load is unconditional, which keeps the compiler's counter waits exact
-// in the pipelined loops.
-template <typename KT, bool WEIGHTED, bool COLS>
+// in the pipelined loops. Without KEYS the key array is not read (packed columns carry the
+// row, see bucket_embed).
+template <typename KT, bool WEIGHTED, bool COLS, bool KEYS = true>
 struct Windows {
     __amdgpu_buffer_rsrc_t rk, rc, rv;
     struct Raw {
@@ -188,7 +189,9 @@ struct Windows {
     }
     __device__ __forceinline__ void load(int i, int lane, Raw &r) const {
         const uint32_t o = (uint32_t)(i * BWIN + BEPL * lane);
-        if (sizeof(KT) == 2) {
+        if (!KEYS) {
+            r.k = make_int4(0, 0, 0, 0);
+        } else if (sizeof(KT) == 2) {
             const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rk, 2 * o, 0, 0));
             r.k = make_int4((int)(q.x & 0xFFFFu), (int)(q.x >> 16), (int)(q.y & 0xFFFFu), (int)(q.y >> 16));
         } else {
@@ -431,7 +434,11 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
     }
 }
 
-template <typename KT, bool WEIGHTED>
+// With PACKED (after a pass B) each column word carries its row inside the bucket above
+// its 22 bits (bucket-path launches hold at most 2^22 rows), so the keys are not read.
+constexpr int kPackShift = 22;
+static_assert(((int64_t)kMaxBuckets << 6) <= ((int64_t)1 << kPackShift), "packed bucket columns");
+template <typename KT, bool WEIGHTED, bool PACKED>
 __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val,
                                                    const int4 *__restrict__ part, int cap,
@@ -460,7 +467,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     }
     wave_lds_fence();
 
-    using W = Windows<KT, WEIGHTED, true>;
+    using W = Windows<KT, WEIGHTED, true, !PACKED>;
     const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
     const W win(key, col, val, pt.y, nwin);
     const __amdgpu_buffer_rsrc_t r_inf = buffer_rsrc(info + node_off, (int64_t)gd.N * 8);
@@ -476,8 +483,9 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
         const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
 #pragma unroll
         for (int j = 0; j < BEPL; ++j) {
-            const unsigned u = j < nv ? (unsigned)(cc[j] - node_off) : 0xFFFFFFFFu;
-            P.row[j] = kk[j] & rmask;
+            const int cj = PACKED ? (cc[j] & ((1 << kPackShift) - 1)) : cc[j];
+            const unsigned u = j < nv ? (unsigned)(cj - node_off) : 0xFFFFFFFFu;
+            P.row[j] = (PACKED ? (cc[j] >> kPackShift) : kk[j]) & rmask;
             P.x[j] = j < nv ? vv[j] : 0.0f;
             P.f[j] = buf_f2(r_inf, u << 3);
         }
@@ -640,8 +648,12 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     const size_t lds = bucket_lds(p.sb, p.Kmax);
     const int zs = p.Kmax << p.sb;  // floats per partial slot
     prof_begin(kKBucketEmbed, s);
-    hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
-                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
+    if (p.s2 > 0)  // pass B packed the rows into the column words
+        hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED, true>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
+                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
+    else
+        hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED, false>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
+                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
     hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,

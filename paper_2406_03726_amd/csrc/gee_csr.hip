@@ -681,7 +681,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
                                                    const int *__restrict__ tile_off, int D,
                                                    uint16_t *__restrict__ okey, int *__restrict__ ocol,
                                                    float *__restrict__ oval, unsigned *status, int bal,
-                                                   const int *__restrict__ tile_seg) {
+                                                   const int *__restrict__ tile_seg, int pack) {
     __shared__ PartLds<uint16_t> L;
     int d, jt, ntd;
     // (with the tile map, tiles are ordered over the grid's capacity, which spares a load)
@@ -728,7 +728,8 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
         if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
             if (!FINAL) L.key[pos[r]] = (uint16_t)(kr[r] & kmask);
             L.dig[pos[r]] = (unsigned char)dg[r];
-            L.col[pos[r]] = cr[r];
+            // (pack: the bucket path's class scatter reads the row from the column word)
+            L.col[pos[r]] = pack ? (cr[r] | ((kr[r] & kmask) << 22)) : cr[r];
             if (oval) L.val[pos[r]] = vr[r];
         }
     }
@@ -994,11 +995,11 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     if (k16) {
         hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
                            aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB);
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
     } else {
         hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
                            p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB);
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
     }
     prof_end(kKBScatter, s);
     return hipGetLastError();
@@ -1029,7 +1030,7 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);
     hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(kThreads), 0, s, key, wk.tcol, tv, 0, p.sb,
-                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT, nullptr);
+                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT, nullptr, 0);
     prof_end(kKCScatter, s);
     return hipGetLastError();
 }
