@@ -54,8 +54,9 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return (8 + wv) * E + (2 + 4 + wv) * M
     if name == "b_hist":
         return 2 * M
-    if name == "b_scatter":  # (low row bits u16, col[, w]) in, (row in bucket u16, col[, w]) out
-        return 2 * (2 + 4 + wv) * M
+    if name == "b_scatter":  # (low row bits u16, col[, w]) in; on the bucket path (column word
+        # with the row in bucket packed in[, w]) out
+        return (2 + 4 + wv) * M + (4 + wv) * M
     if name == "bucket_sort":  # all buckets counted as if sorted here (an upper bound when
         # the largest buckets go to the pass-C tiles): key, col, val in; CSR out
         return (2 + 4 + wv) * M + (4 + wv) * M + 4 * (N + 1)
@@ -67,8 +68,8 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return 4 * (N + 1) + 4 * K * n_empty
     if name == "embed_rows":
         return 4 * (N + 1) + (4 + wv) * M + 8 * N + 4 * N + 4 * N * K
-    if name == "bucket_degree":  # bucketed (row-in-bucket u16[, w]) in; labels in, s_i and {c_i, y_i} out
-        return (2 + wv) * M + 4 * N + 4 * N + 8 * N
+    if name == "bucket_degree":  # bucketed (packed column word[, w]) in; labels in, s_i and {c_i, y_i} out
+        return (4 + wv) * M + 4 * N + 4 * N + 8 * N
     if name == "bucket_embed":  # bucketed (column word with the row in bucket packed above it[, w]) in,
         # {c_j, y_j} and s_i once, Z out (after a pass B, as on every workload measured here)
         return (4 + wv) * M + 8 * N + 4 * N + 4 * N * K

@@ -41,6 +41,10 @@ constexpr int BEPL = 4;          // consecutive entries per lane in a window
 constexpr int BWIN = 64 * BEPL;  // entries per window
 constexpr int kFixThreads = 1024;  // threads per split bucket when combining class sums
 constexpr int kFixUnroll = 4;      // class sums per thread in flight together (R * K <= 4096)
+// After a pass B on the bucket path each column word carries the entry's row inside its
+// bucket above bit kPackShift (bucket-path launches hold at most 2^22 rows).
+constexpr int kPackShift = kBucketPackShift;
+static_assert(((int64_t)kMaxBuckets << 6) <= ((int64_t)1 << kPackShift), "packed bucket columns");
 #ifndef GEE_EMBED_SCHED_BARRIER
 #define GEE_EMBED_SCHED_BARRIER 1
 #endif
@@ -221,9 +225,11 @@ __device__ __forceinline__ bool part_view(const Batch &b, int j, const int4 *__r
 // wavefront adds its entries with plain LDS read-modify-writes, then the high half. A
 // window's 256 entries fall on only R rows, and LDS float atomics on shared sums run at a
 // small fraction of the plain LDS rate. The copies are added in copy order at the end.
+// With PACKED the rows come from the packed column words (see bucket_embed), read in
+// place of the keys.
 constexpr int kDegCopies = 32;
-template <typename KT, bool WEIGHTED>
-__global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restrict__ key,
+template <typename KT, bool WEIGHTED, bool PACKED>
+__global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restrict__ key, const int *__restrict__ pcol,
                                                      const float *__restrict__ val,
                                                      const int4 *__restrict__ part, int cap,
                                                      const int *__restrict__ bmeta, int sb,
@@ -251,13 +257,16 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
     float *mine = dsum + (lane & (kDegCopies - 1)) * RS;
     const bool wt = WEIGHTED && gd.weighted;
     const int rmask = R - 1;
-    using W = Windows<KT, WEIGHTED, false>;
+    using W = Windows<KT, WEIGHTED, PACKED, !PACKED>;
     const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
-    const W win(key, nullptr, val, pt.y, nwin);
+    const W win(key, pcol, val, pt.y, nwin);
     // window i: entries masked past the part's end add 0
     auto add = [&](int i, const typename W::Raw &q) {
         const int nv = min(BEPL, max(0, pt.z - (pt.y + i * BWIN + BEPL * lane)));
-        const int kk[BEPL] = {q.k.x, q.k.y, q.k.z, q.k.w};
+        const int4 k4 = PACKED ? make_int4(q.c.x >> kPackShift, q.c.y >> kPackShift, q.c.z >> kPackShift,
+                                           q.c.w >> kPackShift)
+                               : q.k;
+        const int kk[BEPL] = {k4.x, k4.y, k4.z, k4.w};
         const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
         float x[BEPL];
         int rw[BEPL];
@@ -435,9 +444,7 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
 }
 
 // With PACKED (after a pass B) each column word carries its row inside the bucket above
-// its 22 bits (bucket-path launches hold at most 2^22 rows), so the keys are not read.
-constexpr int kPackShift = 22;
-static_assert(((int64_t)kMaxBuckets << 6) <= ((int64_t)1 << kPackShift), "packed bucket columns");
+// its kPackShift bits, so the keys are not read.
 template <typename KT, bool WEIGHTED, bool PACKED>
 __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val,
@@ -635,8 +642,14 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     const float *val = WEIGHTED ? wk.tval : nullptr;
     prof_begin(kKBucketDegree, s);
     const size_t dlds = (size_t)4 * kDegCopies * ((1 << p.sb) + 1) * sizeof(float);
-    hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key, val,
-                       wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info, mode);
+    if (p.s2 > 0 && !GEE_PASSB_KEYS)  // rows from the packed column words
+        hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED, true>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key,
+                           wk.tcol, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info,
+                           mode);
+    else
+        hipLaunchKernelGGL((bucket_degree<KT, WEIGHTED, false>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b, key,
+                           wk.tcol, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow, wk.info,
+                           mode);
     prof_end(kKBucketDegree, s);
     // split buckets, at most (the grids of the two fix kernels loop over the actual count)
     const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);

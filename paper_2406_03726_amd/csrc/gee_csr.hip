@@ -726,10 +726,10 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
         if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
-            if (!FINAL) L.key[pos[r]] = (uint16_t)(kr[r] & kmask);
+            if (!FINAL && okey) L.key[pos[r]] = (uint16_t)(kr[r] & kmask);
             L.dig[pos[r]] = (unsigned char)dg[r];
-            // (pack: the bucket path's class scatter reads the row from the column word)
-            L.col[pos[r]] = pack ? (cr[r] | ((kr[r] & kmask) << 22)) : cr[r];
+            // (pack: the bucket path's kernels read the row from the column word)
+            L.col[pos[r]] = pack ? (cr[r] | ((kr[r] & kmask) << kBucketPackShift)) : cr[r];
             if (oval) L.val[pos[r]] = vr[r];
         }
     }
@@ -744,7 +744,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
             if (i >= n) break;
             const int64_t g = (int64_t)L.gdelta[dd[u]] + i;
             if (!dbg_ok(g >= s0 && g < (int64_t)s0 + nseg, status)) continue;
-            if (!FINAL) okey[g] = L.key[i];
+            if (!FINAL && okey) okey[g] = L.key[i];
             ocol[g] = L.col[i];
             if (oval) oval[g] = L.val[i];
         }
@@ -992,13 +992,15 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_end(kKBScan, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKBScatter, s);
+    // the bucket path reads its rows from the packed column words: no keys
+    uint16_t *bkeys = (p.bucket && !GEE_PASSB_KEYS) ? nullptr : wk.tkey;
     if (k16) {
         hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
-                           aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
+                           aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
                            p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
     } else {
         hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
-                           p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, wk.tkey, wk.tcol,
+                           p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
                            p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
     }
     prof_end(kKBScatter, s);

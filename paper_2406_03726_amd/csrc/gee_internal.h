@@ -27,6 +27,12 @@ constexpr int kWave = 64;
 constexpr int kMaxBuckets = 65536;     // CSR buckets: 256 high digits x 256 low digits
 constexpr int kMaxBucketRowsLog2 = 12; // rows per bucket (the last sort pass ranks by row)
 constexpr int kMaxClasses = 128;
+// Bucket path after a pass B: each entry's row inside its bucket rides in its column word
+// above this many bits; the keys themselves are written only with GEE_PASSB_KEYS.
+constexpr int kBucketPackShift = 22;
+#ifndef GEE_PASSB_KEYS
+#define GEE_PASSB_KEYS 0
+#endif
 #ifndef GEE_PART_TILE
 #define GEE_PART_TILE 4096
 #endif
