@@ -64,8 +64,8 @@ static size_t bucket_lds(int sb, int Kmax) {
 // group in bucket order, so the longest wavefronts start first.
 
 // One thread per bucket: per-workgroup totals of parts, partial slots, split buckets and
-// large one-part buckets (bucket_part_totals). After a pass B the pass-B scan has formed
-// them already (seg_scan) and this launch is skipped.
+// large one-part buckets (the ptot of part_fill_block). After a pass B the pass-B scan has
+// formed them already (seg_scan) and this launch is skipped.
 __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                           int *__restrict__ ptot) {
     __shared__ int wsum[16];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__
     (void)block_excl_scan<1024>(k, wsum, t0);
     (void)block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
     (void)block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
-    (void)block_excl_scan<1024>(large_single(n, k, P) ? 1 : 0, wsum, t3);  // (the four totals of bucket_part_totals)
+    (void)block_excl_scan<1024>(large_single(n, k, P) ? 1 : 0, wsum, t3);
     if (threadIdx.x == 0) {
         ptot[4 * blockIdx.x] = t0;
         ptot[4 * blockIdx.x + 1] = t1;
@@ -89,66 +89,12 @@ __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__
     }
 }
 
-// One thread per bucket again: its parts {bucket, first entry, end entry, slot} (slot -1
-// for a bucket of one part, else the bucket's first slot + part index) in the order above,
-// and for a split bucket its entry {bucket, first slot, parts} in `multi`.
-// bmeta = {parts, split buckets}. At most 64 workgroups (B <= 65536).
-__global__ __launch_bounds__(1024) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
-                                                         const int *__restrict__ ptot, int4 *__restrict__ part,
-                                                         int4 *__restrict__ multi, int *__restrict__ bmeta) {
-    __shared__ int wsum[16];
-    // before this workgroup: parts, slots, split buckets, large one-part buckets, small
-    // one-part buckets; over all workgroups: slots, large one-part buckets
-    __shared__ int base[7];
-    if (threadIdx.x < 64) {
-        int v[7] = {0, 0, 0, 0, 0, 0, 0};
-        if ((int)threadIdx.x < (int)gridDim.x) {
-            const int q0 = ptot[4 * threadIdx.x], q1 = ptot[4 * threadIdx.x + 1];
-            const int q2 = ptot[4 * threadIdx.x + 2], q3 = ptot[4 * threadIdx.x + 3];
-            v[5] = q1;
-            v[6] = q3;
-            if ((int)threadIdx.x < (int)blockIdx.x) {
-                v[0] = q0;
-                v[1] = q1;
-                v[2] = q2;
-                v[3] = q3;
-                v[4] = q0 - q1 - q3;  // one-part buckets that are not large
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 7; ++c) v[c] = readlane(wave_scan_add(v[c]), 63);
-        if (threadIdx.x == 0)
-            for (int c = 0; c < 7; ++c) base[c] = v[c];
-    }
-    __syncthreads();
-    const int bk = blockIdx.x * 1024 + threadIdx.x;
-    int k = 0, P = 1, s0 = 0, s1 = 0;
-    if (bk < B) {
-        P = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
-        s0 = bstart[bk];
-        s1 = bstart[bk + 1];
-        k = parts_of(s1 - s0, P);
-    }
-    const bool large = large_single(s1 - s0, k, P);
-    const bool small = k == 1 && !large;
-    int t0, t1, t2, t3, t4;
-    (void)block_excl_scan<1024>(k, wsum, t0);
-    const int ss = base[1] + block_excl_scan<1024>(k > 1 ? k : 0, wsum, t1);
-    const int mm = base[2] + block_excl_scan<1024>(k > 1 ? 1 : 0, wsum, t2);
-    const int ll = base[3] + block_excl_scan<1024>(large ? 1 : 0, wsum, t3);
-    const int sm = base[4] + block_excl_scan<1024>(small ? 1 : 0, wsum, t4);
-    if (k > 1) {
-        for (int q = 0; q < k; ++q) part[ss + q] = make_int4(bk, s0 + q * P, min(s0 + (q + 1) * P, s1), ss + q);
-        multi[mm] = make_int4(bk, ss, k, 0);
-    } else if (large) {
-        part[base[5] + ll] = make_int4(bk, s0, s1, -1);
-    } else if (small) {
-        part[base[5] + base[6] + sm] = make_int4(bk, s0, s1, -1);
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        bmeta[0] = base[0] + t0;
-        bmeta[1] = base[2] + t2;
-    }
+// The part table, one workgroup per block of 1024 buckets (part_fill_block). After a pass B
+// the pass-B scatter fills it in extra workgroups instead and this launch is skipped.
+__global__ __launch_bounds__(256) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
+                                                        const int *__restrict__ ptot, int4 *__restrict__ part,
+                                                        int4 *__restrict__ multi, int *__restrict__ bmeta) {
+    part_fill_block(b, bstart, B, sb, ptot, (int)gridDim.x, (int)blockIdx.x, part, multi, bmeta);
 }
 
 // s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count); the
@@ -681,15 +627,15 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
     const bool key16 = with_b || p.sb + p.s2 <= 16;
     const void *key = with_b ? (const void *)wk.tkey : (const void *)wk.akey;
     const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
-    if (!with_b) {  // (after a pass B its scan has written the block totals)
+    if (!with_b) {  // (after a pass B its scan has formed the block totals and its scatter the table)
         prof_begin(kKBucketPartCount, s);
         hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot);
         prof_end(kKBucketPartCount, s);
+        prof_begin(kKBucketPartFill, s);
+        hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
+                           wk.multi, wk.bmeta);
+        prof_end(kKBucketPartFill, s);
     }
-    prof_begin(kKBucketPartFill, s);
-    hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
-                       wk.multi, wk.bmeta);
-    prof_end(kKBucketPartFill, s);
     if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s, mode, sums);
     else if (key16) launch_bucket_sums<uint16_t, false>(b, p, wk, (const uint16_t *)key, s, mode, sums);
     else if (p.weighted) launch_bucket_sums<int, true>(b, p, wk, (const int *)key, s, mode, sums);

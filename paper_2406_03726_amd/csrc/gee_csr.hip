@@ -681,12 +681,20 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
                                                    const int *__restrict__ tile_off, int D,
                                                    uint16_t *__restrict__ okey, int *__restrict__ ocol,
                                                    float *__restrict__ oval, unsigned *status, int bal,
-                                                   const int *__restrict__ tile_seg, int pack) {
+                                                   const int *__restrict__ tile_seg, int pack, Batch b,
+                                                   PartFill pf) {
     __shared__ PartLds<uint16_t> L;
+    // the first pf.nblk workgroups fill the bucket path's part table (its inputs, the bucket
+    // starts and the block totals, are complete once the pass-B scan has run)
+    if ((int)blockIdx.x < pf.nblk) {
+        part_fill_block(b, pf.bstart, pf.B, pf.sb, pf.ptot, pf.nblk, (int)blockIdx.x, pf.part, pf.multi, pf.bmeta);
+        return;
+    }
+    const int jb = (int)blockIdx.x - pf.nblk;
     int d, jt, ntd;
     // (with the tile map, tiles are ordered over the grid's capacity, which spares a load)
-    const int64_t jn = tile_seg ? (int64_t)gridDim.x : (int64_t)tile_off[D];
-    if (!b_tile(tile_off, tile_seg, D, (int)xcd_order(blockIdx.x, jn), d, jt, ntd)) return;
+    const int64_t jn = tile_seg ? (int64_t)gridDim.x - pf.nblk : (int64_t)tile_off[D];
+    if (!b_tile(tile_off, tile_seg, D, (int)xcd_order(jb, jn), d, jt, ntd)) return;
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const int ND = 1 << dbits;
     const int s0 = seg_start[d];
@@ -994,14 +1002,27 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     prof_begin(kKBScatter, s);
     // the bucket path reads its rows from the packed column words: no keys
     uint16_t *bkeys = (p.bucket && !GEE_PASSB_KEYS) ? nullptr : wk.tkey;
+    // the bucket path's part table, in extra workgroups of this launch
+    PartFill pf;
+    if (p.bucket && wk.part && wk.ptot) {
+        pf.bstart = wk.bstart;
+        pf.ptot = wk.ptot;
+        pf.part = wk.part;
+        pf.multi = wk.multi;
+        pf.bmeta = wk.bmeta;
+        pf.B = (int)p.B;
+        pf.sb = p.sb;
+        pf.nblk = (int)((p.B + 1023) / 1024);
+    }
+    const unsigned gB = (unsigned)(p.TBcap + pf.nblk);
     if (k16) {
-        hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, akey16, acol,
-                           aval, p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
+        hipLaunchKernelGGL((seg_scatter<uint16_t, false>), dim3(gB), dim3(kThreads), 0, s, akey16, acol, aval, p.sb, p.s2,
+                           (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0, b, pf);
     } else {
-        hipLaunchKernelGGL((seg_scatter<int, false>), dim3((unsigned)p.TBcap), dim3(kThreads), 0, s, wk.akey, acol, aval,
-                           p.sb, p.s2, (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
-                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0);
+        hipLaunchKernelGGL((seg_scatter<int, false>), dim3(gB), dim3(kThreads), 0, s, wk.akey, acol, aval, p.sb, p.s2,
+                           (1 << p.sb) - 1, wk.ghB, wk.segA, wk.tileB, p.DA, bkeys, wk.tcol,
+                           p.weighted ? wk.tval : nullptr, status, bal, wk.segB, p.bucket ? 1 : 0, b, pf);
     }
     prof_end(kKBScatter, s);
     return hipGetLastError();
@@ -1032,7 +1053,8 @@ static hipError_t launch_pass_c(const KT *key, const Plan &p, const Work &wk, in
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKCScatter, s);
     hipLaunchKernelGGL((seg_scatter<KT, true>), dim3((unsigned)p.TCcap), dim3(kThreads), 0, s, key, wk.tcol, tv, 0, p.sb,
-                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT, nullptr, 0);
+                       0, wk.ghC, wk.bstart, wk.tileC, p.B, nullptr, wk.col, ov, status, GEE_CSR_RANK_BALLOT, nullptr, 0, Batch{},
+                       PartFill{});
     prof_end(kKCScatter, s);
     return hipGetLastError();
 }

@@ -449,6 +449,105 @@ __device__ __forceinline__ void class_count_slice(const Batch &b, int j, int *__
 __device__ __forceinline__ int parts_of(int n, int P) { return n > P ? (n + P - 1) / P : 1; }
 __device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 1 && 4 * n > P; }
 
+// One block of 1024 buckets of the bucket path's part table, by a workgroup of 256 threads
+// (four consecutive buckets each): bucket bk of n entries gets k = parts_of(n, P) parts
+// {bucket, first entry, end entry, slot} (slot -1 for one part, else the bucket's first slot
+// + part index), listed as: the parts of split buckets first (at their slots), then the
+// one-part buckets of more than P/4 entries, then the rest, each group in bucket order; a
+// split bucket also gets {bucket, first slot, parts} in `multi`. ptot holds the four
+// totals of every block (parts, slots, split buckets, large one-part buckets); the last
+// block writes bmeta = {parts, split buckets}.
+__device__ __forceinline__ void part_fill_block(const Batch &b, const int *__restrict__ bstart, int B, int sb,
+                                                const int *__restrict__ ptot, int nblk, int blk,
+                                                int4 *__restrict__ part, int4 *__restrict__ multi,
+                                                int *__restrict__ bmeta) {
+    __shared__ int pf_wsum[4];
+    // before this block: parts, slots, split buckets, large one-part buckets, small
+    // one-part buckets; over all blocks: slots, large one-part buckets
+    __shared__ int pf_base[7];
+    if (threadIdx.x < 64) {
+        int v[7] = {0, 0, 0, 0, 0, 0, 0};
+        if ((int)threadIdx.x < nblk) {
+            const int q0 = ptot[4 * threadIdx.x], q1 = ptot[4 * threadIdx.x + 1];
+            const int q2 = ptot[4 * threadIdx.x + 2], q3 = ptot[4 * threadIdx.x + 3];
+            v[5] = q1;
+            v[6] = q3;
+            if ((int)threadIdx.x < blk) {
+                v[0] = q0;
+                v[1] = q1;
+                v[2] = q2;
+                v[3] = q3;
+                v[4] = q0 - q1 - q3;  // one-part buckets that are not large
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = readlane(wave_scan_add(v[c]), 63);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < 7; ++c) pf_base[c] = v[c];
+    }
+    __syncthreads();
+    int k[4], s0[4], s1[4], P[4];
+    int nk = 0, nslot = 0, nsplit = 0, nlarge = 0, nsmall = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int bk = blk * 1024 + 4 * (int)threadIdx.x + u;
+        k[u] = 0;
+        P[u] = 1;
+        s0[u] = s1[u] = 0;
+        if (bk < B) {
+            P[u] = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
+            s0[u] = bstart[bk];
+            s1[u] = bstart[bk + 1];
+            k[u] = parts_of(s1[u] - s0[u], P[u]);
+        }
+        const bool large = large_single(s1[u] - s0[u], k[u], P[u]);
+        nk += k[u];
+        nslot += k[u] > 1 ? k[u] : 0;
+        nsplit += k[u] > 1 ? 1 : 0;
+        nlarge += large ? 1 : 0;
+        nsmall += (k[u] == 1 && !large) ? 1 : 0;
+    }
+    int t0, t1, t2, t3, t4;
+    (void)block_excl_scan<256>(nk, pf_wsum, t0);
+    int ss = pf_base[1] + block_excl_scan<256>(nslot, pf_wsum, t1);
+    int mm = pf_base[2] + block_excl_scan<256>(nsplit, pf_wsum, t2);
+    int ll = pf_base[3] + block_excl_scan<256>(nlarge, pf_wsum, t3);
+    int sm = pf_base[4] + block_excl_scan<256>(nsmall, pf_wsum, t4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int bk = blk * 1024 + 4 * (int)threadIdx.x + u;
+        if (bk >= B) break;
+        if (k[u] > 1) {
+            for (int q = 0; q < k[u]; ++q)
+                part[ss + q] = make_int4(bk, s0[u] + q * P[u], min(s0[u] + (q + 1) * P[u], s1[u]), ss + q);
+            multi[mm] = make_int4(bk, ss, k[u], 0);
+            ss += k[u];
+            ++mm;
+        } else if (large_single(s1[u] - s0[u], k[u], P[u])) {
+            part[pf_base[5] + ll] = make_int4(bk, s0[u], s1[u], -1);
+            ++ll;
+        } else {
+            part[pf_base[5] + pf_base[6] + sm] = make_int4(bk, s0[u], s1[u], -1);
+            ++sm;
+        }
+    }
+    if (blk == nblk - 1 && threadIdx.x == 0) {
+        bmeta[0] = pf_base[0] + t0;
+        bmeta[1] = pf_base[2] + t2;
+    }
+}
+
+// The part table's inputs and outputs, for the launch that fills it (the pass-B scatter
+// takes its blocks as extra workgroups; nblk = 0: none).
+struct PartFill {
+    const int *bstart = nullptr;
+    const int *ptot = nullptr;
+    int4 *part = nullptr;
+    int4 *multi = nullptr;
+    int *bmeta = nullptr;
+    int B = 0, sb = 0, nblk = 0;
+};
+
 // One wavefront: class c of the launch (all graphs' classes in order).
 __device__ __forceinline__ void class_count_total(const Batch &b, int c, const int *__restrict__ part,
                                                   int *__restrict__ counts, float *__restrict__ inv_n) {
