@@ -542,10 +542,11 @@ def batched_leg(torch, np, gee, dev, table, procs, reps=5, G=512):
 
 def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, n_req=10_000,
                 loads=(0.3, 0.5, 0.7, 0.9, 1.1, 1.5), slots=4, budget_gb=32.0, max_batch=16,
-                max_batch_edges=2_000_000, max_inflight_edges=None, n_check=1_000):
+                max_batch_edges=2_000_000, max_inflight_edges=None, big_edges=8_000_000, n_check=1_000):
     """Poisson requests from a pool of serving-recipe graphs: the server (budget admission,
     continuous batching over `slots` streams) against the plain per-request loop, n_req
-    requests per load. Success criterion: with L* the plain loop's p99 at 0.5 x its
+    requests per load; requests of at least big_edges edges run one at a time, smaller ones
+    passing a large one that waits. Success criterion: with L* the plain loop's p99 at 0.5 x its
     saturation rate, the server keeps p99 <= L* up to a higher load than the plain loop.
     Every result of a separate untimed burst of n_check requests (all arriving at once, so
     batches are as full and overlapped as they get) is compared bitwise with the plain
@@ -593,7 +594,7 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, 
     out = {"pool_graphs": pool_n, "pool_edges_mean": int(np.mean([it["src"].numel() for it in pool])),
            "generation_s": round(gen_s, 1), "requests_per_load": n_req, "slots": slots,
            "budget_bytes": int(budget_gb * 2 ** 30), "max_batch": max_batch, "max_batch_edges": max_batch_edges,
-           "max_inflight_edges": max_inflight_edges,
+           "max_inflight_edges": max_inflight_edges, "big_edges": big_edges, "max_big_inflight": 1,
            "plain_saturation_req_per_s": round(mu, 1),
            "pool_plain_ms_tuned": round(float(np.sum(svc)) * 1e3, 3),
            "pool_plain_ms_default_schedules": round(float(np.sum(svc_d)) * 1e3, 3),
@@ -608,7 +609,7 @@ def serving_leg(torch, np, gee, dev, table, procs, pool_n=64, e_max=20_000_000, 
     def server(on_done=None):
         return GeeServer(backend, int(budget_gb * 2 ** 30), max_batch=max_batch,
                          max_batch_edges=max_batch_edges, max_inflight_edges=max_inflight_edges,
-                         on_done=on_done or drop)
+                         on_done=on_done or drop, big_edges=big_edges, max_big_inflight=1)
 
     def drop(r):
         r.result = None  # results are not kept through the timed runs

@@ -84,13 +84,15 @@ class _Flight:
     reqs: List[Request]
     nbytes: int
     edges: int = 0
+    bigs: int = 0
 
 
 class GeeServer:
     def __init__(self, backend: Backend, budget_bytes: int, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter, max_batch_edges: Optional[int] = None,
                  max_inflight_edges: Optional[int] = None,
-                 on_done: Optional[Callable[[Request], None]] = None):
+                 on_done: Optional[Callable[[Request], None]] = None,
+                 big_edges: Optional[int] = None, max_big_inflight: int = 1):
         if budget_bytes <= 0 or max_batch < 1:
             raise ValueError("budget and batch size must be positive")
         self.backend = backend
@@ -104,6 +106,12 @@ class GeeServer:
         # as it would in the plain loop, and then runs alone).
         self.max_inflight_edges = max_inflight_edges
         self.inflight_edges = 0
+        # Large requests (at least big_edges edges) run at most max_big_inflight at a time:
+        # two of them side by side would each be slowed by the other. A large request that
+        # has to wait for that lets the smaller requests behind it go first.
+        self.big_edges = big_edges
+        self.max_big_inflight = int(max_big_inflight)
+        self.big_inflight = 0
         self.clock = clock
         # called once per request as it completes (e.g. to check and release its result)
         self.on_done = on_done
@@ -162,6 +170,7 @@ class GeeServer:
                         self.on_done(r)
                 self.in_use -= f.nbytes
                 self.inflight_edges -= f.edges
+                self.big_inflight -= f.bigs
                 self.free_slots.append(f.slot)
                 n += 1
             else:
@@ -182,11 +191,15 @@ class GeeServer:
             batch: List[Request] = []
             nbytes = 0
             edges = 0
+            bigs = 0
             for r in self.queue:
                 if len(batch) >= self.max_batch:
                     break
                 if r.cancelled:
                     continue
+                big = self.big_edges is not None and r.E >= self.big_edges
+                if big and self.big_inflight + bigs >= self.max_big_inflight:
+                    continue  # waits for the large request in flight; smaller ones pass it
                 # the batch is charged what it holds with r in it, not the sum of its members
                 need = self.backend.batch_footprint(batch + [r]) if batch else r.nbytes
                 if self.in_use + need > self.budget:
@@ -199,6 +212,7 @@ class GeeServer:
                 batch.append(r)
                 nbytes = need
                 edges += r.E
+                bigs += 1 if big else 0
             if not batch:
                 break
             ids = {id(r) for r in batch}
@@ -208,9 +222,10 @@ class GeeServer:
             for r in batch:
                 r.t_admit = now
             handle = self.backend.launch(batch, slot)
-            self.flights.append(_Flight(slot, handle, batch, nbytes, edges))
+            self.flights.append(_Flight(slot, handle, batch, nbytes, edges, bigs))
             self.in_use += nbytes
             self.inflight_edges += edges
+            self.big_inflight += bigs
             self.peak_in_use = max(self.peak_in_use, self.in_use)
             self.peak_flights = max(self.peak_flights, len(self.flights))
             self.launch_log.append([r.rid for r in batch])

@@ -216,6 +216,38 @@ def test_inflight_edge_cap():
     assert srv.inflight_edges == 0
 
 
+def test_large_requests_run_one_at_a_time_and_smaller_ones_pass():
+    """big_edges: two large requests are never in flight together; a large request that
+    waits for another lets the smaller requests queued behind it go first, and every
+    request still completes."""
+    clk = Clock()
+    be = FakeBackend(clk, slots=4, launch_cost=1e-4, per_edge=1e-5)
+    reqs = _reqs(40, seed=11, rate=1e6)
+    bigs = {4, 5, 6, 20}
+    for i in bigs:
+        reqs[i] = Request(rid=i, graph={"g": random_small_graph(900 + i, N=250, E=1900, K=3)},
+                          arrival=reqs[i].arrival)
+    srv = GeeServer(be, 10 ** 9, max_batch=4, clock=clk, big_edges=1500, max_big_inflight=1)
+    seen = []
+    orig_launch = be.launch
+
+    def launch(batch, slot):
+        seen.append((sum(1 for r in batch if r.E >= 1500), srv.big_inflight))
+        return orig_launch(batch, slot)
+
+    be.launch = launch
+    srv.run_trace(reqs, sleep=clk.sleep)
+    assert all(r.t_done is not None and r.error is None for r in reqs)
+    # at most one large request per batch and none joins another in flight
+    assert all(nb <= 1 and (nb == 0 or inflight == 0) for nb, inflight in seen)
+    assert srv.big_inflight == 0
+    flat = [rid for b in be.launched for rid in b]
+    assert sorted(flat) == list(range(40)) and len(flat) == 40
+    # request 5 waited for request 4, and requests queued behind it started before it
+    pos = {rid: k for k, rid in enumerate(flat)}
+    assert pos[5] > pos[4] and any(pos[j] < pos[5] for j in range(7, 20))
+
+
 class _SizingBackend:
     """The GPU backend's own footprints (library size queries, host only) with launches
     simulated on the virtual clock."""
