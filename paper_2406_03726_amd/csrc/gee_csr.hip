@@ -44,6 +44,9 @@ constexpr int kWaves = GEE_PART_WAVES;    // wavefronts per partition workgroup
 constexpr int kThreads = kWaves * 64;
 constexpr int kQuarter = kTile / kWaves;  // items per wavefront per tile
 constexpr int kRoundsW = kQuarter / 64;   // rounds of one wavefront
+#ifndef GEE_QUARTER_BUF
+#define GEE_QUARTER_BUF 1
+#endif
 #ifndef GEE_OUT_UNROLL
 #define GEE_OUT_UNROLL 4
 #endif
@@ -213,6 +216,49 @@ __device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t
             if (VAL) q.val[r] = val;
             q.valid |= ok ? (1u << r) : 0u;
         }
+    }
+}
+
+// load_quarter for one graph whose edge arrays fit 32-bit buffer offsets: the same entries in
+// the same order, read with buffer loads whose per-round part of the offset is the same for
+// the whole wavefront (a scalar offset) and whose per-lane part is fixed, so the rounds cost
+// no address arithmetic; loads past the arrays' end return 0 (those entries are invalid).
+template <bool VAL>
+__device__ __forceinline__ void load_quarter_buf(const GDesc &gd, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
+                                                 bool &badw) {
+    const int lane = lane_id();
+    q.valid = 0;
+    if (vw >= V) return;
+    const bool sym = gd.flags & kSym;
+    const bool chk = validates(gd);
+    const int64_t lv0 = vw - gd.voff;  // (even: quarters start at multiples of kQuarter)
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(gd.src, gd.E * 4), rd = buffer_rsrc(gd.dst, gd.E * 4);
+    const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(gd.w, gd.w ? gd.E * 4 : 0);
+    // entry lv0 + 64 r + lane is edge (lv0 + 64 r + lane) / 2 under symmetrization
+    const uint32_t lo = (uint32_t)(sym ? (lane >> 1) : lane) * 4u;
+    const int64_t e0 = sym ? (lv0 >> 1) : lv0;
+    const int step = sym ? 32 : 64;
+    int sv[kRoundsW], dv[kRoundsW];
+    float wv[kRoundsW];
+#pragma unroll
+    for (int r = 0; r < kRoundsW; ++r) {
+        const int so = __builtin_amdgcn_readfirstlane((int)((e0 + (int64_t)r * step) * 4));
+        sv[r] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs, lo, so, 0);
+        dv[r] = (int)__builtin_amdgcn_raw_buffer_load_b32(rd, lo, so, 0);
+        if (VAL) wv[r] = gd.w ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, lo, so, 0)) : 1.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundsW; ++r) {
+        const int64_t v = vw + r * 64 + lane;
+        const int side = sym ? (lane & 1) : 0;
+        const bool inb = v < V;
+        const bool inr = (unsigned)sv[r] < (unsigned)gd.N && (unsigned)dv[r] < (unsigned)gd.N;
+        if (chk && inb && !inr) badi = true;
+        if (VAL && chk && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
+        q.key[r] = (side ? dv[r] : sv[r]) + gd.node_off;
+        q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
+        if (VAL) q.val[r] = wv[r];
+        q.valid |= (inb && inr && (side == 0 || sv[r] != dv[r])) ? (1u << r) : 0u;
     }
 }
 
@@ -449,7 +495,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
                                                       float *__restrict__ oval, unsigned *status, int with_b, int B,
                                                       int *__restrict__ seg_start, int *__restrict__ tile_off,
                                                       int *__restrict__ bstart, int *__restrict__ meta, int bal,
-                                                      int *__restrict__ ptot, int *__restrict__ tile_seg) {
+                                                      int *__restrict__ ptot, int *__restrict__ tile_seg,
+                                                      int qbuf) {
     __shared__ PartLds<AK> L;
     const int wv = threadIdx.x >> 6;
     const int64_t t = xcd_order(blockIdx.x, T);
@@ -459,7 +506,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     const int gtile = (int)threadIdx.x < D ? gh[(int64_t)threadIdx.x * T + t] : 0;
     bool badi = false, badw = false;
     Quarter<true> q;
-    load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+    if (qbuf) load_quarter_buf<true>(b.one, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
+    else load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
     __syncthreads();
 #pragma unroll
@@ -970,16 +1018,18 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     // the bucket path's part-table block totals, formed by the pass-B scan
     int *ptot = (p.bucket && with_b) ? wk.ptot : nullptr;
+    // one graph whose edge arrays fit 32-bit offsets: buffer loads with scalar round offsets
+    const int qbuf = (GEE_QUARTER_BUF && b.tab == nullptr && b.one.E * 4 + 256 < (int64_t)0x7FFFFFFF) ? 1 : 0;
     prof_begin(kKAScatter, s);
     const int wb = with_b ? 1 : 0;
     if (k16) {
         hipLaunchKernelGGL(a_scatter<uint16_t>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, akey16, (1 << (p.sb + p.s2)) - 1, acol, aval, status, wb, p.B,
-                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal, ptot, wk.segB);
+                           wk.segA, wk.tileB, wk.bstart, wk.meta, bal, ptot, wk.segB, qbuf);
     } else {
         hipLaunchKernelGGL(a_scatter<int>, dim3((unsigned)p.TA), dim3(kThreads), 0, s, b, p.Vtot, shift, p.DA, nbits,
                            p.TA, wk.ghA, wk.totA, wk.akey, -1, acol, aval, status, wb, p.B, wk.segA, wk.tileB,
-                           wk.bstart, wk.meta, bal, ptot, wk.segB);
+                           wk.bstart, wk.meta, bal, ptot, wk.segB, qbuf);
     }
     prof_end(kKAScatter, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
