@@ -8,7 +8,8 @@
 //   zs_count  per tile: each row's number of non-zero entries (kept), and the tile's total
 //   zs_scan   one workgroup: exclusive scan of the tile counts, total into row_ptr[N]
 //   zs_write  per tile: the rows' counts scanned in LDS, then row_ptr and the compacted
-//             (class, value) pairs at each lane's rank within its row (one pass over Z)
+//             (class, value) pairs at each lane's rank within its row (one pass over Z);
+//             zs_flat does the same over Z as a flat stream when K >= 4
 #include "gee_internal.h"
 
 namespace gee {
@@ -16,6 +17,9 @@ namespace {
 
 constexpr int kZT = 256;   // rows per tile
 constexpr int kZB = 256;   // threads per workgroup of the tile kernels
+#ifndef GEE_ZS_FLAT
+#define GEE_ZS_FLAT 1
+#endif
 
 // Bits of `m` that belong to this lane's group of L lanes, shifted down to bit 0.
 template <int L>
@@ -150,6 +154,75 @@ __global__ __launch_bounds__(kZB) void zs_write(const float *__restrict__ Z, int
     }
 }
 
+// zs_write over Z as one flat row-major stream (K >= 4, Z 16-byte aligned): the output is Z's
+// non-zero values in row-major order, so an entry's place is the tile's offset plus the
+// number of non-zeros before it in the tile. Wavefront w takes the tile's rows 64w ..
+// 64w + 63 (a contiguous range of floats, whose first place comes from the scanned row
+// counts), four consecutive floats per lane per 16-byte load, and ranks each non-zero by
+// four ballots; its class is its index within the row. Same output as zs_write.
+__global__ __launch_bounds__(kZB) void zs_flat(const float *__restrict__ Z, int N, int K,
+                                             const int *__restrict__ row_cnt, const int *__restrict__ tile_off,
+                                             int *__restrict__ row_ptr, int *__restrict__ col,
+                                             float *__restrict__ val, int64_t cap) {
+    static_assert(kZT == kZB && kZB == 256, "one thread per row of the tile, four wavefronts of 64 rows");
+    __shared__ int cnt[kZT];
+    __shared__ int wsum[kZB / 64];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kZT;
+    const int r = threadIdx.x;
+    const int c = base + r < N ? row_cnt[base + r] : 0;
+    int tot = 0;
+    const int x = block_excl_scan<kZB>(c, wsum, tot);
+    cnt[r] = x;
+    const int64_t off = tile_off[blockIdx.x];
+    if (base + r < N) row_ptr[base + r] = (int)(off + x);
+    __syncthreads();
+    const int64_t r0 = base + 64 * wv;
+    const int nrows = (int)min((int64_t)64, (int64_t)N - r0);
+    if (nrows <= 0) return;
+    const int64_t f0 = r0 * K;                  // the wavefront's first float
+    const int nf = nrows * K;                   // its floats
+    const __amdgpu_buffer_rsrc_t rz = buffer_rsrc(Z + f0, (int64_t)nf * 4);
+    int64_t p = off + cnt[64 * wv];             // place of its first non-zero
+    const uint64_t below = (1ull << lane) - 1;  // lane < 64: lane 63 gives 2^63 - 1
+    for (int lf = 4 * lane, c0 = 0; c0 < nf; c0 += 256, lf += 256) {
+        float zz[4];
+        if (lf + 4 <= nf) {
+            const float4 z4 = buf_f4(rz, (uint32_t)lf * 4u);
+            zz[0] = z4.x;
+            zz[1] = z4.y;
+            zz[2] = z4.z;
+            zz[3] = z4.w;
+        } else {  // the range's last floats, one by one (0 past it)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                zz[j] = lf + j < nf ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rz, (uint32_t)(lf + j) * 4u, 0, 0))
+                                    : 0.0f;
+        }
+        uint64_t m[4];
+        int before = 0, mine = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            m[j] = ballot(zz[j] != 0.0f);
+            before += __popcll(m[j] & below);
+        }
+        int cls = lf % K;  // the class of the lane's first float
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (zz[j] != 0.0f) {
+                const int64_t q = p + before + mine;
+                if (q < cap) {
+                    col[q] = cls;
+                    val[q] = zz[j];
+                }
+                ++mine;
+            }
+            if (++cls == K) cls = 0;
+        }
+        p += __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
+    }
+}
+
 template <int L>
 hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
                      int64_t cap, bool counts_given, hipStream_t s) {
@@ -165,7 +238,11 @@ hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, 
     hipLaunchKernelGGL(zs_scan, dim3(1), dim3(1024), 0, s, tile, T, row_ptr, N);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     prof_begin(kKZsWrite, s);
-    hipLaunchKernelGGL(zs_write<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile, row_ptr, col, val, cap);
+    if (GEE_ZS_FLAT && K >= 4 && (reinterpret_cast<uintptr_t>(Z) & 15) == 0)
+        hipLaunchKernelGGL(zs_flat, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile, row_ptr, col, val, cap);
+    else
+        hipLaunchKernelGGL(zs_write<L>, dim3((unsigned)T), dim3(kZB), 0, s, Z, N, K, rcnt, tile, row_ptr, col, val,
+                           cap);
     prof_end(kKZsWrite, s);
     return hipGetLastError();
 }
