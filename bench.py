@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = ["class_count_partial", "class_count_final", "a_hist", "digit_scan", "a_scatter",
            "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows", "degree_rows",
            "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count", "bucket_part_fill", "bucket_degree",
-           "bucket_degree_fix", "bucket_embed", "bucket_embed_fix"]
+           "bucket_degree_fix", "bucket_embed", "bucket_embed_fix", "csr_prep"]
 
 
 def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
@@ -117,7 +117,7 @@ KERNEL_STEP = {
     "class_count_partial": "a1", "class_count_final": "a1",
     "a_hist": "a2", "digit_scan": "a2", "a_scatter": "a2", "b_hist": "a2", "b_scan": "a2", "b_scatter": "a2",
     "c_tiles": "a2", "c_hist": "a2", "c_scan": "a2", "c_scatter": "a2", "bucket_sort": "a2",
-    "bucket_part_count": "a2", "bucket_part_fill": "a2", "graph_meta": "a2", "zero_steps": "a2",
+    "bucket_part_count": "a2", "bucket_part_fill": "a2", "graph_meta": "a2", "zero_steps": "a2", "csr_prep": "a2",
     "node_rows": "a3", "degree_rows": "a3", "degree_fixup": "a3", "node_coef": "a3",
     "bucket_degree": "a3", "bucket_degree_fix": "a3",
     "fill_empty": "a4_a6", "embed_rows": "a4_a6", "embed_fixup": "a4_a6",

@@ -154,8 +154,9 @@ def choose(timings: Dict[Tuple[Tuple[str, int], ...], float]) -> Dict[str, int]:
 def candidates(path: str = "edge", entries: Optional[int] = None) -> List[Dict[str, int]]:
     """The schedules timed for a shape. Edge lists: part sizes x 32/64-row buckets; part
     sizes at or above the shape's entry count all give one part per bucket, so only the
-    smallest of them is kept. Resident CSR: wavefront sizes x wavefronts per workgroup,
-    wavefronts larger than the graph's entries dropped the same way."""
+    smallest of them is kept. Resident CSR: the bucket kernels (part sizes x 32/64-row
+    buckets, as for edge lists) and the CSR path's kernels (wavefront sizes x wavefronts per
+    workgroup, wavefronts larger than the graph's entries dropped the same way)."""
     if path == "edge":
         we = list(WAVE_ENTRIES)
         if entries is not None:
@@ -165,7 +166,8 @@ def candidates(path: str = "edge", entries: Optional[int] = None) -> List[Dict[s
         we = list(CSR_WAVE_ENTRIES)
         if entries is not None:
             we = [w for w in we if w < entries] + [w for w in we if w >= entries][:1]
-        return [{"wave_entries": w, "waves_per_block": b} for w in we for b in CSR_WAVES_PER_BLOCK]
+        return candidates("edge", entries) + [{"wave_entries": w, "waves_per_block": b} for w in we
+                                               for b in CSR_WAVES_PER_BLOCK]
     raise ValueError(path)
 
 

@@ -196,14 +196,16 @@ int bucket_path_sb(const GraphIn *gs, int G) {
 // Plan of a launch over G graphs. `resident`: the graphs are given as CSRs (E = M).
 // `edge_embed`: the launch embeds edge lists (gee_embed and batches), which take the
 // bucket path whenever its buckets can hold the launch's rows.
-int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDesc> &d, bool edge_embed = false) {
+// `csr_bucket`: a resident CSR embedded by the bucket kernels (rows from row_ptr).
+int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDesc> &d, bool edge_embed = false,
+              bool csr_bucket = false) {
     if (G < 1 || G > kMaxBatchGraphs) return GEE_ERR_ARG;
     p = Plan();
     p.G = G;
     d.assign(G, GDesc());
     int64_t voff = 0, noff = 0, woff = 0, parts = 0, coff = 0, cpo = 0, ktot = 0;
     int wpb = 0, sb_req = 0;
-    const int sb_bucket = edge_embed && !resident ? bucket_path_sb(gs, G) : -1;
+    const int sb_bucket = (edge_embed && !resident) || (resident && csr_bucket) ? bucket_path_sb(gs, G) : -1;
     p.bucket = sb_bucket >= 0;
     int64_t bparts = 0;
     for (int g = 0; g < G; ++g) {
@@ -383,6 +385,8 @@ size_t carve(const Plan &p, unsigned parts, char *base, Work &w) {
         if (p.weighted) w.val = (float *)take((size_t)p.Vtot * sizeof(float));
     }
     if ((parts & kPEmbed) && p.bucket) {
+        // (a resident CSR: the bucket starts come from row_ptr, no partition)
+        if (!(parts & kPPart)) w.bstart = (int *)take((size_t)(p.B + 1) * sizeof(int));
         w.info = (float2 *)take((size_t)p.Ntot * sizeof(float2));
         w.srow = (float *)take((size_t)p.Ntot * sizeof(float));
         w.part = (int4 *)take((size_t)p.bparts * sizeof(int4));
@@ -634,7 +638,7 @@ const char *const kKernelNames[kKNumKernels] = {
     "b_hist", "b_scan", "b_scatter", "c_tiles", "c_hist", "c_scan", "c_scatter", "bucket_sort", "graph_meta", "zero_steps", "node_rows",
     "degree_rows", "degree_fixup", "node_coef", "fill_empty", "embed_rows", "embed_fixup", "bucket_part_count",
     "bucket_part_fill", "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix",
-    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish", "zs_count", "zs_write", "zs_tile_sum"};
+    "edge_init", "edge_prep", "edge_coef", "edge_scatter", "edge_finish", "zs_count", "zs_write", "zs_tile_sum", "csr_prep"};
 
 void prof_begin(int kid, hipStream_t s) {
     if (!g_prof_active.load(std::memory_order_relaxed) || t_capturing) return;
@@ -1281,6 +1285,14 @@ int gee_batch_plan_destroy(gee_batch_plan *plan) {
 
 // --------------------------------------------------------------------------- embed from CSR
 
+// gee_embed_csr runs the bucket kernels (rows from row_ptr) unless its schedule asks for the
+// CSR path's kernels: wave_entries or waves_per_block set with no 32- or 64-row bucket size.
+// Past the bucket kernels' row limit it takes the CSR path's kernels in any case.
+bool resident_bucket_mode(const GraphIn &x) {
+    if (x.sc.bucket_rows_log2 == 5 || x.sc.bucket_rows_log2 == 6) return true;
+    return x.sc.wave_entries == 0 && x.sc.waves_per_block == 0 && x.sc.bucket_rows_log2 == 0;
+}
+
 size_t gee_embed_csr_workspace_bytes(int64_t M, int32_t N, int32_t K, uint32_t flags,
                                      const gee_schedule *sched) {
     GraphIn x;
@@ -1292,7 +1304,7 @@ size_t gee_embed_csr_workspace_bytes(int64_t M, int32_t N, int32_t K, uint32_t f
     if (sched) x.sc = *sched;
     Plan p;
     std::vector<GDesc> d;
-    if (M < 0 || make_plan(&x, 1, true, p, d)) return 0;
+    if (M < 0 || make_plan(&x, 1, true, p, d, false, resident_bucket_mode(x))) return 0;
     Work w;
     return carve(p, kPCount | kPEmbed, nullptr, w);
 }
@@ -1322,7 +1334,7 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     if (sched) x.sc = *sched;
     Plan p;
     std::vector<GDesc> d;
-    if ((rc = make_plan(&x, 1, true, p, d))) return rc;
+    if ((rc = make_plan(&x, 1, true, p, d, false, resident_bucket_mode(x)))) return rc;
     Work wk;
     const unsigned parts = kPCount | kPEmbed;
     if (!workspace || workspace_bytes < gee_embed_csr_workspace_bytes(M, N, K, flags, sched))
@@ -1333,6 +1345,11 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     b.one = d[0];
     b.status = st;
     b.gm = wk.gm;
+    if (p.bucket) {  // the bucket kernels, rows from row_ptr; meta[1] holds the CSR's check
+        hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s, wk.meta + 1);
+        if (e == hipSuccess) e = launch_bucket_embed_csr(b, p, wk, row_ptr, col, val, M, st, s);
+        return hip_status(e);
+    }
     hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s);
     if (e == hipSuccess) e = launch_graph_meta(b, nullptr, (int)M, s);
     if (e == hipSuccess) e = launch_node_prep(b, p, row_ptr, val, M, wk, st, s);

@@ -67,12 +67,12 @@ static size_t bucket_lds(int sb, int Kmax) {
 // large one-part buckets (the ptot of part_fill_block). After a pass B the pass-B scan has
 // formed them already (seg_scan) and this launch is skipped.
 __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__restrict__ bstart, int B, int sb,
-                                                          int *__restrict__ ptot) {
+                                                          int *__restrict__ ptot, const int *__restrict__ bad) {
     __shared__ int wsum[16];
     const int bk = blockIdx.x * 1024 + threadIdx.x;
     int k = 0, n = 0, P = 1;
     if (bk < B) {
-        n = bstart[bk + 1] - bstart[bk];
+        n = (bad && *bad) ? 0 : bstart[bk + 1] - bstart[bk];  // (a failed resident CSR: empty buckets)
         P = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
         k = parts_of(n, P);
     }
@@ -93,8 +93,9 @@ __global__ __launch_bounds__(1024) void bucket_part_count(Batch b, const int *__
 // the pass-B scatter fills it in extra workgroups instead and this launch is skipped.
 __global__ __launch_bounds__(256) void bucket_part_fill(Batch b, const int *__restrict__ bstart, int B, int sb,
                                                         const int *__restrict__ ptot, int4 *__restrict__ part,
-                                                        int4 *__restrict__ multi, int *__restrict__ bmeta) {
-    part_fill_block(b, bstart, B, sb, ptot, (int)gridDim.x, (int)blockIdx.x, part, multi, bmeta);
+                                                        int4 *__restrict__ multi, int *__restrict__ bmeta,
+                                                        const int *__restrict__ bad) {
+    part_fill_block(b, bstart, B, sb, ptot, (int)gridDim.x, (int)blockIdx.x, part, multi, bmeta, bad);
 }
 
 // s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count); the
@@ -131,8 +132,12 @@ struct Windows {
         int4 k, c;
         float4 v;
     };
-    __device__ __forceinline__ Windows(const KT *key, const int *col, const float *val, int a, int nwin) {
-        const int64_t n = (int64_t)nwin * BWIN;
+    // limit: entries readable from a (the end of caller arrays that carry no padding)
+    __device__ __forceinline__ Windows(const KT *key, const int *col, const float *val, int a, int nwin,
+                                       int64_t limit = INT64_MAX) {
+        int64_t n = (int64_t)nwin * BWIN;
+        n = n < limit ? n : limit;
+        n = n > 0 ? n : 0;
         rk = buffer_rsrc(key + a, n * (int64_t)sizeof(KT));
         rc = buffer_rsrc(COLS ? (const void *)(col + a) : (const void *)key, COLS ? n * 4 : 0);
         rv = buffer_rsrc(WEIGHTED ? (const void *)(val + a) : (const void *)key, WEIGHTED ? n * 4 : 0);
@@ -149,6 +154,44 @@ struct Windows {
         }
         if (COLS) r.c = buf_i4(rc, 4 * o);
         r.v = WEIGHTED ? buf_f4(rv, 4 * o) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    }
+};
+
+// Rows of a resident CSR's entries inside one bucket, from row_ptr alone (no key array):
+// lane r holds s = the first entry of the bucket's row r; the row of entry e is the number of
+// rows r with s_r <= e, less one. For a window of BWIN entries starting at w0 that is the
+// rows started before w0 (one ballot) plus the rows starting inside the window up to e: each
+// lane adds one to the 8-bit counter of its row's start position (four to a word in `cw`,
+// 64 words of LDS), each lane reads the word of its own four entries, and a wave scan adds
+// the counts of the lanes before it. Rows are clamped into the bucket (a malformed CSR has
+// been refused by csr_prep before any part is listed).
+struct CsrRows {
+    int s;
+    unsigned *cw;
+    __device__ __forceinline__ void init(const int *__restrict__ rp, int N, int64_t M, int row0, int R, int lane,
+                                         unsigned *words) {
+        cw = words;
+        s = INT_MAX;
+        if (lane < R) {
+            const int64_t v = rp[min(row0 + lane, N)];  // rows past N start at rp[N] = M
+            s = (int)(v < 0 ? 0 : (v > M ? M : v));
+        }
+    }
+    __device__ __forceinline__ void rows(int w0, int lane, int R, int (&row)[BEPL]) const {
+        const int before = __popcll(ballot(s < w0));
+        cw[lane] = 0u;
+        wave_lds_fence();
+        const int d = s - w0;  // (s = INT_MAX on lanes past the rows: no overflow, d >= BWIN)
+        if (d >= 0 && d < BWIN) atomicAdd(&cw[d >> 2], 1u << (8 * (d & 3)));
+        wave_lds_fence();
+        const unsigned q = cw[lane];
+        const int c0 = (int)(q & 0xFFu), c1 = c0 + (int)((q >> 8) & 0xFFu);
+        const int c2 = c1 + (int)((q >> 16) & 0xFFu), c3 = c2 + (int)(q >> 24);
+        const int base = before + wave_scan_add(c3) - c3 - 1;
+        const int cc[BEPL] = {c0, c1, c2, c3};
+#pragma unroll
+        for (int j = 0; j < BEPL; ++j) row[j] = min(max(base + cc[j], 0), R - 1);
+        wave_lds_fence();
     }
 };
 
@@ -174,15 +217,18 @@ __device__ __forceinline__ bool part_view(const Batch &b, int j, const int4 *__r
 // With PACKED the rows come from the packed column words (see bucket_embed), read in
 // place of the keys.
 constexpr int kDegCopies = 32;
-template <typename KT, bool WEIGHTED, bool PACKED>
+// With CSRM (a resident CSR: no keys, no packed words) the rows come from row_ptr
+// (CsrRows) and the entry arrays are the caller's, of M entries.
+template <typename KT, bool WEIGHTED, bool PACKED, bool CSRM = false>
 __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restrict__ key, const int *__restrict__ pcol,
                                                      const float *__restrict__ val,
                                                      const int4 *__restrict__ part, int cap,
                                                      const int *__restrict__ bmeta, int sb,
                                                      const float *__restrict__ inv_n,
                                                      float *__restrict__ dpart, float *__restrict__ srow,
-                                                     float2 *__restrict__ info, int mode) {
-    extern __shared__ float dsum_all[];  // [4][kDegCopies][R + 1]
+                                                     float2 *__restrict__ info, int mode,
+                                                     const int *__restrict__ rp = nullptr, int64_t M = 0) {
+    extern __shared__ float dsum_all[];  // [4][kDegCopies][R + 1], then (CSRM) [4][64] row-start counters
     const int lane = lane_id();
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int4 pt;
@@ -203,15 +249,24 @@ __global__ __launch_bounds__(256) void bucket_degree(Batch b, const KT *__restri
     float *mine = dsum + (lane & (kDegCopies - 1)) * RS;
     const bool wt = WEIGHTED && gd.weighted;
     const int rmask = R - 1;
-    using W = Windows<KT, WEIGHTED, PACKED, !PACKED>;
+    using W = Windows<KT, WEIGHTED, PACKED, !PACKED && !CSRM>;
     const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
-    const W win(key, pcol, val, pt.y, nwin);
+    const W win(key, pcol, val, pt.y, nwin, CSRM ? M - pt.y : INT64_MAX);
+    CsrRows cr;
+    if (CSRM)
+        cr.init(rp, gd.N, M, (pt.x << sb) - gd.node_off, R, lane,
+                reinterpret_cast<unsigned *>(dsum_all + 4 * kDegCopies * RS) + 64 * wib);
     // window i: entries masked past the part's end add 0
     auto add = [&](int i, const typename W::Raw &q) {
         const int nv = min(BEPL, max(0, pt.z - (pt.y + i * BWIN + BEPL * lane)));
-        const int4 k4 = PACKED ? make_int4(q.c.x >> kPackShift, q.c.y >> kPackShift, q.c.z >> kPackShift,
-                                           q.c.w >> kPackShift)
-                               : q.k;
+        int4 k4 = PACKED ? make_int4(q.c.x >> kPackShift, q.c.y >> kPackShift, q.c.z >> kPackShift,
+                                     q.c.w >> kPackShift)
+                         : q.k;
+        if (CSRM) {
+            int rr[BEPL];
+            cr.rows(pt.y + i * BWIN, lane, R, rr);
+            k4 = make_int4(rr[0], rr[1], rr[2], rr[3]);
+        }
         const int kk[BEPL] = {k4.x, k4.y, k4.z, k4.w};
         const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
         float x[BEPL];
@@ -391,14 +446,17 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
 
 // With PACKED (after a pass B) each column word carries its row inside the bucket above
 // its kPackShift bits, so the keys are not read.
-template <typename KT, bool WEIGHTED, bool PACKED>
+// With CSRM (a resident CSR) the rows come from row_ptr (CsrRows), the entry arrays are the
+// caller's, of M entries, and columns outside [0, N) are skipped and raise GEE_DATA_CSR.
+template <typename KT, bool WEIGHTED, bool PACKED, bool CSRM = false>
 __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val,
                                                    const int4 *__restrict__ part, int cap,
                                                    const int *__restrict__ bmeta, int sb,
                                                    const float2 *__restrict__ info,
                                                    const float *__restrict__ srow, float *__restrict__ zpart, int zs,
-                                                   int *__restrict__ rcnt) {
+                                                   int *__restrict__ rcnt, const int *__restrict__ rp = nullptr,
+                                                   int64_t M = 0) {
     extern __shared__ float smem_b[];
     const int lane = lane_id();
     int4 pt;
@@ -420,9 +478,14 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     }
     wave_lds_fence();
 
-    using W = Windows<KT, WEIGHTED, true, !PACKED>;
+    using W = Windows<KT, WEIGHTED, true, !PACKED && !CSRM>;
     const int nwin = (pt.z - pt.y + BWIN - 1) / BWIN;
-    const W win(key, col, val, pt.y, nwin);
+    const W win(key, col, val, pt.y, nwin, CSRM ? M - pt.y : INT64_MAX);
+    CsrRows cr;
+    if (CSRM)
+        cr.init(rp, gd.N, M, r0 - node_off, R, lane, reinterpret_cast<unsigned *>(tag + kTagBytes));
+    const bool chk = CSRM && validates(gd);
+    bool badc = false;
     const __amdgpu_buffer_rsrc_t r_inf = buffer_rsrc(info + node_off, (int64_t)gd.N * 8);
     struct Prep {
         int row[BEPL];
@@ -431,15 +494,21 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     };
     auto prep = [&](int i, const typename W::Raw &q, Prep &P) {
         const int nv = min(BEPL, max(0, pt.z - (pt.y + i * BWIN + BEPL * lane)));
-        const int kk[BEPL] = {q.k.x, q.k.y, q.k.z, q.k.w};
+        int kk[BEPL] = {q.k.x, q.k.y, q.k.z, q.k.w};
         const int cc[BEPL] = {q.c.x, q.c.y, q.c.z, q.c.w};
         const float vv[BEPL] = {q.v.x, q.v.y, q.v.z, q.v.w};
+        if (CSRM) cr.rows(pt.y + i * BWIN, lane, R, kk);
 #pragma unroll
         for (int j = 0; j < BEPL; ++j) {
             const int cj = PACKED ? (cc[j] & ((1 << kPackShift) - 1)) : cc[j];
-            const unsigned u = j < nv ? (unsigned)(cj - node_off) : 0xFFFFFFFFu;
+            bool use = j < nv;
+            if (CSRM && use && (unsigned)(cj - node_off) >= (unsigned)gd.N) {
+                badc = true;  // a column outside the graph: skipped
+                use = false;
+            }
+            const unsigned u = use ? (unsigned)(cj - node_off) : 0xFFFFFFFFu;
             P.row[j] = (PACKED ? (cc[j] >> kPackShift) : kk[j]) & rmask;
-            P.x[j] = j < nv ? vv[j] : 0.0f;
+            P.x[j] = use ? vv[j] : 0.0f;
             P.f[j] = buf_f2(r_inf, u << 3);
         }
     };
@@ -486,6 +555,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     }
 #undef EMB_SB
     wave_lds_fence();
+    if (CSRM && chk && __ballot(badc ? 1 : 0) != 0 && lane == 0) raise_error(b.status, kErrCsr);
     if (pt.w < 0) {
         finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, lane, b.status, rcnt);
         wave_lds_fence();
@@ -579,6 +649,82 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
     }
 }
 
+// ----------------------------------------------------------------------------- resident CSR
+
+// Thread per row pointer of a resident CSR: the checks (row_ptr[0] = 0, non-decreasing,
+// within [0, M], row_ptr[N] = M; a failure sets *bad, which empties every bucket, and raises
+// GEE_DATA_CSR unless the graph skips validation) and the bucket starts bstart[b] =
+// row_ptr[b R] (clamped into [0, M]; bstart[B] = row_ptr[N]).
+__global__ __launch_bounds__(256) void csr_prep(const int *__restrict__ rp, int N, int64_t M, int sb,
+                                                int *__restrict__ bstart, int *__restrict__ bad, unsigned *status,
+                                                int chk) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i > N) return;
+    const int64_t v = rp[i];
+    bool wrong = v < 0 || v > M || (i == 0 && v != 0) || (i == N && v != M);
+    if (i < N) wrong = wrong || rp[i + 1] < v;
+    if (wrong) {
+        *bad = 1;
+        if (chk) raise_error(status, kErrCsr);
+    }
+    const int R = 1 << sb;
+    if ((i & (R - 1)) == 0 || i == N) bstart[(i + R - 1) >> sb] = (int)(v < 0 ? 0 : (v > M ? M : v));
+}
+
+template <bool WEIGHTED>
+static hipError_t launch_bucket_sums_csr(const Batch &b, const Plan &p, const Work &wk, const int *rp, const int *col,
+                                         const float *val, int64_t M, hipStream_t s) {
+    const unsigned nbp = (unsigned)p.bparts;
+    const int mode = kDegBoth;
+    prof_begin(kKBucketDegree, s);
+    const size_t dlds = (size_t)4 * kDegCopies * ((1 << p.sb) + 1) * sizeof(float) + 4 * 64 * sizeof(unsigned);
+    hipLaunchKernelGGL((bucket_degree<int, WEIGHTED, false, true>), dim3((nbp + 3) / 4), dim3(256), dlds, s, b,
+                       (const int *)nullptr, col, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow,
+                       wk.info, mode, rp, M);
+    prof_end(kKBucketDegree, s);
+    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);
+    prof_begin(kKBucketDegreeFix, s);
+    hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
+                       wk.dpart, wk.srow, wk.info, mode);
+    prof_end(kKBucketDegreeFix, s);
+    const size_t lds = bucket_lds(p.sb, p.Kmax) + 64 * sizeof(unsigned);
+    const int zs = p.Kmax << p.sb;
+    prof_begin(kKBucketEmbed, s);
+    hipLaunchKernelGGL((bucket_embed<int, WEIGHTED, false, true>), dim3(nbp), dim3(64), lds, s, b, (const int *)nullptr,
+                       col, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs,
+                       (int *)nullptr, rp, M);
+    prof_end(kKBucketEmbed, s);
+    prof_begin(kKBucketEmbedFix, s);
+    hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
+                       wk.srow, wk.zpart, zs, (int *)nullptr);
+    prof_end(kKBucketEmbedFix, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk, const int *rp, const int *col,
+                                   const float *val, int64_t M, unsigned *status, hipStream_t s) {
+    const int N = (int)p.Ntot;
+    int *bad = wk.meta + 1;  // cleared by the class-count launch before this one
+    prof_begin(kKCsrPrep, s);
+    hipLaunchKernelGGL(csr_prep, dim3((unsigned)((N + 1 + 255) / 256)), dim3(256), 0, s, rp, N, M, p.sb, wk.bstart,
+                       bad, status, (b.one.flags & kNoValidate) ? 0 : 1);
+    prof_end(kKCsrPrep, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
+    prof_begin(kKBucketPartCount, s);
+    hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
+                       (const int *)bad);
+    prof_end(kKBucketPartCount, s);
+    prof_begin(kKBucketPartFill, s);
+    hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
+                       wk.multi, wk.bmeta, (const int *)bad);
+    prof_end(kKBucketPartFill, s);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return val ? launch_bucket_sums_csr<true>(b, p, wk, rp, col, val, M, s)
+               : launch_bucket_sums_csr<false>(b, p, wk, rp, col, val, M, s);
+}
+
 // ----------------------------------------------------------------------------- launch
 
 template <typename KT, bool WEIGHTED>
@@ -629,11 +775,12 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
     const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
     if (!with_b) {  // (after a pass B its scan has formed the block totals and its scatter the table)
         prof_begin(kKBucketPartCount, s);
-        hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot);
+        hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
+                           (const int *)nullptr);
         prof_end(kKBucketPartCount, s);
         prof_begin(kKBucketPartFill, s);
         hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
-                           wk.multi, wk.bmeta);
+                           wk.multi, wk.bmeta, (const int *)nullptr);
         prof_end(kKBucketPartFill, s);
     }
     if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s, mode, sums);

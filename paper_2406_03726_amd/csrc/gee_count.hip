@@ -8,8 +8,9 @@
 namespace gee {
 
 __global__ __launch_bounds__(256) void class_count_partial(Batch b, int *__restrict__ part,
-                                                           unsigned *status) {
+                                                           unsigned *status, int *__restrict__ zero_word) {
     __shared__ int hist[kMaxClasses];
+    if (zero_word && blockIdx.x == 0 && threadIdx.x == 0) *zero_word = 0;
     class_count_slice(b, blockIdx.x, part, status, hist);
 }
 
@@ -44,9 +45,10 @@ hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s
 }
 
 hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
-                               unsigned *status, hipStream_t s) {
+                               unsigned *status, hipStream_t s, int *zero_word) {
     prof_begin(kKCountPartial, s);
-    hipLaunchKernelGGL(class_count_partial, dim3((unsigned)p.cnt_blocks), dim3(256), 0, s, b, part, status);
+    hipLaunchKernelGGL(class_count_partial, dim3((unsigned)p.cnt_blocks), dim3(256), 0, s, b, part, status,
+                       zero_word);
     prof_end(kKCountPartial, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

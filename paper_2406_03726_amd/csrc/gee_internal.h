@@ -457,10 +457,12 @@ __device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 
 // split bucket also gets {bucket, first slot, parts} in `multi`. ptot holds the four
 // totals of every block (parts, slots, split buckets, large one-part buckets); the last
 // block writes bmeta = {parts, split buckets}.
+// With `bad` set (a resident CSR that failed its checks) every bucket counts as empty.
 __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__restrict__ bstart, int B, int sb,
                                                 const int *__restrict__ ptot, int nblk, int blk,
                                                 int4 *__restrict__ part, int4 *__restrict__ multi,
-                                                int *__restrict__ bmeta) {
+                                                int *__restrict__ bmeta, const int *__restrict__ bad = nullptr) {
+    const bool none = bad && *bad;
     __shared__ int pf_wsum[4];
     // before this block: parts, slots, split buckets, large one-part buckets, small
     // one-part buckets; over all blocks: slots, large one-part buckets
@@ -497,7 +499,7 @@ __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__res
         if (bk < B) {
             P[u] = load_desc(b, find_graph(b.node_offs, b.G, bk << sb)).WE;
             s0[u] = bstart[bk];
-            s1[u] = bstart[bk + 1];
+            s1[u] = none ? s0[u] : bstart[bk + 1];
             k[u] = parts_of(s1[u] - s0[u], P[u]);
         }
         const bool large = large_single(s1[u] - s0[u], k[u], P[u]);
@@ -583,7 +585,7 @@ enum KernelId : int {
     kKBScatter, kKCTiles, kKCHist, kKCScan, kKCScatter, kKBucketSort, kKGraphMeta, kKZeroSteps, kKNodeRows, kKDegreeRows, kKDegreeFixup,
     kKNodeCoef, kKFillEmpty, kKEmbedRows, kKEmbedFixup, kKBucketPartCount, kKBucketPartFill, kKBucketDegree,
     kKBucketDegreeFix, kKBucketEmbed, kKBucketEmbedFix, kKEdgeInit, kKEdgePrep, kKEdgeCoef, kKEdgeScatter,
-    kKEdgeFinish, kKZsCount, kKZsWrite, kKZsTileSum, kKNumKernels
+    kKEdgeFinish, kKZsCount, kKZsWrite, kKZsTileSum, kKCsrPrep, kKNumKernels
 };
 extern const char *const kKernelNames[kKNumKernels];
 void prof_begin(int kid, hipStream_t s);
@@ -593,9 +595,10 @@ void prof_end(int kid, hipStream_t s);
 // gee_count.hip: host bytes -> device memory, stream-ordered, in kernel-argument chunks.
 constexpr int kUploadChunk = 2048;
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
-// gee_count.hip: counts[class_off + k] and inv_n (inv_n may be nullptr).
+// gee_count.hip: counts[class_off + k] and inv_n (inv_n may be nullptr); zero_word (if
+// given) is set to 0 first, in stream order before every later launch of the call.
 hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
-                               unsigned *status, hipStream_t s);
+                               unsigned *status, hipStream_t s, int *zero_word = nullptr);
 // gee_csr.hip: edge lists -> CSR of the union (rows and columns offset by node_off).
 // With job, the class counts of the launch run in the same launches.
 hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s,
@@ -616,6 +619,10 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
                         int64_t n_entries, const Work &wk, unsigned *status, hipStream_t s);
 // gee_bucket.hip: Z straight from the row buckets of the first two sort passes
 // (launch_csr_build), for plans with p.bucket.
+// A resident CSR through the bucket kernels (plans made with csr_bucket): its checks and
+// bucket starts (csr_prep), the part table, degrees and class sums, rows from row_ptr.
+hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk, const int *rp, const int *col,
+                                   const float *val, int64_t M, unsigned *status, hipStream_t s);
 constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
 constexpr int kBucketDefaultPart = 8192;
 constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end

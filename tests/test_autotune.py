@@ -42,14 +42,19 @@ def test_candidates_skip_equivalent_part_sizes():
     c = at.candidates("edge", 5000)
     assert {x["wave_entries"] for x in c} == {2048, 4096, 8192}
     assert len(at.candidates("edge")) == len(at.WAVE_ENTRIES) * len(at.BUCKET_SB)
+    # resident CSR: the bucket kernels' candidates, then the CSR path's kernels'
     c = at.candidates("csr", 600)
-    assert {x["wave_entries"] for x in c} == {256, 512, 1024}
-    assert {x["waves_per_block"] for x in c} == set(at.CSR_WAVES_PER_BLOCK)
+    bk = [x for x in c if "bucket_rows_log2" in x]
+    cp = [x for x in c if "waves_per_block" in x]
+    assert len(bk) + len(cp) == len(c)
+    assert bk == at.candidates("edge", 600)
+    assert {x["wave_entries"] for x in cp} == {256, 512, 1024}
+    assert {x["waves_per_block"] for x in cp} == set(at.CSR_WAVES_PER_BLOCK)
 
 
 def test_csr_path_table_is_separate():
     shapes = [(200_000, 4000, 8, 7)]  # resident CSR: flags without symmetrization
-    t = at.tune(shapes, lambda s, c: c["wave_entries"] / 1000 + c["waves_per_block"], path="csr")
+    t = at.tune(shapes, lambda s, c: c["wave_entries"] / 1000 + c.get("waves_per_block", 10), path="csr")
     assert t.lookup(200_000, 4000, 8, 7, path="csr") == {"wave_entries": 256, "waves_per_block": 1}
     assert t.lookup(200_000, 4000, 8, 7) == {}  # nothing tuned for edge lists
     assert at.csr_shape((100_000, 4000, 8, 15)) == (200_000, 4000, 8, 7)
