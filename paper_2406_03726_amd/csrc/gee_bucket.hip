@@ -3,13 +3,16 @@
 // The edge-list entry points need every row's sums, not the CSR itself. After the first
 // two partition passes of the sort (gee_csr.hip) the entries of each bucket of R
 // consecutive rows (R = 64; 32 when a graph of the launch has K > 64 and 32-row buckets
-// hold the launch's rows) lie together, in input order. Each bucket is cut into parts of
-// at most P entries (P = the graph's wave_entries, at least kBucketMinPart), one
-// wavefront per part:
+// hold the launch's rows) lie together, in input order; after a pass B each entry's row
+// inside its bucket rides in its column word (above bit kPackShift), and no key array is
+// written. A resident CSR's buckets are contiguous already: its rows come from row_ptr
+// (CsrRows, csr_prep). Each bucket is cut into parts of at most P entries (P = the graph's
+// wave_entries, at least kBucketMinPart), one wavefront per part:
 //
 //   * bucket_part_count / bucket_part_fill  the part table {bucket, entries, partial slot}
 //                    and the list of buckets of several parts (two passes of prefix sums
-//                    over the buckets).
+//                    over the buckets; after a pass B the first runs in its scan and the
+//                    second in extra workgroups of its scatter, part_fill_block).
 //   * bucket_degree  (Laplacian) each part's weighted degrees (entry counts without weights)
 //                    of the bucket's rows, summed in private LDS copies; a one-part bucket
 //                    then sets s_i and c_i = s_i / n_{y_i} of its rows, a longer one leaves
@@ -767,8 +770,8 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
 }
 
 hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hipStream_t s, int mode, bool sums) {
-    // keys of the bucketed entries: pass B's u16 row-in-bucket, else pass A's key (u16
-    // when the row's low bits fit, else the whole row)
+    // rows of the bucketed entries: after a pass B packed into the column words, else pass
+    // A's key (u16 when the row's low bits fit, else the whole row)
     const bool with_b = p.s2 > 0;
     const bool key16 = with_b || p.sb + p.s2 <= 16;
     const void *key = with_b ? (const void *)wk.tkey : (const void *)wk.akey;

@@ -19,7 +19,9 @@
 //           the row inside the bucket as the digit, over many workgroups (c_tiles,
 //           seg_hist, seg_scan, seg_scatter)
 //
-// With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped.
+// With few buckets (s2 = 0) pass A partitions by bucket and pass B is skipped. The bucket
+// path (gee_bucket.hip) stops after pass B: it needs each bucket's entries together, not
+// the rows in order.
 //
 // Tiles are numbered so that each XCD takes one contiguous range of them (xcd_order): the
 // runs that neighbouring tiles write end and start in the same cache lines, which one L2
@@ -720,8 +722,10 @@ __global__ __launch_bounds__(1024) void seg_scan(int *__restrict__ gh, int dbits
 
 // Per tile: sorted by digit in LDS (wave-split ranking over registers), written in runs.
 // FINAL = false (pass B): key, column and value go to the next pass, the key reduced to
-// the row inside its bucket (key & kmask). FINAL = true (pass C): column and value go to
-// their CSR slots.
+// the row inside its bucket (key & kmask) — for the bucket path (pack) packed into the
+// column word above kBucketPackShift instead, with no key array (okey null). FINAL = true
+// (pass C): column and value go to their CSR slots. With pf.nblk > 0 the first workgroups
+// fill the bucket path's part table instead (part_fill_block).
 template <typename KT, bool FINAL>
 __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ key, const int *__restrict__ col,
                                                    const float *__restrict__ val, int dshift, int dbits, int kmask,
