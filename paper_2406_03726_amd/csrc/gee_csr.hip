@@ -405,7 +405,18 @@ struct PartLds {
     unsigned char dig[kTile]; // its digit (at most 256 digits)
     int col[kTile];
     float val[kTile];
+    // kRankMask ranking: each wavefront's 256 peer masks, in the column staging area (not
+    // in use until the ranks are known)
+    __device__ __forceinline__ unsigned long long *masks(int wv) {
+        return reinterpret_cast<unsigned long long *>(col) + wv * 256;
+    }
+    __device__ __forceinline__ void zero_masks() {
+        for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) masks(0)[i] = 0ull;
+    }
 };
+static_assert(kTile * sizeof(int) >= kWaves * 256 * sizeof(unsigned long long), "peer masks fit the column staging");
+static_assert(offsetof(PartLds<uint16_t>, col) % 8 == 0 && offsetof(PartLds<int>, col) % 8 == 0,
+              "peer masks are 8-byte aligned");
 
 // Thread d: the offset from a tile position of digit d to its global position (gdelta =
 // the run's global base minus the tile's first position of d), and the first position of
@@ -446,21 +457,30 @@ __device__ __forceinline__ int wave_rank(int *run, int digit, bool valid) {
 // Positions of a wavefront's R rounds of items (round r: digit[r], valid bit r), in round
 // and lane order. Without bal, wave_rank per item. With bal, the same stable positions
 // without relying on the order in which the LDS serves the lanes of one atomic instruction
-// that hit one word: the lanes of a round with the same digit find each other by ballots
-// over the digit's nbits bits; the last of them alone adds their count to the digit's
-// running position (so no two lanes of an instruction touch one word), and each peer takes
-// the returned base, read from that lane, plus the number of peers below it. The LDS
-// operations of one wavefront take effect in program order, so each round sees the
-// additions of the rounds before it; all rounds' adds are issued before any base is read,
-// so no round waits for the previous one's LDS round trip. The CSR build (its bit-exact
-// contract) ranks this way; the bucket path, whose entry order only sets the
-// floating-point summation order, takes wave_rank.
+// that hit one word: the lanes of a round with the same digit find each other (their peer
+// mask); the last of them alone adds their count to the digit's running position (so no
+// two lanes of an instruction touch one word), and each peer takes the returned base, read
+// from that lane, plus the number of peers below it. The LDS operations of one wavefront
+// take effect in program order, so each round sees the additions of the rounds before it;
+// all rounds' adds are issued before any base is read, so no round waits for the previous
+// one's LDS round trip. Peer masks: with bal = 1 by ballots over the digit's nbits bits;
+// with bal = 2 (kRankMask) each lane sets its bit in its digit's 64-bit word of `mask` with
+// an LDS atomic OR (the result does not depend on the order in which the lanes are
+// served), reads the word back and clears it — three LDS operations per round instead of
+// one ballot per digit bit (the wavefront's words must be zero on entry and are zero again
+// on return). The CSR build (its bit-exact contract) ranks with kRankMask; the bucket
+// path, whose entry order only sets the floating-point summation order, takes wave_rank,
+// which is faster still.
+constexpr int kRankMask = 2;
 #ifndef GEE_CSR_RANK_BALLOT
-#define GEE_CSR_RANK_BALLOT 1
+#define GEE_CSR_RANK_BALLOT kRankMask
+#endif
+#ifndef GEE_BUCKET_RANK
+#define GEE_BUCKET_RANK 0
 #endif
 template <int R>
 __device__ __forceinline__ void wave_ranks(int *run, const int (&digit)[R], unsigned valid, int nbits, int bal,
-                                           int (&pos)[R]) {
+                                           int (&pos)[R], unsigned long long *mask = nullptr) {
     if (!bal) {
 #pragma unroll
         for (int r = 0; r < R; ++r) pos[r] = wave_rank(run, digit[r], valid >> r & 1u);
@@ -470,11 +490,19 @@ __device__ __forceinline__ void wave_ranks(int *run, const int (&digit)[R], unsi
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const bool v = valid >> r & 1u;
-        uint64_t peers = ballot(v);
-        for (int b = 0; b < nbits; ++b) {
-            const bool bit = (digit[r] >> b) & 1;
-            const uint64_t m = ballot(v && bit);
-            peers &= bit ? m : ~m;
+        uint64_t peers;
+        if (bal == kRankMask) {
+            unsigned long long *w = mask + digit[r];
+            if (v) __hip_atomic_fetch_or(w, 1ull << lane_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            peers = v ? __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) : 0ull;
+            if (v) __hip_atomic_store(w, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        } else {
+            peers = ballot(v);
+            for (int b = 0; b < nbits; ++b) {
+                const bool bit = (digit[r] >> b) & 1;
+                const uint64_t m = ballot(v && bit);
+                peers &= bit ? m : ~m;
+            }
         }
         below[r] = count_below(peers);
         const int cnt = __popcll(peers);
@@ -511,6 +539,7 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     if (qbuf) load_quarter_buf<true>(b.one, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
     else load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
+    if (bal == kRankMask) L.zero_masks();
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r)
@@ -545,7 +574,8 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     int dg[kRoundsW], pos[kRoundsW];
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) dg[r] = (q.valid >> r & 1u) ? (q.key[r] >> shift) : 0;
-    wave_ranks<kRoundsW>(L.cnt[wv], dg, q.valid, nbits, bal, pos);
+    wave_ranks<kRoundsW>(L.cnt[wv], dg, q.valid, nbits, bal, pos, L.masks(wv));
+    if (bal == kRankMask) __syncthreads();  // (the masks share the staging area)
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
         if ((q.valid >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
@@ -755,6 +785,7 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
     // this tile's scanned run offsets, loaded before the entries (they do not depend on them)
     const int gtile = (int)threadIdx.x < ND ? seg[((int64_t)jt << dbits) + threadIdx.x] : 0;
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
+    if (bal == kRankMask) L.zero_masks();
     __syncthreads();
     const int e0 = s0 + jt * kTile;
     const int e1 = min(e0 + kTile, s0 + nseg);
@@ -782,7 +813,8 @@ __global__ __launch_bounds__(kThreads) void seg_scatter(const KT *__restrict__ k
         vmask |= valid ? (1u << r) : 0u;
         dg[r] = valid ? ((kr[r] >> dshift) & (ND - 1)) : 0;
     }
-    wave_ranks<kRoundsW>(L.cnt[wv], dg, vmask, dbits, bal, pos);
+    wave_ranks<kRoundsW>(L.cnt[wv], dg, vmask, dbits, bal, pos, L.masks(wv));
+    if (bal == kRankMask) __syncthreads();  // (the masks share the staging area)
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
         if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < kTile, status)) {
@@ -873,7 +905,12 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
         int *cnt = smem_i;                                              // [4][R]
         int *scol2 = cnt + kSortWaves * R;                              // [cap]
         float *sval2 = reinterpret_cast<float *>(scol2 + cap);          // [cap]
+        // kRankMask ranking when the wavefronts' R peer masks fit the column staging area
+        const int rbal = bal == kRankMask ? (8 * R <= cap ? kRankMask : 1) : bal;
+        unsigned long long *masks = reinterpret_cast<unsigned long long *>(scol2);
         for (int i = threadIdx.x; i < kSortWaves * R; i += blockDim.x) cnt[i] = 0;
+        if (rbal == kRankMask)
+            for (int i = threadIdx.x; i < kSortWaves * R; i += blockDim.x) masks[i] = 0ull;
         __syncthreads();
         const int n = e1 - e0;
         // <= kSortCap / kSortWaves: kSortRoundsW rounds
@@ -926,7 +963,8 @@ __global__ __launch_bounds__(256) void bucket_sort(const KT *__restrict__ tkey, 
             vmask |= valid ? (1u << r) : 0u;
             dg[r] = valid ? kr[r] : 0;
         }
-        wave_ranks<kSortRoundsW>(cnt + wv * R, dg, vmask, sb, bal, pos);
+        wave_ranks<kSortRoundsW>(cnt + wv * R, dg, vmask, sb, rbal, pos, masks + wv * R);
+        if (rbal == kRankMask) __syncthreads();  // (the masks share the staging area)
 #pragma unroll
         for (int r = 0; r < kSortRoundsW; ++r) {
             if ((vmask >> r & 1u) && dbg_ok(pos[r] >= 0 && pos[r] < n, status)) {
@@ -1017,8 +1055,8 @@ hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsig
     // pass A keys: the row's low sb + s2 bits, as u16 when they fit
     const bool k16 = p.sb + p.s2 <= 16;
     // ranks: the CSR build keeps its bit-exact stable order without relying on the LDS's
-    // lane order (wave_ranks with bal); the bucket path takes the faster wave_rank
-    const int bal = p.bucket ? 0 : GEE_CSR_RANK_BALLOT;
+    // lane order (wave_ranks with peer masks); the bucket path takes the faster wave_rank
+    const int bal = p.bucket ? GEE_BUCKET_RANK : GEE_CSR_RANK_BALLOT;
     uint16_t *akey16 = reinterpret_cast<uint16_t *>(wk.akey);
     // the bucket path's part-table block totals, formed by the pass-B scan
     int *ptot = (p.bucket && with_b) ? wk.ptot : nullptr;
