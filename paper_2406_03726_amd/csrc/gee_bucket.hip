@@ -101,6 +101,36 @@ __global__ __launch_bounds__(256) void bucket_part_fill(Batch b, const int *__re
     part_fill_block(b, bstart, B, sb, ptot, (int)gridDim.x, (int)blockIdx.x, part, multi, bmeta, bad);
 }
 
+// The bucket path's per-node record {c_i, y_i}: 6 bytes (c_i, then y_i as a u16; y_i = 0
+// when unknown, with c_i = 0), so the gathered table of N records is 6N bytes (plus 2 bytes
+// of padding read by the last record's 8-byte load); with GEE_INFO6 = 0, float2 records.
+#ifndef GEE_INFO6
+#define GEE_INFO6 1
+#endif
+constexpr int kInfoBytes = GEE_INFO6 ? 6 : 8;
+__device__ __forceinline__ void put_info(float2 *info, int r, float c, int y) {
+    if (GEE_INFO6) {
+        unsigned short *q = reinterpret_cast<unsigned short *>(info) + 3 * (int64_t)r;
+        const unsigned cb = __float_as_uint(c);
+        q[0] = (unsigned short)(cb & 0xFFFFu);
+        q[1] = (unsigned short)(cb >> 16);
+        q[2] = (unsigned short)(y >= 0 ? y : 0);
+    } else {
+        info[r] = node_info(c, y);
+    }
+}
+// {c_i, y_i as int bits} from a record read as 8 bytes (its own 6 and 2 of the next)
+__device__ __forceinline__ float2 info_of(float2 raw) {
+    return GEE_INFO6 ? make_float2(raw.x, __int_as_float(__float_as_int(raw.y) & 0xFFFF)) : raw;
+}
+__device__ __forceinline__ float2 get_info(const float2 *info, int r) {
+    if (GEE_INFO6) {
+        const unsigned short *q = reinterpret_cast<const unsigned short *>(info) + 3 * (int64_t)r;
+        return make_float2(__uint_as_float((unsigned)q[0] | ((unsigned)q[1] << 16)), __int_as_float((int)q[2]));
+    }
+    return info[r];
+}
+
 // s_i and c_i of row r of graph gd from its degree d (entries' weight sum, or count); the
 // mode says which of them this pass owns (kDegIn: d is an in-degree, from the transposed
 // entries, and sets c_i only; kDegOut: d is an out-degree and sets s_i only).
@@ -115,7 +145,7 @@ __device__ __forceinline__ void set_row_coef(const GDesc &gd, const float *__res
     if (mode == kDegOut) return;
     int y = gd.labels[r - gd.node_off];
     if (y < 0 || y >= gd.K) y = -1;
-    info[r] = node_info(y >= 0 ? s * inv_n[gd.class_off + y] : 0.0f, y);
+    put_info(info, r, y >= 0 ? s * inv_n[gd.class_off + y] : 0.0f, y);
 }
 
 // ----------------------------------------------------------------------------- windows
@@ -473,7 +503,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     // the lane's row {c_i, y_i} and s_i, needed at the end, loaded now
     const int r0 = pt.x << sb, rl = r0 + lane;
     const bool own = lane < R && rl >= node_off && rl < node_off + gd.N;
-    const float2 q_own = own ? info[rl] : make_float2(0.0f, 0.0f);
+    const float2 q_own = own ? get_info(info, rl) : make_float2(0.0f, 0.0f);
     const float s_own = own ? srow[rl] : 0.0f;
     {
         float4 *a4 = reinterpret_cast<float4 *>(acc);
@@ -489,7 +519,9 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
         cr.init(rp, gd.N, M, r0 - node_off, R, lane, reinterpret_cast<unsigned *>(tag + kTagBytes));
     const bool chk = CSRM && validates(gd);
     bool badc = false;
-    const __amdgpu_buffer_rsrc_t r_inf = buffer_rsrc(info + node_off, (int64_t)gd.N * 8);
+    const __amdgpu_buffer_rsrc_t r_inf =
+        buffer_rsrc(reinterpret_cast<const char *>(info) + (int64_t)node_off * kInfoBytes,
+                    (int64_t)gd.N * kInfoBytes + (GEE_INFO6 ? 2 : 0));
     struct Prep {
         int row[BEPL];
         float x[BEPL];   // val, 0 when masked
@@ -512,7 +544,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
             const unsigned u = use ? (unsigned)(cj - node_off) : 0xFFFFFFFFu;
             P.row[j] = (PACKED ? (cc[j] >> kPackShift) : kk[j]) & rmask;
             P.x[j] = use ? vv[j] : 0.0f;
-            P.f[j] = buf_f2(r_inf, u << 3);
+            P.f[j] = info_of(buf_f2(r_inf, u * (unsigned)kInfoBytes));
         }
     };
     // window update: see lds_tag_add
@@ -601,7 +633,7 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
         const int t = threadIdx.x;
         const int rl = r0 + t;
         const bool own = t < R && rl >= gd.node_off && rl < gd.node_off + gd.N;
-        const float2 q_own = own ? info[rl] : make_float2(0.0f, 0.0f);
+        const float2 q_own = own ? get_info(info, rl) : make_float2(0.0f, 0.0f);
         const float s_own = own ? srow[rl] : 0.0f;
         float *acc = smem_b;
         float *fac = smem_b + R * KP;
