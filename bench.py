@@ -213,8 +213,11 @@ def sparse_leg(torch, np, gee, lib, dev, g, tens, Z_dense, steps, ev):
             ev.destroy(a)
             ev.destroy(b)
             continue
-        # zs_count reads Z; zs_tile_sum the row counts the class-scatter kernels wrote
-        nb = {"zs_count": 4 * N * K, "zs_tile_sum": 4 * N, "zs_write": 4 * N * K + 4 * (N + 1) + 8 * nnz}[name]
+        # zs_count reads Z; zs_tile_sum the row counts the class-scatter kernels wrote; zs_write
+        # (on the bucket path, as on this workload) the row counts and the non-zero pairs the
+        # class-scatter kernels staged in, row_ptr and the pairs' classes and values out
+        nb = {"zs_count": 4 * N * K, "zs_tile_sum": 4 * N,
+              "zs_write": 4 * N + 8 * nnz + 4 * (N + 1) + 8 * nnz}[name]
         kernels[name] = {"ms": round(kms, 5), "algorithmic_bytes": int(nb), "GB_per_s": round(nb / (kms * 1e-3) / 1e9, 1)}
         ev.destroy(a)
         ev.destroy(b)

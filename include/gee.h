@@ -163,9 +163,11 @@ int gee_take_data_errors_async(void *stream, uint32_t *dst);
        "node_coef", "fill_empty", "embed_rows", "embed_fixup";
      bucket path (gee_embed and batches): "bucket_part_count", "bucket_part_fill",
        "bucket_degree", "bucket_degree_fix", "bucket_embed", "bucket_embed_fix";
+     resident CSR on the bucket kernels (gee_embed_csr): "csr_prep";
      original GEE form (gee_embed_atomic): "edge_init", "edge_prep", "edge_coef",
        "edge_scatter", "edge_finish";
-     sparse Z (gee_embed_sparse): "zs_count", "zs_write".
+     sparse Z (gee_embed_sparse): "zs_count" or "zs_tile_sum" (the row counts' tile sums),
+       "zs_write" (the compaction, or the placement of the staged pairs).
    Launches recorded into a batch plan's hipGraph are not hooked. The caller owns the
    events and keeps them alive while the hook is set. Returns GEE_ERR_ARG for an unknown
    name. Process-wide; not meant for concurrent use from several threads. */
@@ -277,9 +279,11 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
  *              capacity can call again with larger arrays (capacity N * K always suffices).
  *              capacity 0 with col and val NULL computes row_ptr alone.
  * An entry is stored when its float32 value is not zero (a -0.0 is not stored).
- * gee_embed_sparse allocates its scratch (which includes a dense Z) with hipMallocAsync /
- * hipFreeAsync on `stream`; the _ws variant takes caller scratch of
- * gee_embed_sparse_workspace_bytes() bytes (0 for invalid sizes) and a schedule. */
+ * gee_embed_sparse allocates its scratch (which includes room for twice a dense Z's bytes:
+ * the class-scatter kernels stage each bucket's non-zero (class, value) pairs there, or write
+ * a dense Z for graphs above 2^22 rows) with hipMallocAsync / hipFreeAsync on `stream`; the
+ * _ws variant takes caller scratch of gee_embed_sparse_workspace_bytes() bytes (0 for
+ * invalid sizes) and a schedule. */
 size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
                                         const gee_schedule *sched);
 int gee_embed_sparse(const int32_t *src, const int32_t *dst, const float *w, int64_t E, int32_t N,

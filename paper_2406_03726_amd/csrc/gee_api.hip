@@ -620,7 +620,8 @@ int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t 
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 int embed_batch(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes, void *stream,
-                int *rcnt = nullptr, bool *counts_given = nullptr);
+                int *rcnt = nullptr, bool *counts_given = nullptr, int2 *zs_pairs = nullptr,
+                int *zs_sb = nullptr);
 // Stream of a call about to enqueue kernels. HIP keeps a thread's last error until it is
 // read; one left by the application's own earlier calls is consumed here, so the checks
 // after this call's launches see only this call's launches.
@@ -938,6 +939,15 @@ int gee_embed_noalloc(const int32_t *src, const int32_t *dst, const float *wgt, 
 
 // --------------------------------------------------------------------------- sparse Z
 
+// Staged sparse Z: on the bucket path the class scatter writes only the non-zero pairs, each
+// bucket's from the place of its first row in a dense Z (r0 K: a bucket never holds more
+// pairs than its rows have classes, whatever the values), into N K staging pairs (class,
+// value bits): twice a dense Z's bytes, of which only the non-zero pairs are touched.
+// The region also holds a dense Z (the CSR path).
+static size_t zs_region_bytes(int32_t N, int32_t K) {
+    return (size_t)N * K * sizeof(float) * (GEE_ZS_STAGED ? 2 : 1);
+}
+
 size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_t flags, int weighted,
                                         const gee_schedule *sched) {
     if (E < 0 || check_common(N, K, flags) || (int64_t)N * K > INT32_MAX) return 0;
@@ -945,7 +955,7 @@ size_t gee_embed_sparse_workspace_bytes(int64_t E, int32_t N, int32_t K, uint32_
     const size_t eb = gee_embed_workspace_bytes(E, N, K, flags, weighted, sched);
     if (eb == 0) return 0;
     auto up = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
-    return up(eb) + up((size_t)N * K * sizeof(float)) + up((size_t)zsparse_tiles(N) * sizeof(int)) +
+    return up(eb) + up(zs_region_bytes(N, K)) + up((size_t)zsparse_tiles(N) * sizeof(int)) +
            up((size_t)N * sizeof(int));
 }
 
@@ -969,8 +979,9 @@ int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt
     const size_t eb = up(gee_embed_workspace_bytes(E, N, K, flags, wgt != nullptr, sched));
     char *base = static_cast<char *>(workspace);
     float *Zd = reinterpret_cast<float *>(base + eb);
-    int *tile = reinterpret_cast<int *>(base + eb + up((size_t)N * K * sizeof(float)));
+    int *tile = reinterpret_cast<int *>(base + eb + up(zs_region_bytes(N, K)));
     int *rcnt = tile + up((size_t)zsparse_tiles(N) * sizeof(int)) / sizeof(int);
+    int2 *zpairs = GEE_ZS_STAGED ? reinterpret_cast<int2 *>(Zd) : nullptr;
     // the class-scatter kernels count each row's non-zero entries as they write it (bucket
     // path), so the compaction reads Z once
     gee_graph g;
@@ -985,8 +996,12 @@ int gee_embed_sparse_ws(const int32_t *src, const int32_t *dst, const float *wgt
     g.Z = Zd;
     g.sched = sched ? *sched : gee_schedule{0, 0, 0, 0};
     bool counts_given = false;
-    rc = embed_batch(&g, 1, workspace, eb, stream, rcnt, &counts_given);
+    int sb = -1;
+    rc = embed_batch(&g, 1, workspace, eb, stream, rcnt, &counts_given, zpairs, &sb);
     if (rc) return rc;
+    if (sb >= 0)  // the bucket kernels staged the non-zero pairs: no dense Z was written
+        return hip_status(launch_zsparse_staged(N, K, sb, zpairs, tile, rcnt, row_ptr, col, val, capacity,
+                                                as_stream(stream)));
     return hip_status(launch_zsparse(Zd, N, K, tile, rcnt, row_ptr, col, val, capacity, counts_given,
                                      as_stream(stream)));
 }
@@ -1064,10 +1079,14 @@ namespace {
 
 // gee_embed_batch_ws; with rcnt (a single graph), the class-scatter kernels also write each Z
 // row's number of non-zero entries there when the graph takes the bucket path, and
-// *counts_given says whether they did.
+// *counts_given says whether they did. With zs_pairs (N K pairs) as well they write the
+// non-zero (class, value bits) pairs there instead of a dense Z (staged sparse Z; each
+// bucket's from its first row's place in a dense Z), and *zs_sb gives the bucket size (log2
+// rows, at most 8; -1 when no staging took place).
 int embed_batch(const gee_graph *graphs, int32_t G, void *workspace, size_t workspace_bytes, void *stream,
-                int *rcnt, bool *counts_given) {
+                int *rcnt, bool *counts_given, int2 *zs_pairs, int *zs_sb) {
     if (counts_given) *counts_given = false;
+    if (zs_sb) *zs_sb = -1;
     std::vector<GraphIn> gs;
     int rc = graphs_from_api(graphs, G, gs);
     if (rc) return rc;
@@ -1089,6 +1108,10 @@ int embed_batch(const gee_graph *graphs, int32_t G, void *workspace, size_t work
         if (rcnt && G == 1 && c.p.bucket) {
             wk.rcnt = rcnt;
             *counts_given = true;
+            if (zs_pairs && zs_sb && c.p.sb <= 8) {
+                wk.zs_pairs = zs_pairs;
+                *zs_sb = c.p.sb;
+            }
         }
         Batch b;
         Batch bT;

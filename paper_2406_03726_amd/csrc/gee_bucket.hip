@@ -387,7 +387,8 @@ __global__ __launch_bounds__(256) void bucket_degree_fix(Batch b, const int4 *__
 // q = {c_i, y_i} and s of the lane's row, loaded by the caller. With rcnt (sparse Z of one
 // graph), also the row's number of non-zero entries of Z, acc * fac exactly as written.
 __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int KP, float *acc, float *fac,
-                                            float2 q, float s, int lane, unsigned *status, int *rcnt) {
+                                            float2 q, float s, int lane, unsigned *status, int *rcnt,
+                                            int *nzl = nullptr) {
     const int r = r0 + lane;
     if (lane < R && r >= gd.node_off && r < gd.node_off + gd.N) {
         float *row = acc + lane * KP;
@@ -412,6 +413,7 @@ __device__ __forceinline__ void finish_rows(const GDesc &gd, int r0, int R, int 
                 nz += (t.x * f != 0.0f) + (t.y * f != 0.0f) + (t.z * f != 0.0f) + (t.w * f != 0.0f);
             }
             rcnt[r - gd.node_off] = nz;
+            if (nzl) nzl[lane] = nz;
         }
     }
 }
@@ -477,6 +479,59 @@ __device__ __forceinline__ void write_rows(const GDesc &gd, int r0, int R, int K
     }
 }
 
+// Rows as write_rows writes them (nv rows from acc / fac, K classes, row stride KP), but only
+// their non-zero values, each as a (class, value bits) pair, in row-major order from place
+// `off` of the staging pairs (sparse Z): one wavefront, four consecutive floats per lane per
+// step, each non-zero placed by the non-zeros before it (four ballots), one 8-byte
+// non-temporal store per pair. The same values, bit for bit, as the dense rows.
+__device__ __forceinline__ void write_rows_sparse(int K, int KP, int nv, const float *acc, const float *fac,
+                                                  int lane, int2 *__restrict__ zp, int64_t off) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const int F = max(nv, 0) * K;
+    const uint64_t below = (1ull << lane) - 1;
+    const int qn = 256 / K, rn = 256 - qn * K;
+    int jj = (4 * lane) / K, kk = 4 * lane - ((4 * lane) / K) * K;
+    for (int f = 4 * lane, c0 = 0; c0 < F; c0 += 256, f += 256) {
+        float v[4];
+        int cls[4];
+        int j2 = jj, k2 = kk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v[e] = f + e < F ? acc[j2 * KP + k2] * fac[j2] : 0.0f;
+            cls[e] = k2;
+            if (++k2 == K) {
+                k2 = 0;
+                ++j2;
+            }
+        }
+        uint64_t m[4];
+        int before = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            m[e] = ballot(v[e] != 0.0f);
+            before += __popcll(m[e] & below);
+        }
+        int mine = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (v[e] != 0.0f) {
+                v2i pr;
+                pr.x = cls[e];
+                pr.y = __float_as_int(v[e]);
+                __builtin_nontemporal_store(pr, reinterpret_cast<v2i *>(zp + off + before + mine));
+                ++mine;
+            }
+        }
+        off += __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
+        kk += rn;
+        jj += qn;
+        if (kk >= K) {
+            kk -= K;
+            ++jj;
+        }
+    }
+}
+
 // With PACKED (after a pass B) each column word carries its row inside the bucket above
 // its kPackShift bits, so the keys are not read.
 // With CSRM (a resident CSR) the rows come from row_ptr (CsrRows), the entry arrays are the
@@ -488,7 +543,8 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
                                                    const int *__restrict__ bmeta, int sb,
                                                    const float2 *__restrict__ info,
                                                    const float *__restrict__ srow, float *__restrict__ zpart, int zs,
-                                                   int *__restrict__ rcnt, const int *__restrict__ rp = nullptr,
+                                                   int *__restrict__ rcnt, int2 *__restrict__ zsp,
+                                                   const int *__restrict__ rp = nullptr,
                                                    int64_t M = 0) {
     extern __shared__ float smem_b[];
     const int lane = lane_id();
@@ -594,7 +650,11 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     if (pt.w < 0) {
         finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, lane, b.status, rcnt);
         wave_lds_fence();
-        write_rows(gd, r0, R, KP, acc, fac, lane, 64);
+        if (zsp)
+            write_rows_sparse(K, KP, min(R, gd.node_off + gd.N - r0), acc, fac, lane, zsp,
+                              (int64_t)(r0 - gd.node_off) * K);
+        else
+            write_rows(gd, r0, R, KP, acc, fac, lane, 64);
         return;
     }
     // a part of a split bucket: its raw sums of the R rows, flat [R][K]
@@ -622,7 +682,7 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
                                                                 const float2 *__restrict__ info,
                                                                 const float *__restrict__ srow,
                                                                 const float *__restrict__ zpart, int zs,
-                                                                int *__restrict__ rcnt) {
+                                                                int *__restrict__ rcnt, int2 *__restrict__ zsp) {
     extern __shared__ float smem_b[];
     const int nmulti = bmeta[1];
     for (int i = blockIdx.x; i < nmulti; i += gridDim.x) {
@@ -678,9 +738,23 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
             }
         }
         __syncthreads();
-        if (t < 64) finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, t, b.status, rcnt);
+        int *nzl = reinterpret_cast<int *>(fac + 64);  // [64] rows' non-zero counts (staged sparse Z)
+        if (t < 64) {
+            if (zsp) nzl[t] = 0;
+            finish_rows(gd, r0, R, KP, acc, fac, q_own, s_own, t, b.status, rcnt, zsp ? nzl : nullptr);
+        }
         __syncthreads();
-        write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
+        if (!zsp) {
+            write_rows(gd, r0, R, KP, acc, fac, t, kFixThreads);
+        } else {
+            // wavefront w writes rows [w rpw, (w + 1) rpw) from the place after the rows before
+            constexpr int kW = kFixThreads / 64;
+            const int rpw = R / kW, w = t >> 6, ra = w * rpw;
+            const int nv = min(ra + rpw, gd.node_off + gd.N - r0) - ra;
+            int64_t off = (int64_t)(r0 - gd.node_off) * K;
+            for (int j = 0; j < ra; ++j) off += nzl[j];
+            write_rows_sparse(K, KP, nv, acc + ra * KP, fac + ra, t & 63, zsp, off);
+        }
     }
 }
 
@@ -727,11 +801,11 @@ static hipError_t launch_bucket_sums_csr(const Batch &b, const Plan &p, const Wo
     prof_begin(kKBucketEmbed, s);
     hipLaunchKernelGGL((bucket_embed<int, WEIGHTED, false, true>), dim3(nbp), dim3(64), lds, s, b, (const int *)nullptr,
                        col, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs,
-                       (int *)nullptr, rp, M);
+                       (int *)nullptr, (int2 *)nullptr, rp, M);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
     hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
-                       wk.srow, wk.zpart, zs, (int *)nullptr);
+                       wk.srow, wk.zpart, zs, (int *)nullptr, (int2 *)nullptr);
     prof_end(kKBucketEmbedFix, s);
     return hipGetLastError();
 }
@@ -790,14 +864,14 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
     prof_begin(kKBucketEmbed, s);
     if (p.s2 > 0)  // pass B packed the rows into the column words
         hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED, true>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
-                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
+                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
     else
         hipLaunchKernelGGL((bucket_embed<KT, WEIGHTED, false>), dim3(nbp), dim3(64), lds, s, b, key, wk.tcol, val,
-                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt);
+                           wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
     hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
-                       wk.srow, wk.zpart, zs, wk.rcnt);
+                       wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
     prof_end(kKBucketEmbedFix, s);
 }
 

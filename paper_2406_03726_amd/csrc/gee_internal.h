@@ -402,6 +402,10 @@ struct Work {
     float *dpart = nullptr;    // [bslots * 64] partial degrees
     float *zpart = nullptr;    // [bslots << sb * Kmax] partial class sums
     int *rcnt = nullptr;       // [N] non-zero entries of each Z row (sparse Z of one graph), or nullptr
+    // sparse Z of one graph on the bucket path: each bucket's non-zero (class, value bits)
+    // pairs in row-major order from its first row's place in a dense Z, r0 K (no dense Z is
+    // written), or nullptr
+    int2 *zs_pairs = nullptr;
 };
 
 // ----------------------------------------------------------------------------- class counts
@@ -642,6 +646,14 @@ hipError_t launch_edge_embed(const int *src, const int *dst, const float *w, int
 int zsparse_tiles(int N);
 // counts_given: rcnt already holds every row's non-zero count (written by the class-scatter
 // kernels), so the count pass over Z is skipped.
+// Staged sparse Z (Work::zs_pairs after the bucket kernels; rcnt given): row_ptr from
+// the row counts, then each bucket's staged run (buckets of 2^sb <= 256 rows, the run of the
+// bucket of first row r0 starting at r0 K) copied to its place.
+#ifndef GEE_ZS_STAGED
+#define GEE_ZS_STAGED 1
+#endif
+hipError_t launch_zsparse_staged(int N, int K, int sb, const int2 *zs_pairs, int *tile, int *rcnt, int *row_ptr,
+                                 int *col, float *val, int64_t cap, hipStream_t s);
 hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
                           int64_t cap, bool counts_given, hipStream_t s);
 

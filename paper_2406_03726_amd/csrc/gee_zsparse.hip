@@ -1,7 +1,11 @@
 // gee_zsparse.hip - the embedding in sparse storage: Z's non-zero entries kept row by row in
 // the CSR layout of Section 3 (index pointers of N + 1 entries, then the class index and the
 // value of each non-zero entry, row after row, classes increasing), as the paper stores the
-// embedding matrix. Z is dense float32 N x K on entry (the class-scatter kernels write it).
+// embedding matrix. On the bucket path (a single graph of at most 2^22 rows) the class-scatter
+// kernels stage each bucket's non-zero (class, value) pairs, row-major, from its first row's
+// place in a dense Z, and each row's count; zs_tile_sum, zs_scan and zs_place then form
+// row_ptr and copy each bucket's run to its place. Otherwise Z is dense float32 N x K on
+// entry and is compacted as below.
 //
 // Rows are taken in tiles of kZT; inside a tile, groups of L lanes (the power of two at or
 // above min(K, 64)) take one row each, a lane the columns sub and sub + L.
@@ -223,6 +227,48 @@ __global__ __launch_bounds__(kZB) void zs_flat(const float *__restrict__ Z, int 
     }
 }
 
+// Staged sparse Z: the class scatter has left each bucket's non-zero pairs, row-major, from
+// its first row r0's place r0 K of the (class, value bits) pairs zp, and each row's count in
+// row_cnt. Per tile of
+// kZT rows (whole buckets: R divides kZT): the rows' counts scanned into row_ptr, then
+// wavefront w copies the runs of the tile's buckets w, w + 4, ... to their places, 64 pairs
+// per step.
+__global__ __launch_bounds__(kZB) void zs_place(int N, int K, int sb, const int2 *__restrict__ zp,
+                                              const int *__restrict__ row_cnt, const int *__restrict__ tile_off,
+                                              int *__restrict__ row_ptr, int *__restrict__ col,
+                                              float *__restrict__ val, int64_t cap) {
+    static_assert(kZT == kZB, "one thread per row of the tile");
+    __shared__ int cnt[kZT + 1];
+    __shared__ int wsum[kZB / 64];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kZT;
+    const int r = threadIdx.x;
+    const int c = base + r < N ? row_cnt[base + r] : 0;
+    int tot = 0;
+    const int x = block_excl_scan<kZB>(c, wsum, tot);
+    cnt[r] = x;
+    if (r == 0) cnt[kZT] = tot;
+    const int64_t off = tile_off[blockIdx.x];
+    if (base + r < N) row_ptr[base + r] = (int)(off + x);
+    __syncthreads();
+    const int R = 1 << sb;
+    const int nb = (int)((min((int64_t)kZT, (int64_t)N - base) + R - 1) >> sb);  // the tile's buckets
+    for (int j = wv; j < nb; j += kZB / 64) {
+        const int bk = (int)(base >> sb) + j;
+        const int n = cnt[min((j + 1) << sb, kZT)] - cnt[j << sb];
+        const int64_t src = ((int64_t)bk << sb) * K;
+        const int64_t dst = off + cnt[j << sb];
+        for (int i = lane; i < n; i += 64) {
+            const int64_t q = dst + i;
+            if (q < cap) {
+                const int2 pr = zp[src + i];
+                col[q] = pr.x;
+                val[q] = __int_as_float(pr.y);
+            }
+        }
+    }
+}
+
 template <int L>
 hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
                      int64_t cap, bool counts_given, hipStream_t s) {
@@ -250,6 +296,24 @@ hipError_t launch_zs(const float *Z, int N, int K, int T, int *tile, int *rcnt, 
 }  // namespace
 
 int zsparse_tiles(int N) { return (N + kZT - 1) / kZT; }
+
+hipError_t launch_zsparse_staged(int N, int K, int sb, const int2 *zs_pairs, int *tile, int *rcnt, int *row_ptr,
+                                 int *col, float *val, int64_t cap, hipStream_t s) {
+    if (sb < 0 || (1 << sb) > kZT) return hipErrorInvalidValue;  // (bucket-path buckets have 32 or 64 rows)
+    const int T = zsparse_tiles(N);
+    prof_begin(kKZsTileSum, s);
+    hipLaunchKernelGGL(zs_tile_sum, dim3((unsigned)T), dim3(kZB), 0, s, rcnt, N, tile);
+    prof_end(kKZsTileSum, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zs_scan, dim3(1), dim3(1024), 0, s, tile, T, row_ptr, N);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    prof_begin(kKZsWrite, s);
+    hipLaunchKernelGGL(zs_place, dim3((unsigned)T), dim3(kZB), 0, s, N, K, sb, zs_pairs, rcnt, tile, row_ptr, col,
+                       val, cap);
+    prof_end(kKZsWrite, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_zsparse(const float *Z, int N, int K, int *tile, int *rcnt, int *row_ptr, int *col, float *val,
                           int64_t cap, bool counts_given, hipStream_t s) {

@@ -65,10 +65,13 @@ def test_sparse_all_options(sym):
                 check_sparse(g.with_options(d, l, c))
 
 
-def test_sparse_capacity_short_and_zero():
-    g = random_small_graph(2, N=3000, E=9000, K=7, weighted=True).with_options(True, True, True)
+@pytest.mark.parametrize("K", [7, 40])
+def test_sparse_capacity_short_and_zero(K):
+    # K = 7: a dense Z compacted afterwards; K = 40: the non-zero pairs staged per bucket by
+    # the class scatter (used when the staging is at most twice a dense Z's size)
+    g = random_small_graph(2, N=3000, E=9000, K=K, weighted=True).with_options(True, True, True)
     s, d, w, lab = graph_tensors(g)
-    _label("sparse Z capacity")
+    _label(f"sparse Z capacity K={K}")
     nnz = check_sparse(g)
     cap = nnz // 3
     check_sparse(g, capacity=cap)
