@@ -115,3 +115,12 @@ def test_sparse_powerlaw_10m_full():
     nnz = check_sparse(g)
     _label(f"sparse Z powerlaw nnz={nnz} of {g.N * g.K}")
     assert gee.gee_get_data_errors() == 0
+
+
+def test_sparse_powerlaw_k128_split_buckets():
+    # K = 128: 32-row buckets; hub rows split buckets into several parts, whose combine stages
+    # the pairs over all its wavefronts; 100,003 rows end in a ragged bucket and tile
+    g = powerlaw_10m(N=100_003, E=800_000, K=128, dmax=20_000.0)
+    _label(f"sparse Z powerlaw N={g.N} E={g.E} K={g.K}")
+    check_sparse(g)
+    check_sparse(g.with_options(False, False, False))
