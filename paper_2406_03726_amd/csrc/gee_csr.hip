@@ -170,61 +170,12 @@ struct Quarter {
     unsigned valid;  // bit r: entry r is a real adjacency entry
 };
 
-template <bool VAL>
-__device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
-                                             bool &badw) {
-    static_assert(kRoundsW <= 16, "Quarter holds at most 16 rounds");
-    const int lane = lane_id();
-    q.valid = 0;
-    if (vw >= V) return;
-    const int64_t vhi = min(vw + (int64_t)kQuarter, V) - 1;
-    const int g0 = find_graph(b.voffs, b.G, vw), g1 = find_graph(b.voffs, b.G, vhi);
-    if (g0 == g1) {
-        // one graph: clamped unconditional loads, then the checks
-        const GDesc gd = load_desc(b, g0);
-        const bool sym = gd.flags & kSym;
-        const bool chk = validates(gd);
-        int sv[kRoundsW], dv[kRoundsW];
-        float wv[kRoundsW];
-#pragma unroll
-        for (int r = 0; r < kRoundsW; ++r) {
-            const int64_t lv = min(vw + r * 64 + lane, vhi) - gd.voff;
-            const int64_t e = sym ? (lv >> 1) : lv;
-            sv[r] = gd.src[e];
-            dv[r] = gd.dst[e];
-            if (VAL) wv[r] = gd.w ? gd.w[e] : 1.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < kRoundsW; ++r) {
-            const int64_t v = vw + r * 64 + lane;
-            const int side = sym ? (int)((v - gd.voff) & 1) : 0;
-            const bool inb = v <= vhi;
-            const bool inr = (unsigned)sv[r] < (unsigned)gd.N && (unsigned)dv[r] < (unsigned)gd.N;
-            if (chk && inb && !inr) badi = true;
-            if (VAL && chk && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
-            q.key[r] = (side ? dv[r] : sv[r]) + gd.node_off;
-            q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
-            if (VAL) q.val[r] = wv[r];
-            q.valid |= (inb && inr && (side == 0 || sv[r] != dv[r])) ? (1u << r) : 0u;
-        }
-    } else {
-        // the quarter spans graphs (small graphs of a batch): entry by entry
-        int g = -1;
-        GDesc gd;
-#pragma unroll
-        for (int r = 0; r < kRoundsW; ++r) {
-            float val = 1.0f;
-            const bool ok = load_virtual<VAL>(b, vw + r * 64 + lane, V, g, gd, q.key[r], q.col[r], val, badi, badw);
-            if (VAL) q.val[r] = val;
-            q.valid |= ok ? (1u << r) : 0u;
-        }
-    }
-}
-
-// load_quarter for one graph whose edge arrays fit 32-bit buffer offsets: the same entries in
-// the same order, read with buffer loads whose per-round part of the offset is the same for
-// the whole wavefront (a scalar offset) and whose per-lane part is fixed, so the rounds cost
-// no address arithmetic; loads past the arrays' end return 0 (those entries are invalid).
+// load_quarter for a quarter inside one graph whose edge arrays fit 32-bit buffer offsets
+// (and, under symmetrization, whose virtual entries start at an even place of the launch):
+// the same entries in the same order, read with buffer loads whose per-round part of the
+// offset is the same for the whole wavefront (a scalar offset) and whose per-lane part is
+// fixed, so the rounds cost no address arithmetic; entries at or past V are invalid (loads
+// past the arrays' end return 0).
 template <bool VAL>
 __device__ __forceinline__ void load_quarter_buf(const GDesc &gd, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
                                                  bool &badw) {
@@ -261,6 +212,62 @@ __device__ __forceinline__ void load_quarter_buf(const GDesc &gd, int64_t vw, in
         q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
         if (VAL) q.val[r] = wv[r];
         q.valid |= (inb && inr && (side == 0 || sv[r] != dv[r])) ? (1u << r) : 0u;
+    }
+}
+
+template <bool VAL>
+__device__ __forceinline__ void load_quarter(const Batch &b, int64_t vw, int64_t V, Quarter<VAL> &q, bool &badi,
+                                             bool &badw) {
+    static_assert(kRoundsW <= 16, "Quarter holds at most 16 rounds");
+    const int lane = lane_id();
+    q.valid = 0;
+    vw = uniform64(vw);  // (the wavefront's quarter: the graph search and descriptor loads are scalar)
+    if (vw >= V) return;
+    const int64_t vhi = min(vw + (int64_t)kQuarter, V) - 1;
+    const int g0 = find_graph(b.voffs, b.G, vw), g1 = find_graph(b.voffs, b.G, vhi);
+    if (g0 == g1) {
+        const GDesc gd = load_desc(b, g0);
+        if (GEE_QUARTER_BUF && gd.E * 4 <= (int64_t)INT32_MAX && (!(gd.flags & kSym) || ((vw - gd.voff) & 1) == 0)) {
+            load_quarter_buf<VAL>(gd, vw, vhi + 1, q, badi, badw);
+            return;
+        }
+        // one graph: clamped unconditional loads, then the checks
+        const bool sym = gd.flags & kSym;
+        const bool chk = validates(gd);
+        int sv[kRoundsW], dv[kRoundsW];
+        float wv[kRoundsW];
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r) {
+            const int64_t lv = min(vw + r * 64 + lane, vhi) - gd.voff;
+            const int64_t e = sym ? (lv >> 1) : lv;
+            sv[r] = gd.src[e];
+            dv[r] = gd.dst[e];
+            if (VAL) wv[r] = gd.w ? gd.w[e] : 1.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r) {
+            const int64_t v = vw + r * 64 + lane;
+            const int side = sym ? (int)((v - gd.voff) & 1) : 0;
+            const bool inb = v <= vhi;
+            const bool inr = (unsigned)sv[r] < (unsigned)gd.N && (unsigned)dv[r] < (unsigned)gd.N;
+            if (chk && inb && !inr) badi = true;
+            if (VAL && chk && inb && gd.w && side == 0 && !isfinite(wv[r])) badw = true;
+            q.key[r] = (side ? dv[r] : sv[r]) + gd.node_off;
+            q.col[r] = (side ? sv[r] : dv[r]) + gd.node_off;
+            if (VAL) q.val[r] = wv[r];
+            q.valid |= (inb && inr && (side == 0 || sv[r] != dv[r])) ? (1u << r) : 0u;
+        }
+    } else {
+        // the quarter spans graphs (small graphs of a batch): entry by entry
+        int g = -1;
+        GDesc gd;
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r) {
+            float val = 1.0f;
+            const bool ok = load_virtual<VAL>(b, vw + r * 64 + lane, V, g, gd, q.key[r], q.col[r], val, badi, badw);
+            if (VAL) q.val[r] = val;
+            q.valid |= ok ? (1u << r) : 0u;
+        }
     }
 }
 

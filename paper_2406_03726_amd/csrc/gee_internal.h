@@ -308,6 +308,14 @@ struct Batch {
 
 __device__ __forceinline__ bool validates(const GDesc &d) { return !(d.flags & kNoValidate); }
 
+// A wave-uniform 64-bit value as a scalar (its first active lane's).
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Last g with offs[g] <= x (offs non-decreasing, offs[0] <= x).
 template <typename T>
 __device__ __forceinline__ int find_graph(const T *__restrict__ offs, int G, T x) {
