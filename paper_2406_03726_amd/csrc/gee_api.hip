@@ -567,10 +567,15 @@ struct Chunk {
     size_t off = 0;  // workspace offset
 };
 constexpr unsigned kEmbedParts = kPCount | kPPart | kPCsrOut | kPEmbed;
+// Rows of a chunk of several graphs, at most (a larger graph takes a chunk of its own): fewer
+// rows per launch mean fewer pass-A digits, hence longer runs per tile in the pass-A scatter.
+#ifndef GEE_CHUNK_ROWS_LOG2
+#define GEE_CHUNK_ROWS_LOG2 22
+#endif
 int plan_chunks(const std::vector<GraphIn> &gs, std::vector<Chunk> &out, size_t &total) {
     out.clear();
     for (int sbp : {6, GEE_BUCKET_SB_MIN}) {
-        const int64_t cap = (int64_t)kMaxBuckets << sbp;
+        const int64_t cap = std::min((int64_t)kMaxBuckets << sbp, (int64_t)1 << GEE_CHUNK_ROWS_LOG2);
         std::vector<GraphIn> cur;
         int64_t rows = 0;
         auto flush = [&]() {

@@ -521,6 +521,75 @@ __device__ __forceinline__ void wave_ranks(int *run, const int (&digit)[R], unsi
     for (int r = 0; r < R; ++r) pos[r] = __shfl(b0[r], last[r], 64) + below[r];
 }
 
+// Tiles whose items share few digits (entries of one small graph of a batch) would serialize
+// LDS atomics on a few words, one lane after another. When the
+// digits of a wavefront's R rounds span at most 2^kNarrowBits values, the lanes of each round
+// with the same digit find each other by one ballot per bit of the digit's offset from the
+// smallest, and one lane per group adds the group's count: the same stable positions (the
+// groups' adds in round order), from a few ballots and at most one LDS atomic per digit and
+// round. Per round, packed: peers below the lane (bits 0-6), group size (7-13), the group's
+// last lane (14-19).
+#ifndef GEE_RANK_NARROW
+#define GEE_RANK_NARROW 1
+#endif
+#ifndef GEE_NARROW_BITS
+#define GEE_NARROW_BITS 2
+#endif
+constexpr int kNarrowBits = GEE_NARROW_BITS;
+// Minimum / maximum over the wavefront by the DPP moves of wave_scan_add (lane 63 of the
+// inclusive scan), the same value on every lane.
+__device__ __forceinline__ int wave_min_i(int x) {
+    x = min(x, dpp_i<0x111>(x, INT_MAX));
+    x = min(x, dpp_i<0x112>(x, INT_MAX));
+    x = min(x, dpp_i<0x114>(x, INT_MAX));
+    x = min(x, dpp_i<0x118>(x, INT_MAX));
+    x = min(x, dpp_i<0x142, 0xA>(x, INT_MAX));
+    x = min(x, dpp_i<0x143, 0xC>(x, INT_MAX));
+    return readlane(x, 63);
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+    x = max(x, dpp_i<0x111>(x, INT_MIN));
+    x = max(x, dpp_i<0x112>(x, INT_MIN));
+    x = max(x, dpp_i<0x114>(x, INT_MIN));
+    x = max(x, dpp_i<0x118>(x, INT_MIN));
+    x = max(x, dpp_i<0x142, 0xA>(x, INT_MIN));
+    x = max(x, dpp_i<0x143, 0xC>(x, INT_MIN));
+    return readlane(x, 63);
+}
+// The smallest digit (lo) and the bits of the span (nb) of the valid items of a wavefront's
+// R rounds; false when the span needs more than kNarrowBits bits.
+template <int R>
+__device__ __forceinline__ bool narrow_span(const int (&key)[R], int shift, unsigned valid, int &lo, int &nb) {
+    int a = INT_MAX, z = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (valid >> r & 1u) {
+            a = min(a, key[r] >> shift);
+            z = max(z, key[r] >> shift);
+        }
+    lo = wave_min_i(a);
+    z = wave_max_i(z);
+    const int span = z >= lo ? z - lo : 0;
+    nb = span == 0 ? 0 : 32 - __clz(span);
+    return nb <= kNarrowBits;
+}
+// One round's peers (lanes with the same digit) by nb ballots over the digit's offset from lo,
+// packed as below.
+__device__ __forceinline__ int narrow_round(int digit, bool v, int lo, int nb) {
+    uint64_t peers = ballot(v);
+    const int off = digit - lo;
+    for (int b = 0; b < nb; ++b) {
+        const bool bit = (off >> b) & 1;
+        const uint64_t m = ballot(v && bit);
+        peers &= bit ? m : ~m;
+    }
+    const int last = v ? 63 - __clzll(peers) : lane_id();
+    return count_below(peers) | (__popcll(peers) << 7) | (last << 14);
+}
+__device__ __forceinline__ int pk_below(int p) { return p & 0x7F; }
+__device__ __forceinline__ int pk_count(int p) { return (p >> 7) & 0x7F; }
+__device__ __forceinline__ int pk_last(int p) { return p >> 14; }
+
 // Pass A scatter: tile t of the virtual entries, sorted by high digit in LDS (wave-split
 // ranking over the wavefront's registers) and written to seg_start[d] + (scanned tile
 // offset) in runs. The key written keeps only the bits the later passes read (amask): the
@@ -547,10 +616,23 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     else load_quarter<true>(b, t * kTile + (int64_t)wv * kQuarter, V, q, badi, badw);
     for (int i = threadIdx.x; i < kWaves * 256; i += blockDim.x) (&L.cnt[0][0])[i] = 0;
     if (bal == kRankMask) L.zero_masks();
+    int nlo = 0, nnb = 0;
+    // (launches of several graphs only: a single graph's tiles spread their rows over the
+    // graph's digits, where the per-item LDS atomics were measured faster)
+    const bool narrow = GEE_RANK_NARROW && b.G > 1 && narrow_span<kRoundsW>(q.key, shift, q.valid, nlo, nnb);
     __syncthreads();
+    if (narrow) {
 #pragma unroll
-    for (int r = 0; r < kRoundsW; ++r)
-        if (q.valid >> r & 1u) atomicAdd(&L.cnt[wv][q.key[r] >> shift], 1);
+        for (int r = 0; r < kRoundsW; ++r) {
+            const bool v = q.valid >> r & 1u;
+            const int pk = narrow_round(q.key[r] >> shift, v, nlo, nnb);
+            if (v && pk_below(pk) == pk_count(pk) - 1) atomicAdd(&L.cnt[wv][q.key[r] >> shift], pk_count(pk));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r)
+            if (q.valid >> r & 1u) atomicAdd(&L.cnt[wv][q.key[r] >> shift], 1);
+    }
     __syncthreads();
     // segment starts: exclusive scan of the digit totals, in every workgroup (workgroup 0
     // also writes them, the entry count M, the pass-B tiles of every segment and, without
@@ -581,7 +663,20 @@ __global__ __launch_bounds__(kThreads) void a_scatter(Batch b, int64_t V, int sh
     int dg[kRoundsW], pos[kRoundsW];
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) dg[r] = (q.valid >> r & 1u) ? (q.key[r] >> shift) : 0;
-    wave_ranks<kRoundsW>(L.cnt[wv], dg, q.valid, nbits, bal, pos, L.masks(wv));
+    if (narrow) {
+        // (each round's base is read right after its add: issuing all adds first would need
+        // the peers formed twice, which measured slower)
+#pragma unroll
+        for (int r = 0; r < kRoundsW; ++r) {
+            const bool v = q.valid >> r & 1u;
+            const int pk = narrow_round(dg[r], v, nlo, nnb);
+            int b0 = 0;
+            if (v && pk_below(pk) == pk_count(pk) - 1) b0 = atomicAdd(&L.cnt[wv][dg[r]], pk_count(pk));
+            pos[r] = __shfl(b0, pk_last(pk), 64) + pk_below(pk);
+        }
+    } else {
+        wave_ranks<kRoundsW>(L.cnt[wv], dg, q.valid, nbits, bal, pos, L.masks(wv));
+    }
     if (bal == kRankMask) __syncthreads();  // (the masks share the staging area)
 #pragma unroll
     for (int r = 0; r < kRoundsW; ++r) {
