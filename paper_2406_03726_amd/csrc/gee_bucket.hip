@@ -42,7 +42,13 @@ namespace gee {
 
 constexpr int BEPL = 4;          // consecutive entries per lane in a window
 constexpr int BWIN = 64 * BEPL;  // entries per window
-constexpr int kFixThreads = 1024;  // threads per split bucket when combining class sums
+// Threads per split bucket when combining class sums: 1024 (one pass over a bucket's sums)
+// when the launch can hold few split buckets, 256 (four workgroups per CU more, four passes
+// per bucket) when it can hold more than kFixManyBuckets, on grids of kFixGrid / kFixGridMany.
+constexpr int kFixThreads = 1024;
+constexpr int kFixThreadsMany = 256;
+constexpr int kFixGrid = 1024, kFixGridMany = 8192;
+constexpr int64_t kFixManyBuckets = 4096;
 constexpr int kFixUnroll = 4;      // class sums per thread in flight together (R * K <= 4096)
 // After a pass B on the bucket path each column word carries the entry's row inside its
 // bucket above bit kPackShift (bucket-path launches hold at most 2^22 rows).
@@ -672,11 +678,13 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     }
 }
 
-// Workgroups take the split buckets in turn (the grid is sized for the largest possible
-// count; far fewer are split): the parts' raw sums added in part order, then the rows
+// Workgroups of kFixThreads take the split buckets in turn (the grid is sized for the
+// largest possible count; far fewer are split): the parts' raw sums added in part order (the
+// same order, so the same bits, whatever the thread count), then the rows
 // finished as in bucket_embed. A thread takes kFixUnroll class sums of the bucket, and the
 // loads of four parts of all of them are in flight together; the finishing lanes load their
 // rows' coefficients first, so a bucket costs few dependent memory round trips.
+template <int kFixThreads>
 __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const int4 *__restrict__ multi,
                                                                 const int *__restrict__ bmeta, int sb,
                                                                 const float2 *__restrict__ info,
@@ -791,7 +799,8 @@ static hipError_t launch_bucket_sums_csr(const Batch &b, const Plan &p, const Wo
                        (const int *)nullptr, col, val, wk.part, (int)nbp, wk.bmeta, p.sb, wk.inv_n, wk.dpart, wk.srow,
                        wk.info, mode, rp, M);
     prof_end(kKBucketDegree, s);
-    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);
+    const bool many = p.bslots / 2 > kFixManyBuckets;  // (split buckets the launch can hold, at most)
+    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, many ? kFixGridMany : kFixGrid);
     prof_begin(kKBucketDegreeFix, s);
     hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
                        wk.dpart, wk.srow, wk.info, mode);
@@ -804,8 +813,12 @@ static hipError_t launch_bucket_sums_csr(const Batch &b, const Plan &p, const Wo
                        (int *)nullptr, (int2 *)nullptr, rp, M);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
-    hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
-                       wk.srow, wk.zpart, zs, (int *)nullptr, (int2 *)nullptr);
+    if (many)
+        hipLaunchKernelGGL(bucket_embed_fix<kFixThreadsMany>, dim3(nm), dim3(kFixThreadsMany), lds, s, b, wk.multi,
+                           wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, (int *)nullptr, (int2 *)nullptr);
+    else
+        hipLaunchKernelGGL(bucket_embed_fix<kFixThreads>, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta,
+                           p.sb, wk.info, wk.srow, wk.zpart, zs, (int *)nullptr, (int2 *)nullptr);
     prof_end(kKBucketEmbedFix, s);
     return hipGetLastError();
 }
@@ -853,7 +866,8 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
                            mode);
     prof_end(kKBucketDegree, s);
     // split buckets, at most (the grids of the two fix kernels loop over the actual count)
-    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, 1024);
+    const bool many = p.bslots / 2 > kFixManyBuckets;  // (split buckets the launch can hold, at most)
+    const unsigned nm = (unsigned)std::min<int64_t>(p.bslots / 2 + 1, many ? kFixGridMany : kFixGrid);
     prof_begin(kKBucketDegreeFix, s);
     hipLaunchKernelGGL(bucket_degree_fix, dim3((nm + 3) / 4), dim3(256), 0, s, b, wk.multi, wk.bmeta, p.sb, wk.inv_n,
                        wk.dpart, wk.srow, wk.info, mode);
@@ -870,8 +884,12 @@ static void launch_bucket_sums(const Batch &b, const Plan &p, const Work &wk, co
                            wk.part, (int)nbp, wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
     prof_end(kKBucketEmbed, s);
     prof_begin(kKBucketEmbedFix, s);
-    hipLaunchKernelGGL(bucket_embed_fix, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta, p.sb, wk.info,
-                       wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
+    if (many)
+        hipLaunchKernelGGL(bucket_embed_fix<kFixThreadsMany>, dim3(nm), dim3(kFixThreadsMany), lds, s, b, wk.multi,
+                           wk.bmeta, p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
+    else
+        hipLaunchKernelGGL(bucket_embed_fix<kFixThreads>, dim3(nm), dim3(kFixThreads), lds, s, b, wk.multi, wk.bmeta,
+                           p.sb, wk.info, wk.srow, wk.zpart, zs, wk.rcnt, wk.zs_pairs);
     prof_end(kKBucketEmbedFix, s);
 }
 
