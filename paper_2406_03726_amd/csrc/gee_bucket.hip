@@ -834,13 +834,15 @@ hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
-    prof_begin(kKBucketPartCount, s);
-    hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
-                       (const int *)bad);
-    prof_end(kKBucketPartCount, s);
+    if (nblk > 1) {  // (one block of buckets forms its own totals)
+        prof_begin(kKBucketPartCount, s);
+        hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
+                           (const int *)bad);
+        prof_end(kKBucketPartCount, s);
+    }
     prof_begin(kKBucketPartFill, s);
-    hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
-                       wk.multi, wk.bmeta, (const int *)bad);
+    hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb,
+                       nblk > 1 ? (const int *)wk.ptot : nullptr, wk.part, wk.multi, wk.bmeta, (const int *)bad);
     prof_end(kKBucketPartFill, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return val ? launch_bucket_sums_csr<true>(b, p, wk, rp, col, val, M, s)
@@ -901,13 +903,16 @@ hipError_t launch_bucket_embed(const Batch &b, const Plan &p, const Work &wk, hi
     const void *key = with_b ? (const void *)wk.tkey : (const void *)wk.akey;
     const unsigned nblk = (unsigned)((p.B + 1023) / 1024);
     if (!with_b) {  // (after a pass B its scan has formed the block totals and its scatter the table)
-        prof_begin(kKBucketPartCount, s);
-        hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
-                           (const int *)nullptr);
-        prof_end(kKBucketPartCount, s);
+        if (nblk > 1) {  // (one block of buckets forms its own totals)
+            prof_begin(kKBucketPartCount, s);
+            hipLaunchKernelGGL(bucket_part_count, dim3(nblk), dim3(1024), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot,
+                               (const int *)nullptr);
+            prof_end(kKBucketPartCount, s);
+        }
         prof_begin(kKBucketPartFill, s);
-        hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb, wk.ptot, wk.part,
-                           wk.multi, wk.bmeta, (const int *)nullptr);
+        hipLaunchKernelGGL(bucket_part_fill, dim3(nblk), dim3(256), 0, s, b, wk.bstart, p.B, p.sb,
+                           nblk > 1 ? (const int *)wk.ptot : nullptr, wk.part, wk.multi, wk.bmeta,
+                           (const int *)nullptr);
         prof_end(kKBucketPartFill, s);
     }
     if (key16 && p.weighted) launch_bucket_sums<uint16_t, true>(b, p, wk, (const uint16_t *)key, s, mode, sums);

@@ -470,6 +470,7 @@ __device__ __forceinline__ bool large_single(int n, int k, int P) { return k == 
 // totals of every block (parts, slots, split buckets, large one-part buckets); the last
 // block writes bmeta = {parts, split buckets}.
 // With `bad` set (a resident CSR that failed its checks) every bucket counts as empty.
+// Without ptot (a single block: nblk = 1) the block's own scan totals are the totals.
 __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__restrict__ bstart, int B, int sb,
                                                 const int *__restrict__ ptot, int nblk, int blk,
                                                 int4 *__restrict__ part, int4 *__restrict__ multi,
@@ -481,7 +482,7 @@ __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__res
     __shared__ int pf_base[7];
     if (threadIdx.x < 64) {
         int v[7] = {0, 0, 0, 0, 0, 0, 0};
-        if ((int)threadIdx.x < nblk) {
+        if (ptot && (int)threadIdx.x < nblk) {
             const int q0 = ptot[4 * threadIdx.x], q1 = ptot[4 * threadIdx.x + 1];
             const int q2 = ptot[4 * threadIdx.x + 2], q3 = ptot[4 * threadIdx.x + 3];
             v[5] = q1;
@@ -527,6 +528,8 @@ __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__res
     int mm = pf_base[2] + block_excl_scan<256>(nsplit, pf_wsum, t2);
     int ll = pf_base[3] + block_excl_scan<256>(nlarge, pf_wsum, t3);
     int sm = pf_base[4] + block_excl_scan<256>(nsmall, pf_wsum, t4);
+    // the one-part buckets follow every split bucket's parts, the small ones every large one
+    const int all_slots = ptot ? pf_base[5] : t1, all_large = ptot ? pf_base[6] : t3;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int bk = blk * 1024 + 4 * (int)threadIdx.x + u;
@@ -538,10 +541,10 @@ __device__ __forceinline__ void part_fill_block(const Batch &b, const int *__res
             ss += k[u];
             ++mm;
         } else if (large_single(s1[u] - s0[u], k[u], P[u])) {
-            part[pf_base[5] + ll] = make_int4(bk, s0[u], s1[u], -1);
+            part[all_slots + ll] = make_int4(bk, s0[u], s1[u], -1);
             ++ll;
         } else {
-            part[pf_base[5] + pf_base[6] + sm] = make_int4(bk, s0[u], s1[u], -1);
+            part[all_slots + all_large + sm] = make_int4(bk, s0[u], s1[u], -1);
             ++sm;
         }
     }
