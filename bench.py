@@ -68,13 +68,13 @@ def algorithmic_bytes(name, E, N, K, M, weighted, n_empty):
         return 4 * (N + 1) + 4 * K * n_empty
     if name == "embed_rows":
         return 4 * (N + 1) + (4 + wv) * M + 8 * N + 4 * N + 4 * N * K
-    if name == "bucket_degree":  # bucketed (packed column word[, w]) in; labels in, s_i and the 6-byte
+    if name == "bucket_degree":  # bucketed (packed column word[, w]) in; labels in, s_i and the 5-byte
         # {c_i, y_i} records out
-        return (4 + wv) * M + 4 * N + 4 * N + 6 * N
+        return (4 + wv) * M + 4 * N + 4 * N + 5 * N
     if name == "bucket_embed":  # bucketed (column word with the row in bucket packed above it[, w]) in,
-        # the 6-byte {c_j, y_j} records and s_i once, Z out (after a pass B, as on every workload
+        # the 5-byte {c_j, y_j} records and s_i once, Z out (after a pass B, as on every workload
         # measured here)
-        return (4 + wv) * M + 6 * N + 4 * N + 4 * N * K
+        return (4 + wv) * M + 5 * N + 4 * N + 4 * N * K
     if name == "edge_scatter":  # edge list in, {c_j, y_j} once, Z written once
         return (8 + wv) * E + 8 * N + 4 * N * K
     if name == "edge_prep":  # labels; under the Laplacian the edge list and the degrees

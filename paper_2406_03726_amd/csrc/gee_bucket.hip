@@ -107,32 +107,38 @@ __global__ __launch_bounds__(256) void bucket_part_fill(Batch b, const int *__re
     part_fill_block(b, bstart, B, sb, ptot, (int)gridDim.x, (int)blockIdx.x, part, multi, bmeta, bad);
 }
 
-// The bucket path's per-node record {c_i, y_i}: 6 bytes (c_i, then y_i as a u16; y_i = 0
-// when unknown, with c_i = 0), so the gathered table of N records is 6N bytes (plus 2 bytes
-// of padding read by the last record's 8-byte load); with GEE_INFO6 = 0, float2 records.
-#ifndef GEE_INFO6
-#define GEE_INFO6 1
+// The bucket path's per-node record {c_i, y_i}: 5 bytes (c_i, then y_i as one byte; y_i = 0
+// when unknown, with c_i = 0), so the gathered table of N records is 5N bytes (plus 3 bytes
+// of padding read by the last record's 8-byte load, which takes the next record's first
+// bytes with it); with GEE_INFO_BYTES = 8, float2 records.
+#ifndef GEE_INFO_BYTES
+#define GEE_INFO_BYTES 5
 #endif
-constexpr int kInfoBytes = GEE_INFO6 ? 6 : 8;
+constexpr int kInfoBytes = GEE_INFO_BYTES;
+static_assert(kInfoBytes == 5 || kInfoBytes == 8, "5- or 8-byte node records");
+static_assert(kMaxClasses <= 256, "a class index fits one byte");
 __device__ __forceinline__ void put_info(float2 *info, int r, float c, int y) {
-    if (GEE_INFO6) {
-        unsigned short *q = reinterpret_cast<unsigned short *>(info) + 3 * (int64_t)r;
+    if (kInfoBytes == 5) {
+        unsigned char *q = reinterpret_cast<unsigned char *>(info) + 5 * (int64_t)r;
         const unsigned cb = __float_as_uint(c);
-        q[0] = (unsigned short)(cb & 0xFFFFu);
-        q[1] = (unsigned short)(cb >> 16);
-        q[2] = (unsigned short)(y >= 0 ? y : 0);
+        q[0] = (unsigned char)(cb & 0xFFu);
+        q[1] = (unsigned char)((cb >> 8) & 0xFFu);
+        q[2] = (unsigned char)((cb >> 16) & 0xFFu);
+        q[3] = (unsigned char)(cb >> 24);
+        q[4] = (unsigned char)(y >= 0 ? y : 0);
     } else {
         info[r] = node_info(c, y);
     }
 }
-// {c_i, y_i as int bits} from a record read as 8 bytes (its own 6 and 2 of the next)
+// {c_i, y_i as int bits} from a record read as 8 bytes
 __device__ __forceinline__ float2 info_of(float2 raw) {
-    return GEE_INFO6 ? make_float2(raw.x, __int_as_float(__float_as_int(raw.y) & 0xFFFF)) : raw;
+    return kInfoBytes == 5 ? make_float2(raw.x, __int_as_float(__float_as_int(raw.y) & 0xFF)) : raw;
 }
 __device__ __forceinline__ float2 get_info(const float2 *info, int r) {
-    if (GEE_INFO6) {
-        const unsigned short *q = reinterpret_cast<const unsigned short *>(info) + 3 * (int64_t)r;
-        return make_float2(__uint_as_float((unsigned)q[0] | ((unsigned)q[1] << 16)), __int_as_float((int)q[2]));
+    if (kInfoBytes == 5) {
+        const unsigned char *q = reinterpret_cast<const unsigned char *>(info) + 5 * (int64_t)r;
+        const unsigned cb = (unsigned)q[0] | ((unsigned)q[1] << 8) | ((unsigned)q[2] << 16) | ((unsigned)q[3] << 24);
+        return make_float2(__uint_as_float(cb), __int_as_float((int)q[4]));
     }
     return info[r];
 }
@@ -583,7 +589,7 @@ __global__ __launch_bounds__(64) void bucket_embed(Batch b, const KT *__restrict
     bool badc = false;
     const __amdgpu_buffer_rsrc_t r_inf =
         buffer_rsrc(reinterpret_cast<const char *>(info) + (int64_t)node_off * kInfoBytes,
-                    (int64_t)gd.N * kInfoBytes + (GEE_INFO6 ? 2 : 0));
+                    (int64_t)gd.N * kInfoBytes + (8 - kInfoBytes));
     struct Prep {
         int row[BEPL];
         float x[BEPL];   // val, 0 when masked

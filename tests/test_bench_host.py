@@ -26,10 +26,10 @@ def test_more_than_one_gpu_is_refused():
 
 def test_algorithmic_bytes_of_the_10m_edge_workload():
     E, N, K, M = 10_000_000, 600_000, 50, 20_000_000
-    # bucket_embed: (column word with its row in bucket packed in, w) per entry, the 6-byte
+    # bucket_embed: (column word with its row in bucket packed in, w) per entry, the 5-byte
     # {c, y} record and s per node, Z once
-    assert bench.algorithmic_bytes("bucket_embed", E, N, K, M, True, 0) == 8 * M + 10 * N + 4 * N * K == 286_000_000
-    assert bench.algorithmic_bytes("bucket_embed", E, N, K, M, False, 0) == 4 * M + 10 * N + 4 * N * K
+    assert bench.algorithmic_bytes("bucket_embed", E, N, K, M, True, 0) == 8 * M + 9 * N + 4 * N * K == 285_400_000
+    assert bench.algorithmic_bytes("bucket_embed", E, N, K, M, False, 0) == 4 * M + 9 * N + 4 * N * K
     assert bench.algorithmic_bytes("a_hist", E, N, K, M, True, 0) == 8 * E + 4 * N
     assert bench.algorithmic_bytes("edge_scatter", E, N, K, M, True, 0) == 12 * E + 8 * N + 4 * N * K
     assert bench.algorithmic_bytes("no_such_kernel", E, N, K, M, True, 0) == 0
