@@ -235,9 +235,9 @@ int gee_embed_ws(const int32_t *src, const int32_t *dst, const float *w, int64_t
  *   Workspace: the library's fixed scratch, a file-scope device array of gee_scratch_bytes()
  *   bytes (256 MiB) that every device the library runs on holds until the process ends. The
  *   call allocates nothing. A request whose gee_embed_workspace_bytes() (default schedule)
- *   exceeds it returns GEE_ERR_SCRATCH and enqueues nothing: up to about 14M CSR entries
- *   unweighted or 10M weighted fit (M = 2E under GEE_SYMMETRIZE; the 10,000-node SBM graph
- *   of 5.57M edges needs 90 MiB).
+ *   exceeds it returns GEE_ERR_SCRATCH and enqueues nothing: up to about 12.8M CSR entries
+ *   unweighted or 7.6M weighted fit at K = 50 (M = 2E under GEE_SYMMETRIZE; the 10,000-node
+ *   SBM graph of 5.57M edges needs 92 MiB).
  *   Concurrency: every call on one device uses the same scratch, so calls whose work
  *   overlaps on one device (different streams, or host threads) race and give wrong
  *   results; order them on one stream or synchronize between them. Nothing in the scratch

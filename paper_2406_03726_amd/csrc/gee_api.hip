@@ -239,7 +239,7 @@ int make_plan(const GraphIn *gs, int G, bool resident, Plan &p, std::vector<GDes
         if (p.bucket) {
             // entries of a bucket part (one wavefront of the bucket path)
             o.WE = x.sc.wave_entries > kBucketMinPart ? x.sc.wave_entries
-                   : x.sc.wave_entries ? kBucketMinPart : kBucketDefaultPart;
+                   : x.sc.wave_entries ? kBucketMinPart : default_bucket_part(mcap);
             bparts += mcap / o.WE;
         } else {
             o.WE = x.sc.wave_entries ? x.sc.wave_entries : default_wave_entries(mcap);

@@ -638,8 +638,19 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
 // bucket starts (csr_prep), the part table, degrees and class sums, rows from row_ptr.
 hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk, const int *rp, const int *col,
                                    const float *val, int64_t M, unsigned *status, hipStream_t s);
-constexpr int kBucketMinPart = 2048;  // entries of a bucket part, at least
-constexpr int kBucketDefaultPart = 8192;
+#ifndef GEE_BUCKET_MIN_PART
+#define GEE_BUCKET_MIN_PART 2048
+#endif
+constexpr int kBucketMinPart = GEE_BUCKET_MIN_PART;  // entries of a bucket part, at least
+// Default part size of a graph of `entries` CSR entries: the largest power of two in
+// [kBucketMinPart, 8192] that still leaves at least 2048 parts, so a small graph's buckets
+// still spread over the chip (2048 on a 2,000-node SBM graph of 446k entries, 4096 at 11M
+// entries, 8192 from 16.8M).
+inline int default_bucket_part(int64_t entries) {
+    int p = kBucketMinPart;
+    while (p < 8192 && (int64_t)p * 2 * 2048 <= entries) p *= 2;
+    return p;
+}
 constexpr int kBucketWindowPad = 256;  // entries allocated past the bucketed arrays' end
 // Degree kernels' outputs: s_i into srow and c_i = s_i / n_{y_i} into info (both), c_i alone
 // from the in-degrees of a transposed pass (in), s_i alone from the out-degrees (out).
