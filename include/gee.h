@@ -111,7 +111,9 @@ typedef enum {
    a graph embedded alone or inside a batch with the same schedule is bit-identical). */
 typedef struct {
     int32_t wave_entries;   /* entries per wavefront in the embed kernel (power of 2, 256..16384);
-                               on the bucket path (below) the entries of a bucket part, at least 2048 */
+                               on the bucket path (below) the entries of a bucket part, at least
+                               2048 (0: the largest power of two up to 8192 that leaves at
+                               least 2048 parts of the graph's CSR entries) */
     int32_t waves_per_block;/* wavefronts per workgroup in the embed kernel (1, 2 or 4) */
     int32_t tile_entries;   /* entries per workgroup tile of the CSR partition passes; this
                                library supports only 4096 (0 = default) */
