@@ -1374,7 +1374,8 @@ int gee_embed_csr_ws(const int32_t *row_ptr, const int32_t *col, const float *va
     b.status = st;
     b.gm = wk.gm;
     if (p.bucket) {  // the bucket kernels, rows from row_ptr; meta[1] holds the CSR's check
-        hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s, wk.meta + 1);
+        // (the class totals are added up by extra workgroups of the CSR checks' launch)
+        hipError_t e = launch_class_counts(b, p, wk.cpart, wk.counts, wk.inv_n, st, s, wk.meta + 1, false);
         if (e == hipSuccess) e = launch_bucket_embed_csr(b, p, wk, row_ptr, col, val, M, st, s);
         return hip_status(e);
     }

@@ -778,9 +778,16 @@ __global__ __launch_bounds__(kFixThreads) void bucket_embed_fix(Batch b, const i
 // within [0, M], row_ptr[N] = M; a failure sets *bad, which empties every bucket, and raises
 // GEE_DATA_CSR unless the graph skips validation) and the bucket starts bstart[b] =
 // row_ptr[b R] (clamped into [0, M]; bstart[B] = row_ptr[N]).
+// Workgroups past the row pointers' take the class totals, one wavefront per class.
 __global__ __launch_bounds__(256) void csr_prep(const int *__restrict__ rp, int N, int64_t M, int sb,
                                                 int *__restrict__ bstart, int *__restrict__ bad, unsigned *status,
-                                                int chk) {
+                                                int chk, int nprep, Batch b, int Ktot, const int *__restrict__ cpart,
+                                                int *__restrict__ counts, float *__restrict__ inv_n) {
+    if ((int)blockIdx.x >= nprep) {
+        const int c = ((int)blockIdx.x - nprep) * 4 + (int)(threadIdx.x >> 6);
+        if (c < Ktot) class_count_total(b, c, cpart, counts, inv_n);
+        return;
+    }
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i > N) return;
     const int64_t v = rp[i];
@@ -833,9 +840,11 @@ hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk
                                    const float *val, int64_t M, unsigned *status, hipStream_t s) {
     const int N = (int)p.Ntot;
     int *bad = wk.meta + 1;  // cleared by the class-count launch before this one
+    const int nprep = (N + 1 + 255) / 256;
     prof_begin(kKCsrPrep, s);
-    hipLaunchKernelGGL(csr_prep, dim3((unsigned)((N + 1 + 255) / 256)), dim3(256), 0, s, rp, N, M, p.sb, wk.bstart,
-                       bad, status, (b.one.flags & kNoValidate) ? 0 : 1);
+    hipLaunchKernelGGL(csr_prep, dim3((unsigned)(nprep + (p.Ktot + 3) / 4)), dim3(256), 0, s, rp, N, M, p.sb,
+                       wk.bstart, bad, status, (b.one.flags & kNoValidate) ? 0 : 1, nprep, b, p.Ktot,
+                       (const int *)wk.cpart, wk.counts, wk.inv_n);
     prof_end(kKCsrPrep, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

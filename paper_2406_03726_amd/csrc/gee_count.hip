@@ -45,13 +45,13 @@ hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s
 }
 
 hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
-                               unsigned *status, hipStream_t s, int *zero_word) {
+                               unsigned *status, hipStream_t s, int *zero_word, bool totals) {
     prof_begin(kKCountPartial, s);
     hipLaunchKernelGGL(class_count_partial, dim3((unsigned)p.cnt_blocks), dim3(256), 0, s, b, part, status,
                        zero_word);
     prof_end(kKCountPartial, s);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !totals) return e;
     prof_begin(kKCountFinal, s);
     hipLaunchKernelGGL(class_count_final, dim3((unsigned)((p.Ktot + 3) / 4)), dim3(256), 0, s, b, p.Ktot, part,
                        counts, inv_n);

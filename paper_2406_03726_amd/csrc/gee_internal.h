@@ -611,9 +611,10 @@ void prof_end(int kid, hipStream_t s);
 constexpr int kUploadChunk = 2048;
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
 // gee_count.hip: counts[class_off + k] and inv_n (inv_n may be nullptr); zero_word (if
-// given) is set to 0 first, in stream order before every later launch of the call.
+// given) is set to 0 first, in stream order before every later launch of the call. Without
+// totals only the per-slice partial counts are formed (a later launch adds them up).
 hipError_t launch_class_counts(const Batch &b, const Plan &p, int *part, int *counts, float *inv_n,
-                               unsigned *status, hipStream_t s, int *zero_word = nullptr);
+                               unsigned *status, hipStream_t s, int *zero_word = nullptr, bool totals = true);
 // gee_csr.hip: edge lists -> CSR of the union (rows and columns offset by node_off).
 // With job, the class counts of the launch run in the same launches.
 hipError_t launch_csr_build(const Batch &b, const Plan &p, const Work &wk, unsigned *status, hipStream_t s,
@@ -635,7 +636,8 @@ hipError_t launch_embed(const Batch &b, const Plan &p, const int *rp, const int 
 // gee_bucket.hip: Z straight from the row buckets of the first two sort passes
 // (launch_csr_build), for plans with p.bucket.
 // A resident CSR through the bucket kernels (plans made with csr_bucket): its checks and
-// bucket starts (csr_prep), the part table, degrees and class sums, rows from row_ptr.
+// bucket starts (csr_prep, whose extra workgroups add up the class counts' partials in
+// wk.cpart), the part table, degrees and class sums, rows from row_ptr.
 hipError_t launch_bucket_embed_csr(const Batch &b, const Plan &p, const Work &wk, const int *rp, const int *col,
                                    const float *val, int64_t M, unsigned *status, hipStream_t s);
 #ifndef GEE_BUCKET_MIN_PART
