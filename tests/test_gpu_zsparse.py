@@ -124,3 +124,28 @@ def test_sparse_powerlaw_k128_split_buckets():
     _label(f"sparse Z powerlaw N={g.N} E={g.E} K={g.K}")
     check_sparse(g)
     check_sparse(g.with_options(False, False, False))
+
+
+def test_sparse_nan_factor_rows_fill_every_class():
+    # a NaN weight makes its rows' Laplacian and correlation factors NaN, so 0 * NaN fills
+    # every class of those rows: the staged pairs (K = 40: staged by the class scatter) must
+    # hold K pairs for such a row, and the sparse form must list exactly the dense Z's
+    # non-zero entries (NaN is not zero), bit for bit
+    g = random_small_graph(33, N=3000, E=20_000, K=40, weighted=True).with_options(True, True, True)
+    g.w[17] = np.float32("nan")
+    s, d, w, lab = graph_tensors(g)
+    _label("sparse Z with a NaN weight, K=40")
+    gee.gee_get_data_errors()
+    rp, col, val = gee.gee_embed_sparse(s, d, w, lab, g.K, flags(g))
+    Zd = gee.gee_embed(s, d, w, lab, g.K, flags(g))
+    torch.cuda.synchronize()
+    assert gee.gee_get_data_errors() & gee.GEE_DATA_WEIGHT
+    Z = Zd.cpu().numpy()
+    nzm = Z != 0.0  # (NaN compares unequal to zero: stored)
+    assert np.isnan(Z).any()
+    rp = rp.cpu().numpy()
+    assert np.array_equal(np.diff(rp), nzm.sum(axis=1)), "row counts"
+    nnz = int(rp[-1])
+    rows, cls = np.nonzero(nzm)
+    assert np.array_equal(col[:nnz].cpu().numpy(), cls.astype(np.int32)), "classes"
+    assert np.array_equal(val[:nnz].cpu().numpy().view(np.uint32), Z[rows, cls].view(np.uint32)), "values"
