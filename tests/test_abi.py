@@ -91,3 +91,25 @@ def test_schedule_validation(lib):
     assert s.wave_entries >= 256 and 1 <= s.waves_per_block <= 4 and s.tile_entries == 4096
     bad = GeeSchedule(300, 0, 0, 0)  # not a power of two
     assert lib.gee_embed_workspace_bytes(1000, 100, 3, 15, 1, ctypes.byref(bad)) == 0
+
+
+def test_default_bucket_part_size_follows_the_entries(lib):
+    # the bucket path's default part: the largest power of two in [2048, 8192] that leaves at
+    # least 2048 parts of the graph's CSR entries (2E under symmetrization; flags 15 = all
+    # options with GEE_SYMMETRIZE)
+    from paper_2406_03726_amd._lib import GeeSchedule
+
+    def part(E, N, K):
+        s = GeeSchedule(0, 0, 0, 0)
+        assert lib.gee_default_schedule(E, N, K, 15, ctypes.byref(s)) == 0
+        return s.wave_entries
+
+    assert part(223_228, 2000, 3) == 2048            # 446k entries: 218 parts of 2048
+    assert part(5_572_753, 10_000, 3) == 4096        # 11.1M entries: 2721 parts of 4096
+    assert part(10_000_000, 600_000, 50) == 8192     # 20M entries: 2441 parts of 8192
+    assert part(1000, 100, 3) == 2048                # tiny graphs: the smallest part
+    assert part(400_000_000, 4_000_000, 50) == 8192  # large graphs: the largest default
+    # the boundaries: 2048 parts of 4096 (8,388,608 entries) and of 8192 (16,777,216 entries)
+    for e, at, below in ((8_388_608, 4096, 2048), (16_777_216, 8192, 4096)):
+        assert part(e // 2, 100_000, 8) == at
+        assert part(e // 2 - 1, 100_000, 8) == below
