@@ -75,9 +75,10 @@ def test_host_only_queries(lib):
     assert lib.gee_embed_atomic_workspace_bytes(-1, 3, 15) == 0
     assert lib.gee_embed_atomic_workspace_bytes(1000, 3, 1 << 9) == 0
     assert lib.gee_embed_atomic_workspace_bytes(2 ** 24 + 1, 3, 15) == 0  # beyond the node limit
-    # sparse Z: the embed workspace, a dense Z and one int per 1024-row tile
+    # sparse Z: the embed workspace, room for N K staged (class, value) pairs (twice a dense Z),
+    # one int per 256-row tile and one per row
     e = lib.gee_embed_sparse_workspace_bytes(1000, 3000, 5, 15, 1, None)
-    assert e >= lib.gee_embed_workspace_bytes(1000, 3000, 5, 15, 1, None) + 3000 * 5 * 4 + 3 * 4
+    assert e >= lib.gee_embed_workspace_bytes(1000, 3000, 5, 15, 1, None) + 2 * 3000 * 5 * 4 + 12 * 4 + 3000 * 4
     assert lib.gee_embed_sparse_workspace_bytes(-1, 3000, 5, 15, 1, None) == 0
     assert lib.gee_embed_sparse_workspace_bytes(1000, 3000, 0, 15, 1, None) == 0
     assert lib.gee_embed_sparse_workspace_bytes(1000, 2 ** 24, 128, 15, 1, None) == 0  # N * K = 2^31
